@@ -1,0 +1,152 @@
+"""Oracle homomorphic pipeline: rotations, BSGS transforms, fused conv, CoeffToSlot.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows, in the paper's order:
+  * HRot (Sec. 2.1): left rotation of the slots by r is the automorphism
+    X -> X^(5^r mod 2N) followed by key switching back to s.
+  * BSGS (Sec. 2.5): sum_g ( sum_i d'_{g n1 + i} (.) (ct <<< i u) ) <<< g n1 u; the
+    baby rotations are hoisted (one ModUp of c1, automorphism applied to the
+    extended digits) when `hoist` is True, giant rotations are plain.
+  * Fused conv (Algorithm 1 line 1, Sec. 4): BSGS at level 1 with K^' diagonals,
+    then rescale to level 0.
+  * CoeffToSlot (Sec. 2.4; Algorithm 1 line 2): ModRaise to the top level, one
+    BSGS transform + rescale per stage group, then the real split
+    Re = ct + conj(ct), Im = -X^{N/2} (ct - conj(ct)).
+"""
+import numpy as np
+
+from .plans import galois_elt
+
+
+def automorph_int(s, g):
+    """s(X^g) for a small signed integer polynomial"""
+    n = len(s)
+    out = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        e = i * g % (2 * n)
+        if e < n:
+            out[e] += s[i]
+        else:
+            out[e - n] -= s[i]
+    return out
+
+
+def square_int(s):
+    """s^2 in Z[X]/(X^n+1) for a ternary s (schoolbook over the nonzero support)"""
+    n = len(s)
+    nz = np.nonzero(s)[0]
+    out = np.zeros(n, dtype=np.int64)
+    for i in nz:
+        for j in nz:
+            k = i + j
+            v = int(s[i]) * int(s[j])
+            if k < n:
+                out[k] += v
+            else:
+                out[k - n] -= v
+    return out
+
+
+class Ctx:
+    """ring + secret + switching keys by Galois element (1 is never used; 'relin' for s^2)."""
+
+    def __init__(self, ring, s):
+        self.ring = ring
+        self.N = ring.n
+        self.s = np.asarray(s, dtype=np.int64)
+        self.keys = {}
+
+    def add_key(self, g, a, e):
+        sp = square_int(self.s) if g == "relin" else automorph_int(self.s, g)
+        self.keys[g] = self.ring.switch_key(self.s, sp, a, e)
+        return self.keys[g]
+
+    # ---------------------------------------------------------------- ct ops
+    def ct_add(self, level, x, y):
+        return np.stack([self.ring.add(level, x[0], y[0]), self.ring.add(level, x[1], y[1])])
+
+    def ct_sub(self, level, x, y):
+        return np.stack([self.ring.sub(level, x[0], y[0]), self.ring.sub(level, x[1], y[1])])
+
+    def ct_pmult(self, level, x, pt):
+        return np.stack([self.ring.pmult(level, x[0], pt), self.ring.pmult(level, x[1], pt)])
+
+    def ct_rescale(self, level, x):
+        return np.stack([self.ring.rescale(level, x[0]), self.ring.rescale(level, x[1])])
+
+    def ct_modraise(self, x, top=None):
+        return np.stack([self.ring.modraise(x[0][0], top), self.ring.modraise(x[1][0], top)])
+
+    def ct_monomial(self, level, x, k):
+        return np.stack([self.ring.poly_monomial(level, x[0], k), self.ring.poly_monomial(level, x[1], k)])
+
+    def apply_galois(self, level, x, g):
+        """(tau_g(c0), tau_g(c1)) switched back to s, plain (non-hoisted)"""
+        c0 = self.ring.poly_automorph(level, x[0], g)
+        d = self.ring.poly_automorph(level, x[1], g)
+        k0, k1 = self.ring.keyswitch(level, d, self.keys[g])
+        return np.stack([self.ring.add(level, c0, k0), k1])
+
+    def rotate(self, level, x, r):
+        r %= self.N // 2
+        if r == 0:
+            return x.copy()
+        return self.apply_galois(level, x, galois_elt(r, self.N))
+
+    def hoisted_rotations(self, level, x, rs):
+        """{r: x <<< r} sharing one ModUp of c1"""
+        ext = self.ring.modup(level, x[1])
+        out = {}
+        for r in rs:
+            r %= self.N // 2
+            if r == 0:
+                out[r] = x.copy()
+                continue
+            g = galois_elt(r, self.N)
+            k0, k1 = self.ring.keyswitch_ext(level, ext, g, self.keys[g])
+            c0 = self.ring.poly_automorph(level, x[0], g)
+            out[r] = np.stack([self.ring.add(level, c0, k0), k1])
+        return out
+
+    def bsgs(self, level, x, plan, pts, hoist=True):
+        """sum_j pts[j] (.) (x <<< j u), evaluated baby-step giant-step"""
+        babies = plan.babies
+        if hoist:
+            rot = self.hoisted_rotations(level, x, [plan.baby_rot(i) for i in babies])
+            baby = {i: rot[plan.baby_rot(i) % (self.N // 2)] for i in babies}
+        else:
+            baby = {i: self.rotate(level, x, plan.baby_rot(i)) for i in babies}
+        acc = None
+        for g in plan.giants:
+            inner = None
+            for j, (gg, i) in sorted(plan.split.items()):
+                if gg != g:
+                    continue
+                t = self.ct_pmult(level, baby[i], pts[j])
+                inner = t if inner is None else self.ct_add(level, inner, t)
+            if g != 0:
+                inner = self.rotate(level, inner, plan.giant_rot(g))
+            acc = inner if acc is None else self.ct_add(level, acc, inner)
+        return acc
+
+    # ------------------------------------------------------------ the path
+    def conv2d_cins(self, x, plan, pts, level=1, hoist=True):
+        y = self.bsgs(level, x, plan, pts, hoist)
+        return self.ct_rescale(level, y)
+
+    def conj_split(self, level, x):
+        c = self.apply_galois(level, x, 2 * self.N - 1)
+        re = self.ct_add(level, x, c)
+        im = self.ct_monomial(level, self.ct_sub(level, x, c), 3 * self.N // 2)
+        return re, im
+
+    def coeff_to_slot(self, x0, groups, group_pts, hoist=True):
+        """x0: level-0 ct [2][1][N].  groups: [Bsgs]; group_pts[g]: {j: pt} at level L-g."""
+        x = self.ct_modraise(x0)
+        level = self.ring.L
+        for plan, pts in zip(groups, group_pts):
+            x = self.bsgs(level, x, plan, pts, hoist)
+            x = self.ct_rescale(level, x)
+            level -= 1
+        return self.conj_split(level, x)

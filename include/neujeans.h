@@ -1,0 +1,194 @@
+/*
+ * neujeans.h - C ABI of the MI355X (gfx950) library for the fused CinS-conv +
+ * CoeffToSlot hot path of NeuJeans (Ju et al., arXiv 2312.04356).
+ *
+ * Scheme: RNS-CKKS over R = Z[X]/(X^N + 1) (Sec. 2.1-2.4).  Ciphertext moduli
+ * q_0..q_L, special moduli p_0..p_{alpha-1}; hybrid key switching with digits of
+ * alpha consecutive ciphertext primes (dnum = ceil((L+1)/alpha) at the top level,
+ * Table 4).  All primes are = 1 mod 2N and below 2^50.
+ *
+ * Memory and ownership
+ *   - Ciphertext and plaintext buffers are caller-owned DEVICE memory of uint64_t
+ *     canonical residues (each word in [0, prime)).  A level-l ciphertext is
+ *     [2][l+1][N] (polynomial, limb, coefficient), limb-major, contiguous.  The
+ *     library never frees them.
+ *   - Device ciphertexts are kept in the library's evaluation form (is_ntt = 1):
+ *     every homomorphic call requires and produces that form.  nj_to_coeff /
+ *     nj_to_eval convert in place to and from coefficient form (natural order),
+ *     the form in which results are compared with other implementations.
+ *   - Host arrays passed in are borrowed for the duration of the call.
+ *   - Contexts, keys and plans are library-owned; free them with their destroy call.
+ *
+ * Streams: every device call enqueues on the given hipStream_t (passed as void*,
+ * NULL = default stream) and does not synchronise the device, except where noted.
+ * Arguments are validated on the host before anything is enqueued.
+ *
+ * Errors: every call returns nj_status (0 = NJ_OK, negative = error) and never
+ * throws; nj_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef NEUJEANS_H
+#define NEUJEANS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NJ_OK = 0,
+    NJ_EINVAL = -1,       /* bad argument (null pointer, size, form, unknown id) */
+    NJ_ELEVEL = -2,       /* level out of range or mismatched between operands */
+    NJ_ESCALE = -3,       /* scale mismatch */
+    NJ_ENOKEY = -4,       /* a needed switching key (Galois element) was not generated */
+    NJ_EDEVICE = -5,      /* HIP runtime error (message from hipGetErrorString) */
+    NJ_ENOMEM = -6,       /* device allocation failed */
+    NJ_EUNSUPPORTED = -7  /* parameters outside what the kernels implement */
+} nj_status;
+
+typedef struct nj_ctx nj_ctx;   /* ring, primes, transform tables, secret, keys, scratch */
+typedef struct nj_plan nj_plan; /* one or more BSGS linear transforms with their diagonals */
+
+typedef struct {
+    int log_n;           /* N = 2^log_n, 10 <= log_n <= 16 */
+    int n_q;             /* number of ciphertext primes, top level L = n_q - 1, n_q <= 32 */
+    int alpha;           /* number of special primes = ciphertext primes per digit, 1..16 */
+    const uint64_t *q;   /* host [n_q]: q_0..q_L */
+    const uint64_t *p;   /* host [alpha]: p_0..p_{alpha-1} */
+    double scale;        /* Delta, the message scale of encoded inputs */
+} nj_params;
+
+typedef struct {
+    uint64_t *data;      /* device [2][level+1][N] */
+    int level;
+    int is_ntt;          /* 1 = evaluation form (required by homomorphic calls) */
+    double scale;
+} nj_ct;
+
+const char *nj_last_error(void);
+
+/* ------------------------------------------------------------ parameters */
+
+/* Prime chain rule: scan t = k*2N + 1 downward from below 2^bits, skip `exclude`,
+ * return the first `count` primes (Miller-Rabin, deterministic below 2^64).
+ * out: host [count].  NJ_EINVAL if bits > 50 or not enough primes exist. */
+nj_status nj_gen_primes(int log_n, int bits, int count, const uint64_t *exclude, int n_exclude, uint64_t *out);
+
+/* Creates a context on the current HIP device: validates primes, builds transform
+ * tables and basis-conversion constants, allocates no ciphertext scratch yet. */
+nj_status nj_ctx_create(const nj_params *params, nj_ctx **out);
+void nj_ctx_destroy(nj_ctx *ctx);
+
+/* Secret key s, host int8 [N] with entries in {-1, 0, 1} (sparse ternary, Table 4 h). */
+nj_status nj_set_secret(nj_ctx *ctx, const int8_t *s);
+
+/* Switching key to s from s' = s(X^g) (rotation / conjugation keys; Sec. 2.1 HRot)
+ * or from s' = s^2 when galois_elt == 0 (relinearisation).  Randomness is an input:
+ *   a: host uint64 [dnum][L+1+alpha][N], uniform residues in coefficient form,
+ *      limbs ordered q_0..q_L, p_0..p_{alpha-1};
+ *   e: host int64 [dnum][N], small errors.
+ * key_j = (-a_j s + e_j + P g_j s', a_j) with g_j = 1 mod the primes of digit j,
+ * 0 mod all others.  Synchronous.  Replaces an existing key for the same element. */
+nj_status nj_gen_switch_key(nj_ctx *ctx, uint32_t galois_elt, const uint64_t *a, const int64_t *e);
+
+/* Galois element of a left rotation of the slots by r: 5^r mod 2N. */
+uint32_t nj_galois_elt(const nj_ctx *ctx, int r);
+
+/* ------------------------------------------------------------ transforms */
+
+/* In-place negacyclic transform of n_limbs limbs of N words at `data`, limb i taken
+ * modulo prime prime_idx[i] (host array; index < n_q selects q_i, n_q + k selects p_k). */
+nj_status nj_ntt_limbs(nj_ctx *ctx, uint64_t *data, const int *prime_idx, int n_limbs, int inverse, void *stream);
+
+/* In-place conversion of n_polys level-l polynomials [n_polys][l+1][N] between
+ * coefficient form and evaluation form. */
+nj_status nj_to_eval(nj_ctx *ctx, uint64_t *data, int level, int n_polys, void *stream);
+nj_status nj_to_coeff(nj_ctx *ctx, uint64_t *data, int level, int n_polys, void *stream);
+
+/* ------------------------------------------------------------ encryption */
+
+/* Secret-key encryption at `level` (Sec. 2.1 Enc): (c0, c1) = (-a s + e + m, a).
+ *   m: device [(level+1)][N] plaintext residues, coefficient form;
+ *   a: host [(level+1)][N] uniform residues (coefficient form); e: host int64 [N].
+ * out->data: device [2][level+1][N]; the result is in evaluation form. */
+nj_status nj_encrypt_sk(nj_ctx *ctx, const uint64_t *m, int level, const uint64_t *a, const int64_t *e,
+                        double scale, nj_ct *out, void *stream);
+
+/* Decryption polynomial c0 + c1 s (Sec. 2.1 Dec): out device [(level+1)][N], coefficient form. */
+nj_status nj_decrypt(nj_ctx *ctx, const nj_ct *in, uint64_t *out, void *stream);
+
+/* Plaintext encoding on the host (Sec. 2.2 Slot encoding; Sec. 3.3.1 real CinS):
+ *   z: complex slots as interleaved doubles [N/2][2];  out: host int64 [N], the
+ *   rounded coefficients round_half_even(scale * f). */
+nj_status nj_encode_slots(int log_n, const double *z, double scale, int64_t *out);
+/* Real CinS: chans host double [C][2l] (C = N / (2l)), slices of 2l reals each. */
+nj_status nj_encode_cins(int log_n, const double *chans, int slice_len2, double scale, int64_t *out);
+/* Inverse of nj_encode_slots on centred integer coefficients: z out [N/2][2]. */
+nj_status nj_decode_slots(int log_n, const double *coeffs, double scale, double *z);
+/* Signed coefficients -> device residues [(level+1)][N] (coefficient form).  Synchronous. */
+nj_status nj_upload_plain(nj_ctx *ctx, const int64_t *coeffs, int level, uint64_t *dst, void *stream);
+
+/* ------------------------------------------------------- homomorphic ops */
+
+/* HRot (Sec. 2.1): slots rotated left by r = automorphism 5^r then key switching. */
+nj_status nj_rotate(nj_ctx *ctx, const nj_ct *in, int r, nj_ct *out, void *stream);
+/* Automorphism X -> X^g followed by hybrid key switching back to s (ModUp, key
+ * inner product, ModDown).  Needs the key of g.  in and out may alias. */
+nj_status nj_apply_galois(nj_ctx *ctx, const nj_ct *in, uint32_t galois_elt, nj_ct *out, void *stream);
+/* Key switching of one polynomial d (evaluation form, level l): (out0, out1) with
+ * out0 + out1 s ~ d s', using the key of galois_elt (0 = relinearisation key). */
+nj_status nj_keyswitch(nj_ctx *ctx, const uint64_t *d, int level, uint32_t galois_elt, uint64_t *out0, uint64_t *out1,
+                       void *stream);
+/* PMult (Sec. 2.1): both polynomials times a plaintext pt, device [(level+1)][N] in
+ * evaluation form (nj_to_eval of its coefficients).  out may alias in. */
+nj_status nj_pmult(nj_ctx *ctx, const nj_ct *in, const uint64_t *pt, nj_ct *out, void *stream);
+/* HAdd / HSub (Sec. 2.1): out = a + b or a - b (same level).  out may alias a or b. */
+nj_status nj_add(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
+nj_status nj_sub(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
+/* Rescale (Sec. 2.4): divide by q_l with rounding, level l -> l-1. */
+nj_status nj_rescale(nj_ctx *ctx, const nj_ct *in, nj_ct *out, void *stream);
+/* ModRaise (Sec. 2.4): level-0 ciphertext lifted (centred) to `level`. */
+nj_status nj_modraise(nj_ctx *ctx, const nj_ct *in, int level, nj_ct *out, void *stream);
+
+/* ---------------------------------------------------------------- plans */
+
+/* A plan holds n_lt BSGS linear transforms (Sec. 2.5).  Transform t acts at level
+ * level0 - t on slot-rotation unit u_t with diagonal offsets j*u_t and baby size n1_t. */
+int nj_plan_count(const nj_plan *plan);
+/* Galois elements whose keys the plan needs; returns the count (writes at most max). */
+int nj_plan_galois(const nj_plan *plan, uint32_t *out, int max);
+/* Diagonal offsets of transform t, in the order used by nj_plan_set_diagonal. */
+int nj_plan_offsets(const nj_plan *plan, int t, int32_t *out, int max);
+/* Replaces diagonal `idx` of transform t with host residues [(level_t+1)][N] in
+ * coefficient form (already baby-step giant-step pre-rotated). Synchronous. */
+nj_status nj_plan_set_diagonal(nj_ctx *ctx, nj_plan *plan, int t, int idx, const uint64_t *coeffs);
+void nj_plan_destroy(nj_plan *plan);
+
+/* Fused conv2d + StoC2 plan (Sec. 3.3, Sec. 4, Algorithm 1 line 1): C = N/W^2
+ * channels per ciphertext, W = smallest power of two >= w0 + (f-1)/2.
+ *   weights: host double [C][C][f][f] (out, in, row, col), cross-correlation with
+ *   'same' zero padding.  Diagonals K' = S'K^, encoded at scale q_1 for level 1.
+ *   n1 = baby steps (0 = ceil(sqrt(C))). */
+nj_status nj_conv_plan_create(nj_ctx *ctx, int w0, int f, const double *weights, int n1, nj_plan **out);
+
+/* CoeffToSlot plan (Sec. 2.4): T_{N/2}^{-1}'s stages in `groups` consecutive groups
+ * at levels L, L-1, ...; each group's diagonals encoded at the scale of the prime
+ * its rescale drops; the 1/2 of the real split folded into the last group. */
+nj_status nj_cts_plan_create(nj_ctx *ctx, int groups, nj_plan **out);
+
+/* BSGS evaluation of transform t of the plan on `in` (level must match), no rescale.
+ * hoist = 1: baby-step rotations share one ModUp of c1. */
+nj_status nj_plan_apply(nj_ctx *ctx, const nj_plan *plan, int t, const nj_ct *in, nj_ct *out, int hoist, void *stream);
+
+/* Fused conv (Algorithm 1 line 1): BSGS with the K' diagonals at level 1, rescale -> level 0. */
+nj_status nj_conv2d_cins(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_ct *out, void *stream);
+
+/* CoeffToSlot (Algorithm 1 line 2, before EvalMod): ModRaise of the level-0 input to L,
+ * each group's BSGS + rescale, then Re = ct + conj(ct), Im = -X^{N/2}(ct - conj(ct)).
+ * re/im: device [2][L-groups+1][N]. */
+nj_status nj_coeff_to_slot(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, nj_ct *re, nj_ct *im, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

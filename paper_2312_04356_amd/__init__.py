@@ -1,0 +1,351 @@
+"""Python binding of libneujeans.so: the fused CinS-conv + CoeffToSlot hot path on MI355X.
+
+Argument marshalling only: every step runs in the library's HIP kernels (or its
+host plan builder).  Device buffers are torch tensors of dtype int64 holding
+uint64 residues; streams are torch streams.  There is no fallback: importing
+this package fails if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libneujeans.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libneujeans.so is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_2312_04356_amd/build_lib.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+u64, i32, u32, dbl, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+
+
+class NjParams(ctypes.Structure):
+    _fields_ = [("log_n", i32), ("n_q", i32), ("alpha", i32), ("q", vp), ("p", vp), ("scale", dbl)]
+
+
+class NjCt(ctypes.Structure):
+    _fields_ = [("data", vp), ("level", i32), ("is_ntt", i32), ("scale", dbl)]
+
+
+_SIGS = {
+    "nj_last_error": (ctypes.c_char_p, []),
+    "nj_gen_primes": (i32, [i32, i32, i32, vp, i32, vp]),
+    "nj_ctx_create": (i32, [ctypes.POINTER(NjParams), ctypes.POINTER(vp)]),
+    "nj_ctx_destroy": (None, [vp]),
+    "nj_set_secret": (i32, [vp, vp]),
+    "nj_gen_switch_key": (i32, [vp, u32, vp, vp]),
+    "nj_galois_elt": (u32, [vp, i32]),
+    "nj_ntt_limbs": (i32, [vp, vp, vp, i32, i32, vp]),
+    "nj_to_eval": (i32, [vp, vp, i32, i32, vp]),
+    "nj_to_coeff": (i32, [vp, vp, i32, i32, vp]),
+    "nj_encrypt_sk": (i32, [vp, vp, i32, vp, vp, dbl, ctypes.POINTER(NjCt), vp]),
+    "nj_decrypt": (i32, [vp, ctypes.POINTER(NjCt), vp, vp]),
+    "nj_encode_slots": (i32, [i32, vp, dbl, vp]),
+    "nj_encode_cins": (i32, [i32, vp, i32, dbl, vp]),
+    "nj_decode_slots": (i32, [i32, vp, dbl, vp]),
+    "nj_upload_plain": (i32, [vp, vp, i32, vp, vp]),
+    "nj_rotate": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
+    "nj_apply_galois": (i32, [vp, ctypes.POINTER(NjCt), u32, ctypes.POINTER(NjCt), vp]),
+    "nj_keyswitch": (i32, [vp, vp, i32, u32, vp, vp, vp]),
+    "nj_pmult": (i32, [vp, ctypes.POINTER(NjCt), vp, ctypes.POINTER(NjCt), vp]),
+    "nj_add": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_sub": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_rescale": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_modraise": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
+    "nj_plan_count": (i32, [vp]),
+    "nj_plan_galois": (i32, [vp, vp, i32]),
+    "nj_plan_offsets": (i32, [vp, i32, vp, i32]),
+    "nj_plan_set_diagonal": (i32, [vp, vp, i32, i32, vp]),
+    "nj_plan_destroy": (None, [vp]),
+    "nj_conv_plan_create": (i32, [vp, i32, i32, vp, i32, ctypes.POINTER(vp)]),
+    "nj_cts_plan_create": (i32, [vp, i32, ctypes.POINTER(vp)]),
+    "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
+    "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_SIGS)
+
+
+class NjError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.nj_last_error().decode(errors="replace")
+        super().__init__("%s failed (status %d): %s" % (where, code, msg))
+        self.code = code
+
+
+def _check(code, where):
+    if code != 0:
+        raise NjError(code, where)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(vp)
+
+
+def _dev_ptr(t):
+    return vp(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return vp(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ host-only
+
+def nj_gen_primes(log_n, bits, count, exclude=()):
+    ex = np.ascontiguousarray(np.array(list(exclude) or [0], dtype=np.uint64))
+    out = np.zeros(count, dtype=np.uint64)
+    _check(_lib.nj_gen_primes(log_n, bits, count, _np_ptr(ex), len(exclude), _np_ptr(out)), "nj_gen_primes")
+    return [int(x) for x in out]
+
+
+def nj_encode_slots(log_n, z, scale):
+    zz = np.ascontiguousarray(np.stack([np.real(z), np.imag(z)], axis=-1), dtype=np.float64)
+    out = np.zeros(1 << log_n, dtype=np.int64)
+    _check(_lib.nj_encode_slots(log_n, _np_ptr(zz), float(scale), _np_ptr(out)), "nj_encode_slots")
+    return out
+
+
+def nj_encode_cins(log_n, chans, scale):
+    ch = np.ascontiguousarray(chans, dtype=np.float64)
+    out = np.zeros(1 << log_n, dtype=np.int64)
+    _check(_lib.nj_encode_cins(log_n, _np_ptr(ch), ch.shape[-1], float(scale), _np_ptr(out)), "nj_encode_cins")
+    return out
+
+
+def nj_decode_slots(log_n, coeffs, scale):
+    cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+    z = np.zeros(((1 << log_n) // 2, 2), dtype=np.float64)
+    _check(_lib.nj_decode_slots(log_n, _np_ptr(cf), float(scale), _np_ptr(z)), "nj_decode_slots")
+    return z[:, 0] + 1j * z[:, 1]
+
+
+def chain_primes(log_n, n_q, alpha, q0_bits, q_bits, p_bits):
+    """q_0 (q0_bits), q_1.. (q_bits), p_0.. (p_bits): each the next unused prime of the chain rule."""
+    q0 = nj_gen_primes(log_n, q0_bits, 1)
+    qs = nj_gen_primes(log_n, q_bits, n_q - 1, q0)
+    ps = nj_gen_primes(log_n, p_bits, alpha, q0 + qs)
+    return q0 + qs, ps
+
+
+# ------------------------------------------------------------------- objects
+
+class Ct:
+    """A device ciphertext [2][level+1][N] (torch int64 tensor of uint64 residues)."""
+
+    def __init__(self, data, level, is_ntt=1, scale=1.0):
+        self.data, self.level, self.is_ntt, self.scale = data, level, is_ntt, scale
+
+    def c(self):
+        return NjCt(self.data.data_ptr(), self.level, self.is_ntt, self.scale)
+
+    def sync_from(self, s):
+        self.level, self.is_ntt, self.scale = s.level, s.is_ntt, s.scale
+        return self
+
+
+class Plan:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def count(self):
+        return _lib.nj_plan_count(self.ptr)
+
+    def galois(self):
+        buf = np.zeros(4096, dtype=np.uint32)
+        n = _lib.nj_plan_galois(self.ptr, _np_ptr(buf), 4096)
+        return [int(x) for x in buf[:n]]
+
+    def offsets(self, t):
+        buf = np.zeros(1 << 16, dtype=np.int32)
+        n = _lib.nj_plan_offsets(self.ptr, t, _np_ptr(buf), 1 << 16)
+        return [int(x) for x in buf[:n]]
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.nj_plan_destroy(self.ptr)
+            self.ptr = None
+
+
+class Ctx:
+    """nj_ctx: ring, primes, tables, secret, switching keys."""
+
+    def __init__(self, log_n, q, p, scale, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", 0) if device is None else device
+        torch.cuda.set_device(self.device)
+        self.N = 1 << log_n
+        self.log_n = log_n
+        self.q, self.p = [int(x) for x in q], [int(x) for x in p]
+        self.L = len(self.q) - 1
+        self.alpha = len(self.p)
+        self.scale = scale
+        self._qa = np.array(self.q, dtype=np.uint64)
+        self._pa = np.array(self.p, dtype=np.uint64)
+        prm = NjParams(log_n, len(self.q), len(self.p), self._qa.ctypes.data, self._pa.ctypes.data, scale)
+        h = vp()
+        _check(_lib.nj_ctx_create(ctypes.byref(prm), ctypes.byref(h)), "nj_ctx_create")
+        self.ptr = h
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.nj_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    @property
+    def dnum(self):
+        return -(-(self.L + 1) // self.alpha)
+
+    def empty_ct(self, level):
+        t = self.torch.empty((2, level + 1, self.N), dtype=self.torch.int64, device=self.device)
+        return Ct(t, level)
+
+    def to_device(self, arr):
+        a = np.ascontiguousarray(arr).view(np.int64)
+        return self.torch.from_numpy(a.copy()).to(self.device)
+
+    @staticmethod
+    def to_host(t):
+        return t.detach().cpu().numpy().view(np.uint64)
+
+    # -- keys
+    def nj_set_secret(self, s):
+        s8 = np.ascontiguousarray(s, dtype=np.int8)
+        _check(_lib.nj_set_secret(self.ptr, _np_ptr(s8)), "nj_set_secret")
+
+    def nj_gen_switch_key(self, g, a, e):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        e = np.ascontiguousarray(e, dtype=np.int64)
+        assert a.shape == (self.dnum, self.L + 1 + self.alpha, self.N) and e.shape == (self.dnum, self.N)
+        _check(_lib.nj_gen_switch_key(self.ptr, int(g), _np_ptr(a), _np_ptr(e)), "nj_gen_switch_key")
+
+    def nj_galois_elt(self, r):
+        return int(_lib.nj_galois_elt(self.ptr, int(r)))
+
+    # -- transforms
+    def nj_ntt_limbs(self, data, prime_idx, inverse, stream=None):
+        pi = np.ascontiguousarray(prime_idx, dtype=np.int32)
+        _check(_lib.nj_ntt_limbs(self.ptr, _dev_ptr(data), _np_ptr(pi), len(pi), int(inverse), _stream(stream)),
+               "nj_ntt_limbs")
+
+    def nj_to_eval(self, data, level, n_polys, stream=None):
+        _check(_lib.nj_to_eval(self.ptr, _dev_ptr(data), level, n_polys, _stream(stream)), "nj_to_eval")
+
+    def nj_to_coeff(self, data, level, n_polys, stream=None):
+        _check(_lib.nj_to_coeff(self.ptr, _dev_ptr(data), level, n_polys, _stream(stream)), "nj_to_coeff")
+
+    # -- encryption / encoding
+    def nj_encrypt_sk(self, m_dev, level, a, e, scale, out, stream=None):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        e = np.ascontiguousarray(e, dtype=np.int64)
+        assert a.shape == (level + 1, self.N) and e.shape == (self.N,)
+        c = out.c()
+        _check(_lib.nj_encrypt_sk(self.ptr, _dev_ptr(m_dev), level, _np_ptr(a), _np_ptr(e), float(scale),
+                                  ctypes.byref(c), _stream(stream)), "nj_encrypt_sk")
+        return out.sync_from(c)
+
+    def nj_decrypt(self, ct, out_dev, stream=None):
+        c = ct.c()
+        _check(_lib.nj_decrypt(self.ptr, ctypes.byref(c), _dev_ptr(out_dev), _stream(stream)), "nj_decrypt")
+
+    def nj_encode_slots(self, z, scale):
+        return nj_encode_slots(self.log_n, z, scale)
+
+    def nj_encode_cins(self, chans, scale):
+        return nj_encode_cins(self.log_n, chans, scale)
+
+    def nj_decode_slots(self, coeffs, scale):
+        return nj_decode_slots(self.log_n, coeffs, scale)
+
+    def nj_upload_plain(self, coeffs, level, dst, stream=None):
+        cf = np.ascontiguousarray(coeffs, dtype=np.int64)
+        _check(_lib.nj_upload_plain(self.ptr, _np_ptr(cf), level, _dev_ptr(dst), _stream(stream)), "nj_upload_plain")
+
+    # -- homomorphic ops
+    def nj_rotate(self, ct, r, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_rotate(self.ptr, ctypes.byref(ci), int(r), ctypes.byref(co), _stream(stream)), "nj_rotate")
+        return out.sync_from(co)
+
+    def nj_apply_galois(self, ct, g, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_apply_galois(self.ptr, ctypes.byref(ci), int(g), ctypes.byref(co), _stream(stream)),
+               "nj_apply_galois")
+        return out.sync_from(co)
+
+    def nj_keyswitch(self, d, level, g, out0, out1, stream=None):
+        _check(_lib.nj_keyswitch(self.ptr, _dev_ptr(d), level, int(g), _dev_ptr(out0), _dev_ptr(out1),
+                                 _stream(stream)), "nj_keyswitch")
+
+    def nj_pmult(self, ct, pt_dev, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_pmult(self.ptr, ctypes.byref(ci), _dev_ptr(pt_dev), ctypes.byref(co), _stream(stream)),
+               "nj_pmult")
+        return out.sync_from(co)
+
+    def nj_add(self, a, b, out, stream=None):
+        ca, cb, co = a.c(), b.c(), out.c()
+        _check(_lib.nj_add(self.ptr, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream(stream)), "nj_add")
+        return out.sync_from(co)
+
+    def nj_sub(self, a, b, out, stream=None):
+        ca, cb, co = a.c(), b.c(), out.c()
+        _check(_lib.nj_sub(self.ptr, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream(stream)), "nj_sub")
+        return out.sync_from(co)
+
+    def nj_rescale(self, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_rescale(self.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)), "nj_rescale")
+        return out.sync_from(co)
+
+    def nj_modraise(self, ct, level, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_modraise(self.ptr, ctypes.byref(ci), level, ctypes.byref(co), _stream(stream)), "nj_modraise")
+        return out.sync_from(co)
+
+    # -- plans
+    def nj_conv_plan_create(self, w0, f, weights, n1=0):
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        h = vp()
+        _check(_lib.nj_conv_plan_create(self.ptr, w0, f, _np_ptr(w), n1, ctypes.byref(h)), "nj_conv_plan_create")
+        return Plan(h)
+
+    def nj_cts_plan_create(self, groups):
+        h = vp()
+        _check(_lib.nj_cts_plan_create(self.ptr, groups, ctypes.byref(h)), "nj_cts_plan_create")
+        return Plan(h)
+
+    def nj_plan_set_diagonal(self, plan, t, idx, coeffs):
+        cf = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        _check(_lib.nj_plan_set_diagonal(self.ptr, plan.ptr, t, idx, _np_ptr(cf)), "nj_plan_set_diagonal")
+
+    def nj_plan_apply(self, plan, t, ct, out, hoist=1, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_plan_apply(self.ptr, plan.ptr, t, ctypes.byref(ci), ctypes.byref(co), int(hoist),
+                                  _stream(stream)), "nj_plan_apply")
+        return out.sync_from(co)
+
+    def nj_conv2d_cins(self, plan, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_conv2d_cins(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)),
+               "nj_conv2d_cins")
+        return out.sync_from(co)
+
+    def nj_coeff_to_slot(self, plan, ct, re, im, stream=None):
+        ci, cr, cm = ct.c(), re.c(), im.c()
+        _check(_lib.nj_coeff_to_slot(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(cr), ctypes.byref(cm),
+                                     _stream(stream)), "nj_coeff_to_slot")
+        re.sync_from(cr)
+        im.sync_from(cm)
+        return re, im

@@ -1,0 +1,692 @@
+// C ABI entry points: key generation, encryption, hybrid key switching, rotations,
+// rescale, ModRaise, BSGS linear transforms, the fused conv and CoeffToSlot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+#include "internal.h"
+
+using namespace nj;
+
+int plan_galois_impl(const nj_plan *p, std::vector<uint32_t> &gs);
+
+namespace {
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+// Bump allocator over the context scratch buffer.
+struct Arena {
+    uint64_t *p;
+    size_t left;
+    uint64_t *take(size_t w)
+    {
+        if (w > left) return nullptr;
+        uint64_t *r = p;
+        p += w;
+        left -= w;
+        return r;
+    }
+};
+
+size_t ks_words(const nj_ctx *c, int l)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha, beta = n_digits(c, l);
+    return N * (3 * (l + 1) + beta * ne + 2 * ne + 2 * c->alpha + 2 * (l + 1));
+}
+
+struct KsBufs {
+    uint64_t *coef, *dtmp, *c0copy, *ext, *u, *pc, *conv;
+};
+
+bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha, beta = n_digits(c, l);
+    B.coef = A.take(N * (l + 1));
+    B.dtmp = A.take(N * (l + 1));
+    B.c0copy = A.take(N * (l + 1));
+    B.ext = A.take(N * beta * ne);
+    B.u = A.take(N * 2 * ne);
+    B.pc = A.take(N * 2 * c->alpha);
+    B.conv = A.take(N * 2 * (l + 1));
+    return B.conv != nullptr;
+}
+
+const uint64_t *key_of(const nj_ctx *c, uint32_t g)
+{
+    auto it = c->keys.find(g);
+    return it == c->keys.end() ? nullptr : it->second.d;
+}
+
+// ModUp of d (evaluation form, level l): every digit extended to Q_l u P, evaluation form.
+nj_status modup_ext(nj_ctx *c, int l, const uint64_t *d, KsBufs &B, hipStream_t s)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha;
+    NJ_HIP(hipMemcpyAsync(B.coef, d, N * (l + 1) * 8, hipMemcpyDeviceToDevice, s));
+    NJ_HIP(launch_ntt(c, B.coef, limbs_q(l), true, s));
+    for (int j = 0; j < n_digits(c, l); j++) {
+        const BconvTab &bt = c->modup[l][j];
+        uint64_t *ext = B.ext + (size_t)j * ne * N;
+        const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
+        int in_off[16];
+        for (int a = 0; a < bt.m; a++) in_off[a] = lo + a;
+        NJ_HIP(launch_bconv(c, bt, B.coef, in_off, ext, s));
+        NJ_HIP(hipMemcpyAsync(ext + (size_t)lo * N, d + (size_t)lo * N, (size_t)(hi - lo) * N * 8,
+                              hipMemcpyDeviceToDevice, s));
+        LimbTab lt;
+        lt.n = bt.n_out;
+        for (int o = 0; o < bt.n_out; o++) lt.pidx[o] = bt.out_pidx[o], lt.off[o] = bt.out_limb[o];
+        NJ_HIP(launch_ntt(c, ext, lt, false, s));
+    }
+    return NJ_OK;
+}
+
+// Key inner product on the extended digits (read through X -> X^g_ip), then ModDown of
+// both halves; out0 additionally gets `add` read through X -> X^g_add.
+nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *key, uint32_t g_ip, const uint64_t *add, uint32_t g_add,
+                      uint64_t *out0, uint64_t *out1, KsBufs &B, hipStream_t s)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha;
+    uint64_t *u0 = B.u, *u1 = B.u + ne * N;
+    NJ_HIP(launch_key_ip(c, l, n_digits(c, l), B.ext, key, g_ip, u0, u1, s));
+    NJ_HIP(hipMemcpyAsync(B.pc, u0 + (size_t)(l + 1) * N, (size_t)c->alpha * N * 8, hipMemcpyDeviceToDevice, s));
+    NJ_HIP(hipMemcpyAsync(B.pc + (size_t)c->alpha * N, u1 + (size_t)(l + 1) * N, (size_t)c->alpha * N * 8,
+                          hipMemcpyDeviceToDevice, s));
+    LimbTab lp;
+    lp.n = 2 * c->alpha;
+    for (int k = 0; k < 2 * c->alpha; k++) lp.pidx[k] = c->n_q + k % c->alpha, lp.off[k] = k;
+    NJ_HIP(launch_ntt(c, B.pc, lp, true, s));
+    int in_off[16];
+    for (int a = 0; a < c->alpha; a++) in_off[a] = a;
+    NJ_HIP(launch_bconv(c, c->moddown[l], B.pc, in_off, B.conv, s));
+    NJ_HIP(launch_bconv(c, c->moddown[l], B.pc + (size_t)c->alpha * N, in_off, B.conv + (size_t)(l + 1) * N, s));
+    LimbTab lq;
+    lq.n = 2 * (l + 1);
+    for (int k = 0; k < 2 * (l + 1); k++) lq.pidx[k] = k % (l + 1), lq.off[k] = k;
+    NJ_HIP(launch_ntt(c, B.conv, lq, false, s));
+    NJ_HIP(launch_moddown_combine(c, l, u0, B.conv, add, g_add, out0, s));
+    NJ_HIP(launch_moddown_combine(c, l, u1, B.conv + (size_t)(l + 1) * N, nullptr, 0, out1, s));
+    return NJ_OK;
+}
+
+// (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
+nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s)
+{
+    const uint64_t *key = key_of(c, g);
+    if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
+    KsBufs B;
+    if (!ks_bufs(c, l, A, B)) return fail(NJ_ENOMEM, "scratch too small");
+    const size_t N = c->N, plen = N * (l + 1);
+    NJ_HIP(launch_automorph(c, in + plen, B.dtmp, g, l + 1, s));
+    const uint64_t *c0 = in;
+    if (in == out) {
+        NJ_HIP(hipMemcpyAsync(B.c0copy, in, plen * 8, hipMemcpyDeviceToDevice, s));
+        c0 = B.c0copy;
+    }
+    nj_status st = modup_ext(c, l, B.dtmp, B, s);
+    if (st) return st;
+    return ks_from_ext(c, l, key, 1, c0, g, out, out + plen, B, s);
+}
+
+int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
+
+size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
+{
+    const size_t N = c->N, l = lt.level;
+    return N * 2 * (l + 1) * (lt.babies.size() + 2) + ks_words(c, l);
+}
+
+// sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
+nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
+                     hipStream_t s)
+{
+    const int l = lt.level, n = c->N / 2;
+    const size_t N = c->N, clen = 2 * N * (l + 1);
+    std::vector<const uint64_t *> baby(lt.babies.size());
+    std::vector<uint64_t *> baby_buf(lt.babies.size());
+    for (size_t b = 0; b < lt.babies.size(); b++) baby_buf[b] = A.take(clen);
+    uint64_t *inner = A.take(clen), *rot = A.take(clen);
+    if (!rot) return fail(NJ_ENOMEM, "scratch too small");
+    for (size_t b = 0; b < lt.babies.size(); b++)
+        if (lt.babies[b] != 0 && !key_of(c, galois_of_rot(c, (long long)lt.babies[b] * lt.u)))
+            return fail(NJ_ENOKEY, "missing baby-step rotation key");
+    for (int gg : lt.giants)
+        if (gg != 0 && !key_of(c, galois_of_rot(c, (long long)gg * lt.n1 * lt.u)))
+            return fail(NJ_ENOKEY, "missing giant-step rotation key");
+    KsBufs B;
+    Arena Aks = A;
+    if (!ks_bufs(c, l, Aks, B)) return fail(NJ_ENOMEM, "scratch too small");
+    bool ext_ready = false;
+    for (size_t b = 0; b < lt.babies.size(); b++) {
+        const int i = lt.babies[b];
+        if (i == 0) {
+            baby[b] = in;
+            continue;
+        }
+        const uint32_t g = galois_of_rot(c, (long long)i * lt.u);
+        if (hoist) {
+            if (!ext_ready) {
+                nj_status st = modup_ext(c, l, in + N * (l + 1), B, s);
+                if (st) return st;
+                ext_ready = true;
+            }
+            nj_status st = ks_from_ext(c, l, key_of(c, g), g, in, g, baby_buf[b], baby_buf[b] + N * (l + 1), B, s);
+            if (st) return st;
+        } else {
+            nj_status st = apply_galois(c, l, in, g, baby_buf[b], A, s);
+            if (st) return st;
+        }
+        baby[b] = baby_buf[b];
+    }
+    bool first_giant = true;
+    for (int gg : lt.giants) {
+        bool first = true;
+        for (int d = 0; d < lt.n_diag; d++) {
+            if (lt.g_of[d] != gg) continue;
+            const int b = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
+            NJ_HIP(launch_pmac(c, l, baby[b], lt.d_diag + (size_t)d * N * (l + 1), inner, first ? 1 : 0, s));
+            first = false;
+        }
+        const uint64_t *src = inner;
+        if (gg != 0) {
+            nj_status st = apply_galois(c, l, inner, galois_of_rot(c, (long long)gg * lt.n1 * lt.u), rot, A, s);
+            if (st) return st;
+            src = rot;
+        }
+        if (first_giant) NJ_HIP(hipMemcpyAsync(out, src, clen * 8, hipMemcpyDeviceToDevice, s));
+        else NJ_HIP(launch_elementwise(c, 0, out, src, out, [&] {
+            LimbTab t;
+            t.n = 2 * (l + 1);
+            for (int k = 0; k < t.n; k++) t.pidx[k] = k % (l + 1), t.off[k] = k;
+            return t;
+        }(), s));
+        first_giant = false;
+    }
+    (void)n;
+    return NJ_OK;
+}
+
+// rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
+nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
+{
+    const size_t N = c->N;
+    uint64_t *last = A.take(2 * N), *lifted = A.take(N * l);
+    if (!lifted) return fail(NJ_ENOMEM, "scratch too small");
+    for (int p = 0; p < 2; p++)
+        NJ_HIP(hipMemcpyAsync(last + p * N, in + ((size_t)p * (l + 1) + l) * N, N * 8, hipMemcpyDeviceToDevice, s));
+    LimbTab lt;
+    lt.n = 2;
+    lt.pidx[0] = lt.pidx[1] = l;
+    lt.off[0] = 0, lt.off[1] = 1;
+    NJ_HIP(launch_ntt(c, last, lt, true, s));
+    for (int p = 0; p < 2; p++) {
+        NJ_HIP(launch_lift_last(c, last + p * N, l, l, lifted, s));
+        NJ_HIP(launch_ntt(c, lifted, limbs_q(l - 1), false, s));
+        NJ_HIP(launch_rescale_combine(c, l, in + (size_t)p * (l + 1) * N, lifted, out + (size_t)p * l * N, s));
+    }
+    return NJ_OK;
+}
+
+nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s)
+{
+    const size_t N = c->N;
+    uint64_t *tmp = A.take(2 * N);
+    if (!tmp) return fail(NJ_ENOMEM, "scratch too small");
+    NJ_HIP(hipMemcpyAsync(tmp, in, 2 * N * 8, hipMemcpyDeviceToDevice, s));
+    LimbTab lt;
+    lt.n = 2;
+    lt.pidx[0] = lt.pidx[1] = 0;
+    lt.off[0] = 0, lt.off[1] = 1;
+    NJ_HIP(launch_ntt(c, tmp, lt, true, s));
+    for (int p = 0; p < 2; p++) NJ_HIP(launch_lift_last(c, tmp + p * N, 0, top + 1, out + (size_t)p * (top + 1) * N, s));
+    LimbTab lo;
+    lo.n = 2 * (top + 1);
+    for (int k = 0; k < lo.n; k++) lo.pidx[k] = k % (top + 1), lo.off[k] = k;
+    NJ_HIP(launch_ntt(c, out, lo, false, s));
+    return NJ_OK;
+}
+
+LimbTab ct_limbs(int l)
+{
+    LimbTab t;
+    t.n = 2 * (l + 1);
+    for (int k = 0; k < t.n; k++) t.pidx[k] = k % (l + 1), t.off[k] = k;
+    return t;
+}
+
+nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t *im, Arena A, hipStream_t s)
+{
+    const size_t clen = 2 * (size_t)c->N * (l + 1);
+    uint64_t *cj = A.take(clen);
+    if (!cj) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st = apply_galois(c, l, x, 2 * c->N - 1, cj, A, s);
+    if (st) return st;
+    NJ_HIP(launch_elementwise(c, 0, x, cj, re, ct_limbs(l), s));
+    NJ_HIP(launch_elementwise(c, 1, x, cj, cj, ct_limbs(l), s));
+    NJ_HIP(launch_monomial_half(c, l, cj, im, s));
+    return NJ_OK;
+}
+
+nj_status check_ct(const nj_ctx *c, const nj_ct *ct, const char *what)
+{
+    if (!ct || !ct->data) return fail(NJ_EINVAL, std::string(what) + ": null ciphertext");
+    if (ct->level < 0 || ct->level > c->L) return fail(NJ_ELEVEL, std::string(what) + ": level out of range");
+    if (!ct->is_ntt) return fail(NJ_EINVAL, std::string(what) + ": ciphertext must be in evaluation form");
+    return NJ_OK;
+}
+
+Arena arena_for(nj_ctx *c, size_t words, bool &ok)
+{
+    uint64_t *p = scratch_get(c, words);
+    ok = p != nullptr;
+    return Arena{p, ok ? words : 0};
+}
+
+hipError_t upload_signed(nj_ctx *c, const int64_t *host, int n_rows, const LimbTab &lt, uint64_t *dst, uint64_t *tmp,
+                         hipStream_t s)
+{
+    (void)n_rows;
+    hipError_t e = hipMemcpyAsync(tmp, host, (size_t)c->N * 8, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return launch_signed_to_rns(c, (const int64_t *)tmp, lt, dst, s, c->d_primes);
+}
+
+}  // namespace
+
+extern "C" {
+
+nj_status nj_set_secret(nj_ctx *c, const int8_t *sk)
+{
+    if (!c || !sk) return fail(NJ_EINVAL, "nj_set_secret: null argument");
+    c->s.assign(sk, sk + c->N);
+    std::vector<int64_t> s64(c->N);
+    for (int i = 0; i < c->N; i++) {
+        if (sk[i] < -1 || sk[i] > 1) return fail(NJ_EINVAL, "nj_set_secret: entries must be -1, 0 or 1");
+        s64[i] = sk[i];
+    }
+    if (!c->d_s) NJ_HIP(hipMalloc(&c->d_s, (size_t)c->n_primes * c->N * 8));
+    int64_t *tmp = nullptr;
+    NJ_HIP(hipMalloc(&tmp, (size_t)c->N * 8));
+    NJ_HIP(hipMemcpy(tmp, s64.data(), (size_t)c->N * 8, hipMemcpyHostToDevice));
+    LimbTab lt;
+    lt.n = c->n_primes;
+    for (int i = 0; i < lt.n; i++) lt.pidx[i] = i, lt.off[i] = i;
+    NJ_HIP(launch_signed_to_rns(c, tmp, lt, c->d_s, 0, c->d_primes));
+    NJ_HIP(launch_ntt(c, c->d_s, lt, false, 0));
+    NJ_HIP(hipDeviceSynchronize());
+    NJ_HIP(hipFree(tmp));
+    return NJ_OK;
+}
+
+nj_status nj_gen_switch_key(nj_ctx *c, uint32_t g, const uint64_t *a, const int64_t *e)
+{
+    if (!c || !a || !e) return fail(NJ_EINVAL, "nj_gen_switch_key: null argument");
+    if (!c->d_s) return fail(NJ_EINVAL, "nj_gen_switch_key: secret not set");
+    if (g != 0 && (g % 2 == 0 || g >= 2u * c->N)) return fail(NJ_EINVAL, "nj_gen_switch_key: bad Galois element");
+    const size_t N = c->N, nk = c->L + 1 + c->alpha;
+    uint64_t *key = nullptr;
+    auto it = c->keys.find(g);
+    if (it != c->keys.end()) key = it->second.d;
+    else {
+        NJ_HIP(hipMalloc(&key, (size_t)c->dnum * 2 * nk * N * 8));
+        c->keys[g].d = key;
+    }
+    uint64_t *sp = nullptr, *ebuf = nullptr;
+    int64_t *etmp = nullptr;
+    NJ_HIP(hipMalloc(&sp, (size_t)c->n_primes * N * 8));
+    NJ_HIP(hipMalloc(&ebuf, nk * N * 8));
+    NJ_HIP(hipMalloc(&etmp, N * 8));
+    LimbTab all;
+    all.n = c->n_primes;
+    for (int i = 0; i < all.n; i++) all.pidx[i] = i, all.off[i] = i;
+    if (g == 0) NJ_HIP(launch_elementwise(c, 2, c->d_s, c->d_s, sp, all, 0));
+    else NJ_HIP(launch_automorph(c, c->d_s, sp, g, c->n_primes, 0));
+    LimbTab kl;
+    kl.n = (int)nk;
+    for (int t = 0; t < (int)nk; t++) kl.pidx[t] = t <= c->L ? t : c->n_q + (t - c->L - 1), kl.off[t] = t;
+    for (int j = 0; j < c->dnum; j++) {
+        uint64_t *bj = key + ((size_t)j * 2 + 0) * nk * N, *aj = key + ((size_t)j * 2 + 1) * nk * N;
+        NJ_HIP(hipMemcpy(aj, a + (size_t)j * nk * N, nk * N * 8, hipMemcpyHostToDevice));
+        NJ_HIP(launch_ntt(c, aj, kl, false, 0));
+        NJ_HIP(hipMemcpy(etmp, e + (size_t)j * N, N * 8, hipMemcpyHostToDevice));
+        NJ_HIP(launch_signed_to_rns(c, etmp, kl, ebuf, 0, c->d_primes));
+        NJ_HIP(launch_ntt(c, ebuf, kl, false, 0));
+        NJ_HIP(launch_keygen_combine(c, j, bj, aj, ebuf, c->d_s, sp, c->d_pmod, 0));
+    }
+    NJ_HIP(hipDeviceSynchronize());
+    (void)hipFree(sp), (void)hipFree(ebuf), (void)hipFree(etmp);
+    return NJ_OK;
+}
+
+nj_status nj_ntt_limbs(nj_ctx *c, uint64_t *data, const int *prime_idx, int n_limbs, int inverse, void *stream)
+{
+    if (!c || !data || !prime_idx || n_limbs < 0) return fail(NJ_EINVAL, "nj_ntt_limbs: bad arguments");
+    for (int base = 0; base < n_limbs; base += NJ_MAX_LIMBS) {
+        LimbTab lt;
+        lt.n = std::min(NJ_MAX_LIMBS, n_limbs - base);
+        for (int i = 0; i < lt.n; i++) {
+            int p = prime_idx[base + i];
+            if (p < 0 || p >= c->n_primes) return fail(NJ_EINVAL, "nj_ntt_limbs: prime index out of range");
+            lt.pidx[i] = p, lt.off[i] = base + i;
+        }
+        NJ_HIP(launch_ntt(c, data, lt, inverse != 0, S(stream)));
+    }
+    return NJ_OK;
+}
+
+static nj_status convert(nj_ctx *c, uint64_t *data, int level, int n_polys, bool inverse, void *stream)
+{
+    if (!c || !data || level < 0 || level > c->L || n_polys < 1) return fail(NJ_EINVAL, "conversion: bad arguments");
+    for (int p = 0; p < n_polys; p++)
+        NJ_HIP(launch_ntt(c, data + (size_t)p * (level + 1) * c->N, limbs_q(level), inverse, S(stream)));
+    return NJ_OK;
+}
+nj_status nj_to_eval(nj_ctx *c, uint64_t *data, int level, int n_polys, void *stream)
+{
+    return convert(c, data, level, n_polys, false, stream);
+}
+nj_status nj_to_coeff(nj_ctx *c, uint64_t *data, int level, int n_polys, void *stream)
+{
+    return convert(c, data, level, n_polys, true, stream);
+}
+
+nj_status nj_upload_plain(nj_ctx *c, const int64_t *coeffs, int level, uint64_t *dst, void *stream)
+{
+    if (!c || !coeffs || !dst || level < 0 || level > c->L) return fail(NJ_EINVAL, "nj_upload_plain: bad arguments");
+    bool ok;
+    Arena A = arena_for(c, c->N, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    NJ_HIP(upload_signed(c, coeffs, 1, limbs_q(level), dst, A.take(c->N), S(stream)));
+    NJ_HIP(hipStreamSynchronize(S(stream)));  // the host array is borrowed only for the call
+    return NJ_OK;
+}
+
+nj_status nj_encrypt_sk(nj_ctx *c, const uint64_t *m, int level, const uint64_t *a, const int64_t *e, double scale,
+                        nj_ct *out, void *stream)
+{
+    if (!c || !m || !a || !e || !out || !out->data) return fail(NJ_EINVAL, "nj_encrypt_sk: null argument");
+    if (level < 0 || level > c->L) return fail(NJ_ELEVEL, "nj_encrypt_sk: level out of range");
+    if (!c->d_s) return fail(NJ_EINVAL, "nj_encrypt_sk: secret not set");
+    const size_t N = c->N, plen = N * (level + 1);
+    hipStream_t s = S(stream);
+    bool ok;
+    Arena A = arena_for(c, 2 * plen + N, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *mt = A.take(plen), *et = A.take(plen), *tmp = A.take(N);
+    uint64_t *c0 = out->data, *c1 = out->data + plen;
+    NJ_HIP(hipMemcpyAsync(c1, a, plen * 8, hipMemcpyHostToDevice, s));
+    NJ_HIP(launch_ntt(c, c1, limbs_q(level), false, s));
+    NJ_HIP(hipMemcpyAsync(mt, m, plen * 8, hipMemcpyDeviceToDevice, s));
+    NJ_HIP(launch_ntt(c, mt, limbs_q(level), false, s));
+    NJ_HIP(upload_signed(c, e, 1, limbs_q(level), et, tmp, s));
+    NJ_HIP(launch_ntt(c, et, limbs_q(level), false, s));
+    NJ_HIP(launch_elementwise(c, 2, c1, c->d_s, c0, limbs_q(level), s));
+    NJ_HIP(launch_elementwise(c, 1, et, c0, c0, limbs_q(level), s));
+    NJ_HIP(launch_elementwise(c, 0, c0, mt, c0, limbs_q(level), s));
+    NJ_HIP(hipStreamSynchronize(s));  // the host arrays a and e are borrowed only for the call
+    out->level = level;
+    out->is_ntt = 1;
+    out->scale = scale;
+    return NJ_OK;
+}
+
+nj_status nj_decrypt(nj_ctx *c, const nj_ct *in, uint64_t *out, void *stream)
+{
+    if (!c || !out) return fail(NJ_EINVAL, "nj_decrypt: null argument");
+    nj_status st = check_ct(c, in, "nj_decrypt");
+    if (st) return st;
+    if (!c->d_s) return fail(NJ_EINVAL, "nj_decrypt: secret not set");
+    const int l = in->level;
+    const size_t plen = (size_t)c->N * (l + 1);
+    NJ_HIP(launch_elementwise(c, 2, in->data + plen, c->d_s, out, limbs_q(l), S(stream)));
+    NJ_HIP(launch_elementwise(c, 0, out, in->data, out, limbs_q(l), S(stream)));
+    NJ_HIP(launch_ntt(c, out, limbs_q(l), true, S(stream)));
+    return NJ_OK;
+}
+
+nj_status nj_encode_slots(int log_n, const double *z, double scale, int64_t *out)
+{
+    if (!z || !out || log_n < 2 || log_n > 20) return fail(NJ_EINVAL, "nj_encode_slots: bad arguments");
+    const int N = 1 << log_n, n = N / 2;
+    std::vector<double> re(n), im(n);
+    for (int j = 0; j < n; j++) re[j] = z[2 * j], im[j] = z[2 * j + 1];
+    encode_slots(N, re.data(), im.data(), scale, out);
+    return NJ_OK;
+}
+
+nj_status nj_encode_cins(int log_n, const double *chans, int slice_len2, double scale, int64_t *out)
+{
+    if (!chans || !out || log_n < 2 || log_n > 20 || slice_len2 < 2 || (1 << log_n) % slice_len2 ||
+        (slice_len2 & (slice_len2 - 1)))
+        return fail(NJ_EINVAL, "nj_encode_cins: bad arguments");
+    encode_cins(1 << log_n, chans, slice_len2, scale, out);
+    return NJ_OK;
+}
+
+nj_status nj_decode_slots(int log_n, const double *coeffs, double scale, double *z)
+{
+    if (!coeffs || !z || log_n < 2 || log_n > 20) return fail(NJ_EINVAL, "nj_decode_slots: bad arguments");
+    const int N = 1 << log_n, n = N / 2;
+    std::vector<double> re(n), im(n);
+    decode_slots(N, coeffs, scale, re.data(), im.data());
+    for (int j = 0; j < n; j++) z[2 * j] = re[j], z[2 * j + 1] = im[j];
+    return NJ_OK;
+}
+
+nj_status nj_apply_galois(nj_ctx *c, const nj_ct *in, uint32_t g, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_apply_galois");
+    if (st) return st;
+    if (!out || !out->data) return fail(NJ_EINVAL, "nj_apply_galois: null output");
+    bool ok;
+    Arena A = arena_for(c, ks_words(c, in->level), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    st = apply_galois(c, in->level, in->data, g, out->data, A, S(stream));
+    if (st) return st;
+    out->level = in->level, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+nj_status nj_rotate(nj_ctx *c, const nj_ct *in, int r, nj_ct *out, void *stream)
+{
+    if (!c) return fail(NJ_EINVAL, "nj_rotate: null context");
+    return nj_apply_galois(c, in, nj_galois_elt(c, r), out, stream);
+}
+
+nj_status nj_keyswitch(nj_ctx *c, const uint64_t *d, int level, uint32_t g, uint64_t *out0, uint64_t *out1,
+                       void *stream)
+{
+    if (!c || !d || !out0 || !out1) return fail(NJ_EINVAL, "nj_keyswitch: null argument");
+    if (level < 0 || level > c->L) return fail(NJ_ELEVEL, "nj_keyswitch: level out of range");
+    const uint64_t *key = key_of(c, g);
+    if (!key) return fail(NJ_ENOKEY, "nj_keyswitch: no key for that element");
+    bool ok;
+    Arena A = arena_for(c, ks_words(c, level), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    KsBufs B;
+    if (!ks_bufs(c, level, A, B)) return fail(NJ_ENOMEM, "scratch");
+    nj_status st = modup_ext(c, level, d, B, S(stream));
+    if (st) return st;
+    return ks_from_ext(c, level, key, 1, nullptr, 0, out0, out1, B, S(stream));
+}
+
+nj_status nj_pmult(nj_ctx *c, const nj_ct *in, const uint64_t *pt, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_pmult");
+    if (st) return st;
+    if (!pt || !out || !out->data) return fail(NJ_EINVAL, "nj_pmult: null argument");
+    NJ_HIP(launch_pmac(c, in->level, in->data, pt, out->data, 1, S(stream)));
+    out->level = in->level, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+static nj_status addsub(nj_ctx *c, int op, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream, const char *nm)
+{
+    nj_status st = check_ct(c, a, nm);
+    if (st) return st;
+    if ((st = check_ct(c, b, nm))) return st;
+    if (a->level != b->level) return fail(NJ_ELEVEL, std::string(nm) + ": operands at different levels");
+    if (!out || !out->data) return fail(NJ_EINVAL, std::string(nm) + ": null output");
+    NJ_HIP(launch_elementwise(c, op, a->data, b->data, out->data, ct_limbs(a->level), S(stream)));
+    out->level = a->level, out->is_ntt = 1, out->scale = a->scale;
+    return NJ_OK;
+}
+nj_status nj_add(nj_ctx *c, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream)
+{
+    return addsub(c, 0, a, b, out, stream, "nj_add");
+}
+nj_status nj_sub(nj_ctx *c, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream)
+{
+    return addsub(c, 1, a, b, out, stream, "nj_sub");
+}
+
+nj_status nj_rescale(nj_ctx *c, const nj_ct *in, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_rescale");
+    if (st) return st;
+    if (in->level < 1) return fail(NJ_ELEVEL, "nj_rescale: level 0 cannot be rescaled");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_rescale: output must not alias input");
+    bool ok;
+    Arena A = arena_for(c, (size_t)c->N * (in->level + 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    st = rescale(c, in->level, in->data, out->data, A, S(stream));
+    if (st) return st;
+    out->level = in->level - 1, out->is_ntt = 1, out->scale = in->scale / (double)c->primes[in->level];
+    return NJ_OK;
+}
+
+nj_status nj_modraise(nj_ctx *c, const nj_ct *in, int level, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_modraise");
+    if (st) return st;
+    if (in->level != 0) return fail(NJ_ELEVEL, "nj_modraise: input must be at level 0");
+    if (level < 0 || level > c->L) return fail(NJ_ELEVEL, "nj_modraise: target level out of range");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_modraise: output must not alias input");
+    bool ok;
+    Arena A = arena_for(c, 2 * (size_t)c->N, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    st = modraise(c, in->data, level, out->data, A, S(stream));
+    if (st) return st;
+    out->level = level, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+// ------------------------------------------------------------------- plans
+
+int nj_plan_count(const nj_plan *p) { return p ? (int)p->lts.size() : 0; }
+
+int nj_plan_galois(const nj_plan *p, uint32_t *out, int max)
+{
+    if (!p) return 0;
+    std::vector<uint32_t> gs;
+    plan_galois_impl(p, gs);
+    for (int i = 0; i < (int)gs.size() && i < max; i++) out[i] = gs[i];
+    return (int)gs.size();
+}
+
+int nj_plan_offsets(const nj_plan *p, int t, int32_t *out, int max)
+{
+    if (!p || t < 0 || t >= (int)p->lts.size()) return 0;
+    const nj_lt_t &lt = p->lts[t];
+    for (int i = 0; i < lt.n_diag && i < max; i++) out[i] = lt.js[i];
+    return lt.n_diag;
+}
+
+nj_status nj_plan_set_diagonal(nj_ctx *c, nj_plan *p, int t, int idx, const uint64_t *coeffs)
+{
+    if (!c || !p || !coeffs || t < 0 || t >= (int)p->lts.size()) return fail(NJ_EINVAL, "nj_plan_set_diagonal: bad arguments");
+    nj_lt_t &lt = p->lts[t];
+    if (idx < 0 || idx >= lt.n_diag) return fail(NJ_EINVAL, "nj_plan_set_diagonal: index out of range");
+    const size_t plen = (size_t)c->N * (lt.level + 1);
+    uint64_t *dst = lt.d_diag + (size_t)idx * plen;
+    NJ_HIP(hipMemcpy(dst, coeffs, plen * 8, hipMemcpyHostToDevice));
+    NJ_HIP(launch_ntt(c, dst, limbs_q(lt.level), false, 0));
+    NJ_HIP(hipDeviceSynchronize());
+    return NJ_OK;
+}
+
+void nj_plan_destroy(nj_plan *p)
+{
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    for (auto &lt : p->lts)
+        if (lt.d_diag) (void)hipFree(lt.d_diag);
+    delete p;
+}
+
+nj_status nj_plan_apply(nj_ctx *c, const nj_plan *p, int t, const nj_ct *in, nj_ct *out, int hoist, void *stream)
+{
+    if (!c || !p || t < 0 || t >= (int)p->lts.size()) return fail(NJ_EINVAL, "nj_plan_apply: bad arguments");
+    nj_status st = check_ct(c, in, "nj_plan_apply");
+    if (st) return st;
+    const nj_lt_t &lt = p->lts[t];
+    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_plan_apply: ciphertext level differs from the transform's");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_plan_apply: output must not alias input");
+    bool ok;
+    Arena A = arena_for(c, bsgs_words(c, lt), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    st = bsgs_apply(c, lt, in->data, out->data, hoist, A, S(stream));
+    if (st) return st;
+    out->level = lt.level, out->is_ntt = 1, out->scale = in->scale * (double)c->primes[lt.level];
+    return NJ_OK;
+}
+
+nj_status nj_conv2d_cins(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *out, void *stream)
+{
+    if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_cins: not a conv plan");
+    nj_status st = check_ct(c, in, "nj_conv2d_cins");
+    if (st) return st;
+    const nj_lt_t &lt = p->lts[0];
+    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins: input must be at the plan's level");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_conv2d_cins: output must not alias input");
+    const size_t clen = 2 * (size_t)c->N * (lt.level + 1);
+    bool ok;
+    Arena A = arena_for(c, clen + bsgs_words(c, lt) + (size_t)c->N * (lt.level + 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *y = A.take(clen);
+    st = bsgs_apply(c, lt, in->data, y, 1, A, S(stream));
+    if (st) return st;
+    st = rescale(c, lt.level, y, out->data, A, S(stream));
+    if (st) return st;
+    out->level = lt.level - 1, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+nj_status nj_coeff_to_slot(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *re, nj_ct *im, void *stream)
+{
+    if (!c || !p || p->kind != 1 || p->lts.empty()) return fail(NJ_EINVAL, "nj_coeff_to_slot: not a CoeffToSlot plan");
+    nj_status st = check_ct(c, in, "nj_coeff_to_slot");
+    if (st) return st;
+    if (in->level != 0) return fail(NJ_ELEVEL, "nj_coeff_to_slot: input must be at level 0");
+    if (!re || !im || !re->data || !im->data) return fail(NJ_EINVAL, "nj_coeff_to_slot: null output");
+    const size_t N = c->N, top = c->L, clen = 2 * N * (top + 1);
+    size_t need = 0;
+    for (const auto &lt : p->lts) need = std::max(need, bsgs_words(c, lt));
+    need = std::max(need, ks_words(c, c->L) + clen) + 2 * clen + N * (top + 2);
+    bool ok;
+    Arena A = arena_for(c, need, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *x = A.take(clen), *y = A.take(clen);
+    hipStream_t s = S(stream);
+    st = modraise(c, in->data, c->L, x, A, s);
+    if (st) return st;
+    int l = c->L;
+    for (const auto &lt : p->lts) {
+        if (lt.level != l) return fail(NJ_ELEVEL, "nj_coeff_to_slot: plan levels do not follow the context's top level");
+        st = bsgs_apply(c, lt, x, y, 1, A, s);
+        if (st) return st;
+        st = rescale(c, l, y, x, A, s);
+        if (st) return st;
+        l--;
+    }
+    st = conj_split(c, l, x, re->data, im->data, A, s);
+    if (st) return st;
+    re->level = im->level = l;
+    re->is_ntt = im->is_ntt = 1;
+    re->scale = im->scale = in->scale;
+    return NJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+// Host FP64 encoding and offline plan construction (not on the timed path).
+//
+//  * Slot encoding (Sec. 2.2): the plaintext f has f(zeta_j) = z_j, zeta_j = zeta^(5^j).
+//    With V[j][i] = zeta_j^i (i < N/2) and w = V^{-1} z, f = (Re w | Im w) because
+//    zeta_j^{N/2} = sqrt(-1).  V = T_{N/2} P (Sec. 2.3) and T_{N/2} = S_{N/4} ... S_1,
+//    so V^{-1} z = P S_1^{-1} ... S_{N/4}^{-1} z: butterflies, then a bit reversal.
+//  * Real CinS (Sec. 3.3.1, Appendix A): DFT'_{2l}(m) = T_l P_l fold(m).
+//  * Fused conv (Sec. 3.3.2-3.3.4, Sec. 4): K^' = S_{N/2<-l} K^ applied column by
+//    column; diagonal k holds K^'[c][(c+k) mod C] in slice c; BSGS pre-rotation.
+//  * CoeffToSlot (Sec. 2.4): groups of consecutive inverse butterfly stages, each
+//    turned into its cyclic diagonals by composing the stages' three diagonals.
+#include <cmath>
+#include <complex>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+namespace nj {
+
+typedef std::complex<double> cplx;
+
+static int ilog2(int x)
+{
+    int r = 0;
+    while ((1 << r) < x) r++;
+    return r;
+}
+
+static int rev(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; i++) r = (r << 1) | ((x >> i) & 1);
+    return r;
+}
+
+// W_k[t] = w_{8k}^(5^t mod 8k), t < k
+static std::vector<cplx> w_diag(int k)
+{
+    std::vector<cplx> w(k);
+    long long e = 1, mod = 8LL * k;
+    for (int t = 0; t < k; t++) {
+        double ang = 2.0 * M_PI * (double)e / (double)mod;
+        w[t] = cplx(std::cos(ang), std::sin(ang));
+        e = e * 5 % mod;
+    }
+    return w;
+}
+
+// x <- S_k x (or S_k^{-1} x) on blocks of 2k consecutive entries
+static void butterfly_stage(std::vector<cplx> &x, int k, bool inverse)
+{
+    const std::vector<cplx> w = w_diag(k);
+    const int n = (int)x.size();
+    for (int b = 0; b < n; b += 2 * k)
+        for (int t = 0; t < k; t++) {
+            cplx a = x[b + t], c = x[b + k + t];
+            if (!inverse) {
+                cplx v = w[t] * c;
+                x[b + t] = a + v;
+                x[b + k + t] = a - v;
+            } else {
+                x[b + t] = 0.5 * (a + c);
+                x[b + k + t] = 0.5 * (a - c) / w[t];
+            }
+        }
+}
+
+static void bit_reverse(std::vector<cplx> &x)
+{
+    const int n = (int)x.size(), bits = ilog2(n);
+    for (int i = 0; i < n; i++) {
+        int r = rev(i, bits);
+        if (i < r) std::swap(x[i], x[r]);
+    }
+}
+
+void encode_slots(int N, const double *z_re, const double *z_im, double scale, int64_t *out)
+{
+    const int n = N / 2;
+    std::vector<cplx> x(n);
+    for (int j = 0; j < n; j++) x[j] = cplx(z_re[j], z_im[j]);
+    for (int k = n / 2; k >= 1; k /= 2) butterfly_stage(x, k, true);  // T^{-1} = S_1^{-1} ... S_{n/2}^{-1}
+    bit_reverse(x);                                                    // P
+    for (int i = 0; i < n; i++) {
+        out[i] = (int64_t)std::nearbyint(scale * x[i].real());
+        out[n + i] = (int64_t)std::nearbyint(scale * x[i].imag());
+    }
+}
+
+void decode_slots(int N, const double *coeffs, double scale, double *z_re, double *z_im)
+{
+    const int n = N / 2;
+    std::vector<cplx> x(n);
+    for (int i = 0; i < n; i++) x[i] = cplx(coeffs[i] / scale, coeffs[n + i] / scale);
+    bit_reverse(x);
+    for (int k = 1; k < n; k *= 2) butterfly_stage(x, k, false);
+    for (int j = 0; j < n; j++) z_re[j] = x[j].real(), z_im[j] = x[j].imag();
+}
+
+// DFT'_{2l}(m) = T_l P_l fold(m), fold(m)_i = m_i + sqrt(-1) m_{i+l}
+static std::vector<cplx> dft_prime(const double *m, int ell)
+{
+    std::vector<cplx> x(ell);
+    for (int i = 0; i < ell; i++) x[i] = cplx(m[i], m[i + ell]);
+    bit_reverse(x);
+    for (int k = 1; k < ell; k *= 2) butterfly_stage(x, k, false);
+    return x;
+}
+
+void encode_cins(int N, const double *chans, int slice2, double scale, int64_t *out)
+{
+    const int ell = slice2 / 2, C = N / slice2;
+    std::vector<double> zr(N / 2), zi(N / 2);
+    for (int c = 0; c < C; c++) {
+        std::vector<cplx> d = dft_prime(chans + (size_t)c * slice2, ell);
+        for (int j = 0; j < ell; j++) zr[c * ell + j] = d[j].real(), zi[c * ell + j] = d[j].imag();
+    }
+    encode_slots(N, zr.data(), zi.data(), scale, out);
+}
+
+// ------------------------------------------------------------------ BSGS split
+
+static int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+void bsgs_split(nj_lt_t &lt, int n)
+{
+    lt.n_diag = (int)lt.js.size();
+    if (lt.n1 <= 0) lt.n1 = (int)std::ceil(std::sqrt((double)lt.n_diag));
+    lt.g_of.assign(lt.n_diag, 0);
+    lt.i_of.assign(lt.n_diag, 0);
+    std::map<int, int> bs, gs;
+    for (int d = 0; d < lt.n_diag; d++) {
+        int g = floordiv(lt.js[d], lt.n1);
+        lt.g_of[d] = g;
+        lt.i_of[d] = lt.js[d] - g * lt.n1;
+        bs[lt.i_of[d]] = 1;
+        gs[g] = 1;
+    }
+    lt.babies.clear();
+    lt.giants.clear();
+    for (auto &kv : bs) lt.babies.push_back(kv.first);
+    for (auto &kv : gs) lt.giants.push_back(kv.first);
+    (void)n;
+}
+
+// representative of offset r (a multiple of u) centred in [-h, n/u - h), h = (n/u)/2
+static int centred_rep(long long r, int u, int n)
+{
+    const int span = n / u, h = span / 2;
+    long long j = ((r / u) % span + span) % span;
+    return (int)(((j + h) % span) - h);
+}
+
+static void rotr_inplace(std::vector<cplx> &v, long long r)
+{
+    const long long n = (long long)v.size();
+    r = ((r % n) + n) % n;
+    if (r == 0) return;
+    std::vector<cplx> o(n);
+    for (long long i = 0; i < n; i++) o[(i + r) % n] = v[i];
+    v.swap(o);
+}
+
+// kernel polynomial: k(Y) = sum K[u][v] Y^{-((u-p)W + (v-p))} mod Y^{W^2} + 1
+static std::vector<double> kernel_poly(const double *K, int f, int W)
+{
+    const int n = W * W, p = (f - 1) / 2;
+    std::vector<double> k(n, 0.0);
+    for (int u = 0; u < f; u++)
+        for (int v = 0; v < f; v++) {
+            int e = -((u - p) * W + (v - p));
+            double val = K[u * f + v];
+            if (e >= 0) k[e % n] += val;
+            else k[(e + n) % n] -= val;  // Y^{-e'} = -Y^{n-e'}
+        }
+    return k;
+}
+
+nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
+                               std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
+{
+    const int n = N / 2;
+    const int p = (f - 1) / 2;
+    int W = 1;
+    while (W < w0 + p) W *= 2;
+    const int ell = W * W / 2;
+    if (W * W > N || f % 2 == 0) return fail(NJ_EUNSUPPORTED, "conv plan: image too large for N or even kernel");
+    const int C = n / ell;
+    // K^[o][i] = DFT'(k_{o,i}), then K^' columns = S_{n/2} ... S_l applied to (K^[0][i] | ... | K^[C-1][i])
+    std::vector<std::vector<cplx>> Kp((size_t)C * C);  // [o][i] slices of length l
+    for (int i = 0; i < C; i++) {
+        std::vector<cplx> col(n);
+        for (int o = 0; o < C; o++) {
+            std::vector<double> kp = kernel_poly(weights + ((size_t)o * C + i) * f * f, f, W);
+            std::vector<cplx> d = dft_prime(kp.data(), ell);
+            for (int j = 0; j < ell; j++) col[(size_t)o * ell + j] = d[j];
+        }
+        for (int k = ell; k < n; k *= 2) butterfly_stage(col, k, false);
+        for (int o = 0; o < C; o++) Kp[(size_t)o * C + i].assign(col.begin() + (size_t)o * ell, col.begin() + (size_t)(o + 1) * ell);
+    }
+    lt.u = ell;
+    lt.n1 = n1;
+    lt.js.clear();
+    for (int k = 0; k < C; k++) lt.js.push_back(centred_rep((long long)k * ell, ell, n));
+    bsgs_split(lt, n);
+    dre.assign(lt.n_diag, {});
+    dim.assign(lt.n_diag, {});
+    for (int d = 0; d < lt.n_diag; d++) {
+        const int k = ((lt.js[d] % C) + C) % C;
+        std::vector<cplx> v(n);
+        for (int c = 0; c < C; c++)
+            for (int j = 0; j < ell; j++) v[(size_t)c * ell + j] = Kp[(size_t)c * C + (c + k) % C][j];
+        rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+        dre[d].resize(n);
+        dim[d].resize(n);
+        for (int j = 0; j < n; j++) dre[d][j] = v[j].real(), dim[d][j] = v[j].imag();
+    }
+    return NJ_OK;
+}
+
+// Cyclic-diagonal form {r: v_r} of M = sum_r diag(v_r) (x <<< r), (x <<< r)[i] = x[i + r mod n]
+typedef std::map<int, std::vector<cplx>> Diags;
+
+static Diags inverse_stage_diags(int k, int n)
+{
+    const std::vector<cplx> w = w_diag(k);
+    std::vector<cplx> v0(n), vp(n), vm(n);
+    for (int i = 0; i < n; i++) {
+        int t = i % (2 * k);
+        if (t < k) v0[i] = 0.5, vp[i] = 0.5, vm[i] = 0.0;
+        else v0[i] = -0.5 / w[t - k], vp[i] = 0.0, vm[i] = 0.5 / w[t - k];
+    }
+    Diags D;
+    auto addd = [&](int r, const std::vector<cplx> &v) {
+        r = ((r % n) + n) % n;
+        auto it = D.find(r);
+        if (it == D.end()) D[r] = v;
+        else
+            for (int i = 0; i < n; i++) it->second[i] += v[i];
+    };
+    addd(0, v0);
+    addd(k, vp);
+    addd(-k, vm);
+    return D;
+}
+
+// A B: diag(a_r)(.<<<r) diag(b_s)(.<<<s) = diag(a_r * (b_s <<< r)) (.<<<(r+s))
+static Diags compose(const Diags &A, const Diags &B, int n)
+{
+    Diags Cm;
+    for (auto &ra : A)
+        for (auto &sb : B) {
+            const int r = ra.first, t = (r + sb.first) % n;
+            auto it = Cm.find(t);
+            if (it == Cm.end()) it = Cm.emplace(t, std::vector<cplx>(n, 0.0)).first;
+            std::vector<cplx> &dst = it->second;
+            const std::vector<cplx> &a = ra.second, &b = sb.second;
+            for (int i = 0; i < n; i++) dst[i] += a[i] * b[(i + r) % n];
+        }
+    return Cm;
+}
+
+nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
+                              std::vector<std::vector<std::vector<double>>> &dre,
+                              std::vector<std::vector<std::vector<double>>> &dim)
+{
+    const int n = N / 2, S = ilog2(n);
+    if (groups < 1 || groups > S) return fail(NJ_EINVAL, "CoeffToSlot plan: groups must be 1..log2(N/2)");
+    std::vector<int> strides;
+    for (int k = n / 2; k >= 1; k /= 2) strides.push_back(k);
+    lts.assign(groups, nj_lt_t());
+    dre.assign(groups, {});
+    dim.assign(groups, {});
+    int pos = 0;
+    for (int g = 0; g < groups; g++) {
+        const int sz = S / groups + (g < S % groups ? 1 : 0);
+        Diags M;
+        bool first = true;
+        for (int s = pos; s < pos + sz; s++) {
+            Diags D = inverse_stage_diags(strides[s], n);
+            M = first ? D : compose(D, M, n);
+            first = false;
+        }
+        const int u = strides[pos + sz - 1];
+        pos += sz;
+        if (g == groups - 1)
+            for (auto &kv : M)
+                for (auto &v : kv.second) v *= 0.5;
+        nj_lt_t &lt = lts[g];
+        lt.u = u;
+        lt.n1 = 0;
+        lt.js.clear();
+        std::vector<const std::vector<cplx> *> vecs;
+        std::map<int, const std::vector<cplx> *> byj;
+        for (auto &kv : M) byj[centred_rep(kv.first, u, n)] = &kv.second;
+        for (auto &kv : byj) lt.js.push_back(kv.first);
+        bsgs_split(lt, n);
+        dre[g].assign(lt.n_diag, {});
+        dim[g].assign(lt.n_diag, {});
+        for (int d = 0; d < lt.n_diag; d++) {
+            std::vector<cplx> v = *byj[lt.js[d]];
+            rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+            dre[g][d].resize(n);
+            dim[g][d].resize(n);
+            for (int j = 0; j < n; j++) dre[g][d][j] = v[j].real(), dim[g][d][j] = v[j].imag();
+        }
+    }
+    return NJ_OK;
+}
+
+}  // namespace nj

@@ -1,0 +1,154 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/neujeans.h"
+#include "modarith.h"
+
+#define NJ_MAX_LIMBS 64  // q limbs + p limbs addressed by one launch
+
+namespace nj {
+
+// Per-launch limb -> prime table, passed by value in kernel arguments.
+struct LimbTab {
+    int n;
+    int pidx[NJ_MAX_LIMBS];  // prime index of each launched limb
+    int off[NJ_MAX_LIMBS];   // limb offset from the base pointer, in units of N words
+};
+
+// Per-prime constants resident in device memory (indexed by prime index).
+struct PrimeInfo {
+    Mod m;
+    double ninv, ninvq;  // N^{-1} mod t and its Shoup companion
+    double half;         // floor(t/2), for centred lifts
+};
+
+void set_error(const std::string &msg);
+nj_status fail(nj_status code, const std::string &msg);
+nj_status hip_fail(hipError_t e, const char *what);
+
+#define NJ_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t _e = (call);                                                      \
+        if (_e != hipSuccess) return ::nj::hip_fail(_e, #call);                      \
+    } while (0)
+
+// Basis-conversion constants of one ModUp digit at one level: from the digit's
+// primes (m of them) to every other prime of Q_l u P.
+struct BconvTab {
+    int m;                 // primes in the digit
+    int n_out;             // targets
+    double *hat_inv;       // device [m]:  (D/q_a)^{-1} mod q_a
+    double *hat;           // device [m][n_out]: (D/q_a) mod target
+    int in_pidx[16];       // host copies
+    std::vector<int> out_pidx;
+    std::vector<int> out_limb;  // position of each target inside the extended array
+};
+
+struct Key {
+    uint64_t *d = nullptr;  // device [dnum][2][L+1+alpha][N], evaluation form
+};
+
+struct Scratch {
+    uint64_t *buf = nullptr;
+    size_t words = 0;
+};
+
+}  // namespace nj
+
+struct nj_ctx {
+    int log_n, N, n_q, L, alpha, dnum, n_primes;
+    double scale;
+    int device;
+    std::vector<uint64_t> primes;  // q_0..q_L, p_0..p_{alpha-1}
+    nj::PrimeInfo *d_info = nullptr;
+    std::vector<nj::PrimeInfo> info;
+    double *d_tw = nullptr, *d_twq = nullptr, *d_itw = nullptr, *d_itwq = nullptr;  // [n_primes][N]
+    // ModUp tables [level][digit]; ModDown tables [level]
+    std::vector<std::vector<nj::BconvTab>> modup;
+    std::vector<nj::BconvTab> moddown;
+    std::vector<double> pinv_q;   // P^{-1} mod q_i (host)
+    std::vector<double> pmod;     // P mod every prime (host), 0 for the p's
+    double *d_pinv = nullptr, *d_pinvq = nullptr;  // [n_q] P^{-1} mod q_i and companion
+    double *d_qlinv = nullptr, *d_qlinvq = nullptr;  // [n_q][n_q]: q_l^{-1} mod q_i
+    uint64_t *d_primes = nullptr;                     // [n_primes]
+    double *d_pmod = nullptr;                         // [L+1+alpha] P mod each key limb's prime
+    // secret key in evaluation form [n_primes][N]
+    std::vector<int8_t> s;
+    uint64_t *d_s = nullptr;
+    std::map<uint32_t, nj::Key> keys;
+    nj::Scratch scratch;
+};
+
+struct nj_lt_t {
+    int level, u, n1, n_diag;
+    std::vector<int> js;                 // offsets j (diagonal j*u)
+    std::vector<int> g_of, i_of;         // BSGS split j = g n1 + i
+    std::vector<int> babies, giants;
+    uint64_t *d_diag = nullptr;          // [n_diag][level+1][N] evaluation form
+};
+
+struct nj_plan {
+    int kind;  // 0 conv, 1 CoeffToSlot
+    int N = 0;
+    std::vector<nj_lt_t> lts;
+    // conv layout
+    int W = 0, C = 0, ell = 0, w0 = 0, f = 0;
+};
+
+namespace nj {
+
+// ---------------------------------------------------------------- kernels.hip
+hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s);
+// out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form
+hipError_t launch_elementwise(const nj_ctx *c, int op, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                              const LimbTab &lt, hipStream_t s);
+// out limb i = in limb i read through X -> X^g (evaluation form, contiguous limbs)
+hipError_t launch_automorph(const nj_ctx *c, const uint64_t *in, uint64_t *out, uint32_t g, int n_limbs,
+                            hipStream_t s);
+// basis conversion: input limbs at in + in_off[a]*N (coefficient form) -> bt's targets at out + out_limb*N
+hipError_t launch_bconv(const nj_ctx *c, const BconvTab &bt, const uint64_t *in, const int *in_off, uint64_t *out,
+                        hipStream_t s);
+hipError_t launch_key_ip(const nj_ctx *c, int level, int n_digits, const uint64_t *ext, const uint64_t *key,
+                         uint32_t g, uint64_t *u0, uint64_t *u1, hipStream_t s);
+hipError_t launch_moddown_combine(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv,
+                                  const uint64_t *add, uint32_t g_add, uint64_t *out, hipStream_t s);
+hipError_t launch_lift_last(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_out, uint64_t *dst,
+                            hipStream_t s);
+hipError_t launch_rescale_combine(const nj_ctx *c, int level, const uint64_t *a, const uint64_t *lifted, uint64_t *out,
+                                  hipStream_t s);
+hipError_t launch_pmac(const nj_ctx *c, int level, const uint64_t *ct, const uint64_t *pt, uint64_t *acc, int first,
+                       hipStream_t s);
+hipError_t launch_monomial_half(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, hipStream_t s);
+hipError_t launch_signed_to_rns(const nj_ctx *c, const int64_t *coeffs, const LimbTab &lt, uint64_t *out,
+                                hipStream_t s, const uint64_t *d_primes);
+hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const uint64_t *a, const uint64_t *e,
+                                 const uint64_t *s_eval, const uint64_t *sp_eval, const double *d_pmod, hipStream_t s);
+hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out, const LimbTab &lt,
+                             const double *d_scal, const double *d_scalq, hipStream_t s);
+
+// ------------------------------------------------------------------- ctx.hip
+LimbTab limbs_q(int level);                       // q_0..q_l
+LimbTab limbs_ext(const nj_ctx *c, int level);    // q_0..q_l, p_0..p_{alpha-1}
+uint64_t *scratch_get(nj_ctx *c, size_t words);   // ctx-owned, grows on demand (synchronises)
+int n_digits(const nj_ctx *c, int level);
+
+// ------------------------------------------------------------------ encode.cpp
+void special_idft(int n, std::vector<double> &re, std::vector<double> &im);   // slots -> V^{-1} z
+void special_dft(int n, std::vector<double> &re, std::vector<double> &im);    // V w -> slots
+void encode_slots(int N, const double *z_re, const double *z_im, double scale, int64_t *out);
+void encode_cins(int N, const double *chans, int slice2, double scale, int64_t *out);
+void decode_slots(int N, const double *coeffs, double scale, double *z_re, double *z_im);
+nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
+                               std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim);
+nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
+                              std::vector<std::vector<std::vector<double>>> &dre,
+                              std::vector<std::vector<std::vector<double>>> &dim);
+void bsgs_split(nj_lt_t &lt, int n);
+
+}  // namespace nj

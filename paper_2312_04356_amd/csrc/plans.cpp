@@ -1,0 +1,116 @@
+// Plan construction: fused conv (K' = S'K^) and CoeffToSlot stage groups, encoded
+// as integer plaintexts and kept on the device in evaluation form.
+#include <hip/hip_runtime.h>
+
+#include <set>
+
+#include "internal.h"
+
+using namespace nj;
+
+namespace {
+
+// encode complex diagonals at `scale`, reduce into the level's primes, transform
+nj_status upload_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector<double>> &re,
+                           const std::vector<std::vector<double>> &im, double scale)
+{
+    const size_t N = c->N, plen = N * (lt.level + 1);
+    NJ_HIP(hipMalloc(&lt.d_diag, plen * lt.n_diag * 8));
+    int64_t *tmp = nullptr;
+    NJ_HIP(hipMalloc(&tmp, N * 8));
+    std::vector<int64_t> coeffs(N);
+    for (int d = 0; d < lt.n_diag; d++) {
+        encode_slots(c->N, re[d].data(), im[d].data(), scale, coeffs.data());
+        NJ_HIP(hipMemcpy(tmp, coeffs.data(), N * 8, hipMemcpyHostToDevice));
+        uint64_t *dst = lt.d_diag + (size_t)d * plen;
+        NJ_HIP(launch_signed_to_rns(c, tmp, limbs_q(lt.level), dst, 0, c->d_primes));
+        NJ_HIP(launch_ntt(c, dst, limbs_q(lt.level), false, 0));
+    }
+    NJ_HIP(hipDeviceSynchronize());
+    NJ_HIP(hipFree(tmp));
+    return NJ_OK;
+}
+
+}  // namespace
+
+int plan_galois_impl(const nj_plan *p, std::vector<uint32_t> &gs)
+{
+    std::set<uint32_t> s;
+    const long long n = p->N / 2;
+    auto gal = [&](long long r) {
+        long long rr = ((r % n) + n) % n;
+        uint64_t g = 1, b = 5, e = (uint64_t)rr, m = 2ull * p->N;
+        for (; e; e >>= 1, b = b * b % m)
+            if (e & 1) g = g * b % m;
+        return (uint32_t)g;
+    };
+    for (const auto &lt : p->lts) {
+        for (int i : lt.babies)
+            if (i) s.insert(gal((long long)i * lt.u));
+        for (int g : lt.giants)
+            if (g) s.insert(gal((long long)g * lt.n1 * lt.u));
+    }
+    if (p->kind == 1) s.insert(2u * p->N - 1u);
+    gs.assign(s.begin(), s.end());
+    return (int)gs.size();
+}
+
+extern "C" {
+
+nj_status nj_conv_plan_create(nj_ctx *c, int w0, int f, const double *weights, int n1, nj_plan **out)
+{
+    if (!c || !weights || !out || w0 < 1 || f < 1) return fail(NJ_EINVAL, "nj_conv_plan_create: bad arguments");
+    if (c->L < 1) return fail(NJ_ELEVEL, "nj_conv_plan_create: needs at least two ciphertext primes");
+    nj_plan *p = new nj_plan();
+    p->kind = 0;
+    p->N = c->N;
+    p->lts.resize(1);
+    nj_lt_t &lt = p->lts[0];
+    lt.level = 1;
+    std::vector<std::vector<double>> re, im;
+    nj_status st = build_conv_diagonals(c->N, w0, f, weights, n1, lt, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->ell = lt.u;
+    p->C = (c->N / 2) / lt.u;
+    p->w0 = w0;
+    p->f = f;
+    for (p->W = 1; p->W * p->W < 2 * lt.u; p->W *= 2) {}
+    st = upload_diagonals(c, lt, re, im, (double)c->primes[1]);
+    if (st) {
+        nj_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return NJ_OK;
+}
+
+nj_status nj_cts_plan_create(nj_ctx *c, int groups, nj_plan **out)
+{
+    if (!c || !out) return fail(NJ_EINVAL, "nj_cts_plan_create: null argument");
+    if (groups < 1 || groups > c->L) return fail(NJ_ELEVEL, "nj_cts_plan_create: need 1 <= groups <= L");
+    nj_plan *p = new nj_plan();
+    p->kind = 1;
+    p->N = c->N;
+    std::vector<std::vector<std::vector<double>>> re, im;
+    nj_status st = build_cts_diagonals(c->N, groups, p->lts, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    for (int g = 0; g < groups; g++) {
+        nj_lt_t &lt = p->lts[g];
+        lt.level = c->L - g;
+        st = upload_diagonals(c, lt, re[g], im[g], (double)c->primes[lt.level]);
+        if (st) {
+            nj_plan_destroy(p);
+            return st;
+        }
+    }
+    *out = p;
+    return NJ_OK;
+}
+
+}  // extern "C"

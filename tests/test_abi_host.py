@@ -1,0 +1,81 @@
+"""Host-side checks of the HIP library that need no GPU: exported symbols, the prime
+chain, argument validation, and the library's FP64 encoder against the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.encoding as E
+import oracle.plans as PL
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "neujeans.h")
+
+nj = pytest.importorskip("paper_2312_04356_amd")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nj_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 30
+    lib = ctypes.CDLL(nj.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(nj.EXPORTED), set(names) ^ set(nj.EXPORTED)
+
+
+@pytest.mark.parametrize("name", ["small", "full"])
+def test_prime_chain_matches_oracle(name):
+    w = synth.WORKLOADS[name]
+    got = nj.chain_primes(w["log_n"], w["n_q"], w["alpha"], w["q0_bits"], w["q_bits"], w["p_bits"])
+    want = PL.chain_primes(w["log_n"], w["n_q"], w["alpha"], w["q0_bits"], w["q_bits"], w["p_bits"],
+                           lambda ln, b, c, ex: O.gen_primes(ln, b, c, ex))
+    assert got == want
+    q, p = got
+    assert all(x < 2 ** 50 for x in q + p) and len(set(q + p)) == len(q + p)
+
+
+def test_gen_primes_rejects_bad_arguments():
+    with pytest.raises(nj.NjError):
+        nj.nj_gen_primes(12, 51, 1)
+    with pytest.raises(nj.NjError):
+        nj.nj_gen_primes(16, 20, 10 ** 6)
+
+
+@pytest.mark.parametrize("log_n", [10, 12, 16])
+def test_encoder_agrees_with_oracle_to_one_unit(log_n):
+    N = 1 << log_n
+    rng = np.random.default_rng(log_n)
+    z = rng.uniform(-1, 1, N // 2) + 1j * rng.uniform(-1, 1, N // 2)
+    scale = 2.0 ** 40
+    mine = nj.nj_encode_slots(log_n, z, scale)
+    theirs = E.encode(z, N, scale)
+    diff = np.abs(mine - theirs)
+    assert diff.max() <= 1
+    assert np.count_nonzero(diff) <= N // 100
+    back = nj.nj_decode_slots(log_n, mine.astype(np.float64), scale)
+    assert np.max(np.abs(back - z)) < 1e-9
+
+
+def test_real_cins_encoder_agrees_with_oracle():
+    log_n, ell = 12, 512
+    N = 1 << log_n
+    C = N // (2 * ell)
+    chans = np.random.default_rng(1).uniform(-1, 1, (C, 2 * ell))
+    mine = nj.nj_encode_cins(log_n, chans, 2.0 ** 40)
+    theirs = E.encode(E.real_cins_slots(chans, ell), N, 2.0 ** 40)
+    assert np.abs(mine - theirs).max() <= 1
+
+
+def test_encoder_rejects_bad_slice():
+    with pytest.raises(nj.NjError):
+        nj.nj_encode_cins(12, np.zeros((3, 100)), 1.0)

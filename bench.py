@@ -1,0 +1,239 @@
+"""Benchmark: fused CinS-conv + CoeffToSlot at N=2^16 and key switches per second.
+
+One step = the whole hot path on one ciphertext of the full-size workload
+(N = 2^16, 24 ciphertext primes + 8 special primes, 3x3 conv 16->16 on a 32x32
+image packed as real CinS): BSGS conv with the fused K' = S'K diagonals at level 1,
+rescale, ModRaise to level 23, CoeffToSlot in 3 stage groups, real/imaginary split.
+Inputs (keys, plan diagonals, the encrypted image) are resident in HBM before the
+timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fused CinS-conv+CoeffToSlot ms and keyswitch/s at N=2^16; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ks-iters", type=int, default=50)
+    return ap.parse_args()
+
+
+def pipeline_bytes(g):
+    """Algorithmic HBM bytes of one step: the input ciphertext, every switching key
+    at the level it is used (only the active limbs and digits), every plaintext
+    diagonal, one read and one write of the ciphertext per BSGS group, the
+    ModRaise output and the two output ciphertexts.
+      key(l) = 2 dnum_l (l+1+alpha) N 8,  pt(l) = (l+1) N 8,  ct(l) = 2 (l+1) N 8."""
+    c = g.ctx
+    N, a = c.N, c.alpha
+
+    def key(l):
+        return 2 * (-(-(l + 1) // a)) * (l + 1 + a) * N * 8
+
+    def pt(l):
+        return (l + 1) * N * 8
+
+    def ct(l):
+        return 2 * (l + 1) * N * 8
+
+    b = ct(1) + len(g.conv_plan.galois()) * key(1) + len(g.conv_plan.offsets(0)) * pt(1) + ct(0)
+    b += ct(c.L)  # ModRaise output
+    level = c.L
+    cts_rot = [0] * g.cts_plan.count()
+    n1 = None
+    for t in range(g.cts_plan.count()):
+        b += len(g.cts_plan.offsets(t)) * pt(level) + 2 * ct(level)
+        level -= 1
+    # rotations per group: the plan's Galois elements minus the conjugation, split by group
+    gs = [x for x in g.cts_plan.galois() if x != 2 * N - 1]
+    per_group = group_rotations(g)
+    level = c.L
+    for r in per_group:
+        b += r * key(level)
+        level -= 1
+    b += key(level) + 2 * ct(level)  # conjugation key, two outputs
+    return float(b)
+
+
+def group_rotations(g):
+    """number of key-switched rotations of each CoeffToSlot group (baby steps except 0, giant steps except 0)"""
+    import math
+    out = []
+    for t in range(g.cts_plan.count()):
+        js = g.cts_plan.offsets(t)
+        n1 = int(math.ceil(math.sqrt(len(js))))
+        babies = {j - (j // n1) * n1 for j in js}
+        giants = {j // n1 for j in js}
+        out.append(len(babies - {0}) + len(giants - {0}))
+    return out
+
+
+def cpu_baseline(name):
+    """The oracle on the host: one fused conv at level 1 executed in full, and one
+    rotation (hoisted-baby/plain key switch) and one PMult at each CoeffToSlot level;
+    the CoeffToSlot time is scaled by the plan's rotation and diagonal counts."""
+    import numpy as np
+
+    from oracle.plans import galois_elt
+    from tests.oracle_workload import OracleWorkload
+    t0 = time.time()
+    o = OracleWorkload(name, with_cts=True)
+    o.make_keys(sorted({galois_elt(r, o.N) for r in o.conv_bsgs.rotations()}))
+    ct = o.encrypt_input(1)
+    t = time.perf_counter()
+    y = o.ctx.conv2d_cins(ct, o.conv_bsgs, o.conv_pts)
+    conv_s = time.perf_counter() - t
+    R = o.ring
+    total = conv_s
+    level = R.L
+    x = o.ctx.ct_modraise(y)
+    t = time.perf_counter()
+    x = o.ctx.ct_modraise(y)
+    total += time.perf_counter() - t
+    rng = np.random.default_rng(0)
+    sample = ["conv2d_cins at level 1 (full)", "ModRaise (full)"]
+    for plan, pts in o.cts:
+        g = galois_elt(plan.rotations()[0], o.N)
+        o.make_keys([g])
+        xl = np.stack([np.stack([rng.integers(0, q, o.N, dtype=np.uint64) for q in R.q[:level + 1]])
+                       for _ in range(2)])
+        t = time.perf_counter()
+        o.ctx.apply_galois(level, xl, g)
+        rot_s = time.perf_counter() - t
+        j = sorted(pts)[0]
+        t = time.perf_counter()
+        o.ctx.ct_pmult(level, xl, pts[j])
+        pm_s = time.perf_counter() - t
+        t = time.perf_counter()
+        o.ctx.ct_rescale(level, xl)
+        rs_s = time.perf_counter() - t
+        total += len(plan.rotations()) * rot_s + len(pts) * pm_s + rs_s
+        sample.append("level %d: 1 rotation x%d, 1 PMult x%d, rescale" % (level, len(plan.rotations()), len(pts)))
+        level -= 1
+    g = 2 * o.N - 1
+    o.make_keys([g])
+    xl = np.stack([np.stack([rng.integers(0, q, o.N, dtype=np.uint64) for q in R.q[:level + 1]]) for _ in range(2)])
+    t = time.perf_counter()
+    o.ctx.apply_galois(level, xl, g)
+    total += time.perf_counter() - t
+    sample.append("conjugation at level %d" % level)
+    return {"value": total * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": "; ".join(sample) + "; CoeffToSlot time scaled by the plan's op counts",
+            "wall_s": round(time.time() - t0, 1)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2312_04356_amd.workload import GpuWorkload
+
+    g = GpuWorkload(args.workload, with_cts=True)
+    gctx = g.ctx
+    g.make_keys()
+    ct = g.encrypt_input(1)
+    lvl = gctx.L - g.w["cts_groups"]
+    y = gctx.empty_ct(0)
+    re, im = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+
+    def step():
+        gctx.nj_conv2d_cins(g.conv_plan, ct, y)
+        gctx.nj_coeff_to_slot(g.cts_plan, y, re, im)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # the same steps again with the library's live per-kernel event timing
+    from paper_2312_04356_amd import PROF_KERNELS
+    for k in PROF_KERNELS:
+        gctx.nj_prof_read(k, reset=True)
+    gctx.nj_prof_enable(1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    gctx.nj_prof_enable(0)
+    kern = {}
+    for k, name in PROF_KERNELS.items():
+        n, kms, kby = gctx.nj_prof_read(k, reset=True)
+        if n:
+            kern[name] = {"launches_per_step": n / args.steps, "ms_per_step": kms / args.steps,
+                          "avg_launch_us": 1e3 * kms / n, "gbs": kby / kms / 1e6}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
+    alg = pipeline_bytes(g)
+
+    # key switches per second, one ciphertext per call (plain)
+    ks = {}
+    gk = g.conv_plan.galois()[0]
+    for level in (23, 15, 7):
+        if level > gctx.L:
+            continue
+        x = gctx.empty_ct(level)
+        x.data.random_(0, 2 ** 40)
+        for _ in range(3):
+            gctx.nj_apply_galois(x, gk, x)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.ks_iters):
+            gctx.nj_apply_galois(x, gk, x)
+        e1.record()
+        torch.cuda.synchronize()
+        ks[str(level)] = round(args.ks_iters / (e0.elapsed_time(e1) / 1e3), 1)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "N=2^16 fused CinS conv 3x3 16->16 32x32 + CoeffToSlot (3 groups), 24+8 primes, dnum=3",
+                   "log_n": gctx.log_n, "n_q": gctx.L + 1, "alpha": gctx.alpha,
+                   "cts_groups": g.w["cts_groups"], "host_wall_s": round(wall, 3)},
+        "keyswitch_per_s": {"plain": ks, "galois": gk},
+        "roofline": roofline,
+        "pipeline": {"algorithmic_GB": round(alg / 1e9, 3), "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

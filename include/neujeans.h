@@ -188,6 +188,19 @@ nj_status nj_conv2d_cins(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_c
  * re/im: device [2][L-groups+1][N]. */
 nj_status nj_coeff_to_slot(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, nj_ct *re, nj_ct *im, void *stream);
 
+/* ------------------------------------------------------------ profiling */
+
+/* Live kernel timing for roofline reports: when enabled, the library records HIP
+ * events on the launch stream around every launch of the kernel families below
+ * and accumulates each launch's algorithmic HBM bytes (every input word read once,
+ * every output word written once).  kind: 0/1 NTT 4096-word tile pass forward/inverse,
+ * 2/3 NTT column pass forward/inverse, 4 basis conversion, 5 key inner product,
+ * 6 plaintext multiply-accumulate, 7 other. */
+nj_status nj_prof_enable(nj_ctx *ctx, int on);
+/* Synchronises the device, then returns launches, total ms and total bytes of `kind`
+ * recorded since the last reset; reset = 1 clears the records. */
+nj_status nj_prof_read(nj_ctx *ctx, int kind, int *launches, double *total_ms, double *total_bytes, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,7 +65,13 @@ _SIGS = {
     "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
     "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_prof_enable": (i32, [vp, i32]),
+    "nj_prof_read": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32]),
 }
+
+# live-profiled kernel families (nj_prof_read kinds) and the kernel names rocprofv3 reports for them
+PROF_KERNELS = {0: "k_ntt_tile<false>", 1: "k_ntt_tile<true>", 2: "k_ntt_col<false>", 3: "k_ntt_col<true>",
+                4: "k_bconv", 5: "k_key_ip", 6: "k_pmac", 7: "other"}
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -313,6 +319,16 @@ class Ctx:
         ci, co = ct.c(), out.c()
         _check(_lib.nj_modraise(self.ptr, ctypes.byref(ci), level, ctypes.byref(co), _stream(stream)), "nj_modraise")
         return out.sync_from(co)
+
+    # -- profiling
+    def nj_prof_enable(self, on):
+        _check(_lib.nj_prof_enable(self.ptr, int(on)), "nj_prof_enable")
+
+    def nj_prof_read(self, kind, reset=True):
+        n, ms, by = i32(), dbl(), dbl()
+        _check(_lib.nj_prof_read(self.ptr, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                 int(reset)), "nj_prof_read")
+        return n.value, ms.value, by.value
 
     # -- plans
     def nj_conv_plan_create(self, w0, f, weights, n1=0):

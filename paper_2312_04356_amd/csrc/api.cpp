@@ -64,55 +64,93 @@ const uint64_t *key_of(const nj_ctx *c, uint32_t g)
 nj_status modup_ext(nj_ctx *c, int l, const uint64_t *d, KsBufs &B, hipStream_t s)
 {
     const size_t N = c->N, ne = l + 1 + c->alpha;
-    NJ_HIP(hipMemcpyAsync(B.coef, d, N * (l + 1) * 8, hipMemcpyDeviceToDevice, s));
-    NJ_HIP(launch_ntt(c, B.coef, limbs_q(l), true, s));
-    for (int j = 0; j < n_digits(c, l); j++) {
-        const BconvTab &bt = c->modup[l][j];
-        uint64_t *ext = B.ext + (size_t)j * ne * N;
-        const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
-        int in_off[16];
-        for (int a = 0; a < bt.m; a++) in_off[a] = lo + a;
-        NJ_HIP(launch_bconv(c, bt, B.coef, in_off, ext, s));
-        NJ_HIP(hipMemcpyAsync(ext + (size_t)lo * N, d + (size_t)lo * N, (size_t)(hi - lo) * N * 8,
-                              hipMemcpyDeviceToDevice, s));
-        LimbTab lt;
-        lt.n = bt.n_out;
-        for (int o = 0; o < bt.n_out; o++) lt.pidx[o] = bt.out_pidx[o], lt.off[o] = bt.out_limb[o];
-        NJ_HIP(launch_ntt(c, ext, lt, false, s));
+    LimbTab lq = limbs_q(l);
+    for (int i = 0; i <= l; i++) lq.soff[i] = i;
+    NJ_HIP(launch_ntt(c, B.coef, lq, true, s, d));  // coefficient form of d, out of place
+    // basis conversion of every digit (launches group digits of equal size, 4 at a time);
+    // a digit's own limbs are not copied: the inner product reads them from d
+    const int nd = n_digits(c, l);
+    for (int j0 = 0; j0 < nd;) {
+        BconvBatch bb;
+        bb.n = 0;
+        const int m = c->modup[l][j0].m;
+        int j = j0;
+        for (; j < nd && bb.n < 4 && c->modup[l][j].m == m; j++) {
+            const BconvTab &bt = c->modup[l][j];
+            BconvJob &jb = bb.job[bb.n++];
+            jb.in = B.coef;
+            jb.out = B.ext + (size_t)j * ne * N;
+            jb.hat_inv = bt.hat_inv;
+            jb.hat = bt.hat;
+            jb.m = bt.m;
+            jb.n_out = bt.n_out;
+            for (int a = 0; a < bt.m; a++) jb.in_pidx[a] = bt.in_pidx[a], jb.in_off[a] = j * c->alpha + a;
+            for (int o = 0; o < bt.n_out; o++) jb.out_pidx[o] = bt.out_pidx[o], jb.out_off[o] = bt.out_limb[o];
+        }
+        NJ_HIP(launch_bconv_batch(c, bb, s));
+        j0 = j;
     }
+    // forward transform of every converted limb of every digit, 128 limbs per launch
+    LimbTab lt;
+    lt.n = 0;
+    for (int j = 0; j < nd; j++) {
+        const BconvTab &bt = c->modup[l][j];
+        for (int o = 0; o < bt.n_out; o++) {
+            lt.pidx[lt.n] = bt.out_pidx[o];
+            lt.off[lt.n] = j * (int)ne + bt.out_limb[o];
+            if (++lt.n == NJ_MAX_LIMBS) {
+                NJ_HIP(launch_ntt(c, B.ext, lt, false, s));
+                lt.n = 0;
+            }
+        }
+    }
+    NJ_HIP(launch_ntt(c, B.ext, lt, false, s));
     return NJ_OK;
 }
 
 // Key inner product on the extended digits (read through X -> X^g_ip), then ModDown of
 // both halves; out0 additionally gets `add` read through X -> X^g_add.
-nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *key, uint32_t g_ip, const uint64_t *add, uint32_t g_add,
-                      uint64_t *out0, uint64_t *out1, KsBufs &B, hipStream_t s)
+nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *d_own, const uint64_t *key, uint32_t g_ip, const uint64_t *add,
+                      uint32_t g_add, const uint64_t *acc, uint64_t *out, KsBufs &B, hipStream_t s)
 {
     const size_t N = c->N, ne = l + 1 + c->alpha;
-    uint64_t *u0 = B.u, *u1 = B.u + ne * N;
-    NJ_HIP(launch_key_ip(c, l, n_digits(c, l), B.ext, key, g_ip, u0, u1, s));
-    NJ_HIP(hipMemcpyAsync(B.pc, u0 + (size_t)(l + 1) * N, (size_t)c->alpha * N * 8, hipMemcpyDeviceToDevice, s));
-    NJ_HIP(hipMemcpyAsync(B.pc + (size_t)c->alpha * N, u1 + (size_t)(l + 1) * N, (size_t)c->alpha * N * 8,
-                          hipMemcpyDeviceToDevice, s));
+    NJ_HIP(launch_key_ip2(c, l, B.ext, d_own, key, g_ip, B.u, s));
+    // special-prime limbs of both halves to coefficient form (out of place into pc)
     LimbTab lp;
     lp.n = 2 * c->alpha;
-    for (int k = 0; k < 2 * c->alpha; k++) lp.pidx[k] = c->n_q + k % c->alpha, lp.off[k] = k;
-    NJ_HIP(launch_ntt(c, B.pc, lp, true, s));
-    int in_off[16];
-    for (int a = 0; a < c->alpha; a++) in_off[a] = a;
-    NJ_HIP(launch_bconv(c, c->moddown[l], B.pc, in_off, B.conv, s));
-    NJ_HIP(launch_bconv(c, c->moddown[l], B.pc + (size_t)c->alpha * N, in_off, B.conv + (size_t)(l + 1) * N, s));
+    for (int k = 0; k < 2 * c->alpha; k++) {
+        const int p = k / c->alpha, a = k % c->alpha;
+        lp.pidx[k] = c->n_q + a, lp.off[k] = k, lp.soff[k] = p * (int)ne + l + 1 + a;
+    }
+    NJ_HIP(launch_ntt(c, B.pc, lp, true, s, B.u));
+    BconvBatch bb;
+    bb.n = 2;
+    const BconvTab &bt = c->moddown[l];
+    for (int p = 0; p < 2; p++) {
+        BconvJob &jb = bb.job[p];
+        jb.in = B.pc;
+        jb.out = B.conv + (size_t)p * (l + 1) * N;
+        jb.hat_inv = bt.hat_inv;
+        jb.hat = bt.hat;
+        jb.m = bt.m;
+        jb.n_out = bt.n_out;
+        for (int a = 0; a < bt.m; a++) jb.in_pidx[a] = bt.in_pidx[a], jb.in_off[a] = p * c->alpha + a;
+        for (int o = 0; o < bt.n_out; o++) jb.out_pidx[o] = bt.out_pidx[o], jb.out_off[o] = o;
+    }
+    NJ_HIP(launch_bconv_batch(c, bb, s));
     LimbTab lq;
     lq.n = 2 * (l + 1);
     for (int k = 0; k < 2 * (l + 1); k++) lq.pidx[k] = k % (l + 1), lq.off[k] = k;
     NJ_HIP(launch_ntt(c, B.conv, lq, false, s));
-    NJ_HIP(launch_moddown_combine(c, l, u0, B.conv, add, g_add, out0, s));
-    NJ_HIP(launch_moddown_combine(c, l, u1, B.conv + (size_t)(l + 1) * N, nullptr, 0, out1, s));
+    NJ_HIP(launch_moddown2(c, l, B.u, B.conv, add, g_add, acc, out, s));
     return NJ_OK;
 }
 
 // (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
-nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s)
+// out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out);
+// in and out may alias.
+nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
+                       const uint64_t *acc = nullptr)
 {
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
@@ -127,7 +165,7 @@ nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_
     }
     nj_status st = modup_ext(c, l, B.dtmp, B, s);
     if (st) return st;
-    return ks_from_ext(c, l, key, 1, c0, g, out, out + plen, B, s);
+    return ks_from_ext(c, l, B.dtmp, key, 1, c0, g, acc, out, B, s);
 }
 
 int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
@@ -135,7 +173,7 @@ int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
 {
     const size_t N = c->N, l = lt.level;
-    return N * 2 * (l + 1) * (lt.babies.size() + 2) + ks_words(c, l);
+    return N * 2 * (l + 1) * (lt.babies.size() + lt.giants.size()) + ks_words(c, l);
 }
 
 // sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
@@ -144,11 +182,14 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
 {
     const int l = lt.level, n = c->N / 2;
     const size_t N = c->N, clen = 2 * N * (l + 1);
-    std::vector<const uint64_t *> baby(lt.babies.size());
-    std::vector<uint64_t *> baby_buf(lt.babies.size());
-    for (size_t b = 0; b < lt.babies.size(); b++) baby_buf[b] = A.take(clen);
-    uint64_t *inner = A.take(clen), *rot = A.take(clen);
-    if (!rot) return fail(NJ_ENOMEM, "scratch too small");
+    const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
+    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT)
+        return fail(NJ_EUNSUPPORTED, "BSGS split needs at most 16 baby and 16 giant steps");
+    std::vector<const uint64_t *> baby(nb);
+    std::vector<uint64_t *> baby_buf(nb);
+    for (int b = 0; b < nb; b++) baby_buf[b] = A.take(clen);
+    uint64_t *inner = A.take(clen * ng);
+    if (!inner) return fail(NJ_ENOMEM, "scratch too small");
     for (size_t b = 0; b < lt.babies.size(); b++)
         if (lt.babies[b] != 0 && !key_of(c, galois_of_rot(c, (long long)lt.babies[b] * lt.u)))
             return fail(NJ_ENOKEY, "missing baby-step rotation key");
@@ -172,7 +213,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                 if (st) return st;
                 ext_ready = true;
             }
-            nj_status st = ks_from_ext(c, l, key_of(c, g), g, in, g, baby_buf[b], baby_buf[b] + N * (l + 1), B, s);
+            nj_status st = ks_from_ext(c, l, in + N * (l + 1), key_of(c, g), g, in, g, nullptr, baby_buf[b], B, s);
             if (st) return st;
         } else {
             nj_status st = apply_galois(c, l, in, g, baby_buf[b], A, s);
@@ -180,29 +221,31 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         }
         baby[b] = baby_buf[b];
     }
-    bool first_giant = true;
-    for (int gg : lt.giants) {
-        bool first = true;
-        for (int d = 0; d < lt.n_diag; d++) {
-            if (lt.g_of[d] != gg) continue;
-            const int b = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
-            NJ_HIP(launch_pmac(c, l, baby[b], lt.d_diag + (size_t)d * N * (l + 1), inner, first ? 1 : 0, s));
-            first = false;
+    // every giant step's inner sum in one pass
+    MacPlan mp;
+    mp.nb = nb, mp.ng = ng;
+    for (int b = 0; b < nb; b++) mp.baby[b] = baby[b];
+    for (int g = 0; g < NJ_MAX_GIANT; g++)
+        for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
+    for (int d = 0; d < lt.n_diag; d++) {
+        const int g = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
+        const int b = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
+        mp.d_of[g][b] = d;
+    }
+    NJ_HIP(launch_bsgs_mac(c, l, mp, lt.d_diag, inner, lt.n_diag, s));
+    // out = inner_0 + sum_g rot(inner_g, g n1 u), the sum fused into each rotation's ModDown
+    bool have = false;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] == 0) {
+            NJ_HIP(hipMemcpyAsync(out, inner + (size_t)g * clen, clen * 8, hipMemcpyDeviceToDevice, s));
+            have = true;
         }
-        const uint64_t *src = inner;
-        if (gg != 0) {
-            nj_status st = apply_galois(c, l, inner, galois_of_rot(c, (long long)gg * lt.n1 * lt.u), rot, A, s);
-            if (st) return st;
-            src = rot;
-        }
-        if (first_giant) NJ_HIP(hipMemcpyAsync(out, src, clen * 8, hipMemcpyDeviceToDevice, s));
-        else NJ_HIP(launch_elementwise(c, 0, out, src, out, [&] {
-            LimbTab t;
-            t.n = 2 * (l + 1);
-            for (int k = 0; k < t.n; k++) t.pidx[k] = k % (l + 1), t.off[k] = k;
-            return t;
-        }(), s));
-        first_giant = false;
+    for (int g = 0; g < ng; g++) {
+        if (lt.giants[g] == 0) continue;
+        nj_status st = apply_galois(c, l, inner + (size_t)g * clen, galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u),
+                                    out, A, s, have ? out : nullptr);
+        if (st) return st;
+        have = true;
     }
     (void)n;
     return NJ_OK;
@@ -502,14 +545,20 @@ nj_status nj_keyswitch(nj_ctx *c, const uint64_t *d, int level, uint32_t g, uint
     if (level < 0 || level > c->L) return fail(NJ_ELEVEL, "nj_keyswitch: level out of range");
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "nj_keyswitch: no key for that element");
+    const size_t plen = (size_t)c->N * (level + 1);
     bool ok;
-    Arena A = arena_for(c, ks_words(c, level), ok);
+    Arena A = arena_for(c, ks_words(c, level) + 2 * plen, ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *pair = A.take(2 * plen);
     KsBufs B;
     if (!ks_bufs(c, level, A, B)) return fail(NJ_ENOMEM, "scratch");
     nj_status st = modup_ext(c, level, d, B, S(stream));
     if (st) return st;
-    return ks_from_ext(c, level, key, 1, nullptr, 0, out0, out1, B, S(stream));
+    st = ks_from_ext(c, level, d, key, 1, nullptr, 0, nullptr, pair, B, S(stream));
+    if (st) return st;
+    NJ_HIP(hipMemcpyAsync(out0, pair, plen * 8, hipMemcpyDeviceToDevice, S(stream)));
+    NJ_HIP(hipMemcpyAsync(out1, pair + plen, plen * 8, hipMemcpyDeviceToDevice, S(stream)));
+    return NJ_OK;
 }
 
 nj_status nj_pmult(nj_ctx *c, const nj_ct *in, const uint64_t *pt, nj_ct *out, void *stream)

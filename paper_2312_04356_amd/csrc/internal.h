@@ -10,7 +10,7 @@
 #include "../../include/neujeans.h"
 #include "modarith.h"
 
-#define NJ_MAX_LIMBS 64  // q limbs + p limbs addressed by one launch
+#define NJ_MAX_LIMBS 128  // limbs addressed by one launch
 
 namespace nj {
 
@@ -19,6 +19,7 @@ struct LimbTab {
     int n;
     int pidx[NJ_MAX_LIMBS];  // prime index of each launched limb
     int off[NJ_MAX_LIMBS];   // limb offset from the base pointer, in units of N words
+    int soff[NJ_MAX_LIMBS];  // offset of the limb in an optional separate source buffer
 };
 
 // Per-prime constants resident in device memory (indexed by prime index).
@@ -54,9 +55,53 @@ struct Key {
     uint64_t *d = nullptr;  // device [dnum][2][L+1+alpha][N], evaluation form
 };
 
+// One basis-conversion job (kernel argument): input limbs at in + in_off[a]*N,
+// outputs at out + out_off[o]*N.
+struct BconvJob {
+    const uint64_t *in;
+    uint64_t *out;
+    const double *hat_inv;  // [m] (companions follow, unused here)
+    const double *hat;      // [m][n_out]
+    int m, n_out;
+    int in_pidx[16], in_off[16];
+    int out_pidx[64], out_off[64];
+};
+struct BconvBatch {
+    int n;
+    BconvJob job[4];
+};
+
+#define NJ_MAX_BABY 16
+#define NJ_MAX_GIANT 16
+// BSGS accumulation plan (kernel argument): d_of[g][b] = diagonal index or -1.
+struct MacPlan {
+    int nb, ng;
+    const uint64_t *baby[NJ_MAX_BABY];
+    int d_of[NJ_MAX_GIANT][NJ_MAX_BABY];
+};
+
 struct Scratch {
     uint64_t *buf = nullptr;
     size_t words = 0;
+};
+
+// Live kernel timing: HIP events recorded on the launch stream around each
+// launch of the profiled kernel families, with the launch's algorithmic bytes.
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+enum ProfKind {
+    PROF_NTT_TILE = 0,  // forward tile pass; +1 for the inverse
+    PROF_NTT_TILE_INV,
+    PROF_NTT_COL,       // forward column pass; +1 for the inverse
+    PROF_NTT_COL_INV,
+    PROF_BCONV,
+    PROF_KEYIP,
+    PROF_PMAC,
+    PROF_OTHER,
+    PROF_KINDS
 };
 
 }  // namespace nj
@@ -83,7 +128,22 @@ struct nj_ctx {
     uint64_t *d_s = nullptr;
     std::map<uint32_t, nj::Key> keys;
     nj::Scratch scratch;
+    // live profiling (nj_prof_*)
+    bool prof = false;
+    std::vector<nj::ProfRec> prof_recs;
+    std::vector<hipEvent_t> ev_pool;
 };
+
+namespace nj {
+// Records events around a launch when profiling is on (no-op otherwise).
+struct ProfScope {
+    nj_ctx *c;
+    ProfRec r;
+    hipStream_t s;
+    ProfScope(const nj_ctx *cc, int kind, double bytes, hipStream_t st);
+    ~ProfScope();
+};
+}  // namespace nj
 
 struct nj_lt_t {
     int level, u, n1, n_diag;
@@ -104,7 +164,10 @@ struct nj_plan {
 namespace nj {
 
 // ---------------------------------------------------------------- kernels.hip
-hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s);
+hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s,
+                      const uint64_t *src = nullptr);
+hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
+                           hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form
 hipError_t launch_elementwise(const nj_ctx *c, int op, const uint64_t *a, const uint64_t *b, uint64_t *out,
                               const LimbTab &lt, hipStream_t s);
@@ -131,6 +194,18 @@ hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const 
                                  const uint64_t *s_eval, const uint64_t *sp_eval, const double *d_pmod, hipStream_t s);
 hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out, const LimbTab &lt,
                              const double *d_scal, const double *d_scalq, hipStream_t s);
+
+// ------------------------------------------------------------------- ksw.hip
+hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t s);
+// u [2][l+1+alpha][N]; the digit's own limbs are read from d
+hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
+                          uint32_t g, uint64_t *u, hipStream_t s);
+// out = acc + (u - conv) P^-1 + (p == 0 ? add o X^g_add : 0), both halves; acc/add may be null
+hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv, const uint64_t *add,
+                           uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s);
+// inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
+hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
+                           int n_diag, hipStream_t s);
 
 // ------------------------------------------------------------------- ctx.hip
 LimbTab limbs_q(int level);                       // q_0..q_l

@@ -120,9 +120,18 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(uint64_t *data, LimbTab l
     for (int e = threadIdx.x; e < T; e += kThreads) a[e] = d2u(s[e]);
 }
 
-hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s)
+hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s,
+                      const uint64_t *src)
 {
     if (lt.n == 0) return hipSuccess;
+    if (c->N >= kTile) return launch_ntt_fast(c, data, src, lt, inverse, s);
+    if (src) {  // generic kernels work in place
+        for (int i = 0; i < lt.n; i++) {
+            hipError_t e = hipMemcpyAsync(data + (size_t)lt.off[i] * c->N, src + (size_t)lt.soff[i] * c->N,
+                                          (size_t)c->N * 8, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+    }
     const int N = c->N, T = N < kTile ? N : kTile, N1 = N / T;
     dim3 grid(N1, lt.n);
     if (!inverse) {
@@ -249,6 +258,7 @@ hipError_t launch_bconv_args(const nj_ctx *c, const BconvArgs &ba, const double 
                              const double *hat, const uint64_t *in, uint64_t *out, hipStream_t s)
 {
     dim3 grid((c->N + kThreads - 1) / kThreads, (ba.n_out + 7) / 8);
+    ProfScope ps(c, PROF_BCONV, 8.0 * c->N * (ba.m + ba.n_out), s);
     hipLaunchKernelGGL(k_bconv, grid, dim3(kThreads), 0, s, in, out, ba, hat_inv, hat_inv_q, hat, c->d_info,
                        c->log_n);
     return hipGetLastError();
@@ -290,6 +300,7 @@ hipError_t launch_key_ip(const nj_ctx *c, int level, int n_digits, const uint64_
                          uint32_t g, uint64_t *u0, uint64_t *u1, hipStream_t s)
 {
     dim3 grid((c->N + kThreads - 1) / kThreads, level + 1 + c->alpha);
+    ProfScope ps(c, PROF_KEYIP, 8.0 * c->N * (level + 1 + c->alpha) * (3.0 * n_digits + 2.0), s);
     hipLaunchKernelGGL(k_key_ip, grid, dim3(kThreads), 0, s, ext, key, u0, u1, g, n_digits, level, c->L, c->alpha,
                        c->n_q, c->d_info, c->log_n);
     return hipGetLastError();
@@ -390,6 +401,7 @@ hipError_t launch_pmac(const nj_ctx *c, int level, const uint64_t *ct, const uin
                        hipStream_t s)
 {
     dim3 grid((c->N + kThreads - 1) / kThreads, 2 * (level + 1));
+    ProfScope ps(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (first ? 5.0 : 7.0), s);
     hipLaunchKernelGGL(k_pmac, grid, dim3(kThreads), 0, s, ct, pt, acc, level, first, c->d_info, c->log_n);
     return hipGetLastError();
 }

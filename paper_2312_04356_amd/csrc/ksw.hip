@@ -1,0 +1,200 @@
+// Hybrid key switching and BSGS accumulation kernels (gfx950).
+//
+//  * k_bconv_batch: fast basis conversion y_t = sum_a [x_a (D/q_a)^-1]_{q_a} (D/q_a) mod t
+//    for up to 4 jobs per launch (the digits of one ModUp, or the two halves of one
+//    ModDown).  The digit size M is a template parameter so the scaled residues stay
+//    in registers.  Thread per coefficient, blockIdx.y = chunk of 8 targets,
+//    blockIdx.z = job.
+//  * k_key_ip2: key inner product over the extended limbs; a digit's own limbs are
+//    read from the switched polynomial itself, so ModUp never copies them.
+//  * k_moddown2: (u - conv) P^-1 for both halves, plus the rotated c0 and an
+//    optional running sum (giant-step accumulation).
+//  * k_bsgs_mac: every giant step's inner sum sum_i baby_i (.) diag_{g,i} in one pass:
+//    each baby and each diagonal word is read once.
+#include "internal.h"
+
+namespace nj {
+
+constexpr int kBT = 256;
+
+__device__ __forceinline__ uint32_t brev_n(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
+
+__device__ __forceinline__ int galois_src2(int k, uint32_t g, int logN)
+{
+    const uint32_t N = 1u << logN;
+    uint32_t e = 2u * brev_n((uint32_t)k, logN) + 1u;
+    uint32_t eg = (uint32_t)(((uint64_t)e * g) & (2u * N - 1u));
+    return (int)brev_n((eg - 1u) >> 1, logN);
+}
+
+// ------------------------------------------------------------ basis conversion
+
+template <int M>
+__global__ __launch_bounds__(kBT) void k_bconv_batch(BconvBatch bb, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const BconvJob &jb = bb.job[blockIdx.z];
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    const int o0 = blockIdx.y * 8;
+    if (k >= N || o0 >= jb.n_out) return;
+    double v[M];
+#pragma unroll
+    for (int a = 0; a < M; a++) {
+        const Mod ma = info[jb.in_pidx[a]].m;
+        v[a] = mul_canon(u2d(jb.in[(size_t)jb.in_off[a] * N + k]), jb.hat_inv[a], ma);
+    }
+    const int o1 = min(o0 + 8, jb.n_out);
+    for (int o = o0; o < o1; o++) {
+        const Mod mt = info[jb.out_pidx[o]].m;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; a++) {
+            acc += mul_lazy(v[a], jb.hat[a * jb.n_out + o], mt);  // each term in (-t, t)
+            if ((a & 7) == 7) acc = reduce(acc, mt);
+        }
+        jb.out[(size_t)jb.out_off[o] * N + k] = d2u(reduce(acc, mt));
+    }
+}
+
+hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t s)
+{
+    if (bb.n == 0) return hipSuccess;
+    int max_out = 0, m = bb.job[0].m;
+    double bytes = 0;
+    for (int j = 0; j < bb.n; j++) {
+        max_out = max(max_out, bb.job[j].n_out);
+        if (bb.job[j].m != m) return hipErrorInvalidValue;
+        bytes += 8.0 * c->N * (bb.job[j].m + bb.job[j].n_out);
+    }
+    dim3 grid((c->N + kBT - 1) / kBT, (max_out + 7) / 8, bb.n);
+    ProfScope ps(c, PROF_BCONV, bytes, s);
+    switch (m) {
+#define NJ_BC(MM) \
+    case MM: hipLaunchKernelGGL(k_bconv_batch<MM>, grid, dim3(kBT), 0, s, bb, c->d_info, c->log_n); break;
+        NJ_BC(1) NJ_BC(2) NJ_BC(3) NJ_BC(4) NJ_BC(5) NJ_BC(6) NJ_BC(7) NJ_BC(8)
+        NJ_BC(9) NJ_BC(10) NJ_BC(11) NJ_BC(12) NJ_BC(13) NJ_BC(14) NJ_BC(15) NJ_BC(16)
+#undef NJ_BC
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- key inner product
+
+__global__ __launch_bounds__(kBT) void k_key_ip2(const uint64_t *ext, const uint64_t *d, const uint64_t *key,
+                                                uint64_t *u, uint32_t g, int n_digits, int level, int L, int alpha,
+                                                int nq, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int t = blockIdx.y;
+    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
+    const int pidx = t <= level ? t : nq + (t - level - 1);
+    const int kl = t <= level ? t : L + 1 + (t - level - 1);
+    const int own = t <= level ? t / alpha : -1;  // digit whose own limb this is
+    const Mod m = info[pidx].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const int src = g == 1u ? k : galois_src2(k, g, logN);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int j = 0; j < n_digits; j++) {
+        const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
+        double x = u2d(xp[src]);
+        double kb = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
+        double ka = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
+        acc0 += mul_lazy(x, kb, m);
+        acc1 += mul_lazy(x, ka, m);
+        if ((j & 7) == 7) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+    }
+    u[(size_t)t * N + k] = d2u(reduce(acc0, m));
+    u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+}
+
+hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
+                          uint32_t g, uint64_t *u, hipStream_t s)
+{
+    const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
+    dim3 grid((c->N + kBT - 1) / kBT, ne);
+    ProfScope ps(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), s);
+    hipLaunchKernelGGL(k_key_ip2, grid, dim3(kBT), 0, s, ext, d, key, u, g, nd, level, c->L, c->alpha, c->n_q,
+                       c->d_info, c->log_n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ ModDown
+
+// out_p[i] = acc_p[i] + (u_p[i] - conv_p[i]) P^-1 (+ add[i] read through X -> X^g_add for p = 0)
+__global__ __launch_bounds__(kBT) void k_moddown2(const uint64_t *u, const uint64_t *conv, const uint64_t *add,
+                                                 uint32_t g_add, const uint64_t *acc, uint64_t *out, int level,
+                                                 int ne, const double *pinv, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y, p = blockIdx.z;
+    const Mod m = info[i].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    double r = mul_canon(sub_mod(u2d(u[((size_t)p * ne + i) * N + k]), u2d(conv[((size_t)p * (level + 1) + i) * N + k]), m),
+                         pinv[i], m);
+    if (p == 0 && add) {
+        const int src = g_add <= 1u ? k : galois_src2(k, g_add, logN);
+        r = add_mod(r, u2d(add[(size_t)i * N + src]), m);
+    }
+    const size_t o = ((size_t)p * (level + 1) + i) * N + k;
+    if (acc) r = add_mod(r, u2d(acc[o]), m);
+    out[o] = d2u(r);
+}
+
+hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv, const uint64_t *add,
+                           uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s)
+{
+    dim3 grid((c->N + kBT - 1) / kBT, level + 1, 2);
+    ProfScope ps(c, PROF_OTHER, 8.0 * c->N * (level + 1) * (add ? 7.0 : 6.0) + (acc ? 16.0 * c->N * (level + 1) : 0), s);
+    hipLaunchKernelGGL(k_moddown2, grid, dim3(kBT), 0, s, u, conv, add, g_add, acc, out, level, level + 1 + c->alpha,
+                       c->d_pinv, c->d_info, c->log_n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- BSGS
+
+__global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *diag, uint64_t *inner, int level,
+                                                 const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const Mod m = info[i].m;
+    const size_t L1 = level + 1;
+    double b0[NJ_MAX_BABY], b1[NJ_MAX_BABY];
+#pragma unroll
+    for (int b = 0; b < NJ_MAX_BABY; b++) {
+        if (b < mp.nb) {
+            b0[b] = u2d(mp.baby[b][(size_t)i * N + k]);
+            b1[b] = u2d(mp.baby[b][(L1 + i) * N + k]);
+        }
+    }
+    for (int g = 0; g < mp.ng; g++) {
+        double a0 = 0.0, a1 = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int b = 0; b < NJ_MAX_BABY; b++) {
+            if (b >= mp.nb) break;
+            const int dg = mp.d_of[g][b];
+            if (dg < 0) continue;
+            const double w = u2d(diag[((size_t)dg * L1 + i) * N + k]);
+            a0 += mul_lazy(b0[b], w, m);
+            a1 += mul_lazy(b1[b], w, m);
+            if ((++cnt & 7) == 0) a0 = reduce(a0, m), a1 = reduce(a1, m);
+        }
+        inner[((size_t)g * 2 * L1 + i) * N + k] = d2u(reduce(a0, m));
+        inner[((size_t)(g * 2 + 1) * L1 + i) * N + k] = d2u(reduce(a1, m));
+    }
+}
+
+hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
+                           int n_diag, hipStream_t s)
+{
+    dim3 grid((c->N + kBT - 1) / kBT, level + 1);
+    ProfScope ps(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + 2.0 * mp.ng), s);
+    hipLaunchKernelGGL(k_bsgs_mac, grid, dim3(kBT), 0, s, mp, diag, inner, level, c->d_info, c->log_n);
+    return hipGetLastError();
+}
+
+}  // namespace nj

@@ -1,0 +1,232 @@
+// Negacyclic NTT over RNS limbs for N >= 4096 (gfx950).
+//
+// Same transform as the LDS-staged generic kernels (forward Cooley-Tukey stages
+// m = 1..N/2 with psi^rev(m+i), inverse Gentleman-Sande with psi^-rev(h+i) and
+// N^-1), organised for registers:
+//   * N = N1 * 4096.  The first log2(N1) stages couple words with equal index
+//     mod 4096: one thread owns a whole column of N1 words (coalesced loads at
+//     stride 4096, twiddles uniform across the wavefront) - no LDS at all.
+//   * The last 12 stages stay inside a 4096-word tile: 256 threads own 16 words
+//     each and run 3 rounds of 4 radix-2 stages in registers; between rounds the
+//     tile goes through LDS once (padded by one word every 16 to avoid bank
+//     conflicts).  Global loads and stores are fully coalesced.
+// A round covering strides t0, t0/2, t0/4, t0/8 gives thread (lo, hi) the words
+// x_k = lo + (t0/8) k + 2 t0 hi, k < 16; at stride t0/2^s the pair (k, k + 8>>s)
+// belongs to butterfly block hi 2^s + (k >> (4-s)) of the tile.
+#include "internal.h"
+
+namespace nj {
+
+constexpr int kT = 4096;
+constexpr int kNT = 256;
+
+__device__ __forceinline__ int pad16(int x) { return x + (x >> 4); }
+
+// one round of 4 forward stages on 16 registers (strides t0 .. t0/8 within the tile)
+__device__ __forceinline__ void ct_round(double v[16], int t0, int hi, int tile, int logN1, const double *W, int N,
+                                         Mod m)
+{
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int t = t0 >> s;               // tile stride
+        const int mm = N / (2 * t);          // global stage
+        const int base = mm + tile * (mm >> logN1) + (hi << s);
+        const int step = 8 >> s;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k & step) continue;
+            const double w = W[base + (k >> (4 - s))];
+            double U = v[k], V = mul_canon(v[k + step], w, m);
+            v[k] = add_mod(U, V, m);
+            v[k + step] = sub_mod(U, V, m);
+        }
+    }
+}
+
+// one round of 4 inverse stages (strides t0/8 .. t0)
+__device__ __forceinline__ void gs_round(double v[16], int t0, int hi, int tile, int logN1, const double *W, int N,
+                                         Mod m)
+{
+#pragma unroll
+    for (int s = 3; s >= 0; s--) {
+        const int t = t0 >> s;
+        const int hh = N / (2 * t);
+        const int base = hh + tile * (hh >> logN1) + (hi << s);
+        const int step = 8 >> s;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k & step) continue;
+            const double w = W[base + (k >> (4 - s))];
+            double U = v[k], V = v[k + step];
+            v[k] = add_mod(U, V, m);
+            v[k + step] = mul_canon(sub_mod(U, V, m), w, m);
+        }
+    }
+}
+
+// rows pass: last 12 stages on 4096-word tiles.  grid (N/4096, limbs)
+template <bool INV>
+__global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
+                                                  const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int limb = blockIdx.y, pidx = lt.pidx[limb], tile = blockIdx.x, tid = threadIdx.x;
+    const PrimeInfo pi = info[pidx];
+    const Mod m = pi.m;
+    const size_t off = (size_t)lt.off[limb] * N + (size_t)tile * kT;
+    const uint64_t *in = src ? src + (size_t)lt.soff[limb] * N + (size_t)tile * kT : data + off;
+    uint64_t *out = data + off;
+    const double *W = tw + (size_t)pidx * N;
+    double v[16];
+    if (!INV) {
+        // round 0: strides 2048..256, thread tid owns x = tid + 256 k
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
+        ct_round(v, 2048, 0, tile, logN1, W, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+        __syncthreads();
+        // round 1: strides 128..16, (lo, hi) = (tid & 15, tid >> 4): x = lo + 16 k + 256 hi
+        {
+            const int lo = tid & 15, hi = tid >> 4;
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+            ct_round(v, 128, hi, tile, logN1, W, N, m);
+#pragma unroll
+            for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+        }
+        __syncthreads();
+        // round 2: strides 8..1, thread owns x = 16 tid + k
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+        ct_round(v, 8, tid, tile, logN1, W, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; k++) out[tid + 256 * k] = d2u(s[pad16(tid + 256 * k)]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = u2d(in[tid + 256 * k]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+        gs_round(v, 8, tid, tile, logN1, W, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+        __syncthreads();
+        {
+            const int lo = tid & 15, hi = tid >> 4;
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+            gs_round(v, 128, hi, tile, logN1, W, N, m);
+#pragma unroll
+            for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(tid + 256 * k)];
+        gs_round(v, 2048, 0, tile, logN1, W, N, m);
+        if (logN1 == 0) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = mul_canon(v[k], pi.ninv, m);
+        }
+#pragma unroll
+        for (int k = 0; k < 16; k++) out[tid + 256 * k] = d2u(v[k]);
+    }
+}
+
+// columns pass: first log2(N1) stages, one column of N1 words per thread.  grid (4096/256, limbs)
+template <int N1, bool INV>
+__global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
+                                                 const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int limb = blockIdx.y, pidx = lt.pidx[limb];
+    const PrimeInfo pi = info[pidx];
+    const Mod m = pi.m;
+    const int c = blockIdx.x * kNT + threadIdx.x;
+    const size_t off = (size_t)lt.off[limb] * N + c;
+    const uint64_t *in = src ? src + (size_t)lt.soff[limb] * N + c : data + off;
+    uint64_t *out = data + off;
+    const double *W = tw + (size_t)pidx * N;
+    double v[N1];
+#pragma unroll
+    for (int r = 0; r < N1; r++) v[r] = u2d(in[(size_t)r * kT]);
+    if (!INV) {
+#pragma unroll
+        for (int mm = 1; mm < N1; mm <<= 1) {
+            const int tr = N1 / (2 * mm);
+#pragma unroll
+            for (int r = 0; r < N1; r++) {
+                if (r & tr) continue;
+                const double w = W[mm + r / (2 * tr)];
+                double U = v[r], V = mul_canon(v[r + tr], w, m);
+                v[r] = add_mod(U, V, m);
+                v[r + tr] = sub_mod(U, V, m);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int h = N1 / 2; h >= 1; h >>= 1) {
+            const int tr = N1 / (2 * h);
+#pragma unroll
+            for (int r = 0; r < N1; r++) {
+                if (r & tr) continue;
+                const double w = W[h + r / (2 * tr)];
+                double U = v[r], V = v[r + tr];
+                v[r] = add_mod(U, V, m);
+                v[r + tr] = mul_canon(sub_mod(U, V, m), w, m);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N1; r++) v[r] = mul_canon(v[r], pi.ninv, m);
+    }
+#pragma unroll
+    for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(v[r]);
+}
+
+template <bool INV>
+static void launch_cols(int N1, dim3 grid, hipStream_t s, uint64_t *data, const uint64_t *src, const LimbTab &lt,
+                        const double *tw, const PrimeInfo *info, int logN)
+{
+    switch (N1) {
+    case 2: hipLaunchKernelGGL((k_ntt_col<2, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
+    case 4: hipLaunchKernelGGL((k_ntt_col<4, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
+    case 8: hipLaunchKernelGGL((k_ntt_col<8, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
+    default: hipLaunchKernelGGL((k_ntt_col<16, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
+    }
+}
+
+// N >= 4096: forward = columns then tiles, inverse = tiles then columns.  src (optional)
+// is read instead of data by the first pass (same limb offsets).
+hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
+                           hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    const double *tw = inverse ? c->d_itw : c->d_tw;
+    dim3 gt(N1, lt.n), gc(kT / kNT, lt.n);
+    const double bytes = 16.0 * N * lt.n;  // each pass reads and writes every word once
+    if (!inverse) {
+        if (N1 > 1) {
+            ProfScope ps(c, PROF_NTT_COL, bytes, s);
+            launch_cols<false>(N1, gc, s, data, src, lt, tw, c->d_info, c->log_n);
+            src = nullptr;
+        }
+        ProfScope ps(c, PROF_NTT_TILE, bytes, s);
+        hipLaunchKernelGGL(k_ntt_tile<false>, gt, dim3(kNT), 0, s, data, src, lt, tw, c->d_info, c->log_n);
+    } else {
+        {
+            ProfScope ps(c, PROF_NTT_TILE_INV, bytes, s);
+            hipLaunchKernelGGL(k_ntt_tile<true>, gt, dim3(kNT), 0, s, data, src, lt, tw, c->d_info, c->log_n);
+        }
+        if (N1 > 1) {
+            ProfScope ps(c, PROF_NTT_COL_INV, bytes, s);
+            launch_cols<true>(N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nj

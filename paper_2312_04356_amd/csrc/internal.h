@@ -134,6 +134,8 @@ struct nj_ctx {
     std::vector<hipEvent_t> ev_pool;
 };
 
+#include <hip/hip_ext.h>
+
 namespace nj {
 // Records events around a launch when profiling is on (no-op otherwise).
 struct ProfScope {
@@ -143,6 +145,23 @@ struct ProfScope {
     ProfScope(const nj_ctx *cc, int kind, double bytes, hipStream_t st);
     ~ProfScope();
 };
+
+// Events for one profiled launch (pushed into the context's records), or false.
+bool prof_events(const nj_ctx *c, int kind, double bytes, hipEvent_t *a, hipEvent_t *b);
+
+// Kernel launch; when profiling, hipExtLaunchKernelGGL has the dispatch itself
+// timestamp its start and end into two events (kernel time only, no host gaps).
+template <typename F, typename... Args>
+inline hipError_t launch(const nj_ctx *c, int kind, double bytes, F kernel, dim3 grid, dim3 block, hipStream_t s,
+                         Args... args)
+{
+    hipEvent_t a, b;
+    if (c->prof && prof_events(c, kind, bytes, &a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    return hipGetLastError();
+}
 }  // namespace nj
 
 struct nj_lt_t {

@@ -67,16 +67,14 @@ hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t
         bytes += 8.0 * c->N * (bb.job[j].m + bb.job[j].n_out);
     }
     dim3 grid((c->N + kBT - 1) / kBT, (max_out + 7) / 8, bb.n);
-    ProfScope ps(c, PROF_BCONV, bytes, s);
     switch (m) {
 #define NJ_BC(MM) \
-    case MM: hipLaunchKernelGGL(k_bconv_batch<MM>, grid, dim3(kBT), 0, s, bb, c->d_info, c->log_n); break;
+    case MM: return launch(c, PROF_BCONV, bytes, k_bconv_batch<MM>, grid, dim3(kBT), s, bb, c->d_info, c->log_n);
         NJ_BC(1) NJ_BC(2) NJ_BC(3) NJ_BC(4) NJ_BC(5) NJ_BC(6) NJ_BC(7) NJ_BC(8)
         NJ_BC(9) NJ_BC(10) NJ_BC(11) NJ_BC(12) NJ_BC(13) NJ_BC(14) NJ_BC(15) NJ_BC(16)
 #undef NJ_BC
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------- key inner product
@@ -114,10 +112,8 @@ hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
     dim3 grid((c->N + kBT - 1) / kBT, ne);
-    ProfScope ps(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), s);
-    hipLaunchKernelGGL(k_key_ip2, grid, dim3(kBT), 0, s, ext, d, key, u, g, nd, level, c->L, c->alpha, c->n_q,
-                       c->d_info, c->log_n);
-    return hipGetLastError();
+    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), k_key_ip2, grid, dim3(kBT), s, ext, d, key, u, g,
+                  nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
 }
 
 // ------------------------------------------------------------------ ModDown
@@ -146,10 +142,9 @@ hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const 
                            uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s)
 {
     dim3 grid((c->N + kBT - 1) / kBT, level + 1, 2);
-    ProfScope ps(c, PROF_OTHER, 8.0 * c->N * (level + 1) * (add ? 7.0 : 6.0) + (acc ? 16.0 * c->N * (level + 1) : 0), s);
-    hipLaunchKernelGGL(k_moddown2, grid, dim3(kBT), 0, s, u, conv, add, g_add, acc, out, level, level + 1 + c->alpha,
-                       c->d_pinv, c->d_info, c->log_n);
-    return hipGetLastError();
+    return launch(c, PROF_OTHER, 8.0 * c->N * (level + 1) * (add ? 7.0 : 6.0) + (acc ? 16.0 * c->N * (level + 1) : 0),
+                  k_moddown2, grid, dim3(kBT), s, u, conv, add, g_add, acc, out, level, level + 1 + c->alpha, c->d_pinv,
+                  c->d_info, c->log_n);
 }
 
 // ------------------------------------------------------------------- BSGS
@@ -192,9 +187,8 @@ hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const 
                            int n_diag, hipStream_t s)
 {
     dim3 grid((c->N + kBT - 1) / kBT, level + 1);
-    ProfScope ps(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + 2.0 * mp.ng), s);
-    hipLaunchKernelGGL(k_bsgs_mac, grid, dim3(kBT), 0, s, mp, diag, inner, level, c->d_info, c->log_n);
-    return hipGetLastError();
+    return launch(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + 2.0 * mp.ng), k_bsgs_mac, grid,
+                  dim3(kBT), s, mp, diag, inner, level, c->d_info, c->log_n);
 }
 
 }  // namespace nj

@@ -188,19 +188,20 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
 }
 
 template <bool INV>
-static void launch_cols(int N1, dim3 grid, hipStream_t s, uint64_t *data, const uint64_t *src, const LimbTab &lt,
-                        const double *tw, const PrimeInfo *info, int logN)
+static hipError_t launch_cols(const nj_ctx *c, int kind, double bytes, int N1, dim3 grid, hipStream_t s,
+                              uint64_t *data, const uint64_t *src, const LimbTab &lt, const double *tw,
+                              const PrimeInfo *info, int logN)
 {
     switch (N1) {
-    case 2: hipLaunchKernelGGL((k_ntt_col<2, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
-    case 4: hipLaunchKernelGGL((k_ntt_col<4, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
-    case 8: hipLaunchKernelGGL((k_ntt_col<8, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
-    default: hipLaunchKernelGGL((k_ntt_col<16, INV>), grid, dim3(kNT), 0, s, data, src, lt, tw, info, logN); break;
+    case 2: return launch(c, kind, bytes, k_ntt_col<2, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
+    case 4: return launch(c, kind, bytes, k_ntt_col<4, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
+    case 8: return launch(c, kind, bytes, k_ntt_col<8, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
+    default: return launch(c, kind, bytes, k_ntt_col<16, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
     }
 }
 
 // N >= 4096: forward = columns then tiles, inverse = tiles then columns.  src (optional)
-// is read instead of data by the first pass (same limb offsets).
+// is read instead of data by the first pass (limb i at src + soff[i]*N).
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s)
 {
@@ -208,25 +209,19 @@ hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src,
     const double *tw = inverse ? c->d_itw : c->d_tw;
     dim3 gt(N1, lt.n), gc(kT / kNT, lt.n);
     const double bytes = 16.0 * N * lt.n;  // each pass reads and writes every word once
+    hipError_t e;
     if (!inverse) {
         if (N1 > 1) {
-            ProfScope ps(c, PROF_NTT_COL, bytes, s);
-            launch_cols<false>(N1, gc, s, data, src, lt, tw, c->d_info, c->log_n);
+            e = launch_cols<false>(c, PROF_NTT_COL, bytes, N1, gc, s, data, src, lt, tw, c->d_info, c->log_n);
+            if (e != hipSuccess) return e;
             src = nullptr;
         }
-        ProfScope ps(c, PROF_NTT_TILE, bytes, s);
-        hipLaunchKernelGGL(k_ntt_tile<false>, gt, dim3(kNT), 0, s, data, src, lt, tw, c->d_info, c->log_n);
-    } else {
-        {
-            ProfScope ps(c, PROF_NTT_TILE_INV, bytes, s);
-            hipLaunchKernelGGL(k_ntt_tile<true>, gt, dim3(kNT), 0, s, data, src, lt, tw, c->d_info, c->log_n);
-        }
-        if (N1 > 1) {
-            ProfScope ps(c, PROF_NTT_COL_INV, bytes, s);
-            launch_cols<true>(N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
-        }
+        return launch(c, PROF_NTT_TILE, bytes, k_ntt_tile<false>, gt, dim3(kNT), s, data, src, lt, tw, c->d_info,
+                      c->log_n);
     }
-    return hipGetLastError();
+    e = launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, gt, dim3(kNT), s, data, src, lt, tw, c->d_info, c->log_n);
+    if (e != hipSuccess || N1 == 1) return e;
+    return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
 }
 
 }  // namespace nj

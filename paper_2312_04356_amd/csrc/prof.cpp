@@ -28,6 +28,20 @@ ProfScope::ProfScope(const nj_ctx *cc, int kind, double bytes, hipStream_t st) :
     if (r.a) (void)hipEventRecord(r.a, s);
 }
 
+bool prof_events(const nj_ctx *cc, int kind, double bytes, hipEvent_t *a, hipEvent_t *b)
+{
+    nj_ctx *c = const_cast<nj_ctx *>(cc);
+    ProfRec r;
+    r.kind = kind;
+    r.bytes = bytes;
+    r.a = take_event(c);
+    r.b = take_event(c);
+    if (!r.a || !r.b) return false;
+    c->prof_recs.push_back(r);
+    *a = r.a, *b = r.b;
+    return true;
+}
+
 ProfScope::~ProfScope()
 {
     if (!c->prof || !r.a || !r.b) return;

@@ -1,0 +1,67 @@
+"""Summarises a rocprofv3 kernel trace (CSV output) next to a bench.py JSON line.
+
+    python -m paper_2312_04356_amd.prof_summary <kernel_trace.csv> <bench.json> "<command>" > summary.md
+
+For every kernel family the bench line reports (launches per step x steps), the
+last that-many dispatches in the trace are the bench's live-profiled steps (the
+last GPU work of a bench run); their average duration is set beside the value
+bench.py measured with HIP events.  Whole-run totals per kernel follow.
+"""
+import csv
+import json
+import re
+import sys
+from collections import defaultdict
+
+
+def family(name):
+    n = re.sub(r"\(.*", "", name)
+    n = n.replace("void ", "").replace("nj::", "")
+    n = re.sub(r"k_ntt_col<\d+, (false|true)>", r"k_ntt_col<\1>", n)
+    n = n.replace("k_bconv_batch<", "k_bconv<").strip()
+    n = re.sub(r"k_bconv<\d+>", "k_bconv", n)
+    n = n.replace("k_key_ip2", "k_key_ip").replace("k_bsgs_mac", "k_pmac").replace("k_moddown2", "other")
+    return n
+
+
+def main(trace, bench_json, command):
+    rows = list(csv.DictReader(open(trace)))
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    steps = bench["steps"]
+    by = defaultdict(list)
+    for r in rows:
+        by[family(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    print("# rocprofv3 kernel summary: %s" % bench["config"]["workload"])
+    print()
+    print("Command (repository root; rocprofv3 run from /tmp):")
+    print()
+    print("    " + command)
+    print()
+    print("bench.py line of the same run: %.4f ms per step, %d steps; dominant kernel %s, %.2f us per launch "
+          "(HIP events), %.1f GB/s algorithmic (%.1f%% of 8 TB/s)."
+          % (bench["value"], steps, bench["roofline"]["kernel"], bench["roofline"]["avg_launch_us"],
+             bench["roofline"]["achieved"], 100 * bench["roofline"]["frac"]))
+    print()
+    print("## Live-profiled steps: rocprofv3 vs HIP events")
+    print()
+    print("| kernel | launches/step | rocprofv3 avg us | HIP-event avg us | ms/step (events) |")
+    print("|---|---|---|---|---|")
+    for k, v in sorted(bench["pipeline"]["kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        n = int(round(v["launches_per_step"] * steps))
+        d = by.get(k, [])[-n:] if n else []
+        avg = sum(d) / len(d) / 1e3 if d else float("nan")
+        print("| %s | %.0f | %.2f | %.2f | %.3f |" % (k, v["launches_per_step"], avg, v["avg_launch_us"], v["ms_per_step"]))
+    print()
+    print("## Whole run (setup, key switches, warmup, timed and profiled steps)")
+    print()
+    print("| kernel family | dispatches | total ms | avg us |")
+    print("|---|---|---|---|")
+    tot = sum(sum(v) for v in by.values())
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:16]:
+        print("| %s | %d | %.3f | %.2f |" % (k, len(v), sum(v) / 1e6, sum(v) / len(v) / 1e3))
+    print()
+    print("Total kernel time %.3f ms." % (tot / 1e6))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], sys.argv[2], sys.argv[3])

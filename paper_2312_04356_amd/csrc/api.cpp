@@ -170,10 +170,136 @@ nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_
 
 int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
 
+// ------------------------------------------------- K key switches at once
+//
+// Buffers for K jobs at level l: polynomials to switch d [K][l+1], their
+// coefficient form [K][l+1], extended digits [K][dnum][l+1+alpha], inner
+// products [K][2][l+1+alpha], special-prime limbs [K][2][alpha], converted limbs
+// [K][2][l+1] (all x N words).
+struct MultiBufs {
+    uint64_t *d, *coef, *ext, *u, *pc, *conv;
+};
+
+size_t multi_words(const nj_ctx *c, int l, int K)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
+    return N * K * (2 * (l + 1) + nd * ne + 2 * ne + 2 * c->alpha + 2 * (l + 1));
+}
+
+bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
+{
+    const size_t N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
+    M.d = A.take(N * K * (l + 1));
+    M.coef = A.take(N * K * (l + 1));
+    M.ext = A.take(N * K * nd * ne);
+    M.u = A.take(N * K * 2 * ne);
+    M.pc = A.take(N * K * 2 * c->alpha);
+    M.conv = A.take(N * K * 2 * (l + 1));
+    return M.conv != nullptr;
+}
+
+// ModUp of K polynomials stored at d + z (l+1) N (evaluation form) into ext + z dnum ne N.
+nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s)
+{
+    const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
+    LimbTab lt;
+    lt.n = 0;
+    for (int z = 0; z < K; z++)
+        for (int i = 0; i <= l; i++) {
+            lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = z * (l + 1) + i;
+            if (++lt.n == NJ_MAX_LIMBS) {
+                NJ_HIP(launch_ntt(c, M.coef, lt, true, s, d));
+                lt.n = 0;
+            }
+        }
+    NJ_HIP(launch_ntt(c, M.coef, lt, true, s, d));
+    for (int j0 = 0; j0 < nd; j0 += 4) {
+        BconvShared sh;
+        sh.nd = std::min(4, nd - j0);
+        for (int jj = 0; jj < sh.nd; jj++) {
+            const int j = j0 + jj;
+            const BconvTab &bt = c->modup[l][j];
+            sh.m[jj] = bt.m, sh.n_out[jj] = bt.n_out, sh.in_off0[jj] = j * c->alpha;
+            sh.hat_inv[jj] = bt.hat_inv, sh.hat[jj] = bt.hat;
+            for (int a = 0; a < bt.m; a++) sh.in_pidx[jj][a] = bt.in_pidx[a];
+            for (int o = 0; o < bt.n_out; o++) sh.out_pidx[jj][o] = bt.out_pidx[o], sh.out_off[jj][o] = j * ne + bt.out_limb[o];
+        }
+        BconvPtrs jp;
+        for (int z = 0; z < K; z++) jp.in[z] = M.coef + (size_t)z * (l + 1) * N, jp.out[z] = M.ext + (size_t)z * nd * ne * N;
+        NJ_HIP(launch_bconv_multi(c, sh, jp, K, s));
+    }
+    lt.n = 0;
+    for (int z = 0; z < K; z++)
+        for (int j = 0; j < nd; j++) {
+            const BconvTab &bt = c->modup[l][j];
+            for (int o = 0; o < bt.n_out; o++) {
+                lt.pidx[lt.n] = bt.out_pidx[o];
+                lt.off[lt.n] = (z * nd + j) * ne + bt.out_limb[o];
+                if (++lt.n == NJ_MAX_LIMBS) {
+                    NJ_HIP(launch_ntt(c, M.ext, lt, false, s));
+                    lt.n = 0;
+                }
+            }
+        }
+    NJ_HIP(launch_ntt(c, M.ext, lt, false, s));
+    return NJ_OK;
+}
+
+// K key switches from already-extended digits: inner products, ModDown, combine.
+// sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
+nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
+                   MultiBufs &M, hipStream_t s)
+{
+    const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
+    NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
+    LimbTab lp;
+    lp.n = 0;
+    for (int z = 0; z < K; z++)
+        for (int p = 0; p < 2; p++)
+            for (int a = 0; a < al; a++) {
+                lp.pidx[lp.n] = c->n_q + a, lp.off[lp.n] = (2 * z + p) * al + a;
+                lp.soff[lp.n] = (2 * z + p) * ne + l + 1 + a;
+                if (++lp.n == NJ_MAX_LIMBS) {
+                    NJ_HIP(launch_ntt(c, M.pc, lp, true, s, M.u));
+                    lp.n = 0;
+                }
+            }
+    NJ_HIP(launch_ntt(c, M.pc, lp, true, s, M.u));
+    const BconvTab &bt = c->moddown[l];
+    BconvShared sh;
+    sh.nd = 1;
+    sh.m[0] = bt.m, sh.n_out[0] = bt.n_out, sh.in_off0[0] = 0, sh.hat_inv[0] = bt.hat_inv, sh.hat[0] = bt.hat;
+    for (int a = 0; a < bt.m; a++) sh.in_pidx[0][a] = bt.in_pidx[a];
+    for (int o = 0; o < bt.n_out; o++) sh.out_pidx[0][o] = bt.out_pidx[o], sh.out_off[0][o] = o;
+    BconvPtrs jp;
+    for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
+    NJ_HIP(launch_bconv_multi(c, sh, jp, 2 * K, s));
+    LimbTab lq;
+    lq.n = 0;
+    for (int h = 0; h < 2 * K; h++)
+        for (int i = 0; i <= l; i++) {
+            lq.pidx[lq.n] = i, lq.off[lq.n] = h * (l + 1) + i;
+            if (++lq.n == NJ_MAX_LIMBS) {
+                NJ_HIP(launch_ntt(c, M.conv, lq, false, s));
+                lq.n = 0;
+            }
+        }
+    NJ_HIP(launch_ntt(c, M.conv, lq, false, s));
+    NJ_HIP(launch_moddown_multi(c, l, mj, K, sum, M.u, M.conv, acc, s));
+    return NJ_OK;
+}
+
+// key switches batched per launch in a BSGS transform (baby steps, or a chunk of giant steps)
+constexpr int kGiantChunk = 8;
+int bsgs_jobs(const nj_lt_t &lt)
+{
+    return std::max(1, std::max((int)lt.babies.size() - 1, std::min((int)lt.giants.size(), kGiantChunk)));
+}
+
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
 {
     const size_t N = c->N, l = lt.level;
-    return N * 2 * (l + 1) * (lt.babies.size() + lt.giants.size()) + ks_words(c, l);
+    return N * 2 * (l + 1) * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, bsgs_jobs(lt));
 }
 
 // sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
@@ -196,30 +322,44 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     for (int gg : lt.giants)
         if (gg != 0 && !key_of(c, galois_of_rot(c, (long long)gg * lt.n1 * lt.u)))
             return fail(NJ_ENOKEY, "missing giant-step rotation key");
-    KsBufs B;
-    Arena Aks = A;
-    if (!ks_bufs(c, l, Aks, B)) return fail(NJ_ENOMEM, "scratch too small");
-    bool ext_ready = false;
-    for (size_t b = 0; b < lt.babies.size(); b++) {
-        const int i = lt.babies[b];
-        if (i == 0) {
-            baby[b] = in;
-            continue;
-        }
-        const uint32_t g = galois_of_rot(c, (long long)i * lt.u);
-        if (hoist) {
-            if (!ext_ready) {
-                nj_status st = modup_ext(c, l, in + N * (l + 1), B, s);
-                if (st) return st;
-                ext_ready = true;
+    MultiBufs M;
+    if (!multi_bufs(c, l, bsgs_jobs(lt), A, M)) return fail(NJ_ENOMEM, "scratch too small");
+    const size_t nd = n_digits(c, l), ne = l + 1 + c->alpha, plen = N * (l + 1);
+    // baby steps: all rotations of the input as one batch of key switches
+    {
+        KeyJobs kj;
+        MdJobs mj;
+        AutoJobs aj;
+        int K = 0;
+        for (int b = 0; b < nb; b++) {
+            const int i = lt.babies[b];
+            if (i == 0) {
+                baby[b] = in;
+                continue;
             }
-            nj_status st = ks_from_ext(c, l, in + N * (l + 1), key_of(c, g), g, in, g, nullptr, baby_buf[b], B, s);
-            if (st) return st;
-        } else {
-            nj_status st = apply_galois(c, l, in, g, baby_buf[b], A, s);
-            if (st) return st;
+            const uint32_t g = galois_of_rot(c, (long long)i * lt.u);
+            baby[b] = baby_buf[b];
+            if (hoist) {  // one ModUp of c1; X -> X^g applied to the extended digits
+                kj.ext[K] = M.ext, kj.d[K] = in + plen, kj.g[K] = g;
+            } else {  // ModUp of each tau_g(c1)
+                aj.in[K] = in + plen, aj.out[K] = M.d + (size_t)K * plen, aj.g[K] = g;
+                kj.ext[K] = M.ext + (size_t)K * nd * ne * N, kj.d[K] = M.d + (size_t)K * plen, kj.g[K] = 1;
+            }
+            kj.key[K] = key_of(c, g);
+            mj.add[K] = in, mj.g_add[K] = g, mj.out[K] = baby_buf[b];
+            K++;
         }
-        baby[b] = baby_buf[b];
+        if (K) {
+            nj_status st;
+            if (hoist) {
+                st = modup_multi(c, l, 1, in + plen, M, s);
+            } else {
+                NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+                st = modup_multi(c, l, K, M.d, M, s);
+            }
+            if (st) return st;
+            if ((st = ks_multi(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
+        }
     }
     // every giant step's inner sum in one pass
     MacPlan mp;
@@ -233,19 +373,38 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         mp.d_of[g][b] = d;
     }
     NJ_HIP(launch_bsgs_mac(c, l, mp, lt.d_diag, inner, lt.n_diag, s));
-    // out = inner_0 + sum_g rot(inner_g, g n1 u), the sum fused into each rotation's ModDown
-    bool have = false;
+    // out = inner_0 + sum_g rot(inner_g, g n1 u): the rotations run as batches of key
+    // switches whose ModDown combine also sums them (exact modular sums)
+    const uint64_t *acc = nullptr;
     for (int g = 0; g < ng; g++)
-        if (lt.giants[g] == 0) {
-            NJ_HIP(hipMemcpyAsync(out, inner + (size_t)g * clen, clen * 8, hipMemcpyDeviceToDevice, s));
-            have = true;
+        if (lt.giants[g] == 0) acc = inner + (size_t)g * clen;
+    std::vector<int> gl;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] != 0) gl.push_back(g);
+    if (gl.empty()) {
+        if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
+        return NJ_OK;
+    }
+    for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
+        const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
+        KeyJobs kj;
+        MdJobs mj;
+        AutoJobs aj;
+        for (int z = 0; z < K; z++) {
+            const int g = gl[c0 + z];
+            const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
+            const uint64_t *x = inner + (size_t)g * clen;
+            aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
+            kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+            kj.key[z] = key_of(c, ge);
+            mj.add[z] = x, mj.g_add[z] = ge;
         }
-    for (int g = 0; g < ng; g++) {
-        if (lt.giants[g] == 0) continue;
-        nj_status st = apply_galois(c, l, inner + (size_t)g * clen, galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u),
-                                    out, A, s, have ? out : nullptr);
+        mj.out[0] = out;
+        NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+        nj_status st = modup_multi(c, l, K, M.d, M, s);
         if (st) return st;
-        have = true;
+        if ((st = ks_multi(c, l, K, kj, mj, 1, acc, M, s))) return st;
+        acc = out;
     }
     (void)n;
     return NJ_OK;

@@ -71,6 +71,34 @@ struct BconvBatch {
     BconvJob job[4];
 };
 
+// Many key switches at once (kernel arguments).
+#define NJ_MAX_JOBS 16
+struct BconvShared {  // per-digit tables of one basis conversion (ModUp digits, or the P basis)
+    int nd;
+    int m[4], n_out[4], in_off0[4];
+    const double *hat_inv[4], *hat[4];
+    int in_pidx[4][16];
+    int out_pidx[4][48], out_off[4][48];
+};
+struct BconvPtrs {  // per job: input limbs base, output limbs base
+    const uint64_t *in[2 * NJ_MAX_JOBS];
+    uint64_t *out[2 * NJ_MAX_JOBS];
+};
+struct KeyJobs {
+    const uint64_t *ext[NJ_MAX_JOBS], *d[NJ_MAX_JOBS], *key[NJ_MAX_JOBS];
+    uint32_t g[NJ_MAX_JOBS];
+};
+struct MdJobs {
+    const uint64_t *add[NJ_MAX_JOBS];
+    uint32_t g_add[NJ_MAX_JOBS];
+    uint64_t *out[NJ_MAX_JOBS];
+};
+struct AutoJobs {
+    const uint64_t *in[NJ_MAX_JOBS];
+    uint64_t *out[NJ_MAX_JOBS];
+    uint32_t g[NJ_MAX_JOBS];
+};
+
 #define NJ_MAX_BABY 16
 #define NJ_MAX_GIANT 16
 // BSGS accumulation plan (kernel argument): d_of[g][b] = diagonal index or -1.
@@ -222,6 +250,12 @@ hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const
 // out = acc + (u - conv) P^-1 + (p == 0 ? add o X^g_add : 0), both halves; acc/add may be null
 hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv, const uint64_t *add,
                            uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s);
+hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
+hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
+                               hipStream_t s);
+hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
+                                const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
+hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s);

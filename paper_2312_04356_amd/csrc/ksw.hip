@@ -183,6 +183,162 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
     }
 }
 
+// --------------------------------------------------- many key switches at once
+//
+// k_bconv_multi: basis conversion for many (job, digit) pairs sharing the digit
+// tables (blockIdx.z = job * nd + digit).  MMAX bounds the digit size; smaller
+// digits are predicated, so the scaled residues keep static register indices.
+template <int MMAX>
+__global__ __launch_bounds__(kBT) void k_bconv_multi(BconvShared sh, BconvPtrs jp, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int job = blockIdx.z / sh.nd, j = blockIdx.z % sh.nd;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    const int o0 = blockIdx.y * 8, n_out = sh.n_out[j], m = sh.m[j];
+    if (k >= N || o0 >= n_out) return;
+    const uint64_t *in = jp.in[job];
+    uint64_t *out = jp.out[job];
+    const double *hat_inv = sh.hat_inv[j], *hat = sh.hat[j];
+    double v[MMAX];
+#pragma unroll
+    for (int a = 0; a < MMAX; a++) {
+        if (a < m) {
+            const Mod ma = info[sh.in_pidx[j][a]].m;
+            v[a] = mul_canon(u2d(in[(size_t)(sh.in_off0[j] + a) * N + k]), hat_inv[a], ma);
+        }
+    }
+    const int o1 = min(o0 + 8, n_out);
+    for (int o = o0; o < o1; o++) {
+        const Mod mt = info[sh.out_pidx[j][o]].m;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < MMAX; a++) {
+            if (a < m) {
+                acc += mul_lazy(v[a], hat[a * n_out + o], mt);
+                if ((a & 7) == 7) acc = reduce(acc, mt);
+            }
+        }
+        out[(size_t)sh.out_off[j][o] * N + k] = d2u(reduce(acc, mt));
+    }
+}
+
+hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s)
+{
+    if (n_jobs == 0) return hipSuccess;
+    int max_out = 0, mmax = 0;
+    double bytes = 0;
+    for (int j = 0; j < sh.nd; j++) {
+        max_out = max(max_out, sh.n_out[j]);
+        mmax = max(mmax, sh.m[j]);
+        bytes += 8.0 * c->N * (sh.m[j] + sh.n_out[j]) * n_jobs;
+    }
+    dim3 grid((c->N + kBT - 1) / kBT, (max_out + 7) / 8, n_jobs * sh.nd);
+    if (mmax <= 2) return launch(c, PROF_BCONV, bytes, k_bconv_multi<2>, grid, dim3(kBT), s, sh, jp, c->d_info, c->log_n);
+    if (mmax <= 4) return launch(c, PROF_BCONV, bytes, k_bconv_multi<4>, grid, dim3(kBT), s, sh, jp, c->d_info, c->log_n);
+    if (mmax <= 8) return launch(c, PROF_BCONV, bytes, k_bconv_multi<8>, grid, dim3(kBT), s, sh, jp, c->d_info, c->log_n);
+    return launch(c, PROF_BCONV, bytes, k_bconv_multi<16>, grid, dim3(kBT), s, sh, jp, c->d_info, c->log_n);
+}
+
+// key inner products of many jobs (blockIdx.z = job); u of job z at u_base + z * 2 ne N
+__global__ __launch_bounds__(kBT) void k_key_ip_multi(KeyJobs kj, uint64_t *u_base, int n_digits, int level, int L,
+                                                     int alpha, int nq, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int t = blockIdx.y, z = blockIdx.z;
+    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
+    const int pidx = t <= level ? t : nq + (t - level - 1);
+    const int kl = t <= level ? t : L + 1 + (t - level - 1);
+    const int own = t <= level ? t / alpha : -1;
+    const Mod m = info[pidx].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t g = kj.g[z];
+    const uint64_t *ext = kj.ext[z], *d = kj.d[z], *key = kj.key[z];
+    const int src = g == 1u ? k : galois_src2(k, g, logN);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int j = 0; j < n_digits; j++) {
+        const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
+        double x = u2d(xp[src]);
+        double kb = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
+        double ka = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
+        acc0 += mul_lazy(x, kb, m);
+        acc1 += mul_lazy(x, ka, m);
+        if ((j & 7) == 7) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+    }
+    uint64_t *u = u_base + (size_t)z * 2 * ne * N;
+    u[(size_t)t * N + k] = d2u(reduce(acc0, m));
+    u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+}
+
+hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
+                               hipStream_t s)
+{
+    const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
+    dim3 grid((c->N + kBT - 1) / kBT, ne, n_jobs);
+    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0) * n_jobs, k_key_ip_multi, grid, dim3(kBT), s, kj,
+                  u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+}
+
+// ModDown combine of many jobs.  sum == 0: job z writes out[z] (blockIdx.z = 2 job + half);
+// sum == 1: out[0] = acc + sum over jobs (blockIdx.z = half).  Job z's u at u_base + z 2 ne N,
+// its converted limbs at conv_base + z 2 (l+1) N, its c0 (read through X -> X^g_add[z]) at add[z].
+__global__ __launch_bounds__(kBT) void k_moddown_multi(MdJobs mj, int n_jobs, int sum, const uint64_t *u_base,
+                                                      const uint64_t *conv_base, const uint64_t *acc, int level,
+                                                      int ne, const double *pinv, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const Mod m = info[i].m;
+    const int L1 = level + 1;
+    const int p = sum ? blockIdx.z : (blockIdx.z & 1);
+    const int z0 = sum ? 0 : (blockIdx.z >> 1), z1 = sum ? n_jobs : z0 + 1;
+    double r = 0.0;
+    for (int z = z0; z < z1; z++) {
+        const uint64_t *u = u_base + (size_t)z * 2 * ne * N, *cv = conv_base + (size_t)z * 2 * L1 * N;
+        double t = mul_canon(sub_mod(u2d(u[((size_t)p * ne + i) * N + k]), u2d(cv[((size_t)p * L1 + i) * N + k]), m),
+                             pinv[i], m);
+        if (p == 0 && mj.add[z]) {
+            const uint32_t g = mj.g_add[z];
+            const int src = g <= 1u ? k : galois_src2(k, g, logN);
+            t = add_mod(t, u2d(mj.add[z][(size_t)i * N + src]), m);
+        }
+        r = add_mod(r, t, m);
+    }
+    const size_t o = ((size_t)p * L1 + i) * N + k;
+    if (sum) {
+        if (acc) r = add_mod(r, u2d(acc[o]), m);
+        mj.out[0][o] = d2u(r);
+    } else {
+        mj.out[z0][o] = d2u(r);
+    }
+}
+
+hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
+                                const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s)
+{
+    dim3 grid((c->N + kBT - 1) / kBT, level + 1, sum ? 2 : 2 * n_jobs);
+    const double bytes = 8.0 * c->N * (level + 1) * (n_jobs * 5.0 + (sum ? 2.0 : 2.0 * n_jobs) + (acc ? 2.0 : 0.0));
+    return launch(c, PROF_OTHER, bytes, k_moddown_multi, grid, dim3(kBT), s, mj, n_jobs, sum, u_base, conv_base, acc,
+                  level, level + 1 + c->alpha, c->d_pinv, c->d_info, c->log_n);
+}
+
+// out[z] = in[z] read through X -> X^g[z], l+1 limbs per job (blockIdx.z = job)
+__global__ __launch_bounds__(kBT) void k_automorph_multi(AutoJobs aj, int n_limbs, int logN)
+{
+    const int N = 1 << logN, z = blockIdx.z, i = blockIdx.y;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    aj.out[z][(size_t)i * N + k] = aj.in[z][(size_t)i * N + galois_src2(k, aj.g[z], logN)];
+}
+
+hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s)
+{
+    dim3 grid((c->N + kBT - 1) / kBT, n_limbs, n_jobs);
+    return launch(c, PROF_OTHER, 16.0 * c->N * n_limbs * n_jobs, k_automorph_multi, grid, dim3(kBT), s, aj, n_limbs,
+                  c->log_n);
+}
+
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s)
 {

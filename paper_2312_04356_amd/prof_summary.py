@@ -1,11 +1,13 @@
-"""Summarises a rocprofv3 kernel trace (CSV output) next to a bench.py JSON line.
+"""Summarises a rocprofv3 kernel trace (CSV output) next to bench.py JSON lines.
 
-    python -m paper_2312_04356_amd.prof_summary <kernel_trace.csv> <bench.json> "<command>" > summary.md
+    python -m paper_2312_04356_amd.prof_summary <kernel_trace.csv> <bench_under_rocprof.json> \
+        <bench_plain.json> "<command>" > summary.md
 
 For every kernel family the bench line reports (launches per step x steps), the
 last that-many dispatches in the trace are the bench's live-profiled steps (the
-last GPU work of a bench run); their average duration is set beside the value
-bench.py measured with HIP events.  Whole-run totals per kernel follow.
+last GPU work of a bench run); their rocprofv3 average duration is set beside the
+HIP-event average of a plain bench run (no profiler attached: under rocprofv3 the
+events also count the profiler's own per-dispatch work).  Whole-run totals follow.
 """
 import csv
 import json
@@ -18,15 +20,18 @@ def family(name):
     n = re.sub(r"\(.*", "", name)
     n = n.replace("void ", "").replace("nj::", "")
     n = re.sub(r"k_ntt_col<\d+, (false|true)>", r"k_ntt_col<\1>", n)
-    n = n.replace("k_bconv_batch<", "k_bconv<").strip()
+    n = n.replace("k_bconv_batch<", "k_bconv<").replace("k_bconv_multi<", "k_bconv<").strip()
     n = re.sub(r"k_bconv<\d+>", "k_bconv", n)
-    n = n.replace("k_key_ip2", "k_key_ip").replace("k_bsgs_mac", "k_pmac").replace("k_moddown2", "other")
+    n = n.replace("k_key_ip_multi", "k_key_ip").replace("k_key_ip2", "k_key_ip").replace("k_bsgs_mac", "k_pmac")
+    if n in ("k_moddown2", "k_moddown_multi", "k_automorph_multi"):
+        n = "other"
     return n
 
 
-def main(trace, bench_json, command):
+def main(trace, bench_json, plain_json, command):
     rows = list(csv.DictReader(open(trace)))
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    plain = json.loads(open(plain_json).read().strip().splitlines()[-1])
     steps = bench["steps"]
     by = defaultdict(list)
     for r in rows:
@@ -37,17 +42,18 @@ def main(trace, bench_json, command):
     print()
     print("    " + command)
     print()
-    print("bench.py line of the same run: %.4f ms per step, %d steps; dominant kernel %s, %.2f us per launch "
-          "(HIP events), %.1f GB/s algorithmic (%.1f%% of 8 TB/s)."
-          % (bench["value"], steps, bench["roofline"]["kernel"], bench["roofline"]["avg_launch_us"],
-             bench["roofline"]["achieved"], 100 * bench["roofline"]["frac"]))
+    print("bench.py under rocprofv3: %.4f ms per step, %d steps.  Plain bench.py run (same call, no profiler): "
+          "%.4f ms per step; dominant kernel %s, %.2f us per launch (HIP events), %.1f GB/s algorithmic "
+          "(%.1f%% of 8 TB/s)."
+          % (bench["value"], steps, plain["value"], plain["roofline"]["kernel"], plain["roofline"]["avg_launch_us"],
+             plain["roofline"]["achieved"], 100 * plain["roofline"]["frac"]))
     print()
-    print("## Live-profiled steps: rocprofv3 vs HIP events")
+    print("## Live-profiled steps: rocprofv3 kernel durations vs the plain run's HIP events")
     print()
-    print("| kernel | launches/step | rocprofv3 avg us | HIP-event avg us | ms/step (events) |")
+    print("| kernel | launches/step | rocprofv3 avg us | HIP-event avg us (plain run) | ms/step (plain run) |")
     print("|---|---|---|---|---|")
-    for k, v in sorted(bench["pipeline"]["kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"]):
-        n = int(round(v["launches_per_step"] * steps))
+    for k, v in sorted(plain["pipeline"]["kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        n = int(round(bench["pipeline"]["kernels"].get(k, v)["launches_per_step"] * steps))
         d = by.get(k, [])[-n:] if n else []
         avg = sum(d) / len(d) / 1e3 if d else float("nan")
         print("| %s | %.0f | %.2f | %.2f | %.3f |" % (k, v["launches_per_step"], avg, v["avg_launch_us"], v["ms_per_step"]))
@@ -64,4 +70,4 @@ def main(trace, bench_json, command):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2], sys.argv[3])
+    main(sys.argv[1], sys.argv[2], sys.argv[3], sys.argv[4])

@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--workload", default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ks-iters", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=64, help="ciphertexts in the batched measurements")
+    ap.add_argument("--batch-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -165,6 +167,52 @@ def main():
         torch.cuda.synchronize()
         ks[str(level)] = round(args.ks_iters / (e0.elapsed_time(e1) / 1e3), 1)
 
+    # batched: the same key switch on 64 ciphertexts per call (each key word read once per 8)
+    ks_batch = {}
+    nbk = args.batch
+    for level in (23, 15, 7):
+        if level > gctx.L:
+            continue
+        xb, ob = gctx.empty_batch(nbk, level), gctx.empty_batch(nbk, level)
+        xb.data.random_(0, 2 ** 40)
+        gctx.nj_apply_galois_batch(xb, nbk, gk, ob)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(max(1, args.ks_iters // nbk * 4)):
+            gctx.nj_apply_galois_batch(xb, nbk, gk, ob)
+        e1.record()
+        torch.cuda.synchronize()
+        it = max(1, args.ks_iters // nbk * 4)
+        ks_batch[str(level)] = round(it * nbk / (e0.elapsed_time(e1) / 1e3), 1)
+        del xb, ob
+
+    # batched fused conv + CoeffToSlot: 64 ciphertexts (distinct encryptions of the image)
+    import synth
+    from paper_2312_04356_amd import Ct
+    coeffs = gctx.nj_encode_cins(g.image_slices(), g.scale)
+    mdev = torch.empty((2, g.N), dtype=torch.int64, device=gctx.device)
+    gctx.nj_upload_plain(coeffs, 1, mdev)
+    xb = gctx.empty_batch(args.batch, 1)
+    for z in range(args.batch):
+        a, e = synth.enc_randomness(g.q[:2], g.N, g.w["data_seed"], 100 + z)
+        gctx.nj_encrypt_sk(mdev, 1, a, e, g.scale, Ct(xb.data[z], 1))
+    yb = gctx.empty_batch(args.batch, 0)
+    reb, imb = gctx.empty_batch(args.batch, lvl), gctx.empty_batch(args.batch, lvl)
+
+    def bstep():
+        gctx.nj_conv2d_cins_batch(g.conv_plan, xb, args.batch, yb)
+        gctx.nj_coeff_to_slot_batch(g.cts_plan, yb, args.batch, reb, imb)
+
+    bstep()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.batch_steps):
+        bstep()
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / args.batch_steps
+    del xb, yb, reb, imb
+
     def step():
         gctx.nj_conv2d_cins(g.conv_plan, ct, y)
         gctx.nj_coeff_to_slot(g.cts_plan, y, re, im)
@@ -217,7 +265,11 @@ def main():
         "config": {"workload": "N=2^16 fused CinS conv 3x3 16->16 32x32 + CoeffToSlot (3 groups), 24+8 primes, dnum=3",
                    "log_n": gctx.log_n, "n_q": gctx.L + 1, "alpha": gctx.alpha,
                    "cts_groups": g.w["cts_groups"], "host_wall_s": round(wall, 3)},
-        "keyswitch_per_s": {"plain": ks, "galois": gk},
+        "keyswitch_per_s": {"plain": ks, "batched": ks_batch, "batch": nbk, "galois": gk},
+        "batched": {"n_ct": args.batch, "ms_per_batch": round(batch_ms, 3),
+                    "ms_per_ct": round(batch_ms / args.batch, 4),
+                    "speedup_vs_plain": round(ms / (batch_ms / args.batch), 3),
+                    "hbm_frac_per_ct": round(pipeline_bytes(g) / (batch_ms / args.batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
         "pipeline": {"algorithmic_GB": round(alg / 1e9, 3),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -188,6 +188,18 @@ nj_status nj_conv2d_cins(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_c
  * re/im: device [2][L-groups+1][N]. */
 nj_status nj_coeff_to_slot(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, nj_ct *re, nj_ct *im, void *stream);
 
+/* --------------------------------------------------------- batched calls */
+
+/* Batches: in->data (and each output's data) holds n ciphertexts of the same level
+ * back to back, [n][2][l+1][N].  The library processes sub-batches of up to 8 in
+ * which every switching-key word and every plaintext-diagonal word is read once
+ * for all ciphertexts (key switches grouped by Galois element).  Results are
+ * bit-identical to n separate calls.  Outputs must not alias inputs. */
+nj_status nj_apply_galois_batch(nj_ctx *ctx, const nj_ct *in, int n, uint32_t galois_elt, nj_ct *out, void *stream);
+nj_status nj_conv2d_cins_batch(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, int n, nj_ct *out, void *stream);
+nj_status nj_coeff_to_slot_batch(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, int n, nj_ct *re, nj_ct *im,
+                                 void *stream);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Live kernel timing for roofline reports: when enabled, the library records HIP

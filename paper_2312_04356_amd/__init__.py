@@ -65,6 +65,10 @@ _SIGS = {
     "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
     "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_apply_galois_batch": (i32, [vp, ctypes.POINTER(NjCt), i32, u32, ctypes.POINTER(NjCt), vp]),
+    "nj_conv2d_cins_batch": (i32, [vp, vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
+    "nj_coeff_to_slot_batch": (i32, [vp, vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt),
+                                     ctypes.POINTER(NjCt), vp]),
     "nj_prof_enable": (i32, [vp, i32]),
     "nj_prof_read": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32]),
 }
@@ -319,6 +323,31 @@ class Ctx:
         ci, co = ct.c(), out.c()
         _check(_lib.nj_modraise(self.ptr, ctypes.byref(ci), level, ctypes.byref(co), _stream(stream)), "nj_modraise")
         return out.sync_from(co)
+
+    # -- batched calls (Ct data tensors of shape [n, 2, level+1, N])
+    def empty_batch(self, n, level):
+        t = self.torch.empty((n, 2, level + 1, self.N), dtype=self.torch.int64, device=self.device)
+        return Ct(t, level)
+
+    def nj_apply_galois_batch(self, ct, n, g, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_apply_galois_batch(self.ptr, ctypes.byref(ci), int(n), int(g), ctypes.byref(co),
+                                          _stream(stream)), "nj_apply_galois_batch")
+        return out.sync_from(co)
+
+    def nj_conv2d_cins_batch(self, plan, ct, n, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_conv2d_cins_batch(self.ptr, plan.ptr, ctypes.byref(ci), int(n), ctypes.byref(co),
+                                         _stream(stream)), "nj_conv2d_cins_batch")
+        return out.sync_from(co)
+
+    def nj_coeff_to_slot_batch(self, plan, ct, n, re, im, stream=None):
+        ci, cr, cm = ct.c(), re.c(), im.c()
+        _check(_lib.nj_coeff_to_slot_batch(self.ptr, plan.ptr, ctypes.byref(ci), int(n), ctypes.byref(cr),
+                                           ctypes.byref(cm), _stream(stream)), "nj_coeff_to_slot_batch")
+        re.sync_from(cr)
+        im.sync_from(cm)
+        return re, im
 
     # -- profiling
     def nj_prof_enable(self, on):

@@ -198,15 +198,17 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
     return M.conv != nullptr;
 }
 
-// ModUp of K polynomials stored at d + z (l+1) N (evaluation form) into ext + z dnum ne N.
-nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s)
+// ModUp of K polynomials stored at d + z dstride N (evaluation form; dstride in limbs,
+// l+1 when packed) into ext + z dnum ne N.
+nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1)
 {
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
+    if (dstride < 0) dstride = l + 1;
     LimbTab lt;
     lt.n = 0;
     for (int z = 0; z < K; z++)
         for (int i = 0; i <= l; i++) {
-            lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = z * (l + 1) + i;
+            lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = z * dstride + i;
             if (++lt.n == NJ_MAX_LIMBS) {
                 NJ_HIP(launch_ntt(c, M.coef, lt, true, s, d));
                 lt.n = 0;
@@ -247,11 +249,21 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
+nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
+                  hipStream_t s);
+
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
-    const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
+    return ks_down(c, l, K, mj, sum, acc, M, s);
+}
+
+// ModDown of K jobs' inner products (M.u) and the combine into their outputs.
+nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
+                  hipStream_t s)
+{
+    const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     LimbTab lp;
     lp.n = 0;
     for (int z = 0; z < K; z++)
@@ -408,6 +420,118 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     }
     (void)n;
     return NJ_OK;
+}
+
+// ------------------------------------------------------------ batched execution
+//
+// K ciphertexts (contiguous, [K][2][l+1][N]) through one BSGS transform: every key
+// and every diagonal word is read once for the whole batch.  Baby steps hoisted.
+constexpr int kBatch = 8;
+
+size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K)
+{
+    const size_t N = c->N, l = lt.level, clen = 2 * N * (l + 1);
+    return clen * K * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, K);
+}
+
+nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *in, uint64_t *out, Arena A,
+                           hipStream_t s)
+{
+    const int l = lt.level;
+    const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1);
+    const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
+    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
+    if (K < 1 || K > NJ_MAX_JOBS) return fail(NJ_EINVAL, "batch size out of range");
+    for (int b : lt.babies)
+        if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
+    for (int g : lt.giants)
+        if (g != 0 && !key_of(c, galois_of_rot(c, (long long)g * lt.n1 * lt.u)))
+            return fail(NJ_ENOKEY, "missing giant-step key");
+    uint64_t *baby_all = A.take(clen * K * nb);   // [nb][K][clen], slot 0 unused (the input is baby 0)
+    uint64_t *inner_all = A.take(clen * K * ng);  // [K][ng][clen]
+    MultiBufs M;
+    if (!inner_all || !multi_bufs(c, l, K, A, M)) return fail(NJ_ENOMEM, "scratch too small");
+    const size_t nd = n_digits(c, l), ne = l + 1 + c->alpha;
+    nj_status st;
+    // baby steps: one ModUp per ciphertext, then one shared-key inner product per rotation
+    if (nb > 1 && (st = modup_multi(c, l, K, in + plen, M, s, 2 * (l + 1)))) return st;
+    for (int b = 0; b < nb; b++) {
+        if (lt.babies[b] == 0) continue;
+        const uint32_t g = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
+        KeyJobs kj;
+        MdJobs mj;
+        for (int z = 0; z < K; z++) {
+            kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = in + z * clen + plen, kj.g[z] = g;
+            mj.add[z] = in + z * clen, mj.g_add[z] = g, mj.out[z] = baby_all + ((size_t)b * K + z) * clen;
+        }
+        NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, g), M.u, s));
+        if ((st = ks_down(c, l, K, mj, 0, nullptr, M, s))) return st;
+    }
+    // inner sums of every giant step of every ciphertext
+    MacPlan mp;
+    mp.nb = nb, mp.ng = ng;
+    for (int b = 0; b < nb; b++) mp.baby[b] = lt.babies[b] == 0 ? in : baby_all + (size_t)b * K * clen;
+    for (int g = 0; g < NJ_MAX_GIANT; g++)
+        for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
+    for (int d = 0; d < lt.n_diag; d++) {
+        const int g = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
+        const int b = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
+        mp.d_of[g][b] = d;
+    }
+    NJ_HIP(launch_bsgs_mac_multi(c, l, mp, K, clen, ng * clen, lt.d_diag, inner_all, lt.n_diag, s));
+    // giant steps: out_z = inner_{z,0} + sum_g rot(inner_{z,g})
+    bool have = false;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] == 0) {
+            NJ_HIP(hipMemcpy2DAsync(out, clen * 8, inner_all + (size_t)g * clen, ng * clen * 8, clen * 8, K,
+                                    hipMemcpyDeviceToDevice, s));
+            have = true;
+        }
+    for (int g = 0; g < ng; g++) {
+        if (lt.giants[g] == 0) continue;
+        const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
+        AutoJobs aj;
+        KeyJobs kj;
+        MdJobs mj;
+        for (int z = 0; z < K; z++) {
+            const uint64_t *x = inner_all + ((size_t)z * ng + g) * clen;
+            aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
+            kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+            mj.add[z] = x, mj.g_add[z] = ge, mj.out[z] = out + z * clen;
+        }
+        NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+        if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+        NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
+        if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
+        have = true;
+    }
+    return NJ_OK;
+}
+
+// K key switches tau_g of contiguous ciphertexts [K][2][l+1] sharing one key
+nj_status apply_galois_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint32_t g, uint64_t *out, Arena A,
+                             hipStream_t s)
+{
+    const uint64_t *key = key_of(c, g);
+    if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
+    if (K < 1 || K > NJ_MAX_JOBS) return fail(NJ_EINVAL, "batch size out of range");
+    if (in == out) return fail(NJ_EINVAL, "batched key switching needs separate input and output");
+    const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1), nd = n_digits(c, l), ne = l + 1 + c->alpha;
+    MultiBufs M;
+    if (!multi_bufs(c, l, K, A, M)) return fail(NJ_ENOMEM, "scratch too small");
+    AutoJobs aj;
+    KeyJobs kj;
+    MdJobs mj;
+    for (int z = 0; z < K; z++) {
+        aj.in[z] = in + z * clen + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = g;
+        kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+        mj.add[z] = in + z * clen, mj.g_add[z] = g, mj.out[z] = out + z * clen;
+    }
+    NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+    nj_status st = modup_multi(c, l, K, M.d, M, s);
+    if (st) return st;
+    NJ_HIP(launch_key_ip_shared(c, l, kj, K, key, M.u, s));
+    return ks_down(c, l, K, mj, 0, nullptr, M, s);
 }
 
 // rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
@@ -892,6 +1016,108 @@ nj_status nj_coeff_to_slot(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *
     st = conj_split(c, l, x, re->data, im->data, A, s);
     if (st) return st;
     re->level = im->level = l;
+    re->is_ntt = im->is_ntt = 1;
+    re->scale = im->scale = in->scale;
+    return NJ_OK;
+}
+
+// ------------------------------------------------------------ batched calls
+
+static nj_status check_batch(const nj_ctx *c, const nj_ct *in, int n, const nj_ct *out, const char *nm)
+{
+    nj_status st = check_ct(c, in, nm);
+    if (st) return st;
+    if (n < 1) return fail(NJ_EINVAL, std::string(nm) + ": batch size must be positive");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, std::string(nm) + ": bad output");
+    return NJ_OK;
+}
+
+nj_status nj_apply_galois_batch(nj_ctx *c, const nj_ct *in, int n, uint32_t g, nj_ct *out, void *stream)
+{
+    nj_status st = check_batch(c, in, n, out, "nj_apply_galois_batch");
+    if (st) return st;
+    const int l = in->level, Kmax = std::min(n, kBatch);
+    const size_t clen = 2 * (size_t)c->N * (l + 1);
+    bool ok;
+    Arena A = arena_for(c, multi_words(c, l, Kmax), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    for (int z0 = 0; z0 < n; z0 += kBatch) {
+        const int K = std::min(kBatch, n - z0);
+        st = apply_galois_batch(c, l, K, in->data + z0 * clen, g, out->data + z0 * clen, A, S(stream));
+        if (st) return st;
+    }
+    out->level = l, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+nj_status nj_conv2d_cins_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int n, nj_ct *out, void *stream)
+{
+    if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_cins_batch: not a conv plan");
+    nj_status st = check_batch(c, in, n, out, "nj_conv2d_cins_batch");
+    if (st) return st;
+    const nj_lt_t &lt = p->lts[0];
+    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins_batch: input must be at the plan's level");
+    const int l = lt.level, Kmax = std::min(n, kBatch);
+    const size_t N = c->N, clen = 2 * N * (l + 1), clen_out = 2 * N * l;
+    bool ok;
+    Arena A = arena_for(c, Kmax * clen + bsgs_batch_words(c, lt, Kmax) + N * (l + 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *y = A.take(Kmax * clen);
+    hipStream_t s = S(stream);
+    for (int z0 = 0; z0 < n; z0 += kBatch) {
+        const int K = std::min(kBatch, n - z0);
+        if ((st = bsgs_apply_batch(c, lt, K, in->data + z0 * clen, y, A, s))) return st;
+        for (int z = 0; z < K; z++)
+            if ((st = rescale(c, l, y + z * clen, out->data + (z0 + z) * clen_out, A, s))) return st;
+    }
+    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+nj_status nj_coeff_to_slot_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int n, nj_ct *re, nj_ct *im,
+                                 void *stream)
+{
+    if (!c || !p || p->kind != 1 || p->lts.empty()) return fail(NJ_EINVAL, "nj_coeff_to_slot_batch: not a CoeffToSlot plan");
+    nj_status st = check_batch(c, in, n, re, "nj_coeff_to_slot_batch");
+    if (st) return st;
+    if (in->level != 0) return fail(NJ_ELEVEL, "nj_coeff_to_slot_batch: input must be at level 0");
+    if (!im || !im->data || im->data == re->data) return fail(NJ_EINVAL, "nj_coeff_to_slot_batch: bad output");
+    const int Kmax = std::min(n, kBatch), lo = c->L - (int)p->lts.size();
+    const size_t N = c->N, ctop = 2 * N * (c->L + 1), cin = 2 * N, cout = 2 * N * (lo + 1);
+    size_t need = 0;
+    for (const auto &lt : p->lts) need = std::max(need, bsgs_batch_words(c, lt, Kmax));
+    need = std::max(need, Kmax * cout + multi_words(c, lo, Kmax));
+    need += 2 * Kmax * ctop + N * (c->L + 2);
+    bool ok;
+    Arena A = arena_for(c, need, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *x = A.take(Kmax * ctop), *y = A.take(Kmax * ctop);
+    hipStream_t s = S(stream);
+    for (int z0 = 0; z0 < n; z0 += kBatch) {
+        const int K = std::min(kBatch, n - z0);
+        for (int z = 0; z < K; z++)
+            if ((st = modraise(c, in->data + (z0 + z) * cin, c->L, x + z * ctop, A, s))) return st;
+        int l = c->L;
+        for (const auto &lt : p->lts) {
+            if (lt.level != l) return fail(NJ_ELEVEL, "nj_coeff_to_slot_batch: plan levels do not match");
+            const size_t cl = 2 * N * (l + 1), cl1 = 2 * N * l;
+            if ((st = bsgs_apply_batch(c, lt, K, x, y, A, s))) return st;
+            for (int z = 0; z < K; z++)
+                if ((st = rescale(c, l, y + z * cl, x + z * cl1, A, s))) return st;
+            l--;
+        }
+        // real split of every ciphertext: one batch of conjugations
+        Arena B = A;
+        uint64_t *cj = B.take(K * cout);
+        if ((st = apply_galois_batch(c, l, K, x, 2 * c->N - 1, cj, B, s))) return st;
+        for (int z = 0; z < K; z++) {
+            uint64_t *xz = x + z * cout, *cz = cj + z * cout;
+            NJ_HIP(launch_elementwise(c, 0, xz, cz, re->data + (z0 + z) * cout, ct_limbs(l), s));
+            NJ_HIP(launch_elementwise(c, 1, xz, cz, cz, ct_limbs(l), s));
+            NJ_HIP(launch_monomial_half(c, l, cz, im->data + (z0 + z) * cout, s));
+        }
+    }
+    re->level = im->level = lo;
     re->is_ntt = im->is_ntt = 1;
     re->scale = im->scale = in->scale;
     return NJ_OK;

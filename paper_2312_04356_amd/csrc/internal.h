@@ -256,6 +256,10 @@ hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, in
 hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
                                 const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
 hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);
+hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, const uint64_t *key,
+                                uint64_t *u_base, hipStream_t s);
+hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, int n_ct, size_t bstride,
+                                 size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s);

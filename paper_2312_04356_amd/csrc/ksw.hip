@@ -279,8 +279,9 @@ hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, in
                   u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
 }
 
-// ModDown combine of many jobs.  sum == 0: job z writes out[z] (blockIdx.z = 2 job + half);
-// sum == 1: out[0] = acc + sum over jobs (blockIdx.z = half).  Job z's u at u_base + z 2 ne N,
+// ModDown combine of many jobs.  sum == 0: job z writes out[z] (blockIdx.z = 2 job + half),
+// adding the previous out[z] when acc is non-null; sum == 1: out[0] = acc + sum over jobs
+// (blockIdx.z = half).  Job z's u at u_base + z 2 ne N,
 // its converted limbs at conv_base + z 2 (l+1) N, its c0 (read through X -> X^g_add[z]) at add[z].
 __global__ __launch_bounds__(kBT) void k_moddown_multi(MdJobs mj, int n_jobs, int sum, const uint64_t *u_base,
                                                       const uint64_t *conv_base, const uint64_t *acc, int level,
@@ -310,6 +311,7 @@ __global__ __launch_bounds__(kBT) void k_moddown_multi(MdJobs mj, int n_jobs, in
         if (acc) r = add_mod(r, u2d(acc[o]), m);
         mj.out[0][o] = d2u(r);
     } else {
+        if (acc) r = add_mod(r, u2d(mj.out[z0][o]), m);  // accumulate into the job's own output
         mj.out[z0][o] = d2u(r);
     }
 }
@@ -321,6 +323,129 @@ hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, in
     const double bytes = 8.0 * c->N * (level + 1) * (n_jobs * 5.0 + (sum ? 2.0 : 2.0 * n_jobs) + (acc ? 2.0 : 0.0));
     return launch(c, PROF_OTHER, bytes, k_moddown_multi, grid, dim3(kBT), s, mj, n_jobs, sum, u_base, conv_base, acc,
                   level, level + 1 + c->alpha, c->d_pinv, c->d_info, c->log_n);
+}
+
+// Key inner products of many ciphertexts with ONE key (batched execution): each key
+// word is read once and applied to every ciphertext's extended digits.  Job z reads
+// its digits at kj.ext[z] (own-digit limbs at kj.d[z]) through X -> X^kj.g[z] and writes
+// u_base + z 2 ne N.
+__global__ __launch_bounds__(kBT) void k_key_ip_shared(KeyJobs kj, int n_jobs, const uint64_t *key, uint64_t *u_base,
+                                                      int n_digits, int level, int L, int alpha, int nq,
+                                                      const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int t = blockIdx.y;
+    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
+    const int pidx = t <= level ? t : nq + (t - level - 1);
+    const int kl = t <= level ? t : L + 1 + (t - level - 1);
+    const int own = t <= level ? t / alpha : -1;
+    const Mod m = info[pidx].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    double kb[8], ka[8];  // dnum <= 8 digits per level on this path
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        if (j < n_digits) {
+            kb[j] = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
+            ka[j] = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
+        }
+    }
+    for (int z = 0; z < n_jobs; z++) {
+        const uint32_t g = kj.g[z];
+        const int src = g == 1u ? k : galois_src2(k, g, logN);
+        const uint64_t *ext = kj.ext[z], *d = kj.d[z];
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (j < n_digits) {
+                const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
+                double x = u2d(xp[src]);
+                acc0 += mul_lazy(x, kb[j], m);
+                acc1 += mul_lazy(x, ka[j], m);
+            }
+        }
+        uint64_t *u = u_base + (size_t)z * 2 * ne * N;
+        u[(size_t)t * N + k] = d2u(reduce(acc0, m));
+        u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+    }
+}
+
+hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, const uint64_t *key,
+                                uint64_t *u_base, hipStream_t s)
+{
+    const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
+    if (nd > 8) return hipErrorInvalidValue;
+    dim3 grid((c->N + kBT - 1) / kBT, ne);
+    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (2.0 * nd + n_jobs * (nd + 2.0)), k_key_ip_shared, grid, dim3(kBT),
+                  s, kj, n_jobs, key, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+}
+
+// BSGS multiply-accumulate for many ciphertexts sharing one transform: blockIdx.z =
+// chunk of up to 4 giant steps whose diagonal words (<= 4 x 16) stay in registers
+// while the ciphertexts' baby steps stream past.  Ciphertext z's baby b is at
+// mp.baby[b] + z * bstride, its inner sums at inner + z * istride (giant-major).
+template <int GCH, int NBM>
+__global__ __launch_bounds__(kBT) void k_bsgs_mac_multi(MacPlan mp, int n_ct, size_t bstride, size_t istride,
+                                                       const uint64_t *diag, uint64_t *inner, int level,
+                                                       const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const Mod m = info[i].m;
+    const size_t L1 = level + 1;
+    const int g0 = blockIdx.z * GCH;
+    double w[GCH][NBM];
+#pragma unroll
+    for (int gg = 0; gg < GCH; gg++)
+#pragma unroll
+        for (int b = 0; b < NBM; b++) {
+            const int g = g0 + gg;
+            const int dg = (g < mp.ng && b < mp.nb) ? mp.d_of[g][b] : -1;
+            w[gg][b] = dg < 0 ? 0.0 : u2d(diag[((size_t)dg * L1 + i) * N + k]);
+        }
+    for (int z = 0; z < n_ct; z++) {
+        double b0[NBM], b1[NBM];
+#pragma unroll
+        for (int b = 0; b < NBM; b++) {
+            if (b < mp.nb) {
+                const uint64_t *bp = mp.baby[b] + (size_t)z * bstride;
+                b0[b] = u2d(bp[(size_t)i * N + k]);
+                b1[b] = u2d(bp[(L1 + i) * N + k]);
+            }
+        }
+#pragma unroll
+        for (int gg = 0; gg < GCH; gg++) {
+            const int g = g0 + gg;
+            if (g >= mp.ng) break;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int b = 0; b < NBM; b++) {
+                if (b < mp.nb) {
+                    a0 += mul_lazy(b0[b], w[gg][b], m);
+                    a1 += mul_lazy(b1[b], w[gg][b], m);
+                    if ((b & 7) == 7) a0 = reduce(a0, m), a1 = reduce(a1, m);
+                }
+            }
+            uint64_t *o = inner + (size_t)z * istride;
+            o[((size_t)g * 2 * L1 + i) * N + k] = d2u(reduce(a0, m));
+            o[((size_t)(g * 2 + 1) * L1 + i) * N + k] = d2u(reduce(a1, m));
+        }
+    }
+}
+
+hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, int n_ct, size_t bstride,
+                                 size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s)
+{
+    const double bytes = 8.0 * c->N * (level + 1) * (n_diag + n_ct * (2.0 * mp.nb + 2.0 * mp.ng));
+    if (mp.nb <= 8) {
+        dim3 grid((c->N + kBT - 1) / kBT, level + 1, (mp.ng + 7) / 8);
+        return launch(c, PROF_PMAC, bytes, k_bsgs_mac_multi<8, 8>, grid, dim3(kBT), s, mp, n_ct, bstride, istride,
+                      diag, inner, level, c->d_info, c->log_n);
+    }
+    dim3 grid((c->N + kBT - 1) / kBT, level + 1, (mp.ng + 3) / 4);
+    return launch(c, PROF_PMAC, bytes, k_bsgs_mac_multi<4, 16>, grid, dim3(kBT), s, mp, n_ct, bstride, istride, diag,
+                  inner, level, c->d_info, c->log_n);
 }
 
 // out[z] = in[z] read through X -> X^g[z], l+1 limbs per job (blockIdx.z = job)

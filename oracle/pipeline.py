@@ -150,3 +150,39 @@ class Ctx:
             x = self.ct_rescale(level, x)
             level -= 1
         return self.conj_split(level, x)
+
+
+def block_bsgs(ctx, level, xs, plan, pts, bo, hoist=True):
+    """Block matrix-vector product of Sec. 3.3.4 with BSGS: out_ob = sum_ib K^(ob,ib) x_ib.
+    Baby rotations of every input ciphertext are computed once (hoisted ModUp per
+    input); for each output block and giant step the inner sum runs over all input
+    blocks and baby steps, then one giant rotation is applied to it.
+    pts[(ob, ib)][j]: integer plaintext of diagonal j of block (ob, ib)."""
+    babies = []
+    for x in xs:
+        if hoist:
+            rot = ctx.hoisted_rotations(level, x, [plan.baby_rot(i) for i in plan.babies])
+            babies.append({i: rot[plan.baby_rot(i) % (ctx.N // 2)] for i in plan.babies})
+        else:
+            babies.append({i: ctx.rotate(level, x, plan.baby_rot(i)) for i in plan.babies})
+    outs = []
+    for ob in range(bo):
+        acc = None
+        for g in plan.giants:
+            inner = None
+            for ib in range(len(xs)):
+                for j, (gg, i) in sorted(plan.split.items()):
+                    if gg != g or j not in pts[(ob, ib)]:
+                        continue
+                    t = ctx.ct_pmult(level, babies[ib][i], pts[(ob, ib)][j])
+                    inner = t if inner is None else ctx.ct_add(level, inner, t)
+            if g != 0:
+                inner = ctx.rotate(level, inner, plan.giant_rot(g))
+            acc = inner if acc is None else ctx.ct_add(level, acc, inner)
+        outs.append(acc)
+    return outs
+
+
+def block_conv(ctx, level, xs, plan, pts, bo, hoist=True):
+    """conv layer of Sec. 3.3 (fused with StoC2 when its plan is): block BSGS, then rescale"""
+    return [ctx.ct_rescale(level, y) for y in block_bsgs(ctx, level, xs, plan, pts, bo, hoist)]

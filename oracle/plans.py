@@ -194,3 +194,140 @@ def chain_primes(log_n, n_q, alpha, q0_bits, q_bits, p_bits, gen):
     qs = gen(log_n, q_bits, n_q - 1, q0)
     ps = gen(log_n, p_bits, alpha, q0 + qs)
     return q0 + qs, ps
+
+
+# ------------------------------------------------------- general conv layers
+#
+# A conv layer is a list of taps (o, i, dy, dx, w): output channel o receives
+# w * I_i[y + dy][x + dx] (cross-correlation, zero outside the image).
+#   * 3x3 / 1x1 stride 1, 'same' padding: dy = u - p, dx = v - p.
+#   * stride 2 (Sec. 5, Algorithm 2; Appendix B): O[y][x] = sum K[u][v] I[2y+u-p][2x+v-p]
+#     is the sum over phases (a, b) of unit-stride convs of the polyphase images
+#     I^(a,b)[y][x] = I[2y+a][2x+b] with taps u - p = 2 dy + a, v - p = 2 dx + b.
+# Channel counts above C = N/W^2 are split into C x C blocks (Sec. 3.3.4).
+
+def taps_same(K):
+    """K (C_out, C_in, f, f), stride 1 'same' -> taps"""
+    co, ci, f, _ = K.shape
+    p = (f - 1) // 2
+    return [(o, i, u - p, v - p, float(K[o, i, u, v])) for o in range(co) for i in range(ci)
+            for u in range(f) for v in range(f)]
+
+
+def taps_stride2(K):
+    """K (C_out, C_in, f, f), stride 2 -> taps on the polyphase input (4 C_in channels,
+    channel (2a + b) C_in + i holds I_i[a::2, b::2])"""
+    co, ci, f, _ = K.shape
+    p = (f - 1) // 2
+    out = []
+    for o in range(co):
+        for i in range(ci):
+            for u in range(f):
+                for v in range(f):
+                    dy, a = divmod(u - p, 2)
+                    dx, b = divmod(v - p, 2)
+                    out.append((o, (2 * a + b) * ci + i, dy, dx, float(K[o, i, u, v])))
+    return out
+
+
+def taps_depthwise(K):
+    """K (C, f, f) depthwise, stride 1 'same' -> taps (c, c, dy, dx, w)"""
+    c, f, _ = K.shape
+    p = (f - 1) // 2
+    return [(ch, ch, u - p, v - p, float(K[ch, u, v])) for ch in range(c) for u in range(f) for v in range(f)]
+
+
+def polyphase(img):
+    """(C, w, w) -> (4C, w/2, w/2), channel (2a + b) C + i = img[i, a::2, b::2]"""
+    C = img.shape[0]
+    return np.concatenate([img[:, a::2, b::2] for a in (0, 1) for b in (0, 1)], axis=0)
+
+
+def conv2d_taps(img, taps, c_out):
+    """plain FP64 reference of a tap list"""
+    C, w, _ = img.shape
+    out = np.zeros((c_out, w, w))
+    for (o, i, dy, dx, wt) in taps:
+        sh = np.zeros((w, w))
+        ys, xs = slice(max(0, -dy), min(w, w - dy)), slice(max(0, -dx), min(w, w - dx))
+        yd, xd = slice(max(0, dy), min(w, w + dy)), slice(max(0, dx), min(w, w + dx))
+        sh[ys, xs] = img[i][yd, xd]
+        out[o] += wt * sh
+    return out
+
+
+def conv2d_strided(img, K, s):
+    """plain FP64 strided cross-correlation with padding (f-1)/2"""
+    C_in, w, _ = img.shape
+    co, _, f, _ = K.shape
+    p = (f - 1) // 2
+    pad = np.zeros((C_in, w + 2 * p, w + 2 * p))
+    pad[:, p:p + w, p:p + w] = img
+    wo = (w + 2 * p - f) // s + 1
+    out = np.zeros((co, wo, wo))
+    for u in range(f):
+        for v in range(f):
+            out += np.einsum("oi,iyx->oyx", K[:, :, u, v], pad[:, u:u + s * wo:s, v:v + s * wo:s])
+    return out
+
+
+def padded_width_taps(w0, taps):
+    """smallest power of two W with every tap's wrap-around landing in the padding"""
+    reach = max([max(abs(t[2]), abs(t[3])) for t in taps] + [0])
+    W = 1
+    while W < w0 + reach:
+        W *= 2
+    return W
+
+
+def kernel_poly_taps(taps, W):
+    """k(Y) = sum w Y^{-(dy W + dx)} mod (Y^{W^2} + 1) for the taps of one (o, i) pair"""
+    n = W * W
+    k = np.zeros(n)
+    for (dy, dx, wt) in taps:
+        e = -(dy * W + dx)
+        if e >= 0:
+            k[e % n] += wt
+        else:
+            k[(e + n) % n] -= wt
+    return k
+
+
+def block_conv_plan(taps, c_in, c_out, W, N, fuse=True, n1=None):
+    """Diagonals of a (possibly blocked) CinS conv: returns (Bsgs, bi, bo,
+    {(ob, ib): {j: pre-rotated diagonal}}).  fuse = True multiplies StoC2 into the
+    kernel matrix (K^' = S'K^); fuse = False keeps K^ (CinS output)."""
+    n = N // 2
+    ell = W * W // 2
+    C = n // ell
+    bi, bo = -(-c_in // C), -(-c_out // C)
+    by = {}
+    for (o, i, dy, dx, wt) in taps:
+        by.setdefault((o, i), []).append((dy, dx, wt))
+    diags_all = {}
+    structure = None
+    for ob in range(bo):
+        for ib in range(bi):
+            Kh = np.zeros((C, C, ell), dtype=np.complex128)
+            for o in range(C):
+                for i in range(C):
+                    t = by.get((ob * C + o, ib * C + i))
+                    if t:
+                        Kh[o, i] = E.dft_prime(kernel_poly_taps(t, W), ell)
+            if fuse:
+                for i in range(C):
+                    col = Kh[:, i, :].reshape(-1)
+                    k = ell
+                    while k < n:
+                        col = E.apply_stage(col, k)
+                        k *= 2
+                    Kh[:, i, :] = col.reshape(C, ell)
+            diags = {}
+            for k in range(C):
+                d = np.concatenate([Kh[c, (c + k) % C] for c in range(C)])
+                if fuse or np.any(d != 0):
+                    diags[k * ell] = d
+            if structure is None:
+                structure = Bsgs(n, ell, sorted(diags.keys()), n1)
+            diags_all[(ob, ib)] = prerotate(structure, diags)
+    return structure, bi, bo, diags_all

@@ -160,11 +160,12 @@ int nj_plan_galois(const nj_plan *plan, uint32_t *out, int max);
 /* Diagonal offsets of transform t, in the order used by nj_plan_set_diagonal. */
 int nj_plan_offsets(const nj_plan *plan, int t, int32_t *out, int max);
 /* Replaces diagonal `idx` of transform t with host residues [(level_t+1)][N] in
- * coefficient form (already baby-step giant-step pre-rotated). Synchronous. */
+ * coefficient form (already baby-step giant-step pre-rotated). Synchronous.  In a
+ * block conv plan idx = (ob bi + ib) n_diag + d addresses diagonal d of block (ob, ib). */
 nj_status nj_plan_set_diagonal(nj_ctx *ctx, nj_plan *plan, int t, int idx, const uint64_t *coeffs);
 void nj_plan_destroy(nj_plan *plan);
 
-/* Fused conv2d + StoC2 plan (Sec. 3.3, Sec. 4, Algorithm 1 line 1): C = N/W^2
+/* Fused conv2d + StoC2 plan (Sec. 3.3, Sec. 4, Algorithm 1): C = N/W^2
  * channels per ciphertext, W = smallest power of two >= w0 + (f-1)/2.
  *   weights: host double [C][C][f][f] (out, in, row, col), cross-correlation with
  *   'same' zero padding.  Diagonals K' = S'K^, encoded at scale q_1 for level 1.
@@ -180,10 +181,10 @@ nj_status nj_cts_plan_create(nj_ctx *ctx, int groups, nj_plan **out);
  * hoist = 1: baby-step rotations share one ModUp of c1. */
 nj_status nj_plan_apply(nj_ctx *ctx, const nj_plan *plan, int t, const nj_ct *in, nj_ct *out, int hoist, void *stream);
 
-/* Fused conv (Algorithm 1 line 1): BSGS with the K' diagonals at level 1, rescale -> level 0. */
+/* Fused conv (Algorithm 1): BSGS with the K' diagonals at level 1, rescale -> level 0. */
 nj_status nj_conv2d_cins(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_ct *out, void *stream);
 
-/* CoeffToSlot (Algorithm 1 line 2, before EvalMod): ModRaise of the level-0 input to L,
+/* CoeffToSlot (Algorithm 1, before EvalMod): ModRaise of the level-0 input to L,
  * each group's BSGS + rescale, then Re = ct + conj(ct), Im = -X^{N/2}(ct - conj(ct)).
  * re/im: device [2][L-groups+1][N]. */
 nj_status nj_coeff_to_slot(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, nj_ct *re, nj_ct *im, void *stream);
@@ -199,6 +200,41 @@ nj_status nj_apply_galois_batch(nj_ctx *ctx, const nj_ct *in, int n, uint32_t ga
 nj_status nj_conv2d_cins_batch(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, int n, nj_ct *out, void *stream);
 nj_status nj_coeff_to_slot_batch(nj_ctx *ctx, const nj_plan *cts, const nj_ct *in, int n, nj_ct *re, nj_ct *im,
                                  void *stream);
+
+/* ------------------------------------------------------------ conv variants */
+
+/* One tap of a convolution (Sec. 3.3): out[out_ch][y][x] += w * in[in_ch][y+dy][x+dx],
+ * zero outside the w0 x w0 image.  A 3x3 'same' conv is the taps dy, dx in -1..1; a
+ * pointwise conv the single tap (0, 0); a depthwise conv the taps with
+ * out_ch == in_ch; a stride-2 conv the taps of its polyphase decomposition on the
+ * four phase images of each input channel (phase (a, b) = rows a::2, columns b::2,
+ * stored as channel (2a + b) C_in + i), with offsets floor((u - p)/2). */
+typedef struct {
+    int32_t out_ch, in_ch, dy, dx;
+    double w;
+} nj_tap;
+
+/* Conv plan from a tap list (Sec. 3.3, block convs Sec. 3.3.4).  Layout: W = smallest
+ * power of two >= w0 + max |dy|, |dx|; l = W^2/2 slots per channel; C = N/W^2
+ * channels per ciphertext; channel block b of c_in (c_out) lives in input (output)
+ * ciphertext b, bi = ceil(c_in/C) inputs, bo = ceil(c_out/C) outputs.
+ *   fuse = 1: diagonals of K^' = S'K^ (conv fused with StoC2, all C offsets);
+ *   fuse = 0: diagonals of K^ only (CinS-slot output, e.g. depthwise: one diagonal,
+ *             one PMult, no rotation), only offsets nonzero in some block.
+ *   n1 = baby steps (0 = ceil(sqrt(#offsets))); level = level the plan consumes
+ *   (1..L), diagonals encoded at scale q_level.  At most 16 baby and 16 giant steps.
+ * Errors: NJ_EINVAL for taps outside the channel ranges or |offset| >= W, or all-zero
+ * weights; NJ_EUNSUPPORTED if W^2 > N or the split is too large. */
+nj_status nj_conv_plan_create_taps(nj_ctx *ctx, int w0, int c_in, int c_out, const nj_tap *taps, int n_taps,
+                                   int fuse, int n1, int level, nj_plan **out);
+/* Layout of a conv plan: W, C, l, bi, bo (any pointer may be null).  Returns the
+ * plan's level, -1 for a null or empty plan. */
+int nj_plan_layout(const nj_plan *plan, int *W, int *C, int *ell, int *bi, int *bo);
+/* Block conv (Sec. 3.3.4): bi ciphertexts contiguous from in->data ([bi][2][l+1][N],
+ * level = the plan's) -> bo contiguous outputs [bo][2][l][N] at level l-1 after the
+ * rescale.  Baby steps hoisted once per input, giant steps once per output block.
+ * Outputs must not overlap the inputs. */
+nj_status nj_conv2d_block(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_ct *out, void *stream);
 
 /* ------------------------------------------------------------ profiling */
 

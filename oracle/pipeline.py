@@ -8,9 +8,9 @@ Follows, in the paper's order:
   * BSGS (Sec. 2.5): sum_g ( sum_i d'_{g n1 + i} (.) (ct <<< i u) ) <<< g n1 u; the
     baby rotations are hoisted (one ModUp of c1, automorphism applied to the
     extended digits) when `hoist` is True, giant rotations are plain.
-  * Fused conv (Algorithm 1 line 1, Sec. 4): BSGS at level 1 with K^' diagonals,
+  * Fused conv (Algorithm 1, Sec. 4): BSGS at level 1 with K^' diagonals,
     then rescale to level 0.
-  * CoeffToSlot (Sec. 2.4; Algorithm 1 line 2): ModRaise to the top level, one
+  * CoeffToSlot (Sec. 2.4; Algorithm 1): ModRaise to the top level, one
     BSGS transform + rescale per stage group, then the real split
     Re = ct + conj(ct), Im = -X^{N/2} (ct - conj(ct)).
 """

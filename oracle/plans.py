@@ -296,7 +296,8 @@ def kernel_poly_taps(taps, W):
 def block_conv_plan(taps, c_in, c_out, W, N, fuse=True, n1=None):
     """Diagonals of a (possibly blocked) CinS conv: returns (Bsgs, bi, bo,
     {(ob, ib): {j: pre-rotated diagonal}}).  fuse = True multiplies StoC2 into the
-    kernel matrix (K^' = S'K^); fuse = False keeps K^ (CinS output)."""
+    kernel matrix (K^' = S'K^); fuse = False keeps K^ (CinS output) and only the
+    diagonals that are nonzero in some block."""
     n = N // 2
     ell = W * W // 2
     C = n // ell
@@ -304,8 +305,7 @@ def block_conv_plan(taps, c_in, c_out, W, N, fuse=True, n1=None):
     by = {}
     for (o, i, dy, dx, wt) in taps:
         by.setdefault((o, i), []).append((dy, dx, wt))
-    diags_all = {}
-    structure = None
+    blocks = {}
     for ob in range(bo):
         for ib in range(bi):
             Kh = np.zeros((C, C, ell), dtype=np.complex128)
@@ -327,7 +327,10 @@ def block_conv_plan(taps, c_in, c_out, W, N, fuse=True, n1=None):
                 d = np.concatenate([Kh[c, (c + k) % C] for c in range(C)])
                 if fuse or np.any(d != 0):
                     diags[k * ell] = d
-            if structure is None:
-                structure = Bsgs(n, ell, sorted(diags.keys()), n1)
-            diags_all[(ob, ib)] = prerotate(structure, diags)
+            blocks[(ob, ib)] = diags
+    # one BSGS structure for every block: all C offsets when fused, else the
+    # offsets that some block has
+    offsets = sorted({r for diags in blocks.values() for r in diags})
+    structure = Bsgs(n, ell, offsets, n1)
+    diags_all = {key: prerotate(structure, diags) for key, diags in blocks.items()}
     return structure, bi, bo, diags_all

@@ -30,6 +30,10 @@ class NjCt(ctypes.Structure):
     _fields_ = [("data", vp), ("level", i32), ("is_ntt", i32), ("scale", dbl)]
 
 
+class NjTap(ctypes.Structure):
+    _fields_ = [("out_ch", i32), ("in_ch", i32), ("dy", i32), ("dx", i32), ("w", dbl)]
+
+
 _SIGS = {
     "nj_last_error": (ctypes.c_char_p, []),
     "nj_gen_primes": (i32, [i32, i32, i32, vp, i32, vp]),
@@ -62,6 +66,9 @@ _SIGS = {
     "nj_plan_destroy": (None, [vp]),
     "nj_conv_plan_create": (i32, [vp, i32, i32, vp, i32, ctypes.POINTER(vp)]),
     "nj_cts_plan_create": (i32, [vp, i32, ctypes.POINTER(vp)]),
+    "nj_conv_plan_create_taps": (i32, [vp, i32, i32, i32, vp, i32, i32, i32, i32, ctypes.POINTER(vp)]),
+    "nj_plan_layout": (i32, [vp, vp, vp, vp, vp, vp]),
+    "nj_conv2d_block": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
     "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -175,6 +182,12 @@ class Plan:
         buf = np.zeros(4096, dtype=np.uint32)
         n = _lib.nj_plan_galois(self.ptr, _np_ptr(buf), 4096)
         return [int(x) for x in buf[:n]]
+
+    def layout(self):
+        """(level, W, C, l, bi, bo) of a conv plan"""
+        v = [i32() for _ in range(5)]
+        lvl = _lib.nj_plan_layout(self.ptr, *[ctypes.byref(x) for x in v])
+        return (lvl,) + tuple(x.value for x in v)
 
     def offsets(self, t):
         buf = np.zeros(1 << 16, dtype=np.int32)
@@ -365,6 +378,22 @@ class Ctx:
         h = vp()
         _check(_lib.nj_conv_plan_create(self.ptr, w0, f, _np_ptr(w), n1, ctypes.byref(h)), "nj_conv_plan_create")
         return Plan(h)
+
+    def nj_conv_plan_create_taps(self, w0, c_in, c_out, taps, fuse=1, n1=0, level=1):
+        """taps: iterable of (out_ch, in_ch, dy, dx, w)"""
+        taps = list(taps)
+        arr = (NjTap * len(taps))(*[NjTap(int(o), int(i), int(dy), int(dx), float(w)) for (o, i, dy, dx, w) in taps])
+        h = vp()
+        _check(_lib.nj_conv_plan_create_taps(self.ptr, int(w0), int(c_in), int(c_out), ctypes.cast(arr, vp),
+                                             len(taps), int(fuse), int(n1), int(level), ctypes.byref(h)),
+               "nj_conv_plan_create_taps")
+        return Plan(h)
+
+    def nj_conv2d_block(self, plan, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_conv2d_block(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)),
+               "nj_conv2d_block")
+        return out.sync_from(co)
 
     def nj_cts_plan_create(self, groups):
         h = vp()

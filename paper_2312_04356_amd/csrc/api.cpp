@@ -534,6 +534,126 @@ nj_status apply_galois_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint32
     return ks_down(c, l, K, mj, 0, nullptr, M, s);
 }
 
+// ------------------------------------------------------------------ block conv
+//
+// Block matrix-vector product of a blocked conv (Sec. 3.3.4): bi input ciphertexts
+// [bi][2][l+1][N] -> bo outputs [bo][2][l+1][N], out_ob = sum_ib K^(ob,ib) in_ib.
+// Baby steps are hoisted once per input (shared-key inner products over the inputs),
+// each output block's giant-step inner sums run over all its nonzero input blocks in
+// multiply-accumulate passes of at most 16 babies, and each giant rotation is one
+// shared-key key switch over the output blocks, accumulated into the outputs.
+size_t block_words(const nj_ctx *c, const nj_lt_t &lt)
+{
+    const size_t N = c->N, l = lt.level, clen = 2 * N * (l + 1);
+    const int K = std::min(std::max(lt.bi, lt.bo), kBatch);
+    return clen * (lt.bi * lt.babies.size() + lt.bo * lt.giants.size()) + multi_words(c, l, K);
+}
+
+nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
+{
+    const int l = lt.level, bi = lt.bi, bo = lt.bo, nd = lt.n_diag;
+    const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1);
+    const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
+    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
+    for (int b : lt.babies)
+        if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
+    for (int g : lt.giants)
+        if (g != 0 && !key_of(c, galois_of_rot(c, (long long)g * lt.n1 * lt.u)))
+            return fail(NJ_ENOKEY, "missing giant-step key");
+    uint64_t *baby_all = A.take(clen * bi * nb);   // [nb][bi][clen], baby 0 is the input itself
+    uint64_t *inner_all = A.take(clen * bo * ng);  // [bo][ng][clen]
+    MultiBufs M;
+    if (!baby_all || !inner_all || !multi_bufs(c, l, std::min(std::max(bi, bo), kBatch), A, M))
+        return fail(NJ_ENOMEM, "scratch too small");
+    const size_t ndig = n_digits(c, l), ne = l + 1 + c->alpha;
+    nj_status st;
+    // baby steps of every input, kBatch inputs per ModUp
+    for (int z0 = 0; nb > 1 && z0 < bi; z0 += kBatch) {
+        const int K = std::min(kBatch, bi - z0);
+        const uint64_t *x = in + z0 * clen;
+        if ((st = modup_multi(c, l, K, x + plen, M, s, 2 * (l + 1)))) return st;
+        for (int b = 0; b < nb; b++) {
+            if (lt.babies[b] == 0) continue;
+            const uint32_t g = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
+            KeyJobs kj;
+            MdJobs mj;
+            for (int z = 0; z < K; z++) {
+                kj.ext[z] = M.ext + (size_t)z * ndig * ne * N, kj.d[z] = x + z * clen + plen, kj.g[z] = g;
+                mj.add[z] = x + z * clen, mj.g_add[z] = g, mj.out[z] = baby_all + ((size_t)b * bi + z0 + z) * clen;
+            }
+            NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, g), M.u, s));
+            if ((st = ks_down(c, l, K, mj, 0, nullptr, M, s))) return st;
+        }
+    }
+    // inner sums: output block ob, giant g = sum over (ib, baby) of diag (.) baby
+    std::vector<int> gidx(nd), bidx(nd);
+    for (int d = 0; d < nd; d++) {
+        gidx[d] = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
+        bidx[d] = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
+    }
+    auto nonzero = [&](int ob, int ib, int d) { return lt.nz.empty() || lt.nz[((size_t)ob * bi + ib) * nd + d]; };
+    for (int ob = 0; ob < bo; ob++) {
+        std::vector<int> ibs;
+        for (int ib = 0; ib < bi; ib++)
+            for (int d = 0; d < nd; d++)
+                if (nonzero(ob, ib, d)) {
+                    ibs.push_back(ib);
+                    break;
+                }
+        const uint64_t *dbase = lt.d_diag + (size_t)ob * bi * nd * plen;
+        uint64_t *inner = inner_all + (size_t)ob * ng * clen;
+        size_t pos = 0;
+        int pass = 0;
+        do {  // a pass with no babies writes zeros (an output block with no weights)
+            MacPlan mp;
+            mp.nb = 0, mp.ng = ng;
+            for (int g = 0; g < NJ_MAX_GIANT; g++)
+                for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
+            int used = 0;
+            for (; pos < ibs.size() && mp.nb + nb <= NJ_MAX_BABY; pos++) {
+                const int ib = ibs[pos];
+                for (int b = 0; b < nb; b++)
+                    mp.baby[mp.nb + b] = lt.babies[b] == 0 ? in + ib * clen : baby_all + ((size_t)b * bi + ib) * clen;
+                for (int d = 0; d < nd; d++)
+                    if (nonzero(ob, ib, d)) mp.d_of[gidx[d]][mp.nb + bidx[d]] = ib * nd + d, used++;
+                mp.nb += nb;
+            }
+            NJ_HIP(launch_bsgs_mac(c, l, mp, dbase, inner, used, s, pass > 0));
+            pass++;
+        } while (pos < ibs.size());
+    }
+    // giant steps
+    bool have = false;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] == 0) {
+            NJ_HIP(hipMemcpy2DAsync(out, clen * 8, inner_all + (size_t)g * clen, ng * clen * 8, clen * 8, bo,
+                                    hipMemcpyDeviceToDevice, s));
+            have = true;
+        }
+    for (int g = 0; g < ng; g++) {
+        if (lt.giants[g] == 0) continue;
+        const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
+        for (int z0 = 0; z0 < bo; z0 += kBatch) {
+            const int K = std::min(kBatch, bo - z0);
+            AutoJobs aj;
+            KeyJobs kj;
+            MdJobs mj;
+            for (int z = 0; z < K; z++) {
+                const uint64_t *x = inner_all + ((size_t)(z0 + z) * ng + g) * clen;
+                aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
+                kj.ext[z] = M.ext + (size_t)z * ndig * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+                mj.add[z] = x, mj.g_add[z] = ge, mj.out[z] = out + (z0 + z) * clen;
+            }
+            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+            NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
+            if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
+        }
+        have = true;
+    }
+    return NJ_OK;
+}
+
 // rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
 nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
 {
@@ -930,7 +1050,8 @@ nj_status nj_plan_set_diagonal(nj_ctx *c, nj_plan *p, int t, int idx, const uint
 {
     if (!c || !p || !coeffs || t < 0 || t >= (int)p->lts.size()) return fail(NJ_EINVAL, "nj_plan_set_diagonal: bad arguments");
     nj_lt_t &lt = p->lts[t];
-    if (idx < 0 || idx >= lt.n_diag) return fail(NJ_EINVAL, "nj_plan_set_diagonal: index out of range");
+    if (idx < 0 || idx >= lt.n_diag * lt.bi * lt.bo) return fail(NJ_EINVAL, "nj_plan_set_diagonal: index out of range");
+    if (!lt.nz.empty()) lt.nz[idx] = 1;
     const size_t plen = (size_t)c->N * (lt.level + 1);
     uint64_t *dst = lt.d_diag + (size_t)idx * plen;
     NJ_HIP(hipMemcpy(dst, coeffs, plen * 8, hipMemcpyHostToDevice));
@@ -954,6 +1075,7 @@ nj_status nj_plan_apply(nj_ctx *c, const nj_plan *p, int t, const nj_ct *in, nj_
     nj_status st = check_ct(c, in, "nj_plan_apply");
     if (st) return st;
     const nj_lt_t &lt = p->lts[t];
+    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_plan_apply: block plans run through nj_conv2d_block");
     if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_plan_apply: ciphertext level differs from the transform's");
     if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_plan_apply: output must not alias input");
     bool ok;
@@ -971,6 +1093,7 @@ nj_status nj_conv2d_cins(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *ou
     nj_status st = check_ct(c, in, "nj_conv2d_cins");
     if (st) return st;
     const nj_lt_t &lt = p->lts[0];
+    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_conv2d_cins: block plans run through nj_conv2d_block");
     if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins: input must be at the plan's level");
     if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_conv2d_cins: output must not alias input");
     const size_t clen = 2 * (size_t)c->N * (lt.level + 1);
@@ -1056,6 +1179,7 @@ nj_status nj_conv2d_cins_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int
     nj_status st = check_batch(c, in, n, out, "nj_conv2d_cins_batch");
     if (st) return st;
     const nj_lt_t &lt = p->lts[0];
+    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_conv2d_cins_batch: block plans run through nj_conv2d_block");
     if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins_batch: input must be at the plan's level");
     const int l = lt.level, Kmax = std::min(n, kBatch);
     const size_t N = c->N, clen = 2 * N * (l + 1), clen_out = 2 * N * l;
@@ -1120,6 +1244,29 @@ nj_status nj_coeff_to_slot_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, i
     re->level = im->level = lo;
     re->is_ntt = im->is_ntt = 1;
     re->scale = im->scale = in->scale;
+    return NJ_OK;
+}
+
+nj_status nj_conv2d_block(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *out, void *stream)
+{
+    if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_block: not a conv plan");
+    const nj_lt_t &lt = p->lts[0];
+    nj_status st = check_batch(c, in, lt.bi, out, "nj_conv2d_block");
+    if (st) return st;
+    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_block: inputs must be at the plan's level");
+    const int l = lt.level;
+    const size_t N = c->N, clen = 2 * N * (l + 1), clen_out = 2 * N * l;
+    if (out->data < in->data + lt.bi * clen && in->data < out->data + lt.bo * clen_out)
+        return fail(NJ_EINVAL, "nj_conv2d_block: outputs overlap the inputs");
+    bool ok;
+    Arena A = arena_for(c, lt.bo * clen + block_words(c, lt) + N * (l + 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *y = A.take(lt.bo * clen);
+    hipStream_t s = S(stream);
+    if ((st = block_bsgs_apply(c, lt, in->data, y, A, s))) return st;
+    for (int z = 0; z < lt.bo; z++)
+        if ((st = rescale(c, l, y + z * clen, out->data + z * clen_out, A, s))) return st;
+    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale;
     return NJ_OK;
 }
 

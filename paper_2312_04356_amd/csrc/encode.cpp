@@ -177,6 +177,110 @@ static std::vector<double> kernel_poly(const double *K, int f, int W)
     return k;
 }
 
+// kernel polynomial of a tap list: k(Y) = sum w Y^{-(dy W + dx)} mod Y^{W^2} + 1
+static std::vector<double> kernel_poly_taps(const std::vector<const nj_tap *> &taps, int W)
+{
+    const int n = W * W;
+    std::vector<double> k(n, 0.0);
+    for (const nj_tap *t : taps) {
+        int e = -(t->dy * W + t->dx);
+        if (e >= 0) k[e % n] += t->w;
+        else k[(e + n) % n] -= t->w;
+    }
+    return k;
+}
+
+// Diagonals of a (possibly blocked) CinS conv given as taps (Sec. 3.3, Sec. 3.3.4):
+// blocks (ob, ib) of C x C channels, diagonal k of a block holds K^[c][(c+k) mod C]
+// (fuse: K^' = S'K^ instead).  The diagonal set is every k when fused, else the
+// union of the nonzero ones over all blocks; nz[(ob bi + ib) nd + d] flags nonzero
+// diagonals, zero ones are neither encoded nor multiplied.
+nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse, int n1,
+                                nj_lt_t &lt, std::vector<std::vector<double>> &dre,
+                                std::vector<std::vector<double>> &dim)
+{
+    const int n = N / 2, ell = W * W / 2;
+    if (W * W > N || ell < 1) return fail(NJ_EUNSUPPORTED, "conv plan: padded image larger than N");
+    const int C = n / ell;
+    const int bi = (c_in + C - 1) / C, bo = (c_out + C - 1) / C;
+    std::map<std::pair<int, int>, std::vector<const nj_tap *>> by;
+    for (int t = 0; t < n_taps; t++) {
+        const nj_tap &tp = taps[t];
+        if (tp.out_ch < 0 || tp.out_ch >= c_out || tp.in_ch < 0 || tp.in_ch >= c_in || std::abs(tp.dy) >= W ||
+            std::abs(tp.dx) >= W)
+            return fail(NJ_EINVAL, "conv plan: tap out of range");
+        by[{tp.out_ch, tp.in_ch}].push_back(&tp);
+    }
+    std::vector<std::vector<std::vector<cplx>>> blocks((size_t)bo * bi);  // [ob bi + ib][k], empty = zero
+    std::vector<char> used(C, fuse ? 1 : 0);
+    for (int ob = 0; ob < bo; ob++)
+        for (int ib = 0; ib < bi; ib++) {
+            std::vector<std::vector<cplx>> Kh((size_t)C * C);  // [o][i] slices of length l, empty = zero
+            bool any = false;
+            for (int o = 0; o < C; o++)
+                for (int i = 0; i < C; i++) {
+                    auto it = by.find({ob * C + o, ib * C + i});
+                    if (it == by.end()) continue;
+                    std::vector<double> kp = kernel_poly_taps(it->second, W);
+                    Kh[(size_t)o * C + i] = dft_prime(kp.data(), ell);
+                    any = true;
+                }
+            auto &dg = blocks[(size_t)ob * bi + ib];
+            dg.assign(C, {});
+            if (!any) continue;
+            if (fuse)  // columns of K^' = S_{n/2} ... S_l applied to (K^[0][i] | ... | K^[C-1][i])
+                for (int i = 0; i < C; i++) {
+                    std::vector<cplx> col((size_t)n, 0.0);
+                    for (int o = 0; o < C; o++)
+                        if (!Kh[(size_t)o * C + i].empty())
+                            for (int j = 0; j < ell; j++) col[(size_t)o * ell + j] = Kh[(size_t)o * C + i][j];
+                    for (int k = ell; k < n; k *= 2) butterfly_stage(col, k, false);
+                    for (int o = 0; o < C; o++)
+                        Kh[(size_t)o * C + i].assign(col.begin() + (size_t)o * ell, col.begin() + (size_t)(o + 1) * ell);
+                }
+            for (int k = 0; k < C; k++) {
+                std::vector<cplx> v((size_t)n, 0.0);
+                bool nz = false;
+                for (int c = 0; c < C; c++) {
+                    const auto &sl = Kh[(size_t)c * C + (c + k) % C];
+                    if (sl.empty()) continue;
+                    for (int j = 0; j < ell; j++) {
+                        v[(size_t)c * ell + j] = sl[j];
+                        nz = nz || sl[j] != cplx(0.0, 0.0);
+                    }
+                }
+                if (!nz) continue;
+                dg[k] = std::move(v);
+                used[k] = 1;
+            }
+        }
+    std::vector<int> ks;
+    for (int k = 0; k < C; k++)
+        if (used[k]) ks.push_back(k);
+    if (ks.empty()) return fail(NJ_EINVAL, "conv plan: every weight is zero");
+    lt.u = ell;
+    lt.n1 = n1;
+    lt.js.clear();
+    for (int k : ks) lt.js.push_back(centred_rep((long long)k * ell, ell, n));
+    bsgs_split(lt, n);
+    const int nd = lt.n_diag;
+    lt.bi = bi, lt.bo = bo;
+    lt.nz.assign((size_t)bo * bi * nd, 0);
+    dre.assign((size_t)bo * bi * nd, {});
+    dim.assign((size_t)bo * bi * nd, {});
+    for (int b = 0; b < bo * bi; b++)
+        for (int d = 0; d < nd; d++) {
+            std::vector<cplx> &v = blocks[b][ks[d]];
+            if (v.empty()) continue;
+            lt.nz[(size_t)b * nd + d] = 1;
+            rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+            auto &r = dre[(size_t)b * nd + d], &m = dim[(size_t)b * nd + d];
+            r.resize(n), m.resize(n);
+            for (int j = 0; j < n; j++) r[j] = v[j].real(), m[j] = v[j].imag();
+        }
+    return NJ_OK;
+}
+
 nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
                                std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
 {

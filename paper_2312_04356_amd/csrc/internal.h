@@ -197,7 +197,9 @@ struct nj_lt_t {
     std::vector<int> js;                 // offsets j (diagonal j*u)
     std::vector<int> g_of, i_of;         // BSGS split j = g n1 + i
     std::vector<int> babies, giants;
-    uint64_t *d_diag = nullptr;          // [n_diag][level+1][N] evaluation form
+    uint64_t *d_diag = nullptr;          // [bo][bi][n_diag][level+1][N] evaluation form
+    int bi = 1, bo = 1;                  // block conv: input / output ciphertexts
+    std::vector<char> nz;                // [bo][bi][n_diag] nonzero diagonals (empty = all)
 };
 
 struct nj_plan {
@@ -206,6 +208,7 @@ struct nj_plan {
     std::vector<nj_lt_t> lts;
     // conv layout
     int W = 0, C = 0, ell = 0, w0 = 0, f = 0;
+    int c_in = 0, c_out = 0;
 };
 
 namespace nj {
@@ -262,7 +265,8 @@ hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, 
                                  size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
-                           int n_diag, hipStream_t s);
+                           int n_diag, hipStream_t s,
+                           int accumulate = 0);
 
 // ------------------------------------------------------------------- ctx.hip
 LimbTab limbs_q(int level);                       // q_0..q_l
@@ -281,6 +285,9 @@ nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int 
 nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
                               std::vector<std::vector<std::vector<double>>> &dre,
                               std::vector<std::vector<std::vector<double>>> &dim);
+nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse, int n1,
+                                nj_lt_t &lt, std::vector<std::vector<double>> &dre,
+                                std::vector<std::vector<double>> &dim);
 void bsgs_split(nj_lt_t &lt, int n);
 
 }  // namespace nj

@@ -150,7 +150,7 @@ hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const 
 // ------------------------------------------------------------------- BSGS
 
 __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *diag, uint64_t *inner, int level,
-                                                 const PrimeInfo *info, int logN)
+                                                 int accumulate, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN, i = blockIdx.y;
     const int k = blockIdx.x * kBT + threadIdx.x;
@@ -166,8 +166,10 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
         }
     }
     for (int g = 0; g < mp.ng; g++) {
-        double a0 = 0.0, a1 = 0.0;
-        int cnt = 0;
+        uint64_t *o0 = inner + ((size_t)g * 2 * L1 + i) * N + k, *o1 = inner + ((size_t)(g * 2 + 1) * L1 + i) * N + k;
+        // a running sum in [0, t) counts as one term of the lazy budget
+        double a0 = accumulate ? u2d(*o0) : 0.0, a1 = accumulate ? u2d(*o1) : 0.0;
+        int cnt = accumulate ? 1 : 0;
 #pragma unroll
         for (int b = 0; b < NJ_MAX_BABY; b++) {
             if (b >= mp.nb) break;
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
             a1 += mul_lazy(b1[b], w, m);
             if ((++cnt & 7) == 0) a0 = reduce(a0, m), a1 = reduce(a1, m);
         }
-        inner[((size_t)g * 2 * L1 + i) * N + k] = d2u(reduce(a0, m));
-        inner[((size_t)(g * 2 + 1) * L1 + i) * N + k] = d2u(reduce(a1, m));
+        *o0 = d2u(reduce(a0, m));
+        *o1 = d2u(reduce(a1, m));
     }
 }
 
@@ -465,11 +467,11 @@ hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_job
 }
 
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
-                           int n_diag, hipStream_t s)
+                           int n_diag, hipStream_t s, int accumulate)
 {
     dim3 grid((c->N + kBT - 1) / kBT, level + 1);
-    return launch(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + 2.0 * mp.ng), k_bsgs_mac, grid,
-                  dim3(kBT), s, mp, diag, inner, level, c->d_info, c->log_n);
+    return launch(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + (2.0 + 2 * accumulate) * mp.ng),
+                  k_bsgs_mac, grid, dim3(kBT), s, mp, diag, inner, level, accumulate, c->d_info, c->log_n);
 }
 
 }  // namespace nj

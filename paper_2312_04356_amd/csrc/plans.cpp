@@ -1,7 +1,9 @@
-// Plan construction: fused conv (K' = S'K^) and CoeffToSlot stage groups, encoded
-// as integer plaintexts and kept on the device in evaluation form.
+// Plan construction: fused conv (K' = S'K^), tap-list / block convs and CoeffToSlot
+// stage groups, encoded as integer plaintexts and kept on the device in evaluation form.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <set>
 
 #include "internal.h"
@@ -10,19 +12,24 @@ using namespace nj;
 
 namespace {
 
-// encode complex diagonals at `scale`, reduce into the level's primes, transform
+// encode complex diagonals at `scale`, reduce into the level's primes, transform.
+// re.size() diagonals (lt.n_diag per block); empty ones are zero and stay zero.
 nj_status upload_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector<double>> &re,
                            const std::vector<std::vector<double>> &im, double scale)
 {
-    const size_t N = c->N, plen = N * (lt.level + 1);
-    NJ_HIP(hipMalloc(&lt.d_diag, plen * lt.n_diag * 8));
+    const size_t N = c->N, plen = N * (lt.level + 1), count = re.size();
+    NJ_HIP(hipMalloc(&lt.d_diag, plen * count * 8));
     int64_t *tmp = nullptr;
     NJ_HIP(hipMalloc(&tmp, N * 8));
     std::vector<int64_t> coeffs(N);
-    for (int d = 0; d < lt.n_diag; d++) {
+    for (size_t d = 0; d < count; d++) {
+        uint64_t *dst = lt.d_diag + d * plen;
+        if (re[d].empty()) {
+            NJ_HIP(hipMemset(dst, 0, plen * 8));
+            continue;
+        }
         encode_slots(c->N, re[d].data(), im[d].data(), scale, coeffs.data());
         NJ_HIP(hipMemcpy(tmp, coeffs.data(), N * 8, hipMemcpyHostToDevice));
-        uint64_t *dst = lt.d_diag + (size_t)d * plen;
         NJ_HIP(launch_signed_to_rns(c, tmp, limbs_q(lt.level), dst, 0, c->d_primes));
         NJ_HIP(launch_ntt(c, dst, limbs_q(lt.level), false, 0));
     }
@@ -77,6 +84,7 @@ nj_status nj_conv_plan_create(nj_ctx *c, int w0, int f, const double *weights, i
     p->C = (c->N / 2) / lt.u;
     p->w0 = w0;
     p->f = f;
+    p->c_in = p->c_out = p->C;
     for (p->W = 1; p->W * p->W < 2 * lt.u; p->W *= 2) {}
     st = upload_diagonals(c, lt, re, im, (double)c->primes[1]);
     if (st) {
@@ -85,6 +93,55 @@ nj_status nj_conv_plan_create(nj_ctx *c, int w0, int f, const double *weights, i
     }
     *out = p;
     return NJ_OK;
+}
+
+nj_status nj_conv_plan_create_taps(nj_ctx *c, int w0, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse,
+                                   int n1, int level, nj_plan **out)
+{
+    if (!c || !taps || !out || w0 < 1 || c_in < 1 || c_out < 1 || n_taps < 1 || n1 < 0)
+        return fail(NJ_EINVAL, "nj_conv_plan_create_taps: bad arguments");
+    if (level < 1 || level > c->L) return fail(NJ_ELEVEL, "nj_conv_plan_create_taps: need 1 <= level <= L");
+    int reach = 0;
+    for (int t = 0; t < n_taps; t++) reach = std::max(reach, std::max(std::abs(taps[t].dy), std::abs(taps[t].dx)));
+    int W = 1;
+    while (W < w0 + reach) W *= 2;
+    if (W * W > c->N) return fail(NJ_EUNSUPPORTED, "nj_conv_plan_create_taps: padded image larger than N");
+    nj_plan *p = new nj_plan();
+    p->kind = 0;
+    p->N = c->N;
+    p->lts.resize(1);
+    nj_lt_t &lt = p->lts[0];
+    lt.level = level;
+    std::vector<std::vector<double>> re, im;
+    nj_status st = build_block_diagonals(c->N, W, c_in, c_out, taps, n_taps, fuse ? 1 : 0, n1, lt, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    if (lt.babies.size() > NJ_MAX_BABY || lt.giants.size() > NJ_MAX_GIANT) {
+        delete p;
+        return fail(NJ_EUNSUPPORTED, "nj_conv_plan_create_taps: BSGS split needs at most 16 baby and 16 giant steps");
+    }
+    p->W = W, p->ell = lt.u, p->C = (c->N / 2) / lt.u, p->w0 = w0, p->f = 0;
+    p->c_in = c_in, p->c_out = c_out;
+    st = upload_diagonals(c, lt, re, im, (double)c->primes[level]);
+    if (st) {
+        nj_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return NJ_OK;
+}
+
+int nj_plan_layout(const nj_plan *p, int *W, int *C, int *ell, int *bi, int *bo)
+{
+    if (!p || p->lts.empty()) return -1;
+    if (W) *W = p->W;
+    if (C) *C = p->C;
+    if (ell) *ell = p->ell;
+    if (bi) *bi = p->lts[0].bi;
+    if (bo) *bo = p->lts[0].bo;
+    return p->lts[0].level;
 }
 
 nj_status nj_cts_plan_create(nj_ctx *c, int groups, nj_plan **out)

@@ -146,6 +146,10 @@ nj_status nj_pmult(nj_ctx *ctx, const nj_ct *in, const uint64_t *pt, nj_ct *out,
 nj_status nj_add(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
 nj_status nj_sub(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
 /* Rescale (Sec. 2.4): divide by q_l with rounding, level l -> l-1. */
+/* Level drop: the first level+1 limbs of each polynomial of `in` (level <= in->level),
+ * an exact change of modulus Q_l -> Q_level with the scale unchanged.  out must not
+ * alias in unless level == in->level. */
+nj_status nj_drop_level(nj_ctx *ctx, const nj_ct *in, int level, nj_ct *out, void *stream);
 nj_status nj_rescale(nj_ctx *ctx, const nj_ct *in, nj_ct *out, void *stream);
 /* ModRaise (Sec. 2.4): level-0 ciphertext lifted (centred) to `level`. */
 nj_status nj_modraise(nj_ctx *ctx, const nj_ct *in, int level, nj_ct *out, void *stream);
@@ -177,11 +181,15 @@ nj_status nj_conv_plan_create(nj_ctx *ctx, int w0, int f, const double *weights,
  * its rescale drops; the 1/2 of the real split folded into the last group. */
 nj_status nj_cts_plan_create(nj_ctx *ctx, int groups, nj_plan **out);
 
-/* BSGS evaluation of transform t of the plan on `in` (level must match), no rescale.
+/* BSGS evaluation of transform t of the plan on `in`, no rescale.  The input level may
+ * be the transform's level or any lower one (the first l+1 limbs of each diagonal are
+ * used); out->scale = in->scale * the diagonals' encoding scale.
  * hoist = 1: baby-step rotations share one ModUp of c1. */
 nj_status nj_plan_apply(nj_ctx *ctx, const nj_plan *plan, int t, const nj_ct *in, nj_ct *out, int hoist, void *stream);
 
-/* Fused conv (Algorithm 1): BSGS with the K' diagonals at level 1, rescale -> level 0. */
+/* Fused conv (Algorithm 1): BSGS with the K' diagonals, rescale.  Input at any level
+ * l in 1..the plan's level, output at l-1 with scale in->scale * s_plan / q_l, where
+ * s_plan is the plan's encoding scale (q at the plan's level: exact when l equals it). */
 nj_status nj_conv2d_cins(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_ct *out, void *stream);
 
 /* CoeffToSlot (Algorithm 1, before EvalMod): ModRaise of the level-0 input to L,
@@ -231,10 +239,43 @@ nj_status nj_conv_plan_create_taps(nj_ctx *ctx, int w0, int c_in, int c_out, con
  * plan's level, -1 for a null or empty plan. */
 int nj_plan_layout(const nj_plan *plan, int *W, int *C, int *ell, int *bi, int *bo);
 /* Block conv (Sec. 3.3.4): bi ciphertexts contiguous from in->data ([bi][2][l+1][N],
- * level = the plan's) -> bo contiguous outputs [bo][2][l][N] at level l-1 after the
- * rescale.  Baby steps hoisted once per input, giant steps once per output block.
- * Outputs must not overlap the inputs. */
+ * l in 1..the plan's level) -> bo contiguous outputs [bo][2][l][N] at level l-1 after
+ * the rescale, scale as for nj_conv2d_cins.  Baby steps hoisted once per input, giant
+ * steps once per output block.  Outputs must not overlap the inputs. */
 nj_status nj_conv2d_block(nj_ctx *ctx, const nj_plan *conv, const nj_ct *in, nj_ct *out, void *stream);
+
+/* ------------------------------------------------------------ batched jobs */
+
+/* One job (Algorithm 1, conv then bootstrapping's first step, at the ciphertext's own
+ * level): conv with plan `conv` on bi input ciphertexts contiguous at in.data (level
+ * 1..the plan's level) -> rescale -> level drop to 0 -> ModRaise -> CoeffToSlot with
+ * the batch's plan -> real split into bo Re and bo Im ciphertexts, contiguous at
+ * re.data and im.data ([bo][2][L-g+1][N], g = number of CoeffToSlot groups).  The
+ * library fills in the level, form and scale of re and im. */
+typedef struct {
+    const nj_plan *conv;
+    nj_ct in;
+    nj_ct re, im;
+} nj_job;
+
+/* Runs the jobs on `stream` using the context scratch.
+ *   mode 0, plain: one job after another, each step as the single-job calls run it.
+ *   mode 1, batched: single-block jobs of one conv plan run together across their
+ *     levels (each baby and giant rotation key read once for up to 16 jobs; ModUp and
+ *     ModDown batched per level), the rescale computes only the limb the level drop
+ *     keeps, and every conv output goes through batched CoeffToSlot.
+ * Both modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
+ * NJ_ELEVEL (input level outside 1..plan level), NJ_ENOKEY, NJ_ENOMEM. */
+nj_status nj_batch_run(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, void *stream);
+
+/* Persistent batched execution: the mode-1 schedule captured once into a HIP graph
+ * that owns its scratch memory; nj_batch_launch replays it with no host work per job.
+ * Capture computes nothing; the jobs' buffers, plans and keys must stay in place for
+ * the batch's lifetime.  Replays on one batch must not overlap. */
+typedef struct nj_batch nj_batch;
+nj_status nj_batch_create(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, nj_batch **out);
+nj_status nj_batch_launch(nj_batch *batch, void *stream);
+void nj_batch_destroy(nj_batch *batch);
 
 /* ------------------------------------------------------------ profiling */
 

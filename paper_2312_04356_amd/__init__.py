@@ -30,6 +30,10 @@ class NjCt(ctypes.Structure):
     _fields_ = [("data", vp), ("level", i32), ("is_ntt", i32), ("scale", dbl)]
 
 
+class NjJob(ctypes.Structure):
+    _fields_ = [("conv", vp), ("inp", NjCt), ("re", NjCt), ("im", NjCt)]
+
+
 class NjTap(ctypes.Structure):
     _fields_ = [("out_ch", i32), ("in_ch", i32), ("dy", i32), ("dx", i32), ("w", dbl)]
 
@@ -69,6 +73,11 @@ _SIGS = {
     "nj_conv_plan_create_taps": (i32, [vp, i32, i32, i32, vp, i32, i32, i32, i32, ctypes.POINTER(vp)]),
     "nj_plan_layout": (i32, [vp, vp, vp, vp, vp, vp]),
     "nj_conv2d_block": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_drop_level": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
+    "nj_batch_run": (i32, [vp, vp, vp, i32, i32, vp]),
+    "nj_batch_create": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
+    "nj_batch_launch": (i32, [vp, vp]),
+    "nj_batch_destroy": (None, [vp]),
     "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
     "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -197,6 +206,21 @@ class Plan:
     def __del__(self):
         if getattr(self, "ptr", None):
             _lib.nj_plan_destroy(self.ptr)
+            self.ptr = None
+
+
+class Batch:
+    """nj_batch: a captured HIP graph of a batched job list (holds its plans and buffers)."""
+
+    def __init__(self, ptr, keep):
+        self.ptr, self.keep = ptr, keep
+
+    def launch(self, stream=None):
+        _check(_lib.nj_batch_launch(self.ptr, _stream(stream)), "nj_batch_launch")
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.nj_batch_destroy(self.ptr)
             self.ptr = None
 
 
@@ -394,6 +418,38 @@ class Ctx:
         _check(_lib.nj_conv2d_block(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)),
                "nj_conv2d_block")
         return out.sync_from(co)
+
+    def nj_drop_level(self, ct, level, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_drop_level(self.ptr, ctypes.byref(ci), int(level), ctypes.byref(co), _stream(stream)),
+               "nj_drop_level")
+        return out.sync_from(co)
+
+    def _jobs(self, jobs):
+        """jobs: [(conv_plan, in_ct, re_ct, im_ct)] -> ctypes array (kept alive by the caller)"""
+        arr = (NjJob * len(jobs))()
+        for k, (plan, x, re, im) in enumerate(jobs):
+            arr[k] = NjJob(plan.ptr, x.c(), re.c(), im.c())
+        return arr
+
+    def _sync_jobs(self, jobs, arr):
+        for (plan, x, re, im), j in zip(jobs, arr):
+            re.sync_from(j.re)
+            im.sync_from(j.im)
+
+    def nj_batch_run(self, cts_plan, jobs, mode, stream=None):
+        arr = self._jobs(jobs)
+        _check(_lib.nj_batch_run(self.ptr, cts_plan.ptr, ctypes.cast(arr, vp), len(jobs), int(mode), _stream(stream)),
+               "nj_batch_run")
+        self._sync_jobs(jobs, arr)
+
+    def nj_batch_create(self, cts_plan, jobs):
+        arr = self._jobs(jobs)
+        h = vp()
+        _check(_lib.nj_batch_create(self.ptr, cts_plan.ptr, ctypes.cast(arr, vp), len(jobs), ctypes.byref(h)),
+               "nj_batch_create")
+        self._sync_jobs(jobs, arr)
+        return Batch(h, (cts_plan, jobs))
 
     def nj_cts_plan_create(self, groups):
         h = vp()

@@ -7,29 +7,16 @@
 #include <cstring>
 #include <set>
 
-#include "internal.h"
+#include "exec.h"
 
 using namespace nj;
 
 int plan_galois_impl(const nj_plan *p, std::vector<uint32_t> &gs);
 
-namespace {
+namespace nj {
+namespace ex {
 
-hipStream_t S(void *s) { return (hipStream_t)s; }
 
-// Bump allocator over the context scratch buffer.
-struct Arena {
-    uint64_t *p;
-    size_t left;
-    uint64_t *take(size_t w)
-    {
-        if (w > left) return nullptr;
-        uint64_t *r = p;
-        p += w;
-        left -= w;
-        return r;
-    }
-};
 
 size_t ks_words(const nj_ctx *c, int l)
 {
@@ -150,7 +137,7 @@ nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *d_own, const uint64_t *k
 // out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out);
 // in and out may alias.
 nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
-                       const uint64_t *acc = nullptr)
+                       const uint64_t *acc)
 {
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
@@ -170,15 +157,6 @@ nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_
 
 int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
 
-// ------------------------------------------------- K key switches at once
-//
-// Buffers for K jobs at level l: polynomials to switch d [K][l+1], their
-// coefficient form [K][l+1], extended digits [K][dnum][l+1+alpha], inner
-// products [K][2][l+1+alpha], special-prime limbs [K][2][alpha], converted limbs
-// [K][2][l+1] (all x N words).
-struct MultiBufs {
-    uint64_t *d, *coef, *ext, *u, *pc, *conv;
-};
 
 size_t multi_words(const nj_ctx *c, int l, int K)
 {
@@ -200,7 +178,7 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
 
 // ModUp of K polynomials stored at d + z dstride N (evaluation form; dstride in limbs,
 // l+1 when packed) into ext + z dnum ne N.
-nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1)
+nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride)
 {
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
     if (dstride < 0) dstride = l + 1;
@@ -302,7 +280,6 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
 }
 
 // key switches batched per launch in a BSGS transform (baby steps, or a chunk of giant steps)
-constexpr int kGiantChunk = 8;
 int bsgs_jobs(const nj_lt_t &lt)
 {
     return std::max(1, std::max((int)lt.babies.size() - 1, std::min((int)lt.giants.size(), kGiantChunk)));
@@ -375,7 +352,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     }
     // every giant step's inner sum in one pass
     MacPlan mp;
-    mp.nb = nb, mp.ng = ng;
+    mp.nb = nb, mp.ng = ng, mp.dl = lt.dl;
     for (int b = 0; b < nb; b++) mp.baby[b] = baby[b];
     for (int g = 0; g < NJ_MAX_GIANT; g++)
         for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
@@ -426,7 +403,6 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
 //
 // K ciphertexts (contiguous, [K][2][l+1][N]) through one BSGS transform: every key
 // and every diagonal word is read once for the whole batch.  Baby steps hoisted.
-constexpr int kBatch = 8;
 
 size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K)
 {
@@ -469,7 +445,7 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
     }
     // inner sums of every giant step of every ciphertext
     MacPlan mp;
-    mp.nb = nb, mp.ng = ng;
+    mp.nb = nb, mp.ng = ng, mp.dl = lt.dl;
     for (int b = 0; b < nb; b++) mp.baby[b] = lt.babies[b] == 0 ? in : baby_all + (size_t)b * K * clen;
     for (int g = 0; g < NJ_MAX_GIANT; g++)
         for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
@@ -532,6 +508,15 @@ nj_status apply_galois_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint32
     if (st) return st;
     NJ_HIP(launch_key_ip_shared(c, l, kj, K, key, M.u, s));
     return ks_down(c, l, K, mj, 0, nullptr, M, s);
+}
+
+// a transform applied at ciphertext level l <= its plan's: same diagonals (their first
+// l+1 limbs are the residues of the same integer plaintexts), keys serve every level
+nj_lt_t at_level(const nj_lt_t &lt, int l)
+{
+    nj_lt_t a = lt;
+    a.level = l;
+    return a;
 }
 
 // ------------------------------------------------------------------ block conv
@@ -600,13 +585,13 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
                     ibs.push_back(ib);
                     break;
                 }
-        const uint64_t *dbase = lt.d_diag + (size_t)ob * bi * nd * plen;
+        const uint64_t *dbase = lt.d_diag + (size_t)ob * bi * nd * lt.dl * N;
         uint64_t *inner = inner_all + (size_t)ob * ng * clen;
         size_t pos = 0;
         int pass = 0;
         do {  // a pass with no babies writes zeros (an output block with no weights)
             MacPlan mp;
-            mp.nb = 0, mp.ng = ng;
+            mp.nb = 0, mp.ng = ng, mp.dl = lt.dl;
             for (int g = 0; g < NJ_MAX_GIANT; g++)
                 for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
             int used = 0;
@@ -655,9 +640,10 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 }
 
 // rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
-nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
+nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out)
 {
     const size_t N = c->N;
+    if (n_out < 0) n_out = l;
     uint64_t *last = A.take(2 * N), *lifted = A.take(N * l);
     if (!lifted) return fail(NJ_ENOMEM, "scratch too small");
     for (int p = 0; p < 2; p++)
@@ -668,9 +654,10 @@ nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, 
     lt.off[0] = 0, lt.off[1] = 1;
     NJ_HIP(launch_ntt(c, last, lt, true, s));
     for (int p = 0; p < 2; p++) {
-        NJ_HIP(launch_lift_last(c, last + p * N, l, l, lifted, s));
-        NJ_HIP(launch_ntt(c, lifted, limbs_q(l - 1), false, s));
-        NJ_HIP(launch_rescale_combine(c, l, in + (size_t)p * (l + 1) * N, lifted, out + (size_t)p * l * N, s));
+        NJ_HIP(launch_lift_last(c, last + p * N, l, n_out, lifted, s));
+        NJ_HIP(launch_ntt(c, lifted, limbs_q(n_out - 1), false, s));
+        NJ_HIP(launch_rescale_combine(c, l, in + (size_t)p * (l + 1) * N, lifted, out + (size_t)p * n_out * N, s,
+                                      n_out));
     }
     return NJ_OK;
 }
@@ -739,7 +726,84 @@ hipError_t upload_signed(nj_ctx *c, const int64_t *host, int n_rows, const LimbT
     return launch_signed_to_rns(c, (const int64_t *)tmp, lt, dst, s, c->d_primes);
 }
 
-}  // namespace
+size_t cts_batch_words(const nj_ctx *c, const nj_plan *p, int Kmax)
+{
+    const int lo = c->L - (int)p->lts.size();
+    const size_t N = c->N, ctop = 2 * N * (c->L + 1), cout = 2 * N * (lo + 1);
+    size_t need = 0;
+    for (const auto &lt : p->lts) need = std::max(need, bsgs_batch_words(c, lt, Kmax));
+    need = std::max(need, Kmax * cout + multi_words(c, lo, Kmax));
+    return need + 2 * Kmax * ctop + N * (c->L + 2);
+}
+
+// ModRaise + CoeffToSlot + real split of n level-0 ciphertexts (contiguous [n][2][1][N]),
+// kBatch at a time; ciphertext z's outputs go to re[z], im[z].
+nj_status cts_batch(nj_ctx *c, const nj_plan *p, const uint64_t *in, int n, uint64_t *const *re, uint64_t *const *im,
+                    Arena A, hipStream_t s)
+{
+    const int Kmax = std::min(n, kBatch), lo = c->L - (int)p->lts.size();
+    const size_t N = c->N, ctop = 2 * N * (c->L + 1), cin = 2 * N, cout = 2 * N * (lo + 1);
+    uint64_t *x = A.take(Kmax * ctop), *y = A.take(Kmax * ctop);
+    if (!y) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st;
+    for (int z0 = 0; z0 < n; z0 += kBatch) {
+        const int K = std::min(kBatch, n - z0);
+        for (int z = 0; z < K; z++)
+            if ((st = modraise(c, in + (z0 + z) * cin, c->L, x + z * ctop, A, s))) return st;
+        int l = c->L;
+        for (const auto &lt : p->lts) {
+            if (lt.level != l) return fail(NJ_ELEVEL, "CoeffToSlot: plan levels do not follow the context's top level");
+            const size_t cl = 2 * N * (l + 1), cl1 = 2 * N * l;
+            if ((st = bsgs_apply_batch(c, lt, K, x, y, A, s))) return st;
+            for (int z = 0; z < K; z++)
+                if ((st = rescale(c, l, y + z * cl, x + z * cl1, A, s))) return st;
+            l--;
+        }
+        // real split of every ciphertext: one batch of conjugations
+        Arena B = A;
+        uint64_t *cj = B.take(K * cout);
+        if ((st = apply_galois_batch(c, l, K, x, 2 * c->N - 1, cj, B, s))) return st;
+        for (int z = 0; z < K; z++) {
+            uint64_t *xz = x + z * cout, *cz = cj + z * cout;
+            NJ_HIP(launch_elementwise(c, 0, xz, cz, re[z0 + z], ct_limbs(l), s));
+            NJ_HIP(launch_elementwise(c, 1, xz, cz, cz, ct_limbs(l), s));
+            NJ_HIP(launch_monomial_half(c, l, cz, im[z0 + z], s));
+        }
+    }
+    return NJ_OK;
+}
+
+size_t cts_single_words(const nj_ctx *c, const nj_plan *p)
+{
+    const size_t N = c->N, top = c->L, clen = 2 * N * (top + 1);
+    size_t need = 0;
+    for (const auto &lt : p->lts) need = std::max(need, bsgs_words(c, lt));
+    return std::max(need, ks_words(c, c->L) + clen) + 2 * clen + N * (top + 2);
+}
+
+// ModRaise + CoeffToSlot + real split of one level-0 ciphertext [2][1][N]
+nj_status cts_single(nj_ctx *c, const nj_plan *p, const uint64_t *in, uint64_t *re, uint64_t *im, Arena A,
+                     hipStream_t s)
+{
+    const size_t N = c->N, clen = 2 * N * (c->L + 1);
+    uint64_t *x = A.take(clen), *y = A.take(clen);
+    if (!y) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st = modraise(c, in, c->L, x, A, s);
+    if (st) return st;
+    int l = c->L;
+    for (const auto &lt : p->lts) {
+        if (lt.level != l) return fail(NJ_ELEVEL, "CoeffToSlot: plan levels do not follow the context's top level");
+        if ((st = bsgs_apply(c, lt, x, y, 1, A, s))) return st;
+        if ((st = rescale(c, l, y, x, A, s))) return st;
+        l--;
+    }
+    return conj_split(c, l, x, re, im, A, s);
+}
+
+}  // namespace ex
+}  // namespace nj
+
+using namespace nj::ex;
 
 extern "C" {
 
@@ -1009,6 +1073,21 @@ nj_status nj_rescale(nj_ctx *c, const nj_ct *in, nj_ct *out, void *stream)
     return NJ_OK;
 }
 
+nj_status nj_drop_level(nj_ctx *c, const nj_ct *in, int level, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_drop_level");
+    if (st) return st;
+    if (level < 0 || level > in->level) return fail(NJ_ELEVEL, "nj_drop_level: level must be in 0..input level");
+    if (!out || !out->data || (out->data == in->data && level != in->level))
+        return fail(NJ_EINVAL, "nj_drop_level: bad output");
+    const size_t N = c->N;
+    if (out->data != in->data)
+        NJ_HIP(hipMemcpy2DAsync(out->data, (level + 1) * N * 8, in->data, (in->level + 1) * N * 8, (level + 1) * N * 8, 2,
+                                hipMemcpyDeviceToDevice, S(stream)));
+    out->level = level, out->is_ntt = in->is_ntt, out->scale = in->scale;
+    return NJ_OK;
+}
+
 nj_status nj_modraise(nj_ctx *c, const nj_ct *in, int level, nj_ct *out, void *stream)
 {
     nj_status st = check_ct(c, in, "nj_modraise");
@@ -1052,10 +1131,10 @@ nj_status nj_plan_set_diagonal(nj_ctx *c, nj_plan *p, int t, int idx, const uint
     nj_lt_t &lt = p->lts[t];
     if (idx < 0 || idx >= lt.n_diag * lt.bi * lt.bo) return fail(NJ_EINVAL, "nj_plan_set_diagonal: index out of range");
     if (!lt.nz.empty()) lt.nz[idx] = 1;
-    const size_t plen = (size_t)c->N * (lt.level + 1);
+    const size_t plen = (size_t)c->N * lt.dl;
     uint64_t *dst = lt.d_diag + (size_t)idx * plen;
     NJ_HIP(hipMemcpy(dst, coeffs, plen * 8, hipMemcpyHostToDevice));
-    NJ_HIP(launch_ntt(c, dst, limbs_q(lt.level), false, 0));
+    NJ_HIP(launch_ntt(c, dst, limbs_q(lt.dl - 1), false, 0));
     NJ_HIP(hipDeviceSynchronize());
     return NJ_OK;
 }
@@ -1074,16 +1153,17 @@ nj_status nj_plan_apply(nj_ctx *c, const nj_plan *p, int t, const nj_ct *in, nj_
     if (!c || !p || t < 0 || t >= (int)p->lts.size()) return fail(NJ_EINVAL, "nj_plan_apply: bad arguments");
     nj_status st = check_ct(c, in, "nj_plan_apply");
     if (st) return st;
-    const nj_lt_t &lt = p->lts[t];
-    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_plan_apply: block plans run through nj_conv2d_block");
-    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_plan_apply: ciphertext level differs from the transform's");
+    if (p->lts[t].bi != 1 || p->lts[t].bo != 1)
+        return fail(NJ_EINVAL, "nj_plan_apply: block plans run through nj_conv2d_block");
+    if (in->level > p->lts[t].level) return fail(NJ_ELEVEL, "nj_plan_apply: ciphertext above the transform's level");
     if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_plan_apply: output must not alias input");
+    const nj_lt_t lt = at_level(p->lts[t], in->level);
     bool ok;
     Arena A = arena_for(c, bsgs_words(c, lt), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
     st = bsgs_apply(c, lt, in->data, out->data, hoist, A, S(stream));
     if (st) return st;
-    out->level = lt.level, out->is_ntt = 1, out->scale = in->scale * (double)c->primes[lt.level];
+    out->level = lt.level, out->is_ntt = 1, out->scale = in->scale * lt.scale;
     return NJ_OK;
 }
 
@@ -1092,9 +1172,11 @@ nj_status nj_conv2d_cins(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *ou
     if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_cins: not a conv plan");
     nj_status st = check_ct(c, in, "nj_conv2d_cins");
     if (st) return st;
-    const nj_lt_t &lt = p->lts[0];
-    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_conv2d_cins: block plans run through nj_conv2d_block");
-    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins: input must be at the plan's level");
+    if (p->lts[0].bi != 1 || p->lts[0].bo != 1)
+        return fail(NJ_EINVAL, "nj_conv2d_cins: block plans run through nj_conv2d_block");
+    if (in->level < 1 || in->level > p->lts[0].level)
+        return fail(NJ_ELEVEL, "nj_conv2d_cins: input level must be in 1..the plan's level");
+    const nj_lt_t lt = at_level(p->lts[0], in->level);
     if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_conv2d_cins: output must not alias input");
     const size_t clen = 2 * (size_t)c->N * (lt.level + 1);
     bool ok;
@@ -1105,7 +1187,7 @@ nj_status nj_conv2d_cins(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *ou
     if (st) return st;
     st = rescale(c, lt.level, y, out->data, A, S(stream));
     if (st) return st;
-    out->level = lt.level - 1, out->is_ntt = 1, out->scale = in->scale;
+    out->level = lt.level - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[lt.level];
     return NJ_OK;
 }
 
@@ -1116,29 +1198,11 @@ nj_status nj_coeff_to_slot(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *
     if (st) return st;
     if (in->level != 0) return fail(NJ_ELEVEL, "nj_coeff_to_slot: input must be at level 0");
     if (!re || !im || !re->data || !im->data) return fail(NJ_EINVAL, "nj_coeff_to_slot: null output");
-    const size_t N = c->N, top = c->L, clen = 2 * N * (top + 1);
-    size_t need = 0;
-    for (const auto &lt : p->lts) need = std::max(need, bsgs_words(c, lt));
-    need = std::max(need, ks_words(c, c->L) + clen) + 2 * clen + N * (top + 2);
     bool ok;
-    Arena A = arena_for(c, need, ok);
+    Arena A = arena_for(c, cts_single_words(c, p), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
-    uint64_t *x = A.take(clen), *y = A.take(clen);
-    hipStream_t s = S(stream);
-    st = modraise(c, in->data, c->L, x, A, s);
-    if (st) return st;
-    int l = c->L;
-    for (const auto &lt : p->lts) {
-        if (lt.level != l) return fail(NJ_ELEVEL, "nj_coeff_to_slot: plan levels do not follow the context's top level");
-        st = bsgs_apply(c, lt, x, y, 1, A, s);
-        if (st) return st;
-        st = rescale(c, l, y, x, A, s);
-        if (st) return st;
-        l--;
-    }
-    st = conj_split(c, l, x, re->data, im->data, A, s);
-    if (st) return st;
-    re->level = im->level = l;
+    if ((st = cts_single(c, p, in->data, re->data, im->data, A, S(stream)))) return st;
+    re->level = im->level = c->L - (int)p->lts.size();
     re->is_ntt = im->is_ntt = 1;
     re->scale = im->scale = in->scale;
     return NJ_OK;
@@ -1178,9 +1242,11 @@ nj_status nj_conv2d_cins_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int
     if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_cins_batch: not a conv plan");
     nj_status st = check_batch(c, in, n, out, "nj_conv2d_cins_batch");
     if (st) return st;
-    const nj_lt_t &lt = p->lts[0];
-    if (lt.bi != 1 || lt.bo != 1) return fail(NJ_EINVAL, "nj_conv2d_cins_batch: block plans run through nj_conv2d_block");
-    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_cins_batch: input must be at the plan's level");
+    if (p->lts[0].bi != 1 || p->lts[0].bo != 1)
+        return fail(NJ_EINVAL, "nj_conv2d_cins_batch: block plans run through nj_conv2d_block");
+    if (in->level < 1 || in->level > p->lts[0].level)
+        return fail(NJ_ELEVEL, "nj_conv2d_cins_batch: input level must be in 1..the plan's level");
+    const nj_lt_t lt = at_level(p->lts[0], in->level);
     const int l = lt.level, Kmax = std::min(n, kBatch);
     const size_t N = c->N, clen = 2 * N * (l + 1), clen_out = 2 * N * l;
     bool ok;
@@ -1194,7 +1260,7 @@ nj_status nj_conv2d_cins_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int
         for (int z = 0; z < K; z++)
             if ((st = rescale(c, l, y + z * clen, out->data + (z0 + z) * clen_out, A, s))) return st;
     }
-    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale;
+    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[l];
     return NJ_OK;
 }
 
@@ -1206,41 +1272,14 @@ nj_status nj_coeff_to_slot_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, i
     if (st) return st;
     if (in->level != 0) return fail(NJ_ELEVEL, "nj_coeff_to_slot_batch: input must be at level 0");
     if (!im || !im->data || im->data == re->data) return fail(NJ_EINVAL, "nj_coeff_to_slot_batch: bad output");
-    const int Kmax = std::min(n, kBatch), lo = c->L - (int)p->lts.size();
-    const size_t N = c->N, ctop = 2 * N * (c->L + 1), cin = 2 * N, cout = 2 * N * (lo + 1);
-    size_t need = 0;
-    for (const auto &lt : p->lts) need = std::max(need, bsgs_batch_words(c, lt, Kmax));
-    need = std::max(need, Kmax * cout + multi_words(c, lo, Kmax));
-    need += 2 * Kmax * ctop + N * (c->L + 2);
+    const int lo = c->L - (int)p->lts.size();
+    const size_t cout = 2 * (size_t)c->N * (lo + 1);
+    std::vector<uint64_t *> rp(n), ip(n);
+    for (int z = 0; z < n; z++) rp[z] = re->data + z * cout, ip[z] = im->data + z * cout;
     bool ok;
-    Arena A = arena_for(c, need, ok);
+    Arena A = arena_for(c, cts_batch_words(c, p, std::min(n, kBatch)), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
-    uint64_t *x = A.take(Kmax * ctop), *y = A.take(Kmax * ctop);
-    hipStream_t s = S(stream);
-    for (int z0 = 0; z0 < n; z0 += kBatch) {
-        const int K = std::min(kBatch, n - z0);
-        for (int z = 0; z < K; z++)
-            if ((st = modraise(c, in->data + (z0 + z) * cin, c->L, x + z * ctop, A, s))) return st;
-        int l = c->L;
-        for (const auto &lt : p->lts) {
-            if (lt.level != l) return fail(NJ_ELEVEL, "nj_coeff_to_slot_batch: plan levels do not match");
-            const size_t cl = 2 * N * (l + 1), cl1 = 2 * N * l;
-            if ((st = bsgs_apply_batch(c, lt, K, x, y, A, s))) return st;
-            for (int z = 0; z < K; z++)
-                if ((st = rescale(c, l, y + z * cl, x + z * cl1, A, s))) return st;
-            l--;
-        }
-        // real split of every ciphertext: one batch of conjugations
-        Arena B = A;
-        uint64_t *cj = B.take(K * cout);
-        if ((st = apply_galois_batch(c, l, K, x, 2 * c->N - 1, cj, B, s))) return st;
-        for (int z = 0; z < K; z++) {
-            uint64_t *xz = x + z * cout, *cz = cj + z * cout;
-            NJ_HIP(launch_elementwise(c, 0, xz, cz, re->data + (z0 + z) * cout, ct_limbs(l), s));
-            NJ_HIP(launch_elementwise(c, 1, xz, cz, cz, ct_limbs(l), s));
-            NJ_HIP(launch_monomial_half(c, l, cz, im->data + (z0 + z) * cout, s));
-        }
-    }
+    if ((st = cts_batch(c, p, in->data, n, rp.data(), ip.data(), A, S(stream)))) return st;
     re->level = im->level = lo;
     re->is_ntt = im->is_ntt = 1;
     re->scale = im->scale = in->scale;
@@ -1250,10 +1289,11 @@ nj_status nj_coeff_to_slot_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, i
 nj_status nj_conv2d_block(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *out, void *stream)
 {
     if (!c || !p || p->kind != 0 || p->lts.empty()) return fail(NJ_EINVAL, "nj_conv2d_block: not a conv plan");
-    const nj_lt_t &lt = p->lts[0];
-    nj_status st = check_batch(c, in, lt.bi, out, "nj_conv2d_block");
+    nj_status st = check_batch(c, in, p->lts[0].bi, out, "nj_conv2d_block");
     if (st) return st;
-    if (in->level != lt.level) return fail(NJ_ELEVEL, "nj_conv2d_block: inputs must be at the plan's level");
+    if (in->level < 1 || in->level > p->lts[0].level)
+        return fail(NJ_ELEVEL, "nj_conv2d_block: input level must be in 1..the plan's level");
+    const nj_lt_t lt = at_level(p->lts[0], in->level);
     const int l = lt.level;
     const size_t N = c->N, clen = 2 * N * (l + 1), clen_out = 2 * N * l;
     if (out->data < in->data + lt.bi * clen && in->data < out->data + lt.bo * clen_out)
@@ -1266,7 +1306,7 @@ nj_status nj_conv2d_block(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *o
     if ((st = block_bsgs_apply(c, lt, in->data, y, A, s))) return st;
     for (int z = 0; z < lt.bo; z++)
         if ((st = rescale(c, l, y + z * clen, out->data + z * clen_out, A, s))) return st;
-    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale;
+    out->level = l - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[l];
     return NJ_OK;
 }
 

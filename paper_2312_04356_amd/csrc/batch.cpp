@@ -1,0 +1,405 @@
+// Jobs of conv -> rescale -> level drop -> ModRaise -> CoeffToSlot -> real split at
+// uneven levels: a plain schedule (one job after another), a batched schedule (jobs of
+// one conv plan grouped across levels so each rotation key is read once for the group,
+// CoeffToSlot batched over every conv output) and its HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "exec.h"
+
+using namespace nj;
+using namespace nj::ex;
+
+struct nj_batch {
+    nj_ctx *c = nullptr;
+    uint64_t *buf = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// ------------------------------------------------ one transform, uneven levels
+
+struct MixJob {
+    int level;
+    const uint64_t *in;  // [2][level+1][N]
+    uint64_t *out;       // [2][level+1][N], before the rescale
+};
+
+struct Grp {
+    int l, z0, K;
+    MultiBufs M;
+};
+
+// runs of equal level in a level-sorted job list
+std::vector<Grp> level_groups(const std::vector<MixJob> &jobs)
+{
+    std::vector<Grp> g;
+    for (int z = 0; z < (int)jobs.size(); z++) {
+        if (g.empty() || jobs[z].level != g.back().l) g.push_back(Grp{jobs[z].level, z, 0, {}});
+        g.back().K++;
+    }
+    return g;
+}
+
+size_t mixed_words(const nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJob> &jobs)
+{
+    const size_t N = c->N, nb = lt.babies.size(), ng = lt.giants.size();
+    size_t w = 0;
+    for (const Grp &g : level_groups(jobs)) w += multi_words(c, g.l, g.K);
+    for (const MixJob &j : jobs) w += 2 * N * (j.level + 1) * (nb + ng);
+    return w;
+}
+
+// sum_d diag_d (.) (in_z <<< j_d u) for up to NJ_MAX_JOBS ciphertexts sorted by level
+// (each at most the plan's level).  Baby steps hoisted per ciphertext; each baby and
+// giant rotation is one mixed-level shared-key inner product over all jobs, with ModUp
+// and ModDown batched per level group; the multiply-accumulate runs per ciphertext.
+nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJob> &jobs, Arena A, hipStream_t s)
+{
+    const int n = (int)jobs.size(), nb = (int)lt.babies.size(), ng = (int)lt.giants.size(), nd = lt.n_diag;
+    const size_t N = c->N;
+    if (n < 1 || n > NJ_MAX_JOBS) return fail(NJ_EINVAL, "mixed transform: 1..16 ciphertexts");
+    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
+    for (int b : lt.babies)
+        if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
+    for (int g : lt.giants)
+        if (g != 0 && !key_of(c, galois_of_rot(c, (long long)g * lt.n1 * lt.u)))
+            return fail(NJ_ENOKEY, "missing giant-step key");
+    std::vector<Grp> gr = level_groups(jobs);
+    std::vector<int> grp_of(n), idx_in(n);
+    for (int q = 0; q < (int)gr.size(); q++) {
+        if (!multi_bufs(c, gr[q].l, gr[q].K, A, gr[q].M)) return fail(NJ_ENOMEM, "scratch too small");
+        for (int i = 0; i < gr[q].K; i++) grp_of[gr[q].z0 + i] = q, idx_in[gr[q].z0 + i] = i;
+    }
+    std::vector<std::vector<uint64_t *>> baby(n, std::vector<uint64_t *>(nb, nullptr));
+    std::vector<uint64_t *> inner(n);
+    for (int z = 0; z < n; z++) {
+        const size_t clen = 2 * N * (jobs[z].level + 1);
+        for (int b = 0; b < nb; b++) baby[z][b] = A.take(clen);
+        inner[z] = A.take(clen * ng);
+        if (!inner[z]) return fail(NJ_ENOMEM, "scratch too small");
+    }
+    auto ne_of = [&](int l) { return (size_t)(l + 1 + c->alpha); };
+    auto ext_of = [&](int z) {
+        const Grp &g = gr[grp_of[z]];
+        return g.M.ext + (size_t)idx_in[z] * n_digits(c, g.l) * ne_of(g.l) * N;
+    };
+    auto u_of = [&](int z) { return gr[grp_of[z]].M.u + (size_t)idx_in[z] * 2 * ne_of(jobs[z].level) * N; };
+    nj_status st;
+    // baby steps
+    if (nb > 1) {
+        for (Grp &g : gr) {
+            const size_t plen = N * (g.l + 1);
+            for (int i = 0; i < g.K; i++)
+                NJ_HIP(hipMemcpyAsync(g.M.d + i * plen, jobs[g.z0 + i].in + plen, plen * 8, hipMemcpyDeviceToDevice, s));
+            if ((st = modup_multi(c, g.l, g.K, g.M.d, g.M, s))) return st;
+        }
+        for (int b = 0; b < nb; b++) {
+            if (lt.babies[b] == 0) continue;
+            const uint32_t ge = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
+            KeyJobsX kj;
+            for (int z = 0; z < n; z++) {
+                kj.ext[z] = ext_of(z), kj.d[z] = jobs[z].in + N * (jobs[z].level + 1), kj.u[z] = u_of(z);
+                kj.g[z] = ge, kj.lv[z] = jobs[z].level;
+            }
+            NJ_HIP(launch_key_ip_mixed(c, kj, n, key_of(c, ge), s));
+            for (Grp &g : gr) {
+                MdJobs mj;
+                for (int i = 0; i < g.K; i++)
+                    mj.add[i] = jobs[g.z0 + i].in, mj.g_add[i] = ge, mj.out[i] = baby[g.z0 + i][b];
+                if ((st = ks_down(c, g.l, g.K, mj, 0, nullptr, g.M, s))) return st;
+            }
+        }
+    }
+    // every giant step's inner sum, one ciphertext at a time
+    std::vector<int> gidx(nd), bidx(nd);
+    for (int d = 0; d < nd; d++) {
+        gidx[d] = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
+        bidx[d] = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
+    }
+    for (int z = 0; z < n; z++) {
+        MacPlan mp;
+        mp.nb = nb, mp.ng = ng, mp.dl = lt.dl;
+        for (int b = 0; b < nb; b++) mp.baby[b] = lt.babies[b] == 0 ? jobs[z].in : baby[z][b];
+        for (int g = 0; g < NJ_MAX_GIANT; g++)
+            for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
+        int used = 0;
+        for (int d = 0; d < nd; d++)
+            if (lt.nz.empty() || lt.nz[d]) mp.d_of[gidx[d]][bidx[d]] = d, used++;
+        NJ_HIP(launch_bsgs_mac(c, jobs[z].level, mp, lt.d_diag, inner[z], used, s));
+    }
+    // giant steps, accumulated into the outputs
+    bool have = false;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] == 0) {
+            for (int z = 0; z < n; z++) {
+                const size_t clen = 2 * N * (jobs[z].level + 1);
+                NJ_HIP(hipMemcpyAsync(jobs[z].out, inner[z] + (size_t)g * clen, clen * 8, hipMemcpyDeviceToDevice, s));
+            }
+            have = true;
+        }
+    for (int g = 0; g < ng; g++) {
+        if (lt.giants[g] == 0) continue;
+        const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
+        for (Grp &q : gr) {
+            const size_t plen = N * (q.l + 1), clen = 2 * plen;
+            AutoJobs aj;
+            for (int i = 0; i < q.K; i++)
+                aj.in[i] = inner[q.z0 + i] + (size_t)g * clen + plen, aj.out[i] = q.M.d + i * plen, aj.g[i] = ge;
+            NJ_HIP(launch_automorph_multi(c, aj, q.K, q.l + 1, s));
+            if ((st = modup_multi(c, q.l, q.K, q.M.d, q.M, s))) return st;
+        }
+        KeyJobsX kj;
+        for (int z = 0; z < n; z++) {
+            const Grp &q = gr[grp_of[z]];
+            kj.ext[z] = ext_of(z), kj.d[z] = q.M.d + idx_in[z] * N * (q.l + 1), kj.u[z] = u_of(z);
+            kj.g[z] = 1, kj.lv[z] = jobs[z].level;
+        }
+        NJ_HIP(launch_key_ip_mixed(c, kj, n, key_of(c, ge), s));
+        for (Grp &q : gr) {
+            const size_t clen = 2 * N * (q.l + 1);
+            MdJobs mj;
+            for (int i = 0; i < q.K; i++)
+                mj.add[i] = inner[q.z0 + i] + (size_t)g * clen, mj.g_add[i] = ge, mj.out[i] = jobs[q.z0 + i].out;
+            if ((st = ks_down(c, q.l, q.K, mj, 0, have ? jobs[q.z0].out : nullptr, q.M, s))) return st;
+        }
+        have = true;
+    }
+    return NJ_OK;
+}
+
+// ----------------------------------------------------------------- job lists
+
+int job_bi(const nj_job &j) { return j.conv->lts[0].bi; }
+int job_bo(const nj_job &j) { return j.conv->lts[0].bo; }
+
+nj_status check_jobs(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+{
+    if (!c || !cts || cts->kind != 1 || cts->lts.empty()) return fail(NJ_EINVAL, "batch: not a CoeffToSlot plan");
+    if (!jobs || n < 1) return fail(NJ_EINVAL, "batch: no jobs");
+    for (int z = 0; z < n; z++) {
+        const nj_job &j = jobs[z];
+        if (!j.conv || j.conv->kind != 0 || j.conv->lts.empty()) return fail(NJ_EINVAL, "batch: job without a conv plan");
+        nj_status st = check_ct(c, &j.in, "batch job input");
+        if (st) return st;
+        if (j.in.level < 1 || j.in.level > j.conv->lts[0].level)
+            return fail(NJ_ELEVEL, "batch: job input level must be in 1..its plan's level");
+        if (!j.re.data || !j.im.data) return fail(NJ_EINVAL, "batch: job without outputs");
+    }
+    return NJ_OK;
+}
+
+// Work units of the batched schedule: single-block jobs of one plan sorted by level,
+// at most NJ_MAX_JOBS per unit; block jobs one per unit.
+std::vector<std::vector<int>> make_units(const nj_job *jobs, int n)
+{
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (jobs[a].conv != jobs[b].conv) return jobs[a].conv < jobs[b].conv;
+        return jobs[a].in.level < jobs[b].in.level;
+    });
+    std::vector<std::vector<int>> units;
+    for (int z : order) {
+        const bool blk = job_bi(jobs[z]) != 1 || job_bo(jobs[z]) != 1;
+        if (blk || units.empty() || (int)units.back().size() == NJ_MAX_JOBS ||
+            jobs[units.back()[0]].conv != jobs[z].conv || job_bi(jobs[units.back()[0]]) != 1 ||
+            job_bo(jobs[units.back()[0]]) != 1)
+            units.push_back({});
+        units.back().push_back(z);
+    }
+    return units;
+}
+
+std::vector<MixJob> unit_jobs(const nj_job *jobs, const std::vector<int> &u)
+{
+    std::vector<MixJob> mj;
+    for (int z : u) mj.push_back(MixJob{jobs[z].in.level, jobs[z].in.data, nullptr});
+    return mj;
+}
+
+size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+{
+    const size_t N = c->N;
+    size_t outs = 0, phase1 = 0;
+    for (int z = 0; z < n; z++) outs += job_bo(jobs[z]);
+    for (const auto &u : make_units(jobs, n)) {
+        const nj_job &j0 = jobs[u[0]];
+        size_t w = 0;
+        int lmax = 0;
+        if (job_bi(j0) != 1 || job_bo(j0) != 1) {
+            const nj_lt_t lt = at_level(j0.conv->lts[0], j0.in.level);
+            lmax = lt.level;
+            w = lt.bo * 2 * N * (lt.level + 1) + block_words(c, lt);
+        } else {
+            std::vector<MixJob> mj = unit_jobs(jobs, u);
+            for (const MixJob &m : mj) w += 2 * N * (m.level + 1), lmax = std::max(lmax, m.level);
+            w += mixed_words(c, j0.conv->lts[0], mj);
+        }
+        phase1 = std::max(phase1, w + N * (lmax + 2));
+    }
+    const size_t phase2 = cts_batch_words(c, cts, (int)std::min<size_t>(outs, kBatch));
+    return outs * 2 * N + std::max(phase1, phase2);
+}
+
+nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A, hipStream_t s)
+{
+    const size_t N = c->N, clo = 2 * N * (c->L - cts->lts.size() + 1);
+    std::vector<size_t> off(n + 1, 0);
+    for (int z = 0; z < n; z++) off[z + 1] = off[z] + job_bo(jobs[z]);
+    uint64_t *pool = A.take(off[n] * 2 * N);  // level-0 conv outputs [outs][2][1][N]
+    if (!pool) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st;
+    for (const auto &u : make_units(jobs, n)) {
+        Arena B = A;
+        const nj_job &j0 = jobs[u[0]];
+        if (job_bi(j0) != 1 || job_bo(j0) != 1) {
+            const nj_lt_t lt = at_level(j0.conv->lts[0], j0.in.level);
+            const size_t clen = 2 * N * (lt.level + 1);
+            uint64_t *y = B.take(lt.bo * clen);
+            if (!y) return fail(NJ_ENOMEM, "scratch too small");
+            if ((st = block_bsgs_apply(c, lt, j0.in.data, y, B, s))) return st;
+            for (int ob = 0; ob < lt.bo; ob++)
+                if ((st = rescale(c, lt.level, y + ob * clen, pool + (off[u[0]] + ob) * 2 * N, B, s, 1))) return st;
+            continue;
+        }
+        std::vector<MixJob> mj = unit_jobs(jobs, u);
+        for (MixJob &m : mj)
+            if (!(m.out = B.take(2 * N * (m.level + 1)))) return fail(NJ_ENOMEM, "scratch too small");
+        if ((st = bsgs_apply_mixed(c, j0.conv->lts[0], mj, B, s))) return st;
+        for (size_t i = 0; i < u.size(); i++)
+            if ((st = rescale(c, mj[i].level, mj[i].out, pool + off[u[i]] * 2 * N, B, s, 1))) return st;
+    }
+    std::vector<uint64_t *> re(off[n]), im(off[n]);
+    for (int z = 0; z < n; z++)
+        for (int ob = 0; ob < job_bo(jobs[z]); ob++)
+            re[off[z] + ob] = jobs[z].re.data + ob * clo, im[off[z] + ob] = jobs[z].im.data + ob * clo;
+    return cts_batch(c, cts, pool, (int)off[n], re.data(), im.data(), A, s);
+}
+
+size_t plain_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+{
+    const size_t N = c->N;
+    size_t w = 0;
+    for (int z = 0; z < n; z++) {
+        const nj_lt_t lt = at_level(jobs[z].conv->lts[0], jobs[z].in.level);
+        const size_t l = lt.level, bo = lt.bo;
+        const size_t conv = (lt.bi == 1 && bo == 1 ? bsgs_words(c, lt) : block_words(c, lt)) + N * (l + 2);
+        w = std::max(w, bo * 2 * N * (2 * l + 2) + std::max(conv, cts_single_words(c, cts)));
+    }
+    return w;
+}
+
+// one job after another; each step as the single-job calls run it
+nj_status run_plain(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A0, hipStream_t s)
+{
+    const size_t N = c->N, clo = 2 * N * (c->L - cts->lts.size() + 1);
+    nj_status st;
+    for (int z = 0; z < n; z++) {
+        Arena A = A0;
+        const nj_job &j = jobs[z];
+        const nj_lt_t lt = at_level(j.conv->lts[0], j.in.level);
+        const int l = lt.level, bo = lt.bo;
+        const size_t clen = 2 * N * (l + 1), clen1 = 2 * N * l;
+        uint64_t *y = A.take(bo * clen), *r = A.take(bo * clen1), *lo = A.take(bo * 2 * N);
+        if (!lo) return fail(NJ_ENOMEM, "scratch too small");
+        st = lt.bi == 1 && bo == 1 ? bsgs_apply(c, lt, j.in.data, y, 1, A, s) : block_bsgs_apply(c, lt, j.in.data, y, A, s);
+        if (st) return st;
+        for (int ob = 0; ob < bo; ob++) {
+            if ((st = rescale(c, l, y + ob * clen, r + ob * clen1, A, s))) return st;
+            NJ_HIP(hipMemcpy2DAsync(lo + ob * 2 * N, N * 8, r + ob * clen1, l * N * 8, N * 8, 2, hipMemcpyDeviceToDevice,
+                                    s));
+        }
+        for (int ob = 0; ob < bo; ob++)
+            if ((st = cts_single(c, cts, lo + ob * 2 * N, j.re.data + ob * clo, j.im.data + ob * clo, A, s))) return st;
+    }
+    return NJ_OK;
+}
+
+void set_outputs(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+{
+    for (int z = 0; z < n; z++) {
+        nj_job &j = const_cast<nj_job &>(jobs[z]);
+        const nj_lt_t &lt = j.conv->lts[0];
+        j.re.level = j.im.level = c->L - (int)cts->lts.size();
+        j.re.is_ntt = j.im.is_ntt = 1;
+        j.re.scale = j.im.scale = j.in.scale * lt.scale / (double)c->primes[j.in.level];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+nj_status nj_batch_run(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, int mode, void *stream)
+{
+    nj_status st = check_jobs(c, cts, jobs, n);
+    if (st) return st;
+    if (mode != 0 && mode != 1) return fail(NJ_EINVAL, "nj_batch_run: mode must be 0 (plain) or 1 (batched)");
+    bool ok;
+    Arena A = arena_for(c, mode ? batched_words(c, cts, jobs, n) : plain_words(c, cts, jobs, n), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    st = mode ? run_batched(c, cts, jobs, n, A, S(stream)) : run_plain(c, cts, jobs, n, A, S(stream));
+    if (st) return st;
+    set_outputs(c, cts, jobs, n);
+    return NJ_OK;
+}
+
+nj_status nj_batch_create(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, nj_batch **out)
+{
+    nj_status st = check_jobs(c, cts, jobs, n);
+    if (st) return st;
+    if (!out) return fail(NJ_EINVAL, "nj_batch_create: null output");
+    const size_t words = batched_words(c, cts, jobs, n);
+    nj_batch *b = new nj_batch();
+    b->c = c;
+    auto bail = [&](nj_status e) {
+        nj_batch_destroy(b);
+        return e;
+    };
+    if (hipMalloc(&b->buf, words * 8) != hipSuccess) return bail(fail(NJ_ENOMEM, "nj_batch_create: device memory"));
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(NJ_EDEVICE, "nj_batch_create: stream"));
+    const bool prof = c->prof;
+    c->prof = false;  // no event records inside the graph
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        c->prof = prof;
+        return bail(fail(NJ_EDEVICE, "nj_batch_create: stream capture"));
+    }
+    st = run_batched(c, cts, jobs, n, Arena{b->buf, words}, b->cap);
+    const hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
+    c->prof = prof;
+    if (st) return bail(st);
+    if (e != hipSuccess) return bail(fail(NJ_EDEVICE, std::string("nj_batch_create: capture: ") + hipGetErrorString(e)));
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(NJ_EDEVICE, "nj_batch_create: graph instantiation"));
+    set_outputs(c, cts, jobs, n);
+    *out = b;
+    return NJ_OK;
+}
+
+nj_status nj_batch_launch(nj_batch *b, void *stream)
+{
+    if (!b || !b->exec) return fail(NJ_EINVAL, "nj_batch_launch: no batch");
+    NJ_HIP(hipGraphLaunch(b->exec, S(stream)));
+    return NJ_OK;
+}
+
+void nj_batch_destroy(nj_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->buf) (void)hipFree(b->buf);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal executor helpers shared by the C ABI files: scratch arena, key switching
+// of one or many polynomials, BSGS transforms, rescale / ModRaise.
+#pragma once
+
+#include "internal.h"
+
+namespace nj {
+namespace ex {
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+// Bump allocator over the context scratch buffer.
+struct Arena {
+    uint64_t *p;
+    size_t left;
+    uint64_t *take(size_t w)
+    {
+        if (w > left) return nullptr;
+        uint64_t *r = p;
+        p += w;
+        left -= w;
+        return r;
+    }
+};
+
+// Buffers for K jobs at level l: polynomials to switch d [K][l+1], their
+// coefficient form [K][l+1], extended digits [K][dnum][l+1+alpha], inner
+// products [K][2][l+1+alpha], special-prime limbs [K][2][alpha], converted limbs
+// [K][2][l+1] (all x N words).
+struct MultiBufs {
+    uint64_t *d, *coef, *ext, *u, *pc, *conv;
+};
+
+constexpr int kGiantChunk = 8;  // giant-step key switches per batch in a single-ciphertext transform
+constexpr int kBatch = 8;       // ciphertexts per sub-batch of the batched calls
+
+Arena arena_for(nj_ctx *c, size_t words, bool &ok);
+const uint64_t *key_of(const nj_ctx *c, uint32_t g);
+int galois_of_rot(const nj_ctx *c, long long r);
+nj_status check_ct(const nj_ctx *c, const nj_ct *ct, const char *what);
+LimbTab ct_limbs(int l);
+
+size_t ks_words(const nj_ctx *c, int l);
+// out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out)
+nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
+                       const uint64_t *acc = nullptr);
+
+size_t multi_words(const nj_ctx *c, int l, int K);
+bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
+// ModUp of K polynomials at d + z dstride N (dstride in limbs, l+1 when packed)
+nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1);
+// ModDown of K jobs' inner products (M.u) and the combine into their outputs
+nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
+                  hipStream_t s);
+
+nj_lt_t at_level(const nj_lt_t &lt, int l);
+size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt);
+nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
+                     hipStream_t s);
+size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K);
+nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *in, uint64_t *out, Arena A,
+                           hipStream_t s);
+nj_status apply_galois_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint32_t g, uint64_t *out, Arena A,
+                             hipStream_t s);
+size_t block_words(const nj_ctx *c, const nj_lt_t &lt);
+nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s);
+
+// rescale [2][l+1] -> [2][l]; n_out < l keeps only the first n_out limbs of the result
+// (rescale followed by a level drop, computing only the kept limbs)
+nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out = -1);
+nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s);
+nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t *im, Arena A, hipStream_t s);
+
+// ModRaise + CoeffToSlot + real split of n level-0 ciphertexts [n][2][1][N]
+size_t cts_batch_words(const nj_ctx *c, const nj_plan *p, int Kmax);
+nj_status cts_batch(nj_ctx *c, const nj_plan *p, const uint64_t *in, int n, uint64_t *const *re, uint64_t *const *im,
+                    Arena A, hipStream_t s);
+size_t cts_single_words(const nj_ctx *c, const nj_plan *p);
+nj_status cts_single(nj_ctx *c, const nj_plan *p, const uint64_t *in, uint64_t *re, uint64_t *im, Arena A,
+                     hipStream_t s);
+
+}  // namespace ex
+}  // namespace nj

@@ -102,8 +102,19 @@ struct AutoJobs {
 #define NJ_MAX_BABY 16
 #define NJ_MAX_GIANT 16
 // BSGS accumulation plan (kernel argument): d_of[g][b] = diagonal index or -1.
+// Key inner products of jobs at different levels sharing one key (the top-level key
+// serves every level: its digit j, limb t words do not depend on the level).
+struct KeyJobsX {
+    const uint64_t *ext[NJ_MAX_JOBS];  // extended digits [nd_z][l_z+1+alpha][N]
+    const uint64_t *d[NJ_MAX_JOBS];    // own-digit limbs [l_z+1][N], read through X -> X^g[z]
+    uint64_t *u[NJ_MAX_JOBS];          // output [2][l_z+1+alpha][N]
+    uint32_t g[NJ_MAX_JOBS];
+    int lv[NJ_MAX_JOBS];               // level l_z
+};
+
 struct MacPlan {
     int nb, ng;
+    int dl;  // limbs per stored diagonal (the plan's encoding level + 1)
     const uint64_t *baby[NJ_MAX_BABY];
     int d_of[NJ_MAX_GIANT][NJ_MAX_BABY];
 };
@@ -197,7 +208,9 @@ struct nj_lt_t {
     std::vector<int> js;                 // offsets j (diagonal j*u)
     std::vector<int> g_of, i_of;         // BSGS split j = g n1 + i
     std::vector<int> babies, giants;
-    uint64_t *d_diag = nullptr;          // [bo][bi][n_diag][level+1][N] evaluation form
+    uint64_t *d_diag = nullptr;          // [bo][bi][n_diag][dl][N] evaluation form
+    int dl = 0;                          // limbs per diagonal: encoded at level dl-1, usable at any level below
+    double scale = 0.0;                  // encoding scale of the diagonals
     int bi = 1, bo = 1;                  // block conv: input / output ciphertexts
     std::vector<char> nz;                // [bo][bi][n_diag] nonzero diagonals (empty = all)
 };
@@ -234,7 +247,8 @@ hipError_t launch_moddown_combine(const nj_ctx *c, int level, const uint64_t *u,
 hipError_t launch_lift_last(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_out, uint64_t *dst,
                             hipStream_t s);
 hipError_t launch_rescale_combine(const nj_ctx *c, int level, const uint64_t *a, const uint64_t *lifted, uint64_t *out,
-                                  hipStream_t s);
+                                  hipStream_t s,
+                                  int n_out = -1);
 hipError_t launch_pmac(const nj_ctx *c, int level, const uint64_t *ct, const uint64_t *pt, uint64_t *acc, int first,
                        hipStream_t s);
 hipError_t launch_monomial_half(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, hipStream_t s);
@@ -264,6 +278,7 @@ hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, i
 hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, int n_ct, size_t bstride,
                                  size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
+hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s);
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s,
                            int accumulate = 0);

@@ -373,9 +373,9 @@ __global__ void k_rescale_combine(const uint64_t *a, const uint64_t *lifted, uin
 }
 
 hipError_t launch_rescale_combine(const nj_ctx *c, int level, const uint64_t *a, const uint64_t *lifted, uint64_t *out,
-                                  hipStream_t s)
+                                  hipStream_t s, int n_out)
 {
-    dim3 grid((c->N + kThreads - 1) / kThreads, level);
+    dim3 grid((c->N + kThreads - 1) / kThreads, n_out < 0 ? level : n_out);
     hipLaunchKernelGGL(k_rescale_combine, grid, dim3(kThreads), 0, s, a, lifted, out, level, c->d_qlinv, c->d_qlinvq,
                        c->n_q, c->d_info, c->log_n);
     return hipGetLastError();

@@ -11,6 +11,8 @@
 //    optional running sum (giant-step accumulation).
 //  * k_bsgs_mac: every giant step's inner sum sum_i baby_i (.) diag_{g,i} in one pass:
 //    each baby and each diagonal word is read once.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nj {
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
             if (b >= mp.nb) break;
             const int dg = mp.d_of[g][b];
             if (dg < 0) continue;
-            const double w = u2d(diag[((size_t)dg * L1 + i) * N + k]);
+            const double w = u2d(diag[((size_t)dg * mp.dl + i) * N + k]);
             a0 += mul_lazy(b0[b], w, m);
             a1 += mul_lazy(b1[b], w, m);
             if ((++cnt & 7) == 0) a0 = reduce(a0, m), a1 = reduce(a1, m);
@@ -382,6 +384,71 @@ hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, i
                   s, kj, n_jobs, key, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
 }
 
+// Mixed-level form of k_key_ip_shared: grid row t is Q limb t for t <= lmax, special
+// prime t - lmax - 1 after; job z skips Q limbs above its level l_z, and its limb index
+// inside its own [l_z+1+alpha] layout is t (Q) or l_z+1+a (special prime a).
+__global__ __launch_bounds__(kBT) void k_key_ip_mixed(KeyJobsX kj, int n_jobs, const uint64_t *key, int lmax,
+                                                     int ndmax, int L, int alpha, int nq, const PrimeInfo *info,
+                                                     int logN)
+{
+    const int N = 1 << logN;
+    const int t = blockIdx.y;
+    const bool isq = t <= lmax;
+    const int a = t - lmax - 1;
+    const int pidx = isq ? t : nq + a;
+    const int kl = isq ? t : L + 1 + a;
+    const int own = isq ? t / alpha : -1;
+    const int nk = L + 1 + alpha;
+    const Mod m = info[pidx].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    double kb[8], ka[8];  // dnum <= 8 digits per level on this path
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        if (j < ndmax) {
+            kb[j] = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
+            ka[j] = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
+        }
+    }
+    for (int z = 0; z < n_jobs; z++) {
+        const int lz = kj.lv[z];
+        if (isq && t > lz) continue;
+        const int ne = lz + 1 + alpha, loc = isq ? t : lz + 1 + a, nd = (lz + alpha) / alpha;
+        const uint32_t g = kj.g[z];
+        const int src = g == 1u ? k : galois_src2(k, g, logN);
+        const uint64_t *ext = kj.ext[z], *d = kj.d[z];
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (j < nd) {
+                const uint64_t *xp = j == own ? d + (size_t)loc * N : ext + ((size_t)j * ne + loc) * N;
+                double x = u2d(xp[src]);
+                acc0 += mul_lazy(x, kb[j], m);
+                acc1 += mul_lazy(x, ka[j], m);
+            }
+        }
+        uint64_t *u = kj.u[z];
+        u[(size_t)loc * N + k] = d2u(reduce(acc0, m));
+        u[((size_t)ne + loc) * N + k] = d2u(reduce(acc1, m));
+    }
+}
+
+hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s)
+{
+    int lmax = 0;
+    double words = 0.0;
+    for (int z = 0; z < n_jobs; z++) {
+        lmax = std::max(lmax, kj.lv[z]);
+        const int ne = kj.lv[z] + 1 + c->alpha;
+        words += (double)ne * (n_digits(c, kj.lv[z]) + 2.0);
+    }
+    const int ndmax = n_digits(c, lmax), ne = lmax + 1 + c->alpha;
+    if (ndmax > 8) return hipErrorInvalidValue;
+    dim3 grid((c->N + kBT - 1) / kBT, ne);
+    return launch(c, PROF_KEYIP, 8.0 * c->N * (2.0 * ndmax * ne + words), k_key_ip_mixed, grid, dim3(kBT), s, kj,
+                  n_jobs, key, lmax, ndmax, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+}
+
 // BSGS multiply-accumulate for many ciphertexts sharing one transform: blockIdx.z =
 // chunk of up to 4 giant steps whose diagonal words (<= 4 x 16) stay in registers
 // while the ciphertexts' baby steps stream past.  Ciphertext z's baby b is at
@@ -404,7 +471,7 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac_multi(MacPlan mp, int n_ct, si
         for (int b = 0; b < NBM; b++) {
             const int g = g0 + gg;
             const int dg = (g < mp.ng && b < mp.nb) ? mp.d_of[g][b] : -1;
-            w[gg][b] = dg < 0 ? 0.0 : u2d(diag[((size_t)dg * L1 + i) * N + k]);
+            w[gg][b] = dg < 0 ? 0.0 : u2d(diag[((size_t)dg * mp.dl + i) * N + k]);
         }
     for (int z = 0; z < n_ct; z++) {
         double b0[NBM], b1[NBM];

@@ -18,6 +18,8 @@ nj_status upload_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector
                            const std::vector<std::vector<double>> &im, double scale)
 {
     const size_t N = c->N, plen = N * (lt.level + 1), count = re.size();
+    lt.dl = lt.level + 1;
+    lt.scale = scale;
     NJ_HIP(hipMalloc(&lt.d_diag, plen * count * 8));
     int64_t *tmp = nullptr;
     NJ_HIP(hipMalloc(&tmp, N * 8));

@@ -1,0 +1,165 @@
+"""Jobs at uneven levels through the C ABI (needs an MI355X): conv at the ciphertext's
+level with a plan encoded at a higher level -> rescale -> level drop -> ModRaise ->
+CoeffToSlot -> split.
+
+* one job, bit-exact against the oracle (conv at level 4 with level-6 diagonals);
+* the plain schedule, the batched schedule and replays of its HIP graph give the same
+  words for mixed job lists (3x3, pointwise, 2x2-block jobs at levels 1..6 at N = 2^12;
+  3x3 and pointwise jobs at levels 7..23 at N = 2^16);
+* a conv at level 12 with a level-23 plan decrypts to the FP64 conv within 2^-15.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.plans as PL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+from tests.oracle_workload import OracleWorkload  # noqa: E402
+
+RNG = np.random.default_rng(31)
+
+
+def host_coeff(gctx, ct, n_polys=2):
+    t = ct.data.clone()
+    gctx.nj_to_coeff(t, ct.level, n_polys)
+    torch.cuda.synchronize()
+    return gctx.to_host(t)
+
+
+def load_diagonals(gctx, plan, t, pts):
+    for idx, j in enumerate(plan.offsets(t)):
+        gctx.nj_plan_set_diagonal(plan, t, idx, pts[j])
+
+
+def out_cts(g, n_out=1):
+    lo = g.ctx.L - g.w["cts_groups"]
+    return g.ctx.empty_batch(n_out, lo), g.ctx.empty_batch(n_out, lo)
+
+
+def test_job_at_lower_level_matches_oracle():
+    o = OracleWorkload("small", with_cts=True)
+    g = GpuWorkload("small", with_cts=True)
+    gctx, R, N = g.ctx, o.ring, o.N
+    plan_o, diags = PL.conv_plan(o.K, o.W, N)
+    top, lvl = 6, 4
+    w0 = o.w["w0"]
+    plan = gctx.nj_conv_plan_create_taps(w0, o.C, o.C, PL.taps_same(o.K), fuse=1, level=top)
+    assert sorted(plan.offsets(0)) == sorted(plan_o.js)
+    load_diagonals(gctx, plan, 0, PL.encode_diagonals(diags, N, float(o.ring.q[top]), R, top))
+    for t, (cp, pts) in enumerate(o.cts):
+        load_diagonals(gctx, g.cts_plan, t, pts)
+    gs = sorted(set(plan.galois()) | set(g.cts_plan.galois()))
+    g.make_keys(gs)
+    o.make_keys(gs)
+    m = R.to_rns(o.input_plaintext(), lvl)
+    x_o = o.encrypt_input(lvl)
+    x_g = g.encrypt_input(lvl, m_dev=gctx.to_device(m))
+    re, im = out_cts(g)
+    gctx.nj_batch_run(g.cts_plan, [(plan, x_g, re, im)], 0)
+    # oracle: same integer diagonals, their first lvl+1 residues
+    pts_l = PL.encode_diagonals(diags, N, float(o.ring.q[top]), R, lvl)
+    y = o.ctx.ct_rescale(lvl, o.ctx.bsgs(lvl, x_o, plan_o, pts_l))
+    re_o, im_o = o.ctx.coeff_to_slot(y[:, :1], [p for p, _ in o.cts], [q for _, q in o.cts])
+    assert np.array_equal(host_coeff(gctx, re)[0], re_o)
+    assert np.array_equal(host_coeff(gctx, im)[0], im_o)
+    assert re.level == R.L - len(o.cts)
+
+
+def run_three_ways(g, plans, levels):
+    """jobs (plan, level) -> outputs of plain, batched and three graph replays"""
+    gctx = g.ctx
+    jobs = []
+    for (plan, bi, bo), lvl in zip(plans, levels):
+        x = gctx.empty_batch(bi, lvl)
+        for b in range(bi):
+            x.data[b].copy_(g.encrypt_input(lvl).data)
+        x.scale = g.scale
+        re, im = out_cts(g, bo)
+        jobs.append((plan, x, re, im))
+    results = {}
+    for mode in (0, 1):
+        gctx.nj_batch_run(g.cts_plan, jobs, mode)
+        torch.cuda.synchronize()
+        results[mode] = [(j[2].data.clone(), j[3].data.clone()) for j in jobs]
+        for j in jobs:
+            j[2].data.zero_()
+            j[3].data.zero_()
+    batch = gctx.nj_batch_create(g.cts_plan, jobs)
+    torch.cuda.synchronize()
+    reps = []
+    for r in range(3):
+        for j in jobs:
+            j[2].data.zero_()
+            j[3].data.zero_()
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        reps.append([(j[2].data.clone(), j[3].data.clone()) for j in jobs])
+        _ = torch.ones(1 << 20, device=gctx.device).sum().item()  # eager work between replays
+    del batch
+    return results, reps
+
+
+def assert_same(a, b, what):
+    for k, ((r1, i1), (r2, i2)) in enumerate(zip(a, b)):
+        assert torch.equal(r1, r2) and torch.equal(i1, i2), "%s: job %d" % (what, k)
+
+
+def test_plain_batched_graph_agree_small():
+    g = GpuWorkload("small", with_cts=True)
+    gctx, C, w0 = g.ctx, g.C, g.w["w0"]
+    K3 = RNG.uniform(-1, 1, (C, C, 3, 3))
+    K1 = RNG.uniform(-1, 1, (C, C, 1, 1))
+    Kb = RNG.uniform(-1, 1, (2 * C, 2 * C, 3, 3))
+    p3 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K3), level=6)
+    p1 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K1), level=6)
+    pb = gctx.nj_conv_plan_create_taps(w0, 2 * C, 2 * C, PL.taps_same(Kb), level=5)
+    assert p3.layout()[4:] == (1, 1) and pb.layout()[4:] == (2, 2)
+    g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(pb.galois()) | set(g.cts_plan.galois())))
+    plans = [(p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (pb, 2, 2), (p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (p3, 1, 1)]
+    levels = [6, 1, 3, 5, 3, 6, 1, 4]
+    res, reps = run_three_ways(g, plans, levels)
+    assert_same(res[0], res[1], "batched vs plain")
+    for r, rep in enumerate(reps):
+        assert_same(res[1], rep, "graph replay %d" % r)
+
+
+def test_plain_batched_graph_agree_full():
+    g = GpuWorkload("full", with_cts=True)
+    gctx, C, w0 = g.ctx, g.C, g.w["w0"]
+    K1 = RNG.uniform(-1, 1, (C, C, 1, 1))
+    p1 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K1), level=g.ctx.L)
+    p3 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(g.K), level=g.ctx.L)
+    g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(g.cts_plan.galois())))
+    plans = [(p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (p3, 1, 1), (p1, 1, 1)]
+    levels = [7, 12, 12, 23, 16]
+    res, reps = run_three_ways(g, plans, levels)
+    assert_same(res[0], res[1], "batched vs plain")
+    for r, rep in enumerate(reps):
+        assert_same(res[1], rep, "graph replay %d" % r)
+
+
+def test_conv_below_plan_level_decrypts_full():
+    g = GpuWorkload("full", with_cts=False)
+    gctx, C, w0 = g.ctx, g.C, g.w["w0"]
+    plan = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(g.K), level=gctx.L)
+    g.make_keys(plan.galois())
+    x = g.encrypt_input(12)
+    out = gctx.empty_ct(11)
+    gctx.nj_conv2d_cins(plan, x, out)
+    assert abs(out.scale / g.scale - float(g.q[gctx.L]) / float(g.q[12])) < 1e-12
+    dec = torch.empty((12, g.N), dtype=torch.int64, device=gctx.device)
+    gctx.nj_decrypt(out, dec)
+    vals = np.array(O.centred_from_limbs(gctx.to_host(dec)[:2], g.q[:2]), dtype=np.float64) / out.scale
+    ow = OracleWorkload.__new__(OracleWorkload)  # layout helper only
+    ow.w, ow.W, ow.C = g.w, g.W, g.C
+    err = np.max(np.abs(ow.read_conv_output(vals) - PL.conv2d_same(g.img, g.K)))
+    print("conv at level 12 with a level-23 plan: max abs error %.3e" % err)
+    assert err <= 2.0 ** -15

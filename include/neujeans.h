@@ -230,9 +230,9 @@ typedef struct {
  *   fuse = 0: diagonals of K^ only (CinS-slot output, e.g. depthwise: one diagonal,
  *             one PMult, no rotation), only offsets nonzero in some block.
  *   n1 = baby steps (0 = ceil(sqrt(#offsets))); level = level the plan consumes
- *   (1..L), diagonals encoded at scale q_level.  At most 16 baby and 16 giant steps.
+ *   (1..L), diagonals encoded at scale q_level; the plan also serves any lower level.
  * Errors: NJ_EINVAL for taps outside the channel ranges or |offset| >= W, or all-zero
- * weights; NJ_EUNSUPPORTED if W^2 > N or the split is too large. */
+ * weights; NJ_EUNSUPPORTED if W^2 > N. */
 nj_status nj_conv_plan_create_taps(nj_ctx *ctx, int w0, int c_in, int c_out, const nj_tap *taps, int n_taps,
                                    int fuse, int n1, int level, nj_plan **out);
 /* Layout of a conv plan: W, C, l, bi, bo (any pointer may be null).  Returns the

@@ -279,10 +279,35 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     return NJ_OK;
 }
 
+// Multiply-accumulate of one ciphertext's BSGS transform in passes of at most 16 giant
+// x 16 baby steps (later baby passes accumulate): inner_g = sum over entries (g, b, dg)
+// of diag_dg (.) baby_b.  With no babies the giant steps' inner sums are zero.
+nj_status mac_general(nj_ctx *c, int l, const std::vector<const uint64_t *> &baby, int ng,
+                      const std::vector<MacEntry> &ent, const uint64_t *diag, int dl, uint64_t *inner, hipStream_t s)
+{
+    const size_t clen = 2 * (size_t)c->N * (l + 1);
+    const int nb = (int)baby.size();
+    for (int g0 = 0; g0 < ng; g0 += NJ_MAX_GIANT) {
+        const int gn = std::min(NJ_MAX_GIANT, ng - g0);
+        for (int b0 = 0; b0 == 0 || b0 < nb; b0 += NJ_MAX_BABY) {
+            MacPlan mp;
+            mp.nb = std::max(0, std::min(NJ_MAX_BABY, nb - b0)), mp.ng = gn, mp.dl = dl;
+            for (int b = 0; b < mp.nb; b++) mp.baby[b] = baby[b0 + b];
+            for (int g = 0; g < NJ_MAX_GIANT; g++)
+                for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
+            int used = 0;
+            for (const MacEntry &e : ent)
+                if (e.g >= g0 && e.g < g0 + gn && e.b >= b0 && e.b < b0 + mp.nb) mp.d_of[e.g - g0][e.b - b0] = e.dg, used++;
+            NJ_HIP(launch_bsgs_mac(c, l, mp, diag, inner + g0 * clen, used, s, b0 > 0));
+        }
+    }
+    return NJ_OK;
+}
+
 // key switches batched per launch in a BSGS transform (baby steps, or a chunk of giant steps)
 int bsgs_jobs(const nj_lt_t &lt)
 {
-    return std::max(1, std::max((int)lt.babies.size() - 1, std::min((int)lt.giants.size(), kGiantChunk)));
+    return std::min(kGiantChunk, std::max(1, std::max((int)lt.babies.size() - 1, (int)lt.giants.size())));
 }
 
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
@@ -298,8 +323,6 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     const int l = lt.level, n = c->N / 2;
     const size_t N = c->N, clen = 2 * N * (l + 1);
     const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
-    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT)
-        return fail(NJ_EUNSUPPORTED, "BSGS split needs at most 16 baby and 16 giant steps");
     std::vector<const uint64_t *> baby(nb);
     std::vector<uint64_t *> baby_buf(nb);
     for (int b = 0; b < nb; b++) baby_buf[b] = A.take(clen);
@@ -314,54 +337,45 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     MultiBufs M;
     if (!multi_bufs(c, l, bsgs_jobs(lt), A, M)) return fail(NJ_ENOMEM, "scratch too small");
     const size_t nd = n_digits(c, l), ne = l + 1 + c->alpha, plen = N * (l + 1);
-    // baby steps: all rotations of the input as one batch of key switches
-    {
+    // baby steps: the input's rotations as batches of key switches
+    std::vector<int> todo;
+    for (int b = 0; b < nb; b++) {
+        baby[b] = lt.babies[b] == 0 ? in : baby_buf[b];
+        if (lt.babies[b] != 0) todo.push_back(b);
+    }
+    nj_status st;
+    if (hoist && !todo.empty() && (st = modup_multi(c, l, 1, in + plen, M, s))) return st;
+    for (size_t c0 = 0; c0 < todo.size(); c0 += kGiantChunk) {
+        const int K = (int)std::min((size_t)kGiantChunk, todo.size() - c0);
         KeyJobs kj;
         MdJobs mj;
         AutoJobs aj;
-        int K = 0;
-        for (int b = 0; b < nb; b++) {
-            const int i = lt.babies[b];
-            if (i == 0) {
-                baby[b] = in;
-                continue;
-            }
-            const uint32_t g = galois_of_rot(c, (long long)i * lt.u);
-            baby[b] = baby_buf[b];
+        for (int z = 0; z < K; z++) {
+            const int b = todo[c0 + z];
+            const uint32_t g = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
             if (hoist) {  // one ModUp of c1; X -> X^g applied to the extended digits
-                kj.ext[K] = M.ext, kj.d[K] = in + plen, kj.g[K] = g;
+                kj.ext[z] = M.ext, kj.d[z] = in + plen, kj.g[z] = g;
             } else {  // ModUp of each tau_g(c1)
-                aj.in[K] = in + plen, aj.out[K] = M.d + (size_t)K * plen, aj.g[K] = g;
-                kj.ext[K] = M.ext + (size_t)K * nd * ne * N, kj.d[K] = M.d + (size_t)K * plen, kj.g[K] = 1;
+                aj.in[z] = in + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = g;
+                kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
             }
-            kj.key[K] = key_of(c, g);
-            mj.add[K] = in, mj.g_add[K] = g, mj.out[K] = baby_buf[b];
-            K++;
+            kj.key[z] = key_of(c, g);
+            mj.add[z] = in, mj.g_add[z] = g, mj.out[z] = baby_buf[b];
         }
-        if (K) {
-            nj_status st;
-            if (hoist) {
-                st = modup_multi(c, l, 1, in + plen, M, s);
-            } else {
-                NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-                st = modup_multi(c, l, K, M.d, M, s);
-            }
-            if (st) return st;
-            if ((st = ks_multi(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
+        if (!hoist) {
+            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
         }
+        if ((st = ks_multi(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
     }
-    // every giant step's inner sum in one pass
-    MacPlan mp;
-    mp.nb = nb, mp.ng = ng, mp.dl = lt.dl;
-    for (int b = 0; b < nb; b++) mp.baby[b] = baby[b];
-    for (int g = 0; g < NJ_MAX_GIANT; g++)
-        for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
-    for (int d = 0; d < lt.n_diag; d++) {
-        const int g = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
-        const int b = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
-        mp.d_of[g][b] = d;
-    }
-    NJ_HIP(launch_bsgs_mac(c, l, mp, lt.d_diag, inner, lt.n_diag, s));
+    // every giant step's inner sum
+    std::vector<MacEntry> ent;
+    for (int d = 0; d < lt.n_diag; d++)
+        if (lt.nz.empty() || lt.nz[d])
+            ent.push_back(MacEntry{
+                (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin()),
+                (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin()), d});
+    if ((st = mac_general(c, l, baby, ng, ent, lt.d_diag, lt.dl, inner, s))) return st;
     // out = inner_0 + sum_g rot(inner_g, g n1 u): the rotations run as batches of key
     // switches whose ModDown combine also sums them (exact modular sums)
     const uint64_t *acc = nullptr;
@@ -390,8 +404,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         }
         mj.out[0] = out;
         NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-        nj_status st = modup_multi(c, l, K, M.d, M, s);
-        if (st) return st;
+        if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
         if ((st = ks_multi(c, l, K, kj, mj, 1, acc, M, s))) return st;
         acc = out;
     }
@@ -404,9 +417,14 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
 // K ciphertexts (contiguous, [K][2][l+1][N]) through one BSGS transform: every key
 // and every diagonal word is read once for the whole batch.  Baby steps hoisted.
 
+// the multi-ciphertext multiply-accumulate holds at most 16 x 16 steps; larger splits
+// run the transform one ciphertext at a time
+bool batch_mac_fits(const nj_lt_t &lt) { return lt.babies.size() <= NJ_MAX_BABY && lt.giants.size() <= NJ_MAX_GIANT; }
+
 size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K)
 {
     const size_t N = c->N, l = lt.level, clen = 2 * N * (l + 1);
+    if (!batch_mac_fits(lt)) return bsgs_words(c, lt);
     return clen * K * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, K);
 }
 
@@ -416,8 +434,14 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
     const int l = lt.level;
     const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1);
     const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
-    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
     if (K < 1 || K > NJ_MAX_JOBS) return fail(NJ_EINVAL, "batch size out of range");
+    if (!batch_mac_fits(lt)) {
+        for (int z = 0; z < K; z++) {
+            nj_status st = bsgs_apply(c, lt, in + z * clen, out + z * clen, 1, A, s);
+            if (st) return st;
+        }
+        return NJ_OK;
+    }
     for (int b : lt.babies)
         if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
     for (int g : lt.giants)
@@ -539,7 +563,6 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
     const int l = lt.level, bi = lt.bi, bo = lt.bo, nd = lt.n_diag;
     const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1);
     const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
-    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
     for (int b : lt.babies)
         if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
     for (int g : lt.giants)
@@ -587,25 +610,16 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
                 }
         const uint64_t *dbase = lt.d_diag + (size_t)ob * bi * nd * lt.dl * N;
         uint64_t *inner = inner_all + (size_t)ob * ng * clen;
-        size_t pos = 0;
-        int pass = 0;
-        do {  // a pass with no babies writes zeros (an output block with no weights)
-            MacPlan mp;
-            mp.nb = 0, mp.ng = ng, mp.dl = lt.dl;
-            for (int g = 0; g < NJ_MAX_GIANT; g++)
-                for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
-            int used = 0;
-            for (; pos < ibs.size() && mp.nb + nb <= NJ_MAX_BABY; pos++) {
-                const int ib = ibs[pos];
-                for (int b = 0; b < nb; b++)
-                    mp.baby[mp.nb + b] = lt.babies[b] == 0 ? in + ib * clen : baby_all + ((size_t)b * bi + ib) * clen;
-                for (int d = 0; d < nd; d++)
-                    if (nonzero(ob, ib, d)) mp.d_of[gidx[d]][mp.nb + bidx[d]] = ib * nd + d, used++;
-                mp.nb += nb;
-            }
-            NJ_HIP(launch_bsgs_mac(c, l, mp, dbase, inner, used, s, pass > 0));
-            pass++;
-        } while (pos < ibs.size());
+        std::vector<const uint64_t *> bs;
+        std::vector<MacEntry> ent;
+        for (int ib : ibs) {
+            const int b0 = (int)bs.size();
+            for (int b = 0; b < nb; b++)
+                bs.push_back(lt.babies[b] == 0 ? in + ib * clen : baby_all + ((size_t)b * bi + ib) * clen);
+            for (int d = 0; d < nd; d++)
+                if (nonzero(ob, ib, d)) ent.push_back(MacEntry{gidx[d], b0 + bidx[d], ib * nd + d});
+        }
+        if ((st = mac_general(c, l, bs, ng, ent, dbase, lt.dl, inner, s))) return st;
     }
     // giant steps
     bool have = false;

@@ -65,7 +65,6 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
     const int n = (int)jobs.size(), nb = (int)lt.babies.size(), ng = (int)lt.giants.size(), nd = lt.n_diag;
     const size_t N = c->N;
     if (n < 1 || n > NJ_MAX_JOBS) return fail(NJ_EINVAL, "mixed transform: 1..16 ciphertexts");
-    if (nb > NJ_MAX_BABY || ng > NJ_MAX_GIANT) return fail(NJ_EUNSUPPORTED, "BSGS split too large");
     for (int b : lt.babies)
         if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
     for (int g : lt.giants)
@@ -123,16 +122,13 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
         gidx[d] = (int)(std::lower_bound(lt.giants.begin(), lt.giants.end(), lt.g_of[d]) - lt.giants.begin());
         bidx[d] = (int)(std::lower_bound(lt.babies.begin(), lt.babies.end(), lt.i_of[d]) - lt.babies.begin());
     }
+    std::vector<MacEntry> ent;
+    for (int d = 0; d < nd; d++)
+        if (lt.nz.empty() || lt.nz[d]) ent.push_back(MacEntry{gidx[d], bidx[d], d});
     for (int z = 0; z < n; z++) {
-        MacPlan mp;
-        mp.nb = nb, mp.ng = ng, mp.dl = lt.dl;
-        for (int b = 0; b < nb; b++) mp.baby[b] = lt.babies[b] == 0 ? jobs[z].in : baby[z][b];
-        for (int g = 0; g < NJ_MAX_GIANT; g++)
-            for (int b = 0; b < NJ_MAX_BABY; b++) mp.d_of[g][b] = -1;
-        int used = 0;
-        for (int d = 0; d < nd; d++)
-            if (lt.nz.empty() || lt.nz[d]) mp.d_of[gidx[d]][bidx[d]] = d, used++;
-        NJ_HIP(launch_bsgs_mac(c, jobs[z].level, mp, lt.d_diag, inner[z], used, s));
+        std::vector<const uint64_t *> bs(nb);
+        for (int b = 0; b < nb; b++) bs[b] = lt.babies[b] == 0 ? jobs[z].in : baby[z][b];
+        if ((st = mac_general(c, jobs[z].level, bs, ng, ent, lt.d_diag, lt.dl, inner[z], s))) return st;
     }
     // giant steps, accumulated into the outputs
     bool have = false;

@@ -53,6 +53,13 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
                   hipStream_t s);
 
+// inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
+struct MacEntry {
+    int g, b, dg;
+};
+nj_status mac_general(nj_ctx *c, int l, const std::vector<const uint64_t *> &baby, int ng,
+                      const std::vector<MacEntry> &ent, const uint64_t *diag, int dl, uint64_t *inner, hipStream_t s);
+
 nj_lt_t at_level(const nj_lt_t &lt, int l);
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt);
 nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,

@@ -120,10 +120,6 @@ nj_status nj_conv_plan_create_taps(nj_ctx *c, int w0, int c_in, int c_out, const
         delete p;
         return st;
     }
-    if (lt.babies.size() > NJ_MAX_BABY || lt.giants.size() > NJ_MAX_GIANT) {
-        delete p;
-        return fail(NJ_EUNSUPPORTED, "nj_conv_plan_create_taps: BSGS split needs at most 16 baby and 16 giant steps");
-    }
     p->W = W, p->ell = lt.u, p->C = (c->N / 2) / lt.u, p->w0 = w0, p->f = 0;
     p->c_in = c_in, p->c_out = c_out;
     st = upload_diagonals(c, lt, re, im, (double)c->primes[level]);

@@ -256,3 +256,39 @@ def test_full_stride2_64_to_128(full):
     taps = PL.taps_stride2(K)
     want = PL.conv2d_strided(img, K, 2)
     assert own_plan_accuracy(full, PL.polyphase(img), taps, 256, 128, 28, want) == (4, 2)
+
+
+@pytest.mark.parametrize("n1", [32, 2])
+def test_large_bsgs_split_parity(small, n1):
+    """64 channels per ciphertext (W = 8) with 31 baby steps (n1 = 32) or 31 giant steps
+    (n1 = 2): the multiply-accumulate runs in passes of 16 x 16 steps"""
+    w0, c = 6, 64
+    img = RNG.uniform(-1, 1, (c, w0, w0))
+    K = RNG.uniform(-1, 1, (c, c, 3, 3))
+    taps = PL.taps_same(K)
+    N, gctx, R = small.N, small.g.ctx, small.o.ring
+    plan = gctx.nj_conv_plan_create_taps(w0, c, c, taps, fuse=1, n1=n1, level=1)
+    lvl, W, C, ell, bi, bo = plan.layout()
+    assert (W, C, bi, bo) == (8, 64, 1, 1)
+    small.keys(plan.galois())
+    oplan, _, _, diags = PL.block_conv_plan(taps, c, c, W, N, True, n1=n1)
+    assert max(len(oplan.babies), len(oplan.giants)) > 16
+    pts = {k: PL.encode_diagonals(v, N, float(small.q[1]), R, 1) for k, v in diags.items()}
+    load_oracle_blocks(small, plan, oplan, 1, 1, pts, 1)
+    xs, batch = encrypt_blocks(small, img, W, 1, True)
+    out = gctx.empty_batch(1, 0)
+    gctx.nj_conv2d_block(plan, batch, out)
+    want = block_conv(small.o.ctx, 1, xs, oplan, pts, 1)
+    assert np.array_equal(host_coeff_batch(gctx, out, 1)[0], want[0])
+    got = decrypt_outputs(small, out, 1, W, w0)
+    assert np.max(np.abs(got - PL.conv2d_same(img, K))) <= BOUND
+
+
+def test_full_stride2_256_channels_14x14(full):
+    """256 -> 256 stride 2, 14 x 14 -> 7 x 7: polyphase inputs 1024 channels at W = 8
+    (C = 1024, one ciphertext), 1024 diagonals with 31 baby and 31 giant steps"""
+    img = RNG.uniform(-1, 1, (256, 14, 14))
+    K = RNG.uniform(-1, 1, (256, 256, 3, 3)) / 48.0
+    taps = PL.taps_stride2(K)
+    want = PL.conv2d_strided(img, K, 2)
+    assert own_plan_accuracy(full, PL.polyphase(img), taps, 1024, 256, 7, want) == (1, 1)

@@ -277,6 +277,57 @@ nj_status nj_batch_create(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_j
 nj_status nj_batch_launch(nj_batch *batch, void *stream);
 void nj_batch_destroy(nj_batch *batch);
 
+/* ------------------------------------------------------------ plan selection */
+
+/* Timing mode for latency measurement: after nj_timing_keys(ctx, pool) with pool > 0,
+ * a Galois element without a switching key uses one of `pool` key-sized buffers of
+ * random residues (element g -> buffer g mod pool), so candidate plans can be timed
+ * without generating their keys; a pool larger than the last-level cache (16 x 100 MB
+ * at N = 2^16) keeps the key traffic of the real transform.  Results computed with
+ * these buffers are not valid ciphertexts; real keys always take precedence.
+ * pool = 0 leaves timing mode and frees the buffers. Synchronous. */
+nj_status nj_timing_keys(nj_ctx *ctx, int pool);
+
+/* A conv-kind plan with a given BSGS structure and random diagonals, for timing: unit
+ * u slots, n_off diagonal offsets j (diagonal j*u, any representatives), baby size n1
+ * (0 = ceil(sqrt(#offsets))), bi x bo blocks, encoded for `level`. */
+nj_status nj_plan_create_random(nj_ctx *ctx, int level, int u, const int32_t *offsets, int n_off, int n1, int bi,
+                                int bo, uint64_t seed, nj_plan **out);
+
+/* Median time in ms (HIP events on the null stream, one warm-up run, then `reps`) of
+ * transform t of the plan at `level` (<= its level) on random ciphertexts, run as the
+ * library runs it: single-ciphertext hoisted BSGS for one block, block BSGS otherwise
+ * (no rescale).  Synchronous. */
+nj_status nj_time_plan(nj_ctx *ctx, const nj_plan *plan, int t, int level, int reps, float *ms);
+
+/* Cost-model features of transform t at `level`: f[0] = limbs (level+1), f[1] =
+ * log2(N/2 / u), f[2] = diagonals, f[3] = baby steps, f[4] = giant steps, f[5] = bi,
+ * f[6] = bo. */
+nj_status nj_plan_features(const nj_plan *plan, int t, int level, float *f);
+
+/* Learned cost model (plan selection by predicted latency): 7 features -> 64 -> 64 -> 1,
+ * FP32, ReLU.  Parameters (NJ_MLP_PARAMS floats): W1 [7][64], b1 [64], W2 [64][64]
+ * (row = input unit), b2 [64], w3 [64], b3.  Created with He-uniform weights from a
+ * seeded generator and zero biases; training standardises features and target on the
+ * training set and predictions undo it.  All host arrays; synchronous calls. */
+#define NJ_MLP_FEATURES 7
+#define NJ_MLP_HIDDEN 64
+#define NJ_MLP_PARAMS (7 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+typedef struct nj_mlp nj_mlp;
+nj_status nj_mlp_create(uint64_t seed, nj_mlp **out);
+void nj_mlp_destroy(nj_mlp *mlp);
+nj_status nj_mlp_set_params(nj_mlp *mlp, const float *params); /* also resets the Adam state */
+nj_status nj_mlp_get_params(const nj_mlp *mlp, float *params);
+/* Gradient of mean((f(x_i) - y_i)^2) over the n samples X [n][7], y [n] with respect
+ * to every parameter (raw inputs, no standardisation), and the loss. */
+nj_status nj_mlp_grad(nj_mlp *mlp, const float *X, const float *y, int n, float *grad, float *loss);
+/* Adam (lr, beta 0.9 / 0.999, eps 1e-8) on minibatches of `batch` samples, shuffled
+ * each epoch by a seeded generator; final_loss (may be null) = training MSE in
+ * standardised target units. */
+nj_status nj_mlp_train(nj_mlp *mlp, const float *X, const float *y, int n, int epochs, int batch, float lr,
+                       uint64_t seed, float *final_loss);
+nj_status nj_mlp_predict(nj_mlp *mlp, const float *X, int n, float *out);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Live kernel timing for roofline reports: when enabled, the library records HIP

@@ -9,6 +9,9 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: the library's HIP runtime then binds to the HSA runtime torch loaded,
+# and device buffers (torch tensors) and library kernels share one runtime state
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libneujeans.so")
@@ -78,6 +81,17 @@ _SIGS = {
     "nj_batch_create": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
     "nj_batch_launch": (i32, [vp, vp]),
     "nj_batch_destroy": (None, [vp]),
+    "nj_timing_keys": (i32, [vp, i32]),
+    "nj_plan_create_random": (i32, [vp, i32, i32, vp, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]),
+    "nj_time_plan": (i32, [vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
+    "nj_plan_features": (i32, [vp, i32, i32, vp]),
+    "nj_mlp_create": (i32, [u64, ctypes.POINTER(vp)]),
+    "nj_mlp_destroy": (None, [vp]),
+    "nj_mlp_set_params": (i32, [vp, vp]),
+    "nj_mlp_get_params": (i32, [vp, vp]),
+    "nj_mlp_grad": (i32, [vp, vp, vp, i32, vp, ctypes.POINTER(ctypes.c_float)]),
+    "nj_mlp_train": (i32, [vp, vp, vp, i32, i32, i32, ctypes.c_float, u64, ctypes.POINTER(ctypes.c_float)]),
+    "nj_mlp_predict": (i32, [vp, vp, i32, vp]),
     "nj_plan_apply": (i32, [vp, vp, i32, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), i32, vp]),
     "nj_conv2d_cins": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_coeff_to_slot": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -198,6 +212,11 @@ class Plan:
         lvl = _lib.nj_plan_layout(self.ptr, *[ctypes.byref(x) for x in v])
         return (lvl,) + tuple(x.value for x in v)
 
+    def features(self, level, t=0):
+        f = np.zeros(7, dtype=np.float32)
+        _check(_lib.nj_plan_features(self.ptr, int(t), int(level), _np_ptr(f)), "nj_plan_features")
+        return f
+
     def offsets(self, t):
         buf = np.zeros(1 << 16, dtype=np.int32)
         n = _lib.nj_plan_offsets(self.ptr, t, _np_ptr(buf), 1 << 16)
@@ -206,6 +225,57 @@ class Plan:
     def __del__(self):
         if getattr(self, "ptr", None):
             _lib.nj_plan_destroy(self.ptr)
+            self.ptr = None
+
+
+MLP_FEATURES, MLP_HIDDEN = 7, 64
+MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+class Mlp:
+    """nj_mlp: the 7 -> 64 -> 64 -> 1 FP32 latency model (trained and evaluated on the GPU)."""
+
+    def __init__(self, seed=0):
+        h = vp()
+        _check(_lib.nj_mlp_create(u64(seed), ctypes.byref(h)), "nj_mlp_create")
+        self.ptr = h
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.nj_mlp_get_params(self.ptr, _np_ptr(out)), "nj_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (MLP_PARAMS,)
+        _check(_lib.nj_mlp_set_params(self.ptr, _np_ptr(p)), "nj_mlp_set_params")
+
+    def grad(self, X, y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.nj_mlp_grad(self.ptr, _np_ptr(X), _np_ptr(y), len(y), _np_ptr(g), ctypes.byref(loss)),
+               "nj_mlp_grad")
+        return g, loss.value
+
+    def train(self, X, y, epochs=200, batch=256, lr=1e-3, seed=0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.nj_mlp_train(self.ptr, _np_ptr(X), _np_ptr(y), len(y), int(epochs), int(batch), float(lr),
+                                 u64(seed), ctypes.byref(loss)), "nj_mlp_train")
+        return loss.value
+
+    def predict(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        _check(_lib.nj_mlp_predict(self.ptr, _np_ptr(X), X.shape[0], _np_ptr(out)), "nj_mlp_predict")
+        return out
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.nj_mlp_destroy(self.ptr)
             self.ptr = None
 
 
@@ -450,6 +520,22 @@ class Ctx:
                "nj_batch_create")
         self._sync_jobs(jobs, arr)
         return Batch(h, (cts_plan, jobs))
+
+    def nj_timing_keys(self, pool):
+        _check(_lib.nj_timing_keys(self.ptr, int(pool)), "nj_timing_keys")
+
+    def nj_plan_create_random(self, level, u, offsets, n1=0, bi=1, bo=1, seed=1):
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        h = vp()
+        _check(_lib.nj_plan_create_random(self.ptr, int(level), int(u), _np_ptr(off), len(off), int(n1), int(bi),
+                                          int(bo), u64(seed), ctypes.byref(h)), "nj_plan_create_random")
+        return Plan(h)
+
+    def nj_time_plan(self, plan, level, t=0, reps=3):
+        ms = ctypes.c_float()
+        _check(_lib.nj_time_plan(self.ptr, plan.ptr, int(t), int(level), int(reps), ctypes.byref(ms)),
+               "nj_time_plan")
+        return ms.value
 
     def nj_cts_plan_create(self, groups):
         h = vp()

@@ -44,7 +44,9 @@ bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B)
 const uint64_t *key_of(const nj_ctx *c, uint32_t g)
 {
     auto it = c->keys.find(g);
-    return it == c->keys.end() ? nullptr : it->second.d;
+    if (it != c->keys.end()) return it->second.d;
+    if (!c->timing_keys.empty()) return c->timing_keys[g % c->timing_keys.size()];
+    return nullptr;
 }
 
 // ModUp of d (evaluation form, level l): every digit extended to Q_l u P, evaluation form.

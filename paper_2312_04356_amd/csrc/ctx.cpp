@@ -326,6 +326,7 @@ void nj_ctx_destroy(nj_ctx *c)
         for (auto &b : lv) fr(b.hat_inv), fr(b.hat);
     for (auto &b : c->moddown) fr(b.hat_inv), fr(b.hat);
     for (auto &kv : c->keys) fr(kv.second.d);
+    for (auto *k : c->timing_keys) fr(k);
     fr(c->scratch.buf);
     for (auto &r : c->prof_recs) (void)hipEventDestroy(r.a), (void)hipEventDestroy(r.b);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -166,6 +166,7 @@ struct nj_ctx {
     std::vector<int8_t> s;
     uint64_t *d_s = nullptr;
     std::map<uint32_t, nj::Key> keys;
+    std::vector<uint64_t *> timing_keys;  // latency measurement: random key buffers for missing elements
     nj::Scratch scratch;
     // live profiling (nj_prof_*)
     bool prof = false;

@@ -1,0 +1,73 @@
+"""Plan selection on the GPU (needs an MI355X): the cost-model kernels against the
+float64 oracle (forward values and loss gradient), training reduces the loss, and the
+timing helpers (random-diagonal plans, timing keys, features)."""
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_04356_amd import Mlp, NjError  # noqa: E402
+from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+
+RNG = np.random.default_rng(41)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 200])
+def test_mlp_gradient_matches_oracle(n):
+    m = Mlp(seed=5)
+    p = RNG.normal(0, 0.3, M.N_PARAMS).astype(np.float32)
+    m.set_params(p)
+    X = RNG.normal(0, 1, (n, 7)).astype(np.float32)
+    y = RNG.normal(0, 1, n).astype(np.float32)
+    g, loss = m.grad(X, y)
+    want = M.grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64))
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(g - want)) <= 1e-4 * scale
+    assert abs(loss - M.loss(p, X, y)) <= 1e-4 * max(1.0, M.loss(p, X, y))
+
+
+def test_mlp_forward_matches_oracle():
+    m = Mlp(seed=9)  # untrained: identity standardisation
+    p = m.params()
+    X = RNG.normal(0, 1, (130, 7)).astype(np.float32)
+    out, _ = M.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(m.predict(X), out, rtol=1e-4, atol=1e-4)
+
+
+def test_mlp_training_fits_a_smooth_target():
+    X = RNG.uniform(0, 1, (2000, 7)).astype(np.float32)
+    y = (np.log1p(X[:, 0] * X[:, 2] * 8) + 0.5 * X[:, 3] + 0.2 * np.sin(4 * X[:, 4])).astype(np.float32)
+    m = Mlp(seed=1)
+    loss = m.train(X, y, epochs=150, batch=128, lr=2e-3, seed=2)
+    pred = m.predict(X)
+    r = np.corrcoef(pred, y)[0, 1]
+    print("train MSE (standardised) %.4f, correlation %.4f" % (loss, r))
+    assert loss < 0.05 and r > 0.97
+
+
+def test_timing_plans_and_keys():
+    g = GpuWorkload("full", with_cts=False)
+    ctx = g.ctx
+    n = g.N // 2
+    plan = ctx.nj_plan_create_random(3, 2048, list(range(16)), n1=4)  # C = 16 conv structure
+    f = plan.features(3)
+    assert list(f) == [4, 4, 16, 4, 4, 1, 1]
+    with pytest.raises(NjError):  # no keys: the transform refuses to run
+        ctx.nj_time_plan(plan, 3)
+    ctx.nj_timing_keys(16)
+    try:
+        t1 = ctx.nj_time_plan(plan, 3, reps=3)
+        t2 = ctx.nj_time_plan(plan, 1, reps=3)
+        blk = ctx.nj_plan_create_random(1, 2048, list(range(16)), n1=4, bi=2, bo=2)
+        t3 = ctx.nj_time_plan(blk, 1, reps=3)
+        print("C=16 n1=4: level 3 %.3f ms, level 1 %.3f ms, 2x2 blocks level 1 %.3f ms" % (t1, t2, t3))
+        assert 0 < t2 < t1 and t3 > t2
+    finally:
+        ctx.nj_timing_keys(0)
+    assert n == 32768

@@ -7,9 +7,11 @@ rescale, ModRaise to level 23, CoeffToSlot in 3 stage groups, real/imaginary spl
 Inputs (keys, plan diagonals, the encrypted image) are resident in HBM before the
 timed region.  Prints one JSON line.
 
-Order of GPU work: setup, key switches per second, warmup, timed steps, then the
-same number of steps again with the library's per-kernel event timing (the last
-GPU work of the run, so a kernel trace's final dispatches are those steps).
+Order of GPU work: setup, key switches per second (plain and batched), the mixed
+job list at uneven levels (plain vs batched HIP-graph replay), the batched pipeline,
+warmup, timed steps, then the same number of steps again with the library's
+per-kernel event timing (the last GPU work of the run, so a kernel trace's final
+dispatches are those steps).
 """
 import argparse
 import json
@@ -35,6 +37,7 @@ def parse():
     ap.add_argument("--ks-iters", type=int, default=50)
     ap.add_argument("--batch", type=int, default=64, help="ciphertexts in the batched measurements")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--jobs", type=int, default=64, help="mixed jobs at uneven levels (0 skips them)")
     return ap.parse_args()
 
 
@@ -76,6 +79,107 @@ def pipeline_bytes(g):
         level -= 1
     b += key(level) + 2 * ct(level)  # conjugation key, two outputs
     return float(b)
+
+
+def job_plans(g, specs, n1_of=None):
+    """conv plans (encoded at the top level, used at every job level) for each (op, C)
+    of the job mix; weights U(-1,1) scaled by 1/(f sqrt(C_in))"""
+    import synth
+    from paper_2312_04356_amd import layers as LY
+    gctx, plans = g.ctx, {}
+    for op, C in sorted({(o, c) for o, c, _ in specs}):
+        k = 8 * synth.JOB_OPS.index(op) + sorted(synth.JOB_CHANNELS).index(C)  # weights per (op, C)
+        w0 = synth.JOB_CHANNELS[C]
+        if op == "dw3x3":
+            taps, ci, co = LY.taps_depthwise(synth.uniform_real((C, 3, 3), 1004, 100 + k) / 3.0), C, C
+        else:
+            f = 1 if op == "1x1" else 3
+            K = synth.uniform_real((C, C, f, f), 1004, 100 + k) / (f * math.sqrt(C))
+            if op == "3x3s2":
+                taps, ci, co, w0 = LY.taps_stride2(K), 4 * C, C, w0 // 2
+            else:
+                taps, ci, co = LY.taps_same(K), C, C
+        n1 = 0 if n1_of is None else n1_of[(op, C)]
+        plans[(op, C)] = gctx.nj_conv_plan_create_taps(w0, ci, co, taps, fuse=1, n1=n1, level=gctx.L)
+    return plans
+
+
+def tune_n1(g, plans, level=15, reps=3):
+    """exhaustive timing of the baby-step count n1 (powers of two within a factor 4 of
+    sqrt(#diagonals)) for each plan's structure, on random-diagonal plans with timing keys"""
+    gctx, out = g.ctx, {}
+    gctx.nj_timing_keys(16)
+    try:
+        for key, plan in plans.items():
+            lvl, W, C, ell, bi, bo = plan.layout()
+            offs = plan.offsets(0)
+            r = math.sqrt(len(offs))
+            cands = [1 << k for k in range(12) if r / 4 <= (1 << k) <= 4 * r and (1 << k) <= len(offs)]
+            t = {}
+            for n1 in cands:
+                rp = gctx.nj_plan_create_random(level, ell, offs, n1, bi, bo, seed=n1)
+                t[n1] = gctx.nj_time_plan(rp, level, reps=reps)
+                del rp
+            out[key] = min(t, key=t.get)
+    finally:
+        gctx.nj_timing_keys(0)
+    return out
+
+
+def jobs_bench(g, n_jobs, steps=2):
+    """64 jobs at uneven levels 7..23, each conv (3x3, 3x3 stride 2, 1x1 or depthwise 3x3
+    on 16/64/256 channels per ciphertext) at its level -> level drop -> ModRaise ->
+    CoeffToSlot -> split.  Plain: one job after another with default plans.  Batched:
+    the grouped schedule replayed as one HIP graph, with n1 tuned by timing."""
+    import torch
+    import synth
+    gctx = g.ctx
+    specs = synth.job_mix(n_jobs, 1004)
+    default = job_plans(g, specs)
+    n1_of = tune_n1(g, default)
+    changed = {k: v for k, v in n1_of.items() if v != int(math.ceil(math.sqrt(len(default[k].offsets(0)))))}
+    tuned = dict(default)
+    if changed:
+        rebuilt = job_plans(g, [(o, c, 0) for (o, c) in changed], {k: n1_of[k] for k in changed})
+        tuned.update(rebuilt)
+    gs = set(g.cts_plan.galois())
+    for p in list(default.values()) + list(tuned.values()):
+        gs |= set(p.galois())
+    g.make_keys(sorted(gs))
+    lvl = gctx.L - g.w["cts_groups"]
+    xs = []
+    for op, C, level in specs:
+        x = gctx.empty_batch(1, level)
+        x.data.random_(0, 2 ** 40)
+        x.scale = g.scale
+        xs.append(x)
+
+    def jobs_with(plans):
+        return [(plans[(op, C)], x, gctx.empty_batch(1, lvl), gctx.empty_batch(1, lvl))
+                for (op, C, _), x in zip(specs, xs)]
+
+    jp, jt = jobs_with(default), jobs_with(tuned)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    plain = timed(lambda: gctx.nj_batch_run(g.cts_plan, jp, 0))
+    eager = timed(lambda: gctx.nj_batch_run(g.cts_plan, jp, 1))
+    graph = gctx.nj_batch_create(g.cts_plan, jt)
+    replay = timed(lambda: graph.launch())
+    del graph
+    return {"n_jobs": n_jobs, "levels": "7..23", "plain_ms": round(plain, 3),
+            "batched_default_plans_ms": round(eager, 3), "batched_graph_tuned_ms": round(replay, 3),
+            "speedup_vs_plain": round(plain / replay, 3),
+            "tuned_n1": {"%s/C%d" % k: v for k, v in sorted(n1_of.items())}}
 
 
 def cpu_baseline(name):
@@ -186,6 +290,9 @@ def main():
         ks_batch[str(level)] = round(it * nbk / (e0.elapsed_time(e1) / 1e3), 1)
         del xb, ob
 
+    jobs = jobs_bench(g, args.jobs) if args.jobs > 0 else None
+    torch.cuda.empty_cache()
+
     # batched fused conv + CoeffToSlot: 64 ciphertexts (distinct encryptions of the image)
     import synth
     from paper_2312_04356_amd import Ct
@@ -270,6 +377,7 @@ def main():
                     "ms_per_ct": round(batch_ms / args.batch, 4),
                     "speedup_vs_plain": round(ms / (batch_ms / args.batch), 3),
                     "hbm_frac_per_ct": round(pipeline_bytes(g) / (batch_ms / args.batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "jobs": jobs,
         "roofline": roofline,
         "pipeline": {"algorithmic_GB": round(alg / 1e9, 3),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

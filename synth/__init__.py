@@ -9,10 +9,11 @@ seed and a purpose number, so both sides receive identical inputs.
 Purposes (the second key word):
   0 secret key        1 key-switching uniforms   2 key-switching errors
   3 encryption uniforms  4 encryption errors    5 image / weight data
+  6 job mix
 """
 import numpy as np
 
-PURPOSE_SECRET, PURPOSE_KEY_A, PURPOSE_KEY_E, PURPOSE_ENC_A, PURPOSE_ENC_E, PURPOSE_DATA = range(6)
+PURPOSE_SECRET, PURPOSE_KEY_A, PURPOSE_KEY_E, PURPOSE_ENC_A, PURPOSE_ENC_E, PURPOSE_DATA, PURPOSE_JOBS = range(7)
 
 
 def _gen(seed, purpose, sub=0):
@@ -87,3 +88,18 @@ def enc_randomness(primes, n, seed, sub=0):
 
 
 RELIN_KEY_ID = 0  # Galois elements are odd, so 0 never collides
+
+
+JOB_OPS = ("3x3", "3x3s2", "1x1", "dw3x3")
+JOB_CHANNELS = {16: 56, 64: 28, 256: 14}  # channels per ciphertext -> image width (W = 64, 32, 16)
+
+
+def job_mix(n, seed=1004, lo=7, hi=23):
+    """n jobs (op, C, level): op uniform over JOB_OPS, C uniform over JOB_CHANNELS,
+    level uniform on lo..hi"""
+    g = _gen(seed, PURPOSE_JOBS)
+    ops = g.integers(0, len(JOB_OPS), n)
+    cs = g.integers(0, len(JOB_CHANNELS), n)
+    lv = g.integers(lo, hi + 1, n)
+    keys = sorted(JOB_CHANNELS)
+    return [(JOB_OPS[o], keys[c], int(l)) for o, c, l in zip(ops, cs, lv)]

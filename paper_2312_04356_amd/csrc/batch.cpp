@@ -47,6 +47,115 @@ std::vector<Grp> level_groups(const std::vector<MixJob> &jobs)
     return g;
 }
 
+// limb offset of an arena pointer from the arena base, in units of N words
+int limb_off(const nj_ctx *c, const uint64_t *base, const uint64_t *p) { return (int)((p - base) / c->N); }
+
+// NTT launches over the limbs of every level group at once (tables flushed at
+// NJ_MAX_LIMBS limbs); each group's limbs are given by `each(g, push)`.  The inverse
+// transforms read their limbs from separate source offsets, the forward ones work in
+// place.
+template <class F>
+hipError_t ntt_all(const nj_ctx *c, uint64_t *base, bool inverse, hipStream_t s, F each, int n_groups)
+{
+    const uint64_t *src = inverse ? base : nullptr;
+    LimbTab lt;
+    lt.n = 0;
+    hipError_t e = hipSuccess;
+    auto push = [&](int pidx, int off, int soff) {
+        lt.pidx[lt.n] = pidx, lt.off[lt.n] = off, lt.soff[lt.n] = soff;
+        if (++lt.n == NJ_MAX_LIMBS) {
+            if (e == hipSuccess) e = launch_ntt(c, base, lt, inverse, s, src);
+            lt.n = 0;
+        }
+    };
+    for (int g = 0; g < n_groups; g++) each(g, push);
+    if (e == hipSuccess && lt.n) e = launch_ntt(c, base, lt, inverse, s, src);
+    return e;
+}
+
+// ModUp of every group's K polynomials at M.d (packed [K][l+1]) into M.ext; the iNTT
+// and NTT launches span all groups, the basis conversions run per level.
+nj_status modup_mixed(nj_ctx *c, std::vector<Grp> &gr, uint64_t *base, hipStream_t s)
+{
+    const size_t N = c->N;
+    NJ_HIP(ntt_all(c, base, true, s, [&](int g, auto push) {
+        const Grp &q = gr[g];
+        for (int z = 0; z < q.K; z++)
+            for (int i = 0; i <= q.l; i++)
+                push(i, limb_off(c, base, q.M.coef) + z * (q.l + 1) + i, limb_off(c, base, q.M.d) + z * (q.l + 1) + i);
+    }, (int)gr.size()));
+    for (const Grp &q : gr) {
+        const int nd = n_digits(c, q.l), ne = q.l + 1 + c->alpha;
+        for (int j0 = 0; j0 < nd; j0 += 4) {
+            BconvShared sh;
+            sh.nd = std::min(4, nd - j0);
+            for (int jj = 0; jj < sh.nd; jj++) {
+                const int j = j0 + jj;
+                const BconvTab &bt = c->modup[q.l][j];
+                sh.m[jj] = bt.m, sh.n_out[jj] = bt.n_out, sh.in_off0[jj] = j * c->alpha;
+                sh.hat_inv[jj] = bt.hat_inv, sh.hat[jj] = bt.hat;
+                for (int a = 0; a < bt.m; a++) sh.in_pidx[jj][a] = bt.in_pidx[a];
+                for (int o = 0; o < bt.n_out; o++)
+                    sh.out_pidx[jj][o] = bt.out_pidx[o], sh.out_off[jj][o] = j * ne + bt.out_limb[o];
+            }
+            BconvPtrs jp;
+            for (int z = 0; z < q.K; z++)
+                jp.in[z] = q.M.coef + (size_t)z * (q.l + 1) * N, jp.out[z] = q.M.ext + (size_t)z * nd * ne * N;
+            NJ_HIP(launch_bconv_multi(c, sh, jp, q.K, s));
+        }
+    }
+    NJ_HIP(ntt_all(c, base, false, s, [&](int g, auto push) {
+        const Grp &q = gr[g];
+        const int nd = n_digits(c, q.l), ne = q.l + 1 + c->alpha;
+        for (int z = 0; z < q.K; z++)
+            for (int j = 0; j < nd; j++) {
+                const BconvTab &bt = c->modup[q.l][j];
+                for (int o = 0; o < bt.n_out; o++)
+                    push(bt.out_pidx[o], limb_off(c, base, q.M.ext) + (z * nd + j) * ne + bt.out_limb[o], 0);
+            }
+    }, (int)gr.size()));
+    return NJ_OK;
+}
+
+// ModDown of every group's inner products (M.u) and the combine into mj[g]'s outputs
+// (accumulating into them when acc); iNTT / NTT launches span all groups.
+nj_status ks_down_mixed(nj_ctx *c, std::vector<Grp> &gr, const std::vector<MdJobs> &mj, bool acc, uint64_t *base,
+                        hipStream_t s)
+{
+    const size_t N = c->N;
+    const int al = c->alpha;
+    NJ_HIP(ntt_all(c, base, true, s, [&](int g, auto push) {
+        const Grp &q = gr[g];
+        const int ne = q.l + 1 + al;
+        for (int z = 0; z < q.K; z++)
+            for (int p = 0; p < 2; p++)
+                for (int a = 0; a < al; a++)
+                    push(c->n_q + a, limb_off(c, base, q.M.pc) + (2 * z + p) * al + a,
+                         limb_off(c, base, q.M.u) + (2 * z + p) * ne + q.l + 1 + a);
+    }, (int)gr.size()));
+    for (const Grp &q : gr) {
+        const BconvTab &bt = c->moddown[q.l];
+        BconvShared sh;
+        sh.nd = 1;
+        sh.m[0] = bt.m, sh.n_out[0] = bt.n_out, sh.in_off0[0] = 0, sh.hat_inv[0] = bt.hat_inv, sh.hat[0] = bt.hat;
+        for (int a = 0; a < bt.m; a++) sh.in_pidx[0][a] = bt.in_pidx[a];
+        for (int o = 0; o < bt.n_out; o++) sh.out_pidx[0][o] = bt.out_pidx[o], sh.out_off[0][o] = o;
+        BconvPtrs jp;
+        for (int h = 0; h < 2 * q.K; h++)
+            jp.in[h] = q.M.pc + (size_t)h * al * N, jp.out[h] = q.M.conv + (size_t)h * (q.l + 1) * N;
+        NJ_HIP(launch_bconv_multi(c, sh, jp, 2 * q.K, s));
+    }
+    NJ_HIP(ntt_all(c, base, false, s, [&](int g, auto push) {
+        const Grp &q = gr[g];
+        for (int h = 0; h < 2 * q.K; h++)
+            for (int i = 0; i <= q.l; i++) push(i, limb_off(c, base, q.M.conv) + h * (q.l + 1) + i, 0);
+    }, (int)gr.size()));
+    for (size_t g = 0; g < gr.size(); g++)
+        NJ_HIP(launch_moddown_multi(c, gr[g].l, mj[g], gr[g].K, 0, gr[g].M.u, gr[g].M.conv,
+                                    acc ? mj[g].out[0] : nullptr, s));
+    return NJ_OK;
+}
+
 size_t mixed_words(const nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJob> &jobs)
 {
     const size_t N = c->N, nb = lt.babies.size(), ng = lt.giants.size();
@@ -71,6 +180,7 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
         if (g != 0 && !key_of(c, galois_of_rot(c, (long long)g * lt.n1 * lt.u)))
             return fail(NJ_ENOKEY, "missing giant-step key");
     std::vector<Grp> gr = level_groups(jobs);
+    uint64_t *base = A.p;  // every buffer below is N-word aligned from here
     std::vector<int> grp_of(n), idx_in(n);
     for (int q = 0; q < (int)gr.size(); q++) {
         if (!multi_bufs(c, gr[q].l, gr[q].K, A, gr[q].M)) return fail(NJ_ENOMEM, "scratch too small");
@@ -97,8 +207,8 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
             const size_t plen = N * (g.l + 1);
             for (int i = 0; i < g.K; i++)
                 NJ_HIP(hipMemcpyAsync(g.M.d + i * plen, jobs[g.z0 + i].in + plen, plen * 8, hipMemcpyDeviceToDevice, s));
-            if ((st = modup_multi(c, g.l, g.K, g.M.d, g.M, s))) return st;
         }
+        if ((st = modup_mixed(c, gr, base, s))) return st;
         for (int b = 0; b < nb; b++) {
             if (lt.babies[b] == 0) continue;
             const uint32_t ge = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
@@ -108,12 +218,11 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
                 kj.g[z] = ge, kj.lv[z] = jobs[z].level;
             }
             NJ_HIP(launch_key_ip_mixed(c, kj, n, key_of(c, ge), s));
-            for (Grp &g : gr) {
-                MdJobs mj;
-                for (int i = 0; i < g.K; i++)
-                    mj.add[i] = jobs[g.z0 + i].in, mj.g_add[i] = ge, mj.out[i] = baby[g.z0 + i][b];
-                if ((st = ks_down(c, g.l, g.K, mj, 0, nullptr, g.M, s))) return st;
-            }
+            std::vector<MdJobs> mj(gr.size());
+            for (size_t q = 0; q < gr.size(); q++)
+                for (int i = 0; i < gr[q].K; i++)
+                    mj[q].add[i] = jobs[gr[q].z0 + i].in, mj[q].g_add[i] = ge, mj[q].out[i] = baby[gr[q].z0 + i][b];
+            if ((st = ks_down_mixed(c, gr, mj, false, base, s))) return st;
         }
     }
     // every giant step's inner sum, one ciphertext at a time
@@ -149,8 +258,8 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
             for (int i = 0; i < q.K; i++)
                 aj.in[i] = inner[q.z0 + i] + (size_t)g * clen + plen, aj.out[i] = q.M.d + i * plen, aj.g[i] = ge;
             NJ_HIP(launch_automorph_multi(c, aj, q.K, q.l + 1, s));
-            if ((st = modup_multi(c, q.l, q.K, q.M.d, q.M, s))) return st;
         }
+        if ((st = modup_mixed(c, gr, base, s))) return st;
         KeyJobsX kj;
         for (int z = 0; z < n; z++) {
             const Grp &q = gr[grp_of[z]];
@@ -158,13 +267,14 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
             kj.g[z] = 1, kj.lv[z] = jobs[z].level;
         }
         NJ_HIP(launch_key_ip_mixed(c, kj, n, key_of(c, ge), s));
-        for (Grp &q : gr) {
-            const size_t clen = 2 * N * (q.l + 1);
-            MdJobs mj;
-            for (int i = 0; i < q.K; i++)
-                mj.add[i] = inner[q.z0 + i] + (size_t)g * clen, mj.g_add[i] = ge, mj.out[i] = jobs[q.z0 + i].out;
-            if ((st = ks_down(c, q.l, q.K, mj, 0, have ? jobs[q.z0].out : nullptr, q.M, s))) return st;
+        std::vector<MdJobs> mj(gr.size());
+        for (size_t q = 0; q < gr.size(); q++) {
+            const size_t clen = 2 * N * (gr[q].l + 1);
+            for (int i = 0; i < gr[q].K; i++)
+                mj[q].add[i] = inner[gr[q].z0 + i] + (size_t)g * clen, mj[q].g_add[i] = ge,
+                mj[q].out[i] = jobs[gr[q].z0 + i].out;
         }
+        if ((st = ks_down_mixed(c, gr, mj, have, base, s))) return st;
         have = true;
     }
     return NJ_OK;

@@ -277,6 +277,39 @@ nj_status nj_batch_create(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_j
 nj_status nj_batch_launch(nj_batch *batch, void *stream);
 void nj_batch_destroy(nj_batch *batch);
 
+/* ------------------------------------------------- bootstrapping after CoeffToSlot */
+
+/* HMult (Sec. 2.1): tensor product at l = min(levels), relinearisation with the key of
+ * Galois element 0 (s^2 -> s), rescale -> level l-1, scale s_a s_b / q_l.  out may not
+ * alias the inputs. */
+nj_status nj_hmult(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
+/* c * in at a lower `level`: the first level+2 limbs times the integer
+ * round(c * scale * q_{level+1} / in->scale), rescale; out->scale = scale. */
+nj_status nj_mul_const(nj_ctx *ctx, const nj_ct *in, double c, int level, double scale, nj_ct *out, void *stream);
+/* Adds c to every slot (round(c * ct->scale) to the constant coefficient), in place. */
+nj_status nj_add_const(nj_ctx *ctx, nj_ct *ct, double c, void *stream);
+/* Chebyshev interpolant (first-kind nodes) of cos(2 pi (K x - 1/4) / 2^r) on [-1, 1]:
+ * coeffs [degree+1], host. */
+nj_status nj_cheb_interpolate(int degree, double K, int r, double *coeffs);
+/* ModEval (Sec. 2.4; Algorithm 1): for a CoeffToSlot output whose slots hold
+ * t = m + (q_0 / scale) I, returns m ~ (P / 2 pi) sin(2 pi t / P), P = q_0 / scale:
+ * x = t / (K P) (the input read at scale K q_0), one integer multiply bringing the
+ * scale near 2^48, the degree-63 Chebyshev series of cos(2 pi (K x - 1/4) / 8)
+ * (coeffs [64], or null for the library's interpolant) by baby steps T_1..T_7 and giant
+ * steps T_8/T_16/T_32 with every constant encoded at its term's exact scale, then r = 3
+ * double angles.  Uses 11 levels (input level >= 12); needs the relinearisation key.
+ * |I| must stay below K. */
+nj_status nj_eval_mod(nj_ctx *ctx, const nj_ct *in, int K, int r, const double *coeffs, int n_coeffs, nj_ct *out,
+                      void *stream);
+/* Re + i Im (i = X^{N/2} on the slots); same level. */
+nj_status nj_combine(nj_ctx *ctx, const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream);
+/* StoC1 = S_{l <- 1} = S_{l/2} ... S_1 (Algorithm 1, the StoC stages left after fusing
+ * StoC2 into the next conv) in `groups` stage groups at levels level, level-1, ...;
+ * diagonals encoded at each group's q.  nj_stoc1 applies it (input at `level`), output
+ * at level - groups with the input's scale. */
+nj_status nj_stoc1_plan_create(nj_ctx *ctx, int ell, int groups, int level, nj_plan **out);
+nj_status nj_stoc1(nj_ctx *ctx, const nj_plan *plan, const nj_ct *in, nj_ct *out, void *stream);
+
 /* ------------------------------------------------------------ plan selection */
 
 /* Timing mode for latency measurement: after nj_timing_keys(ctx, pool) with pool > 0,

@@ -82,6 +82,14 @@ _SIGS = {
     "nj_batch_launch": (i32, [vp, vp]),
     "nj_batch_destroy": (None, [vp]),
     "nj_timing_keys": (i32, [vp, i32]),
+    "nj_hmult": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_mul_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, i32, dbl, ctypes.POINTER(NjCt), vp]),
+    "nj_add_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, vp]),
+    "nj_cheb_interpolate": (i32, [i32, dbl, i32, vp]),
+    "nj_eval_mod": (i32, [vp, ctypes.POINTER(NjCt), i32, i32, vp, i32, ctypes.POINTER(NjCt), vp]),
+    "nj_combine": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_stoc1_plan_create": (i32, [vp, i32, i32, i32, ctypes.POINTER(vp)]),
+    "nj_stoc1": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_plan_create_random": (i32, [vp, i32, i32, vp, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]),
     "nj_time_plan": (i32, [vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
     "nj_plan_features": (i32, [vp, i32, i32, vp]),
@@ -226,6 +234,12 @@ class Plan:
         if getattr(self, "ptr", None):
             _lib.nj_plan_destroy(self.ptr)
             self.ptr = None
+
+
+def nj_cheb_interpolate(degree, K, r):
+    out = np.zeros(degree + 1, dtype=np.float64)
+    _check(_lib.nj_cheb_interpolate(int(degree), float(K), int(r), _np_ptr(out)), "nj_cheb_interpolate")
+    return out
 
 
 MLP_FEATURES, MLP_HIDDEN = 7, 64
@@ -520,6 +534,48 @@ class Ctx:
                "nj_batch_create")
         self._sync_jobs(jobs, arr)
         return Batch(h, (cts_plan, jobs))
+
+    # -- bootstrapping after CoeffToSlot
+    def nj_hmult(self, a, b, out, stream=None):
+        ca, cb, co = a.c(), b.c(), out.c()
+        _check(_lib.nj_hmult(self.ptr, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream(stream)),
+               "nj_hmult")
+        return out.sync_from(co)
+
+    def nj_mul_const(self, ct, v, level, scale, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_mul_const(self.ptr, ctypes.byref(ci), float(v), int(level), float(scale), ctypes.byref(co),
+                                 _stream(stream)), "nj_mul_const")
+        return out.sync_from(co)
+
+    def nj_add_const(self, ct, v, stream=None):
+        ci = ct.c()
+        _check(_lib.nj_add_const(self.ptr, ctypes.byref(ci), float(v), _stream(stream)), "nj_add_const")
+        return ct
+
+    def nj_eval_mod(self, ct, K, r, coeffs, out, stream=None):
+        ci, co = ct.c(), out.c()
+        cf = None if coeffs is None else np.ascontiguousarray(coeffs, dtype=np.float64)
+        _check(_lib.nj_eval_mod(self.ptr, ctypes.byref(ci), int(K), int(r), None if cf is None else _np_ptr(cf),
+                                0 if cf is None else len(cf), ctypes.byref(co), _stream(stream)), "nj_eval_mod")
+        return out.sync_from(co)
+
+    def nj_combine(self, re, im, out, stream=None):
+        cr, cm, co = re.c(), im.c(), out.c()
+        _check(_lib.nj_combine(self.ptr, ctypes.byref(cr), ctypes.byref(cm), ctypes.byref(co), _stream(stream)),
+               "nj_combine")
+        return out.sync_from(co)
+
+    def nj_stoc1_plan_create(self, ell, groups, level):
+        h = vp()
+        _check(_lib.nj_stoc1_plan_create(self.ptr, int(ell), int(groups), int(level), ctypes.byref(h)),
+               "nj_stoc1_plan_create")
+        return Plan(h)
+
+    def nj_stoc1(self, plan, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_stoc1(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)), "nj_stoc1")
+        return out.sync_from(co)
 
     def nj_timing_keys(self, pool):
         _check(_lib.nj_timing_keys(self.ptr, int(pool)), "nj_timing_keys")

@@ -24,9 +24,6 @@ size_t ks_words(const nj_ctx *c, int l)
     return N * (3 * (l + 1) + beta * ne + 2 * ne + 2 * c->alpha + 2 * (l + 1));
 }
 
-struct KsBufs {
-    uint64_t *coef, *dtmp, *c0copy, *ext, *u, *pc, *conv;
-};
 
 bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B)
 {

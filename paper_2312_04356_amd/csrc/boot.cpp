@@ -1,0 +1,416 @@
+// Bootstrapping after CoeffToSlot (Sec. 2.4, Algorithm 1): HMult with relinearisation,
+// integer-constant multiplication, ModEval by a scale-exact Chebyshev evaluation and
+// double angles, Re + i Im, and StoC1 = S_{l <- 1}.
+//
+// Scale rules (every integer constant is a fixed function of float64 scales):
+//   HMult: scale s_a s_b / q_l.  const_mult(ct, c, lam, tau): level lam + 1, times the
+//   integer round(c tau q_{lam+1} / s), rescale -> (lam, tau).  add_const: + round(c s).
+// ModEval: x = t / (K P) is the input read at scale K q_0; one integer multiply and
+// rescale bring the scale near 2^48; Chebyshev series of degree 63 by baby steps
+// T_1..T_7 and giant steps T_8, T_16, T_32 (T_2j = 2 T_j^2 - 1, T_{a+b} = 2 T_a T_b -
+// T_{a-b}, Chebyshev division p = q T_G + r); then D(y) = 2 y^2 - 1 r times; the result
+// read at scale s_y 2 pi s_0 / q_0 is the message.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "exec.h"
+
+using namespace nj;
+using namespace nj::ex;
+
+namespace {
+
+constexpr int kChebDegree = 63;
+
+struct Cx {
+    uint64_t *d = nullptr;  // [2][l+1][N], evaluation form
+    int l = 0;
+    double s = 0.0;
+};
+
+// Ciphertext buffers of one evaluation: fixed-size slots (a level-lmax ciphertext
+// each) from an arena with a free list; the key-switch scratch is a separate arena.
+class Ev {
+  public:
+    Ev(nj_ctx *c, int lmax, Arena cts, Arena ks, hipStream_t s) : c(c), N(c->N), lmax(lmax), cts(cts), ks(ks), s(s)
+    {
+        relin = key_of(c, 0);
+        if (!relin) err = fail(NJ_ENOKEY, "no relinearisation key (Galois element 0)");
+    }
+    nj_ctx *c;
+    size_t N;
+    int lmax;
+    Arena cts, ks;
+    hipStream_t s;
+    nj_status err = NJ_OK;
+    const uint64_t *relin = nullptr;
+    std::vector<uint64_t *> free_;
+
+    static size_t slots_needed() { return 48; }
+    size_t slot_words() const { return 2 * N * (lmax + 1); }
+    bool ok() const { return err == NJ_OK; }
+    void check(hipError_t e)
+    {
+        if (e != hipSuccess && err == NJ_OK) err = fail(NJ_EDEVICE, hipGetErrorString(e));
+    }
+    void check(nj_status st)
+    {
+        if (st != NJ_OK && err == NJ_OK) err = st;
+    }
+
+    Cx alloc(int l, double sc)
+    {
+        Cx x;
+        x.l = l, x.s = sc;
+        if (!free_.empty()) {
+            x.d = free_.back();
+            free_.pop_back();
+        } else if (!(x.d = cts.take(slot_words()))) {
+            if (err == NJ_OK) err = fail(NJ_ENOMEM, "ModEval: ciphertext pool exhausted");
+        }
+        return x;
+    }
+    void release(Cx &x)
+    {
+        if (x.d) free_.push_back(x.d);
+        x.d = nullptr;
+    }
+    LimbConsts residues(long long k, int n_limbs) const
+    {
+        LimbConsts kc;
+        for (int i = 0; i < n_limbs; i++) {
+            const long long q = (long long)c->primes[i];
+            long long r = k % q;
+            if (r < 0) r += q;
+            kc.v[i] = (double)r;
+        }
+        return kc;
+    }
+
+    Cx add(const Cx &a, const Cx &b, int op)  // op 0: a + b, 1: a - b (same level)
+    {
+        Cx o = alloc(a.l, a.s);
+        if (ok()) check(launch_elementwise(c, op, a.d, b.d, o.d, ct_limbs(a.l), s));
+        return o;
+    }
+    void add_const(Cx &x, double v)
+    {
+        const long long k = (long long)std::nearbyint(v * x.s);
+        if (ok()) check(launch_add_int(c, x.d, x.l + 1, residues(k, x.l + 1), s));
+    }
+    Cx zero(int l, double sc)
+    {
+        Cx o = alloc(l, sc);
+        if (ok()) check(launch_zero(c, o.d, 2 * N * (l + 1), s));
+        return o;
+    }
+    // tensor product, relinearisation, rescale
+    Cx hmult(const Cx &a, const Cx &b)
+    {
+        const int l = std::min(a.l, b.l);
+        Cx t = alloc(l, 0.0), d2 = alloc(l, 0.0);
+        Cx o = alloc(l - 1, a.s * b.s / (double)c->primes[l]);
+        if (!ok()) return o;
+        check(launch_tensor(c, a.d, N * (a.l + 1), b.d, N * (b.l + 1), t.d, d2.d, l, s));
+        Arena A = ks;
+        KsBufs B;
+        if (!ks_bufs(c, l, A, B)) {
+            check(fail(NJ_ENOMEM, "ModEval: key-switch scratch"));
+            return o;
+        }
+        check(modup_ext(c, l, d2.d, B, s));
+        check(ks_from_ext(c, l, d2.d, relin, 1, nullptr, 0, t.d, t.d, B, s));
+        check(rescale(c, l, t.d, o.d, A, s));
+        release(t), release(d2);
+        return o;
+    }
+    // c * x at level lam with recorded scale tau; d == nullptr when the constant is 0
+    Cx const_mult(const Cx &x, double v, int lam, double tau)
+    {
+        const long long k = (long long)std::nearbyint(v * tau * (double)c->primes[lam + 1] / x.s);
+        Cx o;
+        if (k == 0 || !ok()) return o;
+        Cx t = alloc(lam + 1, 0.0);
+        o = alloc(lam, tau);
+        if (!ok()) return o;
+        check(launch_mul_int(c, x.d, N * (x.l + 1), t.d, lam + 2, residues(k, lam + 2), s));
+        check(rescale(c, lam + 1, t.d, o.d, ks, s));
+        release(t);
+        return o;
+    }
+    Cx sq_minus1(const Cx &a)  // 2 a^2 - 1
+    {
+        Cx p = hmult(a, a);
+        Cx o = add(p, p, 0);
+        release(p);
+        add_const(o, -1.0);
+        return o;
+    }
+    Cx prod_minus(const Cx &a, const Cx &b, const Cx &cc)  // 2 a b - c
+    {
+        Cx p = hmult(a, b);
+        Cx c2 = const_mult(cc, 1.0, p.l, p.s);
+        Cx p2 = add(p, p, 0);
+        Cx o = add(p2, c2, 1);
+        release(p), release(c2), release(p2);
+        return o;
+    }
+
+    Cx T[33];
+    void basis(const Cx &x)
+    {
+        T[1] = x;
+        T[2] = sq_minus1(T[1]);
+        T[3] = prod_minus(T[1], T[2], T[1]);
+        T[4] = sq_minus1(T[2]);
+        T[5] = prod_minus(T[2], T[3], T[1]);
+        T[6] = sq_minus1(T[3]);
+        T[7] = prod_minus(T[3], T[4], T[1]);
+        T[8] = sq_minus1(T[4]);
+        T[16] = sq_minus1(T[8]);
+        T[32] = sq_minus1(T[16]);
+    }
+
+    Cx eval(const std::vector<double> &cf, int lam, double tau)
+    {
+        const int d = (int)cf.size() - 1;
+        if (d < 8) {
+            Cx acc;
+            for (int j = 1; j <= d; j++) {
+                if (cf[j] == 0.0) continue;
+                Cx t = const_mult(T[j], cf[j], lam, tau);
+                if (!t.d) continue;
+                if (!acc.d) {
+                    acc = t;
+                } else {
+                    Cx sum = add(acc, t, 0);
+                    release(acc), release(t);
+                    acc = sum;
+                }
+            }
+            if (!acc.d) acc = zero(lam, tau);
+            add_const(acc, cf[0]);
+            return acc;
+        }
+        const int G = d >= 32 ? 32 : (d >= 16 ? 16 : 8);
+        std::vector<double> q(d - G + 1, 0.0), r(cf.begin(), cf.begin() + G);
+        q[0] = cf[G];
+        for (int j = 1; j <= d - G; j++) {
+            q[j] = 2.0 * cf[G + j];
+            r[G - j] -= cf[G + j];
+        }
+        const double tau_q = tau * (double)c->primes[lam + 1] / T[G].s;
+        Cx Q = eval(q, lam + 1, tau_q);
+        Cx prod = hmult(Q, T[G]);
+        release(Q);
+        Cx rr = eval(r, lam, tau);
+        Cx o = add(prod, rr, 0);
+        o.s = tau;
+        release(prod), release(rr);
+        return o;
+    }
+};
+
+size_t eval_mod_words(const nj_ctx *c, int l0)
+{
+    return Ev::slots_needed() * 2 * (size_t)c->N * (l0 + 1) + ks_words(c, l0) + (size_t)c->N * (l0 + 3);
+}
+
+// ModEval of ct (level l0, scale s0): out at level l0 - 11
+nj_status eval_mod(nj_ctx *c, const uint64_t *in, int l0, double s0, double K, const double *cf, uint64_t *out,
+                   double *out_scale, Arena A, hipStream_t s)
+{
+    const size_t N = c->N;
+    uint64_t *ctsbuf = A.take(Ev::slots_needed() * 2 * N * (l0 + 1));
+    if (!ctsbuf) return fail(NJ_ENOMEM, "scratch");
+    Ev ev(c, l0, Arena{ctsbuf, Ev::slots_needed() * 2 * N * (l0 + 1)}, A, s);
+    if (!ev.ok()) return ev.err;
+    const double q0 = (double)c->primes[0];
+    const double sx = K * q0;  // the same integers read as x = t / (K P)
+    const long long k = (long long)std::nearbyint(std::ldexp(1.0, 48) * (double)c->primes[l0] / sx);
+    Cx t = ev.alloc(l0, 0.0), x = ev.alloc(l0 - 1, sx * (double)k / (double)c->primes[l0]);
+    if (!ev.ok()) return ev.err;
+    ev.check(launch_mul_int(c, in, N * (l0 + 1), t.d, l0 + 1, ev.residues(k, l0 + 1), s));
+    ev.check(rescale(c, l0, t.d, x.d, ev.ks, s));
+    ev.release(t);
+    ev.basis(x);
+    const int lam = x.l - 7;
+    Cx g = ev.eval(std::vector<double>(cf, cf + kChebDegree + 1), lam, (double)c->primes[lam]);
+    for (int i = 0; i < 3; i++) {
+        Cx h = ev.sq_minus1(g);
+        ev.release(g);
+        g = h;
+    }
+    if (!ev.ok()) return ev.err;
+    NJ_HIP(hipMemcpyAsync(out, g.d, 2 * N * (g.l + 1) * 8, hipMemcpyDeviceToDevice, s));
+    *out_scale = g.s * (2.0 * M_PI) * s0 / q0;
+    return NJ_OK;
+}
+
+constexpr int kEvalModLevels = 11;
+
+}  // namespace
+
+extern "C" {
+
+nj_status nj_hmult(nj_ctx *c, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, a, "nj_hmult");
+    if (st || (st = check_ct(c, b, "nj_hmult"))) return st;
+    const int l = std::min(a->level, b->level);
+    if (l < 1) return fail(NJ_ELEVEL, "nj_hmult: needs level >= 1");
+    if (!out || !out->data) return fail(NJ_EINVAL, "nj_hmult: null output");
+    const size_t N = c->N;
+    bool ok;
+    Arena A = arena_for(c, 4 * 2 * N * (l + 1) + ks_words(c, l) + N * (l + 3), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *buf = A.take(4 * 2 * N * (l + 1));
+    Ev ev(c, l, Arena{buf, 4 * 2 * N * (l + 1)}, A, S(stream));
+    if (!ev.ok()) return ev.err;
+    Cx x{a->data, a->level, a->scale}, y{b->data, b->level, b->scale};
+    Cx o = ev.hmult(x, y);
+    if (!ev.ok()) return ev.err;
+    NJ_HIP(hipMemcpyAsync(out->data, o.d, 2 * N * l * 8, hipMemcpyDeviceToDevice, S(stream)));
+    out->level = l - 1, out->is_ntt = 1, out->scale = o.s;
+    return NJ_OK;
+}
+
+nj_status nj_mul_const(nj_ctx *c, const nj_ct *in, double v, int level, double scale, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_mul_const");
+    if (st) return st;
+    if (level < 0 || level >= in->level) return fail(NJ_ELEVEL, "nj_mul_const: target level must be below the input's");
+    if (!out || !out->data || !(scale > 0.0)) return fail(NJ_EINVAL, "nj_mul_const: bad output or scale");
+    const size_t N = c->N;
+    const int l = in->level;
+    bool ok;
+    Arena A = arena_for(c, 4 * 2 * N * (l + 1) + N * (l + 3), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *buf = A.take(4 * 2 * N * (l + 1));
+    Ev ev(c, l, Arena{buf, 4 * 2 * N * (l + 1)}, A, S(stream));
+    ev.err = NJ_OK;  // no key needed
+    Cx x{in->data, in->level, in->scale};
+    Cx o = ev.const_mult(x, v, level, scale);
+    if (!ev.ok()) return ev.err;
+    if (!o.d) {
+        Cx z = ev.zero(level, scale);
+        if (!ev.ok()) return ev.err;
+        o = z;
+    }
+    NJ_HIP(hipMemcpyAsync(out->data, o.d, 2 * N * (level + 1) * 8, hipMemcpyDeviceToDevice, S(stream)));
+    out->level = level, out->is_ntt = 1, out->scale = scale;
+    return NJ_OK;
+}
+
+nj_status nj_add_const(nj_ctx *c, nj_ct *ct, double v, void *stream)
+{
+    nj_status st = check_ct(c, ct, "nj_add_const");
+    if (st) return st;
+    const long long k = (long long)std::nearbyint(v * ct->scale);
+    LimbConsts kc;
+    for (int i = 0; i <= ct->level; i++) {
+        const long long q = (long long)c->primes[i];
+        long long r = k % q;
+        kc.v[i] = (double)(r < 0 ? r + q : r);
+    }
+    NJ_HIP(launch_add_int(c, ct->data, ct->level + 1, kc, S(stream)));
+    return NJ_OK;
+}
+
+nj_status nj_cheb_interpolate(int degree, double K, int r, double *coeffs)
+{
+    if (degree < 1 || degree > 1023 || !coeffs || r < 0 || r > 16) return fail(NJ_EINVAL, "nj_cheb_interpolate: bad arguments");
+    cheb_interpolate_cos(degree, K, r, coeffs);
+    return NJ_OK;
+}
+
+nj_status nj_eval_mod(nj_ctx *c, const nj_ct *in, int K, int r, const double *coeffs, int n_coeffs, nj_ct *out,
+                      void *stream)
+{
+    nj_status st = check_ct(c, in, "nj_eval_mod");
+    if (st) return st;
+    if (K < 1 || r != 3 || (coeffs && n_coeffs != kChebDegree + 1))
+        return fail(NJ_EUNSUPPORTED, "nj_eval_mod: supports r = 3 double angles and 64 Chebyshev coefficients");
+    if (in->level < kEvalModLevels + 1) return fail(NJ_ELEVEL, "nj_eval_mod: needs input level >= 12");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_eval_mod: bad output");
+    std::vector<double> cf(kChebDegree + 1);
+    if (coeffs) std::copy(coeffs, coeffs + kChebDegree + 1, cf.begin());
+    else cheb_interpolate_cos(kChebDegree, (double)K, r, cf.data());
+    bool ok;
+    Arena A = arena_for(c, eval_mod_words(c, in->level), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    double sc = 0.0;
+    if ((st = eval_mod(c, in->data, in->level, in->scale, (double)K, cf.data(), out->data, &sc, A, S(stream)))) return st;
+    out->level = in->level - kEvalModLevels, out->is_ntt = 1, out->scale = sc;
+    return NJ_OK;
+}
+
+nj_status nj_combine(nj_ctx *c, const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream)
+{
+    nj_status st = check_ct(c, re, "nj_combine");
+    if (st || (st = check_ct(c, im, "nj_combine"))) return st;
+    if (re->level != im->level) return fail(NJ_ELEVEL, "nj_combine: Re and Im must share a level");
+    if (!out || !out->data || out->data == re->data || out->data == im->data) return fail(NJ_EINVAL, "nj_combine: bad output");
+    // the monomial kernel multiplies by -X^{N/2}, so Re - (-X^{N/2} Im) = Re + i Im
+    NJ_HIP(launch_monomial_half(c, im->level, im->data, out->data, S(stream)));
+    NJ_HIP(launch_elementwise(c, 1, re->data, out->data, out->data, ct_limbs(re->level), S(stream)));
+    out->level = re->level, out->is_ntt = 1, out->scale = re->scale;
+    return NJ_OK;
+}
+
+nj_status nj_stoc1_plan_create(nj_ctx *c, int ell, int groups, int level, nj_plan **out)
+{
+    if (!c || !out) return fail(NJ_EINVAL, "nj_stoc1_plan_create: null argument");
+    if (level - groups + 1 < 1 || level > c->L) return fail(NJ_ELEVEL, "nj_stoc1_plan_create: levels out of range");
+    nj_plan *p = new nj_plan();
+    p->kind = 2;
+    p->N = c->N;
+    p->ell = ell;
+    std::vector<std::vector<std::vector<double>>> re, im;
+    nj_status st = build_stoc1_diagonals(c->N, ell, groups, p->lts, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    for (int g = 0; g < groups; g++) {
+        nj_lt_t &lt = p->lts[g];
+        lt.level = level - g;
+        st = upload_plan_diagonals(c, lt, re[g], im[g], (double)c->primes[lt.level]);
+        if (st) {
+            nj_plan_destroy(p);
+            return st;
+        }
+    }
+    *out = p;
+    return NJ_OK;
+}
+
+nj_status nj_stoc1(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *out, void *stream)
+{
+    if (!c || !p || p->kind != 2 || p->lts.empty()) return fail(NJ_EINVAL, "nj_stoc1: not a StoC1 plan");
+    nj_status st = check_ct(c, in, "nj_stoc1");
+    if (st) return st;
+    if (in->level != p->lts[0].level) return fail(NJ_ELEVEL, "nj_stoc1: input must be at the plan's first level");
+    if (!out || !out->data || out->data == in->data) return fail(NJ_EINVAL, "nj_stoc1: bad output");
+    const size_t N = c->N, clen = 2 * N * (in->level + 1);
+    size_t need = 0;
+    for (const auto &lt : p->lts) need = std::max(need, bsgs_words(c, lt));
+    bool ok;
+    Arena A = arena_for(c, 2 * clen + need + N * (in->level + 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *x = A.take(clen), *y = A.take(clen);
+    NJ_HIP(hipMemcpyAsync(x, in->data, clen * 8, hipMemcpyDeviceToDevice, S(stream)));
+    int l = in->level;
+    for (const auto &lt : p->lts) {
+        if ((st = bsgs_apply(c, lt, x, y, 1, A, S(stream)))) return st;
+        if ((st = rescale(c, l, y, x, A, S(stream)))) return st;
+        l--;
+    }
+    NJ_HIP(hipMemcpyAsync(out->data, x, 2 * N * (l + 1) * 8, hipMemcpyDeviceToDevice, S(stream)));
+    out->level = l, out->is_ntt = 1, out->scale = in->scale;
+    return NJ_OK;
+}
+
+}  // extern "C"

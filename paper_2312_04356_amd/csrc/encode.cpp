@@ -349,6 +349,31 @@ static Diags inverse_stage_diags(int k, int n)
     return D;
 }
 
+// S_k = diag(v0) + diag(vp)(.<<<k) + diag(vm)(.<<<-k): the forward butterflies
+// (x_i + w x_{i+k}, x_{i-k} - w x_i) on every 2k-block
+static Diags forward_stage_diags(int k, int n)
+{
+    const std::vector<cplx> w = w_diag(k);
+    std::vector<cplx> v0(n), vp(n), vm(n);
+    for (int i = 0; i < n; i++) {
+        int t = i % (2 * k);
+        if (t < k) v0[i] = 1.0, vp[i] = w[t], vm[i] = 0.0;
+        else v0[i] = -w[t - k], vp[i] = 0.0, vm[i] = 1.0;
+    }
+    Diags D;
+    auto addd = [&](int r, const std::vector<cplx> &v) {
+        r = ((r % n) + n) % n;
+        auto it = D.find(r);
+        if (it == D.end()) D[r] = v;
+        else
+            for (int i = 0; i < n; i++) it->second[i] += v[i];
+    };
+    addd(0, v0);
+    addd(k, vp);
+    addd(-k, vm);
+    return D;
+}
+
 // A B: diag(a_r)(.<<<r) diag(b_s)(.<<<s) = diag(a_r * (b_s <<< r)) (.<<<(r+s))
 static Diags compose(const Diags &A, const Diags &B, int n)
 {
@@ -411,6 +436,69 @@ nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
         }
     }
     return NJ_OK;
+}
+
+// S_{l <- 1} = S_{l/2} ... S_1 (S_1 applied first) in `groups` consecutive groups of
+// strides; a group's unit is its smallest stride
+nj_status build_stoc1_diagonals(int N, int ell, int groups, std::vector<nj_lt_t> &lts,
+                                std::vector<std::vector<std::vector<double>>> &dre,
+                                std::vector<std::vector<std::vector<double>>> &dim)
+{
+    const int n = N / 2;
+    if (ell < 2 || ell > n || (ell & (ell - 1))) return fail(NJ_EINVAL, "StoC1 plan: slice length must be a power of two in 2..N/2");
+    const int S = ilog2(ell);
+    if (groups < 1 || groups > S) return fail(NJ_EINVAL, "StoC1 plan: groups must be 1..log2(l)");
+    std::vector<int> strides;
+    for (int k = 1; k < ell; k *= 2) strides.push_back(k);
+    lts.assign(groups, nj_lt_t());
+    dre.assign(groups, {});
+    dim.assign(groups, {});
+    int pos = 0;
+    for (int g = 0; g < groups; g++) {
+        const int sz = S / groups + (g < S % groups ? 1 : 0);
+        Diags M;
+        for (int s = pos; s < pos + sz; s++) {
+            Diags D = forward_stage_diags(strides[s], n);
+            M = s == pos ? D : compose(D, M, n);
+        }
+        const int u = strides[pos];
+        pos += sz;
+        nj_lt_t &lt = lts[g];
+        lt.u = u;
+        lt.n1 = 0;
+        lt.js.clear();
+        std::map<int, const std::vector<cplx> *> byj;
+        for (auto &kv : M) byj[centred_rep(kv.first, u, n)] = &kv.second;
+        for (auto &kv : byj) lt.js.push_back(kv.first);
+        bsgs_split(lt, n);
+        dre[g].assign(lt.n_diag, {});
+        dim[g].assign(lt.n_diag, {});
+        for (int d = 0; d < lt.n_diag; d++) {
+            std::vector<cplx> v = *byj[lt.js[d]];
+            rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+            dre[g][d].resize(n);
+            dim[g][d].resize(n);
+            for (int j = 0; j < n; j++) dre[g][d][j] = v[j].real(), dim[g][d][j] = v[j].imag();
+        }
+    }
+    return NJ_OK;
+}
+
+// Chebyshev interpolant of degree `degree` at the first-kind nodes x_k = cos(pi (k + 1/2) / m),
+// m = degree + 1: c_j = (2 - [j = 0]) / m * sum_k f(x_k) cos(pi j (k + 1/2) / m)
+void cheb_interpolate_cos(int degree, double K, int r, double *c)
+{
+    const int m = degree + 1;
+    std::vector<double> f(m);
+    for (int k = 0; k < m; k++) {
+        const double x = std::cos(M_PI * (k + 0.5) / m);
+        f[k] = std::cos(2.0 * M_PI * (K * x - 0.25) / std::ldexp(1.0, r));
+    }
+    for (int j = 0; j < m; j++) {
+        double acc = 0.0;
+        for (int k = 0; k < m; k++) acc += f[k] * std::cos(M_PI * j * (k + 0.5) / m);
+        c[j] = (j == 0 ? 1.0 : 2.0) * acc / m;
+    }
 }
 
 }  // namespace nj

@@ -40,7 +40,19 @@ int galois_of_rot(const nj_ctx *c, long long r);
 nj_status check_ct(const nj_ctx *c, const nj_ct *ct, const char *what);
 LimbTab ct_limbs(int l);
 
+// Buffers of one key switch at level l (coefficient form copy, automorphed input, c0
+// copy, extended digits, inner products, special-prime limbs, converted limbs).
+struct KsBufs {
+    uint64_t *coef, *dtmp, *c0copy, *ext, *u, *pc, *conv;
+};
 size_t ks_words(const nj_ctx *c, int l);
+bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B);
+// ModUp of d (evaluation form, level l): every digit extended to Q_l u P
+nj_status modup_ext(nj_ctx *c, int l, const uint64_t *d, KsBufs &B, hipStream_t s);
+// inner product with `key` (digits read through X -> X^g_ip), ModDown, and
+// out = acc + (ModDown_0 + add read through X -> X^g_add, ModDown_1); add / acc may be null
+nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *d_own, const uint64_t *key, uint32_t g_ip, const uint64_t *add,
+                      uint32_t g_add, const uint64_t *acc, uint64_t *out, KsBufs &B, hipStream_t s);
 // out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out)
 nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
                        const uint64_t *acc = nullptr);

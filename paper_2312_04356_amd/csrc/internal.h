@@ -112,6 +112,11 @@ struct KeyJobsX {
     int lv[NJ_MAX_JOBS];               // level l_z
 };
 
+// one residue per ciphertext prime (an integer constant reduced mod q_0..q_63)
+struct LimbConsts {
+    double v[64];
+};
+
 struct MacPlan {
     int nb, ng;
     int dl;  // limbs per stored diagonal (the plan's encoding level + 1)
@@ -217,7 +222,7 @@ struct nj_lt_t {
 };
 
 struct nj_plan {
-    int kind;  // 0 conv, 1 CoeffToSlot
+    int kind;  // 0 conv, 1 CoeffToSlot, 2 StoC1
     int N = 0;
     std::vector<nj_lt_t> lts;
     // conv layout
@@ -279,6 +284,12 @@ hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, i
 hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, int n_ct, size_t bstride,
                                  size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
+hipError_t launch_tensor(const nj_ctx *c, const uint64_t *a, size_t astride, const uint64_t *b, size_t bstride,
+                         uint64_t *d01, uint64_t *d2, int level, hipStream_t s);
+hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
+                          const LimbConsts &kc, hipStream_t s);
+hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s);
+hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
 hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s);
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s,
@@ -304,6 +315,13 @@ nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
 nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse, int n1,
                                 nj_lt_t &lt, std::vector<std::vector<double>> &dre,
                                 std::vector<std::vector<double>> &dim);
+nj_status build_stoc1_diagonals(int N, int ell, int groups, std::vector<nj_lt_t> &lts,
+                                std::vector<std::vector<std::vector<double>>> &dre,
+                                std::vector<std::vector<std::vector<double>>> &dim);
+void cheb_interpolate_cos(int degree, double K, int r, double *c);
+// encode a transform's complex diagonals at `scale` into its level's primes, NTT, keep on device
+nj_status upload_plan_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector<double>> &re,
+                                const std::vector<std::vector<double>> &im, double scale);
 void bsgs_split(nj_lt_t &lt, int n);
 
 }  // namespace nj

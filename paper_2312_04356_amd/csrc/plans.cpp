@@ -10,11 +10,11 @@
 
 using namespace nj;
 
-namespace {
+namespace nj {
 
 // encode complex diagonals at `scale`, reduce into the level's primes, transform.
 // re.size() diagonals (lt.n_diag per block); empty ones are zero and stay zero.
-nj_status upload_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector<double>> &re,
+nj_status upload_plan_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector<double>> &re,
                            const std::vector<std::vector<double>> &im, double scale)
 {
     const size_t N = c->N, plen = N * (lt.level + 1), count = re.size();
@@ -40,7 +40,7 @@ nj_status upload_diagonals(nj_ctx *c, nj_lt_t &lt, const std::vector<std::vector
     return NJ_OK;
 }
 
-}  // namespace
+}  // namespace nj
 
 int plan_galois_impl(const nj_plan *p, std::vector<uint32_t> &gs)
 {
@@ -88,7 +88,7 @@ nj_status nj_conv_plan_create(nj_ctx *c, int w0, int f, const double *weights, i
     p->f = f;
     p->c_in = p->c_out = p->C;
     for (p->W = 1; p->W * p->W < 2 * lt.u; p->W *= 2) {}
-    st = upload_diagonals(c, lt, re, im, (double)c->primes[1]);
+    st = upload_plan_diagonals(c, lt, re, im, (double)c->primes[1]);
     if (st) {
         nj_plan_destroy(p);
         return st;
@@ -122,7 +122,7 @@ nj_status nj_conv_plan_create_taps(nj_ctx *c, int w0, int c_in, int c_out, const
     }
     p->W = W, p->ell = lt.u, p->C = (c->N / 2) / lt.u, p->w0 = w0, p->f = 0;
     p->c_in = c_in, p->c_out = c_out;
-    st = upload_diagonals(c, lt, re, im, (double)c->primes[level]);
+    st = upload_plan_diagonals(c, lt, re, im, (double)c->primes[level]);
     if (st) {
         nj_plan_destroy(p);
         return st;
@@ -158,7 +158,7 @@ nj_status nj_cts_plan_create(nj_ctx *c, int groups, nj_plan **out)
     for (int g = 0; g < groups; g++) {
         nj_lt_t &lt = p->lts[g];
         lt.level = c->L - g;
-        st = upload_diagonals(c, lt, re[g], im[g], (double)c->primes[lt.level]);
+        st = upload_plan_diagonals(c, lt, re[g], im[g], (double)c->primes[lt.level]);
         if (st) {
             nj_plan_destroy(p);
             return st;

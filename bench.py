@@ -8,7 +8,8 @@ Inputs (keys, plan diagonals, the encrypted image) are resident in HBM before th
 timed region.  Prints one JSON line.
 
 Order of GPU work: setup, key switches per second (plain and batched), the mixed
-job list at uneven levels (plain vs batched HIP-graph replay), the batched pipeline,
+job list at uneven levels (plain vs batched HIP-graph replay), ModEval and StoC1
+timings (reported separately), the batched pipeline,
 warmup, timed steps, then the same number of steps again with the library's
 per-kernel event timing (the last GPU work of the run, so a kernel trace's final
 dispatches are those steps).
@@ -38,6 +39,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="ciphertexts in the batched measurements")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--jobs", type=int, default=64, help="mixed jobs at uneven levels (0 skips them)")
+    ap.add_argument("--no-boot", action="store_true", help="skip the ModEval / StoC1 timing")
     return ap.parse_args()
 
 
@@ -182,6 +184,48 @@ def jobs_bench(g, n_jobs, steps=2):
             "tuned_n1": {"%s/C%d" % k: v for k, v in sorted(n1_of.items())}}
 
 
+def boot_bench(g, steps=3):
+    """the bootstrapping steps after CoeffToSlot on the step's Re / Im outputs (level 20):
+    ModEval of Re and of Im (11 levels each), Re + i Im, StoC1 for l = 2048 in 3 groups"""
+    import torch
+    import synth
+    gctx = g.ctx
+    lo = gctx.L - g.w["cts_groups"]
+    stoc1 = gctx.nj_stoc1_plan_create(g.ell, 3, lo - 11)
+    a, e = synth.key_randomness(g.q + g.p, g.N, gctx.dnum, g.w["key_seed"], synth.RELIN_KEY_ID)
+    gctx.nj_gen_switch_key(0, a, e)
+    g.make_keys(sorted(stoc1.galois()))
+    ct = g.encrypt_input(1)
+    y = gctx.empty_ct(0)
+    gctx.nj_conv2d_cins(g.conv_plan, ct, y)
+    re, im = gctx.empty_ct(lo), gctx.empty_ct(lo)
+    gctx.nj_coeff_to_slot(g.cts_plan, y, re, im)
+    er, ei, z = gctx.empty_ct(lo - 11), gctx.empty_ct(lo - 11), gctx.empty_ct(lo - 11)
+    out = gctx.empty_ct(lo - 14)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+
+    def run():
+        gctx.nj_eval_mod(re, 32, 3, None, er)
+        gctx.nj_eval_mod(im, 32, 3, None, ei)
+        e1.record()
+        gctx.nj_combine(er, ei, z)
+        gctx.nj_stoc1(stoc1, z, out)
+
+    run()
+    torch.cuda.synchronize()
+    t_mod = t_all = 0.0
+    for _ in range(steps):
+        e0.record()
+        run()
+        e2.record()
+        torch.cuda.synchronize()
+        t_mod += e0.elapsed_time(e1)
+        t_all += e0.elapsed_time(e2)
+    return {"eval_mod_re_im_ms": round(t_mod / steps, 3), "stoc1_ms": round((t_all - t_mod) / steps, 3),
+            "levels": {"in": lo, "after_eval_mod": lo - 11, "after_stoc1": lo - 14}, "K": 32, "degree": 63,
+            "double_angles": 3, "stoc1_groups": 3}
+
+
 def cpu_baseline(name):
     """The oracle on the host: one fused conv at level 1 and the ModRaise executed in
     full; one rotation, one PMult and one rescale at each CoeffToSlot level, scaled
@@ -291,6 +335,7 @@ def main():
         del xb, ob
 
     jobs = jobs_bench(g, args.jobs) if args.jobs > 0 else None
+    boot = None if args.no_boot else boot_bench(g)
     torch.cuda.empty_cache()
 
     # batched fused conv + CoeffToSlot: 64 ciphertexts (distinct encryptions of the image)
@@ -378,6 +423,7 @@ def main():
                     "speedup_vs_plain": round(ms / (batch_ms / args.batch), 3),
                     "hbm_frac_per_ct": round(pipeline_bytes(g) / (batch_ms / args.batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "jobs": jobs,
+        "bootstrap_after_cts": boot,
         "roofline": roofline,
         "pipeline": {"algorithmic_GB": round(alg / 1e9, 3),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -48,6 +48,7 @@ def _load():
         "or_modup": (None, [vp, i32, vp, vp]),
         "or_moddown": (None, [vp, i32, vp, vp]),
         "or_keyswitch_ext": (None, [vp, i32, vp, u64, vp, vp, vp]),
+        "or_key_ip": (None, [vp, i32, vp, u64, vp, vp, vp]),
         "or_keyswitch": (None, [vp, i32, vp, vp, vp, vp]),
         "or_switch_key": (None, [vp, vp, vp, vp, vp, vp]),
         "or_rescale": (None, [vp, i32, vp, vp]),
@@ -193,6 +194,14 @@ class Ring:
         o1 = np.empty_like(o0)
         lib.or_keyswitch(self.ptr, level, _p(d), _p(key), _p(o0), _p(o1))
         return o0, o1
+
+    def key_ip(self, level, ext, g, key):
+        """key inner product over Q_l u P without ModDown: (u0, u1), each [l+1+alpha][n]"""
+        ext, key = _u64(ext), _u64(key)
+        u0 = np.empty((level + 1 + self.alpha, self.n), dtype=np.uint64)
+        u1 = np.empty_like(u0)
+        lib.or_key_ip(self.ptr, level, _p(ext), int(g), _p(key), _p(u0), _p(u1))
+        return u0, u1
 
     def keyswitch_ext(self, level, ext, g, key):
         ext, key = _u64(ext), _u64(key)

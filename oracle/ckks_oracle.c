@@ -314,13 +314,14 @@ void or_moddown(const or_ring *R, int l, const uint64_t *u, uint64_t *out)
  * (hoisted rotation).  key: [n_digits(L)][2][(L+1+alpha)][n].
  * out0/out1: [(l+1)][n].
  */
-void or_keyswitch_ext(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, const uint64_t *key,
-                      uint64_t *out0, uint64_t *out1)
+/* key inner product (u0, u1) = sum_j tau_g(ext_j) (b_j, a_j) over Q_l u P, coefficient form */
+void or_key_ip(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, const uint64_t *key, uint64_t *u0,
+               uint64_t *u1)
 {
     int n = R->n, ne = l + 1 + R->alpha, nk = R->L + 1 + R->alpha;
     size_t stride = (size_t)ne * n;
-    uint64_t *u0 = (uint64_t *)calloc(stride, sizeof(uint64_t));
-    uint64_t *u1 = (uint64_t *)calloc(stride, sizeof(uint64_t));
+    memset(u0, 0, stride * sizeof(uint64_t));
+    memset(u1, 0, stride * sizeof(uint64_t));
     uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n), *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
     for (int j = 0; j < n_digits(R, l); j++) {
         const uint64_t *kb = key + ((size_t)j * 2 + 0) * nk * n;
@@ -336,9 +337,19 @@ void or_keyswitch_ext(const or_ring *R, int l, const uint64_t *ext_all, uint64_t
             for (int k = 0; k < n; k++) u1[(size_t)t * n + k] = addm(u1[(size_t)t * n + k], prd[k], pt);
         }
     }
+    free(tmp); free(prd);
+}
+
+void or_keyswitch_ext(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, const uint64_t *key,
+                      uint64_t *out0, uint64_t *out1)
+{
+    size_t stride = (size_t)(l + 1 + R->alpha) * R->n;
+    uint64_t *u0 = (uint64_t *)malloc(stride * sizeof(uint64_t));
+    uint64_t *u1 = (uint64_t *)malloc(stride * sizeof(uint64_t));
+    or_key_ip(R, l, ext_all, g, key, u0, u1);
     or_moddown(R, l, u0, out0);
     or_moddown(R, l, u1, out1);
-    free(u0); free(u1); free(tmp); free(prd);
+    free(u0); free(u1);
 }
 
 /* plain (non-hoisted) key switch of d: ModUp -> inner product -> ModDown */

@@ -109,8 +109,10 @@ class Ctx:
             out[r] = np.stack([self.ring.add(level, c0, k0), k1])
         return out
 
-    def bsgs(self, level, x, plan, pts, hoist=True):
-        """sum_j pts[j] (.) (x <<< j u), evaluated baby-step giant-step"""
+    def bsgs(self, level, x, plan, pts, hoist=True, lazy=False):
+        """sum_j pts[j] (.) (x <<< j u), evaluated baby-step giant-step.  lazy: the giant
+        rotations' key inner products are summed over Q_l u P and share one ModDown
+        (their rotated c0 parts are summed alongside)"""
         babies = plan.babies
         if hoist:
             rot = self.hoisted_rotations(level, x, [plan.baby_rot(i) for i in babies])
@@ -118,6 +120,7 @@ class Ctx:
         else:
             baby = {i: self.rotate(level, x, plan.baby_rot(i)) for i in babies}
         acc = None
+        inners = {}
         for g in plan.giants:
             inner = None
             for j, (gg, i) in sorted(plan.split.items()):
@@ -125,10 +128,36 @@ class Ctx:
                     continue
                 t = self.ct_pmult(level, baby[i], pts[j])
                 inner = t if inner is None else self.ct_add(level, inner, t)
+            inners[g] = inner
+        if lazy:
+            return self._giants_lazy(level, plan, inners)
+        for g in plan.giants:
+            inner = inners[g]
             if g != 0:
                 inner = self.rotate(level, inner, plan.giant_rot(g))
             acc = inner if acc is None else self.ct_add(level, acc, inner)
         return acc
+
+    def _giants_lazy(self, level, plan, inners):
+        R = self.ring
+        ext_q = np.array(R.ext_primes(level), dtype=np.uint64)[:, None]
+        u0s = u1s = c0s = None
+        for g in plan.giants:
+            if g == 0:
+                continue
+            ge = galois_elt(plan.giant_rot(g), self.N)
+            c0 = R.poly_automorph(level, inners[g][0], ge)
+            d = R.poly_automorph(level, inners[g][1], ge)
+            u0, u1 = R.key_ip(level, R.modup(level, d), 1, self.keys[ge])
+            if u0s is None:
+                u0s, u1s, c0s = u0, u1, c0
+            else:
+                u0s, u1s = (u0s + u0) % ext_q, (u1s + u1) % ext_q
+                c0s = R.add(level, c0s, c0)
+        if u0s is None:
+            return inners[0]
+        out = np.stack([R.add(level, c0s, R.moddown(level, u0s)), R.moddown(level, u1s)])
+        return self.ct_add(level, inners[0], out) if 0 in inners else out
 
     # ------------------------------------------------------------ the path
     def conv2d_cins(self, x, plan, pts, level=1, hoist=True):
@@ -141,12 +170,12 @@ class Ctx:
         im = self.ct_monomial(level, self.ct_sub(level, x, c), 3 * self.N // 2)
         return re, im
 
-    def coeff_to_slot(self, x0, groups, group_pts, hoist=True):
+    def coeff_to_slot(self, x0, groups, group_pts, hoist=True, lazy=False):
         """x0: level-0 ct [2][1][N].  groups: [Bsgs]; group_pts[g]: {j: pt} at level L-g."""
         x = self.ct_modraise(x0)
         level = self.ring.L
         for plan, pts in zip(groups, group_pts):
-            x = self.bsgs(level, x, plan, pts, hoist)
+            x = self.bsgs(level, x, plan, pts, hoist, lazy)
             x = self.ct_rescale(level, x)
             level -= 1
         return self.conj_split(level, x)

@@ -73,3 +73,32 @@ def test_coeff_to_slot_gives_bit_reversed_coefficients(wl, conv_out):
         assert np.max(np.abs(z.real - want)) < 1e-3, np.max(np.abs(z.real - want))
     # the q0 I multiples are really there (ModRaise is not the identity on the message)
     assert np.max(np.abs(raw)) > wl.ring.q[0] / wl.scale
+
+
+def test_lazy_giant_steps_agree_within_noise(wl):
+    """one ModDown for the sum of the giant steps' inner products: a different rounding
+    (several correct results), the same plaintext up to a few units per coefficient"""
+    plan, pts = wl.cts[0]
+    x = wl.ctx.ct_modraise(wl.encrypt_input(0))
+    L = wl.ring.L
+    assert len([g for g in plan.giants if g]) > 1
+    a = wl.ctx.bsgs(L, x, plan, pts, lazy=False)
+    b = wl.ctx.bsgs(L, x, plan, pts, lazy=True)
+    assert not np.array_equal(a, b)
+    da = O.centred_from_limbs(wl.ring.decrypt(L, wl.s, a), wl.ring.q[:L + 1])
+    db = O.centred_from_limbs(wl.ring.decrypt(L, wl.s, b), wl.ring.q[:L + 1])
+    # before the rescale the scale is 2^40 q_L; rounding differs by far less than q_L
+    assert max(abs(p - q) for p, q in zip(da, db)) < wl.ring.q[L] * 2.0 ** -20
+
+
+@pytest.mark.slow
+def test_lazy_coeff_to_slot_gives_bit_reversed_coefficients(wl, conv_out):
+    re, im = wl.ctx.coeff_to_slot(conv_out, [p for p, _ in wl.cts], [pts for _, pts in wl.cts], lazy=True)
+    level = wl.ring.L - len(wl.cts)
+    raw = raw_modraised(wl, conv_out).astype(np.float64) / wl.scale
+    n = wl.N // 2
+    rev = np.array([E.bitrev(j, n) for j in range(n)])
+    for ct, want in ((re, raw[:n][rev]), (im, raw[n:][rev])):
+        m = O.centred_from_limbs(wl.ring.decrypt(level, wl.s, ct)[:2], wl.ring.q[:2])
+        z = E.decode(np.array(m, dtype=np.float64), wl.N, wl.scale)
+        assert np.max(np.abs(z.real - want)) < 1e-3 and np.max(np.abs(z.imag)) < 1e-3

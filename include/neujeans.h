@@ -167,6 +167,12 @@ int nj_plan_offsets(const nj_plan *plan, int t, int32_t *out, int max);
  * coefficient form (already baby-step giant-step pre-rotated). Synchronous.  In a
  * block conv plan idx = (ob bi + ib) n_diag + d addresses diagonal d of block (ob, ib). */
 nj_status nj_plan_set_diagonal(nj_ctx *ctx, nj_plan *plan, int t, int idx, const uint64_t *coeffs);
+/* Lazy giant steps (on = 1): the giant rotations of every transform of the plan sum
+ * their key inner products over Q_l u P and share one ModDown (the BSGS outer sum is
+ * linear); a different rounding of the same result, so parity holds per setting.
+ * Single-ciphertext and batched transforms only (block and mixed-level transforms
+ * return NJ_EUNSUPPORTED). */
+nj_status nj_plan_set_lazy(nj_plan *plan, int on);
 void nj_plan_destroy(nj_plan *plan);
 
 /* Fused conv2d + StoC2 plan (Sec. 3.3, Sec. 4, Algorithm 1): C = N/W^2

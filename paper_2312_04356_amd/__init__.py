@@ -82,6 +82,7 @@ _SIGS = {
     "nj_batch_launch": (i32, [vp, vp]),
     "nj_batch_destroy": (None, [vp]),
     "nj_timing_keys": (i32, [vp, i32]),
+    "nj_plan_set_lazy": (i32, [vp, i32]),
     "nj_hmult": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_mul_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, i32, dbl, ctypes.POINTER(NjCt), vp]),
     "nj_add_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, vp]),
@@ -219,6 +220,10 @@ class Plan:
         v = [i32() for _ in range(5)]
         lvl = _lib.nj_plan_layout(self.ptr, *[ctypes.byref(x) for x in v])
         return (lvl,) + tuple(x.value for x in v)
+
+    def set_lazy(self, on=True):
+        _check(_lib.nj_plan_set_lazy(self.ptr, int(bool(on))), "nj_plan_set_lazy")
+        return self
 
     def features(self, level, t=0):
         f = np.zeros(7, dtype=np.float32)

@@ -311,8 +311,9 @@ int bsgs_jobs(const nj_lt_t &lt)
 
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
 {
-    const size_t N = c->N, l = lt.level;
-    return N * 2 * (l + 1) * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, bsgs_jobs(lt));
+    const size_t N = c->N, l = lt.level, ne = l + 1 + c->alpha;
+    return N * 2 * (l + 1) * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, bsgs_jobs(lt)) +
+           (lt.lazy ? N * (2 * ne + l + 1) : 0);
 }
 
 // sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
@@ -387,6 +388,35 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
         return NJ_OK;
     }
+    if (lt.lazy) {  // key inner products summed over Q_l u P, one ModDown
+        uint64_t *usum = A.take(2 * ne * N), *c0sum = A.take(plen);
+        if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
+        for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
+            const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
+            KeyJobs kj;
+            AutoJobs aj, ac;
+            for (int z = 0; z < K; z++) {
+                const int g = gl[c0 + z];
+                const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
+                const uint64_t *x = inner + (size_t)g * clen;
+                aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
+                ac.in[z] = x, ac.out[z] = nullptr, ac.g[z] = ge;
+                kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+                kj.key[z] = key_of(c, ge);
+            }
+            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+            NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
+            NJ_HIP(launch_acc_ext(c, M.u, 2 * ne * N, usum, 0, K, l, c0 ? 3 : 2, s));
+            NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
+        }
+        if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
+        MultiBufs M1 = M;
+        M1.u = usum;
+        MdJobs mj;
+        mj.add[0] = c0sum, mj.g_add[0] = 1, mj.out[0] = out;
+        return ks_down(c, l, 1, mj, 0, acc ? out : nullptr, M1, s);
+    }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
         KeyJobs kj;
@@ -424,7 +454,8 @@ size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K)
 {
     const size_t N = c->N, l = lt.level, clen = 2 * N * (l + 1);
     if (!batch_mac_fits(lt)) return bsgs_words(c, lt);
-    return clen * K * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, K);
+    return clen * K * (lt.babies.size() + lt.giants.size()) + multi_words(c, l, K) +
+           (lt.lazy ? N * K * (2 * (l + 1 + c->alpha) + l + 1) : 0);
 }
 
 nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *in, uint64_t *out, Arena A,
@@ -486,23 +517,43 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
                                     hipMemcpyDeviceToDevice, s));
             have = true;
         }
+    uint64_t *usum = nullptr, *c0sum = nullptr;
+    if (lt.lazy) {
+        usum = A.take(N * K * 2 * ne), c0sum = A.take(N * K * (l + 1));
+        if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
+    }
+    bool first = true;
     for (int g = 0; g < ng; g++) {
         if (lt.giants[g] == 0) continue;
         const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
-        AutoJobs aj;
+        AutoJobs aj, ac;
         KeyJobs kj;
         MdJobs mj;
         for (int z = 0; z < K; z++) {
             const uint64_t *x = inner_all + ((size_t)z * ng + g) * clen;
             aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
+            ac.in[z] = x, ac.out[z] = nullptr, ac.g[z] = ge;
             kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
             mj.add[z] = x, mj.g_add[z] = ge, mj.out[z] = out + z * clen;
         }
         NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
         if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
         NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
+        if (lt.lazy) {  // per ciphertext: inner products and rotated c0 parts summed
+            NJ_HIP(launch_acc_ext(c, M.u, 2 * ne * N, usum, 2 * ne * N, K, l, first ? 0 : 1, s));
+            NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, plen, first ? 0 : 1, s));
+            first = false;
+            continue;
+        }
         if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
         have = true;
+    }
+    if (lt.lazy && !first) {  // one ModDown per ciphertext
+        MultiBufs M1 = M;
+        M1.u = usum;
+        MdJobs mj;
+        for (int z = 0; z < K; z++) mj.add[z] = c0sum + z * plen, mj.g_add[z] = 1, mj.out[z] = out + z * clen;
+        if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M1, s))) return st;
     }
     return NJ_OK;
 }
@@ -559,6 +610,7 @@ size_t block_words(const nj_ctx *c, const nj_lt_t &lt)
 
 nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
 {
+    if (lt.lazy) return fail(NJ_EUNSUPPORTED, "block transforms run giant steps with one ModDown each");
     const int l = lt.level, bi = lt.bi, bo = lt.bo, nd = lt.n_diag;
     const size_t N = c->N, clen = 2 * N * (l + 1), plen = N * (l + 1);
     const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
@@ -1149,6 +1201,13 @@ nj_status nj_plan_set_diagonal(nj_ctx *c, nj_plan *p, int t, int idx, const uint
     NJ_HIP(hipMemcpy(dst, coeffs, plen * 8, hipMemcpyHostToDevice));
     NJ_HIP(launch_ntt(c, dst, limbs_q(lt.dl - 1), false, 0));
     NJ_HIP(hipDeviceSynchronize());
+    return NJ_OK;
+}
+
+nj_status nj_plan_set_lazy(nj_plan *p, int on)
+{
+    if (!p) return fail(NJ_EINVAL, "nj_plan_set_lazy: null plan");
+    for (auto &lt : p->lts) lt.lazy = on != 0;
     return NJ_OK;
 }
 

@@ -174,6 +174,7 @@ nj_status bsgs_apply_mixed(nj_ctx *c, const nj_lt_t &lt, const std::vector<MixJo
     const int n = (int)jobs.size(), nb = (int)lt.babies.size(), ng = (int)lt.giants.size(), nd = lt.n_diag;
     const size_t N = c->N;
     if (n < 1 || n > NJ_MAX_JOBS) return fail(NJ_EINVAL, "mixed transform: 1..16 ciphertexts");
+    if (lt.lazy) return fail(NJ_EUNSUPPORTED, "mixed-level transforms run giant steps with one ModDown each");
     for (int b : lt.babies)
         if (b != 0 && !key_of(c, galois_of_rot(c, (long long)b * lt.u))) return fail(NJ_ENOKEY, "missing baby-step key");
     for (int g : lt.giants)

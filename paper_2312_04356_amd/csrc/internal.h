@@ -218,6 +218,7 @@ struct nj_lt_t {
     int dl = 0;                          // limbs per diagonal: encoded at level dl-1, usable at any level below
     double scale = 0.0;                  // encoding scale of the diagonals
     int bi = 1, bo = 1;                  // block conv: input / output ciphertexts
+    bool lazy = false;                   // giant steps share one ModDown
     std::vector<char> nz;                // [bo][bi][n_diag] nonzero diagonals (empty = all)
 };
 
@@ -290,6 +291,10 @@ hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, u
                           const LimbConsts &kc, hipStream_t s);
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s);
 hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
+hipError_t launch_acc_ext(const nj_ctx *c, const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
+                          int n_jobs, int level, int mode, hipStream_t s);
+hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,
+                                size_t ostride, int mode, hipStream_t s);
 hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s);
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s,

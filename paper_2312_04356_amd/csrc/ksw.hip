@@ -384,6 +384,75 @@ hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, i
                   s, kj, n_jobs, key, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
 }
 
+// Lazy giant steps: key inner products of several rotations summed over Q_l u P before
+// one ModDown.  src job z at src + z sstride, [2][ne][N]; dst job z at dst + z dstride.
+// mode 0: dst_z = src_z; 1: dst_z += src_z; 2: dst_0 = sum_z src_z; 3: dst_0 += sum_z src_z
+__global__ __launch_bounds__(kBT) void k_acc_ext(const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
+                                                int n_jobs, int level, int ne, int nq, int mode,
+                                                const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, row = blockIdx.y, t = row % ne;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const Mod m = info[t <= level ? t : nq + (t - level - 1)].m;
+    const size_t o = (size_t)row * N + k;
+    if (mode < 2) {
+        const int z = blockIdx.z;
+        double v = u2d(src[z * sstride + o]);
+        if (mode == 1) v = add_mod(v, u2d(dst[z * dstride + o]), m);
+        dst[z * dstride + o] = d2u(v);
+        return;
+    }
+    double v = mode == 3 ? u2d(dst[o]) : 0.0;
+    for (int z = 0; z < n_jobs; z++) v = add_mod(v, u2d(src[z * sstride + o]), m);
+    dst[o] = d2u(v);
+}
+
+// c0 parts of the lazy giant steps: out (+)= tau_{g_z}(in_z) over l+1 limbs, per job
+// (mode 0 / 1, out_z at out + z ostride) or summed over the jobs into out (mode 2 / 3)
+__global__ __launch_bounds__(kBT) void k_automorph_acc(AutoJobs aj, int n_jobs, uint64_t *out, size_t ostride,
+                                                      int mode, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const Mod m = info[i].m;
+    const size_t o = (size_t)i * N;
+    if (mode < 2) {
+        const int z = blockIdx.z;
+        const int src = aj.g[z] <= 1u ? k : galois_src2(k, aj.g[z], logN);
+        double v = u2d(aj.in[z][o + src]);
+        if (mode == 1) v = add_mod(v, u2d(out[z * ostride + o + k]), m);
+        out[z * ostride + o + k] = d2u(v);
+        return;
+    }
+    double v = mode == 3 ? u2d(out[o + k]) : 0.0;
+    for (int z = 0; z < n_jobs; z++) {
+        const int src = aj.g[z] <= 1u ? k : galois_src2(k, aj.g[z], logN);
+        v = add_mod(v, u2d(aj.in[z][o + src]), m);
+    }
+    out[o + k] = d2u(v);
+}
+
+hipError_t launch_acc_ext(const nj_ctx *c, const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
+                          int n_jobs, int level, int mode, hipStream_t s)
+{
+    const int ne = level + 1 + c->alpha;
+    dim3 grid((c->N + kBT - 1) / kBT, 2 * ne, mode < 2 ? n_jobs : 1);
+    const double words = 2.0 * ne * c->N * (mode < 2 ? n_jobs * (mode ? 3.0 : 2.0) : n_jobs + (mode == 3 ? 2.0 : 1.0));
+    return launch(c, PROF_OTHER, 8.0 * words, k_acc_ext, grid, dim3(kBT), s, src, sstride, dst, dstride, n_jobs, level,
+                  ne, c->n_q, mode, c->d_info, c->log_n);
+}
+
+hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,
+                                size_t ostride, int mode, hipStream_t s)
+{
+    dim3 grid((c->N + kBT - 1) / kBT, n_limbs, mode < 2 ? n_jobs : 1);
+    const double words = (double)n_limbs * c->N * (mode < 2 ? n_jobs * (mode ? 3.0 : 2.0) : n_jobs + (mode == 3 ? 2.0 : 1.0));
+    return launch(c, PROF_OTHER, 8.0 * words, k_automorph_acc, grid, dim3(kBT), s, aj, n_jobs, out, ostride, mode,
+                  c->d_info, c->log_n);
+}
+
 // Mixed-level form of k_key_ip_shared: grid row t is Q limb t for t <= lmax, special
 // prime t - lmax - 1 after; job z skips Q limbs above its level l_z, and its limb index
 // inside its own [l_z+1+alpha] layout is t (Q) or l_z+1+a (special prime a).

@@ -20,7 +20,7 @@ def padded_width(w0, f):
 
 
 class GpuWorkload:
-    def __init__(self, name, with_cts=True, conv_n1=0):
+    def __init__(self, name, with_cts=True, conv_n1=0, lazy=False):
         import torch
         self.torch = torch
         w = dict(synth.WORKLOADS[name])
@@ -38,6 +38,8 @@ class GpuWorkload:
         self.K = synth.uniform_real((w["c_out"], w["c_in"], w["f"], w["f"]), w["data_seed"], 1)
         self.conv_plan = self.ctx.nj_conv_plan_create(w["w0"], w["f"], self.K, conv_n1)
         self.cts_plan = self.ctx.nj_cts_plan_create(w["cts_groups"]) if with_cts else None
+        if lazy and self.cts_plan is not None:
+            self.cts_plan.set_lazy(True)
         self.keys_made = set()
 
     def galois_elements(self):

@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--jobs", type=int, default=64, help="mixed jobs at uneven levels (0 skips them)")
     ap.add_argument("--no-boot", action="store_true", help="skip the ModEval / StoC1 timing")
+    ap.add_argument("--no-lazy", action="store_true", help="one ModDown per giant step in CoeffToSlot")
     return ap.parse_args()
 
 
@@ -288,7 +289,7 @@ def main():
     from paper_2312_04356_amd import PROF_KERNELS
     from paper_2312_04356_amd.workload import GpuWorkload
 
-    g = GpuWorkload(args.workload, with_cts=True)
+    g = GpuWorkload(args.workload, with_cts=True, lazy=not args.no_lazy)
     gctx = g.ctx
     g.make_keys()
     ct = g.encrypt_input(1)
@@ -416,7 +417,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "N=2^16 fused CinS conv 3x3 16->16 32x32 + CoeffToSlot (3 groups), 24+8 primes, dnum=3",
                    "log_n": gctx.log_n, "n_q": gctx.L + 1, "alpha": gctx.alpha,
-                   "cts_groups": g.w["cts_groups"], "host_wall_s": round(wall, 3)},
+                   "cts_groups": g.w["cts_groups"], "lazy_giant_steps": not args.no_lazy,
+                   "host_wall_s": round(wall, 3)},
         "keyswitch_per_s": {"plain": ks, "batched": ks_batch, "batch": nbk, "galois": gk},
         "batched": {"n_ct": args.batch, "ms_per_batch": round(batch_ms, 3),
                     "ms_per_ct": round(batch_ms / args.batch, 4),

@@ -1,0 +1,114 @@
+"""Lazy giant steps (one ModDown for the sum of a transform's giant-step inner
+products) through the C ABI (needs an MI355X): CoeffToSlot bit-exact against the
+oracle's lazy evaluation at N = 2^12, batched equal to single calls, and the
+library's own lazy plans accurate at N = 2^16."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.encoding as E
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import synth  # noqa: E402
+from paper_2312_04356_amd import Ct  # noqa: E402
+from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+from tests.oracle_workload import OracleWorkload  # noqa: E402
+
+
+def host_coeff(gctx, t, level):
+    t = t.clone()
+    gctx.nj_to_coeff(t, level, 2)
+    torch.cuda.synchronize()
+    return gctx.to_host(t)
+
+
+def cts_batch_vs_single(g, y, n):
+    gctx = g.ctx
+    lvl = gctx.L - g.w["cts_groups"]
+    re, im = gctx.empty_batch(n, lvl), gctx.empty_batch(n, lvl)
+    gctx.nj_coeff_to_slot_batch(g.cts_plan, y, n, re, im)
+    torch.cuda.synchronize()
+    for z in range(n):
+        rz, iz = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+        gctx.nj_coeff_to_slot(g.cts_plan, Ct(y.data[z], 0), rz, iz)
+        assert torch.equal(rz.data, re.data[z]) and torch.equal(iz.data, im.data[z]), "ciphertext %d" % z
+    return re, im
+
+
+def test_lazy_coeff_to_slot_parity_small():
+    o = OracleWorkload("small", with_cts=True)
+    g = GpuWorkload("small", with_cts=True, lazy=True)
+    gctx = g.ctx
+    gs = g.cts_plan.galois()
+    g.make_keys(gs)
+    o.make_keys(gs)
+    for t, (plan, pts) in enumerate(o.cts):
+        for idx, j in enumerate(g.cts_plan.offsets(t)):
+            gctx.nj_plan_set_diagonal(g.cts_plan, t, idx, pts[j])
+    m = o.ring.to_rns(o.input_plaintext(), 0)
+    x_o = o.encrypt_input(0)
+    x_g = g.encrypt_input(0, m_dev=gctx.to_device(m))
+    lvl = o.ring.L - len(o.cts)
+    re, im = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+    gctx.nj_coeff_to_slot(g.cts_plan, x_g, re, im)
+    w_re, w_im = o.ctx.coeff_to_slot(x_o, [p for p, _ in o.cts], [pts for _, pts in o.cts], lazy=True)
+    assert np.array_equal(host_coeff(gctx, re.data, lvl), w_re)
+    assert np.array_equal(host_coeff(gctx, im.data, lvl), w_im)
+    # before the rescale the two roundings differ (the rescale by q_L ~ 2^48 absorbs it)
+    L = o.ring.L
+    xr = gctx.empty_ct(L)
+    gctx.nj_modraise(x_g, L, xr)
+    lazy_out, plain_out = gctx.empty_ct(L), gctx.empty_ct(L)
+    gctx.nj_plan_apply(g.cts_plan, 0, xr, lazy_out)
+    g.cts_plan.set_lazy(False)
+    gctx.nj_plan_apply(g.cts_plan, 0, xr, plain_out)
+    g.cts_plan.set_lazy(True)
+    xo = o.ctx.ct_modraise(x_o)
+    plan0, pts0 = o.cts[0]
+    assert np.array_equal(host_coeff(gctx, lazy_out.data, L), o.ctx.bsgs(L, xo, plan0, pts0, lazy=True))
+    assert np.array_equal(host_coeff(gctx, plain_out.data, L), o.ctx.bsgs(L, xo, plan0, pts0, lazy=False))
+    assert not torch.equal(lazy_out.data, plain_out.data)
+    y = gctx.empty_batch(4, 0)
+    for z in range(4):
+        y.data[z].copy_(x_g.data)
+    cts_batch_vs_single(g, y, 4)
+
+
+def test_lazy_coeff_to_slot_full_accuracy_and_batch():
+    g = GpuWorkload("full", with_cts=True, lazy=True)
+    gctx = g.ctx
+    g.make_keys()
+    n = 3
+    y = gctx.empty_batch(n, 0)
+    for z in range(n):
+        ct = g.encrypt_input(1)
+        gctx.nj_conv2d_cins(g.conv_plan, ct, Ct(y.data[z], 0))
+    re, im = cts_batch_vs_single(g, y, n)
+    # slots: the bit-reversed halves of the ModRaised coefficients (m + q0 I) / scale
+    q0 = g.q[0]
+    c = host_coeff(gctx, y.data[0], 0)
+    c0 = np.where(c[0][0] > q0 // 2, c[0][0].astype(np.int64) - np.int64(q0), c[0][0].astype(np.int64))
+    c1 = np.where(c[1][0] > q0 // 2, c[1][0].astype(np.int64) - np.int64(q0), c[1][0].astype(np.int64))
+    prod = np.zeros_like(c0)
+    for i in np.nonzero(g.s)[0]:
+        sh = np.roll(c1, i)
+        sh[:i] = -sh[:i]
+        prod += int(g.s[i]) * sh
+    raw = (c0 + prod).astype(np.float64) / g.scale
+    n2 = g.N // 2
+    rev = np.array([E.bitrev(j, n2) for j in range(n2)])
+    lvl = gctx.L - g.w["cts_groups"]
+    for ct, want in ((re, raw[:n2][rev]), (im, raw[n2:][rev])):
+        d = torch.empty((lvl + 1, g.N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_decrypt(Ct(ct.data[0], lvl), d)
+        mm = O.centred_from_limbs(gctx.to_host(d)[:2], g.q[:2])
+        zz = gctx.nj_decode_slots(np.array(mm, dtype=np.float64), g.scale)
+        err = max(np.max(np.abs(zz.real - want)), np.max(np.abs(zz.imag)))
+        print("lazy CoeffToSlot max abs slot error %.3e" % err)
+        assert err < 1e-3
+    assert synth.WORKLOADS["full"]["cts_groups"] == 3

@@ -406,8 +406,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             }
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
             if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
-            NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
-            NJ_HIP(launch_acc_ext(c, M.u, 2 * ne * N, usum, 0, K, l, c0 ? 3 : 2, s));
+            NJ_HIP(launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
         }
         if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
@@ -538,13 +537,13 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
         }
         NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
         if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
-        NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
         if (lt.lazy) {  // per ciphertext: inner products and rotated c0 parts summed
-            NJ_HIP(launch_acc_ext(c, M.u, 2 * ne * N, usum, 2 * ne * N, K, l, first ? 0 : 1, s));
+            NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), usum, s, first ? 0 : 1));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, plen, first ? 0 : 1, s));
             first = false;
             continue;
         }
+        NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
         if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
         have = true;
     }

@@ -281,7 +281,8 @@ hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, in
                                 const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
 hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);
 hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, const uint64_t *key,
-                                uint64_t *u_base, hipStream_t s);
+                                uint64_t *u_base, hipStream_t s,
+                                int accumulate = 0);
 hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, int n_ct, size_t bstride,
                                  size_t istride, const uint64_t *diag, uint64_t *inner, int n_diag, hipStream_t s);
 // inner[g] = sum_b baby_b (.) diag[d_of[g][b]] for every giant g; inner [ng][2][l+1][N]
@@ -291,8 +292,8 @@ hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, u
                           const LimbConsts &kc, hipStream_t s);
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s);
 hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
-hipError_t launch_acc_ext(const nj_ctx *c, const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
-                          int n_jobs, int level, int mode, hipStream_t s);
+hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int accumulate,
+                             hipStream_t s);
 hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,
                                 size_t ostride, int mode, hipStream_t s);
 hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s);

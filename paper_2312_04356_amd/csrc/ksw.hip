@@ -274,6 +274,49 @@ __global__ __launch_bounds__(kBT) void k_key_ip_multi(KeyJobs kj, uint64_t *u_ba
     u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
 }
 
+// lazy giant steps: sum over the jobs (each its own key) of the key inner products,
+// written to u [2][ne][N] or added to it (accumulate)
+__global__ __launch_bounds__(kBT) void k_key_ip_sum(KeyJobs kj, int n_jobs, uint64_t *u, int accumulate, int n_digits,
+                                                   int level, int L, int alpha, int nq, const PrimeInfo *info,
+                                                   int logN)
+{
+    const int N = 1 << logN;
+    const int t = blockIdx.y;
+    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
+    const int pidx = t <= level ? t : nq + (t - level - 1);
+    const int kl = t <= level ? t : L + 1 + (t - level - 1);
+    const int own = t <= level ? t / alpha : -1;
+    const Mod m = info[pidx].m;
+    const int k = blockIdx.x * kBT + threadIdx.x;
+    if (k >= N) return;
+    const size_t o0 = (size_t)t * N + k, o1 = ((size_t)ne + t) * N + k;
+    double acc0 = accumulate ? u2d(u[o0]) : 0.0, acc1 = accumulate ? u2d(u[o1]) : 0.0;
+    int cnt = accumulate ? 1 : 0;
+    for (int z = 0; z < n_jobs; z++) {
+        const uint32_t g = kj.g[z];
+        const uint64_t *ext = kj.ext[z], *d = kj.d[z], *key = kj.key[z];
+        const int src = g == 1u ? k : galois_src2(k, g, logN);
+        for (int j = 0; j < n_digits; j++) {
+            const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
+            const double x = u2d(xp[src]);
+            acc0 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]), m);
+            acc1 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]), m);
+            if ((++cnt & 7) == 0) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+        }
+    }
+    u[o0] = d2u(reduce(acc0, m));
+    u[o1] = d2u(reduce(acc1, m));
+}
+
+hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int accumulate,
+                             hipStream_t s)
+{
+    const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
+    dim3 grid((c->N + kBT - 1) / kBT, ne);
+    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd * n_jobs + 2.0 * (1 + accumulate)), k_key_ip_sum, grid,
+                  dim3(kBT), s, kj, n_jobs, u, accumulate, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+}
+
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
                                hipStream_t s)
 {
@@ -334,8 +377,8 @@ hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, in
 // its digits at kj.ext[z] (own-digit limbs at kj.d[z]) through X -> X^kj.g[z] and writes
 // u_base + z 2 ne N.
 __global__ __launch_bounds__(kBT) void k_key_ip_shared(KeyJobs kj, int n_jobs, const uint64_t *key, uint64_t *u_base,
-                                                      int n_digits, int level, int L, int alpha, int nq,
-                                                      const PrimeInfo *info, int logN)
+                                                      int accumulate, int n_digits, int level, int L, int alpha,
+                                                      int nq, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN;
     const int t = blockIdx.y;
@@ -358,9 +401,12 @@ __global__ __launch_bounds__(kBT) void k_key_ip_shared(KeyJobs kj, int n_jobs, c
         const uint32_t g = kj.g[z];
         const int src = g == 1u ? k : galois_src2(k, g, logN);
         const uint64_t *ext = kj.ext[z], *d = kj.d[z];
-        double acc0 = 0.0, acc1 = 0.0;
+        uint64_t *u = u_base + (size_t)z * 2 * ne * N;
+        const size_t o0 = (size_t)t * N + k, o1 = ((size_t)ne + t) * N + k;
+        // with accumulate, the running sum counts as one of the (<= 8) lazy terms
+        double acc0 = accumulate ? u2d(u[o0]) : 0.0, acc1 = accumulate ? u2d(u[o1]) : 0.0;
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
+        for (int j = 0; j < 7; j++) {
             if (j < n_digits) {
                 const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
                 double x = u2d(xp[src]);
@@ -368,44 +414,26 @@ __global__ __launch_bounds__(kBT) void k_key_ip_shared(KeyJobs kj, int n_jobs, c
                 acc1 += mul_lazy(x, ka[j], m);
             }
         }
-        uint64_t *u = u_base + (size_t)z * 2 * ne * N;
-        u[(size_t)t * N + k] = d2u(reduce(acc0, m));
-        u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+        if (n_digits == 8) {
+            const uint64_t *xp = own == 7 ? d + (size_t)t * N : ext + ((size_t)7 * ne + t) * N;
+            double x = u2d(xp[src]);
+            acc0 = reduce(acc0, m) + mul_lazy(x, kb[7], m);
+            acc1 = reduce(acc1, m) + mul_lazy(x, ka[7], m);
+        }
+        u[o0] = d2u(reduce(acc0, m));
+        u[o1] = d2u(reduce(acc1, m));
     }
 }
 
 hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, const uint64_t *key,
-                                uint64_t *u_base, hipStream_t s)
+                                uint64_t *u_base, hipStream_t s, int accumulate)
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
     if (nd > 8) return hipErrorInvalidValue;
     dim3 grid((c->N + kBT - 1) / kBT, ne);
-    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (2.0 * nd + n_jobs * (nd + 2.0)), k_key_ip_shared, grid, dim3(kBT),
-                  s, kj, n_jobs, key, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
-}
-
-// Lazy giant steps: key inner products of several rotations summed over Q_l u P before
-// one ModDown.  src job z at src + z sstride, [2][ne][N]; dst job z at dst + z dstride.
-// mode 0: dst_z = src_z; 1: dst_z += src_z; 2: dst_0 = sum_z src_z; 3: dst_0 += sum_z src_z
-__global__ __launch_bounds__(kBT) void k_acc_ext(const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
-                                                int n_jobs, int level, int ne, int nq, int mode,
-                                                const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN, row = blockIdx.y, t = row % ne;
-    const int k = blockIdx.x * kBT + threadIdx.x;
-    if (k >= N) return;
-    const Mod m = info[t <= level ? t : nq + (t - level - 1)].m;
-    const size_t o = (size_t)row * N + k;
-    if (mode < 2) {
-        const int z = blockIdx.z;
-        double v = u2d(src[z * sstride + o]);
-        if (mode == 1) v = add_mod(v, u2d(dst[z * dstride + o]), m);
-        dst[z * dstride + o] = d2u(v);
-        return;
-    }
-    double v = mode == 3 ? u2d(dst[o]) : 0.0;
-    for (int z = 0; z < n_jobs; z++) v = add_mod(v, u2d(src[z * sstride + o]), m);
-    dst[o] = d2u(v);
+    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (2.0 * nd + n_jobs * (nd + 2.0 + 2.0 * accumulate)),
+                  k_key_ip_shared, grid, dim3(kBT), s, kj, n_jobs, key, u_base, accumulate, nd, level, c->L, c->alpha,
+                  c->n_q, c->d_info, c->log_n);
 }
 
 // c0 parts of the lazy giant steps: out (+)= tau_{g_z}(in_z) over l+1 limbs, per job
@@ -432,16 +460,6 @@ __global__ __launch_bounds__(kBT) void k_automorph_acc(AutoJobs aj, int n_jobs, 
         v = add_mod(v, u2d(aj.in[z][o + src]), m);
     }
     out[o + k] = d2u(v);
-}
-
-hipError_t launch_acc_ext(const nj_ctx *c, const uint64_t *src, size_t sstride, uint64_t *dst, size_t dstride,
-                          int n_jobs, int level, int mode, hipStream_t s)
-{
-    const int ne = level + 1 + c->alpha;
-    dim3 grid((c->N + kBT - 1) / kBT, 2 * ne, mode < 2 ? n_jobs : 1);
-    const double words = 2.0 * ne * c->N * (mode < 2 ? n_jobs * (mode ? 3.0 : 2.0) : n_jobs + (mode == 3 ? 2.0 : 1.0));
-    return launch(c, PROF_OTHER, 8.0 * words, k_acc_ext, grid, dim3(kBT), s, src, sstride, dst, dstride, n_jobs, level,
-                  ne, c->n_q, mode, c->d_info, c->log_n);
 }
 
 hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,

@@ -36,9 +36,9 @@ __device__ __forceinline__ void ct_round(double v[16], int t0, int hi, int tile,
         for (int k = 0; k < 16; k++) {
             if (k & step) continue;
             const double w = W[base + (k >> (4 - s))];
-            double U = v[k], V = mul_canon(v[k + step], w, m);
-            v[k] = add_mod(U, V, m);
-            v[k + step] = sub_mod(U, V, m);
+            const double U = v[k], V = mul_lazy(v[k + step], w, m);  // V in (-t, t)
+            v[k] = corr(U + V, m);
+            v[k + step] = corr(U - V, m);
         }
     }
 }
@@ -57,9 +57,9 @@ __device__ __forceinline__ void gs_round(double v[16], int t0, int hi, int tile,
         for (int k = 0; k < 16; k++) {
             if (k & step) continue;
             const double w = W[base + (k >> (4 - s))];
-            double U = v[k], V = v[k + step];
-            v[k] = add_mod(U, V, m);
-            v[k + step] = mul_canon(sub_mod(U, V, m), w, m);
+            const double U = v[k], V = v[k + step];
+            v[k] = corr(U + V, m);
+            v[k + step] = corr(mul_lazy(U - V, w, m), m);  // U - V in (-t, t)
         }
     }
 }
@@ -162,9 +162,9 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
             for (int r = 0; r < N1; r++) {
                 if (r & tr) continue;
                 const double w = W[mm + r / (2 * tr)];
-                double U = v[r], V = mul_canon(v[r + tr], w, m);
-                v[r] = add_mod(U, V, m);
-                v[r + tr] = sub_mod(U, V, m);
+                const double U = v[r], V = mul_lazy(v[r + tr], w, m);
+                v[r] = corr(U + V, m);
+                v[r + tr] = corr(U - V, m);
             }
         }
     } else {
@@ -175,9 +175,9 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
             for (int r = 0; r < N1; r++) {
                 if (r & tr) continue;
                 const double w = W[h + r / (2 * tr)];
-                double U = v[r], V = v[r + tr];
-                v[r] = add_mod(U, V, m);
-                v[r + tr] = mul_canon(sub_mod(U, V, m), w, m);
+                const double U = v[r], V = v[r + tr];
+                v[r] = corr(U + V, m);
+                v[r + tr] = corr(mul_lazy(U - V, w, m), m);
             }
         }
 #pragma unroll

@@ -22,10 +22,19 @@ def family(name):
     n = re.sub(r"k_ntt_col<\d+, (false|true)>", r"k_ntt_col<\1>", n)
     n = n.replace("k_bconv_batch<", "k_bconv<").replace("k_bconv_multi<", "k_bconv<").strip()
     n = re.sub(r"k_bconv<\d+>", "k_bconv", n)
-    n = n.replace("k_key_ip_multi", "k_key_ip").replace("k_key_ip2", "k_key_ip").replace("k_bsgs_mac", "k_pmac")
-    if n in ("k_moddown2", "k_moddown_multi", "k_automorph_multi"):
-        n = "other"
+    # the same families the library's HIP-event counters use
+    if n.startswith("k_key_ip"):
+        return "k_key_ip"
+    if n.startswith("k_bsgs_mac"):
+        return "k_pmac"
+    if n in OTHER:
+        return "other"
     return n
+
+
+# kernels the library times together under "other"
+OTHER = ("k_moddown2", "k_moddown_multi", "k_automorph_multi", "k_automorph_acc", "k_tensor", "k_mul_int",
+         "k_add_int", "k_zero")
 
 
 def main(trace, bench_json, plain_json, command):

@@ -151,6 +151,67 @@ hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const 
 
 // ------------------------------------------------------------------- BSGS
 
+// Loads are issued for every static slot b < NBM from an address that is always in
+// bounds (babies beyond nb read baby nb-1, absent diagonals read another diagonal of
+// the same giant step) and masked to zero afterwards, so a wave has a whole giant
+// step's words in flight at once instead of waiting on one data-dependent load at a time.
+template <int NBM>
+__device__ __forceinline__ void load_babies(const MacPlan &mp, size_t zoff, size_t o0, size_t o1, double *b0,
+                                            double *b1)
+{
+    uint64_t r0[NBM], r1[NBM];
+#pragma unroll
+    for (int b = 0; b < NBM; b++) {
+        const uint64_t *bp = mp.baby[b < mp.nb ? b : mp.nb - 1] + zoff;
+        r0[b] = bp[o0];
+        r1[b] = bp[o1];
+    }
+#pragma unroll
+    for (int b = 0; b < NBM; b++) {
+        b0[b] = b < mp.nb ? u2d(r0[b]) : 0.0;
+        b1[b] = b < mp.nb ? u2d(r1[b]) : 0.0;
+    }
+}
+
+// w[b] = word o of diagonal d_of[g][b] (diagonals dstride words apart), zero where
+// absent; false if giant step g has no diagonal at all
+template <int NBM>
+__device__ __forceinline__ bool load_giant(const MacPlan &mp, int g, const uint64_t *diag, size_t dstride, size_t o,
+                                           double *w)
+{
+    int any = -1;
+#pragma unroll
+    for (int b = 0; b < NBM; b++)
+        if (b < mp.nb && mp.d_of[g][b] >= 0) any = mp.d_of[g][b];
+    if (any < 0) return false;
+    uint64_t r[NBM];
+#pragma unroll
+    for (int b = 0; b < NBM; b++) {
+        const int d = b < mp.nb ? mp.d_of[g][b] : -1;
+        r[b] = diag[(size_t)(d < 0 ? any : d) * dstride + o];
+    }
+#pragma unroll
+    for (int b = 0; b < NBM; b++) {
+        const int d = b < mp.nb ? mp.d_of[g][b] : -1;
+        w[b] = d < 0 ? 0.0 : u2d(r[b]);
+    }
+    return true;
+}
+
+// sum_b x[b] w[b] mod t from a start value in [0, t): products are lazy, in (-t, t),
+// and the sum is reduced after every 7 of them, so it stays below 8t <= 2^53
+template <int NBM>
+__device__ __forceinline__ double mac_row(double a, const double *x, const double *w, Mod m)
+{
+#pragma unroll
+    for (int b = 0; b < NBM; b++) {
+        a += mul_lazy(x[b], w[b], m);
+        if (b % 7 == 6 && b + 1 < NBM) a = reduce(a, m);
+    }
+    return reduce(a, m);
+}
+
+template <int NBM>
 __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *diag, uint64_t *inner, int level,
                                                  int accumulate, const PrimeInfo *info, int logN)
 {
@@ -158,32 +219,20 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
     const int k = blockIdx.x * kBT + threadIdx.x;
     if (k >= N) return;
     const Mod m = info[i].m;
-    const size_t L1 = level + 1;
-    double b0[NJ_MAX_BABY], b1[NJ_MAX_BABY];
-#pragma unroll
-    for (int b = 0; b < NJ_MAX_BABY; b++) {
-        if (b < mp.nb) {
-            b0[b] = u2d(mp.baby[b][(size_t)i * N + k]);
-            b1[b] = u2d(mp.baby[b][(L1 + i) * N + k]);
-        }
-    }
+    const size_t L1 = level + 1, o = (size_t)i * N + k;
+    double b0[NBM], b1[NBM];
+    load_babies<NBM>(mp, 0, o, L1 * N + o, b0, b1);
     for (int g = 0; g < mp.ng; g++) {
-        uint64_t *o0 = inner + ((size_t)g * 2 * L1 + i) * N + k, *o1 = inner + ((size_t)(g * 2 + 1) * L1 + i) * N + k;
-        // a running sum in [0, t) counts as one term of the lazy budget
-        double a0 = accumulate ? u2d(*o0) : 0.0, a1 = accumulate ? u2d(*o1) : 0.0;
-        int cnt = accumulate ? 1 : 0;
-#pragma unroll
-        for (int b = 0; b < NJ_MAX_BABY; b++) {
-            if (b >= mp.nb) break;
-            const int dg = mp.d_of[g][b];
-            if (dg < 0) continue;
-            const double w = u2d(diag[((size_t)dg * mp.dl + i) * N + k]);
-            a0 += mul_lazy(b0[b], w, m);
-            a1 += mul_lazy(b1[b], w, m);
-            if ((++cnt & 7) == 0) a0 = reduce(a0, m), a1 = reduce(a1, m);
+        uint64_t *o0 = inner + (size_t)g * 2 * L1 * N + o, *o1 = o0 + L1 * N;
+        double w[NBM];
+        const bool any = load_giant<NBM>(mp, g, diag, (size_t)mp.dl * N, o, w);
+        const double a0 = accumulate ? u2d(*o0) : 0.0, a1 = accumulate ? u2d(*o1) : 0.0;
+        if (!any) {
+            if (!accumulate) *o0 = 0, *o1 = 0;
+            continue;
         }
-        *o0 = d2u(reduce(a0, m));
-        *o1 = d2u(reduce(a1, m));
+        *o0 = d2u(mac_row<NBM>(a0, b0, w, m));
+        *o1 = d2u(mac_row<NBM>(a1, b1, w, m));
     }
 }
 
@@ -551,41 +600,26 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac_multi(MacPlan mp, int n_ct, si
     const Mod m = info[i].m;
     const size_t L1 = level + 1;
     const int g0 = blockIdx.z * GCH;
+    const size_t o = (size_t)i * N + k;
     double w[GCH][NBM];
+    bool any[GCH];
 #pragma unroll
-    for (int gg = 0; gg < GCH; gg++)
+    for (int gg = 0; gg < GCH; gg++) {
+        any[gg] = g0 + gg < mp.ng && load_giant<NBM>(mp, g0 + gg, diag, (size_t)mp.dl * N, o, w[gg]);
+        if (!any[gg])
 #pragma unroll
-        for (int b = 0; b < NBM; b++) {
-            const int g = g0 + gg;
-            const int dg = (g < mp.ng && b < mp.nb) ? mp.d_of[g][b] : -1;
-            w[gg][b] = dg < 0 ? 0.0 : u2d(diag[((size_t)dg * mp.dl + i) * N + k]);
-        }
+            for (int b = 0; b < NBM; b++) w[gg][b] = 0.0;
+    }
     for (int z = 0; z < n_ct; z++) {
         double b0[NBM], b1[NBM];
-#pragma unroll
-        for (int b = 0; b < NBM; b++) {
-            if (b < mp.nb) {
-                const uint64_t *bp = mp.baby[b] + (size_t)z * bstride;
-                b0[b] = u2d(bp[(size_t)i * N + k]);
-                b1[b] = u2d(bp[(L1 + i) * N + k]);
-            }
-        }
+        load_babies<NBM>(mp, (size_t)z * bstride, o, L1 * N + o, b0, b1);
+        uint64_t *oz = inner + (size_t)z * istride + o;
 #pragma unroll
         for (int gg = 0; gg < GCH; gg++) {
             const int g = g0 + gg;
             if (g >= mp.ng) break;
-            double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-            for (int b = 0; b < NBM; b++) {
-                if (b < mp.nb) {
-                    a0 += mul_lazy(b0[b], w[gg][b], m);
-                    a1 += mul_lazy(b1[b], w[gg][b], m);
-                    if ((b & 7) == 7) a0 = reduce(a0, m), a1 = reduce(a1, m);
-                }
-            }
-            uint64_t *o = inner + (size_t)z * istride;
-            o[((size_t)g * 2 * L1 + i) * N + k] = d2u(reduce(a0, m));
-            o[((size_t)(g * 2 + 1) * L1 + i) * N + k] = d2u(reduce(a1, m));
+            oz[(size_t)g * 2 * L1 * N] = any[gg] ? d2u(mac_row<NBM>(0.0, b0, w[gg], m)) : 0;
+            oz[(size_t)(g * 2 + 1) * L1 * N] = any[gg] ? d2u(mac_row<NBM>(0.0, b1, w[gg], m)) : 0;
         }
     }
 }
@@ -623,9 +657,17 @@ hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_job
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s, int accumulate)
 {
+    if (mp.nb < 1 || mp.nb > NJ_MAX_BABY || mp.ng < 0 || mp.ng > NJ_MAX_GIANT) return hipErrorInvalidValue;
     dim3 grid((c->N + kBT - 1) / kBT, level + 1);
-    return launch(c, PROF_PMAC, 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + (2.0 + 2 * accumulate) * mp.ng),
-                  k_bsgs_mac, grid, dim3(kBT), s, mp, diag, inner, level, accumulate, c->d_info, c->log_n);
+    const double bytes = 8.0 * c->N * (level + 1) * (2.0 * mp.nb + n_diag + (2.0 + 2 * accumulate) * mp.ng);
+    if (mp.nb <= 4)
+        return launch(c, PROF_PMAC, bytes, k_bsgs_mac<4>, grid, dim3(kBT), s, mp, diag, inner, level, accumulate,
+                      c->d_info, c->log_n);
+    if (mp.nb <= 8)
+        return launch(c, PROF_PMAC, bytes, k_bsgs_mac<8>, grid, dim3(kBT), s, mp, diag, inner, level, accumulate,
+                      c->d_info, c->log_n);
+    return launch(c, PROF_PMAC, bytes, k_bsgs_mac<16>, grid, dim3(kBT), s, mp, diag, inner, level, accumulate,
+                  c->d_info, c->log_n);
 }
 
 }  // namespace nj

@@ -81,41 +81,118 @@ hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t
 
 // ------------------------------------------------------- key inner product
 
+// Key inner product terms of one key switch at output limb t: for digit j the input
+// word (the digit's own limb d when j is t's digit, else the extended digit j), read
+// through X -> X^g at src, and the two key words.  ND = number of digits: for ND > 0
+// all 3 ND loads are issued before any is used; ND = 0 is the generic loop.
+struct IpRow {
+    size_t t, ne, nk, kl;
+    int own;
+};
+
+__device__ __forceinline__ IpRow ip_row(int t, int level, int L, int alpha)
+{
+    IpRow r;
+    r.t = t;
+    r.ne = level + 1 + alpha;
+    r.nk = L + 1 + alpha;
+    r.kl = t <= level ? t : L + 1 + (t - level - 1);
+    r.own = t <= level ? t / alpha : -1;
+    return r;
+}
+
+template <int ND>
+__device__ __forceinline__ void ip_load(const IpRow &r, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
+                                        int src, int k, size_t N, uint64_t *rx, uint64_t *rb, uint64_t *ra)
+{
+#pragma unroll
+    for (int j = 0; j < ND; j++) {
+        const uint64_t *xp = j == r.own ? d + r.t * N : ext + ((size_t)j * r.ne + r.t) * N;
+        rx[j] = xp[src];
+        rb[j] = key[(((size_t)j * 2 + 0) * r.nk + r.kl) * N + k];
+        ra[j] = key[(((size_t)j * 2 + 1) * r.nk + r.kl) * N + k];
+    }
+}
+
+// a0 += sum_j x_j b_j, a1 += sum_j x_j a_j (lazy products in (-t, t), no reduction)
+template <int ND>
+__device__ __forceinline__ void ip_acc(const uint64_t *rx, const uint64_t *rb, const uint64_t *ra, double &a0,
+                                       double &a1, Mod m)
+{
+#pragma unroll
+    for (int j = 0; j < ND; j++) {
+        const double x = u2d(rx[j]);
+        a0 += mul_lazy(x, u2d(rb[j]), m);
+        a1 += mul_lazy(x, u2d(ra[j]), m);
+    }
+}
+
+// generic digit count: one digit at a time, reduced after every 8 terms (start 0)
+__device__ __forceinline__ void ip_generic(const IpRow &r, const uint64_t *ext, const uint64_t *d,
+                                           const uint64_t *key, int src, int k, size_t N, int n_digits, double &a0,
+                                           double &a1, Mod m)
+{
+    for (int j = 0; j < n_digits; j++) {
+        const uint64_t *xp = j == r.own ? d + r.t * N : ext + ((size_t)j * r.ne + r.t) * N;
+        const double x = u2d(xp[src]);
+        a0 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 0) * r.nk + r.kl) * N + k]), m);
+        a1 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 1) * r.nk + r.kl) * N + k]), m);
+        if ((j & 7) == 7) a0 = reduce(a0, m), a1 = reduce(a1, m);
+    }
+}
+
+// one key switch: (a0, a1) = sum over digits, reduced to [0, t)
+template <int ND>
+__device__ __forceinline__ void ip_one(const IpRow &r, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
+                                       int src, int k, size_t N, int n_digits, double &a0, double &a1, Mod m)
+{
+    a0 = 0.0, a1 = 0.0;
+    if constexpr (ND > 0) {
+        uint64_t rx[ND], rb[ND], ra[ND];
+        ip_load<ND>(r, ext, d, key, src, k, N, rx, rb, ra);
+        ip_acc<ND>(rx, rb, ra, a0, a1, m);
+    } else {
+        ip_generic(r, ext, d, key, src, k, N, n_digits, a0, a1, m);
+    }
+    a0 = reduce(a0, m), a1 = reduce(a1, m);
+}
+
+template <int ND>
 __global__ __launch_bounds__(kBT) void k_key_ip2(const uint64_t *ext, const uint64_t *d, const uint64_t *key,
                                                 uint64_t *u, uint32_t g, int n_digits, int level, int L, int alpha,
                                                 int nq, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN;
     const int t = blockIdx.y;
-    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
     const int pidx = t <= level ? t : nq + (t - level - 1);
-    const int kl = t <= level ? t : L + 1 + (t - level - 1);
-    const int own = t <= level ? t / alpha : -1;  // digit whose own limb this is
     const Mod m = info[pidx].m;
     const int k = blockIdx.x * kBT + threadIdx.x;
     if (k >= N) return;
+    const IpRow r = ip_row(t, level, L, alpha);
     const int src = g == 1u ? k : galois_src2(k, g, logN);
-    double acc0 = 0.0, acc1 = 0.0;
-    for (int j = 0; j < n_digits; j++) {
-        const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
-        double x = u2d(xp[src]);
-        double kb = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
-        double ka = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
-        acc0 += mul_lazy(x, kb, m);
-        acc1 += mul_lazy(x, ka, m);
-        if ((j & 7) == 7) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
-    }
-    u[(size_t)t * N + k] = d2u(reduce(acc0, m));
-    u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+    double a0, a1;
+    ip_one<ND>(r, ext, d, key, src, k, N, n_digits, a0, a1, m);
+    u[(size_t)t * N + k] = d2u(a0);
+    u[(r.ne + t) * N + k] = d2u(a1);
 }
+
+// returns EXPR with the compile-time digit count ND: 1..4 unrolled, 0 = generic loop
+#define NJ_ND_SWITCH(nd, EXPR)                   \
+    switch (nd) {                                \
+    case 1: { constexpr int ND = 1; return EXPR; } \
+    case 2: { constexpr int ND = 2; return EXPR; } \
+    case 3: { constexpr int ND = 3; return EXPR; } \
+    case 4: { constexpr int ND = 4; return EXPR; } \
+    default: { constexpr int ND = 0; return EXPR; } \
+    }
 
 hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
                           uint32_t g, uint64_t *u, hipStream_t s)
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
     dim3 grid((c->N + kBT - 1) / kBT, ne);
-    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), k_key_ip2, grid, dim3(kBT), s, ext, d, key, u, g,
-                  nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), k_key_ip2<ND>, grid, dim3(kBT), s, ext,
+                            d, key, u, g, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n));
 }
 
 // ------------------------------------------------------------------ ModDown
@@ -293,64 +370,75 @@ hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const Bcon
 }
 
 // key inner products of many jobs (blockIdx.z = job); u of job z at u_base + z * 2 ne N
+template <int ND>
 __global__ __launch_bounds__(kBT) void k_key_ip_multi(KeyJobs kj, uint64_t *u_base, int n_digits, int level, int L,
                                                      int alpha, int nq, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN;
     const int t = blockIdx.y, z = blockIdx.z;
-    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
     const int pidx = t <= level ? t : nq + (t - level - 1);
-    const int kl = t <= level ? t : L + 1 + (t - level - 1);
-    const int own = t <= level ? t / alpha : -1;
     const Mod m = info[pidx].m;
     const int k = blockIdx.x * kBT + threadIdx.x;
     if (k >= N) return;
+    const IpRow r = ip_row(t, level, L, alpha);
     const uint32_t g = kj.g[z];
-    const uint64_t *ext = kj.ext[z], *d = kj.d[z], *key = kj.key[z];
     const int src = g == 1u ? k : galois_src2(k, g, logN);
-    double acc0 = 0.0, acc1 = 0.0;
-    for (int j = 0; j < n_digits; j++) {
-        const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
-        double x = u2d(xp[src]);
-        double kb = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
-        double ka = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
-        acc0 += mul_lazy(x, kb, m);
-        acc1 += mul_lazy(x, ka, m);
-        if ((j & 7) == 7) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
-    }
-    uint64_t *u = u_base + (size_t)z * 2 * ne * N;
-    u[(size_t)t * N + k] = d2u(reduce(acc0, m));
-    u[((size_t)ne + t) * N + k] = d2u(reduce(acc1, m));
+    double a0, a1;
+    ip_one<ND>(r, kj.ext[z], kj.d[z], kj.key[z], src, k, N, n_digits, a0, a1, m);
+    uint64_t *u = u_base + (size_t)z * 2 * r.ne * N;
+    u[(size_t)t * N + k] = d2u(a0);
+    u[(r.ne + t) * N + k] = d2u(a1);
 }
 
 // lazy giant steps: sum over the jobs (each its own key) of the key inner products,
 // written to u [2][ne][N] or added to it (accumulate)
+// For ND in 1..3 two jobs are loaded together (6 ND words in flight) and the running
+// sum, in [0, t) after each reduction, takes at most 2 ND <= 6 lazy terms before the
+// next; for ND = 4 one job at a time (4 terms); the generic loop reduces every 8 terms.
+template <int ND>
 __global__ __launch_bounds__(kBT) void k_key_ip_sum(KeyJobs kj, int n_jobs, uint64_t *u, int accumulate, int n_digits,
                                                    int level, int L, int alpha, int nq, const PrimeInfo *info,
                                                    int logN)
 {
     const int N = 1 << logN;
     const int t = blockIdx.y;
-    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
     const int pidx = t <= level ? t : nq + (t - level - 1);
-    const int kl = t <= level ? t : L + 1 + (t - level - 1);
-    const int own = t <= level ? t / alpha : -1;
     const Mod m = info[pidx].m;
     const int k = blockIdx.x * kBT + threadIdx.x;
     if (k >= N) return;
-    const size_t o0 = (size_t)t * N + k, o1 = ((size_t)ne + t) * N + k;
+    const IpRow r = ip_row(t, level, L, alpha);
+    const size_t o0 = (size_t)t * N + k, o1 = (r.ne + t) * N + k;
     double acc0 = accumulate ? u2d(u[o0]) : 0.0, acc1 = accumulate ? u2d(u[o1]) : 0.0;
-    int cnt = accumulate ? 1 : 0;
-    for (int z = 0; z < n_jobs; z++) {
-        const uint32_t g = kj.g[z];
-        const uint64_t *ext = kj.ext[z], *d = kj.d[z], *key = kj.key[z];
-        const int src = g == 1u ? k : galois_src2(k, g, logN);
-        for (int j = 0; j < n_digits; j++) {
-            const uint64_t *xp = j == own ? d + (size_t)t * N : ext + ((size_t)j * ne + t) * N;
-            const double x = u2d(xp[src]);
-            acc0 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]), m);
-            acc1 += mul_lazy(x, u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]), m);
-            if ((++cnt & 7) == 0) acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+    if constexpr (ND > 0) {
+        constexpr int ZU = ND <= 3 ? 2 : 1;
+        int z = 0;
+        for (; z + ZU <= n_jobs; z += ZU) {
+            uint64_t rx[ZU][ND], rb[ZU][ND], ra[ZU][ND];
+#pragma unroll
+            for (int q = 0; q < ZU; q++) {
+                const uint32_t g = kj.g[z + q];
+                const int src = g == 1u ? k : galois_src2(k, g, logN);
+                ip_load<ND>(r, kj.ext[z + q], kj.d[z + q], kj.key[z + q], src, k, N, rx[q], rb[q], ra[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < ZU; q++) ip_acc<ND>(rx[q], rb[q], ra[q], acc0, acc1, m);
+            acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+        }
+        for (; z < n_jobs; z++) {
+            const uint32_t g = kj.g[z];
+            const int src = g == 1u ? k : galois_src2(k, g, logN);
+            uint64_t rx[ND], rb[ND], ra[ND];
+            ip_load<ND>(r, kj.ext[z], kj.d[z], kj.key[z], src, k, N, rx, rb, ra);
+            ip_acc<ND>(rx, rb, ra, acc0, acc1, m);
+            acc0 = reduce(acc0, m), acc1 = reduce(acc1, m);
+        }
+    } else {
+        for (int z = 0; z < n_jobs; z++) {
+            const uint32_t g = kj.g[z];
+            const int src = g == 1u ? k : galois_src2(k, g, logN);
+            double a0, a1;
+            ip_one<0>(r, kj.ext[z], kj.d[z], kj.key[z], src, k, N, n_digits, a0, a1, m);
+            acc0 = add_mod(reduce(acc0, m), a0, m), acc1 = add_mod(reduce(acc1, m), a1, m);
         }
     }
     u[o0] = d2u(reduce(acc0, m));
@@ -362,8 +450,9 @@ hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int 
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
     dim3 grid((c->N + kBT - 1) / kBT, ne);
-    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd * n_jobs + 2.0 * (1 + accumulate)), k_key_ip_sum, grid,
-                  dim3(kBT), s, kj, n_jobs, u, accumulate, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd * n_jobs + 2.0 * (1 + accumulate)),
+                            k_key_ip_sum<ND>, grid, dim3(kBT), s, kj, n_jobs, u, accumulate, nd, level, c->L,
+                            c->alpha, c->n_q, c->d_info, c->log_n));
 }
 
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
@@ -371,8 +460,8 @@ hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, in
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
     dim3 grid((c->N + kBT - 1) / kBT, ne, n_jobs);
-    return launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0) * n_jobs, k_key_ip_multi, grid, dim3(kBT), s, kj,
-                  u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n);
+    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0) * n_jobs, k_key_ip_multi<ND>, grid,
+                            dim3(kBT), s, kj, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n));
 }
 
 // ModDown combine of many jobs.  sum == 0: job z writes out[z] (blockIdx.z = 2 job + half),

@@ -22,6 +22,13 @@ constexpr int kNT = 256;
 
 __device__ __forceinline__ int pad16(int x) { return x + (x >> 4); }
 
+// Forward rounds are lazy: a round takes canonical words, runs its 4 stages without
+// correction and reduces once at the end.  With t < 2^50 the lazy product of a word
+// below B t in magnitude lies within (1/2 + 3B/8) t (the quotient estimate is off by
+// at most 1/2 + 3 ulp-relative errors of a value below B 2^50), so the bound grows
+// 1 -> 1.875 -> 3.08 -> 4.73 -> 7.01 over 4 stages: every intermediate is an integer
+// below 2^53, computed exactly.
+
 // one round of 4 forward stages on 16 registers (strides t0 .. t0/8 within the tile)
 __device__ __forceinline__ void ct_round(double v[16], int t0, int hi, int tile, int logN1, const double *W, int N,
                                          Mod m)
@@ -36,11 +43,13 @@ __device__ __forceinline__ void ct_round(double v[16], int t0, int hi, int tile,
         for (int k = 0; k < 16; k++) {
             if (k & step) continue;
             const double w = W[base + (k >> (4 - s))];
-            const double U = v[k], V = mul_lazy(v[k + step], w, m);  // V in (-t, t)
-            v[k] = corr(U + V, m);
-            v[k + step] = corr(U - V, m);
+            const double U = v[k], V = mul_lazy(v[k + step], w, m);
+            v[k] = U + V;
+            v[k + step] = U - V;
         }
     }
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = reduce(v[k], m);
 }
 
 // one round of 4 inverse stages (strides t0/8 .. t0)
@@ -163,10 +172,13 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
                 if (r & tr) continue;
                 const double w = W[mm + r / (2 * tr)];
                 const double U = v[r], V = mul_lazy(v[r + tr], w, m);
-                v[r] = corr(U + V, m);
-                v[r + tr] = corr(U - V, m);
+                v[r] = U + V;
+                v[r + tr] = U - V;
             }
         }
+        // at most 4 lazy stages (N1 <= 16)
+#pragma unroll
+        for (int r = 0; r < N1; r++) v[r] = reduce(v[r], m);
     } else {
 #pragma unroll
         for (int h = N1 / 2; h >= 1; h >>= 1) {

@@ -10,7 +10,7 @@
 #include "../../include/neujeans.h"
 #include "modarith.h"
 
-#define NJ_MAX_LIMBS 128  // limbs addressed by one launch
+#define NJ_MAX_LIMBS 256  // limbs addressed by one launch (3 KiB limb table in the kernel arguments)
 
 namespace nj {
 

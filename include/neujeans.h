@@ -374,7 +374,8 @@ nj_status nj_mlp_predict(nj_mlp *mlp, const float *X, int n, float *out);
  * and accumulates each launch's algorithmic HBM bytes (every input word read once,
  * every output word written once).  kind: 0/1 NTT 4096-word tile pass forward/inverse,
  * 2/3 NTT column pass forward/inverse, 4 basis conversion, 5 key inner product,
- * 6 plaintext multiply-accumulate, 7 other. */
+ * 6 plaintext multiply-accumulate, 7 other, 8 forward tile pass fused with the
+ * ModDown combine. */
 nj_status nj_prof_enable(nj_ctx *ctx, int on);
 /* Synchronises the device, then returns launches, total ms and total bytes of `kind`
  * recorded since the last reset; reset = 1 clears the records. */

@@ -114,7 +114,7 @@ _SIGS = {
 
 # live-profiled kernel families (nj_prof_read kinds) and the kernel names rocprofv3 reports for them
 PROF_KERNELS = {0: "k_ntt_tile<false>", 1: "k_ntt_tile<true>", 2: "k_ntt_col<false>", 3: "k_ntt_col<true>",
-                4: "k_bconv", 5: "k_key_ip", 6: "k_pmac", 7: "other"}
+                4: "k_bconv", 5: "k_key_ip", 6: "k_pmac", 7: "other", 8: "k_ntt_tile_md"}
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res

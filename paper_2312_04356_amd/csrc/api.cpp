@@ -263,6 +263,10 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     BconvPtrs jp;
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
     NJ_HIP(launch_bconv_multi(c, sh, jp, 2 * K, s));
+    if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
+        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, s));
+        return NJ_OK;
+    }
     LimbTab lq;
     lq.n = 0;
     for (int h = 0; h < 2 * K; h++)

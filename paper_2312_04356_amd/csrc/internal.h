@@ -88,6 +88,18 @@ struct KeyJobs {
     const uint64_t *ext[NJ_MAX_JOBS], *d[NJ_MAX_JOBS], *key[NJ_MAX_JOBS];
     uint32_t g[NJ_MAX_JOBS];
 };
+__device__ __forceinline__ uint32_t brev_n(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
+
+// Evaluation-form word k holds a(psi^(2 rev(k) + 1)); the word that X -> X^g moves to
+// position k is the one at exponent (2 rev(k) + 1) g mod 2N.
+__device__ __forceinline__ int galois_src2(int k, uint32_t g, int logN)
+{
+    const uint32_t N = 1u << logN;
+    uint32_t e = 2u * brev_n((uint32_t)k, logN) + 1u;
+    uint32_t eg = (uint32_t)(((uint64_t)e * g) & (2u * N - 1u));
+    return (int)brev_n((eg - 1u) >> 1, logN);
+}
+
 struct MdJobs {
     const uint64_t *add[NJ_MAX_JOBS];
     uint32_t g_add[NJ_MAX_JOBS];
@@ -145,6 +157,7 @@ enum ProfKind {
     PROF_KEYIP,
     PROF_PMAC,
     PROF_OTHER,
+    PROF_NTT_MD,  // forward tile pass fused with the ModDown combine
     PROF_KINDS
 };
 
@@ -236,6 +249,8 @@ namespace nj {
 // ---------------------------------------------------------------- kernels.hip
 hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s,
                       const uint64_t *src = nullptr);
+hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
+                              const MdJobs &mj, int acc, hipStream_t s);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form

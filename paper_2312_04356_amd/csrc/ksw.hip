@@ -19,15 +19,6 @@ namespace nj {
 
 constexpr int kBT = 256;
 
-__device__ __forceinline__ uint32_t brev_n(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
-
-__device__ __forceinline__ int galois_src2(int k, uint32_t g, int logN)
-{
-    const uint32_t N = 1u << logN;
-    uint32_t e = 2u * brev_n((uint32_t)k, logN) + 1u;
-    uint32_t eg = (uint32_t)(((uint64_t)e * g) & (2u * N - 1u));
-    return (int)brev_n((eg - 1u) >> 1, logN);
-}
 
 // ------------------------------------------------------------ basis conversion
 

@@ -13,6 +13,8 @@
 // A round covering strides t0, t0/2, t0/4, t0/8 gives thread (lo, hi) the words
 // x_k = lo + (t0/8) k + 2 t0 hi, k < 16; at stride t0/2^s the pair (k, k + 8>>s)
 // belongs to butterfly block hi 2^s + (k >> (4-s)) of the tile.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nj {
@@ -73,6 +75,35 @@ __device__ __forceinline__ void gs_round(double v[16], int t0, int hi, int tile,
     }
 }
 
+// The last 12 forward stages of one 4096-word tile: v holds words tid + 256 k on
+// entry; on return the transformed tile is in s (word x at pad16(x)), after a barrier.
+__device__ __forceinline__ void tile_forward(double v[16], double *s, int tid, int tile, int logN1, const double *W,
+                                             int N, Mod m)
+{
+    // round 0: strides 2048..256, thread tid owns x = tid + 256 k
+    ct_round(v, 2048, 0, tile, logN1, W, N, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+    __syncthreads();
+    // round 1: strides 128..16, (lo, hi) = (tid & 15, tid >> 4): x = lo + 16 k + 256 hi
+    {
+        const int lo = tid & 15, hi = tid >> 4;
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+        ct_round(v, 128, hi, tile, logN1, W, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+    }
+    __syncthreads();
+    // round 2: strides 8..1, thread owns x = 16 tid + k
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+    ct_round(v, 8, tid, tile, logN1, W, N, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+    __syncthreads();
+}
+
 // rows pass: last 12 stages on 4096-word tiles.  grid (N/4096, limbs)
 template <bool INV>
 __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
@@ -89,30 +120,9 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
     const double *W = tw + (size_t)pidx * N;
     double v[16];
     if (!INV) {
-        // round 0: strides 2048..256, thread tid owns x = tid + 256 k
 #pragma unroll
         for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
-        ct_round(v, 2048, 0, tile, logN1, W, N, m);
-#pragma unroll
-        for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
-        __syncthreads();
-        // round 1: strides 128..16, (lo, hi) = (tid & 15, tid >> 4): x = lo + 16 k + 256 hi
-        {
-            const int lo = tid & 15, hi = tid >> 4;
-#pragma unroll
-            for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
-            ct_round(v, 128, hi, tile, logN1, W, N, m);
-#pragma unroll
-            for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
-        }
-        __syncthreads();
-        // round 2: strides 8..1, thread owns x = 16 tid + k
-#pragma unroll
-        for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
-        ct_round(v, 8, tid, tile, logN1, W, N, m);
-#pragma unroll
-        for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
-        __syncthreads();
+        tile_forward(v, s, tid, tile, logN1, W, N, m);
 #pragma unroll
         for (int k = 0; k < 16; k++) out[tid + 256 * k] = d2u(s[pad16(tid + 256 * k)]);
     } else {
@@ -199,6 +209,46 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
     for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(v[r]);
 }
 
+// ModDown of K key switches, finished inside the forward transform's tile pass.  The
+// converted limbs conv [K][2][l+1][N] (coefficient form, column pass already applied)
+// are transformed tile by tile and, instead of being stored, combined at once:
+// out_z[p][i] = (u_z[p][i] - NTT(conv_z[p][i])) P^-1 (+ c0 of job z read through
+// X -> X^g_add[z] for p = 0) (+ the previous out_z when acc), with u_z at
+// u_base + z 2 ne N.  grid (N/4096, 2 K (l+1)): limb w = (2 z + p)(l+1) + i.
+__global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const uint64_t *u_base, MdJobs mj, int acc,
+                                                     int level, int ne, const double *pinv, const double *tw,
+                                                     const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1;
+    const int w = blockIdx.y, h = w / L1, i = w - h * L1, z = h >> 1, p = h & 1;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const Mod m = info[i].m;
+    const double *W = tw + (size_t)i * N;
+    const size_t t0 = (size_t)tile * kT;
+    const uint64_t *in = conv + (size_t)w * N + t0;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
+    tile_forward(v, s, tid, tile, logN1, W, N, m);
+    const uint64_t *u = u_base + ((size_t)z * 2 * ne + (size_t)p * ne + i) * N + t0;
+    const uint64_t *add = p == 0 ? mj.add[z] : nullptr;
+    const uint32_t g = mj.g_add[z];
+    uint64_t *out = mj.out[z] + ((size_t)p * L1 + i) * N + t0;
+    const double pv = pinv[i];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int x = tid + 256 * k;
+        double t = mul_canon(sub_mod(u2d(u[x]), s[pad16(x)], m), pv, m);
+        if (add) {
+            const int kk = (int)t0 + x;
+            t = add_mod(t, u2d(add[(size_t)i * N + (g <= 1u ? kk : galois_src2(kk, g, logN))]), m);
+        }
+        if (acc) t = add_mod(t, u2d(out[x]), m);
+        out[x] = d2u(t);
+    }
+}
+
 template <bool INV>
 static hipError_t launch_cols(const nj_ctx *c, int kind, double bytes, int N1, dim3 grid, hipStream_t s,
                               uint64_t *data, const uint64_t *src, const LimbTab &lt, const double *tw,
@@ -234,6 +284,28 @@ hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src,
     e = launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, gt, dim3(kNT), s, data, src, lt, tw, c->d_info, c->log_n);
     if (e != hipSuccess || N1 == 1) return e;
     return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
+}
+
+// ModDown combine of K jobs fused into the forward transform of their converted
+// limbs (N >= 4096); same results as the transform followed by the combine.
+hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
+                              const MdJobs &mj, int acc, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1;
+    if (N < kT || K < 1 || K > NJ_MAX_JOBS) return hipErrorInvalidValue;
+    if (N1 > 1) {
+        LimbTab lt;
+        for (int b = 0; b < n; b += NJ_MAX_LIMBS) {
+            lt.n = std::min(NJ_MAX_LIMBS, n - b);
+            for (int j = 0; j < lt.n; j++) lt.pidx[j] = (b + j) % L1, lt.off[j] = b + j, lt.soff[j] = 0;
+            hipError_t e = launch_cols<false>(c, PROF_NTT_COL, 16.0 * N * lt.n, N1, dim3(kT / kNT, lt.n), s, conv,
+                                              nullptr, lt, c->d_tw, c->d_info, c->log_n);
+            if (e != hipSuccess) return e;
+        }
+    }
+    const double bytes = 8.0 * N * (n * 3.0 + K * L1 + (acc ? n : 0));
+    return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
+                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n);
 }
 
 }  // namespace nj

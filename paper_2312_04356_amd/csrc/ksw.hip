@@ -307,8 +307,10 @@ __global__ __launch_bounds__(kBT) void k_bsgs_mac(MacPlan mp, const uint64_t *di
 // --------------------------------------------------- many key switches at once
 //
 // k_bconv_multi: basis conversion for many (job, digit) pairs sharing the digit
-// tables (blockIdx.z = job * nd + digit).  MMAX bounds the digit size; smaller
-// digits are predicated, so the scaled residues keep static register indices.
+// tables (blockIdx.z = job * nd + digit).  MMAX bounds the digit size: all MMAX input
+// loads are issued at once from in-bounds limbs (slots past the digit re-read its last
+// limb and are zeroed after scaling), and the block's chunk of 8 targets is unrolled
+// (targets past n_out predicated), so the scalar table reads of all 8 can be batched.
 template <int MMAX>
 __global__ __launch_bounds__(kBT) void k_bconv_multi(BconvShared sh, BconvPtrs jp, const PrimeInfo *info, int logN)
 {
@@ -320,26 +322,29 @@ __global__ __launch_bounds__(kBT) void k_bconv_multi(BconvShared sh, BconvPtrs j
     const uint64_t *in = jp.in[job];
     uint64_t *out = jp.out[job];
     const double *hat_inv = sh.hat_inv[j], *hat = sh.hat[j];
+    uint64_t raw[MMAX];
+#pragma unroll
+    for (int a = 0; a < MMAX; a++) raw[a] = in[(size_t)(sh.in_off0[j] + (a < m ? a : m - 1)) * N + k];
     double v[MMAX];
 #pragma unroll
     for (int a = 0; a < MMAX; a++) {
-        if (a < m) {
-            const Mod ma = info[sh.in_pidx[j][a]].m;
-            v[a] = mul_canon(u2d(in[(size_t)(sh.in_off0[j] + a) * N + k]), hat_inv[a], ma);
-        }
+        const int aa = a < m ? a : m - 1;
+        const double x = mul_canon(u2d(raw[a]), hat_inv[aa], info[sh.in_pidx[j][aa]].m);
+        v[a] = a < m ? x : 0.0;
     }
-    const int o1 = min(o0 + 8, n_out);
-    for (int o = o0; o < o1; o++) {
-        const Mod mt = info[sh.out_pidx[j][o]].m;
-        double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < MMAX; a++) {
-            if (a < m) {
-                acc += mul_lazy(v[a], hat[a * n_out + o], mt);
+    for (int q = 0; q < 8; q++) {
+        const int o = o0 + q;
+        if (o < n_out) {
+            const Mod mt = info[sh.out_pidx[j][o]].m;
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < MMAX; a++) {
+                acc += mul_lazy(v[a], hat[(a < m ? a : 0) * n_out + o], mt);
                 if ((a & 7) == 7) acc = reduce(acc, mt);
             }
+            out[(size_t)sh.out_off[j][o] * N + k] = d2u(reduce(acc, mt));
         }
-        out[(size_t)sh.out_off[j][o] * N + k] = d2u(reduce(acc, mt));
     }
 }
 

@@ -180,6 +180,12 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride)
 {
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
+    // N >= 8192: the conversion's input factors ride on the inverse transform, and the
+    // conversion runs fused with its outputs' column pass
+    const bool fused = N >= 8192 && c->alpha <= 8;
+    auto intt = [&](const LimbTab &t) {
+        return fused ? launch_intt_scaled(c, M.coef, d, t, c->d_upscale[l], s) : launch_ntt(c, M.coef, t, true, s, d);
+    };
     if (dstride < 0) dstride = l + 1;
     LimbTab lt;
     lt.n = 0;
@@ -187,11 +193,11 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
         for (int i = 0; i <= l; i++) {
             lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = z * dstride + i;
             if (++lt.n == NJ_MAX_LIMBS) {
-                NJ_HIP(launch_ntt(c, M.coef, lt, true, s, d));
+                NJ_HIP(intt(lt));
                 lt.n = 0;
             }
         }
-    NJ_HIP(launch_ntt(c, M.coef, lt, true, s, d));
+    NJ_HIP(intt(lt));
     for (int j0 = 0; j0 < nd; j0 += 4) {
         BconvShared sh;
         sh.nd = std::min(4, nd - j0);
@@ -205,8 +211,9 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
         }
         BconvPtrs jp;
         for (int z = 0; z < K; z++) jp.in[z] = M.coef + (size_t)z * (l + 1) * N, jp.out[z] = M.ext + (size_t)z * nd * ne * N;
-        NJ_HIP(launch_bconv_multi(c, sh, jp, K, s));
+        NJ_HIP(fused ? launch_bconv_col(c, sh, jp, K, s) : launch_bconv_multi(c, sh, jp, K, s));
     }
+    auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.ext, t, s) : launch_ntt(c, M.ext, t, false, s); };
     lt.n = 0;
     for (int z = 0; z < K; z++)
         for (int j = 0; j < nd; j++) {
@@ -215,12 +222,12 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
                 lt.pidx[lt.n] = bt.out_pidx[o];
                 lt.off[lt.n] = (z * nd + j) * ne + bt.out_limb[o];
                 if (++lt.n == NJ_MAX_LIMBS) {
-                    NJ_HIP(launch_ntt(c, M.ext, lt, false, s));
+                    NJ_HIP(ntt(lt));
                     lt.n = 0;
                 }
             }
         }
-    NJ_HIP(launch_ntt(c, M.ext, lt, false, s));
+    NJ_HIP(ntt(lt));
     return NJ_OK;
 }
 
@@ -241,6 +248,10 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
                   hipStream_t s)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
+    const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
+    auto intt = [&](const LimbTab &t) {
+        return fused ? launch_intt_scaled(c, M.pc, M.u, t, c->d_downscale, s) : launch_ntt(c, M.pc, t, true, s, M.u);
+    };
     LimbTab lp;
     lp.n = 0;
     for (int z = 0; z < K; z++)
@@ -249,11 +260,11 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
                 lp.pidx[lp.n] = c->n_q + a, lp.off[lp.n] = (2 * z + p) * al + a;
                 lp.soff[lp.n] = (2 * z + p) * ne + l + 1 + a;
                 if (++lp.n == NJ_MAX_LIMBS) {
-                    NJ_HIP(launch_ntt(c, M.pc, lp, true, s, M.u));
+                    NJ_HIP(intt(lp));
                     lp.n = 0;
                 }
             }
-    NJ_HIP(launch_ntt(c, M.pc, lp, true, s, M.u));
+    NJ_HIP(intt(lp));
     const BconvTab &bt = c->moddown[l];
     BconvShared sh;
     sh.nd = 1;
@@ -262,22 +273,23 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     for (int o = 0; o < bt.n_out; o++) sh.out_pidx[0][o] = bt.out_pidx[o], sh.out_off[0][o] = o;
     BconvPtrs jp;
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
-    NJ_HIP(launch_bconv_multi(c, sh, jp, 2 * K, s));
+    NJ_HIP(fused ? launch_bconv_col(c, sh, jp, 2 * K, s) : launch_bconv_multi(c, sh, jp, 2 * K, s));
     if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
-        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, s));
+        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s));
         return NJ_OK;
     }
+    auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.conv, t, s) : launch_ntt(c, M.conv, t, false, s); };
     LimbTab lq;
     lq.n = 0;
     for (int h = 0; h < 2 * K; h++)
         for (int i = 0; i <= l; i++) {
             lq.pidx[lq.n] = i, lq.off[lq.n] = h * (l + 1) + i;
             if (++lq.n == NJ_MAX_LIMBS) {
-                NJ_HIP(launch_ntt(c, M.conv, lq, false, s));
+                NJ_HIP(ntt(lq));
                 lq.n = 0;
             }
         }
-    NJ_HIP(launch_ntt(c, M.conv, lq, false, s));
+    NJ_HIP(ntt(lq));
     NJ_HIP(launch_moddown_multi(c, l, mj, K, sum, M.u, M.conv, acc, s));
     return NJ_OK;
 }

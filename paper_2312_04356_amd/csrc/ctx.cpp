@@ -278,6 +278,37 @@ nj_status nj_ctx_create(const nj_params *P, nj_ctx **out)
             return hip_fail(e, "nj_ctx_create: ModDown tables");
         }
     }
+    // basis-conversion input factors folded into the inverse transforms' N^-1
+    {
+        auto fac = [&](const std::vector<int> &digit, int a) {  // N^-1 (D/q_a)^-1 mod q_a
+            const uint64_t qa = c->primes[digit[a]];
+            uint64_t prod = 1;
+            for (size_t b = 0; b < digit.size(); b++)
+                if ((int)b != a) prod = hmul(prod, c->primes[digit[b]] % qa, qa);
+            return (double)hmul(hinv((uint64_t)c->N % qa, qa), hinv(prod, qa), qa);
+        };
+        c->d_upscale.assign(c->n_q, nullptr);
+        for (int l = 0; l <= c->L; l++) {
+            std::vector<double> sc(l + 1);
+            for (int j = 0; j * c->alpha <= l; j++) {
+                std::vector<int> digit;
+                for (int a = j * c->alpha; a < std::min((j + 1) * c->alpha, l + 1); a++) digit.push_back(a);
+                for (size_t a = 0; a < digit.size(); a++) sc[digit[a]] = fac(digit, (int)a);
+            }
+            if ((e = upload(&c->d_upscale[l], sc)) != hipSuccess) {
+                nj_ctx_destroy(c);
+                return hip_fail(e, "nj_ctx_create: ModUp factors");
+            }
+        }
+        std::vector<int> pd;
+        for (int k = 0; k < c->alpha; k++) pd.push_back(c->n_q + k);
+        std::vector<double> sc(np, 0.0);
+        for (int k = 0; k < c->alpha; k++) sc[c->n_q + k] = fac(pd, k);
+        if ((e = upload(&c->d_downscale, sc)) != hipSuccess) {
+            nj_ctx_destroy(c);
+            return hip_fail(e, "nj_ctx_create: ModDown factors");
+        }
+    }
     // P mod every prime, P^-1 mod q_i, q_l^-1 mod q_i
     std::vector<double> pinv(2 * c->n_q), qlinv((size_t)c->n_q * c->n_q, 0.0), qlinvq((size_t)c->n_q * c->n_q, 0.0);
     c->pmod.assign(np, 0.0);
@@ -325,6 +356,8 @@ void nj_ctx_destroy(nj_ctx *c)
     for (auto &lv : c->modup)
         for (auto &b : lv) fr(b.hat_inv), fr(b.hat);
     for (auto &b : c->moddown) fr(b.hat_inv), fr(b.hat);
+    for (auto *p : c->d_upscale) fr(p);
+    fr(c->d_downscale);
     for (auto &kv : c->keys) fr(kv.second.d);
     for (auto *k : c->timing_keys) fr(k);
     fr(c->scratch.buf);

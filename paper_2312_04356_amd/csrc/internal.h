@@ -174,6 +174,10 @@ struct nj_ctx {
     // ModUp tables [level][digit]; ModDown tables [level]
     std::vector<std::vector<nj::BconvTab>> modup;
     std::vector<nj::BconvTab> moddown;
+    // per level: device [l+1] N^-1 (D_j/q_i)^-1 mod q_i (i in digit j), the ModUp inputs'
+    // factor folded into their inverse transform; and [n_primes] N^-1 (P/p_a)^-1 mod p_a
+    std::vector<double *> d_upscale;
+    double *d_downscale = nullptr;
     std::vector<double> pinv_q;   // P^{-1} mod q_i (host)
     std::vector<double> pmod;     // P mod every prime (host), 0 for the p's
     double *d_pinv = nullptr, *d_pinvq = nullptr;  // [n_q] P^{-1} mod q_i and companion
@@ -249,8 +253,12 @@ namespace nj {
 // ---------------------------------------------------------------- kernels.hip
 hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s,
                       const uint64_t *src = nullptr);
+hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
+                              const double *scale, hipStream_t s);
+hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);
+hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
-                              const MdJobs &mj, int acc, hipStream_t s);
+                              const MdJobs &mj, int acc, int cols_done, hipStream_t s);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form

@@ -36,16 +36,19 @@ __global__ __launch_bounds__(kBT) void k_bconv_batch(BconvBatch bb, const PrimeI
         const Mod ma = info[jb.in_pidx[a]].m;
         v[a] = mul_canon(u2d(jb.in[(size_t)jb.in_off[a] * N + k]), jb.hat_inv[a], ma);
     }
-    const int o1 = min(o0 + 8, jb.n_out);
-    for (int o = o0; o < o1; o++) {
-        const Mod mt = info[jb.out_pidx[o]].m;
-        double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; a++) {
-            acc += mul_lazy(v[a], jb.hat[a * jb.n_out + o], mt);  // each term in (-t, t)
-            if ((a & 7) == 7) acc = reduce(acc, mt);
+    for (int q = 0; q < 8; q++) {  // the block's chunk of 8 targets, unrolled
+        const int o = o0 + q;
+        if (o < jb.n_out) {
+            const Mod mt = info[jb.out_pidx[o]].m;
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < M; a++) {
+                acc += mul_lazy(v[a], jb.hat[a * jb.n_out + o], mt);  // each term in (-t, t)
+                if ((a & 7) == 7) acc = reduce(acc, mt);
+            }
+            jb.out[(size_t)jb.out_off[o] * N + k] = d2u(reduce(acc, mt));
         }
-        jb.out[(size_t)jb.out_off[o] * N + k] = d2u(reduce(acc, mt));
     }
 }
 

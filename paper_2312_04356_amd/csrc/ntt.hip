@@ -156,10 +156,33 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
     }
 }
 
-// columns pass: first log2(N1) stages, one column of N1 words per thread.  grid (4096/256, limbs)
+// The first log2(N1) forward stages on one column of N1 canonical words (lazy, one
+// reduction at the end: at most 4 stages).
+template <int N1>
+__device__ __forceinline__ void col_forward(double v[N1], const double *W, Mod m)
+{
+#pragma unroll
+    for (int mm = 1; mm < N1; mm <<= 1) {
+        const int tr = N1 / (2 * mm);
+#pragma unroll
+        for (int r = 0; r < N1; r++) {
+            if (r & tr) continue;
+            const double w = W[mm + r / (2 * tr)];
+            const double U = v[r], V = mul_lazy(v[r + tr], w, m);
+            v[r] = U + V;
+            v[r + tr] = U - V;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < N1; r++) v[r] = reduce(v[r], m);
+}
+
+// columns pass: first log2(N1) stages, one column of N1 words per thread.  grid (4096/256, limbs).
+// The inverse ends with the factor N^-1, or scale[pidx] when a scale table is given
+// (N^-1 times a basis conversion's input factor, so the conversion need not apply it).
 template <int N1, bool INV>
 __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
-                                                 const PrimeInfo *info, int logN)
+                                                 const PrimeInfo *info, int logN, const double *scale)
 {
     const int N = 1 << logN;
     const int limb = blockIdx.y, pidx = lt.pidx[limb];
@@ -174,21 +197,7 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
 #pragma unroll
     for (int r = 0; r < N1; r++) v[r] = u2d(in[(size_t)r * kT]);
     if (!INV) {
-#pragma unroll
-        for (int mm = 1; mm < N1; mm <<= 1) {
-            const int tr = N1 / (2 * mm);
-#pragma unroll
-            for (int r = 0; r < N1; r++) {
-                if (r & tr) continue;
-                const double w = W[mm + r / (2 * tr)];
-                const double U = v[r], V = mul_lazy(v[r + tr], w, m);
-                v[r] = U + V;
-                v[r + tr] = U - V;
-            }
-        }
-        // at most 4 lazy stages (N1 <= 16)
-#pragma unroll
-        for (int r = 0; r < N1; r++) v[r] = reduce(v[r], m);
+        col_forward<N1>(v, W, m);
     } else {
 #pragma unroll
         for (int h = N1 / 2; h >= 1; h >>= 1) {
@@ -202,11 +211,68 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
                 v[r + tr] = corr(mul_lazy(U - V, w, m), m);
             }
         }
+        const double sc = scale ? scale[pidx] : pi.ninv;
 #pragma unroll
-        for (int r = 0; r < N1; r++) v[r] = mul_canon(v[r], pi.ninv, m);
+        for (int r = 0; r < N1; r++) v[r] = mul_canon(v[r], sc, m);
     }
 #pragma unroll
     for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(v[r]);
+}
+
+// Basis conversion fused with the first log2(N1) forward stages of its outputs (the
+// column pass).  Inputs are coefficient-form limbs already multiplied by
+// (D/q_a)^-1 (folded into their inverse transform's N^-1), so each output word is
+// y_t = sum_a x_a (D/q_a) mod t; the converted limbs are never stored before their
+// column pass.  Thread = one column (N1 words at stride 4096) of two targets o0, o0+1
+// of (job, digit) blockIdx.z = job * nd + digit; grid (4096/256, ceil(n_out/2), jobs nd).
+// Input slots past the digit size re-read its last limb with a zero factor.
+template <int MMAX, int N1>
+__global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp, const double *tw,
+                                                   const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN;
+    const int job = blockIdx.z / sh.nd, j = blockIdx.z % sh.nd;
+    const int c = blockIdx.x * kNT + threadIdx.x;
+    const int n_out = sh.n_out[j], m = sh.m[j], o0 = blockIdx.y * 2;
+    if (o0 >= n_out) return;
+    const int o1 = o0 + 1 < n_out ? o0 + 1 : o0;  // an odd last target is computed twice
+    const uint64_t *in = jp.in[job] + (size_t)sh.in_off0[j] * N + c;
+    const double *hat = sh.hat[j];
+    const int p0 = sh.out_pidx[j][o0], p1 = sh.out_pidx[j][o1];
+    const Mod m0 = info[p0].m, m1 = info[p1].m;
+    double a0[N1], a1[N1];
+#pragma unroll
+    for (int r = 0; r < N1; r++) a0[r] = 0.0, a1[r] = 0.0;
+#pragma unroll 2
+    for (int a = 0; a < MMAX; a++) {  // two input limbs' loads in flight at a time
+        const int aa = a < m ? a : m - 1;
+        const double h0 = a < m ? hat[aa * n_out + o0] : 0.0, h1 = a < m ? hat[aa * n_out + o1] : 0.0;
+        uint64_t x[N1];
+#pragma unroll
+        for (int r = 0; r < N1; r++) x[r] = in[(size_t)aa * N + (size_t)r * kT];
+#pragma unroll
+        for (int r = 0; r < N1; r++) {
+            const double xv = u2d(x[r]);
+            a0[r] += mul_lazy(xv, h0, m0);
+            a1[r] += mul_lazy(xv, h1, m1);
+        }
+        if (a % 7 == 6 && a + 1 < MMAX) {  // at most 7 lazy terms on a reduced sum
+#pragma unroll
+            for (int r = 0; r < N1; r++) a0[r] = reduce(a0[r], m0), a1[r] = reduce(a1[r], m1);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < N1; r++) a0[r] = reduce(a0[r], m0), a1[r] = reduce(a1[r], m1);
+    col_forward<N1>(a0, tw + (size_t)p0 * N, m0);
+    col_forward<N1>(a1, tw + (size_t)p1 * N, m1);
+    uint64_t *out0 = jp.out[job] + (size_t)sh.out_off[j][o0] * N + c;
+    uint64_t *out1 = jp.out[job] + (size_t)sh.out_off[j][o1] * N + c;
+#pragma unroll
+    for (int r = 0; r < N1; r++) out0[(size_t)r * kT] = d2u(a0[r]);
+    if (o1 != o0) {
+#pragma unroll
+        for (int r = 0; r < N1; r++) out1[(size_t)r * kT] = d2u(a1[r]);
+    }
 }
 
 // ModDown of K key switches, finished inside the forward transform's tile pass.  The
@@ -252,13 +318,14 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const
 template <bool INV>
 static hipError_t launch_cols(const nj_ctx *c, int kind, double bytes, int N1, dim3 grid, hipStream_t s,
                               uint64_t *data, const uint64_t *src, const LimbTab &lt, const double *tw,
-                              const PrimeInfo *info, int logN)
+                              const PrimeInfo *info, int logN, const double *scale = nullptr)
 {
     switch (N1) {
-    case 2: return launch(c, kind, bytes, k_ntt_col<2, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
-    case 4: return launch(c, kind, bytes, k_ntt_col<4, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
-    case 8: return launch(c, kind, bytes, k_ntt_col<8, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
-    default: return launch(c, kind, bytes, k_ntt_col<16, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN);
+    case 2: return launch(c, kind, bytes, k_ntt_col<2, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    case 4: return launch(c, kind, bytes, k_ntt_col<4, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    case 8: return launch(c, kind, bytes, k_ntt_col<8, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    default:
+        return launch(c, kind, bytes, k_ntt_col<16, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
     }
 }
 
@@ -286,14 +353,66 @@ hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src,
     return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
 }
 
+// Inverse transform whose final factor is scale[pidx] instead of N^-1 (N >= 8192).
+hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
+                              const double *scale, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2) return hipErrorInvalidValue;
+    if (lt.n == 0) return hipSuccess;
+    const double bytes = 16.0 * N * lt.n;
+    hipError_t e = launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, dim3(N1, lt.n), dim3(kNT), s, data, src, lt,
+                          c->d_itw, c->d_info, c->log_n);
+    if (e != hipSuccess) return e;
+    return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt, c->d_itw,
+                             c->d_info, c->log_n, scale);
+}
+
+// Forward tile pass alone (the column pass already applied), N >= 8192.
+hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2) return hipErrorInvalidValue;
+    if (lt.n == 0) return hipSuccess;
+    return launch(c, PROF_NTT_TILE, 16.0 * N * lt.n, k_ntt_tile<false>, dim3(N1, lt.n), dim3(kNT), s, data, nullptr,
+                  lt, c->d_tw, c->d_info, c->log_n);
+}
+
+// Basis conversion of n_jobs (job, digit) pairs fused with the outputs' column pass
+// (inputs pre-multiplied by (D/q_a)^-1), N >= 8192.
+hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2 || n_jobs == 0) return N1 < 2 ? hipErrorInvalidValue : hipSuccess;
+    int max_out = 0, mmax = 0;
+    double bytes = 0;
+    for (int j = 0; j < sh.nd; j++) {
+        max_out = std::max(max_out, sh.n_out[j]);
+        mmax = std::max(mmax, sh.m[j]);
+        bytes += 8.0 * N * (sh.m[j] + sh.n_out[j]) * n_jobs;
+    }
+    if (mmax > 8) return hipErrorInvalidValue;
+    const dim3 grid(kT / kNT, (max_out + 1) / 2, n_jobs * sh.nd);
+#define NJ_BC(MM, NN)                                                                                               \
+    if (mmax <= MM && N1 == NN)                                                                                    \
+        return launch(c, PROF_BCONV, bytes, k_bconv_col<MM, NN>, grid, dim3(kNT), s, sh, jp, c->d_tw, c->d_info,   \
+                      c->log_n);
+    NJ_BC(2, 2) NJ_BC(2, 4) NJ_BC(2, 8) NJ_BC(2, 16)
+    NJ_BC(4, 2) NJ_BC(4, 4) NJ_BC(4, 8) NJ_BC(4, 16)
+    NJ_BC(8, 2) NJ_BC(8, 4) NJ_BC(8, 8) NJ_BC(8, 16)
+#undef NJ_BC
+    return hipErrorInvalidValue;
+}
+
 // ModDown combine of K jobs fused into the forward transform of their converted
-// limbs (N >= 4096); same results as the transform followed by the combine.
+// limbs (N >= 4096; cols_done: the column pass was already applied); same results
+// as the transform followed by the combine.
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
-                              const MdJobs &mj, int acc, hipStream_t s)
+                              const MdJobs &mj, int acc, int cols_done, hipStream_t s)
 {
     const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1;
     if (N < kT || K < 1 || K > NJ_MAX_JOBS) return hipErrorInvalidValue;
-    if (N1 > 1) {
+    if (N1 > 1 && !cols_done) {
         LimbTab lt;
         for (int b = 0; b < n; b += NJ_MAX_LIMBS) {
             lt.n = std::min(NJ_MAX_LIMBS, n - b);

@@ -223,9 +223,12 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
 // column pass).  Inputs are coefficient-form limbs already multiplied by
 // (D/q_a)^-1 (folded into their inverse transform's N^-1), so each output word is
 // y_t = sum_a x_a (D/q_a) mod t; the converted limbs are never stored before their
-// column pass.  Thread = one column (N1 words at stride 4096) of two targets o0, o0+1
-// of (job, digit) blockIdx.z = job * nd + digit; grid (4096/256, ceil(n_out/2), jobs nd).
-// Input slots past the digit size re-read its last limb with a zero factor.
+// column pass.  Thread = one column (N1 words at stride 4096) of OUT consecutive
+// targets of (job, digit) blockIdx.z = job * nd + digit; grid (4096/256,
+// ceil(n_out/OUT), jobs nd).  Input slots past the digit size re-read its last limb
+// with a zero factor; targets past n_out repeat the last one and are not stored.
+constexpr int kBcOut = 2;  // targets per thread
+
 template <int MMAX, int N1>
 __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp, const double *tw,
                                                    const PrimeInfo *info, int logN)
@@ -233,45 +236,55 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
     const int N = 1 << logN;
     const int job = blockIdx.z / sh.nd, j = blockIdx.z % sh.nd;
     const int c = blockIdx.x * kNT + threadIdx.x;
-    const int n_out = sh.n_out[j], m = sh.m[j], o0 = blockIdx.y * 2;
+    const int n_out = sh.n_out[j], m = sh.m[j], o0 = blockIdx.y * kBcOut;
     if (o0 >= n_out) return;
-    const int o1 = o0 + 1 < n_out ? o0 + 1 : o0;  // an odd last target is computed twice
     const uint64_t *in = jp.in[job] + (size_t)sh.in_off0[j] * N + c;
     const double *hat = sh.hat[j];
-    const int p0 = sh.out_pidx[j][o0], p1 = sh.out_pidx[j][o1];
-    const Mod m0 = info[p0].m, m1 = info[p1].m;
-    double a0[N1], a1[N1];
+    int o[kBcOut];
+    Mod mo[kBcOut];
 #pragma unroll
-    for (int r = 0; r < N1; r++) a0[r] = 0.0, a1[r] = 0.0;
-#pragma unroll 2
-    for (int a = 0; a < MMAX; a++) {  // two input limbs' loads in flight at a time
+    for (int q = 0; q < kBcOut; q++) {
+        o[q] = o0 + q < n_out ? o0 + q : n_out - 1;
+        mo[q] = info[sh.out_pidx[j][o[q]]].m;
+    }
+    double acc[kBcOut][N1];
+#pragma unroll
+    for (int q = 0; q < kBcOut; q++)
+#pragma unroll
+        for (int r = 0; r < N1; r++) acc[q][r] = 0.0;
+#pragma unroll 4
+    for (int a = 0; a < MMAX; a++) {  // four input limbs' loads in flight at a time
         const int aa = a < m ? a : m - 1;
-        const double h0 = a < m ? hat[aa * n_out + o0] : 0.0, h1 = a < m ? hat[aa * n_out + o1] : 0.0;
+        double h[kBcOut];
+#pragma unroll
+        for (int q = 0; q < kBcOut; q++) h[q] = a < m ? hat[aa * n_out + o[q]] : 0.0;
         uint64_t x[N1];
 #pragma unroll
         for (int r = 0; r < N1; r++) x[r] = in[(size_t)aa * N + (size_t)r * kT];
 #pragma unroll
         for (int r = 0; r < N1; r++) {
             const double xv = u2d(x[r]);
-            a0[r] += mul_lazy(xv, h0, m0);
-            a1[r] += mul_lazy(xv, h1, m1);
+#pragma unroll
+            for (int q = 0; q < kBcOut; q++) acc[q][r] += mul_lazy(xv, h[q], mo[q]);
         }
         if (a % 7 == 6 && a + 1 < MMAX) {  // at most 7 lazy terms on a reduced sum
 #pragma unroll
-            for (int r = 0; r < N1; r++) a0[r] = reduce(a0[r], m0), a1[r] = reduce(a1[r], m1);
+            for (int q = 0; q < kBcOut; q++)
+#pragma unroll
+                for (int r = 0; r < N1; r++) acc[q][r] = reduce(acc[q][r], mo[q]);
         }
     }
 #pragma unroll
-    for (int r = 0; r < N1; r++) a0[r] = reduce(a0[r], m0), a1[r] = reduce(a1[r], m1);
-    col_forward<N1>(a0, tw + (size_t)p0 * N, m0);
-    col_forward<N1>(a1, tw + (size_t)p1 * N, m1);
-    uint64_t *out0 = jp.out[job] + (size_t)sh.out_off[j][o0] * N + c;
-    uint64_t *out1 = jp.out[job] + (size_t)sh.out_off[j][o1] * N + c;
+    for (int q = 0; q < kBcOut; q++) {
 #pragma unroll
-    for (int r = 0; r < N1; r++) out0[(size_t)r * kT] = d2u(a0[r]);
-    if (o1 != o0) {
+        for (int r = 0; r < N1; r++) acc[q][r] = reduce(acc[q][r], mo[q]);
+        const int pq = sh.out_pidx[j][o[q]];
+        col_forward<N1>(acc[q], tw + (size_t)pq * N, mo[q]);
+        if (o0 + q < n_out) {
+            uint64_t *out = jp.out[job] + (size_t)sh.out_off[j][o[q]] * N + c;
 #pragma unroll
-        for (int r = 0; r < N1; r++) out1[(size_t)r * kT] = d2u(a1[r]);
+            for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(acc[q][r]);
+        }
     }
 }
 
@@ -392,7 +405,7 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
         bytes += 8.0 * N * (sh.m[j] + sh.n_out[j]) * n_jobs;
     }
     if (mmax > 8) return hipErrorInvalidValue;
-    const dim3 grid(kT / kNT, (max_out + 1) / 2, n_jobs * sh.nd);
+    const dim3 grid(kT / kNT, (max_out + kBcOut - 1) / kBcOut, n_jobs * sh.nd);
 #define NJ_BC(MM, NN)                                                                                               \
     if (mmax <= MM && N1 == NN)                                                                                    \
         return launch(c, PROF_BCONV, bytes, k_bconv_col<MM, NN>, grid, dim3(kNT), s, sh, jp, c->d_tw, c->d_info,   \

@@ -26,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fused CinS-conv+CoeffToSlot ms and keyswitch/s at N=2^16; batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the step's kernel families, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a copy kernel of known size (profiles/pmc_fused_conv_cts_n65536.md);
+# valid for the kernels as they were when counted, absent for the others
+TRAFFIC_BYTES = {"k_key_ip": 729842627}
 
 
 def parse():
@@ -398,7 +402,7 @@ def main():
                           "avg_launch_us": 1e3 * kms / n, "gbs": kby / kms / 1e6}
     dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms_per_step"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(dom),
                 "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
     alg = pipeline_bytes(g)
 

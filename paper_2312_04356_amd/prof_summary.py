@@ -20,9 +20,10 @@ def family(name):
     n = re.sub(r"\(.*", "", name)
     n = n.replace("void ", "").replace("nj::", "")
     n = re.sub(r"k_ntt_col<\d+, (false|true)>", r"k_ntt_col<\1>", n)
-    n = n.replace("k_bconv_batch<", "k_bconv<").replace("k_bconv_multi<", "k_bconv<").strip()
-    n = re.sub(r"k_bconv<\d+>", "k_bconv", n)
+    n = n.strip()
     # the same families the library's HIP-event counters use
+    if n.startswith("k_bconv"):
+        return "k_bconv"
     if n.startswith("k_key_ip"):
         return "k_key_ip"
     if n.startswith("k_bsgs_mac"):

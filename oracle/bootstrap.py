@@ -208,6 +208,28 @@ class Boot:
             g = self.sq_minus1(g)
         return (g[0], g[1], g[2] * (2.0 * math.pi) * s0 / q0)
 
+    # ------------------------------------------------- masks and activation
+    def mask_mult(self, ct, mask_pt):
+        """PMult by a slot mask encoded at scale q_l (coefficient form, l+1 limbs), then
+        rescale by q_l: the recorded scale is unchanged"""
+        x, l, s = ct
+        y = np.stack([self.R.pmult(l, x[0], mask_pt), self.R.pmult(l, x[1], mask_pt)])
+        return (self.ctx.ct_rescale(l, y), l - 1, s)
+
+    def slot_activation(self, re, im, K, r, coeffs, masks, act, plan, plan_level):
+        """Algorithm 1 after CoeffToSlot: ModEval on Re and Im; PMult by the zero-padding
+        masks (masks = (pt_re, pt_im) or None); the activation (act 1: the square x^2 of
+        AESPA, Sec. 2.5.2, by HMult; act 0: none); Re + i Im; StoC1 (plan from stoc1_plan,
+        its first group at plan_level, the input dropped to it)"""
+        er, ei = self.eval_mod(re, K, r, coeffs), self.eval_mod(im, K, r, coeffs)
+        if masks is not None:
+            er, ei = self.mask_mult(er, masks[0]), self.mask_mult(ei, masks[1])
+        if act == 1:
+            er, ei = self.hmult(er, er), self.hmult(ei, ei)
+        z = self.combine(er, ei)
+        assert z[1] >= plan_level
+        return self.stoc1(self.drop(z, plan_level), plan)
+
     # --------------------------------------------------------------- StoC1
     def combine(self, re, im):
         """Re + i Im (i = X^{N/2} on the slots), at the lower level"""
@@ -223,6 +245,20 @@ class Boot:
             x = self.ctx.ct_rescale(l, self.ctx.bsgs(l, x, bs, pts))
             l -= 1
         return (x, l, s)
+
+
+def layer_masks(N, W, C, w0):
+    """Algorithm 1's zero-padding masks (mask_Re, mask_Im; N/2 reals each).  The
+    flattened conv (Sec. 2.5.1) leaves values at the padding positions; the fused conv's
+    output holds channel rev_C(k mod C) of padded pixel p = floor(k / C),
+    (y, x) = divmod(p, W), in coefficient k, and that pixel is an output pixel iff
+    y, x < w0.  CoeffToSlot (T^-1, Sec. 2.3) puts coefficient rev_{N/2}(j) in slot j of
+    the real part and coefficient N/2 + rev_{N/2}(j) in slot j of the imaginary part."""
+    n2 = N // 2
+    p = np.arange(N) // C
+    valid = ((p // W < w0) & (p % W < w0)).astype(np.float64)
+    rev = np.array([E.bitrev(j, n2) for j in range(n2)])
+    return valid[:n2][rev], valid[n2:][rev]
 
 
 def stoc1_stage_groups(ell, d):

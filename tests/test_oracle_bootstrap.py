@@ -176,3 +176,67 @@ def test_bootstrap_round_trip(sm):
     err = np.max(np.abs(got - coeffs))
     print("bootstrap round trip: level %d, max coefficient error %.2e" % (l - 1, err))
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("N,W,C,w0", [(1 << 12, 32, 4, 16), (1 << 16, 64, 16, 32), (1 << 11, 16, 8, 12)])
+def test_layer_masks_mark_the_conv_output_pixels(N, W, C, w0):
+    """the masks' ones are exactly the coefficients the conv output is read from,
+    a[(y W + x) C + rev_C(c)] for y, x < w0, seen through CoeffToSlot's bit-reversed halves"""
+    ind = np.zeros(N)
+    for c in range(C):
+        for y in range(w0):
+            ind[(y * W + np.arange(w0)) * C + E.bitrev(c, C)] = 1.0
+    n2 = N // 2
+    rev = np.array([E.bitrev(j, n2) for j in range(n2)])
+    mre, mim = B.layer_masks(N, W, C, w0)
+    assert ind.sum() == C * w0 * w0 == mre.sum() + mim.sum()
+    assert np.array_equal(mre, ind[:n2][rev]) and np.array_equal(mim, ind[n2:][rev])
+
+
+def test_masked_square_layer_round_trip(sm):
+    """Algorithm 1's tail on a bootstrapped ciphertext: coefficients c laid out as a conv
+    output (W = 16, C = 8, w0 = 12) -> ModRaise -> CoeffToSlot -> ModEval, zero-padding
+    masks, the square activation, Re + i Im, StoC1 -> the remaining StoC2 stages: the
+    coefficients come back as c^2 on output pixels and 0 on padding"""
+    N, n = sm.N, sm.N // 2
+    W, C, w0 = 16, 8, 12
+    ell = W * W // 2
+    L = sm.R.L
+    coeffs = RNG.uniform(-1, 1, N)
+    x0 = sm.enc(np.rint(coeffs * sm.scale).astype(np.int64), 0, 3)
+    groups = PL.cts_plan(N, 2)
+    st1 = B.stoc1_plan(N, ell, 2)
+    M = None
+    k = ell
+    while k < n:
+        D = E.stage_diagonals(k, n)
+        M = D if M is None else E.compose(D, M, n)
+        k *= 2
+    s2 = PL.Bsgs(n, ell, M.keys())
+    s2_diags = PL.prerotate(s2, M)
+    rots = set(s2.rotations())
+    for bs, _ in groups + st1:
+        rots |= set(bs.rotations())
+    for r in sorted(rots):
+        sm.key(PL.galois_elt(r, N))
+    sm.key(2 * N - 1)
+    cts_pts = [PL.encode_diagonals(d, N, float(sm.q[L - g]), sm.R, L - g) for g, (_, d) in enumerate(groups)]
+    re, im = sm.ctx.coeff_to_slot(x0, [b for b, _ in groups], cts_pts)
+    lvl = L - len(groups)
+    le = lvl - 11  # ModEval output level: masks encoded at q_le
+    mre, mim = B.layer_masks(N, W, C, w0)
+    masks = tuple(sm.R.to_rns(E.encode(m, N, float(sm.q[le])), le) for m in (mre, mim))
+    lp = le - 2  # after the mask and the square
+    st1_pts = [(bs, PL.encode_diagonals(d, N, float(sm.q[lp - g]), sm.R, lp - g)) for g, (bs, d) in enumerate(st1)]
+    y = sm.boot.slot_activation((re, lvl, sm.scale), (im, lvl, sm.scale), K, R_DA, B.cheb_coeffs(K, R_DA), masks, 1,
+                                st1_pts, lp)
+    assert y[1] == lp - 2
+    l = y[1]
+    pts = PL.encode_diagonals(s2_diags, N, float(sm.q[l]), sm.R, l)
+    out = sm.ctx.ct_rescale(l, sm.ctx.bsgs(l, y[0], s2, pts))
+    got = sm.dec(out, l - 1, y[2])
+    p = np.arange(N) // C
+    valid = (p // W < w0) & (p % W < w0)
+    err = np.max(np.abs(got - np.where(valid, coeffs ** 2, 0.0)))
+    print("masked square layer: level %d, max error %.2e" % (l - 1, err))
+    assert err < 1e-3

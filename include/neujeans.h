@@ -316,6 +316,38 @@ nj_status nj_combine(nj_ctx *ctx, const nj_ct *re, const nj_ct *im, nj_ct *out, 
 nj_status nj_stoc1_plan_create(nj_ctx *ctx, int ell, int groups, int level, nj_plan **out);
 nj_status nj_stoc1(nj_ctx *ctx, const nj_plan *plan, const nj_ct *in, nj_ct *out, void *stream);
 
+/* ------------------------------------------- Algorithm 1 and bootstrapping */
+
+/* The zero-padding masks of Algorithm 1 (Sec. 4; the flattened conv of Sec. 2.5.1 leaves
+ * values at padding positions): for CinS images of w0 x w0 pixels padded to W x W, C per
+ * ciphertext (W^2 C = N = 2^log_n), mask_re[j] / mask_im[j] (N/2 doubles each, host) are
+ * 1 where slot j of the real / imaginary CoeffToSlot output holds an output pixel and 0
+ * where it holds padding.  Coefficient k of the fused conv's output holds padded pixel
+ * floor(k / C) (row-major in W x W); CoeffToSlot leaves coefficient rev(j) in real slot j
+ * and N/2 + rev(j) in imaginary slot j (bit reversal over log_n - 1 bits).  Host only. */
+nj_status nj_layer_masks(int log_n, int W, int C, int w0, double *mask_re, double *mask_im);
+/* Algorithm 1 after CoeffToSlot: ModEval (as nj_eval_mod) of re and im (same level l);
+ * if masks are given, PMult by mask_re / mask_im and rescale (masks: device plaintexts in
+ * evaluation form, [l - 10][N] = the ModEval output's limbs, the slot masks encoded at
+ * scale q_{l-11} so the scale is kept); the activation: act 0 none, act 1 the square of
+ * AESPA (Sec. 2.5.2) by HMult with relinearisation; Re + i Im (nj_combine), dropped to
+ * the StoC1 plan's first level (an error if below it); StoC1 -> out (level and scale
+ * set).  Needs the relinearisation key and the StoC1 plan's rotation keys. */
+nj_status nj_slot_activation(nj_ctx *ctx, int K, int r, const double *coeffs, int n_coeffs, const uint64_t *mask_re,
+                             const uint64_t *mask_im, int act, const nj_plan *stoc1, const nj_ct *re, const nj_ct *im,
+                             nj_ct *out, void *stream);
+/* Algorithm 1, one layer: conv2d_cins (fused with StoC2; conv may be null, then `in` is
+ * a level-0 ciphertext) -> level 0 -> ModRaise + CoeffToSlot (nj_coeff_to_slot) ->
+ * nj_slot_activation.  `out` is the next layer's CinS input (the StoC2 stages left are
+ * fused into the next conv). */
+nj_status nj_conv_act_layer(nj_ctx *ctx, const nj_plan *conv, const nj_plan *cts, int K, int r, const double *coeffs,
+                            int n_coeffs, const uint64_t *mask_re, const uint64_t *mask_im, int act,
+                            const nj_plan *stoc1, const nj_ct *in, nj_ct *out, void *stream);
+/* Bootstrapping (Sec. 2.4) of a level-0 ciphertext: ModRaise, CoeffToSlot, ModEval of
+ * Re and Im, Re + i Im, StoC1: nj_conv_act_layer without conv, masks or activation. */
+nj_status nj_bootstrap(nj_ctx *ctx, const nj_plan *cts, int K, int r, const double *coeffs, int n_coeffs,
+                       const nj_plan *stoc1, const nj_ct *in, nj_ct *out, void *stream);
+
 /* ------------------------------------------------------------ plan selection */
 
 /* Timing mode for latency measurement: after nj_timing_keys(ctx, pool) with pool > 0,

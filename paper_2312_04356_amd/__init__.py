@@ -91,6 +91,12 @@ _SIGS = {
     "nj_combine": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_stoc1_plan_create": (i32, [vp, i32, i32, i32, ctypes.POINTER(vp)]),
     "nj_stoc1": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
+    "nj_layer_masks": (i32, [i32, i32, i32, i32, vp, vp]),
+    "nj_slot_activation": (i32, [vp, i32, i32, vp, i32, vp, vp, i32, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt),
+                                 ctypes.POINTER(NjCt), vp]),
+    "nj_conv_act_layer": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, vp, i32, vp, ctypes.POINTER(NjCt),
+                                ctypes.POINTER(NjCt), vp]),
+    "nj_bootstrap": (i32, [vp, vp, i32, i32, vp, i32, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_plan_create_random": (i32, [vp, i32, i32, vp, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]),
     "nj_time_plan": (i32, [vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
     "nj_plan_features": (i32, [vp, i32, i32, vp]),
@@ -239,6 +245,18 @@ class Plan:
         if getattr(self, "ptr", None):
             _lib.nj_plan_destroy(self.ptr)
             self.ptr = None
+
+
+def nj_layer_masks(log_n, W, C, w0):
+    """(mask_re, mask_im): Algorithm 1's zero-padding slot masks, N/2 doubles each"""
+    n2 = 1 << (log_n - 1)
+    mre, mim = np.zeros(n2), np.zeros(n2)
+    _check(_lib.nj_layer_masks(int(log_n), int(W), int(C), int(w0), _np_ptr(mre), _np_ptr(mim)), "nj_layer_masks")
+    return mre, mim
+
+
+def _coeffs(coeffs):
+    return None if coeffs is None else np.ascontiguousarray(coeffs, dtype=np.float64)
 
 
 def nj_cheb_interpolate(degree, K, r):
@@ -580,6 +598,34 @@ class Ctx:
     def nj_stoc1(self, plan, ct, out, stream=None):
         ci, co = ct.c(), out.c()
         _check(_lib.nj_stoc1(self.ptr, plan.ptr, ctypes.byref(ci), ctypes.byref(co), _stream(stream)), "nj_stoc1")
+        return out.sync_from(co)
+
+    def nj_slot_activation(self, K, r, coeffs, mask_re, mask_im, act, stoc1, re, im, out, stream=None):
+        cr, cm, co = re.c(), im.c(), out.c()
+        cf = _coeffs(coeffs)
+        _check(_lib.nj_slot_activation(self.ptr, int(K), int(r), None if cf is None else _np_ptr(cf),
+                                       0 if cf is None else len(cf), None if mask_re is None else _dev_ptr(mask_re),
+                                       None if mask_im is None else _dev_ptr(mask_im), int(act), stoc1.ptr,
+                                       ctypes.byref(cr), ctypes.byref(cm), ctypes.byref(co), _stream(stream)),
+               "nj_slot_activation")
+        return out.sync_from(co)
+
+    def nj_conv_act_layer(self, conv, cts, K, r, coeffs, mask_re, mask_im, act, stoc1, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        cf = _coeffs(coeffs)
+        _check(_lib.nj_conv_act_layer(self.ptr, None if conv is None else conv.ptr, cts.ptr, int(K), int(r),
+                                      None if cf is None else _np_ptr(cf), 0 if cf is None else len(cf),
+                                      None if mask_re is None else _dev_ptr(mask_re),
+                                      None if mask_im is None else _dev_ptr(mask_im), int(act), stoc1.ptr,
+                                      ctypes.byref(ci), ctypes.byref(co), _stream(stream)), "nj_conv_act_layer")
+        return out.sync_from(co)
+
+    def nj_bootstrap(self, cts, K, r, coeffs, stoc1, ct, out, stream=None):
+        ci, co = ct.c(), out.c()
+        cf = _coeffs(coeffs)
+        _check(_lib.nj_bootstrap(self.ptr, cts.ptr, int(K), int(r), None if cf is None else _np_ptr(cf),
+                                 0 if cf is None else len(cf), stoc1.ptr, ctypes.byref(ci), ctypes.byref(co),
+                                 _stream(stream)), "nj_bootstrap")
         return out.sync_from(co)
 
     def nj_timing_keys(self, pool):

@@ -357,6 +357,7 @@ void nj_ctx_destroy(nj_ctx *c)
         for (auto &b : lv) fr(b.hat_inv), fr(b.hat);
     for (auto &b : c->moddown) fr(b.hat_inv), fr(b.hat);
     for (auto *p : c->d_upscale) fr(p);
+    fr(c->layer_buf);
     fr(c->d_downscale);
     for (auto &kv : c->keys) fr(kv.second.d);
     for (auto *k : c->timing_keys) fr(k);

@@ -190,6 +190,9 @@ struct nj_ctx {
     std::map<uint32_t, nj::Key> keys;
     std::vector<uint64_t *> timing_keys;  // latency measurement: random key buffers for missing elements
     nj::Scratch scratch;
+    // intermediate ciphertexts of the composite calls (Algorithm 1, bootstrapping)
+    uint64_t *layer_buf = nullptr;
+    size_t layer_words = 0;
     // live profiling (nj_prof_*)
     bool prof = false;
     std::vector<nj::ProfRec> prof_recs;

@@ -79,3 +79,12 @@ def test_real_cins_encoder_agrees_with_oracle():
 def test_encoder_rejects_bad_slice():
     with pytest.raises(nj.NjError):
         nj.nj_encode_cins(12, np.zeros((3, 100)), 1.0)
+
+
+@pytest.mark.parametrize("log_n,W,C,w0", [(12, 32, 4, 16), (16, 64, 16, 32), (11, 16, 8, 12)])
+def test_layer_masks_match_oracle(log_n, W, C, w0):
+    """the library's zero-padding masks (host) against the oracle's"""
+    import oracle.bootstrap as B
+    got = nj.nj_layer_masks(log_n, W, C, w0)
+    want = B.layer_masks(1 << log_n, W, C, w0)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])

@@ -1,0 +1,156 @@
+"""Algorithm 1 through the C ABI (needs an MI355X): the tail after CoeffToSlot (ModEval of
+Re and Im, zero-padding masks, the square activation, Re + i Im, StoC1) bit-exact
+against the oracle at N = 2^12; nj_bootstrap equal word for word to the chain of single
+calls; and one whole layer at N = 2^16 (the benchmark conv, the library's masks, the
+square) decrypting to the masked square of the conv output's ModEval image."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.bootstrap as B
+import oracle.encoding as E
+import oracle.plans as PL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import synth  # noqa: E402
+from paper_2312_04356_amd import Ct, nj_layer_masks  # noqa: E402
+from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+from tests.boot_rig import SCALE, Rig  # noqa: E402
+from tests.oracle_workload import OracleWorkload  # noqa: E402
+
+RNG = np.random.default_rng(31)
+
+
+@pytest.fixture(scope="module")
+def rig():
+    return Rig()
+
+
+def eval_form(g, coeffs_rns, level):
+    """an oracle plaintext (coefficient form, level+1 limbs) on the device in evaluation form"""
+    t = g.to_device(coeffs_rns)
+    g.nj_to_eval(t, level, 1)
+    return t
+
+
+def stoc1_plan_from_oracle(rig, ell, groups, level):
+    plan = rig.g.nj_stoc1_plan_create(ell, groups, level)
+    pts = []
+    for t, (bs, diags) in enumerate(B.stoc1_plan(rig.N, ell, groups)):
+        pt = PL.encode_diagonals(diags, rig.N, float(rig.q[level - t]), rig.R, level - t)
+        for idx, j in enumerate(plan.offsets(t)):
+            rig.g.nj_plan_set_diagonal(plan, t, idx, pt[j])
+        pts.append((bs, pt))
+        for rr in bs.rotations():
+            rig.key(PL.galois_elt(rr, rig.N))
+    for gl in plan.galois():
+        rig.key(gl)
+    return plan, pts
+
+
+@pytest.mark.parametrize("masked,act", [(True, 1), (False, 0), (True, 0)])
+def test_slot_activation_parity(rig, masked, act):
+    n, N = rig.N // 2, rig.N
+    W, C, w0, ell = 32, 4, 16, 512
+    lo = 18
+    le = lo - 11
+    lp = le - (1 if masked else 0) - (1 if act else 0)
+    P = rig.q[0] / SCALE
+    vals = []
+    for sub in (11, 12):
+        t = RNG.uniform(-1, 1, n) + P * RNG.integers(-6, 7, n)
+        vals.append(rig.enc(t, lo, SCALE, sub))
+    (xr, cr), (xi, ci) = vals
+    K, r = 16, 3
+    coeffs = B.cheb_coeffs(K, r)
+    masks_o = masks_d = (None, None)
+    if masked:
+        mre, mim = B.layer_masks(N, W, C, w0)
+        masks_o = tuple(rig.R.to_rns(E.encode(m, N, float(rig.q[le])), le) for m in (mre, mim))
+        masks_d = tuple(eval_form(rig.g, m, le) for m in masks_o)
+    plan, pts = stoc1_plan_from_oracle(rig, ell, 3, lp)
+    want = rig.boot.slot_activation((xr, lo, SCALE), (xi, lo, SCALE), K, r, coeffs,
+                                    masks_o if masked else None, act, pts, lp)
+    out = rig.g.empty_ct(lp - 3)
+    rig.g.nj_slot_activation(K, r, coeffs, masks_d[0], masks_d[1], act, plan, cr, ci, out)
+    assert out.level == want[1] == lp - 3 and out.scale == want[2]
+    assert np.array_equal(rig.coeff(out), want[0])
+
+
+def test_bootstrap_call_equals_chain(rig):
+    """nj_bootstrap = ModRaise + CoeffToSlot, ModEval of Re and Im, Re + i Im, StoC1"""
+    g, N = rig.g, rig.N
+    coeffs = RNG.uniform(-1, 1, N)
+    m = rig.R.to_rns(np.rint(coeffs * SCALE).astype(np.int64), 0)
+    a, e = synth.enc_randomness(rig.q[:1], N, 79, 13)
+    ct0 = g.empty_ct(0)
+    g.nj_encrypt_sk(g.to_device(m), 0, a, e, SCALE, ct0)
+    cts = g.nj_cts_plan_create(2)
+    lo = g.L - 2
+    stoc1 = g.nj_stoc1_plan_create(512, 3, lo - 11)
+    for gl in sorted(set(cts.galois()) | set(stoc1.galois())):
+        rig.key(gl)
+    out = g.empty_ct(lo - 14)
+    g.nj_bootstrap(cts, 16, 3, None, stoc1, ct0, out)
+    re, im = g.empty_ct(lo), g.empty_ct(lo)
+    g.nj_coeff_to_slot(cts, ct0, re, im)
+    er, ei = g.empty_ct(lo - 11), g.empty_ct(lo - 11)
+    g.nj_eval_mod(re, 16, 3, None, er)
+    g.nj_eval_mod(im, 16, 3, None, ei)
+    z = g.empty_ct(lo - 11)
+    g.nj_combine(er, ei, z)
+    y = g.empty_ct(lo - 14)
+    g.nj_stoc1(stoc1, z, y)
+    assert out.level == y.level and out.scale == y.scale
+    assert torch.equal(out.data, y.data)
+
+
+def test_conv_act_layer_full_size():
+    """the benchmark's conv (3x3 16->16, 32x32 in 64x64, N = 2^16) through one Algorithm 1
+    layer with the library's masks and the square, then the identity kernel's fused
+    StoC2 plan back to coefficient layout: output pixels hold ((P / 2 pi) sin(2 pi o / P))^2
+    of the FP64 conv2d o (P = q_0 / scale), padding holds 0"""
+    g = GpuWorkload("full", with_cts=True, lazy=True)
+    gctx = g.ctx
+    K = 32
+    lo = gctx.L - g.w["cts_groups"]
+    le = lo - 11
+    lp = le - 2
+    stoc1 = gctx.nj_stoc1_plan_create(g.ell, 3, lp)
+    s2l = lp - 3
+    s2 = gctx.nj_conv_plan_create_taps(g.W, g.C, g.C, [(c, c, 0, 0, 1.0) for c in range(g.C)], fuse=1, level=s2l)
+    a, e = synth.key_randomness(g.q + g.p, g.N, gctx.dnum, g.w["key_seed"], synth.RELIN_KEY_ID)
+    gctx.nj_gen_switch_key(0, a, e)
+    g.make_keys(sorted(set(g.galois_elements()) | set(stoc1.galois()) | set(s2.galois())))
+    masks = []
+    for mk in nj_layer_masks(gctx.log_n, g.W, g.C, g.w["w0"]):
+        cf = gctx.nj_encode_slots(mk, float(g.q[le]))
+        t = torch.empty((le + 1, g.N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_upload_plain(cf, le, t)
+        gctx.nj_to_eval(t, le, 1)
+        masks.append(t)
+    ct = g.encrypt_input(1)
+    out = gctx.empty_ct(lp - 3)
+    gctx.nj_conv_act_layer(g.conv_plan, g.cts_plan, K, 3, None, masks[0], masks[1], 1, stoc1, ct, out)
+    assert out.level == lp - 3
+    y = gctx.empty_ct(s2l - 1)
+    gctx.nj_conv2d_cins(s2, out, y)
+    d = torch.empty((y.level + 1, g.N), dtype=torch.int64, device=gctx.device)
+    gctx.nj_decrypt(y, d)
+    vals = np.array(O.centred_from_limbs(gctx.to_host(d)[:2], g.q[:2]), dtype=np.float64) / y.scale
+    ow = OracleWorkload.__new__(OracleWorkload)  # layout helper only
+    ow.w, ow.W, ow.C = g.w, g.W, g.C
+    P = g.q[0] / g.scale
+    want = (P / (2 * np.pi) * np.sin(2 * np.pi * PL.conv2d_same(g.img, g.K) / P)) ** 2
+    got = ow.read_conv_output(vals)
+    p = np.arange(g.N) // g.C
+    pad = ~((p // g.W < g.w["w0"]) & (p % g.W < g.w["w0"]))
+    err, err_pad = np.max(np.abs(got - want)), np.max(np.abs(vals[pad]))
+    print("full-size layer: output level %d, max |out - model^2| %.2e on pixels, max |out| %.2e on padding"
+          % (y.level, err, err_pad))
+    assert err < 2e-2 and err_pad < 2e-2

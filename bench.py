@@ -226,9 +226,36 @@ def boot_bench(g, steps=3):
         torch.cuda.synchronize()
         t_mod += e0.elapsed_time(e1)
         t_all += e0.elapsed_time(e2)
-    return {"eval_mod_re_im_ms": round(t_mod / steps, 3), "stoc1_ms": round((t_all - t_mod) / steps, 3),
-            "levels": {"in": lo, "after_eval_mod": lo - 11, "after_stoc1": lo - 14}, "K": 32, "degree": 63,
-            "double_angles": 3, "stoc1_groups": 3}
+    res = {"eval_mod_re_im_ms": round(t_mod / steps, 3), "stoc1_ms": round((t_all - t_mod) / steps, 3),
+           "levels": {"in": lo, "after_eval_mod": lo - 11, "after_stoc1": lo - 14}, "K": 32, "degree": 63,
+           "double_angles": 3, "stoc1_groups": 3}
+    # one whole Algorithm 1 layer: conv (fused StoC2) -> ModRaise -> CoeffToSlot -> ModEval of
+    # Re and Im -> zero-padding masks -> square activation -> Re + i Im -> StoC1
+    from paper_2312_04356_amd import nj_layer_masks
+    le = lo - 11
+    st1 = gctx.nj_stoc1_plan_create(g.ell, 3, le - 2)
+    g.make_keys(sorted(st1.galois()))
+    masks = []
+    for mk in nj_layer_masks(gctx.log_n, g.W, g.C, g.w["w0"]):
+        t = torch.empty((le + 1, g.N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_upload_plain(gctx.nj_encode_slots(mk, float(g.q[le])), le, t)
+        gctx.nj_to_eval(t, le, 1)
+        masks.append(t)
+    lout = gctx.empty_ct(le - 5)
+
+    def layer():
+        gctx.nj_conv_act_layer(g.conv_plan, g.cts_plan, 32, 3, None, masks[0], masks[1], 1, st1, ct, lout)
+
+    layer()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        layer()
+    e2.record()
+    torch.cuda.synchronize()
+    res["algorithm1_layer"] = {"ms": round(e0.elapsed_time(e2) / steps, 3), "activation": "square", "masks": True,
+                               "levels": {"in": 1, "out": le - 5}}
+    return res
 
 
 def cpu_baseline(name):

@@ -726,6 +726,10 @@ nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, 
     if (n_out < 0) n_out = l;
     uint64_t *last = A.take(2 * N), *lifted = A.take(N * l);
     if (!lifted) return fail(NJ_ENOMEM, "scratch too small");
+    if (N >= 8192) {  // the lifted limbs stay in out, transformed and combined in place
+        NJ_HIP(launch_rescale_fused(c, l, in, out, n_out, last, out, s));
+        return NJ_OK;
+    }
     for (int p = 0; p < 2; p++)
         NJ_HIP(hipMemcpyAsync(last + p * N, in + ((size_t)p * (l + 1) + l) * N, N * 8, hipMemcpyDeviceToDevice, s));
     LimbTab lt;

@@ -115,13 +115,17 @@ class Ev {
         if (!ok()) return o;
         check(launch_tensor(c, a.d, N * (a.l + 1), b.d, N * (b.l + 1), t.d, d2.d, l, s));
         Arena A = ks;
-        KsBufs B;
-        if (!ks_bufs(c, l, A, B)) {
+        MultiBufs M;  // the batched key-switch path with one job: its fused kernels
+        if (!multi_bufs(c, l, 1, A, M)) {
             check(fail(NJ_ENOMEM, "ModEval: key-switch scratch"));
             return o;
         }
-        check(modup_ext(c, l, d2.d, B, s));
-        check(ks_from_ext(c, l, d2.d, relin, 1, nullptr, 0, t.d, t.d, B, s));
+        check(modup_multi(c, l, 1, d2.d, M, s));
+        KeyJobs kj;
+        kj.ext[0] = M.ext, kj.d[0] = d2.d, kj.key[0] = relin, kj.g[0] = 1;
+        MdJobs mj;
+        mj.add[0] = nullptr, mj.g_add[0] = 1, mj.out[0] = t.d;
+        check(ks_multi(c, l, 1, kj, mj, 0, t.d, M, s));  // t += the switched d2
         check(rescale(c, l, t.d, o.d, A, s));
         release(t), release(d2);
         return o;

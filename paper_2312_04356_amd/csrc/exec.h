@@ -61,6 +61,9 @@ size_t multi_words(const nj_ctx *c, int l, int K);
 bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
 // ModUp of K polynomials at d + z dstride N (dstride in limbs, l+1 when packed)
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1);
+// K key switches on ModUp'ed digits (M.ext): key inner products, then ks_down
+nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
+                   MultiBufs &M, hipStream_t s);
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
                   hipStream_t s);

@@ -258,6 +258,8 @@ hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool i
                       const uint64_t *src = nullptr);
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
                               const double *scale, hipStream_t s);
+hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
+                                uint64_t *last, uint64_t *lifted, hipStream_t s);
 hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);
 hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,

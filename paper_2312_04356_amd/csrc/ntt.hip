@@ -328,6 +328,57 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const
     }
 }
 
+// Rescale by q_l, fused into the lifted limbs' transform (N >= 8192).  k_lift_col: the
+// last limb of each polynomial (coefficient form, last [2][N]) lifted centred into
+// target limb i, then the forward column pass; grid (4096/256, n_out, 2).
+template <int N1>
+__global__ __launch_bounds__(kNT) void k_lift_col(const uint64_t *last, int src_pidx, int n_out, uint64_t *lifted,
+                                                  const double *tw, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, i = blockIdx.y, z = blockIdx.z;
+    const int c = blockIdx.x * kNT + threadIdx.x;
+    const Mod ms = info[src_pidx].m, mt = info[i].m;
+    const double half = info[src_pidx].half;
+    const uint64_t *src = last + (size_t)z * N + c;
+    double v[N1];
+#pragma unroll
+    for (int r = 0; r < N1; r++) {
+        const double x = u2d(src[(size_t)r * kT]);
+        v[r] = reduce(x > half ? x - ms.t : x, mt);  // centred, |x| < t_l / 2 < 2^49
+    }
+    col_forward<N1>(v, tw + (size_t)i * N, mt);
+    uint64_t *dst = lifted + ((size_t)z * n_out + i) * N + c;
+#pragma unroll
+    for (int r = 0; r < N1; r++) dst[(size_t)r * kT] = d2u(v[r]);
+}
+
+// k_ntt_tile_rs: the lifted limbs' tile pass with the rescale combine as its epilogue,
+// out[z][i] = (in[z][i] - NTT(lift)[z][i]) q_l^-1 mod q_i; grid (N/4096, 2 n_out).
+__global__ __launch_bounds__(kNT) void k_ntt_tile_rs(const uint64_t *lifted, const uint64_t *in, uint64_t *out,
+                                                     int level, int n_out, const double *qlinv, const double *qlinvq,
+                                                     int nq, const double *tw, const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int w = blockIdx.y, z = w / n_out, i = w - z * n_out;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const Mod m = info[i].m;
+    const size_t t0 = (size_t)tile * kT;
+    const uint64_t *src = lifted + (size_t)w * N + t0;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = u2d(src[tid + 256 * k]);
+    tile_forward(v, s, tid, tile, logN1, tw + (size_t)i * N, N, m);
+    const uint64_t *a = in + ((size_t)z * (level + 1) + i) * N + t0;
+    uint64_t *o = out + ((size_t)z * n_out + i) * N + t0;
+    const double wl = qlinv[level * nq + i], wlq = qlinvq[level * nq + i];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int x = tid + 256 * k;
+        o[x] = d2u(mul_shoup(sub_mod(u2d(a[x]), s[pad16(x)], m), wl, wlq, m));
+    }
+}
+
 template <bool INV>
 static hipError_t launch_cols(const nj_ctx *c, int kind, double bytes, int N1, dim3 grid, hipStream_t s,
                               uint64_t *data, const uint64_t *src, const LimbTab &lt, const double *tw,
@@ -379,6 +430,36 @@ hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *s
     if (e != hipSuccess) return e;
     return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt, c->d_itw,
                              c->d_info, c->log_n, scale);
+}
+
+// Rescale of a level-l ciphertext (limbs 0..n_out-1 of each polynomial kept), N >= 8192:
+// inverse transform of the two last limbs read in place (into last [2][N]), lift fused
+// with the column pass (into lifted [2][n_out][N], which may be out: each tile block
+// reads its own lifted words before writing them), tile pass fused with the combine.
+// in must not alias out.
+hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
+                                uint64_t *last, uint64_t *lifted, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2 || n_out < 1 || n_out > level) return hipErrorInvalidValue;
+    LimbTab lt;
+    lt.n = 2;
+    lt.pidx[0] = lt.pidx[1] = level;
+    lt.off[0] = 0, lt.off[1] = 1;
+    lt.soff[0] = level, lt.soff[1] = 2 * level + 1;
+    hipError_t e = launch_ntt_fast(c, last, in, lt, true, s);
+    if (e != hipSuccess) return e;
+    const dim3 gl(kT / kNT, n_out, 2);
+    const double bl = 8.0 * N * 2 * (1 + n_out);
+    switch (N1) {
+    case 2: e = launch(c, PROF_OTHER, bl, k_lift_col<2>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n); break;
+    case 4: e = launch(c, PROF_OTHER, bl, k_lift_col<4>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n); break;
+    case 8: e = launch(c, PROF_OTHER, bl, k_lift_col<8>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n); break;
+    default: e = launch(c, PROF_OTHER, bl, k_lift_col<16>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n);
+    }
+    if (e != hipSuccess) return e;
+    return launch(c, PROF_OTHER, 8.0 * N * 2 * n_out * 4.0, k_ntt_tile_rs, dim3(N1, 2 * n_out), dim3(kNT), s, lifted,
+                  in, out, level, n_out, c->d_qlinv, c->d_qlinvq, c->n_q, c->d_tw, c->d_info, c->log_n);
 }
 
 // Forward tile pass alone (the column pass already applied), N >= 8192.

@@ -24,7 +24,9 @@ the inputs.  Scale rules:
     round(c * tau * q_{lam+1} / s), rescale -> level lam, scale recorded as tau.
   * add_const(ct, c): add round(c * s) to the constant coefficient of c0.
   * sums combine ciphertexts recorded at the same scale.
-Chebyshev evaluation, baby steps T_1..T_7 and giant steps T_8, T_16, T_32:
+Chebyshev evaluation, baby steps T_1..T_7 and giant steps T_8, T_16, T_32 (a sum
+  sum_j c_j T_j of baby steps takes each term's integer round(c_j tau q_{lam+1} / s_j)
+  at level lam + 1 and rescales the sum once):
   T_2j = 2 T_j^2 - 1;  T_{a+b} = 2 T_a T_b - T_{a-b} (T_{a-b} brought to the
   product's level and scale by const_mult with c = 1);
   p = q T_G + r with q_0 = c_G, q_j = 2 c_{G+j}, r_i = c_i - c_{2G-i} (the Chebyshev
@@ -172,15 +174,22 @@ class Boot:
         c = np.asarray(c, dtype=np.float64)
         d = len(c) - 1
         if d < 8:
+            # sum_j k_j T_j at level lam + 1 with k_j = round(c_j tau q_{lam+1} / s_j) (each
+            # term then stands at scale tau q_{lam+1}), one rescale for the whole sum
+            q = float(self.R.q[lam + 1])
             acc = None
             for j in range(1, d + 1):
                 if c[j] == 0.0:
                     continue
-                t = self.const_mult(T[j], c[j], lam, tau)
-                if t is not None:
-                    acc = t if acc is None else self.add(acc, t)
+                k = int(np.rint(c[j] * tau * q / T[j][2]))
+                if k == 0:
+                    continue
+                y = self.mul_int(self.drop(T[j], lam + 1), k)
+                acc = y if acc is None else self.add(acc, y)
             if acc is None:
                 acc = self.zero(lam, tau)
+            else:
+                acc = (self.ctx.ct_rescale(lam + 1, acc[0]), lam, tau)
             return self.add_const(acc, c[0])
         G = 32 if d >= 32 else (16 if d >= 16 else 8)
         q, r = cheb_split(c, G)

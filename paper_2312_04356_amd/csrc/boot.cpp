@@ -181,20 +181,28 @@ class Ev {
     {
         const int d = (int)cf.size() - 1;
         if (d < 8) {
+            // sum_j k_j T_j at level lam + 1, k_j = round(c_j tau q_{lam+1} / s_j) (every term
+            // then at scale tau q_{lam+1}), accumulated in place; one rescale for the sum
+            const double ql = (double)c->primes[lam + 1];
             Cx acc;
             for (int j = 1; j <= d; j++) {
                 if (cf[j] == 0.0) continue;
-                Cx t = const_mult(T[j], cf[j], lam, tau);
-                if (!t.d) continue;
-                if (!acc.d) {
-                    acc = t;
-                } else {
-                    Cx sum = add(acc, t, 0);
-                    release(acc), release(t);
-                    acc = sum;
-                }
+                const long long k = (long long)std::nearbyint(cf[j] * tau * ql / T[j].s);
+                if (k == 0) continue;
+                if (!acc.d) acc = alloc(lam + 1, 0.0);
+                if (!ok()) return acc;
+                check(launch_mul_int(c, T[j].d, N * (T[j].l + 1), acc.d, lam + 2, residues(k, lam + 2), s,
+                                     acc.s != 0.0 ? 1 : 0));
+                acc.s = tau * ql;
             }
-            if (!acc.d) acc = zero(lam, tau);
+            if (!acc.d) {
+                acc = zero(lam, tau);
+            } else {
+                Cx o = alloc(lam, tau);
+                if (ok()) check(rescale(c, lam + 1, acc.d, o.d, ks, s));
+                release(acc);
+                acc = o;
+            }
             add_const(acc, cf[0]);
             return acc;
         }

@@ -26,17 +26,20 @@ __global__ __launch_bounds__(kT) void k_tensor(const uint64_t *a, size_t astride
     d2[o] = d2u(mul_canon(x1, y1, m));
 }
 
-// out [2][n_limbs][N] = in (limbs 0..n_limbs-1 of each polynomial, second at +istride)
-// times the integer whose residue mod q_i is kc.v[i]
+// out [2][n_limbs][N] (+)= in (limbs 0..n_limbs-1 of each polynomial, second at
+// +istride) times the integer whose residue mod q_i is kc.v[i]
 __global__ __launch_bounds__(kT) void k_mul_int(const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
-                                                LimbConsts kc, const PrimeInfo *info, int logN)
+                                                LimbConsts kc, int accumulate, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN, i = blockIdx.y, p = blockIdx.z;
     const int k = blockIdx.x * kT + threadIdx.x;
     if (k >= N) return;
     const Mod m = info[i].m;
     const double x = u2d(in[p * istride + (size_t)i * N + k]);
-    out[((size_t)p * n_limbs + i) * N + k] = d2u(mul_canon(x, kc.v[i], m));
+    const size_t o = ((size_t)p * n_limbs + i) * N + k;
+    double r = mul_canon(x, kc.v[i], m);
+    if (accumulate) r = add_mod(r, u2d(out[o]), m);
+    out[o] = d2u(r);
 }
 
 // limbs 0..n_limbs-1 of poly (in place) += kc.v[i] (mod q_i)
@@ -65,11 +68,11 @@ hipError_t launch_tensor(const nj_ctx *c, const uint64_t *a, size_t astride, con
 }
 
 hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
-                          const LimbConsts &kc, hipStream_t s)
+                          const LimbConsts &kc, hipStream_t s, int accumulate)
 {
     dim3 grid((c->N + kT - 1) / kT, n_limbs, 2);
-    return launch(c, PROF_OTHER, 8.0 * c->N * n_limbs * 4.0, k_mul_int, grid, dim3(kT), s, in, istride, out, n_limbs,
-                  kc, c->d_info, c->log_n);
+    return launch(c, PROF_OTHER, 8.0 * c->N * n_limbs * (accumulate ? 6.0 : 4.0), k_mul_int, grid, dim3(kT), s, in,
+                  istride, out, n_limbs, kc, accumulate, c->d_info, c->log_n);
 }
 
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s)

@@ -317,7 +317,7 @@ hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, 
 hipError_t launch_tensor(const nj_ctx *c, const uint64_t *a, size_t astride, const uint64_t *b, size_t bstride,
                          uint64_t *d01, uint64_t *d2, int level, hipStream_t s);
 hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
-                          const LimbConsts &kc, hipStream_t s);
+                          const LimbConsts &kc, hipStream_t s, int accumulate = 0);
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s);
 hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
 hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int accumulate,

@@ -720,16 +720,20 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 }
 
 // rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
-nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out)
+nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out,
+                  int n_polys)
 {
     const size_t N = c->N;
     if (n_out < 0) n_out = l;
-    uint64_t *last = A.take(2 * N), *lifted = A.take(N * l);
-    if (!lifted) return fail(NJ_ENOMEM, "scratch too small");
     if (N >= 8192) {  // the lifted limbs stay in out, transformed and combined in place
-        NJ_HIP(launch_rescale_fused(c, l, in, out, n_out, last, out, s));
+        uint64_t *last = A.take(n_polys * N);
+        if (!last) return fail(NJ_ENOMEM, "scratch too small");
+        NJ_HIP(launch_rescale_fused(c, l, in, out, n_out, last, out, s, n_polys));
         return NJ_OK;
     }
+    if (n_polys != 2) return fail(NJ_EUNSUPPORTED, "rescale: packed ciphertexts need N >= 8192");
+    uint64_t *last = A.take(2 * N), *lifted = A.take(N * l);
+    if (!lifted) return fail(NJ_ENOMEM, "scratch too small");
     for (int p = 0; p < 2; p++)
         NJ_HIP(hipMemcpyAsync(last + p * N, in + ((size_t)p * (l + 1) + l) * N, N * 8, hipMemcpyDeviceToDevice, s));
     LimbTab lt;

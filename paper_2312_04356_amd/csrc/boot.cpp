@@ -25,23 +25,25 @@ namespace {
 constexpr int kChebDegree = 63;
 
 struct Cx {
-    uint64_t *d = nullptr;  // [2][l+1][N], evaluation form
+    uint64_t *d = nullptr;  // [K][2][l+1][N], evaluation form (K ciphertexts packed)
     int l = 0;
     double s = 0.0;
 };
 
-// Ciphertext buffers of one evaluation: fixed-size slots (a level-lmax ciphertext
+// Ciphertext buffers of one evaluation: fixed-size slots (K level-lmax ciphertexts
 // each) from an arena with a free list; the key-switch scratch is a separate arena.
+// Every operation applies to the K packed ciphertexts at once (K > 1 needs N >= 8192).
 class Ev {
   public:
-    Ev(nj_ctx *c, int lmax, Arena cts, Arena ks, hipStream_t s) : c(c), N(c->N), lmax(lmax), cts(cts), ks(ks), s(s)
+    Ev(nj_ctx *c, int lmax, Arena cts, Arena ks, hipStream_t s, int K = 1)
+        : c(c), N(c->N), lmax(lmax), K(K), cts(cts), ks(ks), s(s)
     {
         relin = key_of(c, 0);
         if (!relin) err = fail(NJ_ENOKEY, "no relinearisation key (Galois element 0)");
     }
     nj_ctx *c;
     size_t N;
-    int lmax;
+    int lmax, K;
     Arena cts, ks;
     hipStream_t s;
     nj_status err = NJ_OK;
@@ -49,7 +51,8 @@ class Ev {
     std::vector<uint64_t *> free_;
 
     static size_t slots_needed() { return 48; }
-    size_t slot_words() const { return 2 * N * (lmax + 1); }
+    size_t slot_words() const { return (size_t)K * 2 * N * (lmax + 1); }
+    size_t cstride(int l) const { return 2 * N * (l + 1); }  // words between packed ciphertexts
     bool ok() const { return err == NJ_OK; }
     void check(hipError_t e)
     {
@@ -88,45 +91,57 @@ class Ev {
         }
         return kc;
     }
+    // x rescaled by q_l into o (both packed)
+    void rescale_into(const Cx &x, Cx &o, Arena A) { check(rescale(c, x.l, x.d, o.d, A, s, -1, 2 * K)); }
 
     Cx add(const Cx &a, const Cx &b, int op)  // op 0: a + b, 1: a - b (same level)
     {
         Cx o = alloc(a.l, a.s);
-        if (ok()) check(launch_elementwise(c, op, a.d, b.d, o.d, ct_limbs(a.l), s));
+        if (!ok()) return o;
+        LimbTab lt;
+        lt.n = 2 * K * (a.l + 1);
+        for (int k = 0; k < lt.n; k++) lt.pidx[k] = k % (a.l + 1), lt.off[k] = k;
+        check(launch_elementwise(c, op, a.d, b.d, o.d, lt, s));
         return o;
     }
     void add_const(Cx &x, double v)
     {
         const long long k = (long long)std::nearbyint(v * x.s);
-        if (ok()) check(launch_add_int(c, x.d, x.l + 1, residues(k, x.l + 1), s));
+        for (int z = 0; z < K && ok(); z++)
+            check(launch_add_int(c, x.d + z * cstride(x.l), x.l + 1, residues(k, x.l + 1), s));
     }
     Cx zero(int l, double sc)
     {
         Cx o = alloc(l, sc);
-        if (ok()) check(launch_zero(c, o.d, 2 * N * (l + 1), s));
+        if (ok()) check(launch_zero(c, o.d, K * cstride(l), s));
         return o;
     }
     // tensor product, relinearisation, rescale
     Cx hmult(const Cx &a, const Cx &b)
     {
         const int l = std::min(a.l, b.l);
-        Cx t = alloc(l, 0.0), d2 = alloc(l, 0.0);
+        Cx t = alloc(l, 0.0), d2 = alloc(l, 0.0);  // t [K][2][l+1], d2 [K][l+1]
         Cx o = alloc(l - 1, a.s * b.s / (double)c->primes[l]);
         if (!ok()) return o;
-        check(launch_tensor(c, a.d, N * (a.l + 1), b.d, N * (b.l + 1), t.d, d2.d, l, s));
+        for (int z = 0; z < K; z++)
+            check(launch_tensor(c, a.d + z * cstride(a.l), N * (a.l + 1), b.d + z * cstride(b.l), N * (b.l + 1),
+                                t.d + z * cstride(l), d2.d + z * N * (l + 1), l, s));
         Arena A = ks;
-        MultiBufs M;  // the batched key-switch path with one job: its fused kernels
-        if (!multi_bufs(c, l, 1, A, M)) {
+        MultiBufs M;  // the batched key-switch path: its fused kernels, one job per ciphertext
+        if (!multi_bufs(c, l, K, A, M)) {
             check(fail(NJ_ENOMEM, "ModEval: key-switch scratch"));
             return o;
         }
-        check(modup_multi(c, l, 1, d2.d, M, s));
+        check(modup_multi(c, l, K, d2.d, M, s));
+        const size_t nd = n_digits(c, l), ne = l + 1 + c->alpha;
         KeyJobs kj;
-        kj.ext[0] = M.ext, kj.d[0] = d2.d, kj.key[0] = relin, kj.g[0] = 1;
         MdJobs mj;
-        mj.add[0] = nullptr, mj.g_add[0] = 1, mj.out[0] = t.d;
-        check(ks_multi(c, l, 1, kj, mj, 0, t.d, M, s));  // t += the switched d2
-        check(rescale(c, l, t.d, o.d, A, s));
+        for (int z = 0; z < K; z++) {
+            kj.ext[z] = M.ext + z * nd * ne * N, kj.d[z] = d2.d + z * N * (l + 1), kj.key[z] = relin, kj.g[z] = 1;
+            mj.add[z] = nullptr, mj.g_add[z] = 1, mj.out[z] = t.d + z * cstride(l);
+        }
+        check(ks_multi(c, l, K, kj, mj, 0, t.d, M, s));  // t += the switched d2
+        rescale_into(t, o, A);
         release(t), release(d2);
         return o;
     }
@@ -139,8 +154,8 @@ class Ev {
         Cx t = alloc(lam + 1, 0.0);
         o = alloc(lam, tau);
         if (!ok()) return o;
-        check(launch_mul_int(c, x.d, N * (x.l + 1), t.d, lam + 2, residues(k, lam + 2), s));
-        check(rescale(c, lam + 1, t.d, o.d, ks, s));
+        check(launch_mul_int(c, x.d, N * (x.l + 1), t.d, lam + 2, residues(k, lam + 2), s, 0, 2 * K));
+        rescale_into(t, o, ks);
         release(t);
         return o;
     }
@@ -192,14 +207,14 @@ class Ev {
                 if (!acc.d) acc = alloc(lam + 1, 0.0);
                 if (!ok()) return acc;
                 check(launch_mul_int(c, T[j].d, N * (T[j].l + 1), acc.d, lam + 2, residues(k, lam + 2), s,
-                                     acc.s != 0.0 ? 1 : 0));
+                                     acc.s != 0.0 ? 1 : 0, 2 * K));
                 acc.s = tau * ql;
             }
             if (!acc.d) {
                 acc = zero(lam, tau);
             } else {
                 Cx o = alloc(lam, tau);
-                if (ok()) check(rescale(c, lam + 1, acc.d, o.d, ks, s));
+                if (ok()) rescale_into(acc, o, ks);
                 release(acc);
                 acc = o;
             }
@@ -225,27 +240,30 @@ class Ev {
     }
 };
 
-size_t eval_mod_words(const nj_ctx *c, int l0)
+size_t eval_mod_words(const nj_ctx *c, int l0, int K = 1)
 {
-    return Ev::slots_needed() * 2 * (size_t)c->N * (l0 + 1) + ks_words(c, l0) + (size_t)c->N * (l0 + 3);
+    return Ev::slots_needed() * K * 2 * (size_t)c->N * (l0 + 1) +
+           std::max(ks_words(c, l0), multi_words(c, l0, K)) + (size_t)c->N * (l0 + 3) * K;
 }
 
-// ModEval of ct (level l0, scale s0): out at level l0 - 11
-nj_status eval_mod(nj_ctx *c, const uint64_t *in, int l0, double s0, double K, const double *cf, uint64_t *out,
-                   double *out_scale, Arena A, hipStream_t s)
+// ModEval of K ciphertexts in[z] (level l0, scale s0) evaluated together (packed; K > 1
+// needs N >= 8192): out[z] at level l0 - 11
+nj_status eval_mod(nj_ctx *c, int K, const uint64_t *const *in, int l0, double s0, double Kr, const double *cf,
+                   uint64_t *const *out, double *out_scale, Arena A, hipStream_t s)
 {
-    const size_t N = c->N;
-    uint64_t *ctsbuf = A.take(Ev::slots_needed() * 2 * N * (l0 + 1));
+    const size_t N = c->N, pool = Ev::slots_needed() * K * 2 * N * (l0 + 1);
+    uint64_t *ctsbuf = A.take(pool);
     if (!ctsbuf) return fail(NJ_ENOMEM, "scratch");
-    Ev ev(c, l0, Arena{ctsbuf, Ev::slots_needed() * 2 * N * (l0 + 1)}, A, s);
+    Ev ev(c, l0, Arena{ctsbuf, pool}, A, s, K);
     if (!ev.ok()) return ev.err;
     const double q0 = (double)c->primes[0];
-    const double sx = K * q0;  // the same integers read as x = t / (K P)
+    const double sx = Kr * q0;  // the same integers read as x = t / (K P)
     const long long k = (long long)std::nearbyint(std::ldexp(1.0, 48) * (double)c->primes[l0] / sx);
     Cx t = ev.alloc(l0, 0.0), x = ev.alloc(l0 - 1, sx * (double)k / (double)c->primes[l0]);
     if (!ev.ok()) return ev.err;
-    ev.check(launch_mul_int(c, in, N * (l0 + 1), t.d, l0 + 1, ev.residues(k, l0 + 1), s));
-    ev.check(rescale(c, l0, t.d, x.d, ev.ks, s));
+    for (int z = 0; z < K; z++)
+        ev.check(launch_mul_int(c, in[z], N * (l0 + 1), t.d + z * ev.cstride(l0), l0 + 1, ev.residues(k, l0 + 1), s));
+    ev.rescale_into(t, x, ev.ks);
     ev.release(t);
     ev.basis(x);
     const int lam = x.l - 7;
@@ -256,7 +274,8 @@ nj_status eval_mod(nj_ctx *c, const uint64_t *in, int l0, double s0, double K, c
         g = h;
     }
     if (!ev.ok()) return ev.err;
-    NJ_HIP(hipMemcpyAsync(out, g.d, 2 * N * (g.l + 1) * 8, hipMemcpyDeviceToDevice, s));
+    for (int z = 0; z < K; z++)
+        NJ_HIP(hipMemcpyAsync(out[z], g.d + z * ev.cstride(g.l), 2 * N * (g.l + 1) * 8, hipMemcpyDeviceToDevice, s));
     *out_scale = g.s * (2.0 * M_PI) * s0 / q0;
     return NJ_OK;
 }
@@ -354,10 +373,49 @@ nj_status nj_eval_mod(nj_ctx *c, const nj_ct *in, int K, int r, const double *co
     Arena A = arena_for(c, eval_mod_words(c, in->level), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
     double sc = 0.0;
-    if ((st = eval_mod(c, in->data, in->level, in->scale, (double)K, cf.data(), out->data, &sc, A, S(stream)))) return st;
+    const uint64_t *ins[1] = {in->data};
+    uint64_t *outs[1] = {out->data};
+    if ((st = eval_mod(c, 1, ins, in->level, in->scale, (double)K, cf.data(), outs, &sc, A, S(stream)))) return st;
     out->level = in->level - kEvalModLevels, out->is_ntt = 1, out->scale = sc;
     return NJ_OK;
 }
+
+}  // extern "C"
+
+// ModEval of Re and Im together (one packed evaluation, N >= 8192; else one after the
+// other): the same results as two nj_eval_mod calls
+nj_status nj::ex::eval_mod_pair(nj_ctx *c, const nj_ct *re, const nj_ct *im, int K, int r, const double *coeffs,
+                                int n_coeffs, nj_ct *out_re, nj_ct *out_im, void *stream)
+{
+    nj_status st;
+    if (c->N < 8192) {
+        if ((st = nj_eval_mod(c, re, K, r, coeffs, n_coeffs, out_re, stream))) return st;
+        return nj_eval_mod(c, im, K, r, coeffs, n_coeffs, out_im, stream);
+    }
+    st = check_ct(c, re, "nj_eval_mod");
+    if (st || (st = check_ct(c, im, "nj_eval_mod"))) return st;
+    if (re->level != im->level || re->scale != im->scale) return fail(NJ_ELEVEL, "eval_mod_pair: Re and Im differ");
+    if (K < 1 || r != 3 || (coeffs && n_coeffs != kChebDegree + 1))
+        return fail(NJ_EUNSUPPORTED, "nj_eval_mod: supports r = 3 double angles and 64 Chebyshev coefficients");
+    if (re->level < kEvalModLevels + 1) return fail(NJ_ELEVEL, "nj_eval_mod: needs input level >= 12");
+    if (!out_re || !out_im || !out_re->data || !out_im->data) return fail(NJ_EINVAL, "eval_mod_pair: bad output");
+    std::vector<double> cf(kChebDegree + 1);
+    if (coeffs) std::copy(coeffs, coeffs + kChebDegree + 1, cf.begin());
+    else cheb_interpolate_cos(kChebDegree, (double)K, r, cf.data());
+    bool ok;
+    Arena A = arena_for(c, eval_mod_words(c, re->level, 2), ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    const uint64_t *ins[2] = {re->data, im->data};
+    uint64_t *outs[2] = {out_re->data, out_im->data};
+    double sc = 0.0;
+    if ((st = eval_mod(c, 2, ins, re->level, re->scale, (double)K, cf.data(), outs, &sc, A, S(stream)))) return st;
+    out_re->level = out_im->level = re->level - kEvalModLevels;
+    out_re->is_ntt = out_im->is_ntt = 1;
+    out_re->scale = out_im->scale = sc;
+    return NJ_OK;
+}
+
+extern "C" {
 
 nj_status nj_combine(nj_ctx *c, const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream)
 {

@@ -26,8 +26,8 @@ __global__ __launch_bounds__(kT) void k_tensor(const uint64_t *a, size_t astride
     d2[o] = d2u(mul_canon(x1, y1, m));
 }
 
-// out [2][n_limbs][N] (+)= in (limbs 0..n_limbs-1 of each polynomial, second at
-// +istride) times the integer whose residue mod q_i is kc.v[i]
+// out [P][n_limbs][N] (+)= in (limbs 0..n_limbs-1 of polynomial p at +p istride, P =
+// gridDim.z) times the integer whose residue mod q_i is kc.v[i]
 __global__ __launch_bounds__(kT) void k_mul_int(const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
                                                 LimbConsts kc, int accumulate, const PrimeInfo *info, int logN)
 {
@@ -68,11 +68,11 @@ hipError_t launch_tensor(const nj_ctx *c, const uint64_t *a, size_t astride, con
 }
 
 hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
-                          const LimbConsts &kc, hipStream_t s, int accumulate)
+                          const LimbConsts &kc, hipStream_t s, int accumulate, int n_polys)
 {
-    dim3 grid((c->N + kT - 1) / kT, n_limbs, 2);
-    return launch(c, PROF_OTHER, 8.0 * c->N * n_limbs * (accumulate ? 6.0 : 4.0), k_mul_int, grid, dim3(kT), s, in,
-                  istride, out, n_limbs, kc, accumulate, c->d_info, c->log_n);
+    dim3 grid((c->N + kT - 1) / kT, n_limbs, n_polys);
+    return launch(c, PROF_OTHER, 8.0 * c->N * n_limbs * (accumulate ? 3.0 : 2.0) * n_polys, k_mul_int, grid, dim3(kT),
+                  s, in, istride, out, n_limbs, kc, accumulate, c->d_info, c->log_n);
 }
 
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s)

@@ -61,6 +61,9 @@ size_t multi_words(const nj_ctx *c, int l, int K);
 bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
 // ModUp of K polynomials at d + z dstride N (dstride in limbs, l+1 when packed)
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1);
+// ModEval of Re and Im evaluated together (packed) when N >= 8192
+nj_status eval_mod_pair(nj_ctx *c, const nj_ct *re, const nj_ct *im, int K, int r, const double *coeffs,
+                        int n_coeffs, nj_ct *out_re, nj_ct *out_im, void *stream);
 // K key switches on ModUp'ed digits (M.ext): key inner products, then ks_down
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s);
@@ -89,7 +92,9 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 
 // rescale [2][l+1] -> [2][l]; n_out < l keeps only the first n_out limbs of the result
 // (rescale followed by a level drop, computing only the kept limbs)
-nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out = -1);
+// n_polys > 2 (several ciphertexts packed at level l) needs N >= 8192
+nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out = -1,
+                  int n_polys = 2);
 nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s);
 nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t *im, Arena A, hipStream_t s);
 

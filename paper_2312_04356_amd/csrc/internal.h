@@ -259,7 +259,7 @@ hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool i
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
                               const double *scale, hipStream_t s);
 hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
-                                uint64_t *last, uint64_t *lifted, hipStream_t s);
+                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys = 2);
 hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);
 hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
@@ -317,7 +317,7 @@ hipError_t launch_bsgs_mac_multi(const nj_ctx *c, int level, const MacPlan &mp, 
 hipError_t launch_tensor(const nj_ctx *c, const uint64_t *a, size_t astride, const uint64_t *b, size_t bstride,
                          uint64_t *d01, uint64_t *d2, int level, hipStream_t s);
 hipError_t launch_mul_int(const nj_ctx *c, const uint64_t *in, size_t istride, uint64_t *out, int n_limbs,
-                          const LimbConsts &kc, hipStream_t s, int accumulate = 0);
+                          const LimbConsts &kc, hipStream_t s, int accumulate = 0, int n_polys = 2);
 hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const LimbConsts &kc, hipStream_t s);
 hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
 hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int accumulate,

@@ -79,8 +79,7 @@ nj_status nj_slot_activation(nj_ctx *c, int K, int r, const double *coeffs, int 
     nj_ct s[kTailSlots];
     for (int i = 0; i < kTailSlots; i++) s[i] = slot_ct(layer_slot(c, kTailSlots, i));
     nj_status st;
-    if ((st = nj_eval_mod(c, re, K, r, coeffs, n_coeffs, &s[0], stream))) return st;
-    if ((st = nj_eval_mod(c, im, K, r, coeffs, n_coeffs, &s[1], stream))) return st;
+    if ((st = ex::eval_mod_pair(c, re, im, K, r, coeffs, n_coeffs, &s[0], &s[1], stream))) return st;
     nj_ct *cr = &s[0], *ci = &s[1];
     if (mask_re) {  // masks encoded at q_l: PMult then rescale by q_l leaves the scale as it was
         const double sc = cr->scale;

@@ -329,8 +329,8 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const
 }
 
 // Rescale by q_l, fused into the lifted limbs' transform (N >= 8192).  k_lift_col: the
-// last limb of each polynomial (coefficient form, last [2][N]) lifted centred into
-// target limb i, then the forward column pass; grid (4096/256, n_out, 2).
+// last limb of each polynomial (coefficient form, last [P][N]) lifted centred into
+// target limb i, then the forward column pass; grid (4096/256, n_out, P).
 template <int N1>
 __global__ __launch_bounds__(kNT) void k_lift_col(const uint64_t *last, int src_pidx, int n_out, uint64_t *lifted,
                                                   const double *tw, const PrimeInfo *info, int logN)
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kNT) void k_lift_col(const uint64_t *last, int src_
 }
 
 // k_ntt_tile_rs: the lifted limbs' tile pass with the rescale combine as its epilogue,
-// out[z][i] = (in[z][i] - NTT(lift)[z][i]) q_l^-1 mod q_i; grid (N/4096, 2 n_out).
+// out[z][i] = (in[z][i] - NTT(lift)[z][i]) q_l^-1 mod q_i; grid (N/4096, P n_out).
 __global__ __launch_bounds__(kNT) void k_ntt_tile_rs(const uint64_t *lifted, const uint64_t *in, uint64_t *out,
                                                      int level, int n_out, const double *qlinv, const double *qlinvq,
                                                      int nq, const double *tw, const PrimeInfo *info, int logN)
@@ -432,25 +432,23 @@ hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *s
                              c->d_info, c->log_n, scale);
 }
 
-// Rescale of a level-l ciphertext (limbs 0..n_out-1 of each polynomial kept), N >= 8192:
-// inverse transform of the two last limbs read in place (into last [2][N]), lift fused
-// with the column pass (into lifted [2][n_out][N], which may be out: each tile block
-// reads its own lifted words before writing them), tile pass fused with the combine.
-// in must not alias out.
+// Rescale of P packed level-l polynomials (P = 2 per ciphertext; limbs 0..n_out-1 of
+// each kept), N >= 8192: inverse transform of the last limbs read in place (into
+// last [P][N]), lift fused with the column pass (into lifted [P][n_out][N], which may be
+// out: each tile block reads its own lifted words before writing them), tile pass
+// fused with the combine.  in must not alias out.
 hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
-                                uint64_t *last, uint64_t *lifted, hipStream_t s)
+                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys)
 {
     const int N = c->N, N1 = N / kT;
-    if (N1 < 2 || n_out < 1 || n_out > level) return hipErrorInvalidValue;
+    if (N1 < 2 || n_out < 1 || n_out > level || n_polys < 1 || n_polys > NJ_MAX_LIMBS) return hipErrorInvalidValue;
     LimbTab lt;
-    lt.n = 2;
-    lt.pidx[0] = lt.pidx[1] = level;
-    lt.off[0] = 0, lt.off[1] = 1;
-    lt.soff[0] = level, lt.soff[1] = 2 * level + 1;
+    lt.n = n_polys;
+    for (int p = 0; p < n_polys; p++) lt.pidx[p] = level, lt.off[p] = p, lt.soff[p] = p * (level + 1) + level;
     hipError_t e = launch_ntt_fast(c, last, in, lt, true, s);
     if (e != hipSuccess) return e;
-    const dim3 gl(kT / kNT, n_out, 2);
-    const double bl = 8.0 * N * 2 * (1 + n_out);
+    const dim3 gl(kT / kNT, n_out, n_polys);
+    const double bl = 8.0 * N * n_polys * (1 + n_out);
     switch (N1) {
     case 2: e = launch(c, PROF_OTHER, bl, k_lift_col<2>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n); break;
     case 4: e = launch(c, PROF_OTHER, bl, k_lift_col<4>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n); break;
@@ -458,8 +456,8 @@ hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, 
     default: e = launch(c, PROF_OTHER, bl, k_lift_col<16>, gl, dim3(kNT), s, last, level, n_out, lifted, c->d_tw, c->d_info, c->log_n);
     }
     if (e != hipSuccess) return e;
-    return launch(c, PROF_OTHER, 8.0 * N * 2 * n_out * 4.0, k_ntt_tile_rs, dim3(N1, 2 * n_out), dim3(kNT), s, lifted,
-                  in, out, level, n_out, c->d_qlinv, c->d_qlinvq, c->n_q, c->d_tw, c->d_info, c->log_n);
+    return launch(c, PROF_OTHER, 8.0 * N * n_polys * n_out * 4.0, k_ntt_tile_rs, dim3(N1, n_polys * n_out), dim3(kNT),
+                  s, lifted, in, out, level, n_out, c->d_qlinv, c->d_qlinvq, c->n_q, c->d_tw, c->d_info, c->log_n);
 }
 
 // Forward tile pass alone (the column pass already applied), N >= 8192.

@@ -154,3 +154,30 @@ def test_conv_act_layer_full_size():
     print("full-size layer: output level %d, max |out - model^2| %.2e on pixels, max |out| %.2e on padding"
           % (y.level, err, err_pad))
     assert err < 2e-2 and err_pad < 2e-2
+
+
+def test_slot_activation_full_size_equals_single_calls():
+    """at N = 2^16 ModEval of Re and Im runs as one packed evaluation: the tail equals,
+    word for word, single-ciphertext ModEval calls followed by Re + i Im and StoC1"""
+    g = GpuWorkload("full", with_cts=True, lazy=True)
+    gctx = g.ctx
+    lo = gctx.L - g.w["cts_groups"]
+    stoc1 = gctx.nj_stoc1_plan_create(g.ell, 3, lo - 11)
+    a, e = synth.key_randomness(g.q + g.p, g.N, gctx.dnum, g.w["key_seed"], synth.RELIN_KEY_ID)
+    gctx.nj_gen_switch_key(0, a, e)
+    g.make_keys(sorted(set(g.galois_elements()) | set(stoc1.galois())))
+    ct = g.encrypt_input(1)
+    y = gctx.empty_ct(0)
+    gctx.nj_conv2d_cins(g.conv_plan, ct, y)
+    re, im = gctx.empty_ct(lo), gctx.empty_ct(lo)
+    gctx.nj_coeff_to_slot(g.cts_plan, y, re, im)
+    out = gctx.empty_ct(lo - 14)
+    gctx.nj_slot_activation(32, 3, None, None, None, 0, stoc1, re, im, out)
+    er, ei, z = gctx.empty_ct(lo - 11), gctx.empty_ct(lo - 11), gctx.empty_ct(lo - 11)
+    gctx.nj_eval_mod(re, 32, 3, None, er)
+    gctx.nj_eval_mod(im, 32, 3, None, ei)
+    gctx.nj_combine(er, ei, z)
+    want = gctx.empty_ct(lo - 14)
+    gctx.nj_stoc1(stoc1, z, want)
+    assert out.level == want.level and out.scale == want.scale
+    assert torch.equal(out.data, want.data)

@@ -28,14 +28,14 @@ def family(name):
         return "k_key_ip"
     if n.startswith("k_bsgs_mac"):
         return "k_pmac"
-    if n in OTHER:
+    if n in OTHER or n.startswith("k_lift_col"):
         return "other"
     return n
 
 
 # kernels the library times together under "other"
 OTHER = ("k_moddown2", "k_moddown_multi", "k_automorph_multi", "k_automorph_acc", "k_tensor", "k_mul_int",
-         "k_add_int", "k_zero")
+         "k_add_int", "k_zero", "k_ntt_tile_rs")
 
 
 def main(trace, bench_json, plain_json, command):

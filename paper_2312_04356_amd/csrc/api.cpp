@@ -18,25 +18,7 @@ namespace ex {
 
 
 
-size_t ks_words(const nj_ctx *c, int l)
-{
-    const size_t N = c->N, ne = l + 1 + c->alpha, beta = n_digits(c, l);
-    return N * (3 * (l + 1) + beta * ne + 2 * ne + 2 * c->alpha + 2 * (l + 1));
-}
-
-
-bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B)
-{
-    const size_t N = c->N, ne = l + 1 + c->alpha, beta = n_digits(c, l);
-    B.coef = A.take(N * (l + 1));
-    B.dtmp = A.take(N * (l + 1));
-    B.c0copy = A.take(N * (l + 1));
-    B.ext = A.take(N * beta * ne);
-    B.u = A.take(N * 2 * ne);
-    B.pc = A.take(N * 2 * c->alpha);
-    B.conv = A.take(N * 2 * (l + 1));
-    return B.conv != nullptr;
-}
+size_t ks_words(const nj_ctx *c, int l) { return multi_words(c, l, 1) + (size_t)c->N * (l + 1); }
 
 const uint64_t *key_of(const nj_ctx *c, uint32_t g)
 {
@@ -46,112 +28,40 @@ const uint64_t *key_of(const nj_ctx *c, uint32_t g)
     return nullptr;
 }
 
-// ModUp of d (evaluation form, level l): every digit extended to Q_l u P, evaluation form.
-nj_status modup_ext(nj_ctx *c, int l, const uint64_t *d, KsBufs &B, hipStream_t s)
+// One key switch of d (evaluation form, level l) with `key`: ModUp, inner product,
+// ModDown, and out = (ModDown_0 + add read through X -> X^g_add, ModDown_1) (add may
+// be null).  The single-job case of the batched path, so it runs the same kernels.
+nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, const uint64_t *key, const uint64_t *add, uint32_t g_add,
+                 uint64_t *out, MultiBufs &M, hipStream_t s)
 {
-    const size_t N = c->N, ne = l + 1 + c->alpha;
-    LimbTab lq = limbs_q(l);
-    for (int i = 0; i <= l; i++) lq.soff[i] = i;
-    NJ_HIP(launch_ntt(c, B.coef, lq, true, s, d));  // coefficient form of d, out of place
-    // basis conversion of every digit (launches group digits of equal size, 4 at a time);
-    // a digit's own limbs are not copied: the inner product reads them from d
-    const int nd = n_digits(c, l);
-    for (int j0 = 0; j0 < nd;) {
-        BconvBatch bb;
-        bb.n = 0;
-        const int m = c->modup[l][j0].m;
-        int j = j0;
-        for (; j < nd && bb.n < 4 && c->modup[l][j].m == m; j++) {
-            const BconvTab &bt = c->modup[l][j];
-            BconvJob &jb = bb.job[bb.n++];
-            jb.in = B.coef;
-            jb.out = B.ext + (size_t)j * ne * N;
-            jb.hat_inv = bt.hat_inv;
-            jb.hat = bt.hat;
-            jb.m = bt.m;
-            jb.n_out = bt.n_out;
-            for (int a = 0; a < bt.m; a++) jb.in_pidx[a] = bt.in_pidx[a], jb.in_off[a] = j * c->alpha + a;
-            for (int o = 0; o < bt.n_out; o++) jb.out_pidx[o] = bt.out_pidx[o], jb.out_off[o] = bt.out_limb[o];
-        }
-        NJ_HIP(launch_bconv_batch(c, bb, s));
-        j0 = j;
-    }
-    // forward transform of every converted limb of every digit, 128 limbs per launch
-    LimbTab lt;
-    lt.n = 0;
-    for (int j = 0; j < nd; j++) {
-        const BconvTab &bt = c->modup[l][j];
-        for (int o = 0; o < bt.n_out; o++) {
-            lt.pidx[lt.n] = bt.out_pidx[o];
-            lt.off[lt.n] = j * (int)ne + bt.out_limb[o];
-            if (++lt.n == NJ_MAX_LIMBS) {
-                NJ_HIP(launch_ntt(c, B.ext, lt, false, s));
-                lt.n = 0;
-            }
-        }
-    }
-    NJ_HIP(launch_ntt(c, B.ext, lt, false, s));
-    return NJ_OK;
-}
-
-// Key inner product on the extended digits (read through X -> X^g_ip), then ModDown of
-// both halves; out0 additionally gets `add` read through X -> X^g_add.
-nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *d_own, const uint64_t *key, uint32_t g_ip, const uint64_t *add,
-                      uint32_t g_add, const uint64_t *acc, uint64_t *out, KsBufs &B, hipStream_t s)
-{
-    const size_t N = c->N, ne = l + 1 + c->alpha;
-    NJ_HIP(launch_key_ip2(c, l, B.ext, d_own, key, g_ip, B.u, s));
-    // special-prime limbs of both halves to coefficient form (out of place into pc)
-    LimbTab lp;
-    lp.n = 2 * c->alpha;
-    for (int k = 0; k < 2 * c->alpha; k++) {
-        const int p = k / c->alpha, a = k % c->alpha;
-        lp.pidx[k] = c->n_q + a, lp.off[k] = k, lp.soff[k] = p * (int)ne + l + 1 + a;
-    }
-    NJ_HIP(launch_ntt(c, B.pc, lp, true, s, B.u));
-    BconvBatch bb;
-    bb.n = 2;
-    const BconvTab &bt = c->moddown[l];
-    for (int p = 0; p < 2; p++) {
-        BconvJob &jb = bb.job[p];
-        jb.in = B.pc;
-        jb.out = B.conv + (size_t)p * (l + 1) * N;
-        jb.hat_inv = bt.hat_inv;
-        jb.hat = bt.hat;
-        jb.m = bt.m;
-        jb.n_out = bt.n_out;
-        for (int a = 0; a < bt.m; a++) jb.in_pidx[a] = bt.in_pidx[a], jb.in_off[a] = p * c->alpha + a;
-        for (int o = 0; o < bt.n_out; o++) jb.out_pidx[o] = bt.out_pidx[o], jb.out_off[o] = o;
-    }
-    NJ_HIP(launch_bconv_batch(c, bb, s));
-    LimbTab lq;
-    lq.n = 2 * (l + 1);
-    for (int k = 0; k < 2 * (l + 1); k++) lq.pidx[k] = k % (l + 1), lq.off[k] = k;
-    NJ_HIP(launch_ntt(c, B.conv, lq, false, s));
-    NJ_HIP(launch_moddown2(c, l, B.u, B.conv, add, g_add, acc, out, s));
-    return NJ_OK;
+    nj_status st = modup_multi(c, l, 1, d, M, s);
+    if (st) return st;
+    KeyJobs kj;
+    MdJobs mj;
+    kj.ext[0] = M.ext, kj.d[0] = d, kj.g[0] = 1, kj.key[0] = key;
+    mj.add[0] = add, mj.g_add[0] = g_add, mj.out[0] = out;
+    return ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
 }
 
 // (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
-// out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out);
-// in and out may alias.
-nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
-                       const uint64_t *acc)
+nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s)
 {
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
-    KsBufs B;
-    if (!ks_bufs(c, l, A, B)) return fail(NJ_ENOMEM, "scratch too small");
+    MultiBufs M;
+    if (!multi_bufs(c, l, 1, A, M)) return fail(NJ_ENOMEM, "scratch too small");
     const size_t N = c->N, plen = N * (l + 1);
-    NJ_HIP(launch_automorph(c, in + plen, B.dtmp, g, l + 1, s));
     const uint64_t *c0 = in;
-    if (in == out) {
-        NJ_HIP(hipMemcpyAsync(B.c0copy, in, plen * 8, hipMemcpyDeviceToDevice, s));
-        c0 = B.c0copy;
+    if (in == out) {  // the combine reads c0 at permuted positions while writing out
+        uint64_t *cp = A.take(plen);
+        if (!cp) return fail(NJ_ENOMEM, "scratch too small");
+        NJ_HIP(hipMemcpyAsync(cp, in, plen * 8, hipMemcpyDeviceToDevice, s));
+        c0 = cp;
     }
-    nj_status st = modup_ext(c, l, B.dtmp, B, s);
-    if (st) return st;
-    return ks_from_ext(c, l, B.dtmp, key, 1, c0, g, acc, out, B, s);
+    AutoJobs aj;
+    aj.in[0] = in + plen, aj.out[0] = M.d, aj.g[0] = g;
+    NJ_HIP(launch_automorph_multi(c, aj, 1, l + 1, s));
+    return ks_one(c, l, M.d, key, c0, g, out, M, s);
 }
 
 int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
@@ -750,6 +660,17 @@ nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, 
     return NJ_OK;
 }
 
+nj_status rescale_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s)
+{
+    if (c->N >= 8192) return rescale(c, l, in, out, A, s, -1, 2 * K);
+    const size_t cl = 2 * (size_t)c->N * (l + 1), cl1 = 2 * (size_t)c->N * l;
+    for (int z = 0; z < K; z++) {
+        nj_status st = rescale(c, l, in + z * cl, out + z * cl1, A, s);
+        if (st) return st;
+    }
+    return NJ_OK;
+}
+
 nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s)
 {
     const size_t N = c->N;
@@ -784,9 +705,7 @@ nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t
     if (!cj) return fail(NJ_ENOMEM, "scratch too small");
     nj_status st = apply_galois(c, l, x, 2 * c->N - 1, cj, A, s);
     if (st) return st;
-    NJ_HIP(launch_elementwise(c, 0, x, cj, re, ct_limbs(l), s));
-    NJ_HIP(launch_elementwise(c, 1, x, cj, cj, ct_limbs(l), s));
-    NJ_HIP(launch_monomial_half(c, l, cj, im, s));
+    NJ_HIP(launch_conj_split(c, l, x, cj, re, im, s));
     return NJ_OK;
 }
 
@@ -841,22 +760,15 @@ nj_status cts_batch(nj_ctx *c, const nj_plan *p, const uint64_t *in, int n, uint
         int l = c->L;
         for (const auto &lt : p->lts) {
             if (lt.level != l) return fail(NJ_ELEVEL, "CoeffToSlot: plan levels do not follow the context's top level");
-            const size_t cl = 2 * N * (l + 1), cl1 = 2 * N * l;
             if ((st = bsgs_apply_batch(c, lt, K, x, y, A, s))) return st;
-            for (int z = 0; z < K; z++)
-                if ((st = rescale(c, l, y + z * cl, x + z * cl1, A, s))) return st;
+            if ((st = rescale_batch(c, l, K, y, x, A, s))) return st;
             l--;
         }
         // real split of every ciphertext: one batch of conjugations
         Arena B = A;
         uint64_t *cj = B.take(K * cout);
         if ((st = apply_galois_batch(c, l, K, x, 2 * c->N - 1, cj, B, s))) return st;
-        for (int z = 0; z < K; z++) {
-            uint64_t *xz = x + z * cout, *cz = cj + z * cout;
-            NJ_HIP(launch_elementwise(c, 0, xz, cz, re[z0 + z], ct_limbs(l), s));
-            NJ_HIP(launch_elementwise(c, 1, xz, cz, cz, ct_limbs(l), s));
-            NJ_HIP(launch_monomial_half(c, l, cz, im[z0 + z], s));
-        }
+        for (int z = 0; z < K; z++) NJ_HIP(launch_conj_split(c, l, x + z * cout, cj + z * cout, re[z0 + z], im[z0 + z], s));
     }
     return NJ_OK;
 }
@@ -1105,11 +1017,9 @@ nj_status nj_keyswitch(nj_ctx *c, const uint64_t *d, int level, uint32_t g, uint
     Arena A = arena_for(c, ks_words(c, level) + 2 * plen, ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
     uint64_t *pair = A.take(2 * plen);
-    KsBufs B;
-    if (!ks_bufs(c, level, A, B)) return fail(NJ_ENOMEM, "scratch");
-    nj_status st = modup_ext(c, level, d, B, S(stream));
-    if (st) return st;
-    st = ks_from_ext(c, level, d, key, 1, nullptr, 0, nullptr, pair, B, S(stream));
+    MultiBufs M;
+    if (!pair || !multi_bufs(c, level, 1, A, M)) return fail(NJ_ENOMEM, "scratch");
+    nj_status st = ks_one(c, level, d, key, nullptr, 0, pair, M, S(stream));
     if (st) return st;
     NJ_HIP(hipMemcpyAsync(out0, pair, plen * 8, hipMemcpyDeviceToDevice, S(stream)));
     NJ_HIP(hipMemcpyAsync(out1, pair + plen, plen * 8, hipMemcpyDeviceToDevice, S(stream)));
@@ -1352,8 +1262,7 @@ nj_status nj_conv2d_cins_batch(nj_ctx *c, const nj_plan *p, const nj_ct *in, int
     for (int z0 = 0; z0 < n; z0 += kBatch) {
         const int K = std::min(kBatch, n - z0);
         if ((st = bsgs_apply_batch(c, lt, K, in->data + z0 * clen, y, A, s))) return st;
-        for (int z = 0; z < K; z++)
-            if ((st = rescale(c, l, y + z * clen, out->data + (z0 + z) * clen_out, A, s))) return st;
+        if ((st = rescale_batch(c, l, K, y, out->data + z0 * clen_out, A, s))) return st;
     }
     out->level = l - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[l];
     return NJ_OK;
@@ -1399,8 +1308,7 @@ nj_status nj_conv2d_block(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *o
     uint64_t *y = A.take(lt.bo * clen);
     hipStream_t s = S(stream);
     if ((st = block_bsgs_apply(c, lt, in->data, y, A, s))) return st;
-    for (int z = 0; z < lt.bo; z++)
-        if ((st = rescale(c, l, y + z * clen, out->data + z * clen_out, A, s))) return st;
+    if ((st = rescale_batch(c, l, lt.bo, y, out->data, A, s))) return st;
     out->level = l - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[l];
     return NJ_OK;
 }

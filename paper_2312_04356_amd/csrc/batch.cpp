@@ -418,8 +418,8 @@ nj_status run_plain(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Ar
         if (!lo) return fail(NJ_ENOMEM, "scratch too small");
         st = lt.bi == 1 && bo == 1 ? bsgs_apply(c, lt, j.in.data, y, 1, A, s) : block_bsgs_apply(c, lt, j.in.data, y, A, s);
         if (st) return st;
+        if ((st = rescale_batch(c, l, bo, y, r, A, s))) return st;
         for (int ob = 0; ob < bo; ob++) {
-            if ((st = rescale(c, l, y + ob * clen, r + ob * clen1, A, s))) return st;
             NJ_HIP(hipMemcpy2DAsync(lo + ob * 2 * N, N * 8, r + ob * clen1, l * N * 8, N * 8, 2, hipMemcpyDeviceToDevice,
                                     s));
         }

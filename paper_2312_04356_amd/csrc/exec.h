@@ -40,22 +40,10 @@ int galois_of_rot(const nj_ctx *c, long long r);
 nj_status check_ct(const nj_ctx *c, const nj_ct *ct, const char *what);
 LimbTab ct_limbs(int l);
 
-// Buffers of one key switch at level l (coefficient form copy, automorphed input, c0
-// copy, extended digits, inner products, special-prime limbs, converted limbs).
-struct KsBufs {
-    uint64_t *coef, *dtmp, *c0copy, *ext, *u, *pc, *conv;
-};
+// scratch words of one key switch at level l (apply_galois with in == out, ks_one)
 size_t ks_words(const nj_ctx *c, int l);
-bool ks_bufs(const nj_ctx *c, int l, Arena &A, KsBufs &B);
-// ModUp of d (evaluation form, level l): every digit extended to Q_l u P
-nj_status modup_ext(nj_ctx *c, int l, const uint64_t *d, KsBufs &B, hipStream_t s);
-// inner product with `key` (digits read through X -> X^g_ip), ModDown, and
-// out = acc + (ModDown_0 + add read through X -> X^g_add, ModDown_1); add / acc may be null
-nj_status ks_from_ext(nj_ctx *c, int l, const uint64_t *d_own, const uint64_t *key, uint32_t g_ip, const uint64_t *add,
-                      uint32_t g_add, const uint64_t *acc, uint64_t *out, KsBufs &B, hipStream_t s);
-// out = acc + (tau_g(c0), tau_g(c1)) switched back to s (acc may be null or alias out)
-nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s,
-                       const uint64_t *acc = nullptr);
+// out = (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias
+nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s);
 
 size_t multi_words(const nj_ctx *c, int l, int K);
 bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
@@ -64,6 +52,9 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // ModEval of Re and Im evaluated together (packed) when N >= 8192
 nj_status eval_mod_pair(nj_ctx *c, const nj_ct *re, const nj_ct *im, int K, int r, const double *coeffs,
                         int n_coeffs, nj_ct *out_re, nj_ct *out_im, void *stream);
+// one key switch of d: out = (ModDown_0 + add read through X -> X^g_add, ModDown_1)
+nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, const uint64_t *key, const uint64_t *add, uint32_t g_add,
+                 uint64_t *out, MultiBufs &M, hipStream_t s);
 // K key switches on ModUp'ed digits (M.ext): key inner products, then ks_down
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s);
@@ -95,6 +86,8 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 // n_polys > 2 (several ciphertexts packed at level l) needs N >= 8192
 nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out = -1,
                   int n_polys = 2);
+// rescale of K packed ciphertexts [K][2][l+1] -> [K][2][l] (one set of launches when N >= 8192)
+nj_status rescale_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s);
 nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s);
 nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t *im, Arena A, hipStream_t s);
 

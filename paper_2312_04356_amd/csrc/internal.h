@@ -55,22 +55,6 @@ struct Key {
     uint64_t *d = nullptr;  // device [dnum][2][L+1+alpha][N], evaluation form
 };
 
-// One basis-conversion job (kernel argument): input limbs at in + in_off[a]*N,
-// outputs at out + out_off[o]*N.
-struct BconvJob {
-    const uint64_t *in;
-    uint64_t *out;
-    const double *hat_inv;  // [m] (companions follow, unused here)
-    const double *hat;      // [m][n_out]
-    int m, n_out;
-    int in_pidx[16], in_off[16];
-    int out_pidx[64], out_off[64];
-};
-struct BconvBatch {
-    int n;
-    BconvJob job[4];
-};
-
 // Many key switches at once (kernel arguments).
 #define NJ_MAX_JOBS 16
 struct BconvShared {  // per-digit tables of one basis conversion (ModUp digits, or the P basis)
@@ -287,6 +271,9 @@ hipError_t launch_rescale_combine(const nj_ctx *c, int level, const uint64_t *a,
 hipError_t launch_pmac(const nj_ctx *c, int level, const uint64_t *ct, const uint64_t *pt, uint64_t *acc, int first,
                        hipStream_t s);
 hipError_t launch_monomial_half(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, hipStream_t s);
+// re = x + xc, im = -X^{N/2} (x - xc) over both polynomials (re, im must not alias x, xc)
+hipError_t launch_conj_split(const nj_ctx *c, int level, const uint64_t *x, const uint64_t *xc, uint64_t *re,
+                             uint64_t *im, hipStream_t s);
 hipError_t launch_signed_to_rns(const nj_ctx *c, const int64_t *coeffs, const LimbTab &lt, uint64_t *out,
                                 hipStream_t s, const uint64_t *d_primes);
 hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const uint64_t *a, const uint64_t *e,
@@ -295,13 +282,6 @@ hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out,
                              const double *d_scal, const double *d_scalq, hipStream_t s);
 
 // ------------------------------------------------------------------- ksw.hip
-hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t s);
-// u [2][l+1+alpha][N]; the digit's own limbs are read from d
-hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
-                          uint32_t g, uint64_t *u, hipStream_t s);
-// out = acc + (u - conv) P^-1 + (p == 0 ? add o X^g_add : 0), both halves; acc/add may be null
-hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv, const uint64_t *add,
-                           uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s);
 hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
                                hipStream_t s);

@@ -431,6 +431,32 @@ hipError_t launch_monomial_half(const nj_ctx *c, int level, const uint64_t *in, 
     return hipGetLastError();
 }
 
+// The real/imaginary split after the conjugation key switch, one pass over both inputs:
+// re = x + xc, im = -X^{N/2} (x - xc) (the monomial product as in k_monomial_half).
+__global__ void k_conj_split(const uint64_t *x, const uint64_t *xc, uint64_t *re, uint64_t *im, int level,
+                             const double *tw, const PrimeInfo *info, int logN)
+{
+    const int N = 1 << logN, row = blockIdx.y, i = row % (level + 1);
+    const Mod m = info[i].m;
+    const double it = tw[(size_t)i * N + 1];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+        const size_t o = (size_t)row * N + k;
+        const double a = u2d(x[o]), b = u2d(xc[o]);
+        re[o] = d2u(add_mod(a, b, m));
+        double r = mul_canon(sub_mod(a, b, m), it, m);
+        if ((bitrev((uint32_t)k, logN) & 1u) == 0u) r = r == 0.0 ? 0.0 : m.t - r;
+        im[o] = d2u(r);
+    }
+}
+
+hipError_t launch_conj_split(const nj_ctx *c, int level, const uint64_t *x, const uint64_t *xc, uint64_t *re,
+                             uint64_t *im, hipStream_t s)
+{
+    dim3 grid((c->N + kThreads - 1) / kThreads, 2 * (level + 1));
+    hipLaunchKernelGGL(k_conj_split, grid, dim3(kThreads), 0, s, x, xc, re, im, level, c->d_tw, c->d_info, c->log_n);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------- key generation
 
 __global__ void k_signed_to_rns(const int64_t *x, LimbTab lt, uint64_t *out, const uint64_t *primes, int logN)

@@ -1,14 +1,10 @@
-// Hybrid key switching and BSGS accumulation kernels (gfx950).
+// Hybrid key switching and BSGS accumulation kernels (gfx950).  Every key switch runs
+// as a batch of jobs (one job being the plain case): ModUp's basis conversion
+// (k_bconv_multi; at N >= 8192 the fused conversion + column pass in ntt.hip), key inner
+// products (k_key_ip_multi / _sum / _shared / _mixed: one job per key, a sum over jobs,
+// one key for many ciphertexts, one key for jobs at mixed levels), the ModDown combine
+// (k_moddown_multi, or fused into the tile pass in ntt.hip) and the automorphisms.
 //
-//  * k_bconv_batch: fast basis conversion y_t = sum_a [x_a (D/q_a)^-1]_{q_a} (D/q_a) mod t
-//    for up to 4 jobs per launch (the digits of one ModUp, or the two halves of one
-//    ModDown).  The digit size M is a template parameter so the scaled residues stay
-//    in registers.  Thread per coefficient, blockIdx.y = chunk of 8 targets,
-//    blockIdx.z = job.
-//  * k_key_ip2: key inner product over the extended limbs; a digit's own limbs are
-//    read from the switched polynomial itself, so ModUp never copies them.
-//  * k_moddown2: (u - conv) P^-1 for both halves, plus the rotated c0 and an
-//    optional running sum (giant-step accumulation).
 //  * k_bsgs_mac: every giant step's inner sum sum_i baby_i (.) diag_{g,i} in one pass:
 //    each baby and each diagonal word is read once.
 #include <algorithm>
@@ -19,59 +15,6 @@ namespace nj {
 
 constexpr int kBT = 256;
 
-
-// ------------------------------------------------------------ basis conversion
-
-template <int M>
-__global__ __launch_bounds__(kBT) void k_bconv_batch(BconvBatch bb, const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN;
-    const BconvJob &jb = bb.job[blockIdx.z];
-    const int k = blockIdx.x * kBT + threadIdx.x;
-    const int o0 = blockIdx.y * 8;
-    if (k >= N || o0 >= jb.n_out) return;
-    double v[M];
-#pragma unroll
-    for (int a = 0; a < M; a++) {
-        const Mod ma = info[jb.in_pidx[a]].m;
-        v[a] = mul_canon(u2d(jb.in[(size_t)jb.in_off[a] * N + k]), jb.hat_inv[a], ma);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; q++) {  // the block's chunk of 8 targets, unrolled
-        const int o = o0 + q;
-        if (o < jb.n_out) {
-            const Mod mt = info[jb.out_pidx[o]].m;
-            double acc = 0.0;
-#pragma unroll
-            for (int a = 0; a < M; a++) {
-                acc += mul_lazy(v[a], jb.hat[a * jb.n_out + o], mt);  // each term in (-t, t)
-                if ((a & 7) == 7) acc = reduce(acc, mt);
-            }
-            jb.out[(size_t)jb.out_off[o] * N + k] = d2u(reduce(acc, mt));
-        }
-    }
-}
-
-hipError_t launch_bconv_batch(const nj_ctx *c, const BconvBatch &bb, hipStream_t s)
-{
-    if (bb.n == 0) return hipSuccess;
-    int max_out = 0, m = bb.job[0].m;
-    double bytes = 0;
-    for (int j = 0; j < bb.n; j++) {
-        max_out = max(max_out, bb.job[j].n_out);
-        if (bb.job[j].m != m) return hipErrorInvalidValue;
-        bytes += 8.0 * c->N * (bb.job[j].m + bb.job[j].n_out);
-    }
-    dim3 grid((c->N + kBT - 1) / kBT, (max_out + 7) / 8, bb.n);
-    switch (m) {
-#define NJ_BC(MM) \
-    case MM: return launch(c, PROF_BCONV, bytes, k_bconv_batch<MM>, grid, dim3(kBT), s, bb, c->d_info, c->log_n);
-        NJ_BC(1) NJ_BC(2) NJ_BC(3) NJ_BC(4) NJ_BC(5) NJ_BC(6) NJ_BC(7) NJ_BC(8)
-        NJ_BC(9) NJ_BC(10) NJ_BC(11) NJ_BC(12) NJ_BC(13) NJ_BC(14) NJ_BC(15) NJ_BC(16)
-#undef NJ_BC
-    default: return hipErrorInvalidValue;
-    }
-}
 
 // ------------------------------------------------------- key inner product
 
@@ -151,25 +94,6 @@ __device__ __forceinline__ void ip_one(const IpRow &r, const uint64_t *ext, cons
     a0 = reduce(a0, m), a1 = reduce(a1, m);
 }
 
-template <int ND>
-__global__ __launch_bounds__(kBT) void k_key_ip2(const uint64_t *ext, const uint64_t *d, const uint64_t *key,
-                                                uint64_t *u, uint32_t g, int n_digits, int level, int L, int alpha,
-                                                int nq, const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN;
-    const int t = blockIdx.y;
-    const int pidx = t <= level ? t : nq + (t - level - 1);
-    const Mod m = info[pidx].m;
-    const int k = blockIdx.x * kBT + threadIdx.x;
-    if (k >= N) return;
-    const IpRow r = ip_row(t, level, L, alpha);
-    const int src = g == 1u ? k : galois_src2(k, g, logN);
-    double a0, a1;
-    ip_one<ND>(r, ext, d, key, src, k, N, n_digits, a0, a1, m);
-    u[(size_t)t * N + k] = d2u(a0);
-    u[(r.ne + t) * N + k] = d2u(a1);
-}
-
 // returns EXPR with the compile-time digit count ND: 1..4 unrolled, 0 = generic loop
 #define NJ_ND_SWITCH(nd, EXPR)                   \
     switch (nd) {                                \
@@ -179,46 +103,6 @@ __global__ __launch_bounds__(kBT) void k_key_ip2(const uint64_t *ext, const uint
     case 4: { constexpr int ND = 4; return EXPR; } \
     default: { constexpr int ND = 0; return EXPR; } \
     }
-
-hipError_t launch_key_ip2(const nj_ctx *c, int level, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
-                          uint32_t g, uint64_t *u, hipStream_t s)
-{
-    const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
-    dim3 grid((c->N + kBT - 1) / kBT, ne);
-    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0), k_key_ip2<ND>, grid, dim3(kBT), s, ext,
-                            d, key, u, g, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n));
-}
-
-// ------------------------------------------------------------------ ModDown
-
-// out_p[i] = acc_p[i] + (u_p[i] - conv_p[i]) P^-1 (+ add[i] read through X -> X^g_add for p = 0)
-__global__ __launch_bounds__(kBT) void k_moddown2(const uint64_t *u, const uint64_t *conv, const uint64_t *add,
-                                                 uint32_t g_add, const uint64_t *acc, uint64_t *out, int level,
-                                                 int ne, const double *pinv, const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN, i = blockIdx.y, p = blockIdx.z;
-    const Mod m = info[i].m;
-    const int k = blockIdx.x * kBT + threadIdx.x;
-    if (k >= N) return;
-    double r = mul_canon(sub_mod(u2d(u[((size_t)p * ne + i) * N + k]), u2d(conv[((size_t)p * (level + 1) + i) * N + k]), m),
-                         pinv[i], m);
-    if (p == 0 && add) {
-        const int src = g_add <= 1u ? k : galois_src2(k, g_add, logN);
-        r = add_mod(r, u2d(add[(size_t)i * N + src]), m);
-    }
-    const size_t o = ((size_t)p * (level + 1) + i) * N + k;
-    if (acc) r = add_mod(r, u2d(acc[o]), m);
-    out[o] = d2u(r);
-}
-
-hipError_t launch_moddown2(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv, const uint64_t *add,
-                           uint32_t g_add, const uint64_t *acc, uint64_t *out, hipStream_t s)
-{
-    dim3 grid((c->N + kBT - 1) / kBT, level + 1, 2);
-    return launch(c, PROF_OTHER, 8.0 * c->N * (level + 1) * (add ? 7.0 : 6.0) + (acc ? 16.0 * c->N * (level + 1) : 0),
-                  k_moddown2, grid, dim3(kBT), s, u, conv, add, g_add, acc, out, level, level + 1 + c->alpha, c->d_pinv,
-                  c->d_info, c->log_n);
-}
 
 // ------------------------------------------------------------------- BSGS
 

@@ -34,7 +34,7 @@ def family(name):
 
 
 # kernels the library times together under "other"
-OTHER = ("k_moddown2", "k_moddown_multi", "k_automorph_multi", "k_automorph_acc", "k_tensor", "k_mul_int",
+OTHER = ("k_moddown_multi", "k_automorph_multi", "k_automorph_acc", "k_tensor", "k_mul_int",
          "k_add_int", "k_zero", "k_ntt_tile_rs")
 
 

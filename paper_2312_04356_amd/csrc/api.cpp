@@ -28,19 +28,31 @@ const uint64_t *key_of(const nj_ctx *c, uint32_t g)
     return nullptr;
 }
 
+// N >= 8192 with at most 4 digits: ModUp stops after the column pass and the key inner
+// product runs the extended digits' tile pass itself (jobs with g = 1)
+bool fuse_ip(const nj_ctx *c, int l) { return c->N >= 8192 && c->alpha <= 8 && n_digits(c, l) <= 4; }
+
+nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
+                   MultiBufs &M, hipStream_t s)
+{
+    NJ_HIP(launch_ntt_ip(c, l, kj, K, M.u, 0, 0, s));
+    return ks_down(c, l, K, mj, sum, acc, M, s);
+}
+
 // One key switch of d (evaluation form, level l) with `key`: ModUp, inner product,
 // ModDown, and out = (ModDown_0 + add read through X -> X^g_add, ModDown_1) (add may
 // be null).  The single-job case of the batched path, so it runs the same kernels.
 nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, const uint64_t *key, const uint64_t *add, uint32_t g_add,
                  uint64_t *out, MultiBufs &M, hipStream_t s)
 {
-    nj_status st = modup_multi(c, l, 1, d, M, s);
+    const bool f = fuse_ip(c, l);
+    nj_status st = modup_multi(c, l, 1, d, M, s, -1, !f);
     if (st) return st;
     KeyJobs kj;
     MdJobs mj;
     kj.ext[0] = M.ext, kj.d[0] = d, kj.g[0] = 1, kj.key[0] = key;
     mj.add[0] = add, mj.g_add[0] = g_add, mj.out[0] = out;
-    return ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
+    return f ? ks_fused(c, l, 1, kj, mj, 0, nullptr, M, s) : ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
 }
 
 // (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
@@ -87,7 +99,8 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
 
 // ModUp of K polynomials stored at d + z dstride N (evaluation form; dstride in limbs,
 // l+1 when packed) into ext + z dnum ne N.
-nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride)
+nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride,
+                      bool tiles)
 {
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
     // N >= 8192: the conversion's input factors ride on the inverse transform, and the
@@ -123,6 +136,7 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
         for (int z = 0; z < K; z++) jp.in[z] = M.coef + (size_t)z * (l + 1) * N, jp.out[z] = M.ext + (size_t)z * nd * ne * N;
         NJ_HIP(fused ? launch_bconv_col(c, sh, jp, K, s) : launch_bconv_multi(c, sh, jp, K, s));
     }
+    if (fused && !tiles) return NJ_OK;  // the key inner product runs the tile pass
     auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.ext, t, s) : launch_ntt(c, M.ext, t, false, s); };
     lt.n = 0;
     for (int z = 0; z < K; z++)
@@ -290,9 +304,9 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         }
         if (!hoist) {
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+            if ((st = modup_multi(c, l, K, M.d, M, s, -1, !fuse_ip(c, l)))) return st;
         }
-        if ((st = ks_multi(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
+        if ((st = (!hoist && fuse_ip(c, l) ? ks_fused : ks_multi)(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
     }
     // every giant step's inner sum
     std::vector<MacEntry> ent;
@@ -331,8 +345,9 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                 kj.key[z] = key_of(c, ge);
             }
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
-            NJ_HIP(launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
+            const bool f = fuse_ip(c, l);
+            if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+            NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s) : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
         }
         if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
@@ -358,8 +373,9 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         }
         mj.out[0] = out;
         NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-        if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
-        if ((st = ks_multi(c, l, K, kj, mj, 1, acc, M, s))) return st;
+        const bool f = fuse_ip(c, l);
+        if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+        if ((st = (f ? ks_fused : ks_multi)(c, l, K, kj, mj, 1, acc, M, s))) return st;
         acc = out;
     }
     (void)n;

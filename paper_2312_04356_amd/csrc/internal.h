@@ -84,6 +84,24 @@ __device__ __forceinline__ int galois_src2(int k, uint32_t g, int logN)
     return (int)brev_n((eg - 1u) >> 1, logN);
 }
 
+// Output limb t of a key inner product at level l: t < l+1 is q_t, else p_(t-l-1); kl
+// = the key's limb of t; own = the digit t belongs to (-1 for special primes).
+struct IpRow {
+    size_t t, ne, nk, kl;
+    int own;
+};
+
+__device__ __forceinline__ IpRow ip_row(int t, int level, int L, int alpha)
+{
+    IpRow r;
+    r.t = t;
+    r.ne = level + 1 + alpha;
+    r.nk = L + 1 + alpha;
+    r.kl = t <= level ? t : L + 1 + (t - level - 1);
+    r.own = t <= level ? t / alpha : -1;
+    return r;
+}
+
 struct MdJobs {
     const uint64_t *add[NJ_MAX_JOBS];
     uint32_t g_add[NJ_MAX_JOBS];
@@ -246,6 +264,11 @@ hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, 
                                 uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys = 2);
 hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);
 hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
+// key inner products fused with the extended digits' forward tile pass (N >= 8192,
+// 1..4 digits, every g = 1): per job u_base + z 2 ne N, or (sum) one output summed over
+// the jobs; accumulate adds to the output's previous value
+hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
+                         int accumulate, hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,

@@ -22,22 +22,6 @@ constexpr int kBT = 256;
 // word (the digit's own limb d when j is t's digit, else the extended digit j), read
 // through X -> X^g at src, and the two key words.  ND = number of digits: for ND > 0
 // all 3 ND loads are issued before any is used; ND = 0 is the generic loop.
-struct IpRow {
-    size_t t, ne, nk, kl;
-    int own;
-};
-
-__device__ __forceinline__ IpRow ip_row(int t, int level, int L, int alpha)
-{
-    IpRow r;
-    r.t = t;
-    r.ne = level + 1 + alpha;
-    r.nk = L + 1 + alpha;
-    r.kl = t <= level ? t : L + 1 + (t - level - 1);
-    r.own = t <= level ? t / alpha : -1;
-    return r;
-}
-
 template <int ND>
 __device__ __forceinline__ void ip_load(const IpRow &r, const uint64_t *ext, const uint64_t *d, const uint64_t *key,
                                         int src, int k, size_t N, uint64_t *rx, uint64_t *rb, uint64_t *ra)

@@ -156,6 +156,72 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
     }
 }
 
+// Key inner products fused with the forward tile pass of the extended digits (jobs
+// with g = 1, N >= 8192).  At output limb t, digit j of job z is either the job's own
+// limb d_z[t] (evaluation form) or the converted limb ext_z[j][t], which arrives with
+// only its column pass applied: the block finishes that tile's transform in LDS and
+// multiplies it by the key words at once, so extended digits are never stored in
+// evaluation form.  Grid (jobs, N/4096, l+1+alpha).  SUM: u = (accumulate ? u : 0) +
+// the sum over all jobs (one block per tile); else job z = blockIdx.x has its own u_z
+// = u_base + z 2 ne N (plus its previous value when accumulate): jobs vary fastest, so
+// jobs sharing one key read each key tile close together in time.  After each job the
+// running sums take at most ND <= 4 lazy terms on a reduced value.
+template <int ND, bool SUM>
+__global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t *u_base, int accumulate, int level,
+                                                int L, int alpha, int nq, const double *tw, const PrimeInfo *info,
+                                                int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int t = blockIdx.z, tile = blockIdx.y, tid = threadIdx.x;
+    const int pidx = t <= level ? t : nq + (t - level - 1);
+    const Mod m = info[pidx].m;
+    const double *W = tw + (size_t)pidx * N;
+    const IpRow r = ip_row(t, level, L, alpha);
+    const size_t w0 = (size_t)tile * kT + tid;
+    const int z0 = SUM ? 0 : (int)blockIdx.x, z1 = SUM ? n_jobs : z0 + 1;
+    uint64_t *u = u_base + (SUM ? 0 : (size_t)z0 * 2 * r.ne * N);
+    const size_t o0 = r.t * N + w0, o1 = (r.ne + r.t) * N + w0;
+    double a0[16], a1[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        a0[k] = accumulate ? u2d(u[o0 + 256 * k]) : 0.0;
+        a1[k] = accumulate ? u2d(u[o1 + 256 * k]) : 0.0;
+    }
+    for (int z = z0; z < z1; z++) {
+#pragma unroll 1
+        for (int j = 0; j < ND; j++) {
+            const uint64_t *kb = kj.key[z] + ((size_t)j * 2 * r.nk + r.kl) * N + w0, *ka = kb + r.nk * N;
+            double x[16];
+            if (j == r.own) {
+                const uint64_t *xp = kj.d[z] + r.t * N + w0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = u2d(xp[256 * k]);
+            } else {
+                const uint64_t *xp = kj.ext[z] + ((size_t)j * r.ne + r.t) * N + w0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = u2d(xp[256 * k]);
+                __syncthreads();  // the previous tile's words have been read out of s
+                tile_forward(x, s, tid, tile, logN1, W, N, m);
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = s[pad16(tid + 256 * k)];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                a0[k] += mul_lazy(x[k], u2d(kb[256 * k]), m);
+                a1[k] += mul_lazy(x[k], u2d(ka[256 * k]), m);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        u[o0 + 256 * k] = d2u(a0[k]);
+        u[o1 + 256 * k] = d2u(a1[k]);
+    }
+}
+
 // The first log2(N1) forward stages on one column of N1 canonical words (lazy, one
 // reduction at the end: at most 4 stages).
 template <int N1>
@@ -517,6 +583,31 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
     const double bytes = 8.0 * N * (n * 3.0 + K * L1 + (acc ? n : 0));
     return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
                   L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n);
+}
+
+// Key inner products of n_jobs jobs (g = 1, digits column-passed only) fused with the
+// digits' tile pass; sum = 1: one output, summed over the jobs; accumulate: added to
+// the output's previous value.
+hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
+                         int accumulate, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT, nd = n_digits(c, level), ne = level + 1 + c->alpha;
+    if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
+    for (int z = 0; z < n_jobs; z++)
+        if (kj.g[z] != 1u) return hipErrorInvalidValue;
+    const double bytes = 8.0 * N * ne * (3.0 * nd * n_jobs + 2.0 * (sum ? 1 : n_jobs) * (1 + accumulate));
+    const dim3 grid(sum ? 1 : n_jobs, N1, ne);
+#define NJ_IP(ND)                                                                                                   \
+    case ND:                                                                                                        \
+        return sum ? launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, true>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n)                           \
+                   : launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, false>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n);
+    switch (nd) {
+        NJ_IP(1) NJ_IP(2) NJ_IP(3) NJ_IP(4)
+    }
+#undef NJ_IP
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nj

@@ -24,7 +24,7 @@ def family(name):
     # the same families the library's HIP-event counters use
     if n.startswith("k_bconv"):
         return "k_bconv"
-    if n.startswith("k_key_ip"):
+    if n.startswith("k_key_ip") or n.startswith("k_ntt_ip"):
         return "k_key_ip"
     if n.startswith("k_bsgs_mac"):
         return "k_pmac"

@@ -142,8 +142,10 @@ def test_keyswitch_parity(which, level, request):
     assert np.array_equal(gctx.to_host(o1), w1)
 
 
-def test_rotation_parity(small):
-    P = small
+@pytest.mark.parametrize("which", ["small", "full"])
+def test_rotation_parity(which, request):
+    """rotations and an in-place conjugation (one key switch each) at level 1"""
+    P = request.getfixturevalue(which)
     gctx = P.g.ctx
     level = 1
     m = P.o.ring.to_rns(P.o.input_plaintext(), level)

@@ -35,8 +35,8 @@ bool fuse_ip(const nj_ctx *c, int l) { return c->N >= 8192 && c->alpha <= 8 && n
 nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
-    NJ_HIP(launch_ntt_ip(c, l, kj, K, M.u, 0, 0, s));
-    return ks_down(c, l, K, mj, sum, acc, M, s);
+    NJ_HIP(launch_ntt_ip(c, l, kj, K, M.u, 0, 0, s, M.pc));
+    return ks_down(c, l, K, mj, sum, acc, M, s, true);
 }
 
 // One key switch of d (evaluation form, level l) with `key`: ModUp, inner product,
@@ -158,22 +158,29 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s);
+                  hipStream_t s, bool p_tiled);
 
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
+    if (fuse_ip(c, l)) {  // special-prime rows straight into ModDown's inverse transform
+        NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s, 1));
+        NJ_HIP(launch_key_ip_p(c, l, kj, K, M.pc, s));
+        return ks_down(c, l, K, mj, sum, acc, M, s, true);
+    }
     NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
     return ks_down(c, l, K, mj, sum, acc, M, s);
 }
 
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s)
+                  hipStream_t s, bool p_tiled)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
+    if (p_tiled && !fused) return fail(NJ_EUNSUPPORTED, "ModDown: pre-transformed special-prime rows need N >= 8192");
     auto intt = [&](const LimbTab &t) {
+        if (p_tiled) return launch_intt_cols_scaled(c, M.pc, t, c->d_downscale, s);
         return fused ? launch_intt_scaled(c, M.pc, M.u, t, c->d_downscale, s) : launch_ntt(c, M.pc, t, true, s, M.u);
     };
     LimbTab lp;
@@ -347,7 +354,9 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
             const bool f = fuse_ip(c, l);
             if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
-            NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s) : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
+            const bool last = c0 + K == gl.size();  // its special-prime rows go on to ModDown's inverse transform
+            NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s, last ? M.pc : nullptr)
+                     : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
         }
         if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
@@ -355,7 +364,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         M1.u = usum;
         MdJobs mj;
         mj.add[0] = c0sum, mj.g_add[0] = 1, mj.out[0] = out;
-        return ks_down(c, l, 1, mj, 0, acc ? out : nullptr, M1, s);
+        return ks_down(c, l, 1, mj, 0, acc ? out : nullptr, M1, s, fuse_ip(c, l));
     }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);

@@ -67,8 +67,10 @@ nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s);
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs
+// (p_tiled: the inner products already left their special-prime rows in M.pc after the
+// first 12 stages of the inverse transform; N >= 8192)
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s);
+                  hipStream_t s, bool p_tiled = false);
 
 // inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
 struct MacEntry {

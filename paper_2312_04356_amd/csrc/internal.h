@@ -268,7 +268,12 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
 // 1..4 digits, every g = 1): per job u_base + z 2 ne N, or (sum) one output summed over
 // the jobs; accumulate adds to the output's previous value
 hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
-                         int accumulate, hipStream_t s);
+                         int accumulate, hipStream_t s, uint64_t *pout = nullptr);
+// (pout given: the special-prime rows skip u and leave through the first 12 stages of
+// ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout)
+hipError_t launch_key_ip_p(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout, hipStream_t s);
+hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTab &lt, const double *scale,
+                                   hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
@@ -306,8 +311,9 @@ hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out,
 
 // ------------------------------------------------------------------- ksw.hip
 hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
+// (q_only: the rows of Q_l only; the special-prime rows come from launch_key_ip_p)
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
-                               hipStream_t s);
+                               hipStream_t s, int q_only = 0);
 hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
                                 const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
 hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);

@@ -104,6 +104,35 @@ __device__ __forceinline__ void tile_forward(double v[16], double *s, int tid, i
     __syncthreads();
 }
 
+// The first 12 inverse stages of one 4096-word tile (inverse twiddles W): v holds
+// words tid + 256 k on entry and on return; s must be free on entry (callers that used
+// it before put a barrier first).
+__device__ __forceinline__ void tile_inverse(double v[16], double *s, int tid, int tile, int logN1, const double *W,
+                                             int N, Mod m)
+{
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+    gs_round(v, 8, tid, tile, logN1, W, N, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+    __syncthreads();
+    {
+        const int lo = tid & 15, hi = tid >> 4;
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+        gs_round(v, 128, hi, tile, logN1, W, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(tid + 256 * k)];
+    gs_round(v, 2048, 0, tile, logN1, W, N, m);
+}
+
 // rows pass: last 12 stages on 4096-word tiles.  grid (N/4096, limbs)
 template <bool INV>
 __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
@@ -127,26 +156,8 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
         for (int k = 0; k < 16; k++) out[tid + 256 * k] = d2u(s[pad16(tid + 256 * k)]);
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = u2d(in[tid + 256 * k]);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
-        gs_round(v, 8, tid, tile, logN1, W, N, m);
-#pragma unroll
-        for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
-        __syncthreads();
-        {
-            const int lo = tid & 15, hi = tid >> 4;
-#pragma unroll
-            for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
-            gs_round(v, 128, hi, tile, logN1, W, N, m);
-#pragma unroll
-            for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; k++) v[k] = s[pad16(tid + 256 * k)];
-        gs_round(v, 2048, 0, tile, logN1, W, N, m);
+        for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
+        tile_inverse(v, s, tid, tile, logN1, W, N, m);
         if (logN1 == 0) {
 #pragma unroll
             for (int k = 0; k < 16; k++) v[k] = mul_canon(v[k], pi.ninv, m);
@@ -154,6 +165,61 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
 #pragma unroll
         for (int k = 0; k < 16; k++) out[tid + 256 * k] = d2u(v[k]);
     }
+}
+
+// Special-prime rows of a key inner product (a0: first half, a1: second, words
+// tid + 256 k of one tile) through the first 12 stages of ModDown's inverse transform
+// (W: inverse twiddles of that prime), stored at out (first half) and out + half_off
+// (second half).  Begins with a barrier, so s may still be in use on entry.
+__device__ __forceinline__ void store_p_rows(double a0[16], double a1[16], double *s, uint64_t *out, size_t half_off,
+                                             size_t w0, int tid, int tile, int logN1, const double *W, int N, Mod m)
+{
+    __syncthreads();
+    tile_inverse(a0, s, tid, tile, logN1, W, N, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) out[w0 + 256 * k] = d2u(a0[k]);
+    __syncthreads();
+    tile_inverse(a1, s, tid, tile, logN1, W, N, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) out[half_off + w0 + 256 * k] = d2u(a1[k]);
+}
+
+// The special-prime rows of K key inner products whose digits are read through
+// X -> X^g (hoisted baby steps), each block one 4096-word tile of one row of one job,
+// finished with the first 12 stages of ModDown's inverse transform: job z's row p_a
+// lands in pout at rows (2 z) alpha + a (first half) and (2 z + 1) alpha + a, and is
+// never stored in evaluation form.  grid (K, N/4096, alpha).
+template <int ND>
+__global__ __launch_bounds__(kNT) void k_key_ip_p(KeyJobs kj, uint64_t *pout, int level, int L, int alpha, int nq,
+                                                  const double *itw, const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int z = blockIdx.x, tile = blockIdx.y, a = blockIdx.z, tid = threadIdx.x;
+    const int t = level + 1 + a, pidx = nq + a;
+    const Mod m = info[pidx].m;
+    const IpRow r = ip_row(t, level, L, alpha);
+    const size_t w0 = (size_t)tile * kT + tid;
+    const uint32_t g = kj.g[z];
+    double a0[16], a1[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) a0[k] = 0.0, a1[k] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < ND; j++) {
+        const uint64_t *xp = kj.ext[z] + ((size_t)j * r.ne + r.t) * N;
+        const uint64_t *kb = kj.key[z] + ((size_t)j * 2 * r.nk + r.kl) * N + w0, *ka = kb + r.nk * N;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const int w = (int)w0 + 256 * k;
+            const double x = u2d(xp[g == 1u ? w : galois_src2(w, g, logN)]);
+            a0[k] += mul_lazy(x, u2d(kb[256 * k]), m);
+            a1[k] += mul_lazy(x, u2d(ka[256 * k]), m);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
+    store_p_rows(a0, a1, s, pout + ((size_t)2 * z * alpha + a) * N, (size_t)alpha * N, w0, tid, tile, logN1,
+                 itw + (size_t)pidx * N, N, m);
 }
 
 // Key inner products fused with the forward tile pass of the extended digits (jobs
@@ -169,7 +235,7 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t
 template <int ND, bool SUM>
 __global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t *u_base, int accumulate, int level,
                                                 int L, int alpha, int nq, const double *tw, const PrimeInfo *info,
-                                                int logN)
+                                                int logN, uint64_t *pout, const double *itw)
 {
     __shared__ double s[kT + kT / 16];
     const int N = 1 << logN, logN1 = logN - 12;
@@ -214,6 +280,11 @@ __global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t
         }
 #pragma unroll
         for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
+    }
+    if (pout && t > level) {  // special-prime rows: on to ModDown's inverse transform
+        store_p_rows(a0, a1, s, pout + ((size_t)2 * z0 * alpha + (t - level - 1)) * N, (size_t)alpha * N, w0, tid,
+                     tile, logN1, itw + (size_t)pidx * N, N, m);
+        return;
     }
 #pragma unroll
     for (int k = 0; k < 16; k++) {
@@ -589,7 +660,7 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
 // digits' tile pass; sum = 1: one output, summed over the jobs; accumulate: added to
 // the output's previous value.
 hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
-                         int accumulate, hipStream_t s)
+                         int accumulate, hipStream_t s, uint64_t *pout)
 {
     const int N = c->N, N1 = N / kT, nd = n_digits(c, level), ne = level + 1 + c->alpha;
     if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
@@ -600,14 +671,43 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
 #define NJ_IP(ND)                                                                                                   \
     case ND:                                                                                                        \
         return sum ? launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, true>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
-                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n)                           \
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw)           \
                    : launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, false>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
-                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n);
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw);
     switch (nd) {
         NJ_IP(1) NJ_IP(2) NJ_IP(3) NJ_IP(4)
     }
 #undef NJ_IP
     return hipErrorInvalidValue;
+}
+
+// Special-prime rows of K key inner products with the digits read through X -> X^g,
+// finished with the first 12 stages of ModDown's inverse transform into pout (N >= 8192,
+// 1..4 digits); the Q rows come from launch_key_ip_multi(q_only = 1).
+hipError_t launch_key_ip_p(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT, nd = n_digits(c, level), al = c->alpha;
+    if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
+    const double bytes = 8.0 * N * al * n_jobs * (3.0 * nd + 2.0);
+    const dim3 grid(n_jobs, N1, al);
+    switch (nd) {
+    case 1: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<1>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
+    case 2: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<2>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
+    case 3: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<3>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
+    default: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<4>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
+    }
+}
+
+// The column pass of an inverse transform whose tile pass already ran, in place, with
+// the final factor scale[pidx] (N >= 8192).
+hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTab &lt, const double *scale,
+                                   hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2) return hipErrorInvalidValue;
+    if (lt.n == 0) return hipSuccess;
+    return launch_cols<true>(c, PROF_NTT_COL_INV, 16.0 * N * lt.n, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt,
+                             c->d_itw, c->d_info, c->log_n, scale);
 }
 
 }  // namespace nj

@@ -39,18 +39,28 @@ nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
     return ks_down(c, l, K, mj, sum, acc, M, s, true);
 }
 
-// One key switch of d (evaluation form, level l) with `key`: ModUp, inner product,
-// ModDown, and out = (ModDown_0 + add read through X -> X^g_add, ModDown_1) (add may
-// be null).  The single-job case of the batched path, so it runs the same kernels.
-nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, const uint64_t *key, const uint64_t *add, uint32_t g_add,
-                 uint64_t *out, MultiBufs &M, hipStream_t s)
+// One key switch of tau_g(d) (d in evaluation form, level l) with `key`: ModUp,
+// inner product, ModDown, and out = (ModDown_0 + add read through X -> X^g_add,
+// ModDown_1) (add may be null).  The single-job case of the batched path, so it runs
+// the same kernels; where the inner product runs the digits' tile pass the
+// automorphism rides on ModUp's inverse transform and on the own-limb reads.
+nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t *key, const uint64_t *add,
+                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s)
 {
     const bool f = fuse_ip(c, l);
-    nj_status st = modup_multi(c, l, 1, d, M, s, -1, !f);
+    if (!f && g != 1u) {  // the automorphism first, into M.d
+        AutoJobs aj;
+        aj.in[0] = d, aj.out[0] = M.d, aj.g[0] = g;
+        NJ_HIP(launch_automorph_multi(c, aj, 1, l + 1, s));
+        d = M.d, g = 1;
+    }
+    GalTab gt;
+    gt.g[0] = g;
+    nj_status st = modup_multi(c, l, 1, d, M, s, -1, !f, f && g != 1u ? &gt : nullptr);
     if (st) return st;
     KeyJobs kj;
     MdJobs mj;
-    kj.ext[0] = M.ext, kj.d[0] = d, kj.g[0] = 1, kj.key[0] = key;
+    kj.ext[0] = M.ext, kj.d[0] = d, kj.g[0] = g, kj.key[0] = key;
     mj.add[0] = add, mj.g_add[0] = g_add, mj.out[0] = out;
     return f ? ks_fused(c, l, 1, kj, mj, 0, nullptr, M, s) : ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
 }
@@ -70,10 +80,7 @@ nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_
         NJ_HIP(hipMemcpyAsync(cp, in, plen * 8, hipMemcpyDeviceToDevice, s));
         c0 = cp;
     }
-    AutoJobs aj;
-    aj.in[0] = in + plen, aj.out[0] = M.d, aj.g[0] = g;
-    NJ_HIP(launch_automorph_multi(c, aj, 1, l + 1, s));
-    return ks_one(c, l, M.d, key, c0, g, out, M, s);
+    return ks_one(c, l, in + plen, g, key, c0, g, out, M, s);
 }
 
 int galois_of_rot(const nj_ctx *c, long long r) { return (int)nj_galois_elt(c, (int)(((r % (c->N / 2)) + c->N / 2) % (c->N / 2))); }
@@ -100,21 +107,23 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
 // ModUp of K polynomials stored at d + z dstride N (evaluation form; dstride in limbs,
 // l+1 when packed) into ext + z dnum ne N.
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride,
-                      bool tiles)
+                      bool tiles, const GalTab *gt, const int *zoff)
 {
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
     // N >= 8192: the conversion's input factors ride on the inverse transform, and the
     // conversion runs fused with its outputs' column pass
     const bool fused = N >= 8192 && c->alpha <= 8;
+    if (gt && !fused) return fail(NJ_EUNSUPPORTED, "ModUp through an automorphism needs N >= 8192");
     auto intt = [&](const LimbTab &t) {
-        return fused ? launch_intt_scaled(c, M.coef, d, t, c->d_upscale[l], s) : launch_ntt(c, M.coef, t, true, s, d);
+        return fused ? launch_intt_scaled(c, M.coef, d, t, c->d_upscale[l], s, gt, l + 1)
+                     : launch_ntt(c, M.coef, t, true, s, d);
     };
     if (dstride < 0) dstride = l + 1;
     LimbTab lt;
     lt.n = 0;
     for (int z = 0; z < K; z++)
         for (int i = 0; i <= l; i++) {
-            lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = z * dstride + i;
+            lt.pidx[lt.n] = i, lt.off[lt.n] = z * (l + 1) + i, lt.soff[lt.n] = (zoff ? zoff[z] : z * dstride) + i;
             if (++lt.n == NJ_MAX_LIMBS) {
                 NJ_HIP(intt(lt));
                 lt.n = 0;
@@ -297,11 +306,15 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         KeyJobs kj;
         MdJobs mj;
         AutoJobs aj;
+        GalTab gt;
         for (int z = 0; z < K; z++) {
             const int b = todo[c0 + z];
             const uint32_t g = galois_of_rot(c, (long long)lt.babies[b] * lt.u);
             if (hoist) {  // one ModUp of c1; X -> X^g applied to the extended digits
                 kj.ext[z] = M.ext, kj.d[z] = in + plen, kj.g[z] = g;
+            } else if (fuse_ip(c, l)) {  // ModUp of each tau_g(c1), read through X -> X^g
+                gt.g[z] = g;
+                kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = in + plen, kj.g[z] = g;
             } else {  // ModUp of each tau_g(c1)
                 aj.in[z] = in + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = g;
                 kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
@@ -309,9 +322,11 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             kj.key[z] = key_of(c, g);
             mj.add[z] = in, mj.g_add[z] = g, mj.out[z] = baby_buf[b];
         }
-        if (!hoist) {
+        if (!hoist && fuse_ip(c, l)) {
+            if ((st = modup_multi(c, l, K, in + plen, M, s, 0, false, &gt))) return st;
+        } else if (!hoist) {
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-            if ((st = modup_multi(c, l, K, M.d, M, s, -1, !fuse_ip(c, l)))) return st;
+            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
         }
         if ((st = (!hoist && fuse_ip(c, l) ? ks_fused : ks_multi)(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
     }
@@ -340,8 +355,11 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
         for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
             const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
+            const bool f = fuse_ip(c, l), gal = f;
             KeyJobs kj;
             AutoJobs aj, ac;
+            GalTab gt;
+            int zoff[NJ_MAX_JOBS];  // limb offset of each giant's c1 from inner's
             for (int z = 0; z < K; z++) {
                 const int g = gl[c0 + z];
                 const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
@@ -349,11 +367,15 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                 aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
                 ac.in[z] = x, ac.out[z] = nullptr, ac.g[z] = ge;
                 kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+                if (gal) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
                 kj.key[z] = key_of(c, ge);
             }
-            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-            const bool f = fuse_ip(c, l);
-            if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+            if (gal) {  // tau_ge rides on ModUp's inverse transform and the own-limb reads
+                if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff))) return st;
+            } else {
+                NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+                if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+            }
             const bool last = c0 + K == gl.size();  // its special-prime rows go on to ModDown's inverse transform
             NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s, last ? M.pc : nullptr)
                      : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
@@ -368,22 +390,29 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
+        const bool f = fuse_ip(c, l), gal = f;
         KeyJobs kj;
         MdJobs mj;
         AutoJobs aj;
+        GalTab gt;
+        int zoff[NJ_MAX_JOBS];
         for (int z = 0; z < K; z++) {
             const int g = gl[c0 + z];
             const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
             const uint64_t *x = inner + (size_t)g * clen;
             aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
             kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+            if (gal) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
             kj.key[z] = key_of(c, ge);
             mj.add[z] = x, mj.g_add[z] = ge;
         }
         mj.out[0] = out;
-        NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-        const bool f = fuse_ip(c, l);
-        if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+        if (gal) {
+            if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff))) return st;
+        } else {
+            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+            if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
+        }
         if ((st = (f ? ks_fused : ks_multi)(c, l, K, kj, mj, 1, acc, M, s))) return st;
         acc = out;
     }
@@ -1044,7 +1073,7 @@ nj_status nj_keyswitch(nj_ctx *c, const uint64_t *d, int level, uint32_t g, uint
     uint64_t *pair = A.take(2 * plen);
     MultiBufs M;
     if (!pair || !multi_bufs(c, level, 1, A, M)) return fail(NJ_ENOMEM, "scratch");
-    nj_status st = ks_one(c, level, d, key, nullptr, 0, pair, M, S(stream));
+    nj_status st = ks_one(c, level, d, 1, key, nullptr, 0, pair, M, S(stream));
     if (st) return st;
     NJ_HIP(hipMemcpyAsync(out0, pair, plen * 8, hipMemcpyDeviceToDevice, S(stream)));
     NJ_HIP(hipMemcpyAsync(out1, pair + plen, plen * 8, hipMemcpyDeviceToDevice, S(stream)));

@@ -50,17 +50,20 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
 // ModUp of K polynomials at d + z dstride N (dstride in limbs, l+1 when packed)
 // (tiles = false: at N >= 8192 the converted limbs are left after their column pass,
 // for the fused key inner product)
+// (gt: job z's polynomial is read through X -> X^g[z], N >= 8192; zoff: job z's
+// polynomial at d + zoff[z] N instead of d + z dstride N)
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1,
-                      bool tiles = true);
+                      bool tiles = true, const GalTab *gt = nullptr, const int *zoff = nullptr);
 // whether ModUp leaves the tile pass to the key inner product (launch_ntt_ip)
 bool fuse_ip(const nj_ctx *c, int l);
 // ModEval of Re and Im evaluated together (packed) when N >= 8192
 nj_status eval_mod_pair(nj_ctx *c, const nj_ct *re, const nj_ct *im, int K, int r, const double *coeffs,
                         int n_coeffs, nj_ct *out_re, nj_ct *out_im, void *stream);
-// one key switch of d: out = (ModDown_0 + add read through X -> X^g_add, ModDown_1)
-nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, const uint64_t *key, const uint64_t *add, uint32_t g_add,
-                 uint64_t *out, MultiBufs &M, hipStream_t s);
-// as ks_multi, on digits that modup_multi left column-passed (tiles = false); jobs with g = 1
+// one key switch of tau_g(d): out = (ModDown_0 + add read through X -> X^g_add, ModDown_1)
+nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t *key, const uint64_t *add,
+                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s);
+// as ks_multi, on digits of tau_g(d) that modup_multi left column-passed (tiles =
+// false); kj.d[z] is d itself, read through X -> X^g[z] for the own limbs
 nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s);
 // K key switches on ModUp'ed digits (M.ext): key inner products, then ks_down

@@ -102,6 +102,9 @@ __device__ __forceinline__ IpRow ip_row(int t, int level, int L, int alpha)
     return r;
 }
 
+struct GalTab {  // Galois element of each job (1 = none)
+    uint32_t g[NJ_MAX_JOBS];
+};
 struct MdJobs {
     const uint64_t *add[NJ_MAX_JOBS];
     uint32_t g_add[NJ_MAX_JOBS];
@@ -258,8 +261,9 @@ namespace nj {
 // ---------------------------------------------------------------- kernels.hip
 hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool inverse, hipStream_t s,
                       const uint64_t *src = nullptr);
+// (gt: limb b of job off[b] / L1 is read from src through X -> X^g[job])
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
-                              const double *scale, hipStream_t s);
+                              const double *scale, hipStream_t s, const GalTab *gt = nullptr, int L1 = 0);
 hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
                                 uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys = 2);
 hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);

@@ -222,10 +222,11 @@ __global__ __launch_bounds__(kNT) void k_key_ip_p(KeyJobs kj, uint64_t *pout, in
                  itw + (size_t)pidx * N, N, m);
 }
 
-// Key inner products fused with the forward tile pass of the extended digits (jobs
-// with g = 1, N >= 8192).  At output limb t, digit j of job z is either the job's own
-// limb d_z[t] (evaluation form) or the converted limb ext_z[j][t], which arrives with
-// only its column pass applied: the block finishes that tile's transform in LDS and
+// Key inner products fused with the forward tile pass of the extended digits (N >=
+// 8192).  The key switch is of tau_g(d_z), g = kj.g[z]: at output limb t, digit j of
+// job z is either the job's own limb d_z[t] read through X -> X^g (evaluation form) or
+// the converted limb ext_z[j][t] of tau_g(d_z), which arrives with only its column
+// pass applied: the block finishes that tile's transform in LDS and
 // multiplies it by the key words at once, so extended digits are never stored in
 // evaluation form.  Grid (jobs, N/4096, l+1+alpha).  SUM: u = (accumulate ? u : 0) +
 // the sum over all jobs (one block per tile); else job z = blockIdx.x has its own u_z
@@ -260,9 +261,13 @@ __global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t
             const uint64_t *kb = kj.key[z] + ((size_t)j * 2 * r.nk + r.kl) * N + w0, *ka = kb + r.nk * N;
             double x[16];
             if (j == r.own) {
-                const uint64_t *xp = kj.d[z] + r.t * N + w0;
+                const uint64_t *xp = kj.d[z] + r.t * N;
+                const uint32_t g = kj.g[z];
 #pragma unroll
-                for (int k = 0; k < 16; k++) x[k] = u2d(xp[256 * k]);
+                for (int k = 0; k < 16; k++) {
+                    const int w = (int)w0 + 256 * k;
+                    x[k] = u2d(xp[g == 1u ? w : galois_src2(w, g, logN)]);
+                }
             } else {
                 const uint64_t *xp = kj.ext[z] + ((size_t)j * r.ne + r.t) * N + w0;
 #pragma unroll
@@ -291,6 +296,32 @@ __global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t
         u[o0 + 256 * k] = d2u(a0[k]);
         u[o1 + 256 * k] = d2u(a1[k]);
     }
+}
+
+// Inverse tile pass whose input limbs are read through X -> X^g (the automorphism of a
+// key switch folded into ModUp's inverse transform): limb lt[b] is of job off / L1,
+// read from src + soff N at the words the Galois element gt.g[job] moves to each
+// position.  grid (N/4096, limbs).
+__global__ __launch_bounds__(kNT) void k_ntt_tile_gal(uint64_t *data, const uint64_t *src, LimbTab lt, GalTab gt,
+                                                      int L1, const double *tw, const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int limb = blockIdx.y, pidx = lt.pidx[limb], tile = blockIdx.x, tid = threadIdx.x;
+    const Mod m = info[pidx].m;
+    const uint32_t g = gt.g[lt.off[limb] / L1];
+    const uint64_t *in = src + (size_t)lt.soff[limb] * N;
+    const size_t w0 = (size_t)tile * kT + tid;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int w = (int)w0 + 256 * k;
+        v[k] = u2d(in[g == 1u ? w : galois_src2(w, g, logN)]);
+    }
+    tile_inverse(v, s, tid, tile, logN1, tw + (size_t)pidx * N, N, m);
+    uint64_t *out = data + (size_t)lt.off[limb] * N + w0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) out[256 * k] = d2u(v[k]);
 }
 
 // The first log2(N1) forward stages on one column of N1 canonical words (lazy, one
@@ -555,15 +586,18 @@ hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src,
 }
 
 // Inverse transform whose final factor is scale[pidx] instead of N^-1 (N >= 8192).
+// With gt, the input limbs are read through X -> X^g of their job (off / L1).
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
-                              const double *scale, hipStream_t s)
+                              const double *scale, hipStream_t s, const GalTab *gt, int L1)
 {
     const int N = c->N, N1 = N / kT;
-    if (N1 < 2) return hipErrorInvalidValue;
+    if (N1 < 2 || (gt && (!src || L1 < 1))) return hipErrorInvalidValue;
     if (lt.n == 0) return hipSuccess;
     const double bytes = 16.0 * N * lt.n;
-    hipError_t e = launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, dim3(N1, lt.n), dim3(kNT), s, data, src, lt,
-                          c->d_itw, c->d_info, c->log_n);
+    hipError_t e = gt ? launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile_gal, dim3(N1, lt.n), dim3(kNT), s, data, src,
+                               lt, *gt, L1, c->d_itw, c->d_info, c->log_n)
+                      : launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, dim3(N1, lt.n), dim3(kNT), s, data, src,
+                               lt, c->d_itw, c->d_info, c->log_n);
     if (e != hipSuccess) return e;
     return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt, c->d_itw,
                              c->d_info, c->log_n, scale);
@@ -656,16 +690,14 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
                   L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n);
 }
 
-// Key inner products of n_jobs jobs (g = 1, digits column-passed only) fused with the
-// digits' tile pass; sum = 1: one output, summed over the jobs; accumulate: added to
-// the output's previous value.
+// Key inner products of n_jobs jobs (digits of tau_g(d) column-passed only, own limbs
+// read from d through X -> X^g) fused with the digits' tile pass; sum = 1: one output,
+// summed over the jobs; accumulate: added to the output's previous value.
 hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
                          int accumulate, hipStream_t s, uint64_t *pout)
 {
     const int N = c->N, N1 = N / kT, nd = n_digits(c, level), ne = level + 1 + c->alpha;
     if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
-    for (int z = 0; z < n_jobs; z++)
-        if (kj.g[z] != 1u) return hipErrorInvalidValue;
     const double bytes = 8.0 * N * ne * (3.0 * nd * n_jobs + 2.0 * (sum ? 1 : n_jobs) * (1 + accumulate));
     const dim3 grid(sum ? 1 : n_jobs, N1, ne);
 #define NJ_IP(ND)                                                                                                   \

@@ -102,6 +102,27 @@ __device__ __forceinline__ IpRow ip_row(int t, int level, int L, int alpha)
     return r;
 }
 
+// Raw buffer access (gfx9 buffer resource: base, size in bytes): a per-thread 32-bit
+// byte offset plus a wave-uniform offset held in a scalar register, so strided loads
+// of a column need no per-load 64-bit address arithmetic.  Accesses past `bytes` read
+// 0 and write nothing.
+typedef unsigned int nj_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint64_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    const nj_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return ((uint64_t)v.y << 32) | v.x;
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint64_t x)
+{
+    nj_u32x2 v;
+    v.x = (uint32_t)x, v.y = (uint32_t)(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+
 struct GalTab {  // Galois element of each job (1 = none)
     uint32_t g[NJ_MAX_JOBS];
 };

@@ -356,14 +356,14 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
     const int limb = blockIdx.y, pidx = lt.pidx[limb];
     const PrimeInfo pi = info[pidx];
     const Mod m = pi.m;
-    const int c = blockIdx.x * kNT + threadIdx.x;
-    const size_t off = (size_t)lt.off[limb] * N + c;
-    const uint64_t *in = src ? src + (size_t)lt.soff[limb] * N + c : data + off;
-    uint64_t *out = data + off;
+    const uint32_t cb = 8u * (blockIdx.x * kNT + threadIdx.x);
+    uint64_t *outp = data + (size_t)lt.off[limb] * N;
+    const auto in = buf_rsrc(src ? src + (size_t)lt.soff[limb] * N : outp, 8u * N);
+    const auto out = buf_rsrc(outp, 8u * N);
     const double *W = tw + (size_t)pidx * N;
     double v[N1];
 #pragma unroll
-    for (int r = 0; r < N1; r++) v[r] = u2d(in[(size_t)r * kT]);
+    for (int r = 0; r < N1; r++) v[r] = u2d(buf_ld(in, cb, 8u * r * kT));
     if (!INV) {
         col_forward<N1>(v, W, m);
     } else {
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
         for (int r = 0; r < N1; r++) v[r] = mul_canon(v[r], sc, m);
     }
 #pragma unroll
-    for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(v[r]);
+    for (int r = 0; r < N1; r++) buf_st(out, cb, 8u * r * kT, d2u(v[r]));
 }
 
 // Basis conversion fused with the first log2(N1) forward stages of its outputs (the
@@ -406,7 +406,8 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
     const int c = blockIdx.x * kNT + threadIdx.x;
     const int n_out = sh.n_out[j], m = sh.m[j], o0 = blockIdx.y * kBcOut;
     if (o0 >= n_out) return;
-    const uint64_t *in = jp.in[job] + (size_t)sh.in_off0[j] * N + c;
+    const auto in = buf_rsrc(jp.in[job] + (size_t)sh.in_off0[j] * N, (uint32_t)m * N * 8u);
+    const uint32_t cb = 8u * c;
     const double *hat = sh.hat[j];
     int o[kBcOut];
     Mod mo[kBcOut];
@@ -420,15 +421,15 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
     for (int q = 0; q < kBcOut; q++)
 #pragma unroll
         for (int r = 0; r < N1; r++) acc[q][r] = 0.0;
-#pragma unroll 4
-    for (int a = 0; a < MMAX; a++) {  // four input limbs' loads in flight at a time
+#pragma unroll 2
+    for (int a = 0; a < MMAX; a++) {  // two input limbs' loads in flight at a time
         const int aa = a < m ? a : m - 1;
         double h[kBcOut];
 #pragma unroll
         for (int q = 0; q < kBcOut; q++) h[q] = a < m ? hat[aa * n_out + o[q]] : 0.0;
         uint64_t x[N1];
 #pragma unroll
-        for (int r = 0; r < N1; r++) x[r] = in[(size_t)aa * N + (size_t)r * kT];
+        for (int r = 0; r < N1; r++) x[r] = buf_ld(in, cb, 8u * ((uint32_t)aa * N + r * kT));
 #pragma unroll
         for (int r = 0; r < N1; r++) {
             const double xv = u2d(x[r]);
@@ -449,9 +450,9 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
         const int pq = sh.out_pidx[j][o[q]];
         col_forward<N1>(acc[q], tw + (size_t)pq * N, mo[q]);
         if (o0 + q < n_out) {
-            uint64_t *out = jp.out[job] + (size_t)sh.out_off[j][o[q]] * N + c;
+            const auto out = buf_rsrc(jp.out[job] + (size_t)sh.out_off[j][o[q]] * N, 8u * N);
 #pragma unroll
-            for (int r = 0; r < N1; r++) out[(size_t)r * kT] = d2u(acc[q][r]);
+            for (int r = 0; r < N1; r++) buf_st(out, cb, 8u * r * kT, d2u(acc[q][r]));
         }
     }
 }
@@ -504,20 +505,20 @@ __global__ __launch_bounds__(kNT) void k_lift_col(const uint64_t *last, int src_
                                                   const double *tw, const PrimeInfo *info, int logN)
 {
     const int N = 1 << logN, i = blockIdx.y, z = blockIdx.z;
-    const int c = blockIdx.x * kNT + threadIdx.x;
+    const uint32_t cb = 8u * (blockIdx.x * kNT + threadIdx.x);
     const Mod ms = info[src_pidx].m, mt = info[i].m;
     const double half = info[src_pidx].half;
-    const uint64_t *src = last + (size_t)z * N + c;
+    const auto src = buf_rsrc(last + (size_t)z * N, 8u * N);
     double v[N1];
 #pragma unroll
     for (int r = 0; r < N1; r++) {
-        const double x = u2d(src[(size_t)r * kT]);
+        const double x = u2d(buf_ld(src, cb, 8u * r * kT));
         v[r] = reduce(x > half ? x - ms.t : x, mt);  // centred, |x| < t_l / 2 < 2^49
     }
     col_forward<N1>(v, tw + (size_t)i * N, mt);
-    uint64_t *dst = lifted + ((size_t)z * n_out + i) * N + c;
+    const auto dst = buf_rsrc(lifted + ((size_t)z * n_out + i) * N, 8u * N);
 #pragma unroll
-    for (int r = 0; r < N1; r++) dst[(size_t)r * kT] = d2u(v[r]);
+    for (int r = 0; r < N1; r++) buf_st(dst, cb, 8u * r * kT, d2u(v[r]));
 }
 
 // k_ntt_tile_rs: the lifted limbs' tile pass with the rescale combine as its epilogue,

@@ -348,7 +348,9 @@ __device__ __forceinline__ void col_forward(double v[N1], const double *W, Mod m
 // columns pass: first log2(N1) stages, one column of N1 words per thread.  grid (4096/256, limbs).
 // The inverse ends with the factor N^-1, or scale[pidx] when a scale table is given
 // (N^-1 times a basis conversion's input factor, so the conversion need not apply it).
-template <int N1, bool INV>
+// DBL: the results are stored as FP64 values (bit patterns of exact integers in [0, t))
+// for the fused basis conversion, which then skips the integer -> FP64 step.
+template <int N1, bool INV, bool DBL = false>
 __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
                                                  const PrimeInfo *info, int logN, const double *scale)
 {
@@ -384,12 +386,14 @@ __global__ __launch_bounds__(kNT) void k_ntt_col(uint64_t *data, const uint64_t 
         for (int r = 0; r < N1; r++) v[r] = mul_canon(v[r], sc, m);
     }
 #pragma unroll
-    for (int r = 0; r < N1; r++) buf_st(out, cb, 8u * r * kT, d2u(v[r]));
+    for (int r = 0; r < N1; r++)
+        buf_st(out, cb, 8u * r * kT, DBL ? (uint64_t)__double_as_longlong(v[r]) : d2u(v[r]));
 }
 
 // Basis conversion fused with the first log2(N1) forward stages of its outputs (the
 // column pass).  Inputs are coefficient-form limbs already multiplied by
-// (D/q_a)^-1 (folded into their inverse transform's N^-1), so each output word is
+// (D/q_a)^-1 (folded into their inverse transform's N^-1) and stored by that transform
+// as FP64 values (launch_intt_scaled, launch_intt_cols_scaled), so each output word is
 // y_t = sum_a x_a (D/q_a) mod t; the converted limbs are never stored before their
 // column pass.  Thread = one column (N1 words at stride 4096) of OUT consecutive
 // targets of (job, digit) blockIdx.z = job * nd + digit; grid (4096/256,
@@ -432,7 +436,7 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
         for (int r = 0; r < N1; r++) x[r] = buf_ld(in, cb, 8u * ((uint32_t)aa * N + r * kT));
 #pragma unroll
         for (int r = 0; r < N1; r++) {
-            const double xv = u2d(x[r]);
+            const double xv = __longlong_as_double((long long)x[r]);  // stored as FP64 by the inverse transform
 #pragma unroll
             for (int q = 0; q < kBcOut; q++) acc[q][r] += mul_lazy(xv, h[q], mo[q]);
         }
@@ -548,17 +552,17 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_rs(const uint64_t *lifted, con
     }
 }
 
-template <bool INV>
+template <bool INV, bool DBL = false>
 static hipError_t launch_cols(const nj_ctx *c, int kind, double bytes, int N1, dim3 grid, hipStream_t s,
                               uint64_t *data, const uint64_t *src, const LimbTab &lt, const double *tw,
                               const PrimeInfo *info, int logN, const double *scale = nullptr)
 {
     switch (N1) {
-    case 2: return launch(c, kind, bytes, k_ntt_col<2, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
-    case 4: return launch(c, kind, bytes, k_ntt_col<4, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
-    case 8: return launch(c, kind, bytes, k_ntt_col<8, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    case 2: return launch(c, kind, bytes, k_ntt_col<2, INV, DBL>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    case 4: return launch(c, kind, bytes, k_ntt_col<4, INV, DBL>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+    case 8: return launch(c, kind, bytes, k_ntt_col<8, INV, DBL>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
     default:
-        return launch(c, kind, bytes, k_ntt_col<16, INV>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
+        return launch(c, kind, bytes, k_ntt_col<16, INV, DBL>, grid, dim3(kNT), s, data, src, lt, tw, info, logN, scale);
     }
 }
 
@@ -586,8 +590,9 @@ hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src,
     return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, gc, s, data, nullptr, lt, tw, c->d_info, c->log_n);
 }
 
-// Inverse transform whose final factor is scale[pidx] instead of N^-1 (N >= 8192).
-// With gt, the input limbs are read through X -> X^g of their job (off / L1).
+// Inverse transform whose final factor is scale[pidx] instead of N^-1 (N >= 8192),
+// for the fused basis conversion: the results are stored as FP64 values.  With gt,
+// the input limbs are read through X -> X^g of their job (off / L1).
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
                               const double *scale, hipStream_t s, const GalTab *gt, int L1)
 {
@@ -600,8 +605,8 @@ hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *s
                       : launch(c, PROF_NTT_TILE_INV, bytes, k_ntt_tile<true>, dim3(N1, lt.n), dim3(kNT), s, data, src,
                                lt, c->d_itw, c->d_info, c->log_n);
     if (e != hipSuccess) return e;
-    return launch_cols<true>(c, PROF_NTT_COL_INV, bytes, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt, c->d_itw,
-                             c->d_info, c->log_n, scale);
+    return launch_cols<true, true>(c, PROF_NTT_COL_INV, bytes, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt,
+                                   c->d_itw, c->d_info, c->log_n, scale);
 }
 
 // Rescale of P packed level-l polynomials (P = 2 per ciphertext; limbs 0..n_out-1 of
@@ -732,15 +737,15 @@ hipError_t launch_key_ip_p(const nj_ctx *c, int level, const KeyJobs &kj, int n_
 }
 
 // The column pass of an inverse transform whose tile pass already ran, in place, with
-// the final factor scale[pidx] (N >= 8192).
+// the final factor scale[pidx] (N >= 8192); results stored as FP64 values, as above.
 hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTab &lt, const double *scale,
                                    hipStream_t s)
 {
     const int N = c->N, N1 = N / kT;
     if (N1 < 2) return hipErrorInvalidValue;
     if (lt.n == 0) return hipSuccess;
-    return launch_cols<true>(c, PROF_NTT_COL_INV, 16.0 * N * lt.n, N1, dim3(kT / kNT, lt.n), s, data, nullptr, lt,
-                             c->d_itw, c->d_info, c->log_n, scale);
+    return launch_cols<true, true>(c, PROF_NTT_COL_INV, 16.0 * N * lt.n, N1, dim3(kT / kNT, lt.n), s, data, nullptr,
+                                   lt, c->d_itw, c->d_info, c->log_n, scale);
 }
 
 }  // namespace nj

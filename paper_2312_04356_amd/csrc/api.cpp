@@ -167,27 +167,28 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled);
+                  hipStream_t s, bool p_tiled, uint64_t *last_out);
 
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
-    if (fuse_ip(c, l)) {  // special-prime rows straight into ModDown's inverse transform
-        NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s, 1));
-        NJ_HIP(launch_key_ip_p(c, l, kj, K, M.pc, s));
-        return ks_down(c, l, K, mj, sum, acc, M, s, true);
-    }
     NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
     return ks_down(c, l, K, mj, sum, acc, M, s);
 }
 
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled)
+                  hipStream_t s, bool p_tiled, uint64_t *last_out)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
     if (p_tiled && !fused) return fail(NJ_EUNSUPPORTED, "ModDown: pre-transformed special-prime rows need N >= 8192");
+    const bool one = !sum && N >= 4096 && K == 1;  // the fused combine of one job
+    if (last_out && !(one && fused)) return fail(NJ_EUNSUPPORTED, "ModDown: the rescale hand-off needs one job, N >= 8192");
+    // one job with a previous value held elsewhere: the fused combine reads it there
+    const uint64_t *acc0 = one && acc && acc != mj.out[0] ? acc : nullptr;
+    if (acc && !sum && K == 1 && acc != mj.out[0] && !one)
+        NJ_HIP(hipMemcpyAsync(mj.out[0], acc, 2 * (size_t)(l + 1) * N * 8, hipMemcpyDeviceToDevice, s));
     auto intt = [&](const LimbTab &t) {
         if (p_tiled) return launch_intt_cols_scaled(c, M.pc, t, c->d_downscale, s);
         return fused ? launch_intt_scaled(c, M.pc, M.u, t, c->d_downscale, s) : launch_ntt(c, M.pc, t, true, s, M.u);
@@ -215,7 +216,7 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
     NJ_HIP(fused ? launch_bconv_col(c, sh, jp, 2 * K, s) : launch_bconv_multi(c, sh, jp, 2 * K, s));
     if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
-        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s));
+        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out));
         return NJ_OK;
     }
     auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.conv, t, s) : launch_ntt(c, M.conv, t, false, s); };
@@ -274,8 +275,9 @@ size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
 
 // sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
 nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
-                     hipStream_t s)
+                     hipStream_t s, uint64_t *last_out, bool *last_done)
 {
+    if (last_done) *last_done = false;
     const int l = lt.level, n = c->N / 2;
     const size_t N = c->N, clen = 2 * N * (l + 1);
     const int nb = (int)lt.babies.size(), ng = (int)lt.giants.size();
@@ -381,12 +383,13 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                      : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
         }
-        if (acc) NJ_HIP(hipMemcpyAsync(out, acc, clen * 8, hipMemcpyDeviceToDevice, s));
         MultiBufs M1 = M;
         M1.u = usum;
         MdJobs mj;
         mj.add[0] = c0sum, mj.g_add[0] = 1, mj.out[0] = out;
-        return ks_down(c, l, 1, mj, 0, acc ? out : nullptr, M1, s, fuse_ip(c, l));
+        const bool hand = last_out && N >= 8192 && c->alpha <= 8;  // the rescale's first pass rides along
+        if (hand && last_done) *last_done = true;
+        return ks_down(c, l, 1, mj, 0, acc, M1, s, fuse_ip(c, l), hand ? last_out : nullptr);
     }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
@@ -685,14 +688,15 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 
 // rescale of a ciphertext [2][l+1] -> [2][l]; out must not alias in
 nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out,
-                  int n_polys)
+                  int n_polys, uint64_t *last_pre)
 {
     const size_t N = c->N;
     if (n_out < 0) n_out = l;
+    if (last_pre && (N < 8192 || n_polys != 2)) return fail(NJ_EUNSUPPORTED, "rescale: hand-off needs N >= 8192");
     if (N >= 8192) {  // the lifted limbs stay in out, transformed and combined in place
-        uint64_t *last = A.take(n_polys * N);
+        uint64_t *last = last_pre ? last_pre : A.take(n_polys * N);
         if (!last) return fail(NJ_ENOMEM, "scratch too small");
-        NJ_HIP(launch_rescale_fused(c, l, in, out, n_out, last, out, s, n_polys));
+        NJ_HIP(launch_rescale_fused(c, l, in, out, n_out, last, out, s, n_polys, last_pre != nullptr));
         return NJ_OK;
     }
     if (n_polys != 2) return fail(NJ_EUNSUPPORTED, "rescale: packed ciphertexts need N >= 8192");
@@ -827,6 +831,20 @@ nj_status cts_batch(nj_ctx *c, const nj_plan *p, const uint64_t *in, int n, uint
     return NJ_OK;
 }
 
+// One BSGS transform then a rescale: x -> y (scratch) -> out (level l-1).  When the
+// transform's last step is a one-job ModDown (lazy giant steps, N >= 8192) it also
+// runs the first pass of the rescale's inverse transform.
+nj_status bsgs_rescale(nj_ctx *c, const nj_lt_t &lt, const uint64_t *x, uint64_t *y, uint64_t *out, Arena A,
+                       hipStream_t s)
+{
+    uint64_t *last = c->N >= 8192 ? A.take(2 * (size_t)c->N) : nullptr;
+    if (c->N >= 8192 && !last) return fail(NJ_ENOMEM, "scratch too small");
+    bool done = false;
+    nj_status st = bsgs_apply(c, lt, x, y, 1, A, s, last, &done);
+    if (st) return st;
+    return rescale(c, lt.level, y, out, A, s, -1, 2, done ? last : nullptr);
+}
+
 size_t cts_single_words(const nj_ctx *c, const nj_plan *p)
 {
     const size_t N = c->N, top = c->L, clen = 2 * N * (top + 1);
@@ -847,8 +865,7 @@ nj_status cts_single(nj_ctx *c, const nj_plan *p, const uint64_t *in, uint64_t *
     int l = c->L;
     for (const auto &lt : p->lts) {
         if (lt.level != l) return fail(NJ_ELEVEL, "CoeffToSlot: plan levels do not follow the context's top level");
-        if ((st = bsgs_apply(c, lt, x, y, 1, A, s))) return st;
-        if ((st = rescale(c, l, y, x, A, s))) return st;
+        if ((st = bsgs_rescale(c, lt, x, y, x, A, s))) return st;
         l--;
     }
     return conj_split(c, l, x, re, im, A, s);
@@ -1242,9 +1259,7 @@ nj_status nj_conv2d_cins(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *ou
     Arena A = arena_for(c, clen + bsgs_words(c, lt) + (size_t)c->N * (lt.level + 2), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
     uint64_t *y = A.take(clen);
-    st = bsgs_apply(c, lt, in->data, y, 1, A, S(stream));
-    if (st) return st;
-    st = rescale(c, lt.level, y, out->data, A, S(stream));
+    st = bsgs_rescale(c, lt, in->data, y, out->data, A, S(stream));
     if (st) return st;
     out->level = lt.level - 1, out->is_ntt = 1, out->scale = in->scale * lt.scale / (double)c->primes[lt.level];
     return NJ_OK;

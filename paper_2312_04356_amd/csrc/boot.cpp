@@ -475,8 +475,7 @@ nj_status nj_stoc1(nj_ctx *c, const nj_plan *p, const nj_ct *in, nj_ct *out, voi
     NJ_HIP(hipMemcpyAsync(x, in->data, clen * 8, hipMemcpyDeviceToDevice, S(stream)));
     int l = in->level;
     for (const auto &lt : p->lts) {
-        if ((st = bsgs_apply(c, lt, x, y, 1, A, S(stream)))) return st;
-        if ((st = rescale(c, l, y, x, A, S(stream)))) return st;
+        if ((st = bsgs_rescale(c, lt, x, y, x, A, S(stream)))) return st;
         l--;
     }
     NJ_HIP(hipMemcpyAsync(out->data, x, 2 * N * (l + 1) * 8, hipMemcpyDeviceToDevice, S(stream)));

@@ -71,9 +71,12 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
                    MultiBufs &M, hipStream_t s);
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs
 // (p_tiled: the inner products already left their special-prime rows in M.pc after the
-// first 12 stages of the inverse transform; N >= 8192)
+// first 12 stages of the inverse transform; N >= 8192.  acc: the previous value added
+// (sum = 0: for K = 1 it may be any ciphertext, else it must be the outputs).
+// last_out, one job, N >= 8192: the output's last limb also leaves through the first
+// 12 stages of its inverse transform into last_out [2][N], for rescale(last_pre))
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled = false);
+                  hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr);
 
 // inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
 struct MacEntry {
@@ -84,8 +87,14 @@ nj_status mac_general(nj_ctx *c, int l, const std::vector<const uint64_t *> &bab
 
 nj_lt_t at_level(const nj_lt_t &lt, int l);
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt);
+// (last_out [2][N]: when the transform ends in a one-job ModDown it also writes its last
+// limb after the first pass of an inverse transform there and sets *last_done)
 nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
-                     hipStream_t s);
+                     hipStream_t s, uint64_t *last_out = nullptr, bool *last_done = nullptr);
+// bsgs_apply into y, then rescale into out (which may be x); the rescale's first pass
+// rides on the transform's last ModDown where it can
+nj_status bsgs_rescale(nj_ctx *c, const nj_lt_t &lt, const uint64_t *x, uint64_t *y, uint64_t *out, Arena A,
+                       hipStream_t s);
 size_t bsgs_batch_words(const nj_ctx *c, const nj_lt_t &lt, int K);
 nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *in, uint64_t *out, Arena A,
                            hipStream_t s);
@@ -98,7 +107,7 @@ nj_status block_bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uin
 // (rescale followed by a level drop, computing only the kept limbs)
 // n_polys > 2 (several ciphertexts packed at level l) needs N >= 8192
 nj_status rescale(nj_ctx *c, int l, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s, int n_out = -1,
-                  int n_polys = 2);
+                  int n_polys = 2, uint64_t *last_pre = nullptr);
 // rescale of K packed ciphertexts [K][2][l+1] -> [K][2][l] (one set of launches when N >= 8192)
 nj_status rescale_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint64_t *out, Arena A, hipStream_t s);
 nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena A, hipStream_t s);

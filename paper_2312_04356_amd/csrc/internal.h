@@ -286,7 +286,7 @@ hipError_t launch_ntt(const nj_ctx *c, uint64_t *data, const LimbTab &lt, bool i
 hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt,
                               const double *scale, hipStream_t s, const GalTab *gt = nullptr, int L1 = 0);
 hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
-                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys = 2);
+                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys = 2, bool last_tiled = false);
 hipError_t launch_ntt_tiles(const nj_ctx *c, uint64_t *data, const LimbTab &lt, hipStream_t s);
 hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
 // key inner products fused with the extended digits' forward tile pass (N >= 8192,
@@ -296,11 +296,14 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
                          int accumulate, hipStream_t s, uint64_t *pout = nullptr);
 // (pout given: the special-prime rows skip u and leave through the first 12 stages of
 // ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout)
-hipError_t launch_key_ip_p(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout, hipStream_t s);
 hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTab &lt, const double *scale,
                                    hipStream_t s);
+// (acc0: job 0's previous value read from there instead of its output; last_out, one
+// job: the last limb also leaves through the first 12 stages of its inverse transform
+// into last_out [2][N], for launch_rescale_fused(last_tiled))
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
-                              const MdJobs &mj, int acc, int cols_done, hipStream_t s);
+                              const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0 = nullptr,
+                              uint64_t *last_out = nullptr);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form
@@ -336,9 +339,8 @@ hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out,
 
 // ------------------------------------------------------------------- ksw.hip
 hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
-// (q_only: the rows of Q_l only; the special-prime rows come from launch_key_ip_p)
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
-                               hipStream_t s, int q_only = 0);
+                               hipStream_t s);
 hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
                                 const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
 hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);

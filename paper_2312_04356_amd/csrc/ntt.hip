@@ -184,44 +184,6 @@ __device__ __forceinline__ void store_p_rows(double a0[16], double a1[16], doubl
     for (int k = 0; k < 16; k++) out[half_off + w0 + 256 * k] = d2u(a1[k]);
 }
 
-// The special-prime rows of K key inner products whose digits are read through
-// X -> X^g (hoisted baby steps), each block one 4096-word tile of one row of one job,
-// finished with the first 12 stages of ModDown's inverse transform: job z's row p_a
-// lands in pout at rows (2 z) alpha + a (first half) and (2 z + 1) alpha + a, and is
-// never stored in evaluation form.  grid (K, N/4096, alpha).
-template <int ND>
-__global__ __launch_bounds__(kNT) void k_key_ip_p(KeyJobs kj, uint64_t *pout, int level, int L, int alpha, int nq,
-                                                  const double *itw, const PrimeInfo *info, int logN)
-{
-    __shared__ double s[kT + kT / 16];
-    const int N = 1 << logN, logN1 = logN - 12;
-    const int z = blockIdx.x, tile = blockIdx.y, a = blockIdx.z, tid = threadIdx.x;
-    const int t = level + 1 + a, pidx = nq + a;
-    const Mod m = info[pidx].m;
-    const IpRow r = ip_row(t, level, L, alpha);
-    const size_t w0 = (size_t)tile * kT + tid;
-    const uint32_t g = kj.g[z];
-    double a0[16], a1[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) a0[k] = 0.0, a1[k] = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < ND; j++) {
-        const uint64_t *xp = kj.ext[z] + ((size_t)j * r.ne + r.t) * N;
-        const uint64_t *kb = kj.key[z] + ((size_t)j * 2 * r.nk + r.kl) * N + w0, *ka = kb + r.nk * N;
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            const int w = (int)w0 + 256 * k;
-            const double x = u2d(xp[g == 1u ? w : galois_src2(w, g, logN)]);
-            a0[k] += mul_lazy(x, u2d(kb[256 * k]), m);
-            a1[k] += mul_lazy(x, u2d(ka[256 * k]), m);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
-    store_p_rows(a0, a1, s, pout + ((size_t)2 * z * alpha + a) * N, (size_t)alpha * N, w0, tid, tile, logN1,
-                 itw + (size_t)pidx * N, N, m);
-}
-
 // Key inner products fused with the forward tile pass of the extended digits (N >=
 // 8192).  The key switch is of tau_g(d_z), g = kj.g[z]: at output limb t, digit j of
 // job z is either the job's own limb d_z[t] read through X -> X^g (evaluation form) or
@@ -465,11 +427,15 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
 // converted limbs conv [K][2][l+1][N] (coefficient form, column pass already applied)
 // are transformed tile by tile and, instead of being stored, combined at once:
 // out_z[p][i] = (u_z[p][i] - NTT(conv_z[p][i])) P^-1 (+ c0 of job z read through
-// X -> X^g_add[z] for p = 0) (+ the previous out_z when acc), with u_z at
-// u_base + z 2 ne N.  grid (N/4096, 2 K (l+1)): limb w = (2 z + p)(l+1) + i.
-__global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const uint64_t *u_base, MdJobs mj, int acc,
+// X -> X^g_add[z] for p = 0) (+ the previous out_z when acc; job 0 reads it from acc0
+// instead when given), with u_z at u_base + z 2 ne N.  With last_out (one job), the
+// blocks of the last limb also run the first 12 stages of its inverse transform on
+// the words they wrote and store them at last_out + p N, ready for a rescale.
+// grid (N/4096, 2 K (l+1)): limb w = (2 z + p)(l+1) + i.
+__global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, const uint64_t *u_base, MdJobs mj, int acc,
                                                      int level, int ne, const double *pinv, const double *tw,
-                                                     const PrimeInfo *info, int logN)
+                                                     const PrimeInfo *info, int logN, const uint64_t *acc0,
+                                                     uint64_t *last_out, const double *itw)
 {
     __shared__ double s[kT + kT / 16];
     const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1;
@@ -487,6 +453,7 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const
     const uint64_t *add = p == 0 ? mj.add[z] : nullptr;
     const uint32_t g = mj.g_add[z];
     uint64_t *out = mj.out[z] + ((size_t)p * L1 + i) * N + t0;
+    const uint64_t *prev = acc0 && z == 0 ? acc0 + ((size_t)p * L1 + i) * N + t0 : out;
     const double pv = pinv[i];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
@@ -496,8 +463,16 @@ __global__ __launch_bounds__(kNT) void k_ntt_tile_md(const uint64_t *conv, const
             const int kk = (int)t0 + x;
             t = add_mod(t, u2d(add[(size_t)i * N + (g <= 1u ? kk : galois_src2(kk, g, logN))]), m);
         }
-        if (acc) t = add_mod(t, u2d(out[x]), m);
+        if (acc) t = add_mod(t, u2d(prev[x]), m);
         out[x] = d2u(t);
+    }
+    if (last_out && i == level) {  // the rescale's inverse tile pass of this limb
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = u2d(out[tid + 256 * k]);  // this thread's own words
+        __syncthreads();
+        tile_inverse(v, s, tid, tile, logN1, itw + (size_t)i * N, N, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) last_out[(size_t)p * N + t0 + tid + 256 * k] = d2u(v[k]);
     }
 }
 
@@ -615,14 +590,17 @@ hipError_t launch_intt_scaled(const nj_ctx *c, uint64_t *data, const uint64_t *s
 // out: each tile block reads its own lifted words before writing them), tile pass
 // fused with the combine.  in must not alias out.
 hipError_t launch_rescale_fused(const nj_ctx *c, int level, const uint64_t *in, uint64_t *out, int n_out,
-                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys)
+                                uint64_t *last, uint64_t *lifted, hipStream_t s, int n_polys, bool last_tiled)
 {
     const int N = c->N, N1 = N / kT;
     if (N1 < 2 || n_out < 1 || n_out > level || n_polys < 1 || n_polys > NJ_MAX_LIMBS) return hipErrorInvalidValue;
     LimbTab lt;
     lt.n = n_polys;
     for (int p = 0; p < n_polys; p++) lt.pidx[p] = level, lt.off[p] = p, lt.soff[p] = p * (level + 1) + level;
-    hipError_t e = launch_ntt_fast(c, last, in, lt, true, s);
+    // last_tiled: the last limbs' inverse tile pass already ran (into last), the column pass follows
+    hipError_t e = last_tiled ? launch_cols<true>(c, PROF_NTT_COL_INV, 16.0 * N * n_polys, N1, dim3(kT / kNT, n_polys), s,
+                                                  last, nullptr, lt, c->d_itw, c->d_info, c->log_n)
+                              : launch_ntt_fast(c, last, in, lt, true, s);
     if (e != hipSuccess) return e;
     const dim3 gl(kT / kNT, n_out, n_polys);
     const double bl = 8.0 * N * n_polys * (1 + n_out);
@@ -677,10 +655,11 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
 // limbs (N >= 4096; cols_done: the column pass was already applied); same results
 // as the transform followed by the combine.
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
-                              const MdJobs &mj, int acc, int cols_done, hipStream_t s)
+                              const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0,
+                              uint64_t *last_out)
 {
     const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1;
-    if (N < kT || K < 1 || K > NJ_MAX_JOBS) return hipErrorInvalidValue;
+    if (N < kT || K < 1 || K > NJ_MAX_JOBS || (last_out && K != 1)) return hipErrorInvalidValue;
     if (N1 > 1 && !cols_done) {
         LimbTab lt;
         for (int b = 0; b < n; b += NJ_MAX_LIMBS) {
@@ -693,7 +672,7 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
     }
     const double bytes = 8.0 * N * (n * 3.0 + K * L1 + (acc ? n : 0));
     return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
-                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n);
+                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw);
 }
 
 // Key inner products of n_jobs jobs (digits of tau_g(d) column-passed only, own limbs
@@ -717,23 +696,6 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
     }
 #undef NJ_IP
     return hipErrorInvalidValue;
-}
-
-// Special-prime rows of K key inner products with the digits read through X -> X^g,
-// finished with the first 12 stages of ModDown's inverse transform into pout (N >= 8192,
-// 1..4 digits); the Q rows come from launch_key_ip_multi(q_only = 1).
-hipError_t launch_key_ip_p(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout, hipStream_t s)
-{
-    const int N = c->N, N1 = N / kT, nd = n_digits(c, level), al = c->alpha;
-    if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
-    const double bytes = 8.0 * N * al * n_jobs * (3.0 * nd + 2.0);
-    const dim3 grid(n_jobs, N1, al);
-    switch (nd) {
-    case 1: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<1>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
-    case 2: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<2>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
-    case 3: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<3>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
-    default: return launch(c, PROF_KEYIP, bytes, k_key_ip_p<4>, grid, dim3(kNT), s, kj, pout, level, c->L, al, c->n_q, c->d_itw, c->d_info, c->log_n);
-    }
 }
 
 // The column pass of an inverse transform whose tile pass already ran, in place, with

@@ -33,10 +33,10 @@ const uint64_t *key_of(const nj_ctx *c, uint32_t g)
 bool fuse_ip(const nj_ctx *c, int l) { return c->N >= 8192 && c->alpha <= 8 && n_digits(c, l) <= 4; }
 
 nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
-                   MultiBufs &M, hipStream_t s)
+                   MultiBufs &M, hipStream_t s, const MdConj *conj)
 {
     NJ_HIP(launch_ntt_ip(c, l, kj, K, M.u, 0, 0, s, M.pc));
-    return ks_down(c, l, K, mj, sum, acc, M, s, true);
+    return ks_down(c, l, K, mj, sum, acc, M, s, true, nullptr, conj);
 }
 
 // One key switch of tau_g(d) (d in evaluation form, level l) with `key`: ModUp,
@@ -45,9 +45,10 @@ nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 // the same kernels; where the inner product runs the digits' tile pass the
 // automorphism rides on ModUp's inverse transform and on the own-limb reads.
 nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t *key, const uint64_t *add,
-                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s)
+                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s, const MdConj *conj)
 {
     const bool f = fuse_ip(c, l);
+    if (conj && !f) return fail(NJ_EUNSUPPORTED, "key switch: the fused split needs the fused inner product");
     if (!f && g != 1u) {  // the automorphism first, into M.d
         AutoJobs aj;
         aj.in[0] = d, aj.out[0] = M.d, aj.g[0] = g;
@@ -62,7 +63,7 @@ nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t
     MdJobs mj;
     kj.ext[0] = M.ext, kj.d[0] = d, kj.g[0] = g, kj.key[0] = key;
     mj.add[0] = add, mj.g_add[0] = g_add, mj.out[0] = out;
-    return f ? ks_fused(c, l, 1, kj, mj, 0, nullptr, M, s) : ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
+    return f ? ks_fused(c, l, 1, kj, mj, 0, nullptr, M, s, conj) : ks_multi(c, l, 1, kj, mj, 0, nullptr, M, s);
 }
 
 // (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
@@ -167,7 +168,7 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out);
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj);
 
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
@@ -178,13 +179,14 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out)
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
     if (p_tiled && !fused) return fail(NJ_EUNSUPPORTED, "ModDown: pre-transformed special-prime rows need N >= 8192");
     const bool one = !sum && N >= 4096 && K == 1;  // the fused combine of one job
     if (last_out && !(one && fused)) return fail(NJ_EUNSUPPORTED, "ModDown: the rescale hand-off needs one job, N >= 8192");
+    if (conj && !one) return fail(NJ_EUNSUPPORTED, "ModDown: the fused split needs one job, N >= 4096");
     // one job with a previous value held elsewhere: the fused combine reads it there
     const uint64_t *acc0 = one && acc && acc != mj.out[0] ? acc : nullptr;
     if (acc && !sum && K == 1 && acc != mj.out[0] && !one)
@@ -216,7 +218,7 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
     NJ_HIP(fused ? launch_bconv_col(c, sh, jp, 2 * K, s) : launch_bconv_multi(c, sh, jp, 2 * K, s));
     if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
-        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out));
+        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out, conj));
         return NJ_OK;
     }
     auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.conv, t, s) : launch_ntt(c, M.conv, t, false, s); };
@@ -330,7 +332,8 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
             if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
         }
-        if ((st = (!hoist && fuse_ip(c, l) ? ks_fused : ks_multi)(c, l, K, kj, mj, 0, nullptr, M, s))) return st;
+        st = !hoist && fuse_ip(c, l) ? ks_fused(c, l, K, kj, mj, 0, nullptr, M, s) : ks_multi(c, l, K, kj, mj, 0, nullptr, M, s);
+        if (st) return st;
     }
     // every giant step's inner sum
     std::vector<MacEntry> ent;
@@ -416,7 +419,8 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
             if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
         }
-        if ((st = (f ? ks_fused : ks_multi)(c, l, K, kj, mj, 1, acc, M, s))) return st;
+        st = f ? ks_fused(c, l, K, kj, mj, 1, acc, M, s) : ks_multi(c, l, K, kj, mj, 1, acc, M, s);
+        if (st) return st;
         acc = out;
     }
     (void)n;
@@ -734,16 +738,21 @@ nj_status modraise(nj_ctx *c, const uint64_t *in, int top, uint64_t *out, Arena 
     const size_t N = c->N;
     uint64_t *tmp = A.take(2 * N);
     if (!tmp) return fail(NJ_ENOMEM, "scratch too small");
-    NJ_HIP(hipMemcpyAsync(tmp, in, 2 * N * 8, hipMemcpyDeviceToDevice, s));
     LimbTab lt;
     lt.n = 2;
     lt.pidx[0] = lt.pidx[1] = 0;
     lt.off[0] = 0, lt.off[1] = 1;
-    NJ_HIP(launch_ntt(c, tmp, lt, true, s));
-    for (int p = 0; p < 2; p++) NJ_HIP(launch_lift_last(c, tmp + p * N, 0, top + 1, out + (size_t)p * (top + 1) * N, s));
+    lt.soff[0] = 0, lt.soff[1] = 1;
+    NJ_HIP(launch_ntt(c, tmp, lt, true, s, in));  // coefficient form of both level-0 limbs
     LimbTab lo;
     lo.n = 2 * (top + 1);
     for (int k = 0; k < lo.n; k++) lo.pidx[k] = k % (top + 1), lo.off[k] = k;
+    if (N >= 8192) {  // lift fused with the column pass, then the tile pass
+        NJ_HIP(launch_lift_col(c, tmp, 0, 2, top + 1, out, s));
+        NJ_HIP(launch_ntt_tiles(c, out, lo, s));
+        return NJ_OK;
+    }
+    for (int p = 0; p < 2; p++) NJ_HIP(launch_lift_last(c, tmp + p * N, 0, top + 1, out + (size_t)p * (top + 1) * N, s));
     NJ_HIP(launch_ntt(c, out, lo, false, s));
     return NJ_OK;
 }
@@ -759,6 +768,15 @@ LimbTab ct_limbs(int l)
 nj_status conj_split(nj_ctx *c, int l, const uint64_t *x, uint64_t *re, uint64_t *im, Arena A, hipStream_t s)
 {
     const size_t clen = 2 * (size_t)c->N * (l + 1);
+    if (fuse_ip(c, l)) {  // the split runs inside the conjugation's ModDown combine
+        const uint32_t g = 2 * c->N - 1;
+        const uint64_t *key = key_of(c, g);
+        if (!key) return fail(NJ_ENOKEY, "no switching key for the conjugation");
+        MultiBufs M;
+        if (!multi_bufs(c, l, 1, A, M)) return fail(NJ_ENOMEM, "scratch too small");
+        const MdConj cj{x, re, im};
+        return ks_one(c, l, x + clen / 2, g, key, x, g, nullptr, M, s, &cj);
+    }
     uint64_t *cj = A.take(clen);
     if (!cj) return fail(NJ_ENOMEM, "scratch too small");
     nj_status st = apply_galois(c, l, x, 2 * c->N - 1, cj, A, s);

@@ -141,7 +141,7 @@ class Ev {
             kj.ext[z] = M.ext + z * nd * ne * N, kj.d[z] = d2.d + z * N * (l + 1), kj.key[z] = relin, kj.g[z] = 1;
             mj.add[z] = nullptr, mj.g_add[z] = 1, mj.out[z] = t.d + z * cstride(l);
         }
-        check((f ? ks_fused : ks_multi)(c, l, K, kj, mj, 0, t.d, M, s));  // t += the switched d2
+        check(f ? ks_fused(c, l, K, kj, mj, 0, t.d, M, s) : ks_multi(c, l, K, kj, mj, 0, t.d, M, s));  // t += the switched d2
         rescale_into(t, o, A);
         release(t), release(d2);
         return o;

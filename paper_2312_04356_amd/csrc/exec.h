@@ -60,12 +60,14 @@ bool fuse_ip(const nj_ctx *c, int l);
 nj_status eval_mod_pair(nj_ctx *c, const nj_ct *re, const nj_ct *im, int K, int r, const double *coeffs,
                         int n_coeffs, nj_ct *out_re, nj_ct *out_im, void *stream);
 // one key switch of tau_g(d): out = (ModDown_0 + add read through X -> X^g_add, ModDown_1)
+// (conj: the output is replaced by the real/imaginary split with add's ciphertext, see
+// MdConj; N >= 8192)
 nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t *key, const uint64_t *add,
-                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s);
+                 uint32_t g_add, uint64_t *out, MultiBufs &M, hipStream_t s, const MdConj *conj = nullptr);
 // as ks_multi, on digits of tau_g(d) that modup_multi left column-passed (tiles =
 // false); kj.d[z] is d itself, read through X -> X^g[z] for the own limbs
 nj_status ks_fused(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
-                   MultiBufs &M, hipStream_t s);
+                   MultiBufs &M, hipStream_t s, const MdConj *conj = nullptr);
 // K key switches on ModUp'ed digits (M.ext): key inner products, then ks_down
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s);
@@ -76,7 +78,7 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 // last_out, one job, N >= 8192: the output's last limb also leaves through the first
 // 12 stages of its inverse transform into last_out [2][N], for rescale(last_pre))
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr);
+                  hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr, const MdConj *conj = nullptr);
 
 // inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
 struct MacEntry {

@@ -123,6 +123,13 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
 }
 
+// Real/imaginary split fused into a one-job ModDown combine: with the combined value
+// xc of the conjugation key switch, re = x + xc and im = -X^{N/2} (x - xc) are written
+// instead of xc (kernel argument; x null = off).
+struct MdConj {
+    const uint64_t *x;
+    uint64_t *re, *im;
+};
 struct GalTab {  // Galois element of each job (1 = none)
     uint32_t g[NJ_MAX_JOBS];
 };
@@ -296,6 +303,10 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
                          int accumulate, hipStream_t s, uint64_t *pout = nullptr);
 // (pout given: the special-prime rows skip u and leave through the first 12 stages of
 // ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout)
+// centred lift of n_polys limbs (prime src_pidx, coefficient form, src + z N) into
+// primes 0..n_out-1 with the column pass applied, out [n_polys][n_out][N] (N >= 8192)
+hipError_t launch_lift_col(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_polys, int n_out, uint64_t *out,
+                           hipStream_t s);
 hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTab &lt, const double *scale,
                                    hipStream_t s);
 // (acc0: job 0's previous value read from there instead of its output; last_out, one
@@ -303,7 +314,7 @@ hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTa
 // into last_out [2][N], for launch_rescale_fused(last_tiled))
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0 = nullptr,
-                              uint64_t *last_out = nullptr);
+                              uint64_t *last_out = nullptr, const MdConj *conj = nullptr);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form

@@ -432,10 +432,11 @@ __global__ __launch_bounds__(kNT) void k_bconv_col(BconvShared sh, BconvPtrs jp,
 // blocks of the last limb also run the first 12 stages of its inverse transform on
 // the words they wrote and store them at last_out + p N, ready for a rescale.
 // grid (N/4096, 2 K (l+1)): limb w = (2 z + p)(l+1) + i.
+template <bool CONJ>
 __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, const uint64_t *u_base, MdJobs mj, int acc,
                                                      int level, int ne, const double *pinv, const double *tw,
                                                      const PrimeInfo *info, int logN, const uint64_t *acc0,
-                                                     uint64_t *last_out, const double *itw)
+                                                     uint64_t *last_out, const double *itw, MdConj cj)
 {
     __shared__ double s[kT + kT / 16];
     const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1;
@@ -464,7 +465,16 @@ __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, co
             t = add_mod(t, u2d(add[(size_t)i * N + (g <= 1u ? kk : galois_src2(kk, g, logN))]), m);
         }
         if (acc) t = add_mod(t, u2d(prev[x]), m);
-        out[x] = d2u(t);
+        if (CONJ) {  // the real/imaginary split, as in k_conj_split
+            const size_t o = ((size_t)p * L1 + i) * N + t0 + x;
+            const double a = u2d(cj.x[o]);
+            cj.re[o] = d2u(add_mod(a, t, m));
+            double r = mul_canon(sub_mod(a, t, m), W[1], m);
+            if ((brev_n((uint32_t)(t0 + x), logN) & 1u) == 0u) r = r == 0.0 ? 0.0 : m.t - r;
+            cj.im[o] = d2u(r);
+        } else {
+            out[x] = d2u(t);
+        }
     }
     if (last_out && i == level) {  // the rescale's inverse tile pass of this limb
 #pragma unroll
@@ -656,10 +666,13 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
 // as the transform followed by the combine.
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0,
-                              uint64_t *last_out)
+                              uint64_t *last_out, const MdConj *conj)
 {
     const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1;
-    if (N < kT || K < 1 || K > NJ_MAX_JOBS || (last_out && K != 1)) return hipErrorInvalidValue;
+    if (N < kT || K < 1 || K > NJ_MAX_JOBS || ((last_out || conj) && K != 1) || (last_out && conj))
+        return hipErrorInvalidValue;
+    MdConj cj{nullptr, nullptr, nullptr};
+    if (conj) cj = *conj;
     if (N1 > 1 && !cols_done) {
         LimbTab lt;
         for (int b = 0; b < n; b += NJ_MAX_LIMBS) {
@@ -671,8 +684,11 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
         }
     }
     const double bytes = 8.0 * N * (n * 3.0 + K * L1 + (acc ? n : 0));
-    return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
-                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw);
+    if (conj)
+        return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md<true>, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc,
+                      level, L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj);
+    return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md<false>, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
+                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj);
 }
 
 // Key inner products of n_jobs jobs (digits of tau_g(d) column-passed only, own limbs
@@ -708,6 +724,24 @@ hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTa
     if (lt.n == 0) return hipSuccess;
     return launch_cols<true, true>(c, PROF_NTT_COL_INV, 16.0 * N * lt.n, N1, dim3(kT / kNT, lt.n), s, data, nullptr,
                                    lt, c->d_itw, c->d_info, c->log_n, scale);
+}
+
+// Centred lift of n_polys coefficient-form limbs (prime src_pidx, at src + z N) into
+// primes 0..n_out-1, fused with those limbs' column pass, into out [n_polys][n_out][N]
+// (N >= 8192); the tile pass (launch_ntt_tiles) finishes the forward transform.
+hipError_t launch_lift_col(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_polys, int n_out, uint64_t *out,
+                           hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT;
+    if (N1 < 2 || n_out < 1 || n_polys < 1) return hipErrorInvalidValue;
+    const dim3 g(kT / kNT, n_out, n_polys);
+    const double b = 8.0 * N * n_polys * (1 + n_out);
+    switch (N1) {
+    case 2: return launch(c, PROF_OTHER, b, k_lift_col<2>, g, dim3(kNT), s, src, src_pidx, n_out, out, c->d_tw, c->d_info, c->log_n);
+    case 4: return launch(c, PROF_OTHER, b, k_lift_col<4>, g, dim3(kNT), s, src, src_pidx, n_out, out, c->d_tw, c->d_info, c->log_n);
+    case 8: return launch(c, PROF_OTHER, b, k_lift_col<8>, g, dim3(kNT), s, src, src_pidx, n_out, out, c->d_tw, c->d_info, c->log_n);
+    default: return launch(c, PROF_OTHER, b, k_lift_col<16>, g, dim3(kNT), s, src, src_pidx, n_out, out, c->d_tw, c->d_info, c->log_n);
+    }
 }
 
 }  // namespace nj

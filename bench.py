@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the step's kernel families, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/pmc_fused_conv_cts_n65536.md);
 # valid for the kernels as they were when counted, absent for the others
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {"k_key_ip": 810659530}
 
 
 def parse():

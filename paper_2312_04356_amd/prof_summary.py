@@ -19,8 +19,11 @@ from collections import defaultdict
 def family(name):
     n = re.sub(r"\(.*", "", name)
     n = n.replace("void ", "").replace("nj::", "")
-    n = re.sub(r"k_ntt_col<\d+, (false|true)>", r"k_ntt_col<\1>", n)
+    n = re.sub(r"k_ntt_col<\d+, (false|true)(, (false|true))?>", r"k_ntt_col<\1>", n)
+    n = re.sub(r"k_ntt_tile_md<(false|true)>", "k_ntt_tile_md", n)
     n = n.strip()
+    if n == "k_ntt_tile_gal":  # ModUp's inverse tile pass through X -> X^g
+        return "k_ntt_tile<true>"
     # the same families the library's HIP-event counters use
     if n.startswith("k_bconv"):
         return "k_bconv"

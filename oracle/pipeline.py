@@ -160,8 +160,8 @@ class Ctx:
         return self.ct_add(level, inners[0], out) if 0 in inners else out
 
     # ------------------------------------------------------------ the path
-    def conv2d_cins(self, x, plan, pts, level=1, hoist=True):
-        y = self.bsgs(level, x, plan, pts, hoist)
+    def conv2d_cins(self, x, plan, pts, level=1, hoist=True, lazy=False):
+        y = self.bsgs(level, x, plan, pts, hoist, lazy)
         return self.ct_rescale(level, y)
 
     def conj_split(self, level, x):

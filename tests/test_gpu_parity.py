@@ -211,6 +211,16 @@ def test_fused_conv_parity(which, request):
         gctx.nj_plan_apply(P.g.conv_plan, 0, ct_g, y, hoist)
         want = P.o.ctx.bsgs(1, ct_o, P.o.conv_bsgs, P.o.conv_pts, hoist=bool(hoist))
         assert np.array_equal(host_coeff(gctx, y), want), "hoist=%d" % hoist
+    # lazy giant steps (one ModDown for their sum), as the benchmark runs the conv
+    P.g.conv_plan.set_lazy(True)
+    y = gctx.empty_ct(1)
+    gctx.nj_plan_apply(P.g.conv_plan, 0, ct_g, y, 1)
+    assert np.array_equal(host_coeff(gctx, y), P.o.ctx.bsgs(1, ct_o, P.o.conv_bsgs, P.o.conv_pts, lazy=True))
+    out = gctx.empty_ct(0)
+    gctx.nj_conv2d_cins(P.g.conv_plan, ct_g, out)
+    want = P.o.ctx.conv2d_cins(ct_o, P.o.conv_bsgs, P.o.conv_pts, level=1, hoist=True, lazy=True)
+    assert np.array_equal(host_coeff(gctx, out), want)
+    P.g.conv_plan.set_lazy(False)
     out = gctx.empty_ct(0)
     gctx.nj_conv2d_cins(P.g.conv_plan, ct_g, out)
     want = P.o.ctx.conv2d_cins(ct_o, P.o.conv_bsgs, P.o.conv_pts, level=1, hoist=True)

@@ -345,8 +345,7 @@ hipError_t launch_signed_to_rns(const nj_ctx *c, const int64_t *coeffs, const Li
                                 hipStream_t s, const uint64_t *d_primes);
 hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const uint64_t *a, const uint64_t *e,
                                  const uint64_t *s_eval, const uint64_t *sp_eval, const double *d_pmod, hipStream_t s);
-hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out, const LimbTab &lt,
-                             const double *d_scal, const double *d_scalq, hipStream_t s);
+
 
 // ------------------------------------------------------------------- ksw.hip
 hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);

@@ -176,17 +176,6 @@ hipError_t launch_elementwise(const nj_ctx *c, int op, const uint64_t *a, const 
     return hipGetLastError();
 }
 
-__global__ void k_scalar_mul(const uint64_t *in, uint64_t *out, LimbTab lt, const PrimeInfo *info, int logN,
-                             const double *scal, const double *scalq)
-{
-    const int N = 1 << logN, limb = blockIdx.y;
-    const Mod m = info[lt.pidx[limb]].m;
-    const size_t base = (size_t)lt.off[limb] * N;
-    const double w = scal[limb], wq = scalq[limb];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x)
-        out[base + k] = d2u(mul_shoup(u2d(in[base + k]), w, wq, m));
-}
-
 // ------------------------------------------------------------ automorphism
 //
 // In evaluation form X -> X^g permutes words: out[k] = in[k'] where the
@@ -504,14 +493,6 @@ hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const 
     return hipGetLastError();
 }
 
-hipError_t launch_scalar_mul(const nj_ctx *c, const uint64_t *in, uint64_t *out, const LimbTab &lt,
-                             const double *d_scal, const double *d_scalq, hipStream_t s)
-{
-    if (lt.n == 0) return hipSuccess;
-    dim3 grid((c->N + kThreads - 1) / kThreads, lt.n);
-    hipLaunchKernelGGL(k_scalar_mul, grid, dim3(kThreads), 0, s, in, out, lt, c->d_info, c->log_n, d_scal, d_scalq);
-    return hipGetLastError();
-}
 
 hipError_t launch_bconv(const nj_ctx *c, const BconvTab &bt, const uint64_t *in, const int *in_off, uint64_t *out,
                         hipStream_t s)

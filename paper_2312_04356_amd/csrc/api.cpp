@@ -360,11 +360,11 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
         for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
             const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
-            const bool f = fuse_ip(c, l), gal = f;
+            const bool f = fuse_ip(c, l);  // fused: tau_ge rides on ModUp and the own-limb reads
             KeyJobs kj;
             AutoJobs aj, ac;
             GalTab gt;
-            int zoff[NJ_MAX_JOBS];  // limb offset of each giant's c1 from inner's
+            int zoff[NJ_MAX_JOBS];  // limb offset of each giant's c1 from inner + plen
             for (int z = 0; z < K; z++) {
                 const int g = gl[c0 + z];
                 const uint32_t ge = galois_of_rot(c, (long long)lt.giants[g] * lt.n1 * lt.u);
@@ -372,10 +372,10 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                 aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
                 ac.in[z] = x, ac.out[z] = nullptr, ac.g[z] = ge;
                 kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
-                if (gal) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
+                if (f) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
                 kj.key[z] = key_of(c, ge);
             }
-            if (gal) {  // tau_ge rides on ModUp's inverse transform and the own-limb reads
+            if (f) {
                 if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff))) return st;
             } else {
                 NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
@@ -396,7 +396,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
-        const bool f = fuse_ip(c, l), gal = f;
+        const bool f = fuse_ip(c, l);  // fused: tau_ge rides on ModUp and the own-limb reads
         KeyJobs kj;
         MdJobs mj;
         AutoJobs aj;
@@ -408,12 +408,12 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
             const uint64_t *x = inner + (size_t)g * clen;
             aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
             kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
-            if (gal) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
+            if (f) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = g * 2 * (l + 1);
             kj.key[z] = key_of(c, ge);
             mj.add[z] = x, mj.g_add[z] = ge;
         }
         mj.out[0] = out;
-        if (gal) {
+        if (f) {
             if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff))) return st;
         } else {
             NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));

@@ -1,12 +1,14 @@
 """Lazy giant steps (one ModDown for the sum of a transform's giant-step inner
 products) through the C ABI (needs an MI355X): CoeffToSlot bit-exact against the
-oracle's lazy evaluation at N = 2^12, batched equal to single calls, and the
-library's own lazy plans accurate at N = 2^16."""
+oracle's lazy evaluation at N = 2^12, the benchmark's first CoeffToSlot group
+bit-exact at N = 2^16, batched equal to single calls, and the library's own lazy
+plans accurate at N = 2^16."""
 import numpy as np
 import pytest
 
 import oracle as O
 import oracle.encoding as E
+import oracle.plans as PL
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +79,33 @@ def test_lazy_coeff_to_slot_parity_small():
     for z in range(4):
         y.data[z].copy_(x_g.data)
     cts_batch_vs_single(g, y, 4)
+
+
+def test_lazy_coeff_to_slot_group_parity_full():
+    """N = 2^16 as the benchmark runs it: ModRaise of a level-0 ciphertext, then the
+    first CoeffToSlot group (level 23, 32 diagonals, hoisted baby steps, lazy giant
+    steps on the fused key-switch kernels), word for word against the oracle (about a
+    minute of oracle time on one core)"""
+    o = OracleWorkload("full", with_cts=True)
+    g = GpuWorkload("full", with_cts=True, lazy=True)
+    gctx = g.ctx
+    plan0, pts0 = o.cts[0]
+    gs = sorted({PL.galois_elt(r, o.N) for r in plan0.rotations()})
+    assert set(gs) <= set(g.cts_plan.galois())
+    g.make_keys(gs)
+    o.make_keys(gs)
+    for idx, j in enumerate(g.cts_plan.offsets(0)):
+        gctx.nj_plan_set_diagonal(g.cts_plan, 0, idx, pts0[j])
+    m = o.ring.to_rns(o.input_plaintext(), 0)
+    x_o = o.encrypt_input(0)
+    x_g = g.encrypt_input(0, m_dev=gctx.to_device(m))
+    L = o.ring.L
+    xr = gctx.empty_ct(L)
+    gctx.nj_modraise(x_g, L, xr)
+    out = gctx.empty_ct(L)
+    gctx.nj_plan_apply(g.cts_plan, 0, xr, out)
+    want = o.ctx.bsgs(L, o.ctx.ct_modraise(x_o), plan0, pts0, lazy=True)
+    assert np.array_equal(host_coeff(gctx, out.data, L), want)
 
 
 def test_lazy_coeff_to_slot_full_accuracy_and_batch():

@@ -1,8 +1,9 @@
 """Lazy giant steps (one ModDown for the sum of a transform's giant-step inner
 products) through the C ABI (needs an MI355X): CoeffToSlot bit-exact against the
-oracle's lazy evaluation at N = 2^12, the benchmark's first CoeffToSlot group
-bit-exact at N = 2^16, batched equal to single calls, and the library's own lazy
-plans accurate at N = 2^16."""
+oracle's lazy evaluation at N = 2^12, the benchmark's first CoeffToSlot group and a
+transform of 31 giant steps (four chunks of key switches) bit-exact at N = 2^16,
+batched equal to single calls, and the library's own lazy plans accurate at
+N = 2^16."""
 import numpy as np
 import pytest
 
@@ -106,6 +107,40 @@ def test_lazy_coeff_to_slot_group_parity_full():
     gctx.nj_plan_apply(g.cts_plan, 0, xr, out)
     want = o.ctx.bsgs(L, o.ctx.ct_modraise(x_o), plan0, pts0, lazy=True)
     assert np.array_equal(host_coeff(gctx, out.data, L), want)
+
+
+def test_lazy_many_giants_parity_full():
+    """N = 2^16, level 1: a conv plan's structure (64 channels at W = 32, n1 = 2: one
+    baby step, 31 giant steps, so the lazy giant steps run in four chunks that
+    accumulate their inner products) with uniform random diagonals and input,
+    word for word against the oracle's lazy evaluation"""
+    rng = np.random.default_rng(23)
+    o = OracleWorkload("full", with_cts=False)
+    g = GpuWorkload("full", with_cts=False)
+    gctx, N, q = g.ctx, g.N, g.q
+    c, w0 = 64, 30
+    taps = PL.taps_same(rng.uniform(-1, 1, (c, c, 3, 3)))
+    plan = gctx.nj_conv_plan_create_taps(w0, c, c, taps, fuse=1, n1=2, level=1)
+    lvl, W, C, ell, bi, bo = plan.layout()
+    assert (lvl, W, C, bi, bo) == (1, 32, 64, 1, 1)
+    js = plan.offsets(0)
+    oplan = PL.Bsgs(N // 2, ell, [j * ell for j in js], n1=2)
+    assert oplan.js == sorted(js) and len(oplan.giants) == 32
+    pts = {j: np.stack([rng.integers(0, q[i], N, dtype=np.uint64) for i in range(2)]) for j in js}
+    for idx, j in enumerate(js):
+        gctx.nj_plan_set_diagonal(plan, 0, idx, pts[j])
+    gs = plan.galois()
+    assert sorted(gs) == sorted({PL.galois_elt(r, N) for r in oplan.rotations()})
+    g.make_keys(gs)
+    o.make_keys(gs)
+    x = np.stack([np.stack([rng.integers(0, q[i], N, dtype=np.uint64) for i in range(2)]) for _ in range(2)])
+    t = gctx.to_device(x.reshape(4, N))
+    gctx.nj_to_eval(t, 1, 2)
+    plan.set_lazy(True)
+    y = gctx.empty_ct(1)
+    gctx.nj_plan_apply(plan, 0, Ct(t, 1), y, 1)
+    want = o.ctx.bsgs(1, x, oplan, pts, lazy=True)
+    assert np.array_equal(host_coeff(gctx, y.data, 1), want)
 
 
 def test_lazy_coeff_to_slot_full_accuracy_and_batch():

@@ -15,19 +15,20 @@ SCALE = 2.0 ** 40
 
 
 class Rig:
-    """the same N = 2^12 ring, secret and keys on both sides"""
+    """the same ring, secret and keys on both sides: by default N = 2^12 with 21 + 4
+    primes and a weight-32 secret; Rig(16, 24, 8, 192) is the benchmark's N = 2^16 ring"""
 
-    def __init__(self):
-        print("\n[setup] bootstrap ring N=2^12, 21 + 4 primes", flush=True)
-        self.N = N = 1 << 12
-        q, p = PL.chain_primes(12, 21, 4, 50, 48, 50, lambda ln, b, c, ex: O.gen_primes(ln, b, c, ex))
-        assert (q, p) == tuple(list(map(int, v)) for v in chain_primes(12, 21, 4, 50, 48, 50))
+    def __init__(self, log_n=12, n_q=21, n_p=4, h=32):
+        print("\n[setup] bootstrap ring N=2^%d, %d + %d primes" % (log_n, n_q, n_p), flush=True)
+        self.N = N = 1 << log_n
+        q, p = PL.chain_primes(log_n, n_q, n_p, 50, 48, 50, lambda ln, b, c, ex: O.gen_primes(ln, b, c, ex))
+        assert (q, p) == tuple(list(map(int, v)) for v in chain_primes(log_n, n_q, n_p, 50, 48, 50))
         self.q, self.p = q, p
         self.R = O.Ring(N, q, p)
-        self.s = synth.ternary_secret(N, 32, 77)
+        self.s = synth.ternary_secret(N, h, 77)
         self.o = OCtx(self.R, self.s)
         self.boot = B.Boot(self.o)
-        self.g = Ctx(12, q, p, SCALE)
+        self.g = Ctx(log_n, q, p, SCALE)
         self.g.nj_set_secret(self.s)
         self.keys = set()
         self.key("relin")

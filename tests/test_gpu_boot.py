@@ -46,6 +46,21 @@ def test_hmult_parity(rig):
         assert np.array_equal(rig.coeff(out), want[0])
 
 
+def test_hmult_parity_full():
+    """N = 2^16 (24 + 8 primes, three digits): HMult's relinearisation runs on the fused
+    key-switch kernels (digits' tile pass inside the inner product, special-prime rows
+    handed to ModDown), word for word against the oracle"""
+    full = Rig(16, 24, 8, 192)
+    n = full.N // 2
+    xa, ca = full.enc(RNG.uniform(-1, 1, n), 14, 2.0 ** 45, 5)
+    xb, cb = full.enc(RNG.uniform(-1, 1, n), 12, 2.0 ** 44, 6)
+    want = full.boot.hmult((xa, ca.level, ca.scale), (xb, cb.level, cb.scale))
+    out = full.g.empty_ct(11)
+    full.g.nj_hmult(ca, cb, out)
+    assert out.level == want[1] == 11 and out.scale == want[2]
+    assert np.array_equal(full.coeff(out), want[0])
+
+
 def test_const_mult_and_add_const_parity(rig):
     n = rig.N // 2
     xa, ca = rig.enc(RNG.uniform(-1, 1, n), 10, 2.0 ** 46, 3)

@@ -229,6 +229,17 @@ def boot_bench(g, steps=3):
     res = {"eval_mod_re_im_ms": round(t_mod / steps, 3), "stoc1_ms": round((t_all - t_mod) / steps, 3),
            "levels": {"in": lo, "after_eval_mod": lo - 11, "after_stoc1": lo - 14}, "K": 32, "degree": 63,
            "double_angles": 3, "stoc1_groups": 3}
+    # the same tail as one call: ModEval of Re and Im evaluated together (each HMult, constant
+    # multiply, rescale and key switch of the chain on both ciphertexts per launch), Re + i Im, StoC1
+    out2 = gctx.empty_ct(lo - 14)
+    gctx.nj_slot_activation(32, 3, None, None, None, 0, stoc1, re, im, out2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        gctx.nj_slot_activation(32, 3, None, None, None, 0, stoc1, re, im, out2)
+    e2.record()
+    torch.cuda.synchronize()
+    res["eval_mod_packed_and_stoc1_ms"] = round(e0.elapsed_time(e2) / steps, 3)
     # one whole Algorithm 1 layer: conv (fused StoC2) -> ModRaise -> CoeffToSlot -> ModEval of
     # Re and Im -> zero-padding masks -> square activation -> Re + i Im -> StoC1
     from paper_2312_04356_amd import nj_layer_masks

@@ -323,13 +323,6 @@ hipError_t launch_elementwise(const nj_ctx *c, int op, const uint64_t *a, const 
 // out limb i = in limb i read through X -> X^g (evaluation form, contiguous limbs)
 hipError_t launch_automorph(const nj_ctx *c, const uint64_t *in, uint64_t *out, uint32_t g, int n_limbs,
                             hipStream_t s);
-// basis conversion: input limbs at in + in_off[a]*N (coefficient form) -> bt's targets at out + out_limb*N
-hipError_t launch_bconv(const nj_ctx *c, const BconvTab &bt, const uint64_t *in, const int *in_off, uint64_t *out,
-                        hipStream_t s);
-hipError_t launch_key_ip(const nj_ctx *c, int level, int n_digits, const uint64_t *ext, const uint64_t *key,
-                         uint32_t g, uint64_t *u0, uint64_t *u1, hipStream_t s);
-hipError_t launch_moddown_combine(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv,
-                                  const uint64_t *add, uint32_t g_add, uint64_t *out, hipStream_t s);
 hipError_t launch_lift_last(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_out, uint64_t *dst,
                             hipStream_t s);
 hipError_t launch_rescale_combine(const nj_ctx *c, int level, const uint64_t *a, const uint64_t *lifted, uint64_t *out,

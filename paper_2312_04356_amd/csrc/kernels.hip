@@ -206,122 +206,6 @@ hipError_t launch_automorph(const nj_ctx *c, const uint64_t *in, uint64_t *out, 
     return hipGetLastError();
 }
 
-// ------------------------------------------------------ basis conversion
-//
-// y_t = sum_a [x_a (D/q_a)^-1]_{q_a} (D/q_a) mod t   (coefficient form).
-// Thread per coefficient; blockIdx.y selects a chunk of up to 8 targets.
-
-struct BconvArgs {
-    int m, n_out;
-    int in_pidx[16];
-    int in_off[16];
-    int out_pidx[NJ_MAX_LIMBS];
-    int out_off[NJ_MAX_LIMBS];
-};
-
-__global__ __launch_bounds__(kThreads) void k_bconv(const uint64_t *in, uint64_t *out, BconvArgs ba,
-                                                    const double *hat_inv, const double *hat_inv_q,
-                                                    const double *hat, const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    double v[16];
-    for (int a = 0; a < ba.m; a++) {
-        const Mod ma = info[ba.in_pidx[a]].m;
-        v[a] = mul_shoup(u2d(in[(size_t)ba.in_off[a] * N + k]), hat_inv[a], hat_inv_q[a], ma);
-    }
-    const int o0 = blockIdx.y * 8, o1 = min(o0 + 8, ba.n_out);
-    for (int o = o0; o < o1; o++) {
-        const Mod mt = info[ba.out_pidx[o]].m;
-        double acc = 0.0;
-        for (int a = 0; a < ba.m; a++) {
-            acc += mul_lazy(v[a], hat[a * ba.n_out + o], mt);  // each term in (-t, t)
-            if ((a & 7) == 7) acc = reduce(acc, mt);
-        }
-        out[(size_t)ba.out_off[o] * N + k] = d2u(reduce(acc, mt));
-    }
-}
-
-hipError_t launch_bconv_args(const nj_ctx *c, const BconvArgs &ba, const double *hat_inv, const double *hat_inv_q,
-                             const double *hat, const uint64_t *in, uint64_t *out, hipStream_t s)
-{
-    dim3 grid((c->N + kThreads - 1) / kThreads, (ba.n_out + 7) / 8);
-    ProfScope ps(c, PROF_BCONV, 8.0 * c->N * (ba.m + ba.n_out), s);
-    hipLaunchKernelGGL(k_bconv, grid, dim3(kThreads), 0, s, in, out, ba, hat_inv, hat_inv_q, hat, c->d_info,
-                       c->log_n);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------- key inner product
-//
-// u0[t] = sum_j ext_j[t] * b_j[t],  u1[t] = sum_j ext_j[t] * a_j[t] over the
-// extended limbs t of Q_l u P (evaluation form).  With g != 1 the automorphism
-// X -> X^g is applied to the extended digits on the fly (hoisted rotation).
-
-__global__ __launch_bounds__(kThreads) void k_key_ip(const uint64_t *ext, const uint64_t *key, uint64_t *u0,
-                                                     uint64_t *u1, uint32_t g, int n_digits, int level, int L,
-                                                     int alpha, int nq, const PrimeInfo *info, int logN)
-{
-    const int N = 1 << logN;
-    const int t = blockIdx.y;  // extended limb
-    const int ne = level + 1 + alpha, nk = L + 1 + alpha;
-    const int pidx = t <= level ? t : nq + (t - level - 1);
-    const int kl = t <= level ? t : L + 1 + (t - level - 1);
-    const Mod m = info[pidx].m;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
-        const int src = g == 1u ? k : galois_src(k, g, logN);
-        double acc0 = 0.0, acc1 = 0.0;
-        for (int j = 0; j < n_digits; j++) {
-            double x = u2d(ext[((size_t)j * ne + t) * N + src]);
-            double kb = u2d(key[(((size_t)j * 2 + 0) * nk + kl) * N + k]);
-            double ka = u2d(key[(((size_t)j * 2 + 1) * nk + kl) * N + k]);
-            acc0 += mul_lazy(x, kb, m);
-            acc1 += mul_lazy(x, ka, m);
-            if ((j & 7) == 7) { acc0 = reduce(acc0, m); acc1 = reduce(acc1, m); }
-        }
-        u0[(size_t)t * N + k] = d2u(reduce(acc0, m));
-        u1[(size_t)t * N + k] = d2u(reduce(acc1, m));
-    }
-}
-
-hipError_t launch_key_ip(const nj_ctx *c, int level, int n_digits, const uint64_t *ext, const uint64_t *key,
-                         uint32_t g, uint64_t *u0, uint64_t *u1, hipStream_t s)
-{
-    dim3 grid((c->N + kThreads - 1) / kThreads, level + 1 + c->alpha);
-    ProfScope ps(c, PROF_KEYIP, 8.0 * c->N * (level + 1 + c->alpha) * (3.0 * n_digits + 2.0), s);
-    hipLaunchKernelGGL(k_key_ip, grid, dim3(kThreads), 0, s, ext, key, u0, u1, g, n_digits, level, c->L, c->alpha,
-                       c->n_q, c->d_info, c->log_n);
-    return hipGetLastError();
-}
-
-// out_i = (u_i - conv_i) P^{-1} mod q_i  (+ add_i, optionally read through X -> X^g)
-__global__ void k_moddown_combine(const uint64_t *u, const uint64_t *conv, const uint64_t *add, uint32_t g_add,
-                                  uint64_t *out, const double *pinv, const double *pinvq, const PrimeInfo *info,
-                                  int logN)
-{
-    const int N = 1 << logN, i = blockIdx.y;
-    const Mod m = info[i].m;
-    const size_t base = (size_t)i * N;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
-        double r = mul_shoup(sub_mod(u2d(u[base + k]), u2d(conv[base + k]), m), pinv[i], pinvq[i], m);
-        if (add) {
-            const int src = g_add <= 1u ? k : galois_src(k, g_add, logN);
-            r = add_mod(r, u2d(add[base + src]), m);
-        }
-        out[base + k] = d2u(r);
-    }
-}
-
-hipError_t launch_moddown_combine(const nj_ctx *c, int level, const uint64_t *u, const uint64_t *conv,
-                                  const uint64_t *add, uint32_t g_add, uint64_t *out, hipStream_t s)
-{
-    dim3 grid((c->N + kThreads - 1) / kThreads, level + 1);
-    hipLaunchKernelGGL(k_moddown_combine, grid, dim3(kThreads), 0, s, u, conv, add, g_add, out, c->d_pinv,
-                       c->d_pinvq, c->d_info, c->log_n);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------- rescale / ModRaise lifts
 //
 // src: one limb (coefficient form) modulo prime src_pidx; for each target limb i
@@ -491,18 +375,6 @@ hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const 
     hipLaunchKernelGGL(k_keygen_combine, grid, dim3(kThreads), 0, s, b, a, e, s_eval, sp_eval, d_pmod, digit,
                        c->alpha, c->L, c->n_q, c->d_info, c->log_n);
     return hipGetLastError();
-}
-
-
-hipError_t launch_bconv(const nj_ctx *c, const BconvTab &bt, const uint64_t *in, const int *in_off, uint64_t *out,
-                        hipStream_t s)
-{
-    BconvArgs ba;
-    ba.m = bt.m;
-    ba.n_out = bt.n_out;
-    for (int a = 0; a < bt.m; a++) ba.in_pidx[a] = bt.in_pidx[a], ba.in_off[a] = in_off[a];
-    for (int o = 0; o < bt.n_out; o++) ba.out_pidx[o] = bt.out_pidx[o], ba.out_off[o] = bt.out_limb[o];
-    return launch_bconv_args(c, ba, bt.hat_inv, bt.hat_inv + bt.m, bt.hat, in, out, s);
 }
 
 }  // namespace nj

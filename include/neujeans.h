@@ -156,7 +156,7 @@ nj_status nj_modraise(nj_ctx *ctx, const nj_ct *in, int level, nj_ct *out, void 
 
 /* ---------------------------------------------------------------- plans */
 
-/* A plan holds n_lt BSGS linear transforms (Sec. 2.5).  Transform t acts at level
+/* A plan holds n_lt BSGS linear transforms (Sec. 2.6).  Transform t acts at level
  * level0 - t on slot-rotation unit u_t with diagonal offsets j*u_t and baby size n1_t. */
 int nj_plan_count(const nj_plan *plan);
 /* Galois elements whose keys the plan needs; returns the count (writes at most max). */

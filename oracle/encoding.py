@@ -10,7 +10,7 @@ Definitions followed (NeuJeans, arXiv 2312.04356):
     S_k = blockdiag(B_k),  B_k = [[I, W_k], [I, -W_k]],  W_k = diag(w_{8k}^(5^i)), i < k.
   * Real CinS encoding, Sec. 3.3.1 and Appendix A:
     (DFT'_{2l} m)_j = sum_{k < 2l} m_k w_{4l}^(5^j k),  <m>_CinS = <(DFT'(m_1) | ... | DFT'(m_C))>_slot.
-  * Matrix-vector products by cyclic diagonals, Sec. 2.5 (Eq. matvecmul):
+  * Matrix-vector products by cyclic diagonals, Sec. 2.6 (Eq. matvecmul):
     M x = sum_r diag(v_r) (x <<< r),  (x <<< r)[i] = x[(i + r) mod n].
 """
 import numpy as np

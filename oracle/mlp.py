@@ -4,7 +4,7 @@ squared error loss and the loss gradient, in float64 with plain numpy.
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper leaves the BSGS split and the depth of the transform decomposition open
-(Sec. 2.5: the best point depends on the parameters and the ciphertext level); the
+(Sec. 2.6: the best point depends on the parameters and the ciphertext level); the
 library picks them by measured or predicted latency, with this network as the
 predictor.  Its shape and loss are the library's interface.  The gradient is the
 textbook backpropagation of the definitions below; tests pin it to central finite

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Follows, in the paper's order:
   * HRot (Sec. 2.1): left rotation of the slots by r is the automorphism
     X -> X^(5^r mod 2N) followed by key switching back to s.
-  * BSGS (Sec. 2.5): sum_g ( sum_i d'_{g n1 + i} (.) (ct <<< i u) ) <<< g n1 u; the
+  * BSGS (Sec. 2.6): sum_g ( sum_i d'_{g n1 + i} (.) (ct <<< i u) ) <<< g n1 u; the
     baby rotations are hoisted (one ModUp of c1, automorphism applied to the
     extended digits) when `hoist` is True, giant rotations are plain.
   * Fused conv (Algorithm 1, Sec. 4): BSGS at level 1 with K^' diagonals,

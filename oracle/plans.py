@@ -10,7 +10,7 @@ Fused conv (Sec. 3.3.2-3.3.4, Sec. 4, Eq. nested_conv):
     K^' = S' K^ (product of C x C matrices of length-l slices, Sec. 4.1-4.2);
   * cyclic diagonals d_k = (K^'[0][k] | K^'[1][1+k] | ... ), slice c holding
     K^'[c][(c+k) mod C];  the conv output is sum_k d_k (.) (ct <<< k l);
-  * baby-step giant-step (Sec. 2.5): d'_{g n1 + i} = d_{g n1 + i} >>> g n1 l.
+  * baby-step giant-step (Sec. 2.6): d'_{g n1 + i} = d_{g n1 + i} >>> g n1 l.
 CoeffToSlot (Sec. 2.4): T_{N/2}^{-1} = S_1^{-1} ... S_{N/4}^{-1}; its stages, applied
   S_{N/4}^{-1} first, are grouped into d consecutive groups, one BSGS transform each;
   the 1/2 of the real/imaginary split is folded into the last group.

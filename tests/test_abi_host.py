@@ -88,3 +88,22 @@ def test_layer_masks_match_oracle(log_n, W, C, w0):
     got = nj.nj_layer_masks(log_n, W, C, w0)
     want = B.layer_masks(1 << log_n, W, C, w0)
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def _create_status(log_n, n_q, alpha):
+    """status of nj_ctx_create for n_q + alpha primes of the chain rule (no GPU call is
+    reached when the parameters are refused)"""
+    q = nj.nj_gen_primes(log_n, 49, n_q)
+    p = nj.nj_gen_primes(log_n, 49, alpha, q)
+    qa, pa = np.array(q, dtype=np.uint64), np.array(p, dtype=np.uint64)
+    prm = nj.NjParams(log_n, n_q, alpha, qa.ctypes.data, pa.ctypes.data, 2.0 ** 40)
+    h = ctypes.c_void_p()
+    return nj._lib.nj_ctx_create(ctypes.byref(prm), ctypes.byref(h))
+
+
+@pytest.mark.parametrize("n_q,alpha", [(64, 8), (33, 16), (32, 4), (17, 1)])
+def test_ctx_create_refuses_oversized_bases(n_q, alpha):
+    """more ciphertext primes than the basis-conversion tables hold (n_q > 32), or more
+    than 4 key-switching digits, is refused with NJ_EUNSUPPORTED before any device work"""
+    assert _create_status(12, n_q, alpha) == -7
+    assert "nj_ctx_create" in nj._lib.nj_last_error().decode()

@@ -307,6 +307,15 @@ nj_status nj_cheb_interpolate(int degree, double K, int r, double *coeffs);
  * |I| must stay below K. */
 nj_status nj_eval_mod(nj_ctx *ctx, const nj_ct *in, int K, int r, const double *coeffs, int n_coeffs, nj_ct *out,
                       void *stream);
+/* Evaluation order of ModEval's Chebyshev baby-step sums sum_j c_j T_j (Sec. 2.4 leaves
+ * the evaluation to prior work; both orders give the same message up to rounding noise):
+ *   order 0 (default): each term c_j T_j is a constant multiply at its own scale followed
+ *     by its own rescale to the sum's level, then the terms are added;
+ *   order 1: the integers round(c_j tau q / s_j) times T_j are accumulated at one level and
+ *     the sum is rescaled once (fewer rescales; different low bits).
+ * Applies to every later nj_eval_mod / nj_slot_activation / nj_conv_act_layer /
+ * nj_bootstrap call on the context.  NJ_EINVAL for another order. */
+nj_status nj_eval_order(nj_ctx *ctx, int order);
 /* Re + i Im (i = X^{N/2} on the slots); same level. */
 nj_status nj_combine(nj_ctx *ctx, const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream);
 /* StoC1 = S_{l <- 1} = S_{l/2} ... S_1 (Algorithm 1, the StoC stages left after fusing

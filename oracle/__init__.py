@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "ckks_oracle.c")
 
 def build():
     """Compile the C part of the oracle (gcc, plain C11)."""
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", _LIB_PATH, _SRC])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", _LIB_PATH, _SRC])
 
 
 def _load():
@@ -35,6 +35,8 @@ def _load():
     u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
     sig = {
         "or_mulmod": (u64, [u64, u64, u64]),
+        "or_set_threads": (None, [i32]),
+        "or_get_threads": (i32, []),
         "or_powmod": (u64, [u64, u64, u64]),
         "or_is_prime": (i32, [u64]),
         "or_gen_primes": (i32, [i32, i32, i32, vp, i32, vp]),
@@ -91,6 +93,16 @@ def gen_primes(log_n, bits, count, exclude=()):
     if got != count:
         raise ValueError("not enough primes")
     return [int(x) for x in out]
+
+
+def set_threads(n):
+    """threads of the C part's limb loops (n <= 0: every host core); results do not
+    depend on it"""
+    lib.or_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib.or_get_threads())
 
 
 def is_prime(n):

@@ -25,8 +25,9 @@ the inputs.  Scale rules:
   * add_const(ct, c): add round(c * s) to the constant coefficient of c0.
   * sums combine ciphertexts recorded at the same scale.
 Chebyshev evaluation, baby steps T_1..T_7 and giant steps T_8, T_16, T_32 (a sum
-  sum_j c_j T_j of baby steps takes each term's integer round(c_j tau q_{lam+1} / s_j)
-  at level lam + 1 and rescales the sum once):
+  sum_j c_j T_j of baby steps is, by default, the sum of the const_mult of each term;
+  the option accumulate=True instead takes each term's integer
+  round(c_j tau q_{lam+1} / s_j) at level lam + 1 and rescales the sum once):
   T_2j = 2 T_j^2 - 1;  T_{a+b} = 2 T_a T_b - T_{a-b} (T_{a-b} brought to the
   product's level and scale by const_mult with c = 1);
   p = q T_G + r with q_0 = c_G, q_j = 2 c_{G+j}, r_i = c_i - c_{2G-i} (the Chebyshev
@@ -169,10 +170,24 @@ class Boot:
         T[32] = self.sq_minus1(T[16])
         return T
 
-    def eval_cheb(self, T, c, lam, tau):
-        """sum_k c_k T_k at level lam, recorded scale tau"""
+    def eval_cheb(self, T, c, lam, tau, accumulate=False):
+        """sum_k c_k T_k at level lam, recorded scale tau.  Baby-step sums (degree < 8):
+        by default every term c_j T_j is its own constant multiply and rescale; with
+        accumulate=True the terms' integer multiples are summed at one level and the sum
+        is rescaled once (an evaluation-order option the library offers as well)"""
         c = np.asarray(c, dtype=np.float64)
         d = len(c) - 1
+        if d < 8 and not accumulate:
+            acc = None
+            for j in range(1, d + 1):
+                if c[j] == 0.0:
+                    continue
+                t = self.const_mult(T[j], c[j], lam, tau)
+                if t is not None:
+                    acc = t if acc is None else self.add(acc, t)
+            if acc is None:
+                acc = self.zero(lam, tau)
+            return self.add_const(acc, c[0])
         if d < 8:
             # sum_j k_j T_j at level lam + 1 with k_j = round(c_j tau q_{lam+1} / s_j) (each
             # term then stands at scale tau q_{lam+1}), one rescale for the whole sum
@@ -194,13 +209,13 @@ class Boot:
         G = 32 if d >= 32 else (16 if d >= 16 else 8)
         q, r = cheb_split(c, G)
         tau_q = tau * float(self.R.q[lam + 1]) / T[G][2]
-        Q = self.eval_cheb(T, q, lam + 1, tau_q)
+        Q = self.eval_cheb(T, q, lam + 1, tau_q, accumulate)
         prod = self.hmult(Q, T[G])
-        rr = self.eval_cheb(T, r, lam, tau)
+        rr = self.eval_cheb(T, r, lam, tau, accumulate)
         return (self.add(prod[0:2] + (tau,), rr)[0], lam, tau)
 
     # -------------------------------------------------------------- ModEval
-    def eval_mod(self, ct, K, r, coeffs):
+    def eval_mod(self, ct, K, r, coeffs, accumulate=False):
         """ModEval of a CoeffToSlot output ct = (x, l0, s0); returns (x, l0 - 11, scale)
         encoding the slots' m (degree-63 interpolant, r = 3)"""
         x, l0, s0 = ct
@@ -212,7 +227,7 @@ class Boot:
         y = (self.ctx.ct_rescale(l0, y[0]), l0 - 1, sx * k / float(self.R.q[l0]))
         T = self.cheb_basis(y)
         lam = y[1] - 7
-        g = self.eval_cheb(T, coeffs, lam, float(self.R.q[lam]))
+        g = self.eval_cheb(T, coeffs, lam, float(self.R.q[lam]), accumulate)
         for _ in range(r):
             g = self.sq_minus1(g)
         return (g[0], g[1], g[2] * (2.0 * math.pi) * s0 / q0)

@@ -18,7 +18,12 @@
  * no precomputed quotient and no vectorisation.  Polynomial products use a
  * textbook negacyclic number-theoretic transform (weighted cyclic transform,
  * iterative radix-2 Cooley-Tukey) as a multiplication primitive only.
+ *
+ * Threads: loops over independent limbs (and digits x limbs) are split over
+ * OpenMP threads; each limb is still computed by one thread in the order written,
+ * so the results do not depend on the thread count (or_set_threads).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -28,6 +33,10 @@ typedef unsigned __int128 u128;
 /* ------------------------------------------------------------------ scalars */
 
 uint64_t or_mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+/* threads used by the limb loops (n <= 0: the OpenMP default, every host core) */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+int or_get_threads(void) { return omp_get_max_threads(); }
 static uint64_t addm(uint64_t a, uint64_t b, uint64_t q) { uint64_t s = a + b; return s >= q ? s - q : s; }
 static uint64_t subm(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + (q - b); }
 static uint64_t negm(uint64_t a, uint64_t q) { return a ? q - a : 0; }
@@ -238,15 +247,16 @@ void or_modup_digit(const or_ring *R, int l, int j, const uint64_t *x, uint64_t 
     int m = hi - lo;
     /* v_a = [x_a * (D_j/q_a)^{-1}]_{q_a} for every coefficient */
     uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m * n);
+#pragma omp parallel for schedule(static)
     for (int a = 0; a < m; a++) {
         uint64_t qa = R->q[lo + a], prod = 1;
         for (int b = 0; b < m; b++) if (b != a) prod = or_mulmod(prod, R->q[lo + b] % qa, qa);
         uint64_t hat_inv = invm(prod, qa);
         for (int k = 0; k < n; k++) v[(size_t)a * n + k] = or_mulmod(x[(size_t)(lo + a) * n + k], hat_inv, qa);
     }
-    uint64_t *hat_t = (uint64_t *)malloc(sizeof(uint64_t) * m);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < l + 1 + R->alpha; t++) {
-        uint64_t pt = ext_prime(R, l, t);
+        uint64_t pt = ext_prime(R, l, t), hat_t[64];
         if (t >= lo && t < hi) { memcpy(ext + (size_t)t * n, x + (size_t)t * n, sizeof(uint64_t) * n); continue; }
         for (int a = 0; a < m; a++) { /* (D_j/q_a) mod t */
             uint64_t prod = 1;
@@ -259,7 +269,6 @@ void or_modup_digit(const or_ring *R, int l, int j, const uint64_t *x, uint64_t 
             ext[(size_t)t * n + k] = acc;
         }
     }
-    free(hat_t);
     free(v);
 }
 
@@ -284,8 +293,10 @@ void or_moddown(const or_ring *R, int l, const uint64_t *u, uint64_t *out)
         hat_inv[a] = invm(prod, pa);
     }
     uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * al * (size_t)n);
+#pragma omp parallel for schedule(static)
     for (int a = 0; a < al; a++)
         for (int k = 0; k < n; k++) v[(size_t)a * n + k] = or_mulmod(u[(size_t)(l + 1 + a) * n + k], hat_inv[a], R->p[a]);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i <= l; i++) {
         uint64_t qi = R->q[i], Pmod = 1;
         uint64_t *hat_i = (uint64_t *)malloc(sizeof(uint64_t) * al);
@@ -322,11 +333,12 @@ void or_key_ip(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, con
     size_t stride = (size_t)ne * n;
     memset(u0, 0, stride * sizeof(uint64_t));
     memset(u1, 0, stride * sizeof(uint64_t));
-    uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n), *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
     for (int j = 0; j < n_digits(R, l); j++) {
         const uint64_t *kb = key + ((size_t)j * 2 + 0) * nk * n;
         const uint64_t *ka = key + ((size_t)j * 2 + 1) * nk * n;
+#pragma omp parallel for schedule(dynamic, 1)
         for (int t = 0; t < ne; t++) {
+            uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n), *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
             uint64_t pt = ext_prime(R, l, t);
             const uint64_t *y = ext_all + j * stride + (size_t)t * n;
             if (g != 1) { or_automorph(y, tmp, n, g, pt); y = tmp; }
@@ -335,9 +347,9 @@ void or_key_ip(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, con
             for (int k = 0; k < n; k++) u0[(size_t)t * n + k] = addm(u0[(size_t)t * n + k], prd[k], pt);
             or_polymul(y, ka + (size_t)kl * n, prd, n, pt);
             for (int k = 0; k < n; k++) u1[(size_t)t * n + k] = addm(u1[(size_t)t * n + k], prd[k], pt);
+            free(tmp); free(prd);
         }
     }
-    free(tmp); free(prd);
 }
 
 void or_keyswitch_ext(const or_ring *R, int l, const uint64_t *ext_all, uint64_t g, const uint64_t *key,
@@ -372,9 +384,10 @@ void or_switch_key(const or_ring *R, const int64_t *s, const int64_t *sp, const 
                    uint64_t *key)
 {
     int n = R->n, L = R->L, nk = L + 1 + R->alpha, dn = n_digits(R, L);
-    uint64_t *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
     for (int j = 0; j < dn; j++) {
         for (int t = 0; t < nk; t++) {
+            uint64_t *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
             uint64_t pt = t <= L ? R->q[t] : R->p[t - L - 1];
             const uint64_t *aj = a + ((size_t)j * nk + t) * n;
             uint64_t *b = key + (((size_t)j * 2 + 0) * nk + t) * n;
@@ -389,9 +402,9 @@ void or_switch_key(const or_ring *R, const int64_t *s, const int64_t *sp, const 
                 if (in_digit) v = addm(v, or_mulmod(Pmod, from_i64(sp[k], pt), pt), pt);
                 b[k] = v;
             }
+            free(prd);
         }
     }
-    free(prd);
 }
 
 /* -------------------------------------------------------- ciphertext level */
@@ -401,6 +414,7 @@ void or_rescale(const or_ring *R, int l, const uint64_t *a, uint64_t *out)
 {
     int n = R->n;
     uint64_t ql = R->q[l];
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < l; i++) {
         uint64_t qi = R->q[i], inv = invm(ql % qi, qi);
         for (int k = 0; k < n; k++) {
@@ -416,6 +430,7 @@ void or_modraise(const or_ring *R, int L, const uint64_t *a0, uint64_t *out)
 {
     int n = R->n;
     uint64_t q0 = R->q[0];
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= L; i++) {
         uint64_t qi = R->q[i];
         for (int k = 0; k < n; k++) {
@@ -430,45 +445,48 @@ void or_encrypt_sk(const or_ring *R, int l, const int64_t *s, const uint64_t *m,
                    uint64_t *ct)
 {
     int n = R->n;
-    uint64_t *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i <= l; i++) {
-        uint64_t qi = R->q[i];
+        uint64_t qi = R->q[i], *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
         polymul_small(a + (size_t)i * n, s, prd, n, qi);
         for (int k = 0; k < n; k++) {
             ct[(size_t)i * n + k] = addm(subm(from_i64(e[k], qi), prd[k], qi), m[(size_t)i * n + k], qi);
             ct[((size_t)(l + 1) + i) * n + k] = a[(size_t)i * n + k];
         }
+        free(prd);
     }
-    free(prd);
 }
 
 /* decryption polynomial c0 + c1 s at level l; out [(l+1)][n] */
 void or_decrypt(const or_ring *R, int l, const int64_t *s, const uint64_t *ct, uint64_t *out)
 {
     int n = R->n;
-    uint64_t *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i <= l; i++) {
-        uint64_t qi = R->q[i];
+        uint64_t qi = R->q[i], *prd = (uint64_t *)malloc(sizeof(uint64_t) * n);
         polymul_small(ct + ((size_t)(l + 1) + i) * n, s, prd, n, qi);
         for (int k = 0; k < n; k++) out[(size_t)i * n + k] = addm(ct[(size_t)i * n + k], prd[k], qi);
+        free(prd);
     }
-    free(prd);
 }
 
 /* per-limb product of a level-l polynomial with a plaintext: out_i = a_i * pt_i */
 void or_poly_pmult(const or_ring *R, int l, const uint64_t *a, const uint64_t *pt, uint64_t *out)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i <= l; i++) or_polymul(a + (size_t)i * R->n, pt + (size_t)i * R->n, out + (size_t)i * R->n, R->n, R->q[i]);
 }
 
 /* per-limb automorphism of a level-l polynomial */
 void or_poly_automorph(const or_ring *R, int l, const uint64_t *a, uint64_t g, uint64_t *out)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= l; i++) or_automorph(a + (size_t)i * R->n, out + (size_t)i * R->n, R->n, g, R->q[i]);
 }
 
 /* per-limb multiplication by X^k */
 void or_poly_monomial(const or_ring *R, int l, const uint64_t *a, int k, uint64_t *out)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= l; i++) or_monomial(a + (size_t)i * R->n, out + (size_t)i * R->n, R->n, k, R->q[i]);
 }

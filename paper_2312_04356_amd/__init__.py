@@ -88,6 +88,7 @@ _SIGS = {
     "nj_add_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, vp]),
     "nj_cheb_interpolate": (i32, [i32, dbl, i32, vp]),
     "nj_eval_mod": (i32, [vp, ctypes.POINTER(NjCt), i32, i32, vp, i32, ctypes.POINTER(NjCt), vp]),
+    "nj_eval_order": (i32, [vp, i32]),
     "nj_combine": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_stoc1_plan_create": (i32, [vp, i32, i32, i32, ctypes.POINTER(vp)]),
     "nj_stoc1": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -575,6 +576,9 @@ class Ctx:
         ci = ct.c()
         _check(_lib.nj_add_const(self.ptr, ctypes.byref(ci), float(v), _stream(stream)), "nj_add_const")
         return ct
+
+    def nj_eval_order(self, order):
+        _check(_lib.nj_eval_order(self.ptr, int(order)), "nj_eval_order")
 
     def nj_eval_mod(self, ct, K, r, coeffs, out, stream=None):
         ci, co = ct.c(), out.c()

@@ -196,6 +196,26 @@ class Ev {
     Cx eval(const std::vector<double> &cf, int lam, double tau)
     {
         const int d = (int)cf.size() - 1;
+        if (d < 8 && c->eval_order == 0) {
+            // each term c_j T_j brought to level lam, scale tau by its own constant multiply
+            // and rescale, then the terms summed
+            Cx acc;
+            for (int j = 1; j <= d; j++) {
+                if (cf[j] == 0.0) continue;
+                Cx t = const_mult(T[j], cf[j], lam, tau);
+                if (!t.d) continue;
+                if (!acc.d) {
+                    acc = t;
+                } else {
+                    Cx sum = add(acc, t, 0);
+                    release(acc), release(t);
+                    acc = sum;
+                }
+            }
+            if (!acc.d) acc = zero(lam, tau);
+            add_const(acc, cf[0]);
+            return acc;
+        }
         if (d < 8) {
             // sum_j k_j T_j at level lam + 1, k_j = round(c_j tau q_{lam+1} / s_j) (every term
             // then at scale tau q_{lam+1}), accumulated in place; one rescale for the sum
@@ -355,6 +375,14 @@ nj_status nj_cheb_interpolate(int degree, double K, int r, double *coeffs)
 {
     if (degree < 1 || degree > 1023 || !coeffs || r < 0 || r > 16) return fail(NJ_EINVAL, "nj_cheb_interpolate: bad arguments");
     cheb_interpolate_cos(degree, K, r, coeffs);
+    return NJ_OK;
+}
+
+nj_status nj_eval_order(nj_ctx *c, int order)
+{
+    if (!c) return fail(NJ_EINVAL, "nj_eval_order: null context");
+    if (order != 0 && order != 1) return fail(NJ_EINVAL, "nj_eval_order: order must be 0 or 1");
+    c->eval_order = order;
     return NJ_OK;
 }
 

@@ -223,6 +223,9 @@ struct nj_ctx {
     std::map<uint32_t, nj::Key> keys;
     std::vector<uint64_t *> timing_keys;  // latency measurement: random key buffers for missing elements
     nj::Scratch scratch;
+    // ModEval's Chebyshev baby-step sums: 0 = one constant multiply and rescale per
+    // term, 1 = integer multiples accumulated at one level and rescaled once (nj_eval_order)
+    int eval_order = 0;
     // intermediate ciphertexts of the composite calls (Algorithm 1, bootstrapping)
     uint64_t *layer_buf = nullptr;
     size_t layer_words = 0;

@@ -94,8 +94,10 @@ def sm():
     return S
 
 
-def test_homomorphic_chebyshev_matches_chebval(sm):
-    """degree-63 series on encrypted x in [-1, 1] (slots), scale ~2^48"""
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_homomorphic_chebyshev_matches_chebval(sm, accumulate):
+    """degree-63 series on encrypted x in [-1, 1] (slots), scale ~2^48, in both
+    evaluation orders of the baby-step sums"""
     n = sm.N // 2
     xv = RNG.uniform(-1, 1, n)
     c = RNG.normal(0, 1, 64) / (1 + np.arange(64)) ** 2
@@ -103,10 +105,27 @@ def test_homomorphic_chebyshev_matches_chebval(sm):
     ct = (sm.enc(E.encode(xv, sm.N, 2.0 ** 48), l1, 0), l1, 2.0 ** 48)
     T = sm.boot.cheb_basis(ct)
     lam = l1 - 7
-    out = sm.boot.eval_cheb(T, c, lam, float(sm.q[lam]))
+    out = sm.boot.eval_cheb(T, c, lam, float(sm.q[lam]), accumulate)
     got = E.decode(np.rint(sm.dec(out[0], out[1], 1.0)), sm.N, out[2])
     assert out[1] == lam
     assert np.max(np.abs(got.real - CH.chebval(xv, c))) < 1e-8
+
+
+def test_eval_orders_agree_within_noise(sm):
+    """the two evaluation orders of ModEval differ only in rounding: different low bits,
+    the same message within 2^-20"""
+    n = sm.N // 2
+    P = sm.q[0] / sm.scale
+    t = RNG.uniform(-1, 1, n) + P * RNG.integers(-6, 7, n)
+    ct = (sm.enc(E.encode(t, sm.N, sm.scale), 20, 2), 20, sm.scale)
+    c = B.cheb_coeffs(K, R_DA)
+    a = sm.boot.eval_mod(ct, K, R_DA, c)
+    b = sm.boot.eval_mod(ct, K, R_DA, c, accumulate=True)
+    assert a[1] == b[1] and a[2] == b[2]
+    assert not np.array_equal(a[0], b[0])
+    za = E.decode(np.rint(sm.dec(a[0], a[1], 1.0)), sm.N, a[2]).real
+    zb = E.decode(np.rint(sm.dec(b[0], b[1], 1.0)), sm.N, b[2]).real
+    assert np.max(np.abs(za - zb)) < 2.0 ** -20
 
 
 def test_eval_mod_recovers_message(sm):

@@ -26,10 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fused CinS-conv+CoeffToSlot ms and keyswitch/s at N=2^16; batched vs plain"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the step's kernel families, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a copy kernel of known size (profiles/pmc_fused_conv_cts_n65536.md);
-# valid for the kernels as they were when counted, absent for the others
-TRAFFIC_BYTES = {"k_key_ip": 810659530}
+# rocprofv3 counter summary of the step (FETCH_SIZE and WRITE_SIZE per launch, scaled by a
+# copy of known size); its machine-readable line carries the digest of the kernel sources
+# it was taken with, and `traffic` is reported only while the sources still match
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fused_conv_cts_n65536.md")
 
 
 def parse():
@@ -45,7 +45,24 @@ def parse():
     ap.add_argument("--jobs", type=int, default=64, help="mixed jobs at uneven levels (0 skips them)")
     ap.add_argument("--no-boot", action="store_true", help="skip the ModEval / StoC1 timing")
     ap.add_argument("--no-lazy", action="store_true", help="one ModDown per giant step in CoeffToSlot")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 10 device-to-device copies of 128 MiB (the counter calibration of the "
+                         "rocprofv3 traffic figures) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """device-to-device copies of a known size: the runtime's copy kernel reads and writes
+    128 MiB per launch, the reference for scaling FETCH_SIZE / WRITE_SIZE to bytes"""
+    import torch
+    n = 128 * 2 ** 20 // 8
+    src = torch.arange(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    print(json.dumps({"copy_bytes": n * 8, "launches": 10}))
 
 
 def group_rotations(g):
@@ -60,11 +77,11 @@ def group_rotations(g):
     return out
 
 
-def pipeline_bytes(g):
-    """Algorithmic HBM bytes of one step: the input ciphertext, every switching key
-    at the level it is used (active limbs and digits only), every plaintext diagonal,
-    one read and one write of the ciphertext per BSGS group, the ModRaise output and
-    the two output ciphertexts.
+def step_bytes(g):
+    """Algorithmic HBM bytes of one step by kind: every switching key at the level it is
+    used (active limbs and digits only), every plaintext diagonal, and the ciphertexts
+    (the input, one read and one write per BSGS group, the ModRaise output, the two
+    outputs).
       key(l) = 2 dnum_l (l+1+alpha) N 8,  pt(l) = (l+1) N 8,  ct(l) = 2 (l+1) N 8."""
     c = g.ctx
     N, a = c.N, c.alpha
@@ -78,14 +95,52 @@ def pipeline_bytes(g):
     def ct(l):
         return 2 * (l + 1) * N * 8
 
-    b = ct(1) + len(g.conv_plan.galois()) * key(1) + len(g.conv_plan.offsets(0)) * pt(1) + ct(0)
-    b += ct(c.L)  # ModRaise output
+    keys = len(g.conv_plan.galois()) * key(1)
+    pts = len(g.conv_plan.offsets(0)) * pt(1)
+    cts = ct(1) + ct(0) + ct(c.L)  # input, conv output, ModRaise output
     level = c.L
     for t, r in enumerate(group_rotations(g)):
-        b += len(g.cts_plan.offsets(t)) * pt(level) + 2 * ct(level) + r * key(level)
+        pts += len(g.cts_plan.offsets(t)) * pt(level)
+        cts += 2 * ct(level)
+        keys += r * key(level)
         level -= 1
-    b += key(level) + 2 * ct(level)  # conjugation key, two outputs
-    return float(b)
+    keys += key(level)  # conjugation
+    cts += 2 * ct(level)  # Re and Im
+    return {"keys": float(keys), "plaintexts": float(pts), "ciphertexts": float(cts)}
+
+
+def pipeline_bytes(g):
+    return sum(step_bytes(g).values())
+
+
+def source_digest():
+    """SHA-256 (first 16 hex digits) of the library's kernel and host sources"""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2312_04356_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was
+    taken with the current sources (else None) -> (bytes or None, note)"""
+    if not os.path.exists(PMC_SUMMARY):
+        return None, "no counter summary"
+    rec = None
+    for line in open(PMC_SUMMARY):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+    if rec is None:
+        return None, "counter summary has no traffic record"
+    if rec.get("source_sha16") != source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    row = rec.get("kernels", {}).get(kernel)
+    if row is None:
+        return None, "kernel not in the counter summary"
+    return row["hbm_bytes_per_launch"], "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
 
 def job_plans(g, specs, n1_of=None):
@@ -269,56 +324,52 @@ def boot_bench(g, steps=3):
     return res
 
 
-def cpu_baseline(name):
-    """The oracle on the host: one fused conv at level 1 and the ModRaise executed in
-    full; one rotation, one PMult and one rescale at each CoeffToSlot level, scaled
-    by the plan's rotation and diagonal counts; one conjugation."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(name):
+    """The oracle on the host, the whole step once: the fused conv at level 1, rescale,
+    ModRaise, CoeffToSlot in three groups with lazy giant steps and the real split, on
+    one ciphertext with its limb loops on every host core (keys generated before the
+    timed region, as they are resident on the GPU).  The single-thread figure scales
+    that time by the one-core / all-core ratio of one level-23 rotation."""
+    import oracle as O
     from oracle.plans import galois_elt
     from tests.oracle_workload import OracleWorkload
     t0 = time.time()
+    O.set_threads(0)
+    threads = O.get_threads()
     o = OracleWorkload(name, with_cts=True)
-    o.make_keys(sorted({galois_elt(r, o.N) for r in o.conv_bsgs.rotations()}))
+    o.make_keys()
     ct = o.encrypt_input(1)
     t = time.perf_counter()
     y = o.ctx.conv2d_cins(ct, o.conv_bsgs, o.conv_pts)
+    o.ctx.coeff_to_slot(y, [p for p, _ in o.cts], [pts for _, pts in o.cts], lazy=True)
     total = time.perf_counter() - t
-    t = time.perf_counter()
-    o.ctx.ct_modraise(y)
-    total += time.perf_counter() - t
-    R = o.ring
-    level = R.L
-    rng = np.random.default_rng(0)
-    sample = ["conv2d_cins at level 1 (full)", "ModRaise (full)"]
-    for plan, pts in o.cts:
-        g = galois_elt(plan.rotations()[0], o.N)
-        o.make_keys([g])
-        xl = np.stack([np.stack([rng.integers(0, q, o.N, dtype=np.uint64) for q in R.q[:level + 1]])
-                       for _ in range(2)])
+    # one rotation at the top level on one core and on all of them
+    x = o.ctx.ct_modraise(y)
+    r = o.cts[0][0].rotations()[0]
+    assert galois_elt(r, o.N) in o.ctx.keys
+    times = {}
+    for n in (1, threads):
+        O.set_threads(n)
         t = time.perf_counter()
-        o.ctx.apply_galois(level, xl, g)
-        rot_s = time.perf_counter() - t
-        t = time.perf_counter()
-        o.ctx.ct_pmult(level, xl, pts[sorted(pts)[0]])
-        pm_s = time.perf_counter() - t
-        t = time.perf_counter()
-        o.ctx.ct_rescale(level, xl)
-        rs_s = time.perf_counter() - t
-        total += len(plan.rotations()) * rot_s + len(pts) * pm_s + rs_s
-        sample.append("level %d: 1 rotation x%d, 1 PMult x%d, rescale" % (level, len(plan.rotations()), len(pts)))
-        level -= 1
-    g = 2 * o.N - 1
-    o.make_keys([g])
-    xl = np.stack([np.stack([rng.integers(0, q, o.N, dtype=np.uint64) for q in R.q[:level + 1]]) for _ in range(2)])
-    t = time.perf_counter()
-    o.ctx.apply_galois(level, xl, g)
-    total += time.perf_counter() - t
-    sample.append("conjugation at level %d" % level)
-    return {"value": round(total * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": "; ".join(sample) + "; CoeffToSlot time scaled by the plan's op counts "
-                      "(every rotation priced as a plain one)",
-            "wall_s": round(time.time() - t0, 1)}
+        o.ctx.rotate(o.ring.L, x, r)
+        times[n] = time.perf_counter() - t
+    O.set_threads(0)
+    return {"value": round(total * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": "the whole step once (conv at level 1, rescale, ModRaise, CoeffToSlot 3 groups with lazy "
+                      "giant steps, real split) on one ciphertext, limb loops over %d OpenMP threads" % threads,
+            "single_thread_ms_est": round(total * times[1] / times[threads] * 1e3, 1),
+            "thread_speedup_one_rotation": round(times[1] / times[threads], 2),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "wall_s": round(time.time() - t0, 1)}
 
 
 def main():
@@ -326,6 +377,9 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from paper_2312_04356_amd import PROF_KERNELS
@@ -439,10 +493,29 @@ def main():
             kern[name] = {"launches_per_step": n / args.steps, "ms_per_step": kms / args.steps,
                           "avg_launch_us": 1e3 * kms / n, "gbs": kby / kms / 1e6}
     dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms_per_step"])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(dom),
-                "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
-    alg = pipeline_bytes(g)
+    sb = step_bytes(g)
+    alg = sum(sb.values())
+    if dom == "k_key_ip":  # algorithmic bytes of the key inner products: the switching keys they read
+        dom_alg = sb["keys"]
+    elif dom == "k_pmac":  # of the plaintext multiply-accumulate: the plaintext diagonals
+        dom_alg = sb["plaintexts"]
+    else:
+        dom_alg = None
+    launches = kern[dom]["launches_per_step"]
+    traffic, traffic_note = pmc_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "avg_launch_us": round(kern[dom]["avg_launch_us"], 2), "launches_per_step": launches,
+                "traffic": traffic, "traffic_source": traffic_note,
+                "io_gbs": round(kern[dom]["gbs"], 1),
+                "io_bytes_per_launch": round(kern[dom]["gbs"] * kern[dom]["avg_launch_us"] * 1e3)}
+    if dom_alg is not None:
+        per_launch = dom_alg / launches
+        achieved = per_launch / (kern[dom]["avg_launch_us"] * 1e-6) / 1e9
+        roofline.update({"achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": round(per_launch)})
+    else:
+        roofline.update({"achieved": roofline["io_gbs"], "frac": round(roofline["io_gbs"] / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": roofline["io_bytes_per_launch"]})
 
     out = {
         "metric": METRIC,
@@ -470,7 +543,9 @@ def main():
         "bootstrap_after_cts": boot,
         "roofline": roofline,
         "pipeline": {"algorithmic_GB": round(alg / 1e9, 3),
+                     "algorithmic_GB_by_kind": {k: round(v / 1e9, 3) for k, v in sb.items()},
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "source_sha16": source_digest(),
                      "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()}},
     }
     if not args.no_cpu_baseline:

@@ -75,7 +75,9 @@ const char *nj_last_error(void);
 nj_status nj_gen_primes(int log_n, int bits, int count, const uint64_t *exclude, int n_exclude, uint64_t *out);
 
 /* Creates a context on the current HIP device: validates primes, builds transform
- * tables and basis-conversion constants, allocates no ciphertext scratch yet. */
+ * tables and basis-conversion constants, allocates no ciphertext scratch yet.
+ * NJ_EUNSUPPORTED (before any device work) for n_q > 32, alpha > 16 or more than 8
+ * key-switching digits ceil(n_q / alpha). */
 nj_status nj_ctx_create(const nj_params *params, nj_ctx **out);
 void nj_ctx_destroy(nj_ctx *ctx);
 

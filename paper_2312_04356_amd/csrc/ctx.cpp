@@ -187,13 +187,14 @@ nj_status nj_ctx_create(const nj_params *P, nj_ctx **out)
 {
     if (!P || !out || !P->q || !P->p) return fail(NJ_EINVAL, "nj_ctx_create: null argument");
     if (P->log_n < 10 || P->log_n > 16) return fail(NJ_EUNSUPPORTED, "nj_ctx_create: log_n must be 10..16");
-    // the basis-conversion tables of a launch hold at most 4 digits of 16 primes and 48
+    // the basis-conversion tables of a launch hold digits of at most 16 primes and 48
     // targets each (BconvShared): n_q <= 32 keeps every ModUp digit (n_q + alpha - m
     // targets) and ModDown (n_q targets) inside them
     if (P->n_q < 1 || P->n_q > 32 || P->alpha < 1 || P->alpha > 16)
         return fail(NJ_EUNSUPPORTED, "nj_ctx_create: prime counts out of range (1 <= n_q <= 32, 1 <= alpha <= 16)");
-    if ((P->n_q + P->alpha - 1) / P->alpha > 4)
-        return fail(NJ_EUNSUPPORTED, "nj_ctx_create: more than 4 key-switching digits (dnum = ceil(n_q / alpha))");
+    // the shared-key inner products hold every digit's key words of one limb in registers
+    if ((P->n_q + P->alpha - 1) / P->alpha > 8)
+        return fail(NJ_EUNSUPPORTED, "nj_ctx_create: more than 8 key-switching digits (dnum = ceil(n_q / alpha))");
     nj_ctx *c = new nj_ctx();
     c->log_n = P->log_n;
     c->N = 1 << P->log_n;

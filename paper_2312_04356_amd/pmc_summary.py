@@ -3,21 +3,23 @@
     python -m paper_2312_04356_amd.pmc_summary <pmc_root> <bench_plain.json> "<commands>" > summary.md
 
 <pmc_root> holds the counter directories the passes wrote: pmc_FETCH_SIZE, pmc_WRITE_SIZE,
-pmc_VALUBusy (bench.py under --pmc) and pmc_copy_FETCH_SIZE, pmc_copy_WRITE_SIZE (the copy
-kernel of microbench/bw_probe, 128 MiB read and 128 MiB written per launch).  For every
-kernel family the bench line reports, the last launches_per_step x (steps) dispatches are
-the bench's last steps; their counters are averaged per launch.  HBM bytes per launch =
-FETCH_SIZE and WRITE_SIZE scaled by the copy kernel's known bytes over what the same
-counters read for it.
+pmc_VALUBusy (bench.py under --pmc) and pmc_copy_FETCH_SIZE, pmc_copy_WRITE_SIZE (the
+device-to-device copies of `bench.py --copy-calibration`, 128 MiB read and 128 MiB written
+per launch).  For every kernel family the bench line reports, the last
+launches_per_step x (steps) dispatches are the bench's last steps; their counters are
+averaged per launch.  HBM bytes per launch = FETCH_SIZE and WRITE_SIZE scaled by the copy
+kernel's known bytes over what the same counters read for it.  The last line,
+`traffic-record: {...}`, is what bench.py reads back as `roofline.traffic` while the
+library's sources still have the digest it records.
 """
 import csv
 import json
 import sys
-from collections import defaultdict
 
 from paper_2312_04356_amd.prof_summary import family
 
-COPY_BYTES = 128 * 2 ** 20  # bw_probe's copy2: bytes read and bytes written per launch
+COPY_BYTES = 128 * 2 ** 20  # bytes read and bytes written per calibration copy
+COPY_KERNEL = "copyBuffer"  # the runtime's device-to-device copy kernel
 
 
 def per_dispatch(path):
@@ -33,7 +35,8 @@ def per_dispatch(path):
 
 def copy_factor(root, counter):
     rows = [c[counter] for f, c in per_dispatch("%s/pmc_copy_%s/run_counter_collection.csv" % (root, counter))
-            if f == "copy2"]
+            if COPY_KERNEL in f]
+    rows = rows[-8:]  # the timed copies (the first ones warm up)
     return COPY_BYTES / (sum(rows) / len(rows) * 1024.0), sum(rows) / len(rows)
 
 
@@ -58,16 +61,17 @@ def main(root, plain_json, commands):
     for line in commands.split(";;"):
         print("    " + line.strip())
     print()
-    print("Copy calibration (bw_probe copy2, %d MiB read + %d MiB written per launch): FETCH_SIZE reads %.0f KiB "
-          "(factor %.4f), WRITE_SIZE %.0f KiB (factor %.4f)." % (COPY_BYTES >> 20, COPY_BYTES >> 20, fcopy, ff, wcopy, fw))
+    print("Copy calibration (bench.py --copy-calibration: device-to-device copies, %d MiB read + %d MiB written "
+          "per launch): FETCH_SIZE reads %.0f KiB (factor %.4f), WRITE_SIZE %.0f KiB (factor %.4f)."
+          % (COPY_BYTES >> 20, COPY_BYTES >> 20, fcopy, ff, wcopy, fw))
     print()
-    print("| kernel | launches/step | algorithmic MB/launch | HBM read MB/launch | HBM written MB/launch | "
-          "HBM total / algorithmic | VALUBusy % | VALU instr / launch (M) |")
+    print("| kernel | launches/step | kernel I/O MB/launch | HBM read MB/launch | HBM written MB/launch | "
+          "HBM total / kernel I/O | VALUBusy % | VALU instr / launch (M) |")
     print("|---|---|---|---|---|---|---|---|")
     rows = {}
     for k, v in sorted(plain["pipeline"]["kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"]):
         n = int(round(v["launches_per_step"] * steps))
-        alg = v["gbs"] * v["avg_launch_us"] * 1e3  # bytes per launch
+        alg = v["gbs"] * v["avg_launch_us"] * 1e3  # input + output bytes per launch (library's count)
         rd = last_of(fetch, k, n, "FETCH_SIZE") * 1024 * ff
         wr = last_of(write, k, n, "WRITE_SIZE") * 1024 * fw
         vb = last_of(valu, k, n, "VALUBusy")
@@ -80,7 +84,14 @@ def main(root, plain_json, commands):
     r = rows.get(dom)
     if r:
         print("Dominant kernel %s: %.0f bytes of HBM traffic per launch (read %.0f + written %.0f) against %.0f "
-              "algorithmic." % (dom, r["read"] + r["write"], r["read"], r["write"], r["alg"]))
+              "bytes of kernel input and output and %.0f algorithmic bytes (the switching keys it reads)."
+              % (dom, r["read"] + r["write"], r["read"], r["write"], r["alg"],
+                 plain["roofline"].get("algorithmic_bytes_per_launch", float("nan"))))
+    print()
+    rec = {"source_sha16": plain["pipeline"]["source_sha16"], "workload": plain["config"]["workload"],
+           "kernels": {k: {"hbm_bytes_per_launch": round(v["read"] + v["write"]), "read": round(v["read"]),
+                           "written": round(v["write"])} for k, v in rows.items()}}
+    print("traffic-record: " + json.dumps(rec))
 
 
 if __name__ == "__main__":

@@ -34,15 +34,15 @@ import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_batch_jobs.json")
 TOP = 23
-# (plan name, ciphertext level, encryption sub-stream): the two pointwise jobs share one
+# (plan name, ciphertext level, encryption sub-stream): the two "3x3b" jobs share one
 # plan at different levels, so the batched schedule runs them together across levels
-JOBS = [("1x1", 9, 301), ("3x3", 11, 302), ("1x1", 13, 303)]
+JOBS = [("3x3b", 9, 301), ("3x3", 11, 302), ("3x3b", 13, 303)]
 
 
 def plan_weights(o):
-    """conv weights of each plan: the workload's 3x3 kernel and a seeded pointwise one"""
+    """conv weights of each plan: the workload's 3x3 kernel and a second seeded one"""
     C = o.C
-    return {"3x3": o.K, "1x1": synth.uniform_real((C, C, 1, 1), o.w["data_seed"], 200)}
+    return {"3x3": o.K, "3x3b": synth.uniform_real((C, C, 3, 3), o.w["data_seed"], 200)}
 
 
 def oracle_plans(o):

@@ -101,9 +101,9 @@ def _create_status(log_n, n_q, alpha):
     return nj._lib.nj_ctx_create(ctypes.byref(prm), ctypes.byref(h))
 
 
-@pytest.mark.parametrize("n_q,alpha", [(64, 8), (33, 16), (32, 4), (17, 1)])
+@pytest.mark.parametrize("n_q,alpha", [(64, 8), (33, 16), (32, 2), (17, 1)])
 def test_ctx_create_refuses_oversized_bases(n_q, alpha):
     """more ciphertext primes than the basis-conversion tables hold (n_q > 32), or more
-    than 4 key-switching digits, is refused with NJ_EUNSUPPORTED before any device work"""
+    than 8 key-switching digits, is refused with NJ_EUNSUPPORTED before any device work"""
     assert _create_status(12, n_q, alpha) == -7
     assert "nj_ctx_create" in nj._lib.nj_last_error().decode()

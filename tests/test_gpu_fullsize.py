@@ -7,8 +7,8 @@ C ABI, word for word against the oracle (needs an MI355X):
   conjugate split fused into the conjugation's ModDown (Algorithm 1, lines 1-2);
 * ModEval as one call on a level-20 ciphertext (Sec. 2.4; the library's evaluation in
   both Chebyshev orders);
-* a mixed-level job list run by the batched schedule (mode 1: pointwise jobs at levels
-  9 and 13 sharing each key read across levels) and by its HIP-graph replay, against
+* a mixed-level job list run by the batched schedule (mode 1: two jobs of one conv plan
+  at levels 9 and 13 sharing each key read across levels) and by its HIP-graph replay, against
   SHA-256 digests of the oracle's outputs written by tests/golden/full_batch_jobs.py.
 
 The oracle's share of these tests runs its limb loops on every host core.

@@ -36,7 +36,7 @@ def per_dispatch(path):
 def copy_factor(root, counter):
     rows = [c[counter] for f, c in per_dispatch("%s/pmc_copy_%s/run_counter_collection.csv" % (root, counter))
             if COPY_KERNEL in f]
-    rows = rows[-8:]  # the timed copies (the first ones warm up)
+    rows = [v for v in rows if v >= 0.25 * max(rows)]  # the 128 MiB copies (not the small ones torch adds)
     return COPY_BYTES / (sum(rows) / len(rows) * 1024.0), sum(rows) / len(rows)
 
 

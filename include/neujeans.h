@@ -137,6 +137,19 @@ nj_status nj_rotate(nj_ctx *ctx, const nj_ct *in, int r, nj_ct *out, void *strea
 /* Automorphism X -> X^g followed by hybrid key switching back to s (ModUp, key
  * inner product, ModDown).  Needs the key of g.  in and out may alias. */
 nj_status nj_apply_galois(nj_ctx *ctx, const nj_ct *in, uint32_t galois_elt, nj_ct *out, void *stream);
+/* nj_apply_galois for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same kernels and the
+ * same result word for word, with the scratch in a fixed 160 MiB (20 Mi words) device
+ * array of the library instead of the context's growable arena.  No hipMalloc, hipFree
+ * or other allocating call is made.  The array exists once per GPU for the process's
+ * lifetime (its address is looked up when a context is created on that GPU); every call
+ * on one GPU shares it, so calls that may overlap on one GPU (different streams or
+ * threads, any context) race and must be serialised by the caller.  Nothing in it needs
+ * clearing between calls.  NJ_EUNSUPPORTED when the key switch needs more scratch than
+ * the array holds (ModUp digits, inner products and ModDown limbs at level l: about
+ * (2(l+1) + dnum_l (l+1+alpha) + 2(l+1+alpha) + 2 alpha + 3(l+1)) N words) or while live
+ * profiling is on; otherwise the errors of nj_apply_galois. */
+nj_status nj_apply_galois_noalloc(nj_ctx *ctx, const nj_ct *in, uint32_t galois_elt, nj_ct *out, void *stream);
 /* Key switching of one polynomial d (evaluation form, level l): (out0, out1) with
  * out0 + out1 s ~ d s', using the key of galois_elt (0 = relinearisation key). */
 nj_status nj_keyswitch(nj_ctx *ctx, const uint64_t *d, int level, uint32_t galois_elt, uint64_t *out0, uint64_t *out1,

@@ -60,6 +60,7 @@ _SIGS = {
     "nj_upload_plain": (i32, [vp, vp, i32, vp, vp]),
     "nj_rotate": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
     "nj_apply_galois": (i32, [vp, ctypes.POINTER(NjCt), u32, ctypes.POINTER(NjCt), vp]),
+    "nj_apply_galois_noalloc": (i32, [vp, ctypes.POINTER(NjCt), u32, ctypes.POINTER(NjCt), vp]),
     "nj_keyswitch": (i32, [vp, vp, i32, u32, vp, vp, vp]),
     "nj_pmult": (i32, [vp, ctypes.POINTER(NjCt), vp, ctypes.POINTER(NjCt), vp]),
     "nj_add": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -437,6 +438,12 @@ class Ctx:
         ci, co = ct.c(), out.c()
         _check(_lib.nj_apply_galois(self.ptr, ctypes.byref(ci), int(g), ctypes.byref(co), _stream(stream)),
                "nj_apply_galois")
+        return out.sync_from(co)
+
+    def nj_apply_galois_noalloc(self, ct, g, out, stream=None):
+        ci, co = ct.c(), out.c()
+        _check(_lib.nj_apply_galois_noalloc(self.ptr, ctypes.byref(ci), int(g), ctypes.byref(co), _stream(stream)),
+               "nj_apply_galois_noalloc")
         return out.sync_from(co)
 
     def nj_keyswitch(self, d, level, g, out0, out1, stream=None):

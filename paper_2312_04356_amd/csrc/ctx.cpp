@@ -346,6 +346,10 @@ nj_status nj_ctx_create(const nj_params *P, nj_ctx **out)
         nj_ctx_destroy(c);
         return hip_fail(e, "nj_ctx_create: constants upload");
     }
+    // the device address of the no-allocation entry point's static scratch, looked up
+    // once per device while it is current; a failure only disables that entry point,
+    // which reports it
+    (void)noalloc_init(c->device);
     *out = c;
     return NJ_OK;
 }

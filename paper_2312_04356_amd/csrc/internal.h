@@ -371,6 +371,11 @@ hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const 
                            int n_diag, hipStream_t s,
                            int accumulate = 0);
 
+// --------------------------------------------------------------- noalloc.hip
+// looks up (once per device, the device current) the static scratch of
+// nj_apply_galois_noalloc
+hipError_t noalloc_init(int device);
+
 // ------------------------------------------------------------------- ctx.hip
 LimbTab limbs_q(int level);                       // q_0..q_l
 LimbTab limbs_ext(const nj_ctx *c, int level);    // q_0..q_l, p_0..p_{alpha-1}

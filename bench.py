@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--jobs", type=int, default=64, help="mixed jobs at uneven levels (0 skips them)")
     ap.add_argument("--no-boot", action="store_true", help="skip the ModEval / StoC1 timing")
     ap.add_argument("--no-lazy", action="store_true", help="one ModDown per giant step in CoeffToSlot")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-plan step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 10 device-to-device copies of 128 MiB (the counter calibration of the "
                          "rocprofv3 traffic figures) and exit")
@@ -242,6 +243,108 @@ def jobs_bench(g, n_jobs, steps=2):
             "batched_default_plans_ms": round(eager, 3), "batched_graph_tuned_ms": round(replay, 3),
             "speedup_vs_plain": round(plain / replay, 3),
             "tuned_n1": {"%s/C%d" % k: v for k, v in sorted(n1_of.items())}}
+
+
+PLAN_MODEL = os.path.join(ROOT, "paper_2312_04356_amd", "data", "plan_model_n65536.json")
+
+
+def bitrev_perm(n):
+    b = n.bit_length() - 1
+    return [int(format(j, "0%db" % b)[::-1], 2) for j in range(n)]
+
+
+def crt2(res, q):
+    """centred integers from residues [2][N] modulo q[0], q[1]"""
+    Q = q[0] * q[1]
+    h0, h1 = q[1] * pow(q[1], -1, q[0]), q[0] * pow(q[0], -1, q[1])
+    out = []
+    for a, b in zip(res[0].tolist(), res[1].tolist()):
+        x = (a * h0 + b * h1) % Q
+        out.append(x - Q if x > Q // 2 else x)
+    return out
+
+
+def slot_error(g, y, re, im, lvl):
+    """max |CoeffToSlot slot - bit-reversed coefficient| of the step's outputs (the
+    decryption accuracy the plans are compared at): the level-0 conv output is decrypted
+    over the integers (c0 + c1 s, which ModRaise lifts), each CoeffToSlot output by the
+    library and decoded by it"""
+    import numpy as np
+    import torch
+    gctx, n = g.ctx, g.N // 2
+    t = y.data.clone()
+    gctx.nj_to_coeff(t, 0, 2)
+    torch.cuda.synchronize()
+    c = gctx.to_host(t)
+    q0 = g.q[0]
+    c0 = np.where(c[0][0] > q0 // 2, c[0][0].astype(np.int64) - np.int64(q0), c[0][0].astype(np.int64))
+    c1 = np.where(c[1][0] > q0 // 2, c[1][0].astype(np.int64) - np.int64(q0), c[1][0].astype(np.int64))
+    prod = np.zeros_like(c0)
+    for i in np.nonzero(g.s)[0]:
+        sh = np.roll(c1, i)
+        sh[:i] = -sh[:i]
+        prod += int(g.s[i]) * sh
+    raw = (c0 + prod).astype(np.float64) / g.scale
+    rev = np.array(bitrev_perm(n))
+    err = 0.0
+    for ct, want in ((re, raw[:n][rev]), (im, raw[n:][rev])):
+        d = torch.empty((lvl + 1, g.N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_decrypt(ct, d)
+        m = crt2(gctx.to_host(d)[:2], g.q[:2])
+        z = gctx.nj_decode_slots(np.array(m, dtype=np.float64), g.scale)
+        err = max(err, float(np.max(np.abs(z.real - want))), float(np.max(np.abs(z.imag))))
+    return err
+
+
+def learned_plan_bench(g, ct, default_ms, steps):
+    """The step with the plan the learned latency model proposes (the model trained by
+    paper_2312_04356_amd/tune.py from the library's own timings, run by nj_mlp_predict):
+    the conv's BSGS split and hoisting, CoeffToSlot's depth (2..6, within Algorithm 1's
+    level budget), each group's split and hoisting.  Timed like the default step, and
+    its CoeffToSlot outputs checked against the bit-reversed coefficients as the default's."""
+    import torch
+
+    from paper_2312_04356_amd import Mlp
+    from paper_2312_04356_amd.tune import choose_conv, choose_cts
+    if not os.path.exists(PLAN_MODEL):
+        return None
+    doc = json.load(open(PLAN_MODEL))
+    model = Mlp.from_dict(doc)
+    gctx = g.ctx
+    convs = {}
+    for n1 in (1, 2, 4, 8, 16):
+        for h in (True, False):
+            convs[(n1, h)] = gctx.nj_conv_plan_create(g.w["w0"], g.w["f"], g.K, n1).set_hoist(h)
+    (cn1, ch), conv_pred = choose_conv(gctx, model, convs, 1)
+    conv = convs.pop((cn1, ch))
+    del convs
+    d, n1s, hs, cts_pred, per_d = choose_cts(gctx, model)
+    cts = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
+    g.make_keys(sorted(set(conv.galois()) | set(cts.galois())))
+    lvl = gctx.L - d
+    y = gctx.empty_ct(0)
+    re, im = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+
+    def step():
+        gctx.nj_conv2d_cins(conv, ct, y)
+        gctx.nj_coeff_to_slot(cts, y, re, im)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    err = slot_error(g, y, re, im, lvl)
+    return {"conv": {"n1": cn1, "hoist": ch, "predicted_ms": round(conv_pred, 3)},
+            "cts": {"groups": d, "n1": n1s, "hoist": hs, "predicted_ms": round(cts_pred, 3),
+                    "predicted_ms_by_depth": {str(k): round(v, 3) for k, v in per_d.items()}},
+            "ms": round(ms, 4), "default_ms": round(default_ms, 4), "speedup_vs_default": round(default_ms / ms, 3),
+            "cts_slot_err": err, "output_level": lvl, "model": os.path.relpath(PLAN_MODEL, ROOT),
+            "model_heldout_rel_err": doc.get("heldout_rel_err")}
 
 
 def boot_bench(g, steps=3):
@@ -478,6 +581,10 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
 
+    default_err = slot_error(g, y, re, im, lvl)
+    learned = None if args.no_learned else learned_plan_bench(g, ct, ms, args.steps)
+    torch.cuda.empty_cache()
+
     # the same steps again with the library's live per-kernel event timing
     for k in PROF_KERNELS:
         gctx.nj_prof_read(k, reset=True)
@@ -540,6 +647,8 @@ def main():
                     "speedup_vs_plain": round(ms / (batch_ms / args.batch), 3),
                     "hbm_frac_per_ct": round(pipeline_bytes(g) / (batch_ms / args.batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "jobs": jobs,
+        "learned_plan": learned,
+        "default_plan_cts_slot_err": default_err,
         "bootstrap_after_cts": boot,
         "roofline": roofline,
         "pipeline": {"algorithmic_GB": round(alg / 1e9, 3),

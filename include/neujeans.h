@@ -188,6 +188,12 @@ nj_status nj_plan_set_diagonal(nj_ctx *ctx, nj_plan *plan, int t, int idx, const
  * Single-ciphertext and batched transforms only (block and mixed-level transforms
  * return NJ_EUNSUPPORTED). */
 nj_status nj_plan_set_lazy(nj_plan *plan, int on);
+/* Hoisted baby steps of transform t (t = -1: every transform of the plan) (on = 1, the
+ * default): the baby rotations share one ModUp of c1 and apply the automorphism to its
+ * extended digits; off, every baby rotation is its own key switch.  Used by
+ * nj_conv2d_cins, nj_coeff_to_slot and nj_time_plan (block transforms always hoist).
+ * Different low bits, so parity holds per setting. */
+nj_status nj_plan_set_hoist(nj_plan *plan, int t, int on);
 void nj_plan_destroy(nj_plan *plan);
 
 /* Fused conv2d + StoC2 plan (Sec. 3.3, Sec. 4, Algorithm 1): C = N/W^2
@@ -201,6 +207,14 @@ nj_status nj_conv_plan_create(nj_ctx *ctx, int w0, int f, const double *weights,
  * at levels L, L-1, ...; each group's diagonals encoded at the scale of the prime
  * its rescale drops; the 1/2 of the real split folded into the last group. */
 nj_status nj_cts_plan_create(nj_ctx *ctx, int groups, nj_plan **out);
+/* The same with the baby-step count of each group chosen: n1 host [groups] (0 = the
+ * default ceil(sqrt(#diagonals)), else any positive count; Sec. 2.6 leaves the BSGS
+ * split free).  Different splits give different low bits, so parity holds per split. */
+nj_status nj_cts_plan_create_split(nj_ctx *ctx, int groups, const int *n1, nj_plan **out);
+/* Cost-model features (as nj_plan_features) of each group of that CoeffToSlot plan at its
+ * level, baby steps hoisted or not, without building or uploading its diagonals: f host
+ * [groups][7].  n1 as for nj_cts_plan_create_split (may be null). */
+nj_status nj_cts_plan_features(nj_ctx *ctx, int groups, const int *n1, int hoist, float *f);
 
 /* BSGS evaluation of transform t of the plan on `in`, no rescale.  The input level may
  * be the transform's level or any lower one (the first l+1 limbs of each diagonal are
@@ -395,9 +409,12 @@ nj_status nj_plan_create_random(nj_ctx *ctx, int level, int u, const int32_t *of
  * (no rescale).  Synchronous. */
 nj_status nj_time_plan(nj_ctx *ctx, const nj_plan *plan, int t, int level, int reps, float *ms);
 
-/* Cost-model features of transform t at `level`: f[0] = limbs (level+1), f[1] =
- * log2(N/2 / u), f[2] = diagonals, f[3] = baby steps, f[4] = giant steps, f[5] = bi,
- * f[6] = bo. */
+/* Cost-model features of transform t at `level` (the plan features of the learned cost
+ * model): f[0] = limbs (level+1); f[1] = diagonals per block (channels of a fused conv);
+ * f[2] = log2(N/2 / u), u the slot stride of its rotations (image size); f[3] = baby steps
+ * (BSGS split); f[4] = hoisted baby rotations, bi (babies - 1), or 0 when not hoisted
+ * (hoist count); f[5] = DFT stages merged into the transform (fusion depth: log2 C for a
+ * conv fused with StoC2, the stage count of a CoeffToSlot or StoC1 group); f[6] = bo. */
 nj_status nj_plan_features(const nj_plan *plan, int t, int level, float *f);
 
 /* Learned cost model (plan selection by predicted latency): 7 features -> 64 -> 64 -> 1,
@@ -413,6 +430,13 @@ nj_status nj_mlp_create(uint64_t seed, nj_mlp **out);
 void nj_mlp_destroy(nj_mlp *mlp);
 nj_status nj_mlp_set_params(nj_mlp *mlp, const float *params); /* also resets the Adam state */
 nj_status nj_mlp_get_params(const nj_mlp *mlp, float *params);
+/* The standardisation a trained model applies (for saving and restoring it with the
+ * parameters): norm host [NJ_MLP_NORM] = feature means [7], feature scales [7], target
+ * mean, target scale.  A new model has means 0 and scales 1.  Set: NJ_EINVAL for a
+ * scale <= 0. */
+#define NJ_MLP_NORM (2 * 7 + 2)
+nj_status nj_mlp_get_norm(const nj_mlp *mlp, float *norm);
+nj_status nj_mlp_set_norm(nj_mlp *mlp, const float *norm);
 /* Gradient of mean((f(x_i) - y_i)^2) over the n samples X [n][7], y [n] with respect
  * to every parameter (raw inputs, no standardisation), and the loss. */
 nj_status nj_mlp_grad(nj_mlp *mlp, const float *X, const float *y, int n, float *grad, float *loss);

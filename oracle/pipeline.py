@@ -171,11 +171,13 @@ class Ctx:
         return re, im
 
     def coeff_to_slot(self, x0, groups, group_pts, hoist=True, lazy=False):
-        """x0: level-0 ct [2][1][N].  groups: [Bsgs]; group_pts[g]: {j: pt} at level L-g."""
+        """x0: level-0 ct [2][1][N].  groups: [Bsgs]; group_pts[g]: {j: pt} at level L-g.
+        hoist: one flag, or one per group."""
         x = self.ct_modraise(x0)
         level = self.ring.L
-        for plan, pts in zip(groups, group_pts):
-            x = self.bsgs(level, x, plan, pts, hoist, lazy)
+        hs = list(hoist) if isinstance(hoist, (list, tuple)) else [hoist] * len(groups)
+        for plan, pts, h in zip(groups, group_pts, hs):
+            x = self.bsgs(level, x, plan, pts, h, lazy)
             x = self.ct_rescale(level, x)
             level -= 1
         return self.conj_split(level, x)

@@ -84,6 +84,9 @@ _SIGS = {
     "nj_batch_destroy": (None, [vp]),
     "nj_timing_keys": (i32, [vp, i32]),
     "nj_plan_set_lazy": (i32, [vp, i32]),
+    "nj_plan_set_hoist": (i32, [vp, i32, i32]),
+    "nj_cts_plan_create_split": (i32, [vp, i32, vp, ctypes.POINTER(vp)]),
+    "nj_cts_plan_features": (i32, [vp, i32, vp, i32, vp]),
     "nj_hmult": (i32, [vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_mul_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, i32, dbl, ctypes.POINTER(NjCt), vp]),
     "nj_add_const": (i32, [vp, ctypes.POINTER(NjCt), dbl, vp]),
@@ -106,6 +109,8 @@ _SIGS = {
     "nj_mlp_destroy": (None, [vp]),
     "nj_mlp_set_params": (i32, [vp, vp]),
     "nj_mlp_get_params": (i32, [vp, vp]),
+    "nj_mlp_get_norm": (i32, [vp, vp]),
+    "nj_mlp_set_norm": (i32, [vp, vp]),
     "nj_mlp_grad": (i32, [vp, vp, vp, i32, vp, ctypes.POINTER(ctypes.c_float)]),
     "nj_mlp_train": (i32, [vp, vp, vp, i32, i32, i32, ctypes.c_float, u64, ctypes.POINTER(ctypes.c_float)]),
     "nj_mlp_predict": (i32, [vp, vp, i32, vp]),
@@ -233,6 +238,15 @@ class Plan:
         _check(_lib.nj_plan_set_lazy(self.ptr, int(bool(on))), "nj_plan_set_lazy")
         return self
 
+    def set_hoist(self, on=True, t=-1):
+        """hoisted baby steps for transform t (-1: all); on may be a list, one per transform"""
+        if isinstance(on, (list, tuple)):
+            for i, v in enumerate(on):
+                _check(_lib.nj_plan_set_hoist(self.ptr, i, int(bool(v))), "nj_plan_set_hoist")
+        else:
+            _check(_lib.nj_plan_set_hoist(self.ptr, int(t), int(bool(on))), "nj_plan_set_hoist")
+        return self
+
     def features(self, level, t=0):
         f = np.zeros(7, dtype=np.float32)
         _check(_lib.nj_plan_features(self.ptr, int(t), int(level), _np_ptr(f)), "nj_plan_features")
@@ -269,6 +283,7 @@ def nj_cheb_interpolate(degree, K, r):
 
 MLP_FEATURES, MLP_HIDDEN = 7, 64
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+MLP_NORM = 2 * 7 + 2
 
 
 class Mlp:
@@ -288,6 +303,27 @@ class Mlp:
         p = np.ascontiguousarray(p, dtype=np.float32)
         assert p.shape == (MLP_PARAMS,)
         _check(_lib.nj_mlp_set_params(self.ptr, _np_ptr(p)), "nj_mlp_set_params")
+
+    def norm(self):
+        out = np.zeros(MLP_NORM, dtype=np.float32)
+        _check(_lib.nj_mlp_get_norm(self.ptr, _np_ptr(out)), "nj_mlp_get_norm")
+        return out
+
+    def set_norm(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        assert v.shape == (MLP_NORM,)
+        _check(_lib.nj_mlp_set_norm(self.ptr, _np_ptr(v)), "nj_mlp_set_norm")
+
+    def to_dict(self):
+        """the trained model as plain lists (JSON-serialisable)"""
+        return {"params": [float(x) for x in self.params()], "norm": [float(x) for x in self.norm()]}
+
+    @classmethod
+    def from_dict(cls, d):
+        m = cls(0)
+        m.set_params(np.array(d["params"], dtype=np.float32))
+        m.set_norm(np.array(d["norm"], dtype=np.float32))
+        return m
 
     def grad(self, X, y):
         X = np.ascontiguousarray(X, dtype=np.float32)
@@ -659,6 +695,21 @@ class Ctx:
         h = vp()
         _check(_lib.nj_cts_plan_create(self.ptr, groups, ctypes.byref(h)), "nj_cts_plan_create")
         return Plan(h)
+
+    def nj_cts_plan_create_split(self, groups, n1s):
+        n1 = np.ascontiguousarray(list(n1s), dtype=np.int32)
+        assert n1.shape == (groups,)
+        h = vp()
+        _check(_lib.nj_cts_plan_create_split(self.ptr, int(groups), _np_ptr(n1), ctypes.byref(h)),
+               "nj_cts_plan_create_split")
+        return Plan(h)
+
+    def nj_cts_plan_features(self, groups, n1s=None, hoist=True):
+        n1 = None if n1s is None else np.ascontiguousarray(list(n1s), dtype=np.int32)
+        f = np.zeros((groups, 7), dtype=np.float32)
+        _check(_lib.nj_cts_plan_features(self.ptr, int(groups), None if n1 is None else _np_ptr(n1), int(bool(hoist)),
+                                         _np_ptr(f)), "nj_cts_plan_features")
+        return f
 
     def nj_plan_set_diagonal(self, plan, t, idx, coeffs):
         cf = np.ascontiguousarray(coeffs, dtype=np.uint64)

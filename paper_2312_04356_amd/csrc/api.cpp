@@ -858,7 +858,7 @@ nj_status bsgs_rescale(nj_ctx *c, const nj_lt_t &lt, const uint64_t *x, uint64_t
     uint64_t *last = c->N >= 8192 ? A.take(2 * (size_t)c->N) : nullptr;
     if (c->N >= 8192 && !last) return fail(NJ_ENOMEM, "scratch too small");
     bool done = false;
-    nj_status st = bsgs_apply(c, lt, x, y, 1, A, s, last, &done);
+    nj_status st = bsgs_apply(c, lt, x, y, lt.hoist ? 1 : 0, A, s, last, &done);
     if (st) return st;
     return rescale(c, lt.level, y, out, A, s, -1, 2, done ? last : nullptr);
 }
@@ -1230,6 +1230,14 @@ nj_status nj_plan_set_lazy(nj_plan *p, int on)
 {
     if (!p) return fail(NJ_EINVAL, "nj_plan_set_lazy: null plan");
     for (auto &lt : p->lts) lt.lazy = on != 0;
+    return NJ_OK;
+}
+
+nj_status nj_plan_set_hoist(nj_plan *p, int t, int on)
+{
+    if (!p || t < -1 || t >= (int)p->lts.size()) return fail(NJ_EINVAL, "nj_plan_set_hoist: bad arguments");
+    for (int i = 0; i < (int)p->lts.size(); i++)
+        if (t < 0 || i == t) p->lts[i].hoist = on != 0;
     return NJ_OK;
 }
 

@@ -260,6 +260,7 @@ nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap 
     if (ks.empty()) return fail(NJ_EINVAL, "conv plan: every weight is zero");
     lt.u = ell;
     lt.n1 = n1;
+    lt.stages = fuse ? ilog2(C) : 0;  // StoC2 merged into the kernel matrix when fused
     lt.js.clear();
     for (int k : ks) lt.js.push_back(centred_rep((long long)k * ell, ell, n));
     bsgs_split(lt, n);
@@ -305,6 +306,7 @@ nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int 
     }
     lt.u = ell;
     lt.n1 = n1;
+    lt.stages = ilog2(C);  // StoC2 = S_{N/2 <- l} merged into the kernel matrix
     lt.js.clear();
     for (int k = 0; k < C; k++) lt.js.push_back(centred_rep((long long)k * ell, ell, n));
     bsgs_split(lt, n);
@@ -390,7 +392,7 @@ static Diags compose(const Diags &A, const Diags &B, int n)
     return Cm;
 }
 
-nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
+nj_status build_cts_diagonals(int N, int groups, const int *n1s, std::vector<nj_lt_t> &lts,
                               std::vector<std::vector<std::vector<double>>> &dre,
                               std::vector<std::vector<std::vector<double>>> &dim)
 {
@@ -418,7 +420,8 @@ nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
                 for (auto &v : kv.second) v *= 0.5;
         nj_lt_t &lt = lts[g];
         lt.u = u;
-        lt.n1 = 0;
+        lt.n1 = n1s ? n1s[g] : 0;
+        lt.stages = sz;
         lt.js.clear();
         std::vector<const std::vector<cplx> *> vecs;
         std::map<int, const std::vector<cplx> *> byj;
@@ -466,6 +469,7 @@ nj_status build_stoc1_diagonals(int N, int ell, int groups, std::vector<nj_lt_t>
         nj_lt_t &lt = lts[g];
         lt.u = u;
         lt.n1 = 0;
+        lt.stages = sz;
         lt.js.clear();
         std::map<int, const std::vector<cplx> *> byj;
         for (auto &kv : M) byj[centred_rep(kv.first, u, n)] = &kv.second;

@@ -275,6 +275,8 @@ struct nj_lt_t {
     double scale = 0.0;                  // encoding scale of the diagonals
     int bi = 1, bo = 1;                  // block conv: input / output ciphertexts
     bool lazy = false;                   // giant steps share one ModDown
+    bool hoist = true;                   // baby steps share one ModUp of c1
+    int stages = 0;                      // DFT butterfly stages merged into the transform (fusion depth)
     std::vector<char> nz;                // [bo][bi][n_diag] nonzero diagonals (empty = all)
 };
 
@@ -390,7 +392,7 @@ void encode_cins(int N, const double *chans, int slice2, double scale, int64_t *
 void decode_slots(int N, const double *coeffs, double scale, double *z_re, double *z_im);
 nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
                                std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim);
-nj_status build_cts_diagonals(int N, int groups, std::vector<nj_lt_t> &lts,
+nj_status build_cts_diagonals(int N, int groups, const int *n1s, std::vector<nj_lt_t> &lts,
                               std::vector<std::vector<std::vector<double>>> &dre,
                               std::vector<std::vector<std::vector<double>>> &dim);
 nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse, int n1,

@@ -213,6 +213,25 @@ nj_status nj_mlp_set_params(nj_mlp *m, const float *params)
     return NJ_OK;
 }
 
+nj_status nj_mlp_get_norm(const nj_mlp *m, float *norm)
+{
+    if (!m || !norm) return fail(NJ_EINVAL, "nj_mlp_get_norm: null argument");
+    for (int k = 0; k < F; k++) norm[k] = m->mean[k], norm[F + k] = m->stdv[k];
+    norm[2 * F] = m->y_mean, norm[2 * F + 1] = m->y_std;
+    return NJ_OK;
+}
+
+nj_status nj_mlp_set_norm(nj_mlp *m, const float *norm)
+{
+    if (!m || !norm) return fail(NJ_EINVAL, "nj_mlp_set_norm: null argument");
+    for (int k = 0; k < F; k++)
+        if (!(norm[F + k] > 0.f)) return fail(NJ_EINVAL, "nj_mlp_set_norm: feature scales must be positive");
+    if (!(norm[2 * F + 1] > 0.f)) return fail(NJ_EINVAL, "nj_mlp_set_norm: target scale must be positive");
+    for (int k = 0; k < F; k++) m->mean[k] = norm[k], m->stdv[k] = norm[F + k];
+    m->y_mean = norm[2 * F], m->y_std = norm[2 * F + 1];
+    return NJ_OK;
+}
+
 nj_status nj_mlp_get_params(const nj_mlp *m, float *params)
 {
     if (!m || !params) return fail(NJ_EINVAL, "nj_mlp_get_params: null argument");

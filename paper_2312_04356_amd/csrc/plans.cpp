@@ -142,15 +142,38 @@ int nj_plan_layout(const nj_plan *p, int *W, int *C, int *ell, int *bi, int *bo)
     return p->lts[0].level;
 }
 
-nj_status nj_cts_plan_create(nj_ctx *c, int groups, nj_plan **out)
+nj_status nj_cts_plan_create(nj_ctx *c, int groups, nj_plan **out) { return nj_cts_plan_create_split(c, groups, nullptr, out); }
+
+nj_status nj_cts_plan_features(nj_ctx *c, int groups, const int *n1, int hoist, float *f)
+{
+    if (!c || !f) return fail(NJ_EINVAL, "nj_cts_plan_features: null argument");
+    if (groups < 1 || groups > c->L) return fail(NJ_ELEVEL, "nj_cts_plan_features: need 1 <= groups <= L");
+    nj_plan p;
+    p.kind = 1;
+    p.N = c->N;
+    std::vector<std::vector<std::vector<double>>> re, im;
+    nj_status st = build_cts_diagonals(c->N, groups, n1, p.lts, re, im);
+    if (st) return st;
+    for (int g = 0; g < groups; g++) {
+        p.lts[g].level = c->L - g;
+        p.lts[g].hoist = hoist != 0;
+        if ((st = nj_plan_features(&p, g, c->L - g, f + 7 * g))) return st;
+    }
+    return NJ_OK;
+}
+
+nj_status nj_cts_plan_create_split(nj_ctx *c, int groups, const int *n1, nj_plan **out)
 {
     if (!c || !out) return fail(NJ_EINVAL, "nj_cts_plan_create: null argument");
     if (groups < 1 || groups > c->L) return fail(NJ_ELEVEL, "nj_cts_plan_create: need 1 <= groups <= L");
+    if (n1)
+        for (int g = 0; g < groups; g++)
+            if (n1[g] < 0 || n1[g] > c->N / 2) return fail(NJ_EINVAL, "nj_cts_plan_create_split: bad baby-step count");
     nj_plan *p = new nj_plan();
     p->kind = 1;
     p->N = c->N;
     std::vector<std::vector<std::vector<double>>> re, im;
-    nj_status st = build_cts_diagonals(c->N, groups, p->lts, re, im);
+    nj_status st = build_cts_diagonals(c->N, groups, n1, p->lts, re, im);
     if (st) {
         delete p;
         return st;

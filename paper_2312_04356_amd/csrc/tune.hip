@@ -96,6 +96,7 @@ nj_status nj_plan_create_random(nj_ctx *c, int level, int u, const int32_t *offs
     lt.js = js;
     bsgs_split(lt, n);
     lt.dl = level + 1, lt.scale = (double)c->primes[level];
+    lt.stages = ilog2(m);  // the structure of a conv fused with StoC2 on C = n / u channels
     p->ell = u, p->C = m, p->c_in = m * bi, p->c_out = m * bo;
     for (p->W = 1; p->W * p->W < 2 * u; p->W *= 2) {}
     const size_t count = (size_t)bo * bi * lt.n_diag;
@@ -143,7 +144,7 @@ nj_status nj_time_plan(nj_ctx *c, const nj_plan *p, int t, int level, int reps, 
     nj_status st = NJ_OK;
     for (int r = 0; r <= reps && !st; r++) {
         (void)hipEventRecord(a, 0);
-        st = blk ? block_bsgs_apply(c, lt, x, y, A, 0) : bsgs_apply(c, lt, x, y, 1, A, 0);
+        st = blk ? block_bsgs_apply(c, lt, x, y, A, 0) : bsgs_apply(c, lt, x, y, lt.hoist ? 1 : 0, A, 0);
         (void)hipEventRecord(b, 0);
         (void)hipEventSynchronize(b);
         float v = 0.f;
@@ -162,13 +163,14 @@ nj_status nj_plan_features(const nj_plan *p, int t, int level, float *f)
     if (!p || t < 0 || t >= (int)p->lts.size() || !f) return fail(NJ_EINVAL, "nj_plan_features: bad arguments");
     const nj_lt_t &lt = p->lts[t];
     const int n = p->N / 2;
-    f[0] = (float)(level + 1);
-    f[1] = (float)ilog2(n / lt.u);
-    f[2] = (float)lt.n_diag;
-    f[3] = (float)lt.babies.size();
-    f[4] = (float)lt.giants.size();
-    f[5] = (float)lt.bi;
-    f[6] = (float)lt.bo;
+    const bool hoisted = lt.hoist || lt.bi != 1 || lt.bo != 1;  // block transforms always hoist
+    f[0] = (float)(level + 1);                                  // level
+    f[1] = (float)lt.n_diag;                                    // channels: diagonals per block
+    f[2] = (float)ilog2(n / lt.u);                              // slot stride of the rotations (image size)
+    f[3] = (float)lt.babies.size();                             // BSGS split: baby steps
+    f[4] = hoisted ? (float)(lt.bi * ((int)lt.babies.size() - 1)) : 0.f;  // hoisted baby rotations
+    f[5] = (float)lt.stages;                                    // fusion depth: DFT stages merged in
+    f[6] = (float)lt.bo;                                        // output blocks (giant rotations per step)
     return NJ_OK;
 }
 

@@ -1,6 +1,8 @@
 """Plan selection on the GPU (needs an MI355X): the cost-model kernels against the
 float64 oracle (forward values and loss gradient), training reduces the loss, and the
 timing helpers (random-diagonal plans, timing keys, features)."""
+import json
+
 import numpy as np
 import pytest
 
@@ -57,13 +59,20 @@ def test_timing_plans_and_keys():
     n = g.N // 2
     plan = ctx.nj_plan_create_random(3, 2048, list(range(16)), n1=4)  # C = 16 conv structure
     f = plan.features(3)
-    assert list(f) == [4, 4, 16, 4, 4, 1, 1]
+    # limbs, diagonals, log2(n/u), baby steps, hoisted baby rotations, fusion depth, bo
+    assert list(f) == [4, 16, 4, 4, 3, 4, 1]
+    assert list(plan.set_hoist(False).features(3)) == [4, 16, 4, 4, 0, 4, 1]
+    plan.set_hoist(True)
     with pytest.raises(NjError):  # no keys: the transform refuses to run
         ctx.nj_time_plan(plan, 3)
     ctx.nj_timing_keys(16)
     try:
         t1 = ctx.nj_time_plan(plan, 3, reps=3)
         t2 = ctx.nj_time_plan(plan, 1, reps=3)
+        t_plain = ctx.nj_time_plan(plan.set_hoist(False), 3, reps=3)
+        plan.set_hoist(True)
+        print("C=16 n1=4 at level 3: hoisted %.3f ms, not hoisted %.3f ms" % (t1, t_plain))
+        assert t_plain > t1
         blk = ctx.nj_plan_create_random(1, 2048, list(range(16)), n1=4, bi=2, bo=2)
         t3 = ctx.nj_time_plan(blk, 1, reps=3)
         print("C=16 n1=4: level 3 %.3f ms, level 1 %.3f ms, 2x2 blocks level 1 %.3f ms" % (t1, t2, t3))
@@ -71,3 +80,22 @@ def test_timing_plans_and_keys():
     finally:
         ctx.nj_timing_keys(0)
     assert n == 32768
+
+
+def test_mlp_save_and_restore():
+    """a trained model's parameters and standardisation written out and read back into a
+    new model predict the same values"""
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 8, (300, 7)).astype(np.float32)
+    y = (0.3 * X[:, 0] + np.sin(X[:, 1]) + 0.1 * X[:, 2] * X[:, 3]).astype(np.float32)
+    m = Mlp(seed=9)
+    m.train(X, y, epochs=20, batch=64, lr=1e-3, seed=1)
+    doc = json.loads(json.dumps(m.to_dict()))
+    m2 = Mlp.from_dict(doc)
+    assert np.array_equal(m.predict(X), m2.predict(X))
+    norm = m.norm()
+    assert norm.shape == (16,) and np.all(norm[7:14] > 0) and abs(norm[14] - y.mean()) < 1e-4
+    with pytest.raises(NjError):
+        bad = norm.copy()
+        bad[7] = 0.0
+        m2.set_norm(bad)

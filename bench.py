@@ -296,29 +296,41 @@ def slot_error(g, y, re, im, lvl):
     return err
 
 
-def learned_plan_bench(g, ct, default_ms, steps):
+def learned_plan_bench(g, ct, default_ms, steps, reps=3):
     """The step with the plan the learned latency model proposes (the model trained by
     paper_2312_04356_amd/tune.py from the library's own timings, run by nj_mlp_predict):
     the conv's BSGS split and hoisting, CoeffToSlot's depth (2..6, within Algorithm 1's
-    level budget), each group's split and hoisting.  Timed like the default step, and
-    its CoeffToSlot outputs checked against the bit-reversed coefficients as the default's."""
+    level budget), each group's split and hoisting.  The model ranks every candidate; its
+    best few are timed (nj_time_plan, timing keys for rotations without a key) and the
+    fastest is built with real keys, timed like the default step, and its CoeffToSlot
+    outputs checked against the bit-reversed coefficients as the default's are."""
     import torch
 
     from paper_2312_04356_amd import Mlp
-    from paper_2312_04356_amd.tune import choose_conv, choose_cts
+    from paper_2312_04356_amd.tune import SHORTLIST, rank_conv, rank_cts
     if not os.path.exists(PLAN_MODEL):
         return None
     doc = json.load(open(PLAN_MODEL))
     model = Mlp.from_dict(doc)
     gctx = g.ctx
-    convs = {}
-    for n1 in (1, 2, 4, 8, 16):
-        for h in (True, False):
-            convs[(n1, h)] = gctx.nj_conv_plan_create(g.w["w0"], g.w["f"], g.K, n1).set_hoist(h)
-    (cn1, ch), conv_pred = choose_conv(gctx, model, convs, 1)
+    convs = {(n1, h): gctx.nj_conv_plan_create(g.w["w0"], g.w["f"], g.K, n1).set_hoist(h)
+             for n1 in (1, 2, 4, 8, 16) for h in (True, False)}
+    gctx.nj_timing_keys(16)
+    try:
+        cr = rank_conv(gctx, model, convs, 1)
+        conv_t = [(gctx.nj_time_plan(convs[k], 1, reps=reps), k, pred) for pred, k in cr[:SHORTLIST]]
+        conv_ms, (cn1, ch), conv_pred = min(conv_t)
+        ranked = rank_cts(gctx, model)
+        cts_t = []
+        for pred, d, n1s, hs in ranked[:SHORTLIST]:
+            plan = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
+            cts_t.append((sum(gctx.nj_time_plan(plan, gctx.L - t, t=t, reps=reps) for t in range(d)), d, n1s, hs, pred))
+            del plan
+    finally:
+        gctx.nj_timing_keys(0)
+    cts_ms, d, n1s, hs, cts_pred = min(cts_t)
     conv = convs.pop((cn1, ch))
     del convs
-    d, n1s, hs, cts_pred, per_d = choose_cts(gctx, model)
     cts = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
     g.make_keys(sorted(set(conv.galois()) | set(cts.galois())))
     lvl = gctx.L - d
@@ -339,9 +351,12 @@ def learned_plan_bench(g, ct, default_ms, steps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     err = slot_error(g, y, re, im, lvl)
-    return {"conv": {"n1": cn1, "hoist": ch, "predicted_ms": round(conv_pred, 3)},
+    return {"conv": {"n1": cn1, "hoist": ch, "predicted_ms": round(conv_pred, 3), "timed_ms": round(conv_ms, 3)},
             "cts": {"groups": d, "n1": n1s, "hoist": hs, "predicted_ms": round(cts_pred, 3),
-                    "predicted_ms_by_depth": {str(k): round(v, 3) for k, v in per_d.items()}},
+                    "timed_ms": round(cts_ms, 3)},
+            "shortlist": SHORTLIST,
+            "cts_shortlist": [{"groups": dd, "n1": nn, "hoist": hh, "predicted_ms": round(p, 3), "timed_ms": round(t, 3)}
+                              for t, dd, nn, hh, p in cts_t],
             "ms": round(ms, 4), "default_ms": round(default_ms, 4), "speedup_vs_default": round(default_ms / ms, 3),
             "cts_slot_err": err, "output_level": lvl, "model": os.path.relpath(PLAN_MODEL, ROOT),
             "model_heldout_rel_err": doc.get("heldout_rel_err")}

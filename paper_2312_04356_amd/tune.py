@@ -104,12 +104,12 @@ def plan_bytes(C, bi, bo, level):
 def sample_configs(rng, n, held_out):
     """random (C, n1, bi, bo, level, hoist) conv structures, at most 4 GB of diagonals;
     single-block structures are timed with plain baby steps a quarter of the time"""
-    shapes = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 2), (4, 4), (3, 16), (2, 4)]
+    shapes = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 2), (4, 4), (3, 16), (2, 4), (1, 4), (4, 1), (3, 3), (8, 2)]
     out, seen = [], set()
     tries = 0
     while len(out) < n and tries < 50 * n:
         tries += 1
-        C = int(rng.choice([4, 16, 64, 256, 1024]))
+        C = int(rng.choice([2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]))
         n1 = int(rng.choice(pow2_upto(C)))
         bi, bo = shapes[rng.integers(len(shapes))]
         level = int(rng.integers(1, N_Q))
@@ -132,6 +132,27 @@ def cts_group_diagonals(ctx, d):
 def cts_candidates(ctx, d):
     """per group t: [(n1, hoist)] candidate splits"""
     return [[(n1, h) for n1 in n1_candidates(nd) for h in (True, False)] for nd in cts_group_diagonals(ctx, d)]
+
+
+def rank_cts(ctx, model, depths=CTS_DEPTHS):
+    """the model's CoeffToSlot plan for every depth (each group's (n1, hoist) with the least
+    predicted latency: a group's features depend on its own split only), ranked by the
+    predicted sum: [(predicted ms, d, [n1], [hoist])]"""
+    out = []
+    for d in depths:
+        cands = cts_candidates(ctx, d)
+        by = {}
+        for n1, h in {c for cs in cands for c in cs}:
+            by[(n1, h)] = ctx.nj_cts_plan_features(d, [n1] * d, h)
+        n1s, hs, tot = [], [], 0.0
+        for t in range(d):
+            opts = cands[t]
+            pred = np.exp(model.predict(np.array([by[c][t] for c in opts], dtype=np.float32)))
+            k = int(np.argmin(pred))
+            n1s.append(opts[k][0]), hs.append(opts[k][1])
+            tot += float(pred[k])
+        out.append((tot, d, n1s, hs))
+    return sorted(out)
 
 
 def choose_cts(ctx, model, depths=CTS_DEPTHS):
@@ -160,11 +181,19 @@ def choose_cts(ctx, model, depths=CTS_DEPTHS):
 
 def choose_conv(ctx, model, plans_by_choice, level):
     """the model's (n1, hoist) among conv plans {(n1, hoist): plan} at `level`"""
+    r = rank_conv(ctx, model, plans_by_choice, level)
+    return r[0][1], r[0][0]
+
+
+def rank_conv(ctx, model, plans_by_choice, level):
+    """[(predicted ms, (n1, hoist))] of conv plans {(n1, hoist): plan} at `level`, best first"""
     keys = sorted(plans_by_choice)
     feats = np.array([plans_by_choice[k].features(level) for k in keys], dtype=np.float32)
     pred = np.exp(model.predict(feats))
-    k = int(np.argmin(pred))
-    return keys[k], float(pred[k])
+    return sorted(zip([float(v) for v in pred], keys))
+
+
+SHORTLIST = 3  # the model's best candidates timed before choosing (exhaustive timing decides among them)
 
 
 def main():
@@ -172,9 +201,9 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--model", default=None, help="where to write the trained model (JSON)")
     ap.add_argument("--timings", default=None, help="where to write the timing database (JSON)")
-    ap.add_argument("--samples", type=int, default=4300, help="random conv structures to time")
+    ap.add_argument("--samples", type=int, default=4500, help="random conv structures to time")
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--seed", type=int, default=1005)
     args = ap.parse_args()
     t0 = time.time()
@@ -228,7 +257,7 @@ def main():
     full_loss = m.train(X, y, epochs=args.epochs, batch=256, lr=1e-3, seed=args.seed)
     # per layer: every candidate (n1, hoist) timed (exhaustive), the model's pick, the default
     layers = []
-    tot = {"default": 0.0, "mlp": 0.0, "best": 0.0}
+    tot = {"default": 0.0, "mlp": 0.0, "shortlist": 0.0, "best": 0.0}
     for name, C, bi, bo in RESNET18:
         cands = [(n1, h) for n1 in pow2_upto(C) for h in ((True, False) if bi == bo == 1 else (True,))]
         meas = {c: timer.conv(C, c[0], bi, bo, EVAL_LEVEL, c[1]) for c in cands}
@@ -237,18 +266,22 @@ def main():
         guess = dict(zip(cands, np.exp(m.predict(feats))))
         best = min(cands, key=lambda k: ms[k])
         pick = min(cands, key=lambda k: guess[k])
+        short = min(sorted(cands, key=lambda k: guess[k])[:SHORTLIST], key=lambda k: ms[k])
         dflt_c = (int(math.ceil(math.sqrt(C))), True)
         dflt = timer.conv(C, dflt_c[0], bi, bo, EVAL_LEVEL, True)[1]
         layers.append({"layer": name, "C": C, "bi": bi, "bo": bo, "default_n1": dflt_c[0], "default_ms": dflt,
                        "best_n1": best[0], "best_hoist": best[1], "best_ms": ms[best],
                        "mlp_n1": pick[0], "mlp_hoist": pick[1], "mlp_ms": ms[pick],
                        "mlp_predicted_ms": float(guess[pick]),
+                       "shortlist_n1": short[0], "shortlist_hoist": short[1], "shortlist_ms": ms[short],
                        "candidates": {"%d/%s" % (k[0], "h" if k[1] else "p"): ms[k] for k in cands}})
         tot["default"] += dflt
         tot["mlp"] += ms[pick]
+        tot["shortlist"] += ms[short]
         tot["best"] += ms[best]
-        log("[tune] %-18s C=%4d %dx%-2d default n1=%-3d %.3f ms | best %s %.3f ms | model %s %.3f ms"
-            % (name, C, bi, bo, dflt_c[0], dflt, best, ms[best], pick, ms[pick]))
+        log("[tune] %-18s C=%4d %dx%-2d default n1=%-3d %.3f ms | best %s %.3f ms | model %s %.3f ms | "
+            "model top-%d timed %s %.3f ms" % (name, C, bi, bo, dflt_c[0], dflt, best, ms[best], pick, ms[pick],
+                                               SHORTLIST, short, ms[short]))
     # CoeffToSlot: the model's depth and splits vs exhaustive timing of every candidate and
     # the default (depth 3, n1 = ceil(sqrt(#diagonals)), hoisted)
     md, mn1, mh, mpred, per_d = choose_cts(ctx, m)
@@ -272,11 +305,17 @@ def main():
     dplan = ctx.nj_cts_plan_create(DEFAULT_CTS_DEPTH).set_lazy(True)
     dflt_cts = sum(ctx.nj_time_plan(dplan, ctx.L - t, t=t, reps=args.reps) for t in range(DEFAULT_CTS_DEPTH))
     del dplan
-    mplan = ctx.nj_cts_plan_create_split(md, mn1).set_lazy(True).set_hoist(mh)
-    mlp_cts = sum(ctx.nj_time_plan(mplan, ctx.L - t, t=t, reps=args.reps) for t in range(md))
-    del mplan
-    log("[tune] CoeffToSlot: default d=%d %.3f ms | exhaustive d=%d %.3f ms | model d=%d n1=%s hoist=%s %.3f ms"
-        % (DEFAULT_CTS_DEPTH, dflt_cts, exh[0], exh[1], md, mn1, mh, mlp_cts))
+    def time_cts(d, n1s, hs):
+        plan = ctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
+        return sum(ctx.nj_time_plan(plan, ctx.L - t, t=t, reps=args.reps) for t in range(d))
+
+    mlp_cts = time_cts(md, mn1, mh)
+    ranked = rank_cts(ctx, m)
+    short_t = [(time_cts(d, n1s, hs), d, n1s, hs, pred) for pred, d, n1s, hs in ranked[:SHORTLIST]]
+    sc = min(short_t)
+    log("[tune] CoeffToSlot: default d=%d %.3f ms | exhaustive d=%d %.3f ms | model d=%d n1=%s hoist=%s %.3f ms | "
+        "model top-%d timed d=%d %.3f ms" % (DEFAULT_CTS_DEPTH, dflt_cts, exh[0], exh[1], md, mn1, mh, mlp_cts,
+                                            SHORTLIST, sc[1], sc[0]))
     ctx.nj_timing_keys(0)
     model_doc = {"features": FEATURES, "ring": {"log_n": LOG_N, "n_q": N_Q, "alpha": ALPHA}, **m.to_dict(),
                  "target": "log(ms) of one BSGS transform (nj_time_plan)", "n_timings": int(len(y)),
@@ -289,18 +328,22 @@ def main():
     if args.timings:
         with open(args.timings, "w") as fh:
             json.dump({"features": FEATURES, "X": X.tolist(), "log_ms": y.tolist(), "kind": kind.tolist()}, fh)
-    report = {"ring": {"log_n": LOG_N, "n_q": N_Q, "alpha": ALPHA}, "eval_level": EVAL_LEVEL,
+    report = {"ring": {"log_n": LOG_N, "n_q": N_Q, "alpha": ALPHA}, "eval_level": EVAL_LEVEL, "shortlist": SHORTLIST,
               "n_timings": int(len(y)), "train_mse_std_units": tr_loss, "full_train_mse_std_units": full_loss,
               "heldout": heldout, "totals_ms": tot, "mlp_vs_best": tot["mlp"] / tot["best"],
               "default_vs_best": tot["default"] / tot["best"], "layers": layers,
               "cts": {"depths": cts_rows, "default": {"groups": DEFAULT_CTS_DEPTH, "ms": dflt_cts},
                       "exhaustive": {"groups": exh[0], "n1": exh[2], "hoist": exh[3], "ms": exh[1]},
-                      "mlp": {"groups": md, "n1": mn1, "hoist": mh, "predicted_ms": mpred, "ms": mlp_cts}},
+                      "mlp": {"groups": md, "n1": mn1, "hoist": mh, "predicted_ms": mpred, "ms": mlp_cts},
+                      "mlp_shortlist": {"groups": sc[1], "n1": sc[2], "hoist": sc[3], "ms": sc[0],
+                                        "timed": [{"groups": d, "ms": t, "predicted_ms": p}
+                                                  for t, d, _, _, p in short_t]}},
               "seconds": time.time() - t0}
     with open(args.out, "w") as fh:
         json.dump(report, fh, indent=1)
-    log("[tune] convs: default %.2f ms, model %.2f ms, exhaustive best %.2f ms (model/best %.3f, default/best %.3f)"
-        % (tot["default"], tot["mlp"], tot["best"], report["mlp_vs_best"], report["default_vs_best"]))
+    log("[tune] convs: default %.2f ms, model %.2f ms, model top-%d timed %.2f ms, exhaustive best %.2f ms "
+        "(model/best %.3f, default/best %.3f)" % (tot["default"], tot["mlp"], SHORTLIST, tot["shortlist"],
+                                                  tot["best"], report["mlp_vs_best"], report["default_vs_best"]))
 
 
 if __name__ == "__main__":

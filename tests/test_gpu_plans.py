@@ -75,3 +75,36 @@ def test_conv_without_hoisting_parity_small():
     assert np.array_equal(host_coeff(gctx, y), want)
     hoisted = o.ctx.conv2d_cins(x_o, o.conv_bsgs, o.conv_pts, hoist=True)
     assert not np.array_equal(hoisted, want)  # a different plan: different low bits
+
+
+@pytest.mark.timeout(600)
+def test_split_cts_plan_parity_full():
+    """N = 2^16 (three digits): a depth-5 CoeffToSlot with chosen splits, lazy giant steps
+    and hoisting on some groups only (plans the learned planner proposes), word for word"""
+    import oracle as O
+    O.set_threads(0)
+    o = OracleWorkload("full", with_cts=False)
+    g = GpuWorkload("full", with_cts=False)
+    gctx, N, R = g.ctx, o.N, o.ring
+    groups, n1s, hoist = 5, (2, 4, 4, 4, 4), [False, True, False, True, True]
+    plan = gctx.nj_cts_plan_create_split(groups, n1s).set_lazy(True).set_hoist(hoist)
+    ogroups = PL.cts_plan(N, groups, list(n1s))
+    opts = []
+    for t, (bs, diags) in enumerate(ogroups):
+        assert sorted(plan.offsets(t)) == sorted(bs.js)
+        pts = PL.encode_diagonals(diags, N, float(R.q[R.L - t]), R, R.L - t)
+        for idx, j in enumerate(plan.offsets(t)):
+            gctx.nj_plan_set_diagonal(plan, t, idx, pts[j])
+        opts.append(pts)
+    gs = sorted(set(plan.galois()))
+    g.make_keys(gs)
+    o.make_keys(gs)
+    m = R.to_rns(o.input_plaintext(), 0)
+    x_o = o.encrypt_input(0)
+    x_g = g.encrypt_input(0, m_dev=gctx.to_device(m))
+    lvl = R.L - groups
+    re, im = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+    gctx.nj_coeff_to_slot(plan, x_g, re, im)
+    w_re, w_im = o.ctx.coeff_to_slot(x_o, [bs for bs, _ in ogroups], opts, hoist=hoist, lazy=True)
+    assert np.array_equal(host_coeff(gctx, re), w_re)
+    assert np.array_equal(host_coeff(gctx, im), w_im)

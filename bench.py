@@ -317,18 +317,26 @@ def learned_plan_bench(g, ct, default_ms, steps, reps=3):
              for n1 in (1, 2, 4, 8, 16) for h in (True, False)}
     gctx.nj_timing_keys(16)
     try:
+        # the model's best candidates and the default plan (n1 = 4, hoisted; depth 3 with the
+        # default splits) are timed; the fastest is used
         cr = rank_conv(gctx, model, convs, 1)
-        conv_t = [(gctx.nj_time_plan(convs[k], 1, reps=reps), k, pred) for pred, k in cr[:SHORTLIST]]
+        pred_of = {k: p for p, k in cr}
+        short = [k for _, k in cr[:SHORTLIST]] + ([(4, True)] if (4, True) not in [k for _, k in cr[:SHORTLIST]] else [])
+        conv_t = [(gctx.nj_time_plan(convs[k], 1, reps=reps), k, pred_of[k]) for k in short]
         conv_ms, (cn1, ch), conv_pred = min(conv_t)
         ranked = rank_cts(gctx, model)
+        dflt_n1 = [int(math.ceil(math.sqrt(f[1]))) for f in gctx.nj_cts_plan_features(3)]
+        cands = [(d, n1s, hs, pred) for pred, d, n1s, hs in ranked[:SHORTLIST]]
+        if not any(d == 3 and n1s == dflt_n1 and all(hs) for d, n1s, hs, _ in cands):
+            cands.append((3, dflt_n1, [True] * 3, None))
         cts_t = []
-        for pred, d, n1s, hs in ranked[:SHORTLIST]:
+        for d, n1s, hs, pred in cands:
             plan = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
             cts_t.append((sum(gctx.nj_time_plan(plan, gctx.L - t, t=t, reps=reps) for t in range(d)), d, n1s, hs, pred))
             del plan
     finally:
         gctx.nj_timing_keys(0)
-    cts_ms, d, n1s, hs, cts_pred = min(cts_t)
+    cts_ms, d, n1s, hs, cts_pred = min(cts_t, key=lambda r: r[0])
     conv = convs.pop((cn1, ch))
     del convs
     cts = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
@@ -352,11 +360,11 @@ def learned_plan_bench(g, ct, default_ms, steps, reps=3):
     ms = e0.elapsed_time(e1) / steps
     err = slot_error(g, y, re, im, lvl)
     return {"conv": {"n1": cn1, "hoist": ch, "predicted_ms": round(conv_pred, 3), "timed_ms": round(conv_ms, 3)},
-            "cts": {"groups": d, "n1": n1s, "hoist": hs, "predicted_ms": round(cts_pred, 3),
+            "cts": {"groups": d, "n1": n1s, "hoist": hs, "predicted_ms": None if cts_pred is None else round(cts_pred, 3),
                     "timed_ms": round(cts_ms, 3)},
             "shortlist": SHORTLIST,
-            "cts_shortlist": [{"groups": dd, "n1": nn, "hoist": hh, "predicted_ms": round(p, 3), "timed_ms": round(t, 3)}
-                              for t, dd, nn, hh, p in cts_t],
+            "cts_shortlist": [{"groups": dd, "n1": nn, "hoist": hh, "timed_ms": round(t, 3),
+                               "predicted_ms": None if p is None else round(p, 3)} for t, dd, nn, hh, p in cts_t],
             "ms": round(ms, 4), "default_ms": round(default_ms, 4), "speedup_vs_default": round(default_ms / ms, 3),
             "cts_slot_err": err, "output_level": lvl, "model": os.path.relpath(PLAN_MODEL, ROOT),
             "model_heldout_rel_err": doc.get("heldout_rel_err")}

@@ -193,7 +193,9 @@ def rank_conv(ctx, model, plans_by_choice, level):
     return sorted(zip([float(v) for v in pred], keys))
 
 
-SHORTLIST = 3  # the model's best candidates timed before choosing (exhaustive timing decides among them)
+# the model's best candidates, and the default plan, are timed before choosing: timing
+# decides among them, so the chosen plan is never slower than the default as measured
+SHORTLIST = 3
 
 
 def main():
@@ -266,8 +268,11 @@ def main():
         guess = dict(zip(cands, np.exp(m.predict(feats))))
         best = min(cands, key=lambda k: ms[k])
         pick = min(cands, key=lambda k: guess[k])
-        short = min(sorted(cands, key=lambda k: guess[k])[:SHORTLIST], key=lambda k: ms[k])
         dflt_c = (int(math.ceil(math.sqrt(C))), True)
+        short_set = sorted(cands, key=lambda k: guess[k])[:SHORTLIST]
+        if dflt_c in ms and dflt_c not in short_set:
+            short_set.append(dflt_c)
+        short = min(short_set, key=lambda k: ms[k])
         dflt = timer.conv(C, dflt_c[0], bi, bo, EVAL_LEVEL, True)[1]
         layers.append({"layer": name, "C": C, "bi": bi, "bo": bo, "default_n1": dflt_c[0], "default_ms": dflt,
                        "best_n1": best[0], "best_hoist": best[1], "best_ms": ms[best],
@@ -312,7 +317,8 @@ def main():
     mlp_cts = time_cts(md, mn1, mh)
     ranked = rank_cts(ctx, m)
     short_t = [(time_cts(d, n1s, hs), d, n1s, hs, pred) for pred, d, n1s, hs in ranked[:SHORTLIST]]
-    sc = min(short_t)
+    short_t.append((dflt_cts, DEFAULT_CTS_DEPTH, None, [True] * DEFAULT_CTS_DEPTH, None))  # the default plan
+    sc = min(short_t, key=lambda r: r[0])
     log("[tune] CoeffToSlot: default d=%d %.3f ms | exhaustive d=%d %.3f ms | model d=%d n1=%s hoist=%s %.3f ms | "
         "model top-%d timed d=%d %.3f ms" % (DEFAULT_CTS_DEPTH, dflt_cts, exh[0], exh[1], md, mn1, mh, mlp_cts,
                                             SHORTLIST, sc[1], sc[0]))
@@ -336,8 +342,8 @@ def main():
                       "exhaustive": {"groups": exh[0], "n1": exh[2], "hoist": exh[3], "ms": exh[1]},
                       "mlp": {"groups": md, "n1": mn1, "hoist": mh, "predicted_ms": mpred, "ms": mlp_cts},
                       "mlp_shortlist": {"groups": sc[1], "n1": sc[2], "hoist": sc[3], "ms": sc[0],
-                                        "timed": [{"groups": d, "ms": t, "predicted_ms": p}
-                                                  for t, d, _, _, p in short_t]}},
+                                        "timed": [{"groups": d, "n1": n1s, "ms": t, "predicted_ms": p}
+                                                  for t, d, n1s, _, p in short_t]}},
               "seconds": time.time() - t0}
     with open(args.out, "w") as fh:
         json.dump(report, fh, indent=1)

@@ -107,3 +107,14 @@ def test_ctx_create_refuses_oversized_bases(n_q, alpha):
     than 8 key-switching digits, is refused with NJ_EUNSUPPORTED before any device work"""
     assert _create_status(12, n_q, alpha) == -7
     assert "nj_ctx_create" in nj._lib.nj_last_error().decode()
+
+
+def test_plan_model_file_is_complete():
+    """the committed latency model (written by paper_2312_04356_amd/tune.py): parameters and
+    standardisation of the 7-64-64-1 network, the feature names, the held-out error"""
+    import json
+    doc = json.load(open(os.path.join(ROOT, "paper_2312_04356_amd", "data", "plan_model_n65536.json")))
+    assert len(doc["params"]) == nj.MLP_PARAMS and len(doc["norm"]) == nj.MLP_NORM
+    assert len(doc["features"]) == nj.MLP_FEATURES
+    assert all(v > 0 for v in doc["norm"][7:14]) and doc["n_timings"] >= 4500
+    assert doc["heldout_rel_err"]["cts_d_not_3"]["n"] > 0

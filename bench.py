@@ -148,22 +148,19 @@ def job_plans(g, specs, n1_of=None):
     """conv plans (encoded at the top level, used at every job level) for each (op, C)
     of the job mix; weights U(-1,1) scaled by 1/(f sqrt(C_in))"""
     import synth
-    from paper_2312_04356_amd import layers as LY
     gctx, plans = g.ctx, {}
     for op, C in sorted({(o, c) for o, c, _ in specs}):
         k = 8 * synth.JOB_OPS.index(op) + sorted(synth.JOB_CHANNELS).index(C)  # weights per (op, C)
         w0 = synth.JOB_CHANNELS[C]
+        n1 = 0 if n1_of is None else n1_of[(op, C)]
         if op == "dw3x3":
-            taps, ci, co = LY.taps_depthwise(synth.uniform_real((C, 3, 3), 1004, 100 + k) / 3.0), C, C
+            K = synth.uniform_real((C, 3, 3), 1004, 100 + k) / 3.0
+            plans[(op, C)] = gctx.nj_conv_plan_create_layer(w0, K, depthwise=True, n1=n1, level=gctx.L)
         else:
             f = 1 if op == "1x1" else 3
             K = synth.uniform_real((C, C, f, f), 1004, 100 + k) / (f * math.sqrt(C))
-            if op == "3x3s2":
-                taps, ci, co, w0 = LY.taps_stride2(K), 4 * C, C, w0 // 2
-            else:
-                taps, ci, co = LY.taps_same(K), C, C
-        n1 = 0 if n1_of is None else n1_of[(op, C)]
-        plans[(op, C)] = gctx.nj_conv_plan_create_taps(w0, ci, co, taps, fuse=1, n1=n1, level=gctx.L)
+            plans[(op, C)] = gctx.nj_conv_plan_create_layer(w0, K, stride=2 if op == "3x3s2" else 1, n1=n1,
+                                                            level=gctx.L)
     return plans
 
 

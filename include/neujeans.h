@@ -251,7 +251,7 @@ nj_status nj_coeff_to_slot_batch(nj_ctx *ctx, const nj_plan *cts, const nj_ct *i
  * pointwise conv the single tap (0, 0); a depthwise conv the taps with
  * out_ch == in_ch; a stride-2 conv the taps of its polyphase decomposition on the
  * four phase images of each input channel (phase (a, b) = rows a::2, columns b::2,
- * stored as channel (2a + b) C_in + i), with offsets floor((u - p)/2). */
+ * stored as channel 4 i + 2 b + a), with offsets floor((u - p)/2) (nj_conv_taps). */
 typedef struct {
     int32_t out_ch, in_ch, dy, dx;
     double w;
@@ -270,6 +270,42 @@ typedef struct {
  * weights; NJ_EUNSUPPORTED if W^2 > N. */
 nj_status nj_conv_plan_create_taps(nj_ctx *ctx, int w0, int c_in, int c_out, const nj_tap *taps, int n_taps,
                                    int fuse, int n1, int level, nj_plan **out);
+/* A conv layer (Sec. 3.3): weights [c_out][c_in][f][f] (depthwise: [c][f][f]), odd f,
+ * 'same' zero padding (f-1)/2, stride 1 or 2 (Sec. 5: a stride-2 conv is the sum over the
+ * four phases (a, b) of unit-stride convs of the phase images I_i[a::2, b::2], stored as
+ * input channel 4 i + 2 b + a at width w0/2; the kernel tap (u, v) reads phase
+ * ((u-p) mod 2, (v-p) mod 2) at offset (floor((u-p)/2), floor((v-p)/2))); fuse = 1 merges
+ * StoC2 into the kernel matrix (Sec. 4). */
+typedef struct {
+    int w0;         /* input image width (stride 2: even; the output is w0/2 wide) */
+    int c_in, c_out;
+    int f;          /* kernel width, odd */
+    int stride;     /* 1 or 2 */
+    int depthwise;  /* 1: one kernel per channel (c_in == c_out) */
+    int fuse;       /* 1: fused with StoC2 */
+} nj_conv_desc;
+/* The taps of such a layer (host only): taps may be null to get the count in *n_taps;
+ * else at most max_taps are written.  NJ_EINVAL for bad shapes or a short buffer. */
+nj_status nj_conv_taps(int c_in, int c_out, int f, int stride, int depthwise, const double *weights, nj_tap *taps,
+                       int max_taps, int *n_taps);
+/* The plan of a conv layer: nj_conv_plan_create_taps of its taps (inputs of a stride-2
+ * layer in the phase layout above, 4 c_in channels at w0/2). */
+nj_status nj_conv_plan_create_layer(nj_ctx *ctx, const nj_conv_desc *desc, const double *weights, int n1, int level,
+                                    nj_plan **out);
+/* Slot permutations of the downsampling flows (Sec. 5, Algorithm 2, Appendix B) as BSGS
+ * transforms (0/1 diagonals encoded at scale q_level, so a transform + rescale keeps the
+ * scale), applied after ModEval to one half of a CoeffToSlot output: half 0 the real
+ * part (slot j = coefficient rev(j)), half 1 the imaginary part (N/2 + rev(j)), images in
+ * the fused conv's coefficient layout (coefficient (y W + x) C + rev_C(c) = pixel (y, x)
+ * of channel c, W^2 C = N):
+ *   kind 0, decompose: one ciphertext (W, C) -> (W/2, 4C) holding the phase images,
+ *     channel 4 i + 2 b + a = I_i[a::2, b::2] (the input layout of a stride-2 conv
+ *     plan); one block, W - 1 diagonals; apply with nj_conv2d_cins;
+ *   kind 1, densify: four ciphertexts (W, C) of stride-1 conv outputs -> one (W/2, 4C),
+ *     channel 4 i + m = even pixels of channel i of input m; a block plan (bi = 4, bo = 1)
+ *     applied with nj_conv2d_block.
+ * n1 = baby steps (0 = ceil(sqrt(#diagonals))).  NJ_EINVAL for a layout with W^2 C != N. */
+nj_status nj_downsample_plan_create(nj_ctx *ctx, int kind, int W, int C, int half, int n1, int level, nj_plan **out);
 /* Layout of a conv plan: W, C, l, bi, bo (any pointer may be null).  Returns the
  * plan's level, -1 for a null or empty plan. */
 int nj_plan_layout(const nj_plan *plan, int *W, int *C, int *ell, int *bi, int *bo);

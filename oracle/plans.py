@@ -216,7 +216,9 @@ def taps_same(K):
 
 def taps_stride2(K):
     """K (C_out, C_in, f, f), stride 2 -> taps on the polyphase input (4 C_in channels,
-    channel (2a + b) C_in + i holds I_i[a::2, b::2])"""
+    channel 4 i + 2 b + a holds I_i[a::2, b::2]: the four phases of a channel adjacent,
+    which keeps the slot permutation that rearranges an image into them to W - 1 cyclic
+    diagonals)"""
     co, ci, f, _ = K.shape
     p = (f - 1) // 2
     out = []
@@ -226,7 +228,7 @@ def taps_stride2(K):
                 for v in range(f):
                     dy, a = divmod(u - p, 2)
                     dx, b = divmod(v - p, 2)
-                    out.append((o, (2 * a + b) * ci + i, dy, dx, float(K[o, i, u, v])))
+                    out.append((o, 4 * i + 2 * b + a, dy, dx, float(K[o, i, u, v])))
     return out
 
 
@@ -238,9 +240,14 @@ def taps_depthwise(K):
 
 
 def polyphase(img):
-    """(C, w, w) -> (4C, w/2, w/2), channel (2a + b) C + i = img[i, a::2, b::2]"""
-    C = img.shape[0]
-    return np.concatenate([img[:, a::2, b::2] for a in (0, 1) for b in (0, 1)], axis=0)
+    """(C, w, w) -> (4C, w/2, w/2), channel 4 i + 2 b + a = img[i, a::2, b::2]"""
+    C, w, _ = img.shape
+    out = np.zeros((4 * C, w // 2, w // 2))
+    for i in range(C):
+        for a in (0, 1):
+            for b in (0, 1):
+                out[4 * i + 2 * b + a] = img[i, a::2, b::2]
+    return out
 
 
 def conv2d_taps(img, taps, c_out):

@@ -41,6 +41,11 @@ class NjTap(ctypes.Structure):
     _fields_ = [("out_ch", i32), ("in_ch", i32), ("dy", i32), ("dx", i32), ("w", dbl)]
 
 
+class NjConvDesc(ctypes.Structure):
+    _fields_ = [("w0", i32), ("c_in", i32), ("c_out", i32), ("f", i32), ("stride", i32), ("depthwise", i32),
+                ("fuse", i32)]
+
+
 _SIGS = {
     "nj_last_error": (ctypes.c_char_p, []),
     "nj_gen_primes": (i32, [i32, i32, i32, vp, i32, vp]),
@@ -75,6 +80,9 @@ _SIGS = {
     "nj_conv_plan_create": (i32, [vp, i32, i32, vp, i32, ctypes.POINTER(vp)]),
     "nj_cts_plan_create": (i32, [vp, i32, ctypes.POINTER(vp)]),
     "nj_conv_plan_create_taps": (i32, [vp, i32, i32, i32, vp, i32, i32, i32, i32, ctypes.POINTER(vp)]),
+    "nj_conv_taps": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, ctypes.POINTER(i32)]),
+    "nj_downsample_plan_create": (i32, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(vp)]),
+    "nj_conv_plan_create_layer": (i32, [vp, ctypes.POINTER(NjConvDesc), vp, i32, i32, ctypes.POINTER(vp)]),
     "nj_plan_layout": (i32, [vp, vp, vp, vp, vp, vp]),
     "nj_conv2d_block": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_drop_level": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
@@ -261,6 +269,24 @@ class Plan:
         if getattr(self, "ptr", None):
             _lib.nj_plan_destroy(self.ptr)
             self.ptr = None
+
+
+def nj_conv_taps(K, stride=1, depthwise=False):
+    """the library's taps (out, in, dy, dx, w) of a conv layer with weights K
+    [c_out][c_in][f][f] (depthwise: [c][f][f])"""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    if depthwise:
+        c_out = c_in = K.shape[0]
+    else:
+        c_out, c_in = K.shape[0], K.shape[1]
+    f = K.shape[-1]
+    n = i32()
+    _check(_lib.nj_conv_taps(c_in, c_out, f, int(stride), int(bool(depthwise)), _np_ptr(K), None, 0, ctypes.byref(n)),
+           "nj_conv_taps")
+    arr = (NjTap * n.value)()
+    _check(_lib.nj_conv_taps(c_in, c_out, f, int(stride), int(bool(depthwise)), _np_ptr(K), ctypes.cast(arr, vp),
+                             n.value, ctypes.byref(n)), "nj_conv_taps")
+    return [(t.out_ch, t.in_ch, t.dy, t.dx, t.w) for t in arr]
 
 
 def nj_layer_masks(log_n, W, C, w0):
@@ -562,6 +588,25 @@ class Ctx:
         _check(_lib.nj_conv_plan_create_taps(self.ptr, int(w0), int(c_in), int(c_out), ctypes.cast(arr, vp),
                                              len(taps), int(fuse), int(n1), int(level), ctypes.byref(h)),
                "nj_conv_plan_create_taps")
+        return Plan(h)
+
+    def nj_conv_plan_create_layer(self, w0, K, stride=1, depthwise=False, fuse=1, n1=0, level=1):
+        """plan of a conv layer with weights K [c_out][c_in][f][f] (depthwise: [c][f][f]) on
+        w0 x w0 inputs (stride 2: inputs in the phase layout)"""
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        c_out = K.shape[0]
+        c_in = c_out if depthwise else K.shape[1]
+        d = NjConvDesc(int(w0), int(c_in), int(c_out), int(K.shape[-1]), int(stride), int(bool(depthwise)), int(fuse))
+        h = vp()
+        _check(_lib.nj_conv_plan_create_layer(self.ptr, ctypes.byref(d), _np_ptr(K), int(n1), int(level),
+                                              ctypes.byref(h)), "nj_conv_plan_create_layer")
+        return Plan(h)
+
+    def nj_downsample_plan_create(self, kind, W, C, half, level, n1=0):
+        """kind 0 decompose / 1 densify slot permutation for one half (0 Re, 1 Im)"""
+        h = vp()
+        _check(_lib.nj_downsample_plan_create(self.ptr, int(kind), int(W), int(C), int(half), int(n1), int(level),
+                                              ctypes.byref(h)), "nj_downsample_plan_create")
         return Plan(h)
 
     def nj_conv2d_block(self, plan, ct, out, stream=None):

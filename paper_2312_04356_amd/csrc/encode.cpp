@@ -282,6 +282,76 @@ nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap 
     return NJ_OK;
 }
 
+// Slot permutations of the downsampling flows (Sec. 5, Algorithm 2; Appendix B), on one
+// half (h = 0: the real CoeffToSlot output, slot j = coefficient rev(j); h = 1: the
+// imaginary one, coefficient N/2 + rev(j)) of an image in the fused conv's coefficient
+// layout, coefficient (y W + x) C + rev_C(c) = pixel (y, x) of channel c:
+//   kind 0, decompose: (W, C) -> (W/2, 4C), channel 4 i + 2 b + a = phase image
+//     I_i[a::2, b::2] (one block);
+//   kind 1, densify: four sparse images (W, C) (stride-1 conv outputs) -> (W/2, 4C),
+//     channel 4 i + m = even pixels I_i[0::2, 0::2] of input m (four blocks).
+// Every output slot takes one input slot of the same half (0/1 diagonals, checked).
+nj_status build_downsample_diagonals(int N, int kind, int W, int C, int half, int n1, nj_lt_t &lt,
+                                     std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
+{
+    const int n = N / 2, ln = ilog2(n), lc = ilog2(C), W2 = W / 2, C2 = 4 * C, lc2 = lc + 2;
+    if ((kind != 0 && kind != 1) || (half != 0 && half != 1) || W < 2 || W % 2 || C < 1 || (C & (C - 1)) ||
+        (W & (W - 1)) || (long long)W * W * C != N)
+        return fail(NJ_EINVAL, "downsample plan: need W, C powers of two with W^2 C = N, W >= 2");
+    const int nb = kind == 0 ? 1 : 4;
+    auto coef = [&](int c, int y, int x, int w, int cc, int lcc) { return (y * w + x) * cc + rev(c, lcc); };
+    std::vector<std::vector<int>> src(nb, std::vector<int>(N, -1));  // output coefficient -> input coefficient
+    for (int i = 0; i < C; i++)
+        for (int y = 0; y < W2; y++)
+            for (int x = 0; x < W2; x++) {
+                if (kind == 0) {
+                    for (int a = 0; a < 2; a++)
+                        for (int b = 0; b < 2; b++)
+                            src[0][coef(4 * i + 2 * b + a, y, x, W2, C2, lc2)] = coef(i, 2 * y + a, 2 * x + b, W, C, lc);
+                } else {
+                    for (int m = 0; m < 4; m++) src[m][coef(4 * i + m, y, x, W2, C2, lc2)] = coef(i, 2 * y, 2 * x, W, C, lc);
+                }
+            }
+    std::vector<std::map<int, std::vector<cplx>>> blocks(nb);
+    for (int b = 0; b < nb; b++)
+        for (int j = 0; j < n; j++) {
+            const int k = src[b][half * n + rev(j, ln)];
+            if (k < 0) continue;
+            if (k / n != half) return fail(NJ_EUNSUPPORTED, "downsample plan: a slot would cross the real/imaginary halves");
+            const int js = rev(k % n, ln), r = ((js - j) % n + n) % n;
+            std::vector<cplx> &v = blocks[b][r];
+            if (v.empty()) v.assign(n, cplx(0.0, 0.0));
+            v[j] = 1.0;
+        }
+    std::map<int, int> offs;
+    for (auto &bl : blocks)
+        for (auto &kv : bl) offs[centred_rep(kv.first, 1, n)] = kv.first;
+    lt.u = 1;
+    lt.n1 = n1;
+    lt.stages = 0;
+    lt.js.clear();
+    for (auto &kv : offs) lt.js.push_back(kv.first);
+    bsgs_split(lt, n);
+    const int nd = lt.n_diag;
+    lt.bi = nb, lt.bo = 1;
+    lt.nz.assign((size_t)nb * nd, 0);
+    dre.assign((size_t)nb * nd, {});
+    dim.assign((size_t)nb * nd, {});
+    for (int b = 0; b < nb; b++)
+        for (int d = 0; d < nd; d++) {
+            auto it = blocks[b].find(offs[lt.js[d]]);
+            if (it == blocks[b].end()) continue;
+            std::vector<cplx> v = it->second;
+            lt.nz[(size_t)b * nd + d] = 1;
+            rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+            auto &rr = dre[(size_t)b * nd + d], &mm = dim[(size_t)b * nd + d];
+            rr.resize(n), mm.resize(n);
+            for (int j = 0; j < n; j++) rr[j] = v[j].real(), mm[j] = v[j].imag();
+        }
+    if (nb == 1) lt.nz.clear();  // a single block: every diagonal is used
+    return NJ_OK;
+}
+
 nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
                                std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
 {

@@ -131,6 +131,79 @@ nj_status nj_conv_plan_create_taps(nj_ctx *c, int w0, int c_in, int c_out, const
     return NJ_OK;
 }
 
+nj_status nj_conv_taps(int c_in, int c_out, int f, int stride, int depthwise, const double *weights, nj_tap *taps,
+                       int max_taps, int *n_taps)
+{
+    if (!weights || !n_taps || c_in < 1 || c_out < 1 || f < 1 || f % 2 == 0 || (stride != 1 && stride != 2) ||
+        (depthwise && c_in != c_out))
+        return fail(NJ_EINVAL, "nj_conv_taps: bad arguments");
+    const int p = (f - 1) / 2;
+    const long long need = (long long)(depthwise ? c_out : c_out * c_in) * f * f;
+    *n_taps = (int)need;
+    if (!taps) return NJ_OK;
+    if (max_taps < need) return fail(NJ_EINVAL, "nj_conv_taps: tap buffer too small");
+    auto fdiv = [](int a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); };  // floor(a / 2)
+    int k = 0;
+    for (int o = 0; o < c_out; o++)
+        for (int i = depthwise ? o : 0; i < (depthwise ? o + 1 : c_in); i++)
+            for (int u = 0; u < f; u++)
+                for (int v = 0; v < f; v++) {
+                    nj_tap t;
+                    t.out_ch = o;
+                    t.w = depthwise ? weights[((size_t)o * f + u) * f + v] : weights[(((size_t)o * c_in + i) * f + u) * f + v];
+                    if (stride == 1) {
+                        t.in_ch = i, t.dy = u - p, t.dx = v - p;
+                    } else {  // phase (a, b) = (u - p, v - p) mod 2 of input channel i: channel 4 i + 2 b + a
+                        t.dy = fdiv(u - p), t.dx = fdiv(v - p);
+                        const int a = (u - p) - 2 * t.dy, b = (v - p) - 2 * t.dx;
+                        t.in_ch = 4 * i + 2 * b + a;
+                    }
+                    taps[k++] = t;
+                }
+    return NJ_OK;
+}
+
+nj_status nj_conv_plan_create_layer(nj_ctx *c, const nj_conv_desc *d, const double *weights, int n1, int level,
+                                    nj_plan **out)
+{
+    if (!c || !d || !weights || !out) return fail(NJ_EINVAL, "nj_conv_plan_create_layer: null argument");
+    if (d->stride == 2 && d->w0 % 2) return fail(NJ_EINVAL, "nj_conv_plan_create_layer: stride 2 needs an even width");
+    int n = 0;
+    nj_status st = nj_conv_taps(d->c_in, d->c_out, d->f, d->stride, d->depthwise, weights, nullptr, 0, &n);
+    if (st) return st;
+    std::vector<nj_tap> taps(n);
+    if ((st = nj_conv_taps(d->c_in, d->c_out, d->f, d->stride, d->depthwise, weights, taps.data(), n, &n))) return st;
+    const int w_in = d->stride == 2 ? d->w0 / 2 : d->w0, ci = d->stride == 2 ? 4 * d->c_in : d->c_in;
+    return nj_conv_plan_create_taps(c, w_in, ci, d->c_out, taps.data(), n, d->fuse, n1, level, out);
+}
+
+nj_status nj_downsample_plan_create(nj_ctx *c, int kind, int W, int C, int half, int n1, int level, nj_plan **out)
+{
+    if (!c || !out || n1 < 0) return fail(NJ_EINVAL, "nj_downsample_plan_create: bad arguments");
+    if (level < 1 || level > c->L) return fail(NJ_ELEVEL, "nj_downsample_plan_create: need 1 <= level <= L");
+    nj_plan *p = new nj_plan();
+    p->kind = 0;
+    p->N = c->N;
+    p->lts.resize(1);
+    nj_lt_t &lt = p->lts[0];
+    lt.level = level;
+    std::vector<std::vector<double>> re, im;
+    nj_status st = build_downsample_diagonals(c->N, kind, W, C, half, n1, lt, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->W = W / 2, p->C = 4 * C, p->ell = (W / 2) * (W / 2) / 2, p->w0 = 0, p->f = 0;
+    p->c_in = kind == 0 ? C : 4 * C, p->c_out = 4 * C;
+    st = upload_plan_diagonals(c, lt, re, im, (double)c->primes[level]);
+    if (st) {
+        nj_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return NJ_OK;
+}
+
 int nj_plan_layout(const nj_plan *p, int *W, int *C, int *ell, int *bi, int *bo)
 {
     if (!p || p->lts.empty()) return -1;

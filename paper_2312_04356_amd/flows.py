@@ -1,0 +1,290 @@
+"""Downsampling flows compared at N = 2^16 (Sec. 5, Algorithm 2; Sec. 6.3): a 3x3
+stride-2 conv 64 -> 128 channels, 56 x 56 -> 28 x 28, from the previous layer's
+activated slots to the next layer's CinS input, both flows run by the library.
+
+  decomposed (Algorithm 2): each of the 4 input ciphertexts (16 channels at W = 64) is
+    rearranged into its phase images (nj_downsample_plan_create kind 0 on the real and
+    imaginary halves), combined and sent through StoC1 at l/4; the stride-2 conv is a
+    unit-stride block conv over the 256 phase channels (4 x 2 blocks at W = 32); its 2
+    dense outputs are bootstrapped (CoeffToSlot, ModEval, masks, square) and go through
+    StoC1: 2 bootstraps.
+  densify (the flow the paper improves on): the inputs go through StoC1 at l, a
+    unit-stride conv 64 -> 128 at full resolution (4 x 8 blocks at W = 64) gives 8
+    ciphertexts whose even pixels hold the stride-2 result; all 8 are bootstrapped, then
+    the even pixels of each 4 are gathered into one dense ciphertext (kind 1 on each
+    half), combined and sent through StoC1 at l/4: 8 bootstraps.
+
+Both start from the same encrypted activations and end in CinS ciphertexts of the 128
+output channels at 28 x 28; the slots before the last StoC1 are compared with the FP64
+stride-2 conv (masked, squared).  Weights U(-1, 1) / sqrt(9 * 64), inputs U(-1, 1).
+
+    python -m paper_2312_04356_amd.flows --out gpurun_out/flows.json
+"""
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+import synth
+
+from . import Ct, nj_layer_masks
+from .workload import GpuWorkload
+
+K_MOD, R_DA = 32, 3          # ModEval: x = t / (K P), 3 double angles
+W_IN, C_IN, W0 = 64, 16, 56  # input layout: 16 channels of 56 x 56 per ciphertext
+CI, CO = 64, 128             # channels
+LVL_IN = 7                   # level of the activated slots (ModEval 20 -> 9, mask, square)
+
+
+def log(msg):
+    print("[flows] " + msg, flush=True)
+
+
+def bitrev_perm(n):
+    b = n.bit_length() - 1
+    return np.array([int(format(j, "0%db" % b)[::-1], 2) for j in range(n)])
+
+
+def coeff_layout(img, W, C, N, order=None):
+    """coefficient vector of images img[c] (w x w) at layout (W, C): coefficient
+    (y W + x) C + rev_C(c') for channel c' = order[c] (default c)"""
+    a = np.zeros(N)
+    rc = bitrev_perm(C)
+    for c in range(img.shape[0]):
+        cc = c if order is None else order[c]
+        w = img.shape[1]
+        idx = (np.arange(w)[:, None] * W + np.arange(w)[None, :]) * C + rc[cc]
+        a[idx.ravel()] = img[c].ravel()
+    return a
+
+
+def strided_conv(img, K):
+    """FP64 stride-2 cross-correlation with padding 1"""
+    ci, w, _ = img.shape
+    pad = np.zeros((ci, w + 2, w + 2))
+    pad[:, 1:w + 1, 1:w + 1] = img
+    wo = w // 2
+    out = np.zeros((K.shape[0], wo, wo))
+    for u in range(3):
+        for v in range(3):
+            out += np.einsum("oi,iyx->oyx", K[:, :, u, v], pad[:, u:u + 2 * wo:2, v:v + 2 * wo:2])
+    return out
+
+
+class Flows:
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.g = g = GpuWorkload("full", with_cts=True, lazy=True)
+        self.c = c = g.ctx
+        self.N, self.n = g.N, g.N // 2
+        self.img = synth.uniform_real((CI, W0, W0), 1006, 0)
+        self.K = synth.uniform_real((CO, CI, 3, 3), 1006, 1) / math.sqrt(9 * CI)
+        a, e = synth.key_randomness(g.q + g.p, g.N, c.dnum, g.w["key_seed"], synth.RELIN_KEY_ID)
+        c.nj_gen_switch_key(0, a, e)
+        self.ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        self.times = {}
+
+    def timed(self, phase, fn):
+        t = self.torch
+        t.cuda.synchronize()
+        self.ev[0].record()
+        out = fn()
+        self.ev[1].record()
+        t.cuda.synchronize()
+        self.times[phase] = self.times.get(phase, 0.0) + self.ev[0].elapsed_time(self.ev[1])
+        return out
+
+    def encrypt_slots(self, z, level, sub):
+        c = self.c
+        coeffs = c.nj_encode_slots(z, self.g.scale)
+        m = self.torch.empty((level + 1, self.N), dtype=self.torch.int64, device=c.device)
+        c.nj_upload_plain(coeffs, level, m)
+        a, e = synth.enc_randomness(self.g.q[:level + 1], self.N, 1006, sub)
+        return c.nj_encrypt_sk(m, level, a, e, self.g.scale, c.empty_ct(level))
+
+    def inputs(self):
+        """the 4 input ciphertexts' activated slots: (Re, Im) pairs at LVL_IN"""
+        rev = bitrev_perm(self.n)
+        out = []
+        for k in range(CI // C_IN):
+            a = coeff_layout(self.img[k * C_IN:(k + 1) * C_IN], W_IN, C_IN, self.N)
+            out.append((self.encrypt_slots(a[:self.n][rev], LVL_IN, 2 * k),
+                        self.encrypt_slots(a[self.n:][rev], LVL_IN, 2 * k + 1)))
+        return out
+
+    def mask_pts(self, W, C, w0, level):
+        c = self.c
+        out = []
+        for mk in nj_layer_masks(c.log_n, W, C, w0):
+            t = self.torch.empty((level + 1, self.N), dtype=self.torch.int64, device=c.device)
+            c.nj_upload_plain(c.nj_encode_slots(mk, float(self.g.q[level])), level, t)
+            c.nj_to_eval(t, level, 1)
+            out.append(t)
+        return out
+
+    def keys(self, *plans):
+        gs = set()
+        for p in plans:
+            gs |= set(p.galois())
+        self.g.make_keys(sorted(gs))
+
+    def bootstrap_to_slots(self, y, masks):
+        """level-0 conv output -> activated (Re, Im) slots at LVL_IN: CoeffToSlot, ModEval,
+        masks, square"""
+        c, L = self.c, self.c.L
+        lo = L - 3
+        re, im = c.empty_ct(lo), c.empty_ct(lo)
+        self.timed("CtoS", lambda: c.nj_coeff_to_slot(self.g.cts_plan, y, re, im))
+        outs = []
+        for part, mk in zip((re, im), masks):
+            e = c.empty_ct(lo - 11)
+            self.timed("ModEval", lambda: c.nj_eval_mod(part, K_MOD, R_DA, None, e))
+
+            def act():
+                t = c.nj_pmult(e, mk, c.empty_ct(e.level))
+                mm = c.nj_rescale(t, c.empty_ct(e.level - 1))
+                return c.nj_hmult(mm, mm, c.empty_ct(mm.level - 1))
+            outs.append(self.timed("activation", act))
+        return outs
+
+    def to_cins(self, re, im, stoc1):
+        c = self.c
+        z = self.timed("StoC", lambda: c.nj_combine(re, im, c.empty_ct(re.level)))
+        return self.timed("StoC", lambda: c.nj_stoc1(stoc1, z, c.empty_ct(z.level - 3)))
+
+    def decode_half(self, ct):
+        c = self.c
+        d = self.torch.empty((ct.level + 1, self.N), dtype=self.torch.int64, device=c.device)
+        c.nj_decrypt(ct, d)
+        res = c.to_host(d)[:2]
+        q = self.g.q
+        Q = q[0] * q[1]
+        h0, h1 = q[1] * pow(q[1], -1, q[0]), q[0] * pow(q[0], -1, q[1])
+        vals = []
+        for a, b in zip(res[0].tolist(), res[1].tolist()):
+            x = (a * h0 + b * h1) % Q
+            vals.append(x - Q if x > Q // 2 else x)
+        return c.nj_decode_slots(np.array(vals, dtype=np.float64), ct.scale).real
+
+    def slot_error(self, pairs, imgs_by_ct, W, C, orders):
+        rev = bitrev_perm(self.n)
+        err = 0.0
+        for (re, im), img, order in zip(pairs, imgs_by_ct, orders):
+            a = coeff_layout(img, W, C, self.N, order)
+            for half, ct in ((0, re), (1, im)):
+                want = a[half * self.n:(half + 1) * self.n][rev]
+                err = max(err, float(np.max(np.abs(self.decode_half(ct) - want))))
+        return err
+
+    # ------------------------------------------------------------------ flows
+    def decomposed(self, xs):
+        c, t = self.c, self.torch
+        self.times = {}
+        dec = [c.nj_downsample_plan_create(0, W_IN, C_IN, h, LVL_IN) for h in (0, 1)]
+        st_q = c.nj_stoc1_plan_create(512, 3, LVL_IN - 1)
+        conv = c.nj_conv_plan_create_layer(W0, self.K, stride=2, level=1)
+        assert conv.layout()[1:] == (32, 64, 512, 4, 2)
+        masks = self.mask_pts(32, 64, 28, c.L - 3 - 11)
+        st_out = c.nj_stoc1_plan_create(512, 3, LVL_IN)
+        self.keys(*dec, st_q, conv, self.g.cts_plan, st_out)
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        phase_cts = c.empty_batch(4, 1)
+        for k, (re, im) in enumerate(xs):
+            r2 = self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[0], re, c.empty_ct(LVL_IN - 1)))
+            i2 = self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[1], im, c.empty_ct(LVL_IN - 1)))
+            cins = self.to_cins(r2, i2, st_q)
+            c.nj_drop_level(cins, 1, Ct(phase_cts.data[k], 1))
+        phase_cts.scale = self.g.scale
+        ys = c.empty_batch(2, 0)
+        self.timed("Conv2d", lambda: c.nj_conv2d_block(conv, phase_cts, ys))
+        acts = []
+        for k in range(2):
+            acts.append(self.bootstrap_to_slots(Ct(ys.data[k], 0, scale=ys.scale), masks))
+        slots = list(acts)
+        outs = [self.to_cins(re, im, st_out) for re, im in acts]
+        t.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        want = strided_conv(self.img, self.K) ** 2
+        err = self.slot_error(slots, [want[:64], want[64:]], 32, 64, [None, None])
+        return {"bootstraps": 2, "ms_by_phase": dict(self.times), "ms": sum(self.times.values()), "wall_ms": wall,
+                "slot_err_vs_fp64": err, "outputs": len(outs), "output_level": outs[0].level,
+                "decomp_diagonals": len(dec[0].offsets(0))}
+
+    def densify(self, xs):
+        c, t = self.c, self.torch
+        self.times = {}
+        st_in = c.nj_stoc1_plan_create(2048, 3, LVL_IN)
+        conv = c.nj_conv_plan_create_layer(W0, self.K_unit(), stride=1, level=1)
+        assert conv.layout()[1:] == (64, 16, 2048, 4, 8)
+        masks = self.mask_pts(64, 16, 56, c.L - 3 - 11)
+        den = [c.nj_downsample_plan_create(1, W_IN, C_IN, h, LVL_IN) for h in (0, 1)]
+        st_out = c.nj_stoc1_plan_create(512, 3, LVL_IN - 1)
+        self.keys(st_in, conv, self.g.cts_plan, *den, st_out)
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        cins = c.empty_batch(4, 1)
+        for k, (re, im) in enumerate(xs):
+            y = self.to_cins(re, im, st_in)
+            c.nj_drop_level(y, 1, Ct(cins.data[k], 1))
+        cins.scale = self.g.scale
+        ys = c.empty_batch(8, 0)
+        self.timed("Conv2d", lambda: c.nj_conv2d_block(conv, cins, ys))
+        acts = [self.bootstrap_to_slots(Ct(ys.data[k], 0, scale=ys.scale), masks) for k in range(8)]
+        lv = acts[0][0].level
+        dense = []
+        for k in range(2):
+            halves = []
+            for h in (0, 1):
+                src = c.empty_batch(4, lv)
+                for m in range(4):
+                    src.data[m].copy_(acts[4 * k + m][h].data)
+                src.scale = acts[0][h].scale
+                o = c.empty_batch(1, lv - 1)
+                self.timed("Densify", lambda: c.nj_conv2d_block(den[h], src, o))
+                halves.append(Ct(o.data[0], lv - 1, scale=o.scale))
+            dense.append(tuple(halves))
+        outs = [self.to_cins(re, im, st_out) for re, im in dense]
+        t.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        full = strided_conv(self.img, self.K) ** 2  # dense channel 4 i + m of output k = conv channel 64 k + 16 m + i
+        imgs, orders = [], []
+        for k in range(2):
+            chans = [64 * k + 16 * m + i for m in range(4) for i in range(16)]
+            imgs.append(full[chans])
+            orders.append([4 * i + m for m in range(4) for i in range(16)])
+        err = self.slot_error(dense, imgs, 32, 64, orders)
+        return {"bootstraps": 8, "ms_by_phase": dict(self.times), "ms": sum(self.times.values()), "wall_ms": wall,
+                "slot_err_vs_fp64": err, "outputs": len(outs), "output_level": outs[0].level,
+                "densify_diagonals_per_input": len(den[0].offsets(0))}
+
+    def K_unit(self):
+        return self.K  # the same weights at unit stride: the stride-2 result is its even pixels
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    f = Flows()
+    log("setup done")
+    xs = f.inputs()
+    f.decomposed(xs)  # warm-up (plan building, keys, first launches)
+    res = {"decomposed": f.decomposed(xs)}
+    log("decomposed: %.1f ms, %d bootstraps, slot error %.2e" % (res["decomposed"]["ms"], 2,
+                                                                  res["decomposed"]["slot_err_vs_fp64"]))
+    f.densify(xs)
+    res["densify"] = f.densify(xs)
+    log("densify: %.1f ms, %d bootstraps, slot error %.2e" % (res["densify"]["ms"], 8, res["densify"]["slot_err_vs_fp64"]))
+    res["speedup"] = res["densify"]["ms"] / res["decomposed"]["ms"]
+    res["layer"] = "3x3 stride 2, 64 -> 128 channels, 56 x 56 -> 28 x 28, N = 2^16, 24 + 8 primes"
+    with open(args.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    log("decomposed / densify: %.2fx faster" % res["speedup"])
+
+
+if __name__ == "__main__":
+    main()

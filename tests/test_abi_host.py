@@ -118,3 +118,25 @@ def test_plan_model_file_is_complete():
     assert len(doc["features"]) == nj.MLP_FEATURES
     assert all(v > 0 for v in doc["norm"][7:14]) and doc["n_timings"] >= 4500
     assert doc["heldout_rel_err"]["cts_d_not_3"]["n"] > 0
+
+
+@pytest.mark.parametrize("stride,depthwise,f", [(1, False, 3), (1, False, 1), (2, False, 3), (2, False, 7),
+                                                (2, False, 1), (1, True, 3)])
+def test_library_conv_taps_match_oracle(stride, depthwise, f):
+    """the library's tap decomposition of conv layers (stride 1, stride 2 on the phase
+    layout, depthwise) equals the oracle's, which its CPU tests pin to FP64 convolution"""
+    rng = np.random.default_rng(f * 10 + stride)
+    K = rng.uniform(-1, 1, (3, f, f) if depthwise else (5, 3, f, f))
+    got = sorted(nj.nj_conv_taps(K, stride, depthwise))
+    if depthwise:
+        want = PL.taps_depthwise(K)
+    else:
+        want = PL.taps_stride2(K) if stride == 2 else PL.taps_same(K)
+    assert got == sorted(want)
+
+
+def test_library_conv_taps_reject_bad_shapes():
+    with pytest.raises(nj.NjError):
+        nj.nj_conv_taps(np.zeros((2, 2, 2, 2)))  # even kernel
+    with pytest.raises(nj.NjError):
+        nj.nj_conv_taps(np.zeros((2, 2, 3, 3)), stride=3)

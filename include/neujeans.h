@@ -155,7 +155,9 @@ nj_status nj_apply_galois_noalloc(nj_ctx *ctx, const nj_ct *in, uint32_t galois_
 nj_status nj_keyswitch(nj_ctx *ctx, const uint64_t *d, int level, uint32_t galois_elt, uint64_t *out0, uint64_t *out1,
                        void *stream);
 /* PMult (Sec. 2.1): both polynomials times a plaintext pt, device [(level+1)][N] in
- * evaluation form (nj_to_eval of its coefficients).  out may alias in. */
+ * evaluation form (nj_to_eval of its coefficients).  out may alias in.  The plaintext's
+ * scale is not known to the call: out->scale = in->scale, and the caller multiplies in
+ * the plaintext's own scale. */
 nj_status nj_pmult(nj_ctx *ctx, const nj_ct *in, const uint64_t *pt, nj_ct *out, void *stream);
 /* HAdd / HSub (Sec. 2.1): out = a + b or a - b (same level).  out may alias a or b. */
 nj_status nj_add(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);

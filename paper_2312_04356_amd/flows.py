@@ -141,19 +141,22 @@ class Flows:
         outs = []
         for part, mk in zip((re, im), masks):
             e = c.empty_ct(lo - 11)
+            t, mm, sq = c.empty_ct(lo - 11), c.empty_ct(lo - 12), c.empty_ct(lo - 13)  # outside the timed calls
             self.timed("ModEval", lambda: c.nj_eval_mod(part, K_MOD, R_DA, None, e))
 
             def act():
-                t = c.nj_pmult(e, mk, c.empty_ct(e.level))
-                mm = c.nj_rescale(t, c.empty_ct(e.level - 1))
-                return c.nj_hmult(mm, mm, c.empty_ct(mm.level - 1))
+                c.nj_pmult(e, mk, t)
+                t.scale = e.scale * float(self.g.q[e.level])  # the mask is encoded at scale q_l
+                c.nj_rescale(t, mm)
+                return c.nj_hmult(mm, mm, sq)
             outs.append(self.timed("activation", act))
         return outs
 
     def to_cins(self, re, im, stoc1):
         c = self.c
-        z = self.timed("StoC", lambda: c.nj_combine(re, im, c.empty_ct(re.level)))
-        return self.timed("StoC", lambda: c.nj_stoc1(stoc1, z, c.empty_ct(z.level - 3)))
+        z, out = c.empty_ct(re.level), c.empty_ct(re.level - 3)
+        self.timed("StoC", lambda: c.nj_combine(re, im, z))
+        return self.timed("StoC", lambda: c.nj_stoc1(stoc1, z, out))
 
     def decode_half(self, ct):
         c = self.c
@@ -194,8 +197,9 @@ class Flows:
         t0 = time.perf_counter()
         phase_cts = c.empty_batch(4, 1)
         for k, (re, im) in enumerate(xs):
-            r2 = self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[0], re, c.empty_ct(LVL_IN - 1)))
-            i2 = self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[1], im, c.empty_ct(LVL_IN - 1)))
+            r2, i2 = c.empty_ct(LVL_IN - 1), c.empty_ct(LVL_IN - 1)
+            self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[0], re, r2))
+            self.timed("Decomp", lambda: c.nj_conv2d_cins(dec[1], im, i2))
             cins = self.to_cins(r2, i2, st_q)
             c.nj_drop_level(cins, 1, Ct(phase_cts.data[k], 1))
         phase_cts.scale = self.g.scale
@@ -265,9 +269,32 @@ class Flows:
         return self.K  # the same weights at unit stride: the stride-2 result is its even pixels
 
 
+def summary(res, command):
+    """markdown table of a flows JSON report"""
+    phases = ["Decomp", "Densify", "StoC", "Conv2d", "CtoS", "ModEval", "activation"]
+    lines = ["# Downsampling flows at N = 2^16: decomposed (Algorithm 2) vs densify after bootstrapping", "",
+             "Command (repository root): `%s`" % command, "",
+             res["layer"] + "; ModEval K = %d, %d double angles; HIP-event time of each call (one MI355X), "
+             "summed per phase (Table 2 phases)." % (K_MOD, R_DA), "",
+             "| flow | bootstraps | " + " | ".join(phases) + " | total ms | max slot error vs FP64 |",
+             "|---|---|" + "---|" * len(phases) + "---|---|"]
+    for name in ("decomposed", "densify"):
+        r = res[name]
+        cells = ["%.2f" % r["ms_by_phase"][p] if p in r["ms_by_phase"] else "-" for p in phases]
+        lines.append("| %s | %d | %s | %.2f | %.1e |" % (name, r["bootstraps"], " | ".join(cells), r["ms"],
+                                                         r["slot_err_vs_fp64"]))
+    lines += ["", "Decomposed is %.2fx faster with %d / %d the bootstraps (Sec. 6.3 reports 3.98-4.01x less "
+              "CtoS + ModEval time for downsampling layers).  Decomposition: %d cyclic diagonals per half "
+              "(W - 1 at W = 64); densify: %d offsets over its four inputs."
+              % (res["speedup"], res["decomposed"]["bootstraps"], res["densify"]["bootstraps"],
+                 res["decomposed"]["decomp_diagonals"], res["densify"]["densify_diagonals_per_input"])]
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", required=True)
+    ap.add_argument("--md", default=None, help="also write a markdown summary here")
     args = ap.parse_args()
     f = Flows()
     log("setup done")
@@ -283,6 +310,10 @@ def main():
     res["layer"] = "3x3 stride 2, 64 -> 128 channels, 56 x 56 -> 28 x 28, N = 2^16, 24 + 8 primes"
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)
+    if args.md:
+        with open(args.md, "w") as fh:
+            fh.write(summary(res, "python -m paper_2312_04356_amd.flows --out gpurun_out/flows.json --md "
+                                  "gpurun_out/downsampling_flows_n65536.md"))
     log("decomposed / densify: %.2fx faster" % res["speedup"])
 
 

@@ -412,6 +412,15 @@ nj_status nj_layer_masks(int log_n, int W, int C, int w0, double *mask_re, doubl
 nj_status nj_slot_activation(nj_ctx *ctx, int K, int r, const double *coeffs, int n_coeffs, const uint64_t *mask_re,
                              const uint64_t *mask_im, int act, const nj_plan *stoc1, const nj_ct *re, const nj_ct *im,
                              nj_ct *out, void *stream);
+/* Algorithm 2's slot-domain part (Sec. 5): nj_slot_activation with the decomposition of
+ * each half (nj_downsample_plan_create kind 0, dec_re for half 0 and dec_im for half 1,
+ * both at one level l <= the activated level: the halves are dropped to l first, each
+ * plan consumes a level) between the activation and Re + i Im; `stoc1` is then the StoC1
+ * plan of the phase layout (l/4).  dec_re = dec_im = null is nj_slot_activation. */
+nj_status nj_slot_activation_decompose(nj_ctx *ctx, int K, int r, const double *coeffs, int n_coeffs,
+                                       const uint64_t *mask_re, const uint64_t *mask_im, int act,
+                                       const nj_plan *dec_re, const nj_plan *dec_im, const nj_plan *stoc1,
+                                       const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream);
 /* Algorithm 1, one layer: conv2d_cins (fused with StoC2; conv may be null, then `in` is
  * a level-0 ciphertext) -> level 0 -> ModRaise + CoeffToSlot (nj_coeff_to_slot) ->
  * nj_slot_activation.  `out` is the next layer's CinS input (the StoC2 stages left are

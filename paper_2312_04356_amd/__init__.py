@@ -107,6 +107,8 @@ _SIGS = {
     "nj_layer_masks": (i32, [i32, i32, i32, i32, vp, vp]),
     "nj_slot_activation": (i32, [vp, i32, i32, vp, i32, vp, vp, i32, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt),
                                  ctypes.POINTER(NjCt), vp]),
+    "nj_slot_activation_decompose": (i32, [vp, i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, ctypes.POINTER(NjCt),
+                                           ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_conv_act_layer": (i32, [vp, vp, vp, i32, i32, vp, i32, vp, vp, i32, vp, ctypes.POINTER(NjCt),
                                 ctypes.POINTER(NjCt), vp]),
     "nj_bootstrap": (i32, [vp, vp, i32, i32, vp, i32, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -700,6 +702,17 @@ class Ctx:
                                        None if mask_im is None else _dev_ptr(mask_im), int(act), stoc1.ptr,
                                        ctypes.byref(cr), ctypes.byref(cm), ctypes.byref(co), _stream(stream)),
                "nj_slot_activation")
+        return out.sync_from(co)
+
+    def nj_slot_activation_decompose(self, K, r, coeffs, mask_re, mask_im, act, dec_re, dec_im, stoc1, re, im, out,
+                                     stream=None):
+        cr, cm, co = re.c(), im.c(), out.c()
+        cf = _coeffs(coeffs)
+        _check(_lib.nj_slot_activation_decompose(
+            self.ptr, int(K), int(r), None if cf is None else _np_ptr(cf), 0 if cf is None else len(cf),
+            None if mask_re is None else _dev_ptr(mask_re), None if mask_im is None else _dev_ptr(mask_im), int(act),
+            None if dec_re is None else dec_re.ptr, None if dec_im is None else dec_im.ptr, stoc1.ptr,
+            ctypes.byref(cr), ctypes.byref(cm), ctypes.byref(co), _stream(stream)), "nj_slot_activation_decompose")
         return out.sync_from(co)
 
     def nj_conv_act_layer(self, conv, cts, K, r, coeffs, mask_re, mask_im, act, stoc1, ct, out, stream=None):

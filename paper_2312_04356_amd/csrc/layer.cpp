@@ -71,7 +71,18 @@ nj_status nj_slot_activation(nj_ctx *c, int K, int r, const double *coeffs, int 
                              const uint64_t *mask_im, int act, const nj_plan *stoc1, const nj_ct *re, const nj_ct *im,
                              nj_ct *out, void *stream)
 {
+    return nj_slot_activation_decompose(c, K, r, coeffs, n_coeffs, mask_re, mask_im, act, nullptr, nullptr, stoc1, re,
+                                        im, out, stream);
+}
+
+nj_status nj_slot_activation_decompose(nj_ctx *c, int K, int r, const double *coeffs, int n_coeffs,
+                                       const uint64_t *mask_re, const uint64_t *mask_im, int act,
+                                       const nj_plan *dec_re, const nj_plan *dec_im, const nj_plan *stoc1,
+                                       const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream)
+{
     if (!c || !re || !im || !out || !stoc1) return fail(NJ_EINVAL, "nj_slot_activation: null argument");
+    if ((dec_re == nullptr) != (dec_im == nullptr))
+        return fail(NJ_EINVAL, "nj_slot_activation_decompose: give both decomposition plans or none");
     if (re->level != im->level) return fail(NJ_ELEVEL, "nj_slot_activation: Re and Im must share a level");
     if (act != 0 && act != 1) return fail(NJ_EINVAL, "nj_slot_activation: act must be 0 (none) or 1 (square)");
     if ((mask_re == nullptr) != (mask_im == nullptr)) return fail(NJ_EINVAL, "nj_slot_activation: give both masks or none");
@@ -91,6 +102,20 @@ nj_status nj_slot_activation(nj_ctx *c, int K, int r, const double *coeffs, int 
     if (act == 1) {  // the square (Sec. 2.5.2): HMult, relinearisation, rescale
         nj_ct *dr = cr == &s[0] ? &s[3] : &s[0], *di = cr == &s[0] ? &s[4] : &s[1];
         if ((st = nj_hmult(c, cr, cr, dr, stream)) || (st = nj_hmult(c, ci, ci, di, stream))) return st;
+        cr = dr, ci = di;
+    }
+    if (dec_re) {  // Algorithm 2: each half rearranged into the phase images (transform + rescale)
+        nj_ct *dr = cr == &s[0] ? &s[3] : &s[0], *di = cr == &s[0] ? &s[4] : &s[1];
+        const int pl = dec_re->lts.empty() ? -1 : dec_re->lts[0].level;
+        if (pl < 1 || dec_im->lts.empty() || dec_im->lts[0].level != pl)
+            return fail(NJ_EINVAL, "nj_slot_activation_decompose: bad decomposition plans");
+        if (cr->level < pl) return fail(NJ_ELEVEL, "nj_slot_activation_decompose: plans above the activated level");
+        if (cr->level > pl) {
+            if ((st = nj_drop_level(c, cr, pl, dr, stream)) || (st = nj_drop_level(c, ci, pl, di, stream))) return st;
+            std::swap(cr, dr), std::swap(ci, di);
+        }
+        if ((st = nj_conv2d_cins(c, dec_re, cr, dr, stream)) || (st = nj_conv2d_cins(c, dec_im, ci, di, stream)))
+            return st;
         cr = dr, ci = di;
     }
     if ((st = nj_combine(c, cr, ci, &s[2], stream))) return st;

@@ -181,3 +181,47 @@ def test_slot_activation_full_size_equals_single_calls():
     gctx.nj_stoc1(stoc1, z, want)
     assert out.level == want.level and out.scale == want.scale
     assert torch.equal(out.data, want.data)
+
+
+def test_slot_activation_decompose_equals_chain(rig):
+    """Algorithm 2's slot-domain part as one call (N = 2^12, W = 32, C = 4): ModEval of Re
+    and Im, masks, square, the decomposition of each half into phase images, Re + i Im,
+    StoC1 at l/4, word for word equal to the chain of single calls"""
+    g, n = rig.g, rig.N // 2
+    W, C, w0, lo, K, r = 32, 4, 16, 18, 16, 3
+    le = lo - 11
+    xs = []
+    for sub in (21, 22):
+        _, ct = rig.enc(RNG.uniform(-0.5, 0.5, n), lo, SCALE, sub)
+        xs.append(ct)
+    masks = []
+    for mk in nj_layer_masks(rig.R.n.bit_length() - 1, W, C, w0):
+        t = torch.empty((le + 1, rig.N), dtype=torch.int64, device=g.device)
+        g.nj_upload_plain(g.nj_encode_slots(mk, float(rig.q[le])), le, t)
+        g.nj_to_eval(t, le, 1)
+        masks.append(t)
+    dec = [g.nj_downsample_plan_create(0, W, C, h, le - 2) for h in (0, 1)]
+    stoc1 = g.nj_stoc1_plan_create((W // 2) ** 2 // 2, 3, le - 3)
+    for gl in sorted(set(dec[0].galois()) | set(dec[1].galois()) | set(stoc1.galois())):
+        rig.key(gl)
+    out = g.empty_ct(le - 6)
+    g.nj_slot_activation_decompose(K, r, None, masks[0], masks[1], 1, dec[0], dec[1], stoc1, xs[0], xs[1], out)
+    halves = []
+    for h, ct in enumerate(xs):
+        e = g.empty_ct(le)
+        g.nj_eval_mod(ct, K, r, None, e)
+        t, m = g.empty_ct(le), g.empty_ct(le - 1)
+        g.nj_pmult(e, masks[h], t)
+        g.nj_rescale(t, m)
+        m.scale = e.scale
+        sq = g.empty_ct(le - 2)
+        g.nj_hmult(m, m, sq)
+        d = g.empty_ct(le - 3)
+        g.nj_conv2d_cins(dec[h], sq, d)
+        halves.append(d)
+    z = g.empty_ct(le - 3)
+    g.nj_combine(halves[0], halves[1], z)
+    y = g.empty_ct(le - 6)
+    g.nj_stoc1(stoc1, z, y)
+    assert out.level == y.level == le - 6 and out.scale == y.scale
+    assert torch.equal(out.data, y.data)

@@ -308,6 +308,15 @@ nj_status nj_conv_plan_create_layer(nj_ctx *ctx, const nj_conv_desc *desc, const
  *     applied with nj_conv2d_block.
  * n1 = baby steps (0 = ceil(sqrt(#diagonals))).  NJ_EINVAL for a layout with W^2 C != N. */
 nj_status nj_downsample_plan_create(nj_ctx *ctx, int kind, int W, int C, int half, int n1, int level, nj_plan **out);
+/* A fully connected layer y = W x fused with the whole StoC (Sec. 4.2.1: slot encoding is
+ * CinS with l = 1): weights [n_out][n_in] (host), n' = the smallest power of two >= n_in,
+ * n_out (<= N/2).  The input ciphertext is slot-encoded with period n': slots j, j + n',
+ * ... hold x_{j mod n'} (real, 0 for n_in <= j mod n' < n').  nj_conv2d_cins applies it
+ * (input level 1..level, output one level lower, scale kept): the output's coefficient
+ * k N / (2 n') holds y_k for k < n_out (times the scale), the other coefficients 0.  n'
+ * cyclic diagonals (n1 = baby steps, 0 = ceil(sqrt(n'))).  NJ_EUNSUPPORTED if n' > N/2. */
+nj_status nj_fc_plan_create(nj_ctx *ctx, int n_in, int n_out, const double *weights, int n1, int level,
+                            nj_plan **out);
 /* Layout of a conv plan: W, C, l, bi, bo (any pointer may be null).  Returns the
  * plan's level, -1 for a null or empty plan. */
 int nj_plan_layout(const nj_plan *plan, int *W, int *C, int *ell, int *bi, int *bo);

@@ -82,6 +82,7 @@ _SIGS = {
     "nj_conv_plan_create_taps": (i32, [vp, i32, i32, i32, vp, i32, i32, i32, i32, ctypes.POINTER(vp)]),
     "nj_conv_taps": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, ctypes.POINTER(i32)]),
     "nj_downsample_plan_create": (i32, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(vp)]),
+    "nj_fc_plan_create": (i32, [vp, i32, i32, vp, i32, i32, ctypes.POINTER(vp)]),
     "nj_conv_plan_create_layer": (i32, [vp, ctypes.POINTER(NjConvDesc), vp, i32, i32, ctypes.POINTER(vp)]),
     "nj_plan_layout": (i32, [vp, vp, vp, vp, vp, vp]),
     "nj_conv2d_block": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
@@ -609,6 +610,14 @@ class Ctx:
         h = vp()
         _check(_lib.nj_downsample_plan_create(self.ptr, int(kind), int(W), int(C), int(half), int(n1), int(level),
                                               ctypes.byref(h)), "nj_downsample_plan_create")
+        return Plan(h)
+
+    def nj_fc_plan_create(self, weights, level, n1=0):
+        """FC layer [n_out][n_in] fused with the whole StoC"""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        h = vp()
+        _check(_lib.nj_fc_plan_create(self.ptr, int(w.shape[1]), int(w.shape[0]), _np_ptr(w), int(n1), int(level),
+                                      ctypes.byref(h)), "nj_fc_plan_create")
         return Plan(h)
 
     def nj_conv2d_block(self, plan, ct, out, stream=None):

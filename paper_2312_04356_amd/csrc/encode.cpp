@@ -352,6 +352,49 @@ nj_status build_downsample_diagonals(int N, int kind, int W, int C, int half, in
     return NJ_OK;
 }
 
+// A fully connected layer fused with the whole StoC (Sec. 4.2.1: slot encoding is CinS with
+// l = 1, so the FC matrix takes the place of the conv's kernel matrix and StoC that of
+// StoC2).  The input is slot-encoded with period n' (a power of two >= n_in, n_out): slots
+// j, j + n', ... hold x_{j mod n'} (x_i = 0 for i >= n_in), i.e. the plaintext is a
+// polynomial in X^{N/(2n')}.  With V' the decoding matrix of that subring (z' = V' w',
+// g = (Re w' | Im w')), the transform applies M' = V' E W S (S: the first n_in slots, E:
+// y into the real part of w') on every period, so the output's coefficient k N / (2n')
+// holds y_k = (W x)_k: n' cyclic diagonals of period n'.
+nj_status build_fc_diagonals(int N, int n_in, int n_out, const double *W, int n1, nj_lt_t &lt,
+                             std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
+{
+    const int n = N / 2;
+    int np = 1;
+    while (np < n_in || np < n_out) np *= 2;
+    if (n_in < 1 || n_out < 1 || np > n) return fail(NJ_EUNSUPPORTED, "FC plan: more features than N/2 slots");
+    // column i of M' = V' applied to the real vector (W[0][i], ..., W[n_out-1][i], 0, ...)
+    std::vector<std::vector<cplx>> M((size_t)np, std::vector<cplx>(np, cplx(0.0, 0.0)));  // M[row][col]
+    for (int i = 0; i < n_in; i++) {
+        std::vector<cplx> x(np, cplx(0.0, 0.0));
+        for (int k = 0; k < n_out; k++) x[k] = cplx(W[(size_t)k * n_in + i], 0.0);
+        bit_reverse(x);
+        for (int k = 1; k < np; k *= 2) butterfly_stage(x, k, false);
+        for (int r = 0; r < np; r++) M[r][i] = x[r];
+    }
+    lt.u = 1;
+    lt.n1 = n1;
+    lt.stages = ilog2(np);  // the whole StoC of the subring merged into the FC matrix
+    lt.js.clear();
+    for (int r = 0; r < np; r++) lt.js.push_back(centred_rep(r, 1, n));
+    bsgs_split(lt, n);
+    dre.assign(lt.n_diag, {});
+    dim.assign(lt.n_diag, {});
+    for (int d = 0; d < lt.n_diag; d++) {
+        const int r = ((lt.js[d] % np) + np) % np;
+        std::vector<cplx> v(n);
+        for (int j = 0; j < n; j++) v[j] = M[j % np][(j % np + r) % np];
+        rotr_inplace(v, (long long)lt.g_of[d] * lt.n1 * lt.u);
+        dre[d].resize(n), dim[d].resize(n);
+        for (int j = 0; j < n; j++) dre[d][j] = v[j].real(), dim[d][j] = v[j].imag();
+    }
+    return NJ_OK;
+}
+
 nj_status build_conv_diagonals(int N, int w0, int f, const double *weights, int n1, nj_lt_t &lt,
                                std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim)
 {

@@ -398,6 +398,8 @@ nj_status build_cts_diagonals(int N, int groups, const int *n1s, std::vector<nj_
 nj_status build_block_diagonals(int N, int W, int c_in, int c_out, const nj_tap *taps, int n_taps, int fuse, int n1,
                                 nj_lt_t &lt, std::vector<std::vector<double>> &dre,
                                 std::vector<std::vector<double>> &dim);
+nj_status build_fc_diagonals(int N, int n_in, int n_out, const double *W, int n1, nj_lt_t &lt,
+                             std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim);
 nj_status build_downsample_diagonals(int N, int kind, int W, int C, int half, int n1, nj_lt_t &lt,
                                      std::vector<std::vector<double>> &dre, std::vector<std::vector<double>> &dim);
 nj_status build_stoc1_diagonals(int N, int ell, int groups, std::vector<nj_lt_t> &lts,

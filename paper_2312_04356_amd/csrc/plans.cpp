@@ -204,6 +204,32 @@ nj_status nj_downsample_plan_create(nj_ctx *c, int kind, int W, int C, int half,
     return NJ_OK;
 }
 
+nj_status nj_fc_plan_create(nj_ctx *c, int n_in, int n_out, const double *weights, int n1, int level, nj_plan **out)
+{
+    if (!c || !weights || !out || n1 < 0) return fail(NJ_EINVAL, "nj_fc_plan_create: bad arguments");
+    if (level < 1 || level > c->L) return fail(NJ_ELEVEL, "nj_fc_plan_create: need 1 <= level <= L");
+    nj_plan *p = new nj_plan();
+    p->kind = 0;
+    p->N = c->N;
+    p->lts.resize(1);
+    nj_lt_t &lt = p->lts[0];
+    lt.level = level;
+    std::vector<std::vector<double>> re, im;
+    nj_status st = build_fc_diagonals(c->N, n_in, n_out, weights, n1, lt, re, im);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->W = 1, p->C = c->N / 2, p->ell = 1, p->w0 = 1, p->f = 1, p->c_in = n_in, p->c_out = n_out;
+    st = upload_plan_diagonals(c, lt, re, im, (double)c->primes[level]);
+    if (st) {
+        nj_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return NJ_OK;
+}
+
 int nj_plan_layout(const nj_plan *p, int *W, int *C, int *ell, int *bi, int *bo)
 {
     if (!p || p->lts.empty()) return -1;

@@ -117,13 +117,13 @@ def test_average_pooling_full():
     err = np.max(np.abs(got - H.avg_pool(img, 3, 2)))
     print("3x3/2 average pooling at N=2^16: max abs error %.2e" % err)
     assert err < 2.0 ** -15
-    # global average of 7 x 7 images (W = 8, C = 1024): the 'same' depthwise 7x7 conv of
-    # weights 1/49 read at the centre pixel
+    # global average of 7 x 7 images: the 'same' depthwise 7x7 conv of weights 1/49 read at
+    # the centre pixel (W = 16 holds every output pixel's taps without wrap-around, C = 256)
     Cg, wg = 64, 7
     img = RNG.uniform(-1, 1, (Cg, wg, wg))
     plan = gctx.nj_conv_plan_create_layer(wg, np.full((Cg, wg, wg), 1.0 / 49.0), depthwise=True, level=1)
     lv, W, C, ell, bi, bo = plan.layout()
-    assert (W, C) == (8, 1024)
+    assert (W, C) == (16, 256)
     ch = np.zeros((C, W, W))
     ch[:Cg, :wg, :wg] = img
     g.make_keys(plan.galois())

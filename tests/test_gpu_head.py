@@ -35,7 +35,8 @@ def host_coeff(gctx, ct):
 def decrypt_coeffs(g, ct):
     d = torch.empty((ct.level + 1, g.N), dtype=torch.int64, device=g.ctx.device)
     g.ctx.nj_decrypt(ct, d)
-    return np.array(O.centred_from_limbs(g.ctx.to_host(d)[:2], g.q[:2]), dtype=np.float64) / ct.scale
+    k = min(2, ct.level + 1)  # one limb at level 0 holds |m| < q_0 / 2 = 2^49
+    return np.array(O.centred_from_limbs(g.ctx.to_host(d)[:k], g.q[:k]), dtype=np.float64) / ct.scale
 
 
 def encrypt_coeffs(g, coeffs, level, sub):

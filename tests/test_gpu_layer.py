@@ -116,9 +116,13 @@ def test_conv_act_layer_full_size():
     fused StoC2 plan back to coefficient layout.  The bound B = 16 of the conv output is
     folded into the conv diagonals (weights / B) and back into the masks (value B), so
     ModEval sees |m / B| <= 1, where its sine departs from the identity by at most
-    (2 pi)^2 / (6 P^2) ~ 6e-6 (P = q_0 / scale = 2^10; Sec. 2.4).  Without activation the
-    output pixels hold the masked conv output within 1e-4; with the square (Sec. 2.5.2)
-    its square within 3e-3 absolute (the same error times 2 |m|); padding holds 0."""
+    (2 pi)^2 / (6 P^2) ~ 6e-6 (P = q_0 / scale = 2^10; Sec. 2.4).  The larger term is
+    bootstrapping's noise floor: CoeffToSlot's noise, in units of ModEval's input
+    (m + q_0 I) / (K q_0), is multiplied by K q_0 / scale = 2^15 on the way back to message
+    units, about 3e-5 of B (measured 4.6e-4 absolute).  Recombining Re + i Im carries each
+    half's imaginary error onto the other half's coefficients, so padding sees the same
+    magnitude although its slots are masked.  Bounds: 1e-3 without activation; 2e-2 with
+    the square (Sec. 2.5.2), the same error times 2 |m| <= 30 (measured 5.8e-3)."""
     g = GpuWorkload("full", with_cts=True, lazy=True)
     gctx = g.ctx
     K, B = 32, 16.0
@@ -159,8 +163,8 @@ def test_conv_act_layer_full_size():
         errs[act] = (np.max(np.abs(got - want)), np.max(np.abs(vals[pad])), np.max(np.abs(want)))
         print("full-size layer, act %d: max |out - exact| %.2e on pixels (max |exact| %.1f), max |out| %.2e on "
               "padding" % (act, errs[act][0], errs[act][2], errs[act][1]))
-    assert errs[0][0] < 1e-4 and errs[0][1] < 1e-4
-    assert errs[1][0] < 3e-3 and errs[1][1] < 1e-4
+    assert errs[0][0] < 1e-3 and errs[0][1] < 1e-3
+    assert errs[1][0] < 2e-2 and errs[1][1] < 2e-2
 
 
 def test_slot_activation_full_size_equals_single_calls():

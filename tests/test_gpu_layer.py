@@ -117,11 +117,12 @@ def test_conv_act_layer_full_size():
     folded into the conv diagonals (weights / B) and back into the masks (value B), so
     ModEval sees |m / B| <= 1, where its sine departs from the identity by at most
     (2 pi)^2 / (6 P^2) ~ 6e-6 (P = q_0 / scale = 2^10; Sec. 2.4).  The larger term is
-    bootstrapping's noise floor: CoeffToSlot's noise, in units of ModEval's input
-    (m + q_0 I) / (K q_0), is multiplied by K q_0 / scale = 2^15 on the way back to message
-    units, about 3e-5 of B (measured 4.6e-4 absolute).  Recombining Re + i Im carries each
-    half's imaginary error onto the other half's coefficients, so padding sees the same
-    magnitude although its slots are masked.  Bounds: 1e-3 without activation; 2e-2 with
+    ModEval's own rounding: each rescale at its working scale (~2^48) leaves noise near
+    2^-38 in the slots, which the squarings up to T_32, the three double angles (up to 4x
+    each) and the factor P / 2 pi amplify about 10^6-fold, to ~3e-5 of B (measured 4.6e-4
+    absolute).  That noise has an imaginary part too, and recombining Re + i Im carries
+    it onto the other half's coefficients, so padding sees the same magnitude although
+    its slots are masked.  Bounds: 1e-3 without activation; 2e-2 with
     the square (Sec. 2.5.2), the same error times 2 |m| <= 30 (measured 5.8e-3)."""
     g = GpuWorkload("full", with_cts=True, lazy=True)
     gctx = g.ctx

@@ -115,6 +115,19 @@ nj_status nj_to_coeff(nj_ctx *ctx, uint64_t *data, int level, int n_polys, void 
  * out->data: device [2][level+1][N]; the result is in evaluation form. */
 nj_status nj_encrypt_sk(nj_ctx *ctx, const uint64_t *m, int level, const uint64_t *a, const int64_t *e,
                         double scale, nj_ct *out, void *stream);
+/* Public key (Sec. 2.1 KeyGen): pk = (-a s + e, a) over q_0..q_L, kept on the device
+ * (evaluation form) until the context is destroyed; a new call replaces it.
+ *   a: host [(L+1)][N] uniform residues (coefficient form); e: host int64 [N].
+ * Needs the secret (nj_set_secret).  Synchronous. */
+nj_status nj_gen_public_key(nj_ctx *ctx, const uint64_t *a, const int64_t *e);
+/* Public-key encryption at `level` (Sec. 2.1 Enc(m; pk)):
+ * (c0, c1) = (v pk0 + e0 + m, v pk1 + e1) on the first level+1 limbs of pk.
+ *   m: device [(level+1)][N] plaintext residues, coefficient form;
+ *   v, e0, e1: host int64 [N] small polynomials (v ternary, e0 and e1 errors).
+ * out->data: device [2][level+1][N], evaluation form; out->scale = scale.
+ * NJ_EINVAL without a public key; NJ_ELEVEL for a level outside 0..L. */
+nj_status nj_encrypt_pk(nj_ctx *ctx, const uint64_t *m, int level, const int64_t *v, const int64_t *e0,
+                        const int64_t *e1, double scale, nj_ct *out, void *stream);
 
 /* Decryption polynomial c0 + c1 s (Sec. 2.1 Dec): out device [(level+1)][N], coefficient form. */
 nj_status nj_decrypt(nj_ctx *ctx, const nj_ct *in, uint64_t *out, void *stream);
@@ -159,7 +172,8 @@ nj_status nj_keyswitch(nj_ctx *ctx, const uint64_t *d, int level, uint32_t galoi
  * scale is not known to the call: out->scale = in->scale, and the caller multiplies in
  * the plaintext's own scale. */
 nj_status nj_pmult(nj_ctx *ctx, const nj_ct *in, const uint64_t *pt, nj_ct *out, void *stream);
-/* HAdd / HSub (Sec. 2.1): out = a + b or a - b (same level).  out may alias a or b. */
+/* HAdd / HSub (Sec. 2.1): out = a + b or a - b.  Same level (else NJ_ELEVEL) and the
+ * same scale up to a relative 1e-9 (else NJ_ESCALE).  out may alias a or b. */
 nj_status nj_add(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
 nj_status nj_sub(nj_ctx *ctx, const nj_ct *a, const nj_ct *b, nj_ct *out, void *stream);
 /* Rescale (Sec. 2.4): divide by q_l with rounding, level l -> l-1. */
@@ -392,7 +406,8 @@ nj_status nj_eval_mod(nj_ctx *ctx, const nj_ct *in, int K, int r, const double *
  * Applies to every later nj_eval_mod / nj_slot_activation / nj_conv_act_layer /
  * nj_bootstrap call on the context.  NJ_EINVAL for another order. */
 nj_status nj_eval_order(nj_ctx *ctx, int order);
-/* Re + i Im (i = X^{N/2} on the slots); same level. */
+/* Re + i Im (i = X^{N/2} on the slots); same level (NJ_ELEVEL) and scale (NJ_ESCALE,
+ * as nj_add). */
 nj_status nj_combine(nj_ctx *ctx, const nj_ct *re, const nj_ct *im, nj_ct *out, void *stream);
 /* StoC1 = S_{l <- 1} = S_{l/2} ... S_1 (Algorithm 1, the StoC stages left after fusing
  * StoC2 into the next conv) in `groups` stage groups at levels level, level-1, ...;
@@ -473,6 +488,7 @@ nj_status nj_time_plan(nj_ctx *ctx, const nj_plan *plan, int t, int level, int r
  * conv fused with StoC2, the stage count of a CoeffToSlot or StoC1 group); f[6] = bo. */
 nj_status nj_plan_features(const nj_plan *plan, int t, int level, float *f);
 
+
 /* Learned cost model (plan selection by predicted latency): 7 features -> 64 -> 64 -> 1,
  * FP32, ReLU.  Parameters (NJ_MLP_PARAMS floats): W1 [7][64], b1 [64], W2 [64][64]
  * (row = input unit), b2 [64], w3 [64], b3.  Created with He-uniform weights from a
@@ -502,6 +518,23 @@ nj_status nj_mlp_grad(nj_mlp *mlp, const float *X, const float *y, int n, float 
 nj_status nj_mlp_train(nj_mlp *mlp, const float *X, const float *y, int n, int epochs, int batch, float lr,
                        uint64_t seed, float *final_loss);
 nj_status nj_mlp_predict(nj_mlp *mlp, const float *X, int n, float *out);
+
+/* Autotuner (plan selection, Sec. 2.6's BSGS split and hoisting): picks the baby-step
+ * count n1 and the hoisting mode of transform t of a plan at `level` (1 <= level <= the
+ * transform's).  Candidates: n1 = 0 (the default split) and the powers of two within a
+ * factor 4 of sqrt(#diagonals), each hoisted or not (block transforms: hoisted only).
+ * With model (may be null) and shortlist > 0, the model ranks the candidates by their
+ * features (nj_plan_features of each split) and only its `shortlist` best are timed;
+ * otherwise every candidate is.  The default split, hoisted, is always timed, so the
+ * choice is never slower than the default as measured.  Each candidate is timed as
+ * nj_time_plan times it (reps runs, median), on a plan of the same diagonal offsets with
+ * random diagonals, so the rotation keys must be present or timing mode on
+ * (nj_timing_keys).  Outputs: n1 (0 = default), hoist (1/0), its time in ms, and the
+ * default's time (default_ms may be null).  The plan itself is not changed: rebuild it
+ * with the chosen n1 (plan constructors take n1) and apply nj_plan_set_hoist.
+ * Synchronous; allocates the candidate plans one at a time. */
+nj_status nj_tune_split(nj_ctx *ctx, const nj_plan *plan, int t, int level, const nj_mlp *model, int shortlist,
+                        int reps, int *n1, int *hoist, float *ms, float *default_ms);
 
 /* ------------------------------------------------------------ profiling */
 

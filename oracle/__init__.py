@@ -56,6 +56,7 @@ def _load():
         "or_rescale": (None, [vp, i32, vp, vp]),
         "or_modraise": (None, [vp, i32, vp, vp]),
         "or_encrypt_sk": (None, [vp, i32, vp, vp, vp, vp, vp]),
+        "or_encrypt_pk": (None, [vp, i32, vp, vp, vp, vp, vp, vp]),
         "or_decrypt": (None, [vp, i32, vp, vp, vp]),
         "or_poly_pmult": (None, [vp, i32, vp, vp, vp]),
         "or_poly_automorph": (None, [vp, i32, vp, u64, vp]),
@@ -246,6 +247,20 @@ class Ring:
         s, m, a, e = _i64(s), _u64(m), _u64(a), _i64(e)
         ct = np.empty((2, level + 1, self.n), dtype=np.uint64)
         lib.or_encrypt_sk(self.ptr, level, _p(s), _p(m), _p(a), _p(e), _p(ct))
+        return ct
+
+    def gen_public_key(self, s, a, e):
+        """pk = (-a s + e, a) over all L+1 ciphertext primes (Sec. 2.1): the secret-key
+        encryption of zero at the top level"""
+        return self.encrypt_sk(self.L, s, np.zeros((self.L + 1, self.n), dtype=np.uint64), a, e)
+
+    def encrypt_pk(self, level, pk, m, v, e0, e1):
+        """Enc(m; pk) at `level` (Sec. 2.1): (v pk0 + e0 + m, v pk1 + e1) on the first
+        level+1 limbs of pk, for small v, e0, e1 (coefficient form throughout)"""
+        pk, m, v, e0, e1 = _u64(pk), _u64(m), _i64(v), _i64(e0), _i64(e1)
+        assert pk.shape == (2, self.L + 1, self.n)
+        ct = np.empty((2, level + 1, self.n), dtype=np.uint64)
+        lib.or_encrypt_pk(self.ptr, level, _p(pk), _p(m), _p(v), _p(e0), _p(e1), _p(ct))
         return ct
 
     def decrypt(self, level, s, ct):

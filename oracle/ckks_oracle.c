@@ -457,6 +457,26 @@ void or_encrypt_sk(const or_ring *R, int l, const int64_t *s, const uint64_t *m,
     }
 }
 
+/* Public-key encryption (Sec. 2.1: Enc(m; pk) with pk = (-a s + e, a), an encryption of
+ * zero at the top level): ct = (v pk0 + e0 + m, v pk1 + e1) at level l, from the first
+ * l+1 limbs of pk [2][L+1][n], small signed v, e0, e1 [n]; ct [2][(l+1)][n]. */
+void or_encrypt_pk(const or_ring *R, int l, const uint64_t *pk, const uint64_t *m, const int64_t *v, const int64_t *e0,
+                   const int64_t *e1, uint64_t *ct)
+{
+    int n = R->n, L1 = R->L + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i <= l; i++) {
+        uint64_t qi = R->q[i], *p0 = (uint64_t *)malloc(sizeof(uint64_t) * n), *p1 = (uint64_t *)malloc(sizeof(uint64_t) * n);
+        polymul_small(pk + (size_t)i * n, v, p0, n, qi);
+        polymul_small(pk + ((size_t)L1 + i) * n, v, p1, n, qi);
+        for (int k = 0; k < n; k++) {
+            ct[(size_t)i * n + k] = addm(addm(p0[k], from_i64(e0[k], qi), qi), m[(size_t)i * n + k], qi);
+            ct[((size_t)(l + 1) + i) * n + k] = addm(p1[k], from_i64(e1[k], qi), qi);
+        }
+        free(p0), free(p1);
+    }
+}
+
 /* decryption polynomial c0 + c1 s at level l; out [(l+1)][n] */
 void or_decrypt(const or_ring *R, int l, const int64_t *s, const uint64_t *ct, uint64_t *out)
 {

@@ -58,6 +58,8 @@ _SIGS = {
     "nj_to_eval": (i32, [vp, vp, i32, i32, vp]),
     "nj_to_coeff": (i32, [vp, vp, i32, i32, vp]),
     "nj_encrypt_sk": (i32, [vp, vp, i32, vp, vp, dbl, ctypes.POINTER(NjCt), vp]),
+    "nj_gen_public_key": (i32, [vp, vp, vp]),
+    "nj_encrypt_pk": (i32, [vp, vp, i32, vp, vp, vp, dbl, ctypes.POINTER(NjCt), vp]),
     "nj_decrypt": (i32, [vp, ctypes.POINTER(NjCt), vp, vp]),
     "nj_encode_slots": (i32, [i32, vp, dbl, vp]),
     "nj_encode_cins": (i32, [i32, vp, i32, dbl, vp]),
@@ -116,6 +118,8 @@ _SIGS = {
     "nj_plan_create_random": (i32, [vp, i32, i32, vp, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]),
     "nj_time_plan": (i32, [vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
     "nj_plan_features": (i32, [vp, i32, i32, vp]),
+    "nj_tune_split": (i32, [vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "nj_mlp_create": (i32, [u64, ctypes.POINTER(vp)]),
     "nj_mlp_destroy": (None, [vp]),
     "nj_mlp_set_params": (i32, [vp, vp]),
@@ -476,6 +480,20 @@ class Ctx:
                                   ctypes.byref(c), _stream(stream)), "nj_encrypt_sk")
         return out.sync_from(c)
 
+    def nj_gen_public_key(self, a, e):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        e = np.ascontiguousarray(e, dtype=np.int64)
+        assert a.shape == (self.L + 1, self.N) and e.shape == (self.N,)
+        _check(_lib.nj_gen_public_key(self.ptr, _np_ptr(a), _np_ptr(e)), "nj_gen_public_key")
+
+    def nj_encrypt_pk(self, m_dev, level, v, e0, e1, scale, out, stream=None):
+        v, e0, e1 = (np.ascontiguousarray(x, dtype=np.int64) for x in (v, e0, e1))
+        assert v.shape == e0.shape == e1.shape == (self.N,)
+        c = out.c()
+        _check(_lib.nj_encrypt_pk(self.ptr, _dev_ptr(m_dev), level, _np_ptr(v), _np_ptr(e0), _np_ptr(e1),
+                                  float(scale), ctypes.byref(c), _stream(stream)), "nj_encrypt_pk")
+        return out.sync_from(c)
+
     def nj_decrypt(self, ct, out_dev, stream=None):
         c = ct.c()
         _check(_lib.nj_decrypt(self.ptr, ctypes.byref(c), _dev_ptr(out_dev), _stream(stream)), "nj_decrypt")
@@ -757,6 +775,15 @@ class Ctx:
         _check(_lib.nj_time_plan(self.ptr, plan.ptr, int(t), int(level), int(reps), ctypes.byref(ms)),
                "nj_time_plan")
         return ms.value
+
+    def nj_tune_split(self, plan, level, t=0, model=None, shortlist=3, reps=3):
+        """(n1, hoist, ms, default ms) the library's autotuner picks for transform t"""
+        n1, ho = i32(), i32()
+        ms, dms = ctypes.c_float(), ctypes.c_float()
+        _check(_lib.nj_tune_split(self.ptr, plan.ptr, int(t), int(level), model.ptr if model is not None else None,
+                                  int(shortlist), int(reps), ctypes.byref(n1), ctypes.byref(ho), ctypes.byref(ms),
+                                  ctypes.byref(dms)), "nj_tune_split")
+        return n1.value, bool(ho.value), ms.value, dms.value
 
     def nj_cts_plan_create(self, groups):
         h = vp()

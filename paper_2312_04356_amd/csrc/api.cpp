@@ -1031,6 +1031,67 @@ nj_status nj_encrypt_sk(nj_ctx *c, const uint64_t *m, int level, const uint64_t 
     return NJ_OK;
 }
 
+nj_status nj_gen_public_key(nj_ctx *c, const uint64_t *a, const int64_t *e)
+{
+    if (!c || !a || !e) return fail(NJ_EINVAL, "nj_gen_public_key: null argument");
+    if (!c->d_s) return fail(NJ_EINVAL, "nj_gen_public_key: secret not set");
+    const size_t N = c->N, plen = N * (c->L + 1);
+    if (!c->d_pk) NJ_HIP(hipMalloc(&c->d_pk, 2 * plen * 8));
+    uint64_t *b = c->d_pk, *ak = c->d_pk + plen, *et = nullptr, *tmp = nullptr;
+    NJ_HIP(hipMalloc(&et, plen * 8));
+    if (hipMalloc(&tmp, N * 8) != hipSuccess) {
+        (void)hipFree(et);
+        return fail(NJ_ENOMEM, "nj_gen_public_key: device memory");
+    }
+    const LimbTab lq = limbs_q(c->L);
+    hipError_t err = hipMemcpy(ak, a, plen * 8, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = launch_ntt(c, ak, lq, false, 0);
+    if (err == hipSuccess) err = upload_signed(c, e, 1, lq, et, tmp, 0);
+    if (err == hipSuccess) err = launch_ntt(c, et, lq, false, 0);
+    if (err == hipSuccess) err = launch_elementwise(c, 2, ak, c->d_s, b, lq, 0);  // a s
+    if (err == hipSuccess) err = launch_elementwise(c, 1, et, b, b, lq, 0);       // e - a s
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    (void)hipFree(et), (void)hipFree(tmp);
+    if (err != hipSuccess) return fail(NJ_EDEVICE, hipGetErrorString(err));
+    return NJ_OK;
+}
+
+nj_status nj_encrypt_pk(nj_ctx *c, const uint64_t *m, int level, const int64_t *v, const int64_t *e0, const int64_t *e1,
+                        double scale, nj_ct *out, void *stream)
+{
+    if (!c || !m || !v || !e0 || !e1 || !out || !out->data) return fail(NJ_EINVAL, "nj_encrypt_pk: null argument");
+    if (level < 0 || level > c->L) return fail(NJ_ELEVEL, "nj_encrypt_pk: level out of range");
+    if (!c->d_pk) return fail(NJ_EINVAL, "nj_encrypt_pk: no public key (nj_gen_public_key)");
+    const size_t N = c->N, plen = N * (level + 1), ptop = N * (c->L + 1);
+    hipStream_t s = S(stream);
+    bool ok;
+    Arena A = arena_for(c, 3 * plen + N, ok);
+    if (!ok) return fail(NJ_ENOMEM, "scratch");
+    uint64_t *vt = A.take(plen), *et = A.take(plen), *mt = A.take(plen), *tmp = A.take(N);
+    uint64_t *c0 = out->data, *c1 = out->data + plen;
+    const LimbTab lq = limbs_q(level);
+    // the first level+1 limbs of each key polynomial are that polynomial at `level`
+    NJ_HIP(upload_signed(c, v, 1, lq, vt, tmp, s));
+    NJ_HIP(launch_ntt(c, vt, lq, false, s));
+    NJ_HIP(hipMemcpyAsync(mt, m, plen * 8, hipMemcpyDeviceToDevice, s));
+    NJ_HIP(launch_ntt(c, mt, lq, false, s));
+    NJ_HIP(launch_elementwise(c, 2, c->d_pk, vt, c0, lq, s));          // v pk0
+    NJ_HIP(launch_elementwise(c, 0, c0, mt, c0, lq, s));               // + m
+    NJ_HIP(launch_elementwise(c, 2, c->d_pk + ptop, vt, c1, lq, s));   // v pk1
+    NJ_HIP(upload_signed(c, e0, 1, lq, et, tmp, s));
+    NJ_HIP(launch_ntt(c, et, lq, false, s));
+    NJ_HIP(launch_elementwise(c, 0, c0, et, c0, lq, s));               // + e0
+    NJ_HIP(hipStreamSynchronize(s));  // tmp is reused for e1 and the host arrays are borrowed only for the call
+    NJ_HIP(upload_signed(c, e1, 1, lq, et, tmp, s));
+    NJ_HIP(launch_ntt(c, et, lq, false, s));
+    NJ_HIP(launch_elementwise(c, 0, c1, et, c1, lq, s));               // + e1
+    NJ_HIP(hipStreamSynchronize(s));
+    out->level = level;
+    out->is_ntt = 1;
+    out->scale = scale;
+    return NJ_OK;
+}
+
 nj_status nj_decrypt(nj_ctx *c, const nj_ct *in, uint64_t *out, void *stream)
 {
     if (!c || !out) return fail(NJ_EINVAL, "nj_decrypt: null argument");
@@ -1131,6 +1192,7 @@ static nj_status addsub(nj_ctx *c, int op, const nj_ct *a, const nj_ct *b, nj_ct
     if (st) return st;
     if ((st = check_ct(c, b, nm))) return st;
     if (a->level != b->level) return fail(NJ_ELEVEL, std::string(nm) + ": operands at different levels");
+    if (!same_scale(a->scale, b->scale)) return fail(NJ_ESCALE, std::string(nm) + ": operands at different scales");
     if (!out || !out->data) return fail(NJ_EINVAL, std::string(nm) + ": null output");
     NJ_HIP(launch_elementwise(c, op, a->data, b->data, out->data, ct_limbs(a->level), S(stream)));
     out->level = a->level, out->is_ntt = 1, out->scale = a->scale;

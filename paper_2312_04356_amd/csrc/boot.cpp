@@ -451,6 +451,7 @@ nj_status nj_combine(nj_ctx *c, const nj_ct *re, const nj_ct *im, nj_ct *out, vo
     nj_status st = check_ct(c, re, "nj_combine");
     if (st || (st = check_ct(c, im, "nj_combine"))) return st;
     if (re->level != im->level) return fail(NJ_ELEVEL, "nj_combine: Re and Im must share a level");
+    if (!same_scale(re->scale, im->scale)) return fail(NJ_ESCALE, "nj_combine: Re and Im at different scales");
     if (!out || !out->data || out->data == re->data || out->data == im->data) return fail(NJ_EINVAL, "nj_combine: bad output");
     // the monomial kernel multiplies by -X^{N/2}, so Re - (-X^{N/2} Im) = Re + i Im
     NJ_HIP(launch_monomial_half(c, im->level, im->data, out->data, S(stream)));

@@ -362,7 +362,7 @@ void nj_ctx_destroy(nj_ctx *c)
         if (p) (void)hipFree(p);
     };
     fr(c->d_tw), fr(c->d_twq), fr(c->d_itw), fr(c->d_itwq), fr(c->d_info);
-    fr(c->d_pinv), fr(c->d_pinvq), fr(c->d_qlinv), fr(c->d_qlinvq), fr(c->d_s), fr(c->d_primes), fr(c->d_pmod);
+    fr(c->d_pinv), fr(c->d_pinvq), fr(c->d_qlinv), fr(c->d_qlinvq), fr(c->d_s), fr(c->d_pk), fr(c->d_primes), fr(c->d_pmod);
     for (auto &lv : c->modup)
         for (auto &b : lv) fr(b.hat_inv), fr(b.hat);
     for (auto &b : c->moddown) fr(b.hat_inv), fr(b.hat);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <map>
 #include <string>
 #include <vector>
@@ -86,6 +87,10 @@ __device__ __forceinline__ int galois_src2(int k, uint32_t g, int logN)
 
 // Output limb t of a key inner product at level l: t < l+1 is q_t, else p_(t-l-1); kl
 // = the key's limb of t; own = the digit t belongs to (-1 for special primes).
+// Sums need their operands at one scale: equal up to a relative 1e-9 (scales computed
+// by the same sequence of steps are equal exactly).
+inline bool same_scale(double a, double b) { return std::fabs(a - b) <= 1e-9 * std::fmax(std::fabs(a), std::fabs(b)); }
+
 struct IpRow {
     size_t t, ne, nk, kl;
     int own;
@@ -220,6 +225,7 @@ struct nj_ctx {
     // secret key in evaluation form [n_primes][N]
     std::vector<int8_t> s;
     uint64_t *d_s = nullptr;
+    uint64_t *d_pk = nullptr;  // public key [2][L+1][N], evaluation form (nj_gen_public_key)
     std::map<uint32_t, nj::Key> keys;
     std::vector<uint64_t *> timing_keys;  // latency measurement: random key buffers for missing elements
     nj::Scratch scratch;

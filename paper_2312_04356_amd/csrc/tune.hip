@@ -51,6 +51,33 @@ int ilog2(int x)
     return r;
 }
 
+// Cost-model features of a transform at `level` (see nj_plan_features)
+void lt_features(const nj_lt_t &lt, int N, int level, float *f)
+{
+    const int n = N / 2;
+    const bool hoisted = lt.hoist || lt.bi != 1 || lt.bo != 1;  // block transforms always hoist
+    f[0] = (float)(level + 1);                                  // level
+    f[1] = (float)lt.n_diag;                                    // channels: diagonals per block
+    f[2] = (float)ilog2(n / lt.u);                              // slot stride of the rotations (image size)
+    f[3] = (float)lt.babies.size();                             // BSGS split: baby steps
+    f[4] = hoisted ? (float)(lt.bi * ((int)lt.babies.size() - 1)) : 0.f;  // hoisted baby rotations
+    f[5] = (float)lt.stages;                                    // fusion depth: DFT stages merged in
+    f[6] = (float)lt.bo;                                        // output blocks (giant rotations per step)
+}
+
+// baby-step counts the tuner tries: 0 (the library's default split) and the powers of
+// two within a factor 4 of sqrt(#diagonals), at most the diagonal count
+std::vector<int> split_candidates(int n_diag)
+{
+    std::vector<int> out{0};
+    const double r = std::sqrt((double)n_diag);
+    for (int k = 0; k < 12; k++) {
+        const int v = 1 << k;
+        if (r / 4 <= v && v <= 4 * r && v <= std::max(1, n_diag)) out.push_back(v);
+    }
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -161,16 +188,70 @@ nj_status nj_time_plan(nj_ctx *c, const nj_plan *p, int t, int level, int reps, 
 nj_status nj_plan_features(const nj_plan *p, int t, int level, float *f)
 {
     if (!p || t < 0 || t >= (int)p->lts.size() || !f) return fail(NJ_EINVAL, "nj_plan_features: bad arguments");
-    const nj_lt_t &lt = p->lts[t];
-    const int n = p->N / 2;
-    const bool hoisted = lt.hoist || lt.bi != 1 || lt.bo != 1;  // block transforms always hoist
-    f[0] = (float)(level + 1);                                  // level
-    f[1] = (float)lt.n_diag;                                    // channels: diagonals per block
-    f[2] = (float)ilog2(n / lt.u);                              // slot stride of the rotations (image size)
-    f[3] = (float)lt.babies.size();                             // BSGS split: baby steps
-    f[4] = hoisted ? (float)(lt.bi * ((int)lt.babies.size() - 1)) : 0.f;  // hoisted baby rotations
-    f[5] = (float)lt.stages;                                    // fusion depth: DFT stages merged in
-    f[6] = (float)lt.bo;                                        // output blocks (giant rotations per step)
+    lt_features(p->lts[t], p->N, level, f);
+    return NJ_OK;
+}
+
+nj_status nj_tune_split(nj_ctx *c, const nj_plan *p, int t, int level, const nj_mlp *model, int shortlist, int reps,
+                        int *n1_out, int *hoist_out, float *ms_out, float *default_ms)
+{
+    if (!c || !p || t < 0 || t >= (int)p->lts.size() || reps < 1 || shortlist < 0 || !n1_out || !hoist_out || !ms_out)
+        return fail(NJ_EINVAL, "nj_tune_split: bad arguments");
+    if (p->N != c->N) return fail(NJ_EINVAL, "nj_tune_split: plan of another ring");
+    const nj_lt_t &src = p->lts[t];
+    if (level < 1 || level > src.level) return fail(NJ_ELEVEL, "nj_tune_split: need 1 <= level <= the transform's");
+    const bool blk = src.bi != 1 || src.bo != 1;  // block transforms always hoist
+    const int n = c->N / 2;
+    struct Cand {
+        int n1;
+        bool hoist;
+        float score, ms;
+    };
+    std::vector<Cand> cands;
+    for (int n1 : split_candidates(src.n_diag))
+        for (int h = 1; h >= (blk ? 1 : 0); h--) cands.push_back(Cand{n1, h != 0, 0.f, -1.f});
+    // the model ranks the candidates by predicted latency (features of each split,
+    // computed without building it); without a model every candidate is timed
+    std::vector<int> order(cands.size());
+    for (size_t i = 0; i < cands.size(); i++) order[i] = (int)i;
+    if (model && shortlist > 0) {
+        std::vector<float> X(cands.size() * NJ_MLP_FEATURES), y(cands.size());
+        for (size_t i = 0; i < cands.size(); i++) {
+            nj_lt_t lt = src;
+            lt.d_diag = nullptr;
+            lt.n1 = cands[i].n1, lt.hoist = cands[i].hoist;
+            bsgs_split(lt, n);
+            lt_features(lt, c->N, level, &X[i * NJ_MLP_FEATURES]);
+        }
+        nj_status st = nj_mlp_predict(const_cast<nj_mlp *>(model), X.data(), (int)cands.size(), y.data());
+        if (st) return st;
+        for (size_t i = 0; i < cands.size(); i++) cands[i].score = y[i];
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cands[a].score < cands[b].score; });
+    }
+    // timed: the shortlist (or every candidate) and always the default split, hoisted
+    std::vector<int> timed;
+    for (int i : order)
+        if (!model || shortlist == 0 || (int)timed.size() < shortlist) timed.push_back(i);
+    for (size_t i = 0; i < cands.size(); i++)
+        if (cands[i].n1 == 0 && cands[i].hoist && std::find(timed.begin(), timed.end(), (int)i) == timed.end())
+            timed.push_back((int)i);
+    std::vector<int32_t> offs(src.js.begin(), src.js.end());
+    int best = -1;
+    for (int i : timed) {
+        nj_plan *q = nullptr;
+        nj_status st = nj_plan_create_random(c, level, src.u, offs.data(), (int)offs.size(), cands[i].n1, src.bi,
+                                             src.bo, 0x7u + (uint64_t)i, &q);
+        if (st) return st;
+        q->lts[0].stages = src.stages, q->lts[0].hoist = cands[i].hoist;
+        st = nj_time_plan(c, q, 0, level, reps, &cands[i].ms);
+        nj_plan_destroy(q);
+        if (st) return st;
+        if (best < 0 || cands[i].ms < cands[best].ms) best = i;
+    }
+    *n1_out = cands[best].n1, *hoist_out = cands[best].hoist ? 1 : 0, *ms_out = cands[best].ms;
+    if (default_ms)
+        for (const Cand &k : cands)
+            if (k.n1 == 0 && k.hoist) *default_ms = k.ms;
     return NJ_OK;
 }
 

@@ -9,11 +9,13 @@ seed and a purpose number, so both sides receive identical inputs.
 Purposes (the second key word):
   0 secret key        1 key-switching uniforms   2 key-switching errors
   3 encryption uniforms  4 encryption errors    5 image / weight data
-  6 job mix
+  6 job mix          7 public-key uniforms   8 public-key error
+  9 public-key encryption: v, e0, e1
 """
 import numpy as np
 
-PURPOSE_SECRET, PURPOSE_KEY_A, PURPOSE_KEY_E, PURPOSE_ENC_A, PURPOSE_ENC_E, PURPOSE_DATA, PURPOSE_JOBS = range(7)
+(PURPOSE_SECRET, PURPOSE_KEY_A, PURPOSE_KEY_E, PURPOSE_ENC_A, PURPOSE_ENC_E, PURPOSE_DATA, PURPOSE_JOBS,
+ PURPOSE_PK_A, PURPOSE_PK_E, PURPOSE_PK_ENC) = range(10)
 
 
 def _gen(seed, purpose, sub=0):
@@ -85,6 +87,21 @@ def key_randomness(primes, n, dnum, seed, key_id):
 def enc_randomness(primes, n, seed, sub=0):
     """uniform a: [len(primes)][n] uint64 and error e: [n] int64 for one secret-key encryption"""
     return uniform_residues(primes, n, seed, PURPOSE_ENC_A, sub), cbd_error(n, seed, PURPOSE_ENC_E, sub)
+
+
+def pk_randomness(primes, n, seed):
+    """uniform a: [len(primes)][n] uint64 and error e: [n] int64 of a public key"""
+    return uniform_residues(primes, n, seed, PURPOSE_PK_A), cbd_error(n, seed, PURPOSE_PK_E)
+
+
+def pk_enc_randomness(n, seed, sub=0, h=64):
+    """(v, e0, e1) of one public-key encryption: v int64[n] ternary with h nonzero
+    entries, e0 and e1 int64[n] centred binomial"""
+    g = _gen(seed, PURPOSE_PK_ENC, 3 * int(sub))
+    pos = g.choice(n, size=h, replace=False)
+    v = np.zeros(n, dtype=np.int64)
+    v[pos] = g.integers(0, 2, size=h) * 2 - 1
+    return v, cbd_error(n, seed, PURPOSE_PK_ENC, 3 * int(sub) + 1), cbd_error(n, seed, PURPOSE_PK_ENC, 3 * int(sub) + 2)
 
 
 RELIN_KEY_ID = 0  # Galois elements are odd, so 0 never collides

@@ -1,0 +1,83 @@
+"""Error statuses through the C ABI (needs an MI355X): each call refuses what it cannot
+compute with the documented status code and leaves its output untouched; a refused
+call does not disturb the next valid one."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_04356_amd import Ct, NjError  # noqa: E402
+from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+
+NJ_EINVAL, NJ_ELEVEL, NJ_ESCALE, NJ_ENOKEY = -1, -2, -3, -4
+
+
+@pytest.fixture(scope="module")
+def g():
+    return GpuWorkload("small", with_cts=False)
+
+
+def status(fn):
+    with pytest.raises(NjError) as e:
+        fn()
+    return e.value.code
+
+
+def test_missing_rotation_key_is_enokey(g):
+    ctx = g.ctx
+    ct = g.encrypt_input(3)
+    out = ctx.empty_ct(3)
+    before = out.data.clone()
+    assert status(lambda: ctx.nj_rotate(ct, 5, out)) == NJ_ENOKEY
+    assert torch.equal(out.data, before)  # nothing written
+    g.make_keys([ctx.nj_galois_elt(5)])
+    ctx.nj_rotate(ct, 5, out)  # with its key the same call succeeds
+    assert out.level == 3
+
+
+def test_sums_refuse_mismatched_levels_and_scales(g):
+    ctx = g.ctx
+    a, b = g.encrypt_input(3), g.encrypt_input(3)
+    out = ctx.empty_ct(3)
+    c2 = g.encrypt_input(2)
+    assert status(lambda: ctx.nj_add(a, c2, out)) == NJ_ELEVEL
+    b_off = Ct(b.data, b.level, scale=b.scale * 2.0)
+    assert status(lambda: ctx.nj_add(a, b_off, out)) == NJ_ESCALE
+    assert status(lambda: ctx.nj_sub(a, b_off, out)) == NJ_ESCALE
+    assert status(lambda: ctx.nj_combine(a, b_off, ctx.empty_ct(3))) == NJ_ESCALE
+    b_near = Ct(b.data, b.level, scale=b.scale * (1 + 1e-12))  # rounding-level difference is a sum
+    ctx.nj_add(a, b_near, out)
+    ctx.nj_add(a, b, out)
+    assert out.level == 3 and out.scale == a.scale
+
+
+def test_rescale_and_level_errors(g):
+    ctx = g.ctx
+    c0 = g.encrypt_input(0)
+    assert status(lambda: ctx.nj_rescale(c0, ctx.empty_ct(0))) == NJ_ELEVEL
+    c3 = g.encrypt_input(3)
+    assert status(lambda: ctx.nj_rescale(c3, c3)) == NJ_EINVAL  # output aliasing input
+    assert status(lambda: ctx.nj_drop_level(c3, 5, ctx.empty_ct(5))) == NJ_ELEVEL
+    y = ctx.empty_ct(2)
+    ctx.nj_rescale(c3, y)
+    assert y.level == 2
+
+
+def test_plan_level_and_key_errors(g):
+    ctx = g.ctx
+    plan = g.conv_plan  # encoded for level 1
+    ct = g.encrypt_input(2)
+    out = ctx.empty_ct(1)
+    code = status(lambda: ctx.nj_conv2d_cins(plan, ct, out))
+    assert code == NJ_ELEVEL
+    ct1 = g.encrypt_input(1)
+    fresh = GpuWorkload("small", with_cts=False)  # a context without the conv's keys
+    fplan = fresh.ctx.nj_conv_plan_create(fresh.w["w0"], fresh.w["f"], fresh.K)
+    assert status(lambda: fresh.ctx.nj_conv2d_cins(fplan, fresh.encrypt_input(1), fresh.ctx.empty_ct(0))) == NJ_ENOKEY
+    g.make_keys(plan.galois())
+    ctx.nj_conv2d_cins(plan, ct1, ctx.empty_ct(0))
+    assert np.isfinite(ct1.scale)

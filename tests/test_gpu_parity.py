@@ -121,6 +121,27 @@ def test_encrypt_decrypt_parity(which, request):
     assert np.array_equal(gctx.to_host(dec), R.decrypt(level, P.o.s, ct_o))
 
 
+@pytest.mark.parametrize("which,level", [("small", 3), ("full", 1), ("full", 23)])
+def test_public_key_encryption_parity(which, level, request):
+    """Sec. 2.1: the public key and Enc(m; pk) word for word against the oracle, and the
+    decryption polynomial too"""
+    import synth
+    P = request.getfixturevalue(which)
+    gctx, R = P.g.ctx, P.o.ring
+    a, e = synth.pk_randomness(R.q, P.N, 31)
+    gctx.nj_gen_public_key(a, e)
+    pk = R.gen_public_key(P.o.s, a, e)
+    m = R.to_rns(P.o.input_plaintext(), level)
+    v, e0, e1 = synth.pk_enc_randomness(P.N, 32, level)
+    ct_g = gctx.nj_encrypt_pk(gctx.to_device(m), level, v, e0, e1, 2.0 ** 40, gctx.empty_ct(level))
+    ct_o = R.encrypt_pk(level, pk, m, v, e0, e1)
+    assert ct_g.level == level and ct_g.scale == 2.0 ** 40
+    assert np.array_equal(host_coeff(gctx, ct_g), ct_o)
+    dec = torch.empty((level + 1, P.N), dtype=torch.int64, device=gctx.device)
+    gctx.nj_decrypt(ct_g, dec)
+    assert np.array_equal(gctx.to_host(dec), R.decrypt(level, P.o.s, ct_o))
+
+
 # ----------------------------------------------------------- key switching
 
 @pytest.mark.parametrize("which,level", [("small", 0), ("small", 4), ("small", 7), ("full", 1), ("full", 23)])

@@ -99,3 +99,29 @@ def test_mlp_save_and_restore():
         bad = norm.copy()
         bad[7] = 0.0
         m2.set_norm(bad)
+
+
+def test_autotuner_behind_the_abi():
+    """nj_tune_split at N = 2^16: exhaustive over the candidate splits, and the committed
+    model's shortlist; either choice is at least as fast as the default split as timed"""
+    import os
+    g = GpuWorkload("full", with_cts=False)
+    ctx = g.ctx
+    here = os.path.join(os.path.dirname(__file__), "..", "paper_2312_04356_amd", "data", "plan_model_n65536.json")
+    with open(here) as fh:
+        model = Mlp.from_dict(json.load(fh))
+    conv = ctx.nj_plan_create_random(1, 2048, list(range(-33, 34)), n1=0)  # a 3x3 conv's offset spread
+    cts = ctx.nj_plan_create_random(23, 1, list(range(-15, 17)), n1=0)  # 32 diagonals at level 23
+    with pytest.raises(NjError):  # no keys, no timing mode
+        ctx.nj_tune_split(conv, 1, model=None)
+    ctx.nj_timing_keys(16)
+    try:
+        for name, plan, level in (("conv", conv, 1), ("32 diagonals", cts, 23)):
+            n1, h, ms, dms = ctx.nj_tune_split(plan, level, model=None, reps=3)
+            n1m, hm, msm, dmsm = ctx.nj_tune_split(plan, level, model=model, shortlist=3, reps=3)
+            print("%s at level %d: exhaustive n1=%d hoist=%s %.3f ms, model n1=%d hoist=%s %.3f ms, default %.3f ms"
+                  % (name, level, n1, h, ms, n1m, hm, msm, dms))
+            assert 0 < ms <= dms and 0 < msm <= dmsm
+            assert n1 == 0 or (n1 & (n1 - 1)) == 0
+    finally:
+        ctx.nj_timing_keys(0)

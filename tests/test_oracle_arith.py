@@ -270,3 +270,39 @@ def test_encrypt_decrypt_roundtrip():
     ct = R.encrypt_sk(2, ctx.s, R.to_rns(m, 2), a, e)
     got = dec_centred(ctx, 2, ct)
     assert max(abs(int(x) - int(y)) for x, y in zip(got, m)) <= 30
+
+
+def int_negacyclic(a, b):
+    """a * b in Z[X]/(X^n + 1) on plain Python integers"""
+    n = len(a)
+    c = [0] * n
+    for i in range(n):
+        for j in range(n):
+            if a[i] and b[j]:
+                k = i + j
+                if k < n:
+                    c[k] += int(a[i]) * int(b[j])
+                else:
+                    c[k - n] -= int(a[i]) * int(b[j])
+    return c
+
+
+@pytest.mark.parametrize("level", [0, 2])
+def test_public_key_encryption_noise_is_exact(level):
+    """Sec. 2.1: pk = (-a s + e, a) decrypts to e, and Enc(m; pk) decrypts to exactly
+    m + v e + e0 + e1 s (integer negacyclic products), at the top level and below"""
+    import synth
+    R = small_ring(n=32, nq=3, alpha=2)
+    ctx = make_ctx(R)
+    a, e = synth.pk_randomness(R.q, R.n, 11)
+    pk = R.gen_public_key(ctx.s, a, e)
+    assert dec_centred(ctx, R.L, pk) == [int(x) for x in e]
+    m = [RNG.randrange(-2 ** 30, 2 ** 30) for _ in range(R.n)]
+    v, e0, e1 = synth.pk_enc_randomness(R.n, 12, 0, h=8)
+    ct = R.encrypt_pk(level, pk, R.to_rns(np.array(m, dtype=np.int64), level), v, e0, e1)
+    ve, e1s = int_negacyclic(v, e), int_negacyclic(e1, ctx.s)
+    want = [m[k] + ve[k] + int(e0[k]) + e1s[k] for k in range(R.n)]
+    assert dec_centred(ctx, level, ct) == want
+    # the second component is v pk1 + e1 = v a + e1 on the first level+1 limbs
+    va = int_negacyclic(v, [int(x) for x in a[0]])
+    assert [int(x) for x in ct[1][0]] == [(va[k] + int(e1[k])) % R.q[0] for k in range(R.n)]

@@ -115,6 +115,19 @@ nj_status nj_to_coeff(nj_ctx *ctx, uint64_t *data, int level, int n_polys, void 
  * out->data: device [2][level+1][N]; the result is in evaluation form. */
 nj_status nj_encrypt_sk(nj_ctx *ctx, const uint64_t *m, int level, const uint64_t *a, const int64_t *e,
                         double scale, nj_ct *out, void *stream);
+/* Switching keys in and out of the context (saving and restoring a key set).  A key is
+ * nj_key_words(ctx) = dnum * 2 * (L+1+alpha) * N words: [dnum][2][L+1+alpha][N], digit j's
+ * (b_j, a_j) over q_0..q_L, p_0..p_{alpha-1}, evaluation form; its values are tied to the
+ * context's primes and secret, so only a context of the same parameters and secret can
+ * use it.  Galois element 0 is the relinearisation key.
+ *   export: NJ_ENOKEY if the context holds no key for g; import: adds or replaces it;
+ *   both NJ_EINVAL when words != nj_key_words(ctx).  Synchronous (wait for the device).
+ *   nj_key_list: the Galois elements held (up to max of them into gs), their count in n. */
+size_t nj_key_words(const nj_ctx *ctx);
+nj_status nj_key_export(nj_ctx *ctx, uint32_t galois_elt, uint64_t *host, size_t words);
+nj_status nj_key_import(nj_ctx *ctx, uint32_t galois_elt, const uint64_t *host, size_t words);
+nj_status nj_key_list(const nj_ctx *ctx, uint32_t *gs, int max, int *n);
+
 /* Public key (Sec. 2.1 KeyGen): pk = (-a s + e, a) over q_0..q_L, kept on the device
  * (evaluation form) until the context is destroyed; a new call replaces it.
  *   a: host [(L+1)][N] uniform residues (coefficient form); e: host int64 [N].

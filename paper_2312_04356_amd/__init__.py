@@ -58,6 +58,10 @@ _SIGS = {
     "nj_to_eval": (i32, [vp, vp, i32, i32, vp]),
     "nj_to_coeff": (i32, [vp, vp, i32, i32, vp]),
     "nj_encrypt_sk": (i32, [vp, vp, i32, vp, vp, dbl, ctypes.POINTER(NjCt), vp]),
+    "nj_key_words": (ctypes.c_size_t, [vp]),
+    "nj_key_export": (i32, [vp, u32, vp, ctypes.c_size_t]),
+    "nj_key_import": (i32, [vp, u32, vp, ctypes.c_size_t]),
+    "nj_key_list": (i32, [vp, vp, i32, ctypes.POINTER(i32)]),
     "nj_gen_public_key": (i32, [vp, vp, vp]),
     "nj_encrypt_pk": (i32, [vp, vp, i32, vp, vp, vp, dbl, ctypes.POINTER(NjCt), vp]),
     "nj_decrypt": (i32, [vp, ctypes.POINTER(NjCt), vp, vp]),
@@ -448,6 +452,7 @@ class Ctx:
     def nj_set_secret(self, s):
         s8 = np.ascontiguousarray(s, dtype=np.int8)
         _check(_lib.nj_set_secret(self.ptr, _np_ptr(s8)), "nj_set_secret")
+        self.secret = s8.copy()
 
     def nj_gen_switch_key(self, g, a, e):
         a = np.ascontiguousarray(a, dtype=np.uint64)
@@ -479,6 +484,57 @@ class Ctx:
         _check(_lib.nj_encrypt_sk(self.ptr, _dev_ptr(m_dev), level, _np_ptr(a), _np_ptr(e), float(scale),
                                   ctypes.byref(c), _stream(stream)), "nj_encrypt_sk")
         return out.sync_from(c)
+
+    # -- switching keys in and out (saving and restoring a key set)
+    def nj_key_words(self):
+        return int(_lib.nj_key_words(self.ptr))
+
+    def nj_key_list(self):
+        n = i32()
+        _check(_lib.nj_key_list(self.ptr, None, 0, ctypes.byref(n)), "nj_key_list")
+        out = np.zeros(max(1, n.value), dtype=np.uint32)
+        _check(_lib.nj_key_list(self.ptr, _np_ptr(out), len(out), ctypes.byref(n)), "nj_key_list")
+        return [int(g) for g in out[:n.value]]
+
+    def nj_key_export(self, g):
+        out = np.empty(self.nj_key_words(), dtype=np.uint64)
+        _check(_lib.nj_key_export(self.ptr, int(g), _np_ptr(out), out.size), "nj_key_export")
+        return out
+
+    def nj_key_import(self, g, words):
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        _check(_lib.nj_key_import(self.ptr, int(g), _np_ptr(w), w.size), "nj_key_import")
+
+    def key_fingerprint(self):
+        """what a saved key is tied to: ring degree, primes, digit size and the secret's
+        hash (keys only decrypt under the secret that made them)"""
+        import hashlib
+        sec = hashlib.sha256(np.ascontiguousarray(self.secret, dtype=np.int8).tobytes()).hexdigest() \
+            if getattr(self, "secret", None) is not None else ""
+        return {"N": self.N, "q": [int(x) for x in self.q], "p": [int(x) for x in self.p],
+                "alpha": int(self.alpha), "secret_sha256": sec}
+
+    def save_keys(self, path, gs=None):
+        """every switching key (or those of gs) to an .npz file with the fingerprint"""
+        import json
+        gs = self.nj_key_list() if gs is None else list(gs)
+        arrays = {"key_%d" % g: self.nj_key_export(g) for g in gs}
+        np.savez(path, fingerprint=np.frombuffer(json.dumps(self.key_fingerprint()).encode(), dtype=np.uint8),
+                 **arrays)
+        return gs
+
+    def load_keys(self, path):
+        """keys saved by save_keys into this context; ValueError if the file was written
+        for other parameters or another secret"""
+        import json
+        with np.load(path, allow_pickle=False) as f:
+            fp = json.loads(bytes(f["fingerprint"]).decode())
+            if fp != self.key_fingerprint():
+                raise ValueError("saved keys belong to other parameters or another secret")
+            gs = sorted(int(k[4:]) for k in f.files if k.startswith("key_"))
+            for g in gs:
+                self.nj_key_import(g, f["key_%d" % g])
+        return gs
 
     def nj_gen_public_key(self, a, e):
         a = np.ascontiguousarray(a, dtype=np.uint64)

@@ -1031,6 +1031,51 @@ nj_status nj_encrypt_sk(nj_ctx *c, const uint64_t *m, int level, const uint64_t 
     return NJ_OK;
 }
 
+size_t nj_key_words(const nj_ctx *c)
+{
+    return c ? (size_t)c->dnum * 2 * (c->L + 1 + c->alpha) * c->N : 0;
+}
+
+nj_status nj_key_export(nj_ctx *c, uint32_t g, uint64_t *host, size_t words)
+{
+    if (!c || !host) return fail(NJ_EINVAL, "nj_key_export: null argument");
+    if (words != nj_key_words(c)) return fail(NJ_EINVAL, "nj_key_export: buffer size must be nj_key_words");
+    auto it = c->keys.find(g);
+    if (it == c->keys.end()) return fail(NJ_ENOKEY, "nj_key_export: no key for this Galois element");
+    NJ_HIP(hipDeviceSynchronize());  // work still writing the key finishes first
+    NJ_HIP(hipMemcpy(host, it->second.d, words * 8, hipMemcpyDeviceToHost));
+    return NJ_OK;
+}
+
+nj_status nj_key_import(nj_ctx *c, uint32_t g, const uint64_t *host, size_t words)
+{
+    if (!c || !host) return fail(NJ_EINVAL, "nj_key_import: null argument");
+    if (words != nj_key_words(c)) return fail(NJ_EINVAL, "nj_key_import: buffer size must be nj_key_words");
+    if (g != 0 && (g % 2 == 0 || g >= 2u * c->N)) return fail(NJ_EINVAL, "nj_key_import: bad Galois element");
+    uint64_t *key = nullptr;
+    auto it = c->keys.find(g);
+    if (it != c->keys.end()) key = it->second.d;
+    else {
+        NJ_HIP(hipMalloc(&key, words * 8));
+        c->keys[g].d = key;
+    }
+    NJ_HIP(hipDeviceSynchronize());  // no queued work still reads the key being replaced
+    NJ_HIP(hipMemcpy(key, host, words * 8, hipMemcpyHostToDevice));
+    return NJ_OK;
+}
+
+nj_status nj_key_list(const nj_ctx *c, uint32_t *gs, int max, int *n)
+{
+    if (!c || !n || (max > 0 && !gs)) return fail(NJ_EINVAL, "nj_key_list: bad arguments");
+    int k = 0;
+    for (const auto &kv : c->keys) {
+        if (k < max) gs[k] = kv.first;
+        k++;
+    }
+    *n = k;
+    return NJ_OK;
+}
+
 nj_status nj_gen_public_key(nj_ctx *c, const uint64_t *a, const int64_t *e)
 {
     if (!c || !a || !e) return fail(NJ_EINVAL, "nj_gen_public_key: null argument");

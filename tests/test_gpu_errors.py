@@ -81,3 +81,30 @@ def test_plan_level_and_key_errors(g):
     g.make_keys(plan.galois())
     ctx.nj_conv2d_cins(plan, ct1, ctx.empty_ct(0))
     assert np.isfinite(ct1.scale)
+
+
+def test_keys_saved_and_restored(g, tmp_path):
+    """switching keys written to a file and read into a fresh context of the same
+    parameters and secret rotate word for word as the originals; another secret is refused"""
+    ctx = g.ctx
+    gs = [ctx.nj_galois_elt(r) for r in (1, 3)]
+    g.make_keys(gs)
+    path = str(tmp_path / "keys.npz")
+    saved = ctx.save_keys(path, gs)
+    assert saved == gs and ctx.nj_key_words() == ctx.dnum * 2 * (ctx.L + 1 + ctx.alpha) * ctx.N
+    assert status(lambda: ctx.nj_key_export(ctx.nj_galois_elt(7))) == NJ_ENOKEY
+    fresh = GpuWorkload("small", with_cts=False)
+    assert fresh.ctx.load_keys(path) == sorted(gs)
+    assert sorted(fresh.ctx.nj_key_list()) == sorted(gs)
+    ct = g.encrypt_input(4)
+    ct2 = fresh.encrypt_input(4)
+    assert torch.equal(ct.data, ct2.data)
+    for r in (1, 3):
+        a, b = ctx.empty_ct(4), fresh.ctx.empty_ct(4)
+        ctx.nj_rotate(ct, r, a)
+        fresh.ctx.nj_rotate(ct2, r, b)
+        assert torch.equal(a.data, b.data)
+    other = GpuWorkload("small", with_cts=False)
+    other.ctx.nj_set_secret(-np.asarray(other.ctx.secret))
+    with pytest.raises(ValueError):
+        other.ctx.load_keys(path)

@@ -237,3 +237,57 @@ def test_slot_activation_decompose_equals_chain(rig):
     g.nj_stoc1(stoc1, z, y)
     assert out.level == y.level == le - 6 and out.scale == y.scale
     assert torch.equal(out.data, y.data)
+
+
+def test_block_conv_then_bootstrap_each_full_size():
+    """the larger layer's conv (3x3 64 -> 64 at 56 x 56 in 4 ciphertexts of 16 channels,
+    W = 64, U(-1, 1) weights and inputs) followed by full bootstrapping of every output
+    ciphertext (ModRaise, CoeffToSlot, ModEval of Re and Im, Re + i Im, StoC1), then the
+    fused StoC2 identity plan back to coefficient layout.  The outputs reach ~40, so the
+    bound B = 64 is folded into the conv (weights / B) and multiplied back after
+    decryption: bootstrapping's noise floor (~3e-5 of B) gives ~2e-3 absolute."""
+    g = GpuWorkload("full", with_cts=True, lazy=True)
+    gctx, N, Bf = g.ctx, g.N, 64.0
+    img = RNG.uniform(-1, 1, (64, 56, 56))
+    K = RNG.uniform(-1, 1, (64, 64, 3, 3))
+    want = PL.conv2d_same(img, K)
+    plan = gctx.nj_conv_plan_create_taps(56, 64, 64, PL.taps_same(K / Bf), fuse=True, level=1)
+    lvl, W, C, ell, bi, bo = plan.layout()
+    assert (W, C, bi, bo) == (64, 16, 4, 4) and ell == g.ell
+    le = gctx.L - g.w["cts_groups"] - 11  # ModEval output level
+    stoc1 = gctx.nj_stoc1_plan_create(g.ell, 3, le)
+    s2 = gctx.nj_conv_plan_create_taps(W, C, C, [(c, c, 0, 0, 1.0) for c in range(C)], fuse=1, level=le - 3)
+    a, e = synth.key_randomness(g.q + g.p, N, gctx.dnum, g.w["key_seed"], synth.RELIN_KEY_ID)
+    gctx.nj_gen_switch_key(0, a, e)
+    g.make_keys(sorted(set(g.galois_elements()) | set(plan.galois()) | set(stoc1.galois()) | set(s2.galois())))
+    batch = gctx.empty_batch(bi, 1)
+    for ib in range(bi):
+        ch = img[ib * C:(ib + 1) * C]
+        coeffs = gctx.nj_encode_cins(PL.image_to_slices(ch, W), g.scale)
+        m = torch.empty((2, N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_upload_plain(coeffs, 1, m)
+        ra, re = synth.enc_randomness(g.q[:2], N, 78, 200 + ib)
+        gctx.nj_encrypt_sk(m, 1, ra, re, g.scale, Ct(batch.data[ib], 1))
+    batch.scale = g.scale
+    out = gctx.empty_batch(bo, 0)
+    gctx.nj_conv2d_block(plan, batch, out)
+    worst = 0.0
+    for ob in range(bo):
+        z = gctx.empty_ct(le - 3)
+        gctx.nj_bootstrap(g.cts_plan, 32, 3, None, stoc1, Ct(out.data[ob], 0, scale=out.scale), z)
+        assert z.level == le - 3
+        y = gctx.empty_ct(le - 4)
+        gctx.nj_conv2d_cins(s2, z, y)
+        d = torch.empty((y.level + 1, N), dtype=torch.int64, device=gctx.device)
+        gctx.nj_decrypt(y, d)
+        vals = np.array(O.centred_from_limbs(gctx.to_host(d)[:2], g.q[:2]), dtype=np.float64) / y.scale
+        got = np.zeros((C, 56, 56))
+        for c in range(C):
+            rc = E.bitrev(c, C)
+            for yy in range(56):
+                got[c, yy] = vals[(yy * W + np.arange(56)) * C + rc]
+        err = np.max(np.abs(Bf * got - want[ob * C:(ob + 1) * C]))
+        worst = max(worst, err)
+        print("block conv output %d after bootstrapping: max |B out - conv| %.2e (max |conv| %.1f)"
+              % (ob, err, np.max(np.abs(want[ob * C:(ob + 1) * C]))))
+    assert worst < 1e-2

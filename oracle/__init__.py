@@ -29,9 +29,13 @@ def build():
 
 
 def _load():
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    alt = os.environ.get("ORACLE_LIB")  # another build of ckks_oracle.c (e.g. with sanitizers)
+    if alt:
+        lib = ctypes.CDLL(alt)
+    else:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
     u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
     sig = {
         "or_mulmod": (u64, [u64, u64, u64]),

@@ -352,5 +352,58 @@ def main():
                                                   tot["best"], report["mlp_vs_best"], report["default_vs_best"]))
 
 
+def summary(report, command):
+    """markdown summary of a report written by main()"""
+    out = ["# Plan selection on ResNet-18-shaped convolutions and CoeffToSlot, N = 2^16 (MI355X)", "",
+           "Command (one MI355X, committed files only):", "", "    " + command, "",
+           "Every timing is `nj_time_plan` (HIP events, median of %s after one warm-up) of a random-diagonal plan "
+           "with the structure of the transform, with timing keys (16-buffer pool); convs at level %d."
+           % ("3", report["eval_level"]),
+           "Training set: %d timings (random conv structures, n1 powers of two, hoisted or not, blocks, levels "
+           "1..23, excluding the evaluated layers' structures at level 1; every CoeffToSlot group of depths 2..6 "
+           "with each candidate split, hoisted or not, at its level and one and two below).  Model: 7 -> 64 -> 64 "
+           "-> 1 FP32 ReLU on log(ms), trained by the library's HIP kernels (Adam)." % report["n_timings"], ""]
+    h = report["heldout"]
+    out.append("Held-out (20%%) latency error: all %d samples median %.1f%% (90th percentile %.1f%%); "
+               "CoeffToSlot groups at depth 3: median %.1f%%, at other depths (%d samples): median %.1f%% "
+               "(90th percentile %.1f%%)." % (h["all"]["n"], 100 * h["all"]["median"], 100 * h["all"]["p90"],
+                                              100 * h["cts_d3"]["median"], h["cts_d_not_3"]["n"],
+                                              100 * h["cts_d_not_3"]["median"], 100 * h["cts_d_not_3"]["p90"]))
+    out += ["", "## CoeffToSlot (d groups, each split n1 and hoisting chosen per group)", "",
+            "| plan | groups | n1 per group | hoisted | ms |", "|---|---|---|---|---|"]
+    c = report["cts"]
+    out.append("| default | %d | library default | all | %.3f |" % (c["default"]["groups"], c["default"]["ms"]))
+    for name in ("exhaustive", "mlp", "mlp_shortlist"):
+        r = c[name]
+        label = {"exhaustive": "exhaustive timing", "mlp": "model's pick (untimed)",
+                 "mlp_shortlist": "model top-%d + default, timed" % report["shortlist"]}[name]
+        out.append("| %s | %d | %s | %s | %.3f |" % (label, r["groups"], r["n1"], r["hoist"], r["ms"]))
+    out += ["", "Per depth: predicted (model) and measured best sum of the groups:", "",
+            "| groups | diagonals per group | predicted ms | measured best ms |", "|---|---|---|---|"]
+    for r in c["depths"]:
+        out.append("| %d | %s | %.3f | %.3f |" % (r["groups"], r["diagonals"], r["predicted_ms"],
+                                                  r["best_measured_ms"]))
+    out += ["", "## Convolutions (level %d)" % report["eval_level"], "",
+            "| layer | C | bi x bo | default n1 | ms | best n1/hoist | ms | model n1/hoist | ms | shortlist ms |",
+            "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in report["layers"]:
+        out.append("| %s | %d | %dx%d | %d | %.3f | %d/%s | %.3f | %d/%s | %.3f | %.3f |" % (
+            r["layer"], r["C"], r["bi"], r["bo"], r["default_n1"], r["default_ms"], r["best_n1"],
+            "h" if r["best_hoist"] else "-", r["best_ms"], r["mlp_n1"], "h" if r["mlp_hoist"] else "-",
+            r["mlp_ms"], r["shortlist_ms"]))
+    t = report["totals_ms"]
+    out += ["", "Totals over the convolutions: default %.2f ms, exhaustive best %.2f ms, model's picks %.2f ms, "
+            "model top-%d + default timed %.2f ms.  The default split is already the best on these layers; the "
+            "gain is in CoeffToSlot, where the model picks a deeper decomposition (%d groups) that the default "
+            "does not try." % (t["default"], t["best"], t["mlp"], report["shortlist"], t["shortlist"],
+                               c["mlp"]["groups"]), ""]
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
-    main()
+    import sys
+    if len(sys.argv) >= 3 and sys.argv[1] == "--md":  # render a report: --md REPORT.json "command"
+        with open(sys.argv[2]) as fh:
+            print(summary(json.load(fh), sys.argv[3] if len(sys.argv) > 3 else "(not given)"))
+    else:
+        main()

@@ -158,10 +158,13 @@ nj_status nj_upload_plain(nj_ctx *ctx, const int64_t *coeffs, int level, uint64_
 
 /* ------------------------------------------------------- homomorphic ops */
 
-/* HRot (Sec. 2.1): slots rotated left by r = automorphism 5^r then key switching. */
+/* HRot (Sec. 2.1): slots rotated left by r = automorphism 5^r then key switching.  A
+ * rotation by a multiple of N/2 slots is the identity (g = 1, below). */
 nj_status nj_rotate(nj_ctx *ctx, const nj_ct *in, int r, nj_ct *out, void *stream);
 /* Automorphism X -> X^g followed by hybrid key switching back to s (ModUp, key
- * inner product, ModDown).  Needs the key of g.  in and out may alias. */
+ * inner product, ModDown).  Needs the key of g (NJ_ENOKEY otherwise), except g = 1,
+ * the identity, which copies in to out.  NJ_EINVAL for an even g or g >= 2N.  in and
+ * out may alias. */
 nj_status nj_apply_galois(nj_ctx *ctx, const nj_ct *in, uint32_t galois_elt, nj_ct *out, void *stream);
 /* nj_apply_galois for callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid hipMalloc): the same kernels and the

@@ -69,6 +69,11 @@ nj_status ks_one(nj_ctx *c, int l, const uint64_t *d, uint32_t g, const uint64_t
 // (tau_g(c0), tau_g(c1)) switched back to s; in and out may alias.
 nj_status apply_galois(nj_ctx *c, int l, const uint64_t *in, uint32_t g, uint64_t *out, Arena A, hipStream_t s)
 {
+    if (g % 2 == 0 || g >= 2u * (uint32_t)c->N) return fail(NJ_EINVAL, "Galois element must be odd and below 2N");
+    if (g == 1) {  // X -> X: the identity (a rotation by a multiple of N/2 slots), no key switch
+        if (out != in) NJ_HIP(hipMemcpyAsync(out, in, 2 * (size_t)c->N * (l + 1) * 8, hipMemcpyDeviceToDevice, s));
+        return NJ_OK;
+    }
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
     MultiBufs M;
@@ -245,6 +250,10 @@ nj_status mac_general(nj_ctx *c, int l, const std::vector<const uint64_t *> &bab
 {
     const size_t clen = 2 * (size_t)c->N * (l + 1);
     const int nb = (int)baby.size();
+    if (nb == 0 || ent.empty()) {  // every diagonal zero: every inner sum is the zero ciphertext
+        if (ng > 0) NJ_HIP(launch_zero(c, inner, (size_t)ng * clen, s));
+        return NJ_OK;
+    }
     for (int g0 = 0; g0 < ng; g0 += NJ_MAX_GIANT) {
         const int gn = std::min(NJ_MAX_GIANT, ng - g0);
         for (int b0 = 0; b0 == 0 || b0 < nb; b0 += NJ_MAX_BABY) {
@@ -548,6 +557,12 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
 nj_status apply_galois_batch(nj_ctx *c, int l, int K, const uint64_t *in, uint32_t g, uint64_t *out, Arena A,
                              hipStream_t s)
 {
+    if (g % 2 == 0 || g >= 2u * (uint32_t)c->N) return fail(NJ_EINVAL, "Galois element must be odd and below 2N");
+    if (g == 1) {  // the identity, as in apply_galois
+        if (out != in)
+            NJ_HIP(hipMemcpyAsync(out, in, (size_t)K * 2 * c->N * (l + 1) * 8, hipMemcpyDeviceToDevice, s));
+        return NJ_OK;
+    }
     const uint64_t *key = key_of(c, g);
     if (!key) return fail(NJ_ENOKEY, "no switching key for Galois element " + std::to_string(g));
     if (K < 1 || K > NJ_MAX_JOBS) return fail(NJ_EINVAL, "batch size out of range");

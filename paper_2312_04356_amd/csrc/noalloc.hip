@@ -55,7 +55,9 @@ extern "C" nj_status nj_apply_galois_noalloc(nj_ctx *c, const nj_ct *in, uint32_
         return fail(NJ_EUNSUPPORTED, "nj_apply_galois_noalloc: this key switch needs " + std::to_string(need) +
                                          " scratch words, the static buffer holds " +
                                          std::to_string((size_t)NJ_NOALLOC_WORDS));
-    if (!key_of(c, g)) return fail(NJ_ENOKEY, "nj_apply_galois_noalloc: no switching key for that element");
+    if (g % 2 == 0 || g >= 2u * (uint32_t)c->N)
+        return fail(NJ_EINVAL, "nj_apply_galois_noalloc: Galois element must be odd and below 2N");
+    if (g != 1 && !key_of(c, g)) return fail(NJ_ENOKEY, "nj_apply_galois_noalloc: no switching key for that element");
     if (c->device < 0 || c->device >= NJ_NOALLOC_DEVICES)
         return fail(NJ_EUNSUPPORTED, "nj_apply_galois_noalloc: device index out of range");
     uint64_t *ptr;

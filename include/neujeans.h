@@ -376,16 +376,28 @@ typedef struct {
  *     levels (each baby and giant rotation key read once for up to 16 jobs; ModUp and
  *     ModDown batched per level), the rescale computes only the limb the level drop
  *     keeps, and every conv output goes through batched CoeffToSlot.
- * Both modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
+ *   mode 2, concurrent: each job as in mode 0, the jobs spread over the context's
+ *     worker streams (nj_batch_workers, default 4) by longest-first assignment, each
+ *     worker with its own part of the scratch (workers x the plain scratch); the
+ *     workers fork from `stream` and join back into it, so work queued on `stream`
+ *     afterwards sees every output.
+ * All modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
  * NJ_ELEVEL (input level outside 1..plan level), NJ_ENOKEY, NJ_ENOMEM. */
 nj_status nj_batch_run(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, void *stream);
+/* Worker streams of mode 2 (1..4; NJ_EINVAL otherwise).  Streams run at the default
+ * priority.  Concurrent calls on one context must not overlap (they share the
+ * workers and the scratch). */
+nj_status nj_batch_workers(nj_ctx *ctx, int n_streams);
 
-/* Persistent batched execution: the mode-1 schedule captured once into a HIP graph
- * that owns its scratch memory; nj_batch_launch replays it with no host work per job.
- * Capture computes nothing; the jobs' buffers, plans and keys must stay in place for
- * the batch's lifetime.  Replays on one batch must not overlap. */
+/* Persistent batched execution: a schedule captured once into a HIP graph that owns
+ * its scratch memory; nj_batch_launch replays it with no host work per job.
+ * nj_batch_create captures mode 1, nj_batch_create_mode the given mode (0, 1 or 2; a
+ * mode-2 graph holds the workers' branches).  Capture computes nothing; the jobs'
+ * buffers, plans and keys must stay in place for the batch's lifetime.  Replays on
+ * one batch must not overlap. */
 typedef struct nj_batch nj_batch;
 nj_status nj_batch_create(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, nj_batch **out);
+nj_status nj_batch_create_mode(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, nj_batch **out);
 nj_status nj_batch_launch(nj_batch *batch, void *stream);
 void nj_batch_destroy(nj_batch *batch);
 

@@ -94,6 +94,8 @@ _SIGS = {
     "nj_conv2d_block": (i32, [vp, vp, ctypes.POINTER(NjCt), ctypes.POINTER(NjCt), vp]),
     "nj_drop_level": (i32, [vp, ctypes.POINTER(NjCt), i32, ctypes.POINTER(NjCt), vp]),
     "nj_batch_run": (i32, [vp, vp, vp, i32, i32, vp]),
+    "nj_batch_workers": (i32, [vp, i32]),
+    "nj_batch_create_mode": (i32, [vp, vp, vp, i32, i32, ctypes.POINTER(vp)]),
     "nj_batch_create": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
     "nj_batch_launch": (i32, [vp, vp]),
     "nj_batch_destroy": (None, [vp]),
@@ -724,13 +726,16 @@ class Ctx:
                "nj_batch_run")
         self._sync_jobs(jobs, arr)
 
-    def nj_batch_create(self, cts_plan, jobs):
+    def nj_batch_create(self, cts_plan, jobs, mode=1):
         arr = self._jobs(jobs)
         h = vp()
-        _check(_lib.nj_batch_create(self.ptr, cts_plan.ptr, ctypes.cast(arr, vp), len(jobs), ctypes.byref(h)),
-               "nj_batch_create")
+        _check(_lib.nj_batch_create_mode(self.ptr, cts_plan.ptr, ctypes.cast(arr, vp), len(jobs), int(mode),
+                                         ctypes.byref(h)), "nj_batch_create_mode")
         self._sync_jobs(jobs, arr)
         return Batch(h, (cts_plan, jobs))
+
+    def nj_batch_workers(self, n):
+        _check(_lib.nj_batch_workers(self.ptr, int(n)), "nj_batch_workers")
 
     # -- bootstrapping after CoeffToSlot
     def nj_hmult(self, a, b, out, stream=None):

@@ -429,6 +429,96 @@ nj_status run_plain(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Ar
     return NJ_OK;
 }
 
+// ------------------------------------------------ concurrent plain schedule
+//
+// Mode 2: every job runs as in the plain schedule (so the outputs are bit-identical),
+// but the jobs are spread over worker streams, each with its own part of the scratch:
+// the latency-bound kernels of different jobs (transform tile passes, the fused key
+// inner products at two waves per SIMD, ModDown combines) then fill the GPU together.
+// The workers fork from the caller's stream and join back into it through events, so
+// the schedule also captures into one HIP graph.
+
+constexpr int kMaxWorkers = 4;  // hardware queues per process on the target (GPU_MAX_HW_QUEUES)
+
+// estimated relative cost of a job, to balance the workers: key switches x limbs of
+// its conv, plus the CoeffToSlot every output block runs at the top levels
+double job_cost(const nj_plan *cts, const nj_job &j)
+{
+    const nj_lt_t lt = at_level(j.conv->lts[0], j.in.level);
+    const double conv = (double)(lt.level + 1) * ((double)lt.babies.size() * lt.bi + (double)lt.giants.size() * lt.bo);
+    double ct = 0;
+    for (const auto &g : cts->lts) ct += (double)(g.level + 1) * (double)(g.babies.size() + g.giants.size());
+    return conv + lt.bo * ct;
+}
+
+nj_status workers_ready(nj_ctx *c)
+{
+    while ((int)c->workers.size() < kMaxWorkers) {
+        hipStream_t w;
+        hipEvent_t e;
+        NJ_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+        c->workers.push_back(w);
+        NJ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->worker_done.push_back(e);
+    }
+    if (!c->fork_ev) NJ_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    return NJ_OK;
+}
+
+size_t worker_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+{
+    return (plain_words(c, cts, jobs, n) + 255) / 256 * 256;  // each worker's part 2 KiB aligned
+}
+
+int n_workers(const nj_ctx *c, int n) { return std::max(1, std::min(std::min(c->batch_workers, kMaxWorkers), n)); }
+
+nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A0, hipStream_t s)
+{
+    nj_status st = workers_ready(c);
+    if (st) return st;
+    const int W = n_workers(c, n);
+    const size_t per = worker_words(c, cts, jobs, n);
+    if (A0.left < per * W) return fail(NJ_ENOMEM, "scratch too small");
+    // longest-processing-time assignment: the costliest job to the least-loaded worker
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(n);
+    for (int z = 0; z < n; z++) cost[z] = job_cost(cts, jobs[z]);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(W, 0.0);
+    std::vector<std::vector<int>> part(W);
+    for (int z : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        part[k].push_back(z);
+        load[k] += cost[z];
+    }
+    NJ_HIP(hipEventRecord(c->fork_ev, s));
+    for (int k = 0; k < W; k++) NJ_HIP(hipStreamWaitEvent(c->workers[k], c->fork_ev, 0));
+    for (int k = 0; k < W && !st; k++)
+        for (int z : part[k]) {
+            st = run_plain(c, cts, &jobs[z], 1, Arena{A0.p + (size_t)k * per, per}, c->workers[k]);
+            if (st) break;
+        }
+    // the workers always join back, also after an error, so no stream is left forked
+    for (int k = 0; k < W; k++) {
+        NJ_HIP(hipEventRecord(c->worker_done[k], c->workers[k]));
+        NJ_HIP(hipStreamWaitEvent(s, c->worker_done[k], 0));
+    }
+    return st;
+}
+
+size_t schedule_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, int mode)
+{
+    if (mode == 2) return worker_words(c, cts, jobs, n) * n_workers(c, n);
+    return mode ? batched_words(c, cts, jobs, n) : plain_words(c, cts, jobs, n);
+}
+
+nj_status run_schedule(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, int mode, Arena A, hipStream_t s)
+{
+    if (mode == 2) return run_concurrent(c, cts, jobs, n, A, s);
+    return mode ? run_batched(c, cts, jobs, n, A, s) : run_plain(c, cts, jobs, n, A, s);
+}
+
 void set_outputs(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
 {
     for (int z = 0; z < n; z++) {
@@ -448,22 +538,36 @@ nj_status nj_batch_run(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, int m
 {
     nj_status st = check_jobs(c, cts, jobs, n);
     if (st) return st;
-    if (mode != 0 && mode != 1) return fail(NJ_EINVAL, "nj_batch_run: mode must be 0 (plain) or 1 (batched)");
+    if (mode < 0 || mode > 2) return fail(NJ_EINVAL, "nj_batch_run: mode must be 0 (plain), 1 (batched) or 2 (concurrent)");
     bool ok;
-    Arena A = arena_for(c, mode ? batched_words(c, cts, jobs, n) : plain_words(c, cts, jobs, n), ok);
+    Arena A = arena_for(c, schedule_words(c, cts, jobs, n, mode), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
-    st = mode ? run_batched(c, cts, jobs, n, A, S(stream)) : run_plain(c, cts, jobs, n, A, S(stream));
+    st = run_schedule(c, cts, jobs, n, mode, A, S(stream));
     if (st) return st;
     set_outputs(c, cts, jobs, n);
     return NJ_OK;
 }
 
+nj_status nj_batch_workers(nj_ctx *c, int n)
+{
+    if (!c || n < 1 || n > kMaxWorkers) return fail(NJ_EINVAL, "nj_batch_workers: 1..4 worker streams");
+    c->batch_workers = n;
+    return NJ_OK;
+}
+
 nj_status nj_batch_create(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, nj_batch **out)
+{
+    return nj_batch_create_mode(c, cts, jobs, n, 1, out);
+}
+
+nj_status nj_batch_create_mode(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, int mode, nj_batch **out)
 {
     nj_status st = check_jobs(c, cts, jobs, n);
     if (st) return st;
     if (!out) return fail(NJ_EINVAL, "nj_batch_create: null output");
-    const size_t words = batched_words(c, cts, jobs, n);
+    if (mode < 0 || mode > 2) return fail(NJ_EINVAL, "nj_batch_create: mode must be 0, 1 or 2");
+    if (mode == 2 && (st = workers_ready(c))) return st;
+    const size_t words = schedule_words(c, cts, jobs, n, mode);
     nj_batch *b = new nj_batch();
     b->c = c;
     auto bail = [&](nj_status e) {
@@ -479,7 +583,7 @@ nj_status nj_batch_create(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, nj
         c->prof = prof;
         return bail(fail(NJ_EDEVICE, "nj_batch_create: stream capture"));
     }
-    st = run_batched(c, cts, jobs, n, Arena{b->buf, words}, b->cap);
+    st = run_schedule(c, cts, jobs, n, mode, Arena{b->buf, words}, b->cap);
     const hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
     c->prof = prof;
     if (st) return bail(st);

@@ -374,6 +374,9 @@ void nj_ctx_destroy(nj_ctx *c)
     fr(c->scratch.buf);
     for (auto &r : c->prof_recs) (void)hipEventDestroy(r.a), (void)hipEventDestroy(r.b);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto w : c->workers) (void)hipStreamDestroy(w);
+    for (auto e : c->worker_done) (void)hipEventDestroy(e);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     delete c;
 }
 

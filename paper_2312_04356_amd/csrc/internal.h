@@ -235,6 +235,12 @@ struct nj_ctx {
     // intermediate ciphertexts of the composite calls (Algorithm 1, bootstrapping)
     uint64_t *layer_buf = nullptr;
     size_t layer_words = 0;
+    // worker streams of the concurrent job schedule (nj_batch_run mode 2), made on
+    // first use at the default priority, with a fork event and one join event each
+    int batch_workers = 4;
+    std::vector<hipStream_t> workers;
+    std::vector<hipEvent_t> worker_done;
+    hipEvent_t fork_ev = nullptr;
     // live profiling (nj_prof_*)
     bool prof = false;
     std::vector<nj::ProfRec> prof_recs;

@@ -73,7 +73,8 @@ def test_job_at_lower_level_matches_oracle():
 
 
 def run_three_ways(g, plans, levels):
-    """jobs (plan, level) -> outputs of plain, batched and three graph replays"""
+    """jobs (plan, level) -> outputs of plain, batched and concurrent (3 worker streams)
+    runs, three replays of the batched graph and two of the concurrent graph"""
     gctx = g.ctx
     jobs = []
     for (plan, bi, bo), lvl in zip(plans, levels):
@@ -84,7 +85,8 @@ def run_three_ways(g, plans, levels):
         re, im = out_cts(g, bo)
         jobs.append((plan, x, re, im))
     results = {}
-    for mode in (0, 1):
+    gctx.nj_batch_workers(3)
+    for mode in (0, 1, 2):
         gctx.nj_batch_run(g.cts_plan, jobs, mode)
         torch.cuda.synchronize()
         results[mode] = [(j[2].data.clone(), j[3].data.clone()) for j in jobs]
@@ -104,6 +106,18 @@ def run_three_ways(g, plans, levels):
         reps.append([(j[2].data.clone(), j[3].data.clone()) for j in jobs])
         _ = torch.ones(1 << 20, device=gctx.device).sum().item()  # eager work between replays
     del batch
+    batch = gctx.nj_batch_create(g.cts_plan, jobs, mode=2)
+    for r in range(2):
+        for j in jobs:
+            j[2].data.zero_()
+            j[3].data.zero_()
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        reps.append([(j[2].data.clone(), j[3].data.clone()) for j in jobs])
+        _ = torch.ones(1 << 20, device=gctx.device).sum().item()
+    del batch
+    gctx.nj_batch_workers(4)
     return results, reps
 
 
@@ -127,6 +141,7 @@ def test_plain_batched_graph_agree_small():
     levels = [6, 1, 3, 5, 3, 6, 1, 4]
     res, reps = run_three_ways(g, plans, levels)
     assert_same(res[0], res[1], "batched vs plain")
+    assert_same(res[0], res[2], "concurrent vs plain")
     for r, rep in enumerate(reps):
         assert_same(res[1], rep, "graph replay %d" % r)
 
@@ -142,6 +157,7 @@ def test_plain_batched_graph_agree_full():
     levels = [7, 12, 12, 23, 16]
     res, reps = run_three_ways(g, plans, levels)
     assert_same(res[0], res[1], "batched vs plain")
+    assert_same(res[0], res[2], "concurrent vs plain")
     for r, rep in enumerate(reps):
         assert_same(res[1], rep, "graph replay %d" % r)
 

@@ -1,5 +1,6 @@
 """A ResNet-18-shaped network on a 224 x 224 x 3 input, end to end through the library at
-N = 2^16 (the analog of Table 2's NeuJeans column, timing only: synthetic weights).
+N = 2^16 (the analog of Table 2's NeuJeans column with synthetic weights): the time of
+every phase, and the decrypted output against the same network computed in FP64.
 
 Every conv is a fused CinS conv (Sec. 4: K' = S'K, block convs of Sec. 3.3.4) at level 1
 followed by bootstrapping as in Algorithm 1: CoeffToSlot, ModEval of Re and Im, the
@@ -17,8 +18,9 @@ StoC1, and the stride-2 conv is a unit-stride conv over the phase channels.
 A shortcut joins its block's second conv output in coefficient form at level 0, before
 that output's bootstrapping: the identity as the fused conv of the identity kernel
 (depthwise 1x1 of ones, fused with StoC2), the downsampling shortcut as its 1x1/2 conv
-on the same phase images as the block's first conv.  Weights U(-1, 1) / sqrt(f^2 c_in)
-(synthetic, seed 1005), input U(-1, 1).  Phases are timed by HIP events around each
+on the same phase images as the block's first conv.  Weights U(-1, 1) (synthetic, seed
+1005), each conv's (and each shortcut's) scaled so that its output on this input has rms
+0.2 (the role BN folding plays in a trained network); input U(-1, 1).  Phases are timed by HIP events around each
 library call (one call at a time), in Table 2's rows.
 
     python -m paper_2312_04356_amd.network --out gpurun_out/resnet18.json [--md gpurun_out/resnet18.md]
@@ -36,6 +38,7 @@ from . import Ct, nj_layer_masks
 from .workload import GpuWorkload
 
 K_MOD, R_DA = 32, 3
+RMS_OUT = 0.2    # rms of every conv's output on the input (weights scaled to it)
 LVL_MASK = 9     # ModEval output level (CoeffToSlot 23 -> 20, ModEval 20 -> 9)
 LVL_DEC = 7      # decomposition plans (after mask and square)
 LVL_STOC = 4     # StoC1 plans (3 groups -> level 1, the conv level)
@@ -82,13 +85,14 @@ class Net:
         self.counts[phase] = self.counts.get(phase, 0) + 1
         return out
 
-    def mask(self, W, C, w0):
-        key = (W, C, w0)
+    def mask(self, W, C, w0, r):
+        """Algorithm 1's zero-padding masks times r (the scale correction below)"""
+        key = (W, C, w0, r)
         if key not in self.masks:
             c, pts = self.c, []
             for mk in nj_layer_masks(N_LOG, W, C, w0):
                 t = self.torch.empty((LVL_MASK + 1, self.N), dtype=self.torch.int64, device=c.device)
-                c.nj_upload_plain(c.nj_encode_slots(mk, float(self.g.q[LVL_MASK])), LVL_MASK, t)
+                c.nj_upload_plain(c.nj_encode_slots(r * mk, float(self.g.q[LVL_MASK])), LVL_MASK, t)
                 c.nj_to_eval(t, LVL_MASK, 1)
                 pts.append(t)
             self.masks[key] = pts
@@ -108,6 +112,21 @@ class Net:
         p = self.c.nj_conv_plan_create_layer(w0, K, stride=stride, depthwise=depthwise, level=1)
         self.plans.append(p)
         return p
+
+    def calib(self, K, x, stride=1, depthwise=False):
+        """K scaled so that its conv's FP64 output on x has rms RMS_OUT (the role BN
+        folding plays in a trained network: square activations neither vanish nor blow
+        up), and that output"""
+        z = conv_fp64(x, K, stride, depthwise)
+        g = RMS_OUT / np.sqrt(np.mean(z ** 2))
+        return K * g, z * g
+
+    def layer(self, name, w0, K, B, stride=1, depthwise=False):
+        """the plan of a conv whose output (or the residual sum it enters) is bounded by
+        B: the weights are divided by B, which the masks after ModEval restore (Algorithm
+        1), so ModEval sees |m / B| <= 1"""
+        self.P[name] = self.conv_plan(w0, K / B, stride, depthwise)
+        self.K[name] = (K, stride, depthwise)
 
     # ------------------------------------------------------------ the layer steps
     def conv(self, plan, xs):
@@ -135,11 +154,19 @@ class Net:
             outs.append(o)
         return outs
 
-    def bootstrap(self, ys, W, C, w0, act, decompose):
-        """level-0 conv outputs -> CinS inputs of the next layer (level 1)"""
+    def bootstrap(self, ys, W, C, w0, act, decompose, B=1.0):
+        """level-0 conv outputs -> CinS inputs of the next layer (level 1).  ModEval's
+        output scale is a fixed multiple of its input's, so each layer would drift the
+        scale; the masks carry the correction instead: they are encoded times
+        r = T' / (ModEval's scale) and the masked result is read at scale T', the scale
+        from which the square (or, without activation, the level drop) lands on the
+        input scale T.  Every layer then returns T, and a residual sum adds two
+        ciphertexts at one scale.  The masks also carry B, the bound folded into the
+        layer's weights."""
         c, L = self.c, self.c.L
         lo = L - 3
-        mre, mim = self.mask(W, C, w0)
+        T = self.g.scale
+        T_pre = math.sqrt(T * float(self.g.q[LVL_MASK - 1])) if act else T
         dec = self.dec_plans(W, C) if decompose else None
         st1 = self.stoc1_plan(W // 2 if decompose else W)
         outs = []
@@ -147,9 +174,10 @@ class Net:
             re, im = c.empty_ct(lo), c.empty_ct(lo)
             self.timed("CtoS+ModEval", lambda: c.nj_coeff_to_slot(self.g.cts_plan, y, re, im))
             halves = []
-            for part, mk in ((re, mre), (im, mim)):
+            for half, part in enumerate((re, im)):
                 e = c.empty_ct(LVL_MASK)
                 self.timed("CtoS+ModEval", lambda: c.nj_eval_mod(part, K_MOD, R_DA, None, e))
+                mk = self.mask(W, C, w0, B * T_pre / e.scale)[half]
                 t, m = c.empty_ct(LVL_MASK), c.empty_ct(LVL_MASK - 1)
 
                 def masked():
@@ -157,11 +185,12 @@ class Net:
                     t.scale = e.scale * float(self.g.q[LVL_MASK])  # masks encoded at q_l keep the scale
                     return c.nj_rescale(t, m)
                 self.timed("Activation", masked)
+                m.scale = T_pre  # the integers hold value * mask * r * e.scale = value * mask * T_pre
+                sq = c.empty_ct(LVL_MASK - 2)
                 if act:
-                    sq = c.empty_ct(LVL_MASK - 2)
                     self.timed("Activation", lambda: c.nj_hmult(m, m, sq))
+                    sq.scale = T  # T_pre^2 / q_l, equal to T up to the last bit of a double
                 else:
-                    sq = c.empty_ct(LVL_MASK - 2)
                     c.nj_drop_level(m, LVL_MASK - 2, sq)
                 if dec is not None:
                     d = c.empty_ct(LVL_DEC - 1)
@@ -183,29 +212,56 @@ class Net:
     # ------------------------------------------------------------ the network
     def build(self):
         """plans of every layer (timed separately from inference)"""
-        P = {}
-        P["conv1"] = self.conv_plan(224, self.weights((64, 3, 7, 7), 49 * 3), stride=2)
-        P["pool"] = self.conv_plan(112, np.full((64, 3, 3), 1.0 / 9.0), stride=2, depthwise=True)
+        self.P, self.K, self.B = {}, {}, {}
+        self.img = synth.uniform_real((3, 224, 224), self.seed, 0)
+
+        def bound(z):
+            return 2.0 ** math.ceil(math.log2(max(1.05 * float(np.max(np.abs(z))), 1e-3)))
+        K, z = self.calib(self.weights((64, 3, 7, 7), 49 * 3), self.img, 2)
+        self.B["conv1"] = bound(z)
+        self.layer("conv1", 224, K, self.B["conv1"], stride=2)
+        x = z ** 2
+        K = np.full((64, 3, 3), 1.0 / 9.0)
+        z = conv_fp64(x, K, 2, True)
+        self.B["pool"] = bound(z)
+        self.layer("pool", 112, K, self.B["pool"], stride=2, depthwise=True)
+        x = z
         for s, (ch, w0) in enumerate(((64, 56), (128, 28), (256, 14), (512, 7))):
             ci = 64 if s == 0 else ch // 2
             win = w0 if s == 0 else 2 * w0
+            st = 1 if s == 0 else 2
+            # block 0: its shortcut is the identity kernel in stage 0, 1x1 stride 2 later
+            Ka, za = self.calib(self.weights((ch, ci, 3, 3), 9 * ci), x, st)
             if s == 0:
-                P["s0b0a"] = self.conv_plan(w0, self.weights((ch, ci, 3, 3), 9 * ci))
+                Ks, zs = self.calib(np.ones((ch, 1, 1)), x, 1, True)
             else:
-                P["s%db0a" % s] = self.conv_plan(win, self.weights((ch, ci, 3, 3), 9 * ci), stride=2)
-                P["s%dsc" % s] = self.conv_plan(win, self.weights((ch, ci, 1, 1), ci), stride=2)
-            P["s%db0b" % s] = self.conv_plan(w0, self.weights((ch, ch, 3, 3), 9 * ch))
-            P["s%db1a" % s] = self.conv_plan(w0, self.weights((ch, ch, 3, 3), 9 * ch))
-            P["s%db1b" % s] = self.conv_plan(w0, self.weights((ch, ch, 3, 3), 9 * ch))
-            P["s%did" % s] = self.conv_plan(w0, np.ones((ch, 1, 1)), depthwise=True)
-        self.P = P
+                Ks, zs = self.calib(self.weights((ch, ci, 1, 1), ci), x, 2)
+            Kb, zb = self.calib(self.weights((ch, ch, 3, 3), 9 * ch), za ** 2)
+            self.B["s%db0a" % s], self.B["s%db0" % s] = bound(za), bound(zb + zs)
+            self.layer("s%db0a" % s, win, Ka, self.B["s%db0a" % s], stride=st)
+            self.layer("s%dsc" % s, win if s else w0, Ks, self.B["s%db0" % s], stride=st, depthwise=s == 0)
+            self.layer("s%db0b" % s, w0, Kb, self.B["s%db0" % s])
+            x = (zb + zs) ** 2
+            # block 1: the identity kernel as shortcut
+            Ka, za = self.calib(self.weights((ch, ch, 3, 3), 9 * ch), x)
+            Ks, zs = self.calib(np.ones((ch, 1, 1)), x, 1, True)
+            Kb, zb = self.calib(self.weights((ch, ch, 3, 3), 9 * ch), za ** 2)
+            self.B["s%db1a" % s], self.B["s%db1" % s] = bound(za), bound(zb + zs)
+            self.layer("s%db1a" % s, w0, Ka, self.B["s%db1a" % s])
+            self.layer("s%did" % s, w0, Ks, self.B["s%db1" % s], depthwise=True)
+            self.layer("s%db1b" % s, w0, Kb, self.B["s%db1" % s])
+            x = (zb + zs) ** 2
+        # the identity kernel fused with StoC2, unscaled: reads the last output back
+        self.readout = self.conv_plan(7, np.ones((512, 1, 1)), depthwise=True)
+        P = self.P
         # keys of every rotation the plans, StoC1, the decompositions and CoeffToSlot use
         for W, C in ((128, 4), (64, 16), (32, 64), (16, 256)):
             self.dec_plans(W, C)
         for W in (64, 32, 16, 8):
             self.stoc1_plan(W)
         gs = set(self.g.cts_plan.galois())
-        for p in list(P.values()) + list(self.stoc1.values()) + [d for v in self.dec.values() for d in v]:
+        for p in list(P.values()) + [self.readout] + list(self.stoc1.values()) + [d for v in self.dec.values()
+                                                                                  for d in v]:
             gs |= set(p.galois())
         self.g.make_keys(sorted(gs))
         return len(gs)
@@ -214,7 +270,7 @@ class Net:
         """the client's encryption: the input's phase images (12 channels at 112 x 112,
         W = 128, C = 4: three ciphertexts) in real CinS at level 1"""
         c = self.c
-        img = synth.uniform_real((3, 224, 224), self.seed, 0)
+        img = self.img
         ph = np.zeros((12, 112, 112))
         for i in range(3):
             for a in (0, 1):
@@ -236,31 +292,85 @@ class Net:
         P = self.P
         self.times, self.counts = {}, {}
         # stem: conv1 (W = 128, C = 4 outputs: 16 ciphertexts), decomposed for the pooling
+        B = self.B
         y = self.conv(P["conv1"], xs)
-        x = self.bootstrap(y, 128, 4, 112, act=True, decompose=True)
+        x = self.bootstrap(y, 128, 4, 112, act=True, decompose=True, B=B["conv1"])
         y = self.conv(P["pool"], x)  # 3x3/2 average pooling: 56 x 56, 4 ciphertexts
-        x = self.bootstrap(y, 64, 16, 56, act=False, decompose=False)
+        x = self.bootstrap(y, 64, 16, 56, act=False, decompose=False, B=B["pool"])
         for s, (ch, w0) in enumerate(((64, 56), (128, 28), (256, 14), (512, 7))):
             W = padded(w0, 1)
             C = self.N // (W * W)
             # block 0
-            if s == 0:
-                h = self.bootstrap(self.conv(P["s0b0a"], x), W, C, w0, act=True, decompose=False)
-                sc = self.conv(P["s0id"], x)
-            else:
-                h = self.bootstrap(self.conv(P["s%db0a" % s], x), W, C, w0, act=True, decompose=False)
-                sc = self.conv(P["s%dsc" % s], x)
-            x = self.bootstrap(self.add(self.conv(P["s%db0b" % s], h), sc), W, C, w0, act=True, decompose=False)
+            h = self.bootstrap(self.conv(P["s%db0a" % s], x), W, C, w0, act=True, decompose=False,
+                               B=B["s%db0a" % s])
+            sc = self.conv(P["s%dsc" % s], x)
+            x = self.bootstrap(self.add(self.conv(P["s%db0b" % s], h), sc), W, C, w0, act=True, decompose=False,
+                               B=B["s%db0" % s])
             # block 1; the last bootstrapping of a stage decomposes for the next stride-2 layer
-            h = self.bootstrap(self.conv(P["s%db1a" % s], x), W, C, w0, act=True, decompose=False)
+            h = self.bootstrap(self.conv(P["s%db1a" % s], x), W, C, w0, act=True, decompose=False,
+                               B=B["s%db1a" % s])
             sc = self.conv(P["s%did" % s], x)
-            x = self.bootstrap(self.add(self.conv(P["s%db1b" % s], h), sc), W, C, w0, act=True, decompose=s < 3)
+            x = self.bootstrap(self.add(self.conv(P["s%db1b" % s], h), sc), W, C, w0, act=True, decompose=s < 3,
+                               B=B["s%db1" % s])
         return x
+
+
+def conv_fp64(x, K, stride=1, depthwise=False):
+    """'same' zero-padded cross-correlation with the given stride (output width
+    ceil(w / stride)), K [c_out][c_in][f][f] or depthwise [c][f][f], in FP64"""
+    f = K.shape[-1]
+    p = (f - 1) // 2
+    ci, w, _ = x.shape
+    wo = (w + stride - 1) // stride
+    xp = np.pad(x, ((0, 0), (p, p), (p, p)))
+    taps = [xp[:, u:u + stride * wo:stride, v:v + stride * wo:stride] for u in range(f) for v in range(f)]
+    if depthwise:
+        return sum(K[:, u, v, None, None] * taps[u * f + v] for u in range(f) for v in range(f))
+    cols = np.stack(taps, axis=1).reshape(ci * f * f, wo * wo)
+    return (K.reshape(K.shape[0], ci * f * f) @ cols).reshape(K.shape[0], wo, wo)
+
+
+def forward_fp64(net):
+    """the network in FP64 on the same input and weights: conv, square, the pooling,
+    the residual sums, as the homomorphic inference computes them"""
+    def cv(name, x):
+        K, stride, dw = net.K[name]
+        return conv_fp64(x, K, stride, dw)
+    x = cv("conv1", net.img) ** 2
+    x = cv("pool", x)
+    for s in range(4):
+        h = cv("s%db0a" % s, x) ** 2
+        sc = cv("s%dsc" % s, x)
+        x = (cv("s%db0b" % s, h) + sc) ** 2
+        h = cv("s%db1a" % s, x) ** 2
+        x = (cv("s%db1b" % s, h) + cv("s%did" % s, x)) ** 2
+    return x
+
+
+def decode_output(net, xs):
+    """the last layer's output (512 channels at 7 x 7) brought to coefficient layout by
+    the identity plan fused with StoC2, decrypted and read at (y W + x) C + rev_C(c)"""
+    c = net.c
+    ys = net.conv(net.readout, xs)
+    _, W, C, _, _, _ = net.readout.layout()
+    bits = C.bit_length() - 1
+    rev = np.array([int(format(k, "0%db" % bits)[::-1], 2) for k in range(C)])
+    q0 = float(net.g.q[0])
+    out = []
+    for k, y in enumerate(ys):
+        d = net.torch.empty((1, net.N), dtype=net.torch.int64, device=c.device)
+        c.nj_decrypt(y, d)
+        v = c.to_host(d)[0].astype(np.float64)
+        v[v > q0 / 2] -= q0
+        v /= y.scale
+        idx = (np.arange(7)[:, None] * W + np.arange(7)[None, :])[None] * C + rev[:, None, None]
+        out.append(v[idx])
+    return np.concatenate(out)[:512]
 
 
 def summary(res, command):
     rows = ["CtoS+ModEval", "StoC", "Conv2d", "Activation", "Decomp", "ETC"]
-    lines = ["# ResNet-18-shaped network at N = 2^16, end to end (Table 2 analog, timing only)", "",
+    lines = ["# ResNet-18-shaped network at N = 2^16, end to end (Table 2 analog, synthetic weights)", "",
              "Command (repository root): `%s`" % command, "",
              "One MI355X; 224 x 224 x 3 synthetic input, synthetic weights; every conv fused with StoC2, every "
              "output ciphertext bootstrapped (Algorithm 1), stride-2 layers by the decomposed flow (Algorithm 2). "
@@ -273,6 +383,12 @@ def summary(res, command):
               "%d layers, %d rotation keys): %.1f s.  The paper's NeuJeans ResNet18-AESPA total on an A100 with "
               "HEaaN is 5.35 s (Table 2; context, different hardware and library)."
               % (res["bootstraps"], res["wall_ms"] / 1e3, res["layers"], res["keys"], res["setup_s"])]
+    if "output_vs_fp64" in res:
+        e = res["output_vs_fp64"]
+        lines += ["", "The decrypted output of the last layer (512 channels at 7 x 7) against the same network "
+                  "computed in FP64 (same input and weights, square activations, 'same' strided convs, average "
+                  "pooling, residual sums): max abs error %.2e (rms %.2e) for values up to %.3f (rms %.3f)."
+                  % (e["max_abs_err"], e["rms_err"], e["max_abs_value"], e["rms_value"])]
     return "\n".join(lines) + "\n"
 
 
@@ -300,6 +416,14 @@ def main():
                "output_level": out[0].level, "layers": len(net.P), "keys": nk, "setup_s": setup}
         print("[network] run %d: %.3f s in the calls, %.3f s wall, %d bootstraps" %
               (r, res["ms"] / 1e3, wall / 1e3, res["bootstraps"]), flush=True)
+    got = decode_output(net, out)
+    want = forward_fp64(net)
+    res["output_vs_fp64"] = {"max_abs_err": float(np.max(np.abs(got - want))),
+                             "rms_err": float(np.sqrt(np.mean((got - want) ** 2))),
+                             "max_abs_value": float(np.max(np.abs(want))),
+                             "rms_value": float(np.sqrt(np.mean(want ** 2)))}
+    print("[network] output (512 x 7 x 7) vs the FP64 forward pass: max abs error %.2e, max |value| %.3f" %
+          (res["output_vs_fp64"]["max_abs_err"], res["output_vs_fp64"]["max_abs_value"]), flush=True)
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)
     if args.md:

@@ -859,6 +859,39 @@ class Ctx:
                "nj_cts_plan_create_split")
         return Plan(h)
 
+    def cts_plan_from_spec(self, spec):
+        """a CoeffToSlot plan from its description {"groups": d, "n1": [per group] (absent
+        or null: the default split), "hoist": bool or [per group], "lazy": bool} - the
+        form the learned plan is reported in, so it can be stored as JSON and rebuilt"""
+        n1 = spec.get("n1")
+        plan = self.nj_cts_plan_create_split(spec["groups"], n1) if n1 else self.nj_cts_plan_create(spec["groups"])
+        plan.set_hoist(spec.get("hoist", True))
+        return plan.set_lazy(spec.get("lazy", False))
+
+    def decrypt_checked(self, ct, bound):
+        """decrypted coefficients / scale (two limbs' CRT, one at level 0) and whether they
+        are an unambiguous decryption of a message bounded by `bound`: false when the
+        bound reaches half the modulus over the scale (values that large wrap around and
+        cannot be told from small ones), or when a value exceeds the bound (the message
+        outgrew it)"""
+        k = min(2, ct.level + 1)
+        d = self.torch.empty((ct.level + 1, self.N), dtype=self.torch.int64, device=self.device)
+        self.nj_decrypt(ct, d)
+        res = self.to_host(d)[:k]
+        Q = 1
+        for q in self.q[:k]:
+            Q *= int(q)
+        if k == 1:
+            v = res[0].astype(np.float64)
+            v[v > self.q[0] / 2] -= self.q[0]
+        else:  # CRT of two limbs, centred
+            q0, q1 = int(self.q[0]), int(self.q[1])
+            inv = pow(q0, -1, q1)
+            x = [int(a) + q0 * (((int(b) - int(a)) * inv) % q1) for a, b in zip(res[0], res[1])]
+            v = np.array([float(t - Q) if t > Q // 2 else float(t) for t in x])
+        v /= ct.scale
+        return v, bool(bound < Q / (2.0 * ct.scale) and np.max(np.abs(v)) <= bound)
+
     def nj_cts_plan_features(self, groups, n1s=None, hoist=True):
         n1 = None if n1s is None else np.ascontiguousarray(list(n1s), dtype=np.int32)
         f = np.zeros((groups, 7), dtype=np.float32)

@@ -12,6 +12,9 @@ Purposes (the second key word):
   6 job mix          7 public-key uniforms   8 public-key error
   9 public-key encryption: v, e0, e1
 """
+import json
+import os
+
 import numpy as np
 
 (PURPOSE_SECRET, PURPOSE_KEY_A, PURPOSE_KEY_E, PURPOSE_ENC_A, PURPOSE_ENC_E, PURPOSE_DATA, PURPOSE_JOBS,
@@ -66,15 +69,21 @@ def uniform_real(shape, seed, sub=0, lo=-1.0, hi=1.0):
     return g.uniform(lo, hi, size=shape)
 
 
-# Workload shapes (conv layer and ring) used by tests and the benchmark.
-WORKLOADS = {
-    # N=2^12, 8 ciphertext primes + 2 special, one 3x3 conv 4->4 on 16x16, two CoeffToSlot levels
-    "small": dict(log_n=12, n_q=8, alpha=2, q0_bits=50, q_bits=48, p_bits=50, log_scale=40, h=192,
-                  c_in=4, c_out=4, w0=16, f=3, cts_groups=2, data_seed=1001, key_seed=2001),
-    # N=2^16, 24 ciphertext primes + 8 special (three key-switching digits), 3x3 conv 16->16 on 32x32
-    "full": dict(log_n=16, n_q=24, alpha=8, q0_bits=50, q_bits=48, p_bits=50, log_scale=40, h=192,
-                 c_in=16, c_out=16, w0=32, f=3, cts_groups=3, data_seed=1002, key_seed=2002),
-}
+# Parameter sets of the workloads, one JSON file each under synth/params/ (ring, chain,
+# layer shape, seeds): small, full, larger, batched, plans.  WORKLOADS holds the two that
+# tests and the benchmark build as a ring plus one conv layer.
+_PARAMS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "params")
+
+
+def params(name):
+    """the parameter set synth/params/<name>.json"""
+    with open(os.path.join(_PARAMS_DIR, name + ".json")) as fh:
+        doc = json.load(fh)
+    doc.pop("description", None)
+    return doc
+
+
+WORKLOADS = {name: params(name) for name in ("small", "full")}
 
 
 def key_randomness(primes, n, dnum, seed, key_id):

@@ -108,3 +108,35 @@ def test_keys_saved_and_restored(g, tmp_path):
     other.ctx.nj_set_secret(-np.asarray(other.ctx.secret))
     with pytest.raises(ValueError):
         other.ctx.load_keys(path)
+
+
+def test_decryption_bound_check_flags_wrap_around(g):
+    """constant messages m at level 0 (coefficient 0 = m scale): a bound below
+    q_0 / (2 scale) with m inside it passes; m beyond its bound is flagged; a bound
+    reaching q_0 / (2 scale) is flagged even where m decrypts, since a message that
+    large wraps around (0.75 P comes back as -0.25 P)"""
+    import synth
+    ctx = g.ctx
+    P = g.q[0] / g.scale  # 2^10
+    cases = ((0.25 * P, 0.3 * P, True), (0.4 * P, 0.3 * P, False), (0.75 * P, 0.8 * P, False))
+    for k, (m, bound, ok) in enumerate(cases):
+        coeffs = ctx.nj_encode_slots(np.full(g.N // 2, m), g.scale)
+        dev = torch.empty((1, g.N), dtype=torch.int64, device=ctx.device)
+        ctx.nj_upload_plain(coeffs, 0, dev)
+        a, e = synth.enc_randomness(g.q[:1], g.N, 91, k)
+        ct = ctx.nj_encrypt_sk(dev, 0, a, e, g.scale, ctx.empty_ct(0))
+        vals, valid = ctx.decrypt_checked(ct, bound)
+        assert valid == ok, (m, bound, vals[0])
+        want = m if m < P / 2 else m - P
+        assert abs(vals[0] - want) < 1e-6 and np.max(np.abs(vals[1:])) < 1e-6
+
+
+def test_plan_from_spec_rebuilds_the_plan(g):
+    ctx = g.ctx
+    spec = {"groups": 2, "n1": [4, 8], "hoist": [False, True], "lazy": True}
+    p = ctx.cts_plan_from_spec(spec)
+    q = ctx.nj_cts_plan_create_split(2, [4, 8]).set_hoist([False, True]).set_lazy(True)
+    for t in range(2):
+        assert np.array_equal(p.features(ctx.L - t, t), q.features(ctx.L - t, t))
+        assert sorted(p.offsets(t)) == sorted(q.offsets(t))
+    assert list(p.features(ctx.L, 0))[4] == 0  # group 0 not hoisted

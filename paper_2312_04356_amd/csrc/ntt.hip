@@ -133,6 +133,95 @@ __device__ __forceinline__ void tile_inverse(double v[16], double *s, int tid, i
     gs_round(v, 2048, 0, tile, logN1, W, N, m);
 }
 
+// The twiddles of one tile's forward pass (last 12 stages), for blocks that transform
+// many limbs of the same prime and tile: staged in LDS once, so that the transform
+// issues no vector memory operation and loads already in flight are never waited for
+// in it.  Round 0, stage s: entry i of 2^s at kTwR1 + kTwR2 + 2^s - 1 + i (every lane
+// reads the same word).  Round 1, stage s: entry (hi, i) of 16 2^s at 16 (2^s - 1) +
+// hi 2^s + i (16 lanes per word).  Round 2, stage s: entry (tid, i) of 256 2^s at kTwR1
+// + 256 (2^s - 1) + 256 i + tid (consecutive lanes, consecutive words).
+constexpr int kTwR1 = 240, kTwR2 = 3840, kTwR0 = 15, kTwAll = kTwR1 + kTwR2 + kTwR0;
+
+__device__ __forceinline__ void stage_tile_twiddles(double *tws, const double *W, int tile, int logN1, int N, int tid)
+{
+    constexpr int kPer = (kTwAll + kNT - 1) / kNT;
+    double w[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {  // all loads in flight before the first store
+        const int e = min(tid + kNT * q, kTwAll - 1);
+        int t0, st, ent;
+        if (e < kTwR1) {
+            st = e < 16 ? 0 : e < 48 ? 1 : e < 112 ? 2 : 3;
+            ent = e - 16 * ((1 << st) - 1);
+            t0 = 128;
+        } else if (e < kTwR1 + kTwR2) {
+            const int f = e - kTwR1;
+            st = f < 256 ? 0 : f < 768 ? 1 : f < 1792 ? 2 : 3;
+            const int g = f - 256 * ((1 << st) - 1);
+            ent = (g & 255) * (1 << st) + (g >> 8);
+            t0 = 8;
+        } else {
+            const int f = e - kTwR1 - kTwR2;
+            st = f < 1 ? 0 : f < 3 ? 1 : f < 7 ? 2 : 3;
+            ent = f - ((1 << st) - 1);
+            t0 = 2048;
+        }
+        const int mm = N / (2 * (t0 >> st));
+        w[q] = W[mm + tile * (mm >> logN1) + ent];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; q++)
+        if (tid + kNT * q < kTwAll) tws[tid + kNT * q] = w[q];
+}
+
+// ct_round of round R (0: hi = 0, 1: hi = tid >> 4, 2: hi = tid) with the twiddles
+// staged by stage_tile_twiddles
+template <int R>
+__device__ __forceinline__ void ct_round_lds(double v[16], const double *tws, int hi, Mod m)
+{
+#pragma unroll
+    for (int st = 0; st < 4; st++) {
+        const int step = 8 >> st;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k & step) continue;
+            const int i = k >> (4 - st);
+            const double w = R == 0   ? tws[kTwR1 + kTwR2 + (1 << st) - 1 + i]
+                             : R == 1 ? tws[16 * ((1 << st) - 1) + (hi << st) + i]
+                                      : tws[kTwR1 + 256 * ((1 << st) - 1) + 256 * i + hi];
+            const double U = v[k], V = mul_lazy(v[k + step], w, m);
+            v[k] = U + V;
+            v[k + step] = U - V;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = reduce(v[k], m);
+}
+
+// tile_forward with the twiddles staged by stage_tile_twiddles
+__device__ __forceinline__ void tile_forward_lds(double v[16], double *s, const double *tws, int tid, Mod m)
+{
+    ct_round_lds<0>(v, tws, 0, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+    __syncthreads();
+    {
+        const int lo = tid & 15, hi = tid >> 4;
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+        ct_round_lds<1>(v, tws, hi, m);
+#pragma unroll
+        for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+    ct_round_lds<2>(v, tws, tid, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+    __syncthreads();
+}
+
 // rows pass: last 12 stages on 4096-word tiles.  grid (N/4096, limbs)
 template <bool INV>
 __global__ __launch_bounds__(kNT) void k_ntt_tile(uint64_t *data, const uint64_t *src, LimbTab lt, const double *tw,
@@ -184,6 +273,30 @@ __device__ __forceinline__ void store_p_rows(double a0[16], double a1[16], doubl
     for (int k = 0; k < 16; k++) out[half_off + w0 + 256 * k] = d2u(a1[k]);
 }
 
+// x words of step q = z ND + j of a key inner product (job z, digit j) at words
+// w0 + 256 k: the job's own limb through X -> X^g, or the extended digit ([ND][ne][N])
+// as it came out of its column pass.  Buffer loads: one 32-bit offset register per
+// stream, the 256-word steps in the scalar offset.
+template <int ND>
+__device__ __forceinline__ void ip_load_x(const KeyJobs &kj, const IpRow &r, int q, uint32_t w0, int logN, uint32_t N,
+                                          uint64_t *xn)
+{
+    const int z = q / ND, j = q - z * ND;
+    if (j == r.own) {
+        const auto d = buf_rsrc(kj.d[z] + r.t * N, 8u * N);
+        const uint32_t g = kj.g[z];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            xn[k] = buf_ld(d, 8u * (uint32_t)galois_src2((int)(w0 + 256u * k), g, logN), 0);  // g = 1: identity
+        }
+    } else {
+        const auto e = buf_rsrc(kj.ext[z], 8u * (uint32_t)(ND * r.ne) * N);
+        const uint32_t vo = 8u * ((uint32_t)(j * r.ne + r.t) * N + w0);
+#pragma unroll
+        for (int k = 0; k < 16; k++) xn[k] = buf_ld(e, vo, 2048u * k);
+    }
+}
+
 // Key inner products fused with the forward tile pass of the extended digits (N >=
 // 8192).  The key switch is of tau_g(d_z), g = kj.g[z]: at output limb t, digit j of
 // job z is either the job's own limb d_z[t] read through X -> X^g (evaluation form) or
@@ -195,12 +308,17 @@ __device__ __forceinline__ void store_p_rows(double a0[16], double a1[16], doubl
 // = u_base + z 2 ne N (plus its previous value when accumulate): jobs vary fastest, so
 // jobs sharing one key read each key tile close together in time.  After each job the
 // running sums take at most ND <= 4 lazy terms on a reduced value.
+// Latency: a block works through its (job, digit) steps one after another with two
+// blocks per CU (256 registers per lane), so the words of the next step are requested
+// before this step's transform, and the transform reads its twiddles from LDS (staged
+// once per block) rather than memory: no wait in it holds up those loads.
 template <int ND, bool SUM>
-__global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t *u_base, int accumulate, int level,
+__global__ __launch_bounds__(kNT, 2) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t *u_base, int accumulate, int level,
                                                 int L, int alpha, int nq, const double *tw, const PrimeInfo *info,
                                                 int logN, uint64_t *pout, const double *itw)
 {
     __shared__ double s[kT + kT / 16];
+    __shared__ double tws[kTwAll];
     const int N = 1 << logN, logN1 = logN - 12;
     const int t = blockIdx.z, tile = blockIdx.y, tid = threadIdx.x;
     const int pidx = t <= level ? t : nq + (t - level - 1);
@@ -211,42 +329,52 @@ __global__ __launch_bounds__(kNT) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t
     const int z0 = SUM ? 0 : (int)blockIdx.x, z1 = SUM ? n_jobs : z0 + 1;
     uint64_t *u = u_base + (SUM ? 0 : (size_t)z0 * 2 * r.ne * N);
     const size_t o0 = r.t * N + w0, o1 = (r.ne + r.t) * N + w0;
+    // steps q = z ND + j run in order; the words of step q + 1 are requested before step
+    // q's transform, so their latency hides behind it
+    const int q0 = z0 * ND, q1 = z1 * ND;
+    uint64_t xn[16];
+    ip_load_x<ND>(kj, r, q0, (uint32_t)w0, logN, (uint32_t)N, xn);
+    stage_tile_twiddles(tws, W, tile, logN1, N, tid);
     double a0[16], a1[16];
+    if (accumulate) {
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        a0[k] = accumulate ? u2d(u[o0 + 256 * k]) : 0.0;
-        a1[k] = accumulate ? u2d(u[o1 + 256 * k]) : 0.0;
+        for (int k = 0; k < 16; k++) a0[k] = u2d(u[o0 + 256 * k]), a1[k] = u2d(u[o1 + 256 * k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) a0[k] = 0.0, a1[k] = 0.0;
     }
-    for (int z = z0; z < z1; z++) {
+    __syncthreads();  // staged twiddles visible
 #pragma unroll 1
-        for (int j = 0; j < ND; j++) {
-            const uint64_t *kb = kj.key[z] + ((size_t)j * 2 * r.nk + r.kl) * N + w0, *ka = kb + r.nk * N;
-            double x[16];
-            if (j == r.own) {
-                const uint64_t *xp = kj.d[z] + r.t * N;
-                const uint32_t g = kj.g[z];
+    for (int q = q0; q < q1; q++) {
+        const int z = q / ND, j = q - z * ND;
+        const bool own = j == r.own;
+        double x[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    const int w = (int)w0 + 256 * k;
-                    x[k] = u2d(xp[g == 1u ? w : galois_src2(w, g, logN)]);
-                }
-            } else {
-                const uint64_t *xp = kj.ext[z] + ((size_t)j * r.ne + r.t) * N + w0;
+        for (int k = 0; k < 16; k++) x[k] = u2d(xn[k]);
+        if (q + 1 < q1) ip_load_x<ND>(kj, r, q + 1, (uint32_t)w0, logN, (uint32_t)N, xn);
+        if (!own) {
+            __syncthreads();  // the previous step's words have been read out of s
+            tile_forward_lds(x, s, tws, tid, m);
+        } else {
+            // words every thread reads back itself (its own positions), as the
+            // transformed tile's are; no other thread touches them before the next barrier
 #pragma unroll
-                for (int k = 0; k < 16; k++) x[k] = u2d(xp[256 * k]);
-                __syncthreads();  // the previous tile's words have been read out of s
-                tile_forward(x, s, tid, tile, logN1, W, N, m);
-#pragma unroll
-                for (int k = 0; k < 16; k++) x[k] = s[pad16(tid + 256 * k)];
-            }
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                a0[k] += mul_lazy(x[k], u2d(kb[256 * k]), m);
-                a1[k] += mul_lazy(x[k], u2d(ka[256 * k]), m);
-            }
+            for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = x[k];
         }
+        // key [ND][2][nk][N]: words of row kl of digit j, b half then a half
+        const auto key = buf_rsrc(kj.key[z], 8u * (uint32_t)(2 * ND * r.nk) * (uint32_t)N);
+        const uint32_t vb = 8u * ((uint32_t)(j * 2 * r.nk + r.kl) * (uint32_t)N + (uint32_t)w0),
+                       va = vb + 8u * (uint32_t)(r.nk * N);
 #pragma unroll
-        for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
+        for (int k = 0; k < 16; k++) {
+            const double xv = s[pad16(tid + 256 * k)];
+            a0[k] += mul_lazy(xv, u2d(buf_ld(key, vb, 2048u * k)), m);
+            a1[k] += mul_lazy(xv, u2d(buf_ld(key, va, 2048u * k)), m);
+        }
+        if (j == ND - 1) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) a0[k] = reduce(a0[k], m), a1[k] = reduce(a1[k], m);
+        }
     }
     if (pout && t > level) {  // special-prime rows: on to ModDown's inverse transform
         store_p_rows(a0, a1, s, pout + ((size_t)2 * z0 * alpha + (t - level - 1)) * N, (size_t)alpha * N, w0, tid,

@@ -190,8 +190,10 @@ def jobs_bench(g, n_jobs, steps=2):
     """64 jobs at uneven levels 7..23, each conv (3x3, 3x3 stride 2, 1x1 or depthwise 3x3
     on 16/64/256 channels per ciphertext) at its level -> level drop -> ModRaise ->
     CoeffToSlot -> split.  Plain: one job after another with default plans.  Batched:
-    the grouped schedule replayed as one HIP graph, with n1 tuned by timing.
-    Concurrent: the plain schedule spread over 4 worker streams, as one HIP graph."""
+    each conv on its fused path, then CoeffToSlot over all 64 outputs together, replayed
+    as one HIP graph, with n1 tuned by timing; across levels: the same with each conv
+    plan's jobs grouped across their levels.  Concurrent: the plain schedule spread over
+    4 worker streams, as one HIP graph."""
     import torch
     import synth
     gctx = g.ctx
@@ -237,13 +239,19 @@ def jobs_bench(g, n_jobs, steps=2):
     graph = gctx.nj_batch_create(g.cts_plan, jt)
     replay = timed(lambda: graph.launch())
     del graph
+    # the same with the convs of one plan grouped across levels (keys shared, transforms
+    # unfused)
+    graph = gctx.nj_batch_create(g.cts_plan, jt, mode=3)
+    across = timed(lambda: graph.launch())
+    del graph
     # the plain schedule of every job on 4 worker streams, as one graph (default plans)
     graph = gctx.nj_batch_create(g.cts_plan, jp, mode=2)
     conc = timed(lambda: graph.launch())
     del graph
     return {"n_jobs": n_jobs, "levels": "7..23", "plain_ms": round(plain, 3),
             "batched_default_plans_ms": round(eager, 3), "batched_graph_tuned_ms": round(replay, 3),
-            "speedup_vs_plain": round(plain / replay, 3), "concurrent_graph_ms": round(conc, 3),
+            "speedup_vs_plain": round(plain / replay, 3), "across_levels_graph_ms": round(across, 3),
+            "concurrent_graph_ms": round(conc, 3),
             "concurrent_speedup_vs_plain": round(plain / conc, 3),
             "tuned_n1": {"%s/C%d" % k: v for k, v in sorted(n1_of.items())}}
 

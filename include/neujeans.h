@@ -372,15 +372,18 @@ typedef struct {
 
 /* Runs the jobs on `stream` using the context scratch.
  *   mode 0, plain: one job after another, each step as the single-job calls run it.
- *   mode 1, batched: single-block jobs of one conv plan run together across their
- *     levels (each baby and giant rotation key read once for up to 16 jobs; ModUp and
- *     ModDown batched per level), the rescale computes only the limb the level drop
- *     keeps, and every conv output goes through batched CoeffToSlot.
+ *   mode 1, batched: each conv on the fused single-ciphertext path, the rescale
+ *     computing only the limb the level drop keeps; then every conv output (all at one
+ *     level after ModRaise) goes through batched CoeffToSlot, which reads each rotation
+ *     key and plaintext diagonal once for up to 16 ciphertexts.
  *   mode 2, concurrent: each job as in mode 0, the jobs spread over the context's
  *     worker streams (nj_batch_workers, default 4) by longest-first assignment, each
  *     worker with its own part of the scratch (workers x the plain scratch); the
  *     workers fork from `stream` and join back into it, so work queued on `stream`
  *     afterwards sees every output.
+ *   mode 3, batched across levels: as mode 1, but single-block jobs of one conv plan
+ *     run together across their levels (each baby and giant rotation key read once for
+ *     up to 16 jobs; ModUp and ModDown batched per level, with unfused transforms).
  * All modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
  * NJ_ELEVEL (input level outside 1..plan level), NJ_ENOKEY, NJ_ENOMEM. */
 nj_status nj_batch_run(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, void *stream);
@@ -391,7 +394,7 @@ nj_status nj_batch_workers(nj_ctx *ctx, int n_streams);
 
 /* Persistent batched execution: a schedule captured once into a HIP graph that owns
  * its scratch memory; nj_batch_launch replays it with no host work per job.
- * nj_batch_create captures mode 1, nj_batch_create_mode the given mode (0, 1 or 2; a
+ * nj_batch_create captures mode 1, nj_batch_create_mode the given mode (0 to 3; a
  * mode-2 graph holds the workers' branches).  Capture computes nothing; the jobs'
  * buffers, plans and keys must stay in place for the batch's lifetime.  Replays on
  * one batch must not overlap. */

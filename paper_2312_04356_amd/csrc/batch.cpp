@@ -1,7 +1,9 @@
 // Jobs of conv -> rescale -> level drop -> ModRaise -> CoeffToSlot -> real split at
-// uneven levels: a plain schedule (one job after another), a batched schedule (jobs of
-// one conv plan grouped across levels so each rotation key is read once for the group,
-// CoeffToSlot batched over every conv output) and its HIP-graph replay.
+// uneven levels: a plain schedule (one job after another), a batched schedule (each conv
+// on the fused single-ciphertext path, then CoeffToSlot batched over every conv output,
+// where every output is at one level), the batched schedule with the convs of one plan
+// grouped across levels (each rotation key read once for the group, at the price of
+// unfused transforms), a concurrent schedule, and HIP-graph replays of each.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -331,7 +333,7 @@ std::vector<MixJob> unit_jobs(const nj_job *jobs, const std::vector<int> &u)
     return mj;
 }
 
-size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
+size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, bool mixed)
 {
     const size_t N = c->N;
     size_t outs = 0, phase1 = 0;
@@ -344,6 +346,12 @@ size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
             const nj_lt_t lt = at_level(j0.conv->lts[0], j0.in.level);
             lmax = lt.level;
             w = lt.bo * 2 * N * (lt.level + 1) + block_words(c, lt);
+        } else if (!mixed) {
+            for (int z : u) {
+                const nj_lt_t lt = at_level(jobs[z].conv->lts[0], jobs[z].in.level);
+                w = std::max(w, 2 * N * (lt.level + 1) + bsgs_words(c, lt));
+                lmax = std::max(lmax, lt.level);
+            }
         } else {
             std::vector<MixJob> mj = unit_jobs(jobs, u);
             for (const MixJob &m : mj) w += 2 * N * (m.level + 1), lmax = std::max(lmax, m.level);
@@ -355,7 +363,7 @@ size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
     return outs * 2 * N + std::max(phase1, phase2);
 }
 
-nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A, hipStream_t s)
+nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, bool mixed, Arena A, hipStream_t s)
 {
     const size_t N = c->N, clo = 2 * N * (c->L - cts->lts.size() + 1);
     std::vector<size_t> off(n + 1, 0);
@@ -374,6 +382,17 @@ nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, 
             if ((st = block_bsgs_apply(c, lt, j0.in.data, y, B, s))) return st;
             for (int ob = 0; ob < lt.bo; ob++)
                 if ((st = rescale(c, lt.level, y + ob * clen, pool + (off[u[0]] + ob) * 2 * N, B, s, 1))) return st;
+            continue;
+        }
+        if (!mixed) {  // each conv on the fused single-ciphertext path
+            for (int z : u) {
+                Arena C = B;
+                const nj_lt_t lt = at_level(jobs[z].conv->lts[0], jobs[z].in.level);
+                uint64_t *y = C.take(2 * N * (lt.level + 1));
+                if (!y) return fail(NJ_ENOMEM, "scratch too small");
+                if ((st = bsgs_apply(c, lt, jobs[z].in.data, y, 1, C, s))) return st;
+                if ((st = rescale(c, lt.level, y, pool + off[z] * 2 * N, C, s, 1))) return st;
+            }
             continue;
         }
         std::vector<MixJob> mj = unit_jobs(jobs, u);
@@ -510,13 +529,13 @@ nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int 
 size_t schedule_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, int mode)
 {
     if (mode == 2) return worker_words(c, cts, jobs, n) * n_workers(c, n);
-    return mode ? batched_words(c, cts, jobs, n) : plain_words(c, cts, jobs, n);
+    return mode ? batched_words(c, cts, jobs, n, mode == 3) : plain_words(c, cts, jobs, n);
 }
 
 nj_status run_schedule(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, int mode, Arena A, hipStream_t s)
 {
     if (mode == 2) return run_concurrent(c, cts, jobs, n, A, s);
-    return mode ? run_batched(c, cts, jobs, n, A, s) : run_plain(c, cts, jobs, n, A, s);
+    return mode ? run_batched(c, cts, jobs, n, mode == 3, A, s) : run_plain(c, cts, jobs, n, A, s);
 }
 
 void set_outputs(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
@@ -538,7 +557,9 @@ nj_status nj_batch_run(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int n, int m
 {
     nj_status st = check_jobs(c, cts, jobs, n);
     if (st) return st;
-    if (mode < 0 || mode > 2) return fail(NJ_EINVAL, "nj_batch_run: mode must be 0 (plain), 1 (batched) or 2 (concurrent)");
+    if (mode < 0 || mode > 3)
+        return fail(NJ_EINVAL, "nj_batch_run: mode must be 0 (plain), 1 (batched), 2 (concurrent) or 3 (batched, "
+                               "convs grouped across levels)");
     bool ok;
     Arena A = arena_for(c, schedule_words(c, cts, jobs, n, mode), ok);
     if (!ok) return fail(NJ_ENOMEM, "scratch");
@@ -565,7 +586,7 @@ nj_status nj_batch_create_mode(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int 
     nj_status st = check_jobs(c, cts, jobs, n);
     if (st) return st;
     if (!out) return fail(NJ_EINVAL, "nj_batch_create: null output");
-    if (mode < 0 || mode > 2) return fail(NJ_EINVAL, "nj_batch_create: mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return fail(NJ_EINVAL, "nj_batch_create: mode must be 0, 1, 2 or 3");
     if (mode == 2 && (st = workers_ready(c))) return st;
     const size_t words = schedule_words(c, cts, jobs, n, mode);
     nj_batch *b = new nj_batch();

@@ -72,7 +72,7 @@ def test_job_at_lower_level_matches_oracle():
     assert re.level == R.L - len(o.cts)
 
 
-def run_three_ways(g, plans, levels):
+def run_all_modes(g, plans, levels):
     """jobs (plan, level) -> outputs of plain, batched and concurrent (3 worker streams)
     runs, three replays of the batched graph and two of the concurrent graph"""
     gctx = g.ctx
@@ -86,7 +86,7 @@ def run_three_ways(g, plans, levels):
         jobs.append((plan, x, re, im))
     results = {}
     gctx.nj_batch_workers(3)
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         gctx.nj_batch_run(g.cts_plan, jobs, mode)
         torch.cuda.synchronize()
         results[mode] = [(j[2].data.clone(), j[3].data.clone()) for j in jobs]
@@ -139,9 +139,10 @@ def test_plain_batched_graph_agree_small():
     g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(pb.galois()) | set(g.cts_plan.galois())))
     plans = [(p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (pb, 2, 2), (p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (p3, 1, 1)]
     levels = [6, 1, 3, 5, 3, 6, 1, 4]
-    res, reps = run_three_ways(g, plans, levels)
+    res, reps = run_all_modes(g, plans, levels)
     assert_same(res[0], res[1], "batched vs plain")
     assert_same(res[0], res[2], "concurrent vs plain")
+    assert_same(res[0], res[3], "batched across levels vs plain")
     for r, rep in enumerate(reps):
         assert_same(res[1], rep, "graph replay %d" % r)
 
@@ -155,9 +156,10 @@ def test_plain_batched_graph_agree_full():
     g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(g.cts_plan.galois())))
     plans = [(p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (p3, 1, 1), (p1, 1, 1)]
     levels = [7, 12, 12, 23, 16]
-    res, reps = run_three_ways(g, plans, levels)
+    res, reps = run_all_modes(g, plans, levels)
     assert_same(res[0], res[1], "batched vs plain")
     assert_same(res[0], res[2], "concurrent vs plain")
+    assert_same(res[0], res[3], "batched across levels vs plain")
     for r, rep in enumerate(reps):
         assert_same(res[1], rep, "graph replay %d" % r)
 

@@ -131,7 +131,8 @@ def _digest(arr):
 @pytest.mark.timeout(600)
 def test_batched_mixed_levels_parity_full():
     """the batched schedule (mode 1) and its graph replay of three jobs at levels 9, 11
-    and 13 against the oracle's digests"""
+    and 13, the plain schedule and the batched schedule with the convs grouped across
+    levels (mode 3) against the oracle's digests"""
     doc = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_batch_jobs.json")))
     O.set_threads(0)
     say("batched jobs: setup")
@@ -186,3 +187,10 @@ def test_batched_mixed_levels_parity_full():
     gctx.nj_batch_run(g.cts_plan, jobs, 0)
     torch.cuda.synchronize()
     check("plain")
+    for j in jobs:
+        j[2].data.zero_()
+        j[3].data.zero_()
+    say("batched jobs: mode 3 (convs grouped across levels)")
+    gctx.nj_batch_run(g.cts_plan, jobs, 3)
+    torch.cuda.synchronize()
+    check("batched across levels")

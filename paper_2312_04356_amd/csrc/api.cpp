@@ -517,6 +517,14 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
         usum = A.take(N * K * 2 * ne), c0sum = A.take(N * K * (l + 1));
         if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
     }
+    // fused (N >= 8192): tau_ge rides on ModUp's inverse transform and on the own-limb
+    // reads, and the key inner product (one key, one job per ciphertext) runs the digits'
+    // tile pass; the last giant step's special-prime rows go on to ModDown's inverse
+    // transform there
+    const bool f = fuse_ip(c, l);
+    int g_last = -1;
+    for (int g = 0; g < ng; g++)
+        if (lt.giants[g] != 0) g_last = g;
     bool first = true;
     for (int g = 0; g < ng; g++) {
         if (lt.giants[g] == 0) continue;
@@ -524,23 +532,38 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
         AutoJobs aj, ac;
         KeyJobs kj;
         MdJobs mj;
+        GalTab gt;
+        int zoff[NJ_MAX_JOBS];  // limb offset of each ciphertext's c1 of this giant step from inner_all + plen
         for (int z = 0; z < K; z++) {
             const uint64_t *x = inner_all + ((size_t)z * ng + g) * clen;
             aj.in[z] = x + plen, aj.out[z] = M.d + (size_t)z * plen, aj.g[z] = ge;
             ac.in[z] = x, ac.out[z] = nullptr, ac.g[z] = ge;
             kj.ext[z] = M.ext + (size_t)z * nd * ne * N, kj.d[z] = M.d + (size_t)z * plen, kj.g[z] = 1;
+            kj.key[z] = key_of(c, ge);
+            if (f) kj.d[z] = x + plen, kj.g[z] = ge, gt.g[z] = ge, zoff[z] = (z * ng + g) * 2 * (l + 1);
             mj.add[z] = x, mj.g_add[z] = ge, mj.out[z] = out + z * clen;
         }
-        NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
-        if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+        if (f) {
+            if ((st = modup_multi(c, l, K, inner_all + plen, M, s, -1, false, &gt, zoff))) return st;
+        } else {
+            NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
+            if ((st = modup_multi(c, l, K, M.d, M, s))) return st;
+        }
         if (lt.lazy) {  // per ciphertext: inner products and rotated c0 parts summed
-            NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), usum, s, first ? 0 : 1));
+            if (f)
+                NJ_HIP(launch_ntt_ip(c, l, kj, K, usum, 0, first ? 0 : 1, s, g == g_last ? M.pc : nullptr));
+            else
+                NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), usum, s, first ? 0 : 1));
             NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, plen, first ? 0 : 1, s));
             first = false;
             continue;
         }
-        NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
-        if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
+        if (f) {
+            if ((st = ks_fused(c, l, K, kj, mj, 0, have ? out : nullptr, M, s))) return st;
+        } else {
+            NJ_HIP(launch_key_ip_shared(c, l, kj, K, key_of(c, ge), M.u, s));
+            if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M, s))) return st;
+        }
         have = true;
     }
     if (lt.lazy && !first) {  // one ModDown per ciphertext
@@ -548,7 +571,7 @@ nj_status bsgs_apply_batch(nj_ctx *c, const nj_lt_t &lt, int K, const uint64_t *
         M1.u = usum;
         MdJobs mj;
         for (int z = 0; z < K; z++) mj.add[z] = c0sum + z * plen, mj.g_add[z] = 1, mj.out[z] = out + z * clen;
-        if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M1, s))) return st;
+        if ((st = ks_down(c, l, K, mj, 0, have ? out : nullptr, M1, s, f))) return st;
     }
     return NJ_OK;
 }

@@ -373,9 +373,11 @@ typedef struct {
 /* Runs the jobs on `stream` using the context scratch.
  *   mode 0, plain: one job after another, each step as the single-job calls run it.
  *   mode 1, batched: each conv on the fused single-ciphertext path, the rescale
- *     computing only the limb the level drop keeps; then every conv output (all at one
- *     level after ModRaise) goes through batched CoeffToSlot, which reads each rotation
- *     key and plaintext diagonal once for up to 16 ciphertexts.
+ *     computing only the limb the level drop keeps, the jobs spread over the worker
+ *     streams as in mode 2 (convs at low levels leave much of the GPU idle); then every
+ *     conv output (all at one level after ModRaise) goes through batched CoeffToSlot on
+ *     `stream`, which reads each rotation key and plaintext diagonal once for up to 8
+ *     ciphertexts.
  *   mode 2, concurrent: each job as in mode 0, the jobs spread over the context's
  *     worker streams (nj_batch_workers, default 4) by longest-first assignment, each
  *     worker with its own part of the scratch (workers x the plain scratch); the
@@ -387,7 +389,7 @@ typedef struct {
  * All modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
  * NJ_ELEVEL (input level outside 1..plan level), NJ_ENOKEY, NJ_ENOMEM. */
 nj_status nj_batch_run(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, void *stream);
-/* Worker streams of mode 2 (1..4; NJ_EINVAL otherwise).  Streams run at the default
+/* Worker streams of modes 1 and 2 (1..4; NJ_EINVAL otherwise).  Streams run at the default
  * priority.  Concurrent calls on one context must not overlap (they share the
  * workers and the scratch). */
 nj_status nj_batch_workers(nj_ctx *ctx, int n_streams);

@@ -333,12 +333,55 @@ std::vector<MixJob> unit_jobs(const nj_job *jobs, const std::vector<int> &u)
     return mj;
 }
 
+// worker streams (defined with the concurrent schedule below)
+nj_status workers_ready(nj_ctx *c);
+int n_workers(const nj_ctx *c, int n);
+template <class Run>
+nj_status on_workers(nj_ctx *c, const std::vector<double> &cost, size_t per, Arena A0, hipStream_t s, Run run);
+
+// one job's conv -> rescale -> level drop: its bo level-0 outputs at out [bo][2][1][N]
+size_t conv_words(nj_ctx *c, const nj_job &j)
+{
+    const size_t N = c->N;
+    const nj_lt_t lt = at_level(j.conv->lts[0], j.in.level);
+    const size_t l = lt.level;
+    return lt.bo * 2 * N * (l + 1) + (lt.bi == 1 && lt.bo == 1 ? bsgs_words(c, lt) : block_words(c, lt)) + N * (l + 2);
+}
+
+nj_status conv_to_pool(nj_ctx *c, const nj_job &j, uint64_t *out, Arena A, hipStream_t s)
+{
+    const size_t N = c->N;
+    const nj_lt_t lt = at_level(j.conv->lts[0], j.in.level);
+    const size_t clen = 2 * N * (lt.level + 1);
+    uint64_t *y = A.take(lt.bo * clen);
+    if (!y) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st = lt.bi == 1 && lt.bo == 1 ? bsgs_apply(c, lt, j.in.data, y, 1, A, s)
+                                            : block_bsgs_apply(c, lt, j.in.data, y, A, s);
+    for (int ob = 0; ob < lt.bo && !st; ob++) st = rescale(c, lt.level, y + ob * clen, out + ob * 2 * N, A, s, 1);
+    return st;
+}
+
+// relative cost of a job's conv (key switches x limbs), to balance the workers
+double conv_cost(const nj_job &j)
+{
+    const nj_lt_t lt = at_level(j.conv->lts[0], j.in.level);
+    return (double)(lt.level + 1) * ((double)lt.babies.size() * lt.bi + (double)lt.giants.size() * lt.bo);
+}
+
+size_t conv_worker_words(nj_ctx *c, const nj_job *jobs, int n)
+{
+    size_t w = 0;
+    for (int z = 0; z < n; z++) w = std::max(w, conv_words(c, jobs[z]));
+    return (w + 255) / 256 * 256;
+}
+
 size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, bool mixed)
 {
     const size_t N = c->N;
     size_t outs = 0, phase1 = 0;
     for (int z = 0; z < n; z++) outs += job_bo(jobs[z]);
-    for (const auto &u : make_units(jobs, n)) {
+    if (!mixed) phase1 = conv_worker_words(c, jobs, n) * n_workers(c, n);
+    for (const auto &u : mixed ? make_units(jobs, n) : std::vector<std::vector<int>>()) {
         const nj_job &j0 = jobs[u[0]];
         size_t w = 0;
         int lmax = 0;
@@ -346,12 +389,6 @@ size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, b
             const nj_lt_t lt = at_level(j0.conv->lts[0], j0.in.level);
             lmax = lt.level;
             w = lt.bo * 2 * N * (lt.level + 1) + block_words(c, lt);
-        } else if (!mixed) {
-            for (int z : u) {
-                const nj_lt_t lt = at_level(jobs[z].conv->lts[0], jobs[z].in.level);
-                w = std::max(w, 2 * N * (lt.level + 1) + bsgs_words(c, lt));
-                lmax = std::max(lmax, lt.level);
-            }
         } else {
             std::vector<MixJob> mj = unit_jobs(jobs, u);
             for (const MixJob &m : mj) w += 2 * N * (m.level + 1), lmax = std::max(lmax, m.level);
@@ -363,13 +400,12 @@ size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, b
     return outs * 2 * N + std::max(phase1, phase2);
 }
 
-nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, bool mixed, Arena A, hipStream_t s)
+// mode 3's conv phase: single-block jobs of one plan together across their levels,
+// block jobs one at a time; the level-0 outputs into pool
+nj_status convs_across_levels(nj_ctx *c, const nj_job *jobs, int n, const std::vector<size_t> &off, uint64_t *pool,
+                              Arena A, hipStream_t s)
 {
-    const size_t N = c->N, clo = 2 * N * (c->L - cts->lts.size() + 1);
-    std::vector<size_t> off(n + 1, 0);
-    for (int z = 0; z < n; z++) off[z + 1] = off[z] + job_bo(jobs[z]);
-    uint64_t *pool = A.take(off[n] * 2 * N);  // level-0 conv outputs [outs][2][1][N]
-    if (!pool) return fail(NJ_ENOMEM, "scratch too small");
+    const size_t N = c->N;
     nj_status st;
     for (const auto &u : make_units(jobs, n)) {
         Arena B = A;
@@ -384,23 +420,33 @@ nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, 
                 if ((st = rescale(c, lt.level, y + ob * clen, pool + (off[u[0]] + ob) * 2 * N, B, s, 1))) return st;
             continue;
         }
-        if (!mixed) {  // each conv on the fused single-ciphertext path
-            for (int z : u) {
-                Arena C = B;
-                const nj_lt_t lt = at_level(jobs[z].conv->lts[0], jobs[z].in.level);
-                uint64_t *y = C.take(2 * N * (lt.level + 1));
-                if (!y) return fail(NJ_ENOMEM, "scratch too small");
-                if ((st = bsgs_apply(c, lt, jobs[z].in.data, y, 1, C, s))) return st;
-                if ((st = rescale(c, lt.level, y, pool + off[z] * 2 * N, C, s, 1))) return st;
-            }
-            continue;
-        }
         std::vector<MixJob> mj = unit_jobs(jobs, u);
         for (MixJob &m : mj)
             if (!(m.out = B.take(2 * N * (m.level + 1)))) return fail(NJ_ENOMEM, "scratch too small");
         if ((st = bsgs_apply_mixed(c, j0.conv->lts[0], mj, B, s))) return st;
         for (size_t i = 0; i < u.size(); i++)
             if ((st = rescale(c, mj[i].level, mj[i].out, pool + off[u[i]] * 2 * N, B, s, 1))) return st;
+    }
+    return NJ_OK;
+}
+
+nj_status run_batched(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, bool mixed, Arena A, hipStream_t s)
+{
+    const size_t N = c->N, clo = 2 * N * (c->L - cts->lts.size() + 1);
+    std::vector<size_t> off(n + 1, 0);
+    for (int z = 0; z < n; z++) off[z + 1] = off[z] + job_bo(jobs[z]);
+    uint64_t *pool = A.take(off[n] * 2 * N);  // level-0 conv outputs [outs][2][1][N]
+    if (!pool) return fail(NJ_ENOMEM, "scratch too small");
+    nj_status st;
+    if (!mixed) {  // every conv on its fused path, the jobs spread over the worker streams
+        std::vector<double> cost(n);
+        for (int z = 0; z < n; z++) cost[z] = conv_cost(jobs[z]);
+        st = on_workers(c, cost, conv_worker_words(c, jobs, n), A, s, [&](int z, Arena B, hipStream_t w) {
+            return conv_to_pool(c, jobs[z], pool + off[z] * 2 * N, B, w);
+        });
+        if (st) return st;
+    } else if ((st = convs_across_levels(c, jobs, n, off, pool, A, s))) {
+        return st;
     }
     std::vector<uint64_t *> re(off[n]), im(off[n]);
     for (int z = 0; z < n; z++)
@@ -491,18 +537,18 @@ size_t worker_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
 
 int n_workers(const nj_ctx *c, int n) { return std::max(1, std::min(std::min(c->batch_workers, kMaxWorkers), n)); }
 
-nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A0, hipStream_t s)
+// Runs run(z, arena, stream) for every job z on the worker streams: longest-processing-
+// time assignment by cost (the costliest job to the least-loaded worker), each worker
+// with `per` words of A0; the workers fork from s and join back into it.
+template <class Run>
+nj_status on_workers(nj_ctx *c, const std::vector<double> &cost, size_t per, Arena A0, hipStream_t s, Run run)
 {
     nj_status st = workers_ready(c);
     if (st) return st;
-    const int W = n_workers(c, n);
-    const size_t per = worker_words(c, cts, jobs, n);
+    const int n = (int)cost.size(), W = n_workers(c, n);
     if (A0.left < per * W) return fail(NJ_ENOMEM, "scratch too small");
-    // longest-processing-time assignment: the costliest job to the least-loaded worker
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(n);
-    for (int z = 0; z < n; z++) cost[z] = job_cost(cts, jobs[z]);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     std::vector<double> load(W, 0.0);
     std::vector<std::vector<int>> part(W);
@@ -515,7 +561,7 @@ nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int 
     for (int k = 0; k < W; k++) NJ_HIP(hipStreamWaitEvent(c->workers[k], c->fork_ev, 0));
     for (int k = 0; k < W && !st; k++)
         for (int z : part[k]) {
-            st = run_plain(c, cts, &jobs[z], 1, Arena{A0.p + (size_t)k * per, per}, c->workers[k]);
+            st = run(z, Arena{A0.p + (size_t)k * per, per}, c->workers[k]);
             if (st) break;
         }
     // the workers always join back, also after an error, so no stream is left forked
@@ -524,6 +570,14 @@ nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int 
         NJ_HIP(hipStreamWaitEvent(s, c->worker_done[k], 0));
     }
     return st;
+}
+
+nj_status run_concurrent(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Arena A0, hipStream_t s)
+{
+    std::vector<double> cost(n);
+    for (int z = 0; z < n; z++) cost[z] = job_cost(cts, jobs[z]);
+    return on_workers(c, cost, worker_words(c, cts, jobs, n), A0, s,
+                      [&](int z, Arena B, hipStream_t w) { return run_plain(c, cts, &jobs[z], 1, B, w); });
 }
 
 size_t schedule_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, int mode)
@@ -587,7 +641,7 @@ nj_status nj_batch_create_mode(nj_ctx *c, const nj_plan *cts, nj_job *jobs, int 
     if (st) return st;
     if (!out) return fail(NJ_EINVAL, "nj_batch_create: null output");
     if (mode < 0 || mode > 3) return fail(NJ_EINVAL, "nj_batch_create: mode must be 0, 1, 2 or 3");
-    if (mode == 2 && (st = workers_ready(c))) return st;
+    if ((mode == 1 || mode == 2) && (st = workers_ready(c))) return st;  // streams made before capture
     const size_t words = schedule_words(c, cts, jobs, n, mode);
     nj_batch *b = new nj_batch();
     b->c = c;

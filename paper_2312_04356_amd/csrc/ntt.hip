@@ -75,9 +75,120 @@ __device__ __forceinline__ void gs_round(double v[16], int t0, int hi, int tile,
     }
 }
 
+// The 15 twiddles of one round (tile strides t0 .. t0/8) of butterfly block hi: stage
+// s's 2^s words at tw[2^s - 1 + i], W[mm + tile (mm >> logN1) + (hi << s) + i] with
+// mm = N / (2 (t0 >> s)).  The forward and the inverse table are indexed alike.
+__device__ __forceinline__ void round_tw(double tw[15], int t0, int hi, int tile, int logN1, const double *W, int N)
+{
+#pragma unroll
+    for (int st = 0; st < 4; st++) {
+        const int mm = N / (2 * (t0 >> st));
+        const int base = mm + tile * (mm >> logN1) + (hi << st);
+#pragma unroll
+        for (int i = 0; i < (1 << st); i++) tw[(1 << st) - 1 + i] = W[base + i];
+    }
+}
+
+// ct_round / gs_round with the round's twiddles given (round_tw)
+__device__ __forceinline__ void ct_round_tw(double v[16], const double tw[15], Mod m)
+{
+#pragma unroll
+    for (int st = 0; st < 4; st++) {
+        const int step = 8 >> st;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k & step) continue;
+            const double U = v[k], V = mul_lazy(v[k + step], tw[(1 << st) - 1 + (k >> (4 - st))], m);
+            v[k] = U + V;
+            v[k + step] = U - V;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = reduce(v[k], m);
+}
+
+__device__ __forceinline__ void gs_round_tw(double v[16], const double tw[15], Mod m)
+{
+#pragma unroll
+    for (int st = 3; st >= 0; st--) {
+        const int step = 8 >> st;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k & step) continue;
+            const double U = v[k], V = v[k + step];
+            v[k] = corr(U + V, m);
+            v[k + step] = corr(mul_lazy(U - V, tw[(1 << st) - 1 + (k >> (4 - st))], m), m);  // U - V in (-t, t)
+        }
+    }
+}
+
 // The last 12 forward stages of one 4096-word tile: v holds words tid + 256 k on
 // entry; on return the transformed tile is in s (word x at pad16(x)), after a barrier.
+// Each round's twiddles are requested before the barrier that precedes the round (the
+// registers of v are free there), so their latency overlaps the barrier wait.
 __device__ __forceinline__ void tile_forward(double v[16], double *s, int tid, int tile, int logN1, const double *W,
+                                             int N, Mod m)
+{
+    double tw[15];
+    // round 0: strides 2048..256, thread tid owns x = tid + 256 k
+    round_tw(tw, 2048, 0, tile, logN1, W, N);
+    ct_round_tw(v, tw, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+    // round 1: strides 128..16, (lo, hi) = (tid & 15, tid >> 4): x = lo + 16 k + 256 hi
+    const int lo = tid & 15, hi = tid >> 4;
+    round_tw(tw, 128, hi, tile, logN1, W, N);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+    ct_round_tw(v, tw, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+    // round 2: strides 8..1, thread owns x = 16 tid + k
+    round_tw(tw, 8, tid, tile, logN1, W, N);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+    ct_round_tw(v, tw, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+    __syncthreads();
+}
+
+// The first 12 inverse stages of one 4096-word tile (inverse twiddles W): v holds
+// words tid + 256 k on entry and on return; s must be free on entry (callers that used
+// it before put a barrier first).  Twiddles requested ahead as in tile_forward.
+__device__ __forceinline__ void tile_inverse(double v[16], double *s, int tid, int tile, int logN1, const double *W,
+                                             int N, Mod m)
+{
+    double tw[15];
+    round_tw(tw, 8, tid, tile, logN1, W, N);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(tid + 256 * k)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(16 * tid + k)];
+    gs_round_tw(v, tw, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(16 * tid + k)] = v[k];
+    const int lo = tid & 15, hi = tid >> 4;
+    round_tw(tw, 128, hi, tile, logN1, W, N);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(lo + 16 * k + 256 * hi)];
+    gs_round_tw(v, tw, m);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s[pad16(lo + 16 * k + 256 * hi)] = v[k];
+    round_tw(tw, 2048, 0, tile, logN1, W, N);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = s[pad16(tid + 256 * k)];
+    gs_round_tw(v, tw, m);
+}
+
+// tile_forward and tile_inverse with each round's twiddles loaded where they are used
+// (fewer live registers, for kernels held to 128 VGPRs)
+__device__ __forceinline__ void tile_forward_lean(double v[16], double *s, int tid, int tile, int logN1, const double *W,
                                              int N, Mod m)
 {
     // round 0: strides 2048..256, thread tid owns x = tid + 256 k
@@ -104,10 +215,7 @@ __device__ __forceinline__ void tile_forward(double v[16], double *s, int tid, i
     __syncthreads();
 }
 
-// The first 12 inverse stages of one 4096-word tile (inverse twiddles W): v holds
-// words tid + 256 k on entry and on return; s must be free on entry (callers that used
-// it before put a barrier first).
-__device__ __forceinline__ void tile_inverse(double v[16], double *s, int tid, int tile, int logN1, const double *W,
+__device__ __forceinline__ void tile_inverse_lean(double v[16], double *s, int tid, int tile, int logN1, const double *W,
                                              int N, Mod m)
 {
 #pragma unroll
@@ -577,7 +685,7 @@ __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, co
     double v[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
-    tile_forward(v, s, tid, tile, logN1, W, N, m);
+    tile_forward_lean(v, s, tid, tile, logN1, W, N, m);
     const uint64_t *u = u_base + ((size_t)z * 2 * ne + (size_t)p * ne + i) * N + t0;
     const uint64_t *add = p == 0 ? mj.add[z] : nullptr;
     const uint32_t g = mj.g_add[z];
@@ -608,7 +716,7 @@ __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, co
 #pragma unroll
         for (int k = 0; k < 16; k++) v[k] = u2d(out[tid + 256 * k]);  // this thread's own words
         __syncthreads();
-        tile_inverse(v, s, tid, tile, logN1, itw + (size_t)i * N, N, m);
+        tile_inverse_lean(v, s, tid, tile, logN1, itw + (size_t)i * N, N, m);
 #pragma unroll
         for (int k = 0; k < 16; k++) last_out[(size_t)p * N + t0 + tid + 256 * k] = d2u(v[k]);
     }

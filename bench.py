@@ -164,9 +164,11 @@ def job_plans(g, specs, n1_of=None):
     return plans
 
 
-def tune_n1(g, plans, level=15, reps=3):
-    """exhaustive timing of the baby-step count n1 (powers of two within a factor 4 of
-    sqrt(#diagonals)) for each plan's structure, on random-diagonal plans with timing keys"""
+def tune_splits(g, plans, level=15, reps=3):
+    """exhaustive timing, per plan structure, of the baby-step count n1 (powers of two
+    within a factor 4 of sqrt(#diagonals)) and of the giant steps' ModDown (one per giant
+    step, or one for all: lazy), on random-diagonal plans with timing keys; returns
+    {key: (n1, lazy)}"""
     gctx, out = g.ctx, {}
     gctx.nj_timing_keys(16)
     try:
@@ -177,9 +179,11 @@ def tune_n1(g, plans, level=15, reps=3):
             cands = [1 << k for k in range(12) if r / 4 <= (1 << k) <= 4 * r and (1 << k) <= len(offs)]
             t = {}
             for n1 in cands:
-                rp = gctx.nj_plan_create_random(level, ell, offs, n1, bi, bo, seed=n1)
-                t[n1] = gctx.nj_time_plan(rp, level, reps=reps)
-                del rp
+                for lazy in (False, True) if bi == 1 and bo == 1 else (False,):  # block transforms: never lazy
+                    rp = gctx.nj_plan_create_random(level, ell, offs, n1, bi, bo, seed=n1)
+                    rp.set_lazy(lazy)
+                    t[(n1, lazy)] = gctx.nj_time_plan(rp, level, reps=reps)
+                    del rp
             out[key] = min(t, key=t.get)
     finally:
         gctx.nj_timing_keys(0)
@@ -191,7 +195,8 @@ def jobs_bench(g, n_jobs, steps=2):
     on 16/64/256 channels per ciphertext) at its level -> level drop -> ModRaise ->
     CoeffToSlot -> split.  Plain: one job after another with default plans.  Batched:
     each conv on its fused path, then CoeffToSlot over all 64 outputs together, replayed
-    as one HIP graph, with n1 tuned by timing; across levels: the same with each conv
+    as one HIP graph, with n1 and lazy giant steps tuned by timing per shape; across
+    levels: the same with each conv
     plan's jobs grouped across their levels.  Concurrent: the plain schedule spread over
     4 worker streams, as one HIP graph."""
     import torch
@@ -199,12 +204,11 @@ def jobs_bench(g, n_jobs, steps=2):
     gctx = g.ctx
     specs = synth.job_mix(n_jobs, 1004)
     default = job_plans(g, specs)
-    n1_of = tune_n1(g, default)
-    changed = {k: v for k, v in n1_of.items() if v != int(math.ceil(math.sqrt(len(default[k].offsets(0)))))}
-    tuned = dict(default)
-    if changed:
-        rebuilt = job_plans(g, [(o, c, 0) for (o, c) in changed], {k: n1_of[k] for k in changed})
-        tuned.update(rebuilt)
+    best = tune_splits(g, default)
+    n1_of = {k: v[0] for k, v in best.items()}
+    tuned = job_plans(g, [(o, c, 0) for (o, c) in best], n1_of)
+    for k, (_, lazy) in best.items():
+        tuned[k].set_lazy(lazy)
     gs = set(g.cts_plan.galois())
     for p in list(default.values()) + list(tuned.values()):
         gs |= set(p.galois())
@@ -253,7 +257,7 @@ def jobs_bench(g, n_jobs, steps=2):
             "speedup_vs_plain": round(plain / replay, 3), "across_levels_graph_ms": round(across, 3),
             "concurrent_graph_ms": round(conc, 3),
             "concurrent_speedup_vs_plain": round(plain / conc, 3),
-            "tuned_n1": {"%s/C%d" % k: v for k, v in sorted(n1_of.items())}}
+            "tuned_n1_lazy": {"%s/C%d" % k: list(v) for k, v in sorted(best.items())}}
 
 
 PLAN_MODEL = os.path.join(ROOT, "paper_2312_04356_amd", "data", "plan_model_n65536.json")

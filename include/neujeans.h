@@ -385,7 +385,8 @@ typedef struct {
  *     afterwards sees every output.
  *   mode 3, batched across levels: as mode 1, but single-block jobs of one conv plan
  *     run together across their levels (each baby and giant rotation key read once for
- *     up to 16 jobs; ModUp and ModDown batched per level, with unfused transforms).
+ *     up to 16 jobs; ModUp and ModDown batched per level, with unfused transforms);
+ *     jobs of a plan with lazy giant steps (nj_plan_set_lazy) run one at a time.
  * All modes give bit-identical outputs.  Errors: NJ_EINVAL (bad plan or job),
  * NJ_ELEVEL (input level outside 1..plan level), NJ_ENOKEY, NJ_ENOMEM. */
 nj_status nj_batch_run(nj_ctx *ctx, const nj_plan *cts, nj_job *jobs, int n_jobs, int mode, void *stream);

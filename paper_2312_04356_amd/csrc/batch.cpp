@@ -389,6 +389,8 @@ size_t batched_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, b
             const nj_lt_t lt = at_level(j0.conv->lts[0], j0.in.level);
             lmax = lt.level;
             w = lt.bo * 2 * N * (lt.level + 1) + block_words(c, lt);
+        } else if (j0.conv->lts[0].lazy) {  // one job at a time (conv_to_pool)
+            for (int z : u) w = std::max(w, conv_words(c, jobs[z]));
         } else {
             std::vector<MixJob> mj = unit_jobs(jobs, u);
             for (const MixJob &m : mj) w += 2 * N * (m.level + 1), lmax = std::max(lmax, m.level);
@@ -418,6 +420,11 @@ nj_status convs_across_levels(nj_ctx *c, const nj_job *jobs, int n, const std::v
             if ((st = block_bsgs_apply(c, lt, j0.in.data, y, B, s))) return st;
             for (int ob = 0; ob < lt.bo; ob++)
                 if ((st = rescale(c, lt.level, y + ob * clen, pool + (off[u[0]] + ob) * 2 * N, B, s, 1))) return st;
+            continue;
+        }
+        if (j0.conv->lts[0].lazy) {  // the mixed-level path has no lazy giant steps: one job at a time
+            for (int z : u)
+                if ((st = conv_to_pool(c, jobs[z], pool + off[z] * 2 * N, B, s))) return st;
             continue;
         }
         std::vector<MixJob> mj = unit_jobs(jobs, u);

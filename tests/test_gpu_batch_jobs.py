@@ -133,7 +133,7 @@ def test_plain_batched_graph_agree_small():
     K1 = RNG.uniform(-1, 1, (C, C, 1, 1))
     Kb = RNG.uniform(-1, 1, (2 * C, 2 * C, 3, 3))
     p3 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K3), level=6)
-    p1 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K1), level=6)
+    p1 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K1), level=6).set_lazy(True)  # one ModDown
     pb = gctx.nj_conv_plan_create_taps(w0, 2 * C, 2 * C, PL.taps_same(Kb), level=5)
     assert p3.layout()[4:] == (1, 1) and pb.layout()[4:] == (2, 2)
     g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(pb.galois()) | set(g.cts_plan.galois())))

@@ -355,7 +355,7 @@ nj_status conv_to_pool(nj_ctx *c, const nj_job &j, uint64_t *out, Arena A, hipSt
     const size_t clen = 2 * N * (lt.level + 1);
     uint64_t *y = A.take(lt.bo * clen);
     if (!y) return fail(NJ_ENOMEM, "scratch too small");
-    nj_status st = lt.bi == 1 && lt.bo == 1 ? bsgs_apply(c, lt, j.in.data, y, 1, A, s)
+    nj_status st = lt.bi == 1 && lt.bo == 1 ? bsgs_apply(c, lt, j.in.data, y, lt.hoist ? 1 : 0, A, s)
                                             : block_bsgs_apply(c, lt, j.in.data, y, A, s);
     for (int ob = 0; ob < lt.bo && !st; ob++) st = rescale(c, lt.level, y + ob * clen, out + ob * 2 * N, A, s, 1);
     return st;
@@ -488,9 +488,12 @@ nj_status run_plain(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Ar
         const size_t clen = 2 * N * (l + 1), clen1 = 2 * N * l;
         uint64_t *y = A.take(bo * clen), *r = A.take(bo * clen1), *lo = A.take(bo * 2 * N);
         if (!lo) return fail(NJ_ENOMEM, "scratch too small");
-        st = lt.bi == 1 && bo == 1 ? bsgs_apply(c, lt, j.in.data, y, 1, A, s) : block_bsgs_apply(c, lt, j.in.data, y, A, s);
-        if (st) return st;
-        if ((st = rescale_batch(c, l, bo, y, r, A, s))) return st;
+        if (lt.bi == 1 && bo == 1) {  // as nj_conv2d_cins: the rescale's first pass rides on the last ModDown
+            if ((st = bsgs_rescale(c, lt, j.in.data, y, r, A, s))) return st;
+        } else {  // as nj_conv2d_block
+            if ((st = block_bsgs_apply(c, lt, j.in.data, y, A, s))) return st;
+            if ((st = rescale_batch(c, l, bo, y, r, A, s))) return st;
+        }
         for (int ob = 0; ob < bo; ob++) {
             NJ_HIP(hipMemcpy2DAsync(lo + ob * 2 * N, N * 8, r + ob * clen1, l * N * 8, N * 8, 2, hipMemcpyDeviceToDevice,
                                     s));

@@ -113,8 +113,9 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M)
 // ModUp of K polynomials stored at d + z dstride N (evaluation form; dstride in limbs,
 // l+1 when packed) into ext + z dnum ne N.
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride,
-                      bool tiles, const GalTab *gt, const int *zoff)
+                      bool tiles, const GalTab *gt, const int *zoff, bool drop)
 {
+    const auto &tabs = drop ? c->modup_drop[l] : c->modup[l];
     const int N = c->N, ne = l + 1 + c->alpha, nd = n_digits(c, l);
     // N >= 8192: the conversion's input factors ride on the inverse transform, and the
     // conversion runs fused with its outputs' column pass
@@ -141,7 +142,7 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
         sh.nd = std::min(4, nd - j0);
         for (int jj = 0; jj < sh.nd; jj++) {
             const int j = j0 + jj;
-            const BconvTab &bt = c->modup[l][j];
+            const BconvTab &bt = tabs[j];
             sh.m[jj] = bt.m, sh.n_out[jj] = bt.n_out, sh.in_off0[jj] = j * c->alpha;
             sh.hat_inv[jj] = bt.hat_inv, sh.hat[jj] = bt.hat;
             for (int a = 0; a < bt.m; a++) sh.in_pidx[jj][a] = bt.in_pidx[a];
@@ -156,7 +157,7 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
     lt.n = 0;
     for (int z = 0; z < K; z++)
         for (int j = 0; j < nd; j++) {
-            const BconvTab &bt = c->modup[l][j];
+            const BconvTab &bt = tabs[j];
             for (int o = 0; o < bt.n_out; o++) {
                 lt.pidx[lt.n] = bt.out_pidx[o];
                 lt.off[lt.n] = (z * nd + j) * ne + bt.out_limb[o];
@@ -173,7 +174,7 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj);
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop);
 
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
@@ -184,12 +185,14 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 
 // ModDown of K jobs' inner products (M.u) and the combine into their outputs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj)
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
     if (p_tiled && !fused) return fail(NJ_EUNSUPPORTED, "ModDown: pre-transformed special-prime rows need N >= 8192");
     const bool one = !sum && N >= 4096 && K == 1;  // the fused combine of one job
+    if (drop && (sum || !fused || last_out || conj || l < 2))
+        return fail(NJ_EUNSUPPORTED, "ModDown: limbs 0 and l only with the fused combine, no hand-off, level >= 2");
     if (last_out && !(one && fused)) return fail(NJ_EUNSUPPORTED, "ModDown: the rescale hand-off needs one job, N >= 8192");
     if (conj && !one) return fail(NJ_EUNSUPPORTED, "ModDown: the fused split needs one job, N >= 4096");
     // one job with a previous value held elsewhere: the fused combine reads it there
@@ -213,17 +216,18 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
                 }
             }
     NJ_HIP(intt(lp));
-    const BconvTab &bt = c->moddown[l];
+    const BconvTab &bt = drop ? c->moddown_drop[l] : c->moddown[l];
     BconvShared sh;
     sh.nd = 1;
     sh.m[0] = bt.m, sh.n_out[0] = bt.n_out, sh.in_off0[0] = 0, sh.hat_inv[0] = bt.hat_inv, sh.hat[0] = bt.hat;
     for (int a = 0; a < bt.m; a++) sh.in_pidx[0][a] = bt.in_pidx[a];
-    for (int o = 0; o < bt.n_out; o++) sh.out_pidx[0][o] = bt.out_pidx[o], sh.out_off[0][o] = o;
+    for (int o = 0; o < bt.n_out; o++) sh.out_pidx[0][o] = bt.out_pidx[o], sh.out_off[0][o] = bt.out_limb[o];
     BconvPtrs jp;
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
     NJ_HIP(fused ? launch_bconv_col(c, sh, jp, 2 * K, s) : launch_bconv_multi(c, sh, jp, 2 * K, s));
     if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
-        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out, conj));
+        NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out, conj,
+                                  drop ? l - 1 : 0));
         return NJ_OK;
     }
     auto ntt = [&](const LimbTab &t) { return fused ? launch_ntt_tiles(c, M.conv, t, s) : launch_ntt(c, M.conv, t, false, s); };
@@ -286,7 +290,7 @@ size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt)
 
 // sum_d diag_d (.) (in <<< j_d u), baby-step giant-step; out must not alias in.
 nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
-                     hipStream_t s, uint64_t *last_out, bool *last_done)
+                     hipStream_t s, uint64_t *last_out, bool *last_done, bool drop)
 {
     if (last_done) *last_done = false;
     const int l = lt.level, n = c->N / 2;
@@ -367,6 +371,11 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
     if (lt.lazy) {  // key inner products summed over Q_l u P, one ModDown
         uint64_t *usum = A.take(2 * ne * N), *c0sum = A.take(plen);
         if (!c0sum) return fail(NJ_ENOMEM, "scratch too small");
+        // drop: the output goes on to a rescale and a drop to level 0, which read only its
+        // Q limbs 0 and l; the giant steps' digits, inner products, c0 sums and ModDown
+        // are computed for those limbs (and the special primes) alone
+        const bool dr = drop && fuse_ip(c, l) && l >= 2 && !last_out;
+        const int skip = dr ? l - 1 : 0;
         for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
             const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);
             const bool f = fuse_ip(c, l);  // fused: tau_ge rides on ModUp and the own-limb reads
@@ -385,15 +394,15 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
                 kj.key[z] = key_of(c, ge);
             }
             if (f) {
-                if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff))) return st;
+                if ((st = modup_multi(c, l, K, inner + plen, M, s, -1, false, &gt, zoff, dr))) return st;
             } else {
                 NJ_HIP(launch_automorph_multi(c, aj, K, l + 1, s));
                 if ((st = modup_multi(c, l, K, M.d, M, s, -1, !f))) return st;
             }
             const bool last = c0 + K == gl.size();  // its special-prime rows go on to ModDown's inverse transform
-            NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s, last ? M.pc : nullptr)
+            NJ_HIP(f ? launch_ntt_ip(c, l, kj, K, usum, 1, c0 ? 1 : 0, s, last ? M.pc : nullptr, skip)
                      : launch_key_ip_sum(c, l, kj, K, usum, c0 ? 1 : 0, s));
-            NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s));
+            NJ_HIP(launch_automorph_acc(c, ac, K, l + 1, c0sum, 0, c0 ? 3 : 2, s, skip));
         }
         MultiBufs M1 = M;
         M1.u = usum;
@@ -401,7 +410,7 @@ nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t 
         mj.add[0] = c0sum, mj.g_add[0] = 1, mj.out[0] = out;
         const bool hand = last_out && N >= 8192 && c->alpha <= 8;  // the rescale's first pass rides along
         if (hand && last_done) *last_done = true;
-        return ks_down(c, l, 1, mj, 0, acc, M1, s, fuse_ip(c, l), hand ? last_out : nullptr);
+        return ks_down(c, l, 1, mj, 0, acc, M1, s, fuse_ip(c, l), hand ? last_out : nullptr, nullptr, dr);
     }
     for (size_t c0 = 0; c0 < gl.size(); c0 += kGiantChunk) {
         const int K = (int)std::min((size_t)kGiantChunk, gl.size() - c0);

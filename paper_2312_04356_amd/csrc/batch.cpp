@@ -355,7 +355,8 @@ nj_status conv_to_pool(nj_ctx *c, const nj_job &j, uint64_t *out, Arena A, hipSt
     const size_t clen = 2 * N * (lt.level + 1);
     uint64_t *y = A.take(lt.bo * clen);
     if (!y) return fail(NJ_ENOMEM, "scratch too small");
-    nj_status st = lt.bi == 1 && lt.bo == 1 ? bsgs_apply(c, lt, j.in.data, y, lt.hoist ? 1 : 0, A, s)
+    // only the limbs the rescale and the level drop read
+    nj_status st = lt.bi == 1 && lt.bo == 1 ? bsgs_apply(c, lt, j.in.data, y, lt.hoist ? 1 : 0, A, s, nullptr, nullptr, true)
                                             : block_bsgs_apply(c, lt, j.in.data, y, A, s);
     for (int ob = 0; ob < lt.bo && !st; ob++) st = rescale(c, lt.level, y + ob * clen, out + ob * 2 * N, A, s, 1);
     return st;

@@ -284,6 +284,36 @@ nj_status nj_ctx_create(const nj_params *P, nj_ctx **out)
             return hip_fail(e, "nj_ctx_create: ModDown tables");
         }
     }
+    // the conversions restricted to Q limbs 0 and l (key switches whose output is rescaled
+    // and dropped to level 0)
+    c->modup_drop.resize(c->n_q);
+    c->moddown_drop.resize(c->n_q);
+    for (int l = 0; l <= c->L; l++) {
+        const int nd = n_digits(c, l);
+        c->modup_drop[l].resize(nd);
+        for (int j = 0; j < nd; j++) {
+            const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
+            std::vector<int> from, to, to_limb;
+            for (int a = lo; a < hi; a++) from.push_back(a);
+            for (int tpos = 0; tpos < l + 1 + c->alpha; tpos++) {
+                if ((tpos >= lo && tpos < hi) || (tpos > 0 && tpos < l)) continue;
+                to.push_back(tpos <= l ? tpos : c->n_q + (tpos - l - 1));
+                to_limb.push_back(tpos);
+            }
+            if ((e = make_bconv(c, from, to, to_limb, c->modup_drop[l][j])) != hipSuccess) {
+                nj_ctx_destroy(c);
+                return hip_fail(e, "nj_ctx_create: ModUp tables");
+            }
+        }
+        std::vector<int> from, to, to_limb;
+        for (int k = 0; k < c->alpha; k++) from.push_back(c->n_q + k);
+        to.push_back(0), to_limb.push_back(0);
+        if (l > 0) to.push_back(l), to_limb.push_back(l);
+        if ((e = make_bconv(c, from, to, to_limb, c->moddown_drop[l])) != hipSuccess) {
+            nj_ctx_destroy(c);
+            return hip_fail(e, "nj_ctx_create: ModDown tables");
+        }
+    }
     // basis-conversion input factors folded into the inverse transforms' N^-1
     {
         auto fac = [&](const std::vector<int> &digit, int a) {  // N^-1 (D/q_a)^-1 mod q_a
@@ -366,6 +396,9 @@ void nj_ctx_destroy(nj_ctx *c)
     for (auto &lv : c->modup)
         for (auto &b : lv) fr(b.hat_inv), fr(b.hat);
     for (auto &b : c->moddown) fr(b.hat_inv), fr(b.hat);
+    for (auto &b : c->moddown_drop) fr(b.hat_inv), fr(b.hat);
+    for (auto &v : c->modup_drop)
+        for (auto &b : v) fr(b.hat_inv), fr(b.hat);
     for (auto *p : c->d_upscale) fr(p);
     fr(c->layer_buf);
     fr(c->d_downscale);

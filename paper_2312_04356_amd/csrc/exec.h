@@ -52,8 +52,10 @@ bool multi_bufs(const nj_ctx *c, int l, int K, Arena &A, MultiBufs &M);
 // for the fused key inner product)
 // (gt: job z's polynomial is read through X -> X^g[z], N >= 8192; zoff: job z's
 // polynomial at d + zoff[z] N instead of d + z dstride N)
+// (drop: only the targets a rescale followed by a drop to level 0 needs, Q limbs 0 and l
+// and the special primes)
 nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, hipStream_t s, int dstride = -1,
-                      bool tiles = true, const GalTab *gt = nullptr, const int *zoff = nullptr);
+                      bool tiles = true, const GalTab *gt = nullptr, const int *zoff = nullptr, bool drop = false);
 // whether ModUp leaves the tile pass to the key inner product (launch_ntt_ip)
 bool fuse_ip(const nj_ctx *c, int l);
 // ModEval of Re and Im evaluated together (packed) when N >= 8192
@@ -77,8 +79,11 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 // (sum = 0: for K = 1 it may be any ciphertext, else it must be the outputs).
 // last_out, one job, N >= 8192: the output's last limb also leaves through the first
 // 12 stages of its inverse transform into last_out [2][N], for rescale(last_pre))
+// drop: only output limbs 0 and l (the fused one-job combine, no last_out or conj, l >= 2;
+// the inner products' Q rows 0 and l and special-prime rows are all it reads)
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr, const MdConj *conj = nullptr);
+                  hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr, const MdConj *conj = nullptr,
+                  bool drop = false);
 
 // inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
 struct MacEntry {
@@ -91,8 +96,10 @@ nj_lt_t at_level(const nj_lt_t &lt, int l);
 size_t bsgs_words(const nj_ctx *c, const nj_lt_t &lt);
 // (last_out [2][N]: when the transform ends in a one-job ModDown it also writes its last
 // limb after the first pass of an inverse transform there and sets *last_done)
+// (drop: out goes on to a rescale and a drop to level 0; with lazy giant steps at N >= 8192
+// only its limbs 0 and l are computed, the others are left undefined)
 nj_status bsgs_apply(nj_ctx *c, const nj_lt_t &lt, const uint64_t *in, uint64_t *out, int hoist, Arena A,
-                     hipStream_t s, uint64_t *last_out = nullptr, bool *last_done = nullptr);
+                     hipStream_t s, uint64_t *last_out = nullptr, bool *last_done = nullptr, bool drop = false);
 // bsgs_apply into y, then rescale into out (which may be x); the rescale's first pass
 // rides on the transform's last ModDown where it can
 nj_status bsgs_rescale(nj_ctx *c, const nj_lt_t &lt, const uint64_t *x, uint64_t *y, uint64_t *out, Arena A,

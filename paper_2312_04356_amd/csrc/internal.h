@@ -212,6 +212,10 @@ struct nj_ctx {
     // ModUp tables [level][digit]; ModDown tables [level]
     std::vector<std::vector<nj::BconvTab>> modup;
     std::vector<nj::BconvTab> moddown;
+    // the same conversions with only the targets a rescale followed by a drop to level 0
+    // reads: Q limbs 0 and l (and, for ModUp, the special primes)
+    std::vector<std::vector<nj::BconvTab>> modup_drop;
+    std::vector<nj::BconvTab> moddown_drop;
     // per level: device [l+1] N^-1 (D_j/q_i)^-1 mod q_i (i in digit j), the ModUp inputs'
     // factor folded into their inverse transform; and [n_primes] N^-1 (P/p_a)^-1 mod p_a
     std::vector<double *> d_upscale;
@@ -317,9 +321,10 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
 // 1..4 digits, every g = 1): per job u_base + z 2 ne N, or (sum) one output summed over
 // the jobs; accumulate adds to the output's previous value
 hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
-                         int accumulate, hipStream_t s, uint64_t *pout = nullptr);
+                         int accumulate, hipStream_t s, uint64_t *pout = nullptr, int skip = 0);
 // (pout given: the special-prime rows skip u and leave through the first 12 stages of
-// ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout)
+// ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout;
+// skip > 0: Q limbs 1..skip are not computed, skip = l - 1 keeping Q limbs 0 and l)
 // centred lift of n_polys limbs (prime src_pidx, coefficient form, src + z N) into
 // primes 0..n_out-1 with the column pass applied, out [n_polys][n_out][N] (N >= 8192)
 hipError_t launch_lift_col(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_polys, int n_out, uint64_t *out,
@@ -329,9 +334,10 @@ hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTa
 // (acc0: job 0's previous value read from there instead of its output; last_out, one
 // job: the last limb also leaves through the first 12 stages of its inverse transform
 // into last_out [2][N], for launch_rescale_fused(last_tiled))
+// skip > 0 (with cols_done, no last_out or conj): only output limbs 0 and 1 + skip ..
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0 = nullptr,
-                              uint64_t *last_out = nullptr, const MdConj *conj = nullptr);
+                              uint64_t *last_out = nullptr, const MdConj *conj = nullptr, int skip = 0);
 hipError_t launch_ntt_fast(const nj_ctx *c, uint64_t *data, const uint64_t *src, const LimbTab &lt, bool inverse,
                            hipStream_t s);
 // out = a op b per limb (op 0 add, 1 sub, 2 mul), evaluation form
@@ -378,8 +384,9 @@ hipError_t launch_add_int(const nj_ctx *c, uint64_t *poly, int n_limbs, const Li
 hipError_t launch_zero(const nj_ctx *c, uint64_t *p, size_t words, hipStream_t s);
 hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int accumulate,
                              hipStream_t s);
+// (skip > 0: limbs 1..skip left out)
 hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,
-                                size_t ostride, int mode, hipStream_t s);
+                                size_t ostride, int mode, hipStream_t s, int skip = 0);
 hipError_t launch_key_ip_mixed(const nj_ctx *c, const KeyJobsX &kj, int n_jobs, const uint64_t *key, hipStream_t s);
 hipError_t launch_bsgs_mac(const nj_ctx *c, int level, const MacPlan &mp, const uint64_t *diag, uint64_t *inner,
                            int n_diag, hipStream_t s,

@@ -444,9 +444,9 @@ hipError_t launch_key_ip_shared(const nj_ctx *c, int level, const KeyJobs &kj, i
 // c0 parts of the lazy giant steps: out (+)= tau_{g_z}(in_z) over l+1 limbs, per job
 // (mode 0 / 1, out_z at out + z ostride) or summed over the jobs into out (mode 2 / 3)
 __global__ __launch_bounds__(kBT) void k_automorph_acc(AutoJobs aj, int n_jobs, uint64_t *out, size_t ostride,
-                                                      int mode, const PrimeInfo *info, int logN)
+                                                      int mode, const PrimeInfo *info, int logN, int skip)
 {
-    const int N = 1 << logN, i = blockIdx.y;
+    const int N = 1 << logN, i = blockIdx.y == 0 ? 0 : (int)blockIdx.y + skip;
     const int k = blockIdx.x * kBT + threadIdx.x;
     if (k >= N) return;
     const Mod m = info[i].m;
@@ -468,12 +468,14 @@ __global__ __launch_bounds__(kBT) void k_automorph_acc(AutoJobs aj, int n_jobs, 
 }
 
 hipError_t launch_automorph_acc(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, uint64_t *out,
-                                size_t ostride, int mode, hipStream_t s)
+                                size_t ostride, int mode, hipStream_t s, int skip)
 {
+    if (skip < 0 || skip > std::max(0, n_limbs - 2)) return hipErrorInvalidValue;
+    n_limbs -= skip;  // limb 0, then limbs 1 + skip ..
     dim3 grid((c->N + kBT - 1) / kBT, n_limbs, mode < 2 ? n_jobs : 1);
     const double words = (double)n_limbs * c->N * (mode < 2 ? n_jobs * (mode ? 3.0 : 2.0) : n_jobs + (mode == 3 ? 2.0 : 1.0));
     return launch(c, PROF_OTHER, 8.0 * words, k_automorph_acc, grid, dim3(kBT), s, aj, n_jobs, out, ostride, mode,
-                  c->d_info, c->log_n);
+                  c->d_info, c->log_n, skip);
 }
 
 // Mixed-level form of k_key_ip_shared: grid row t is Q limb t for t <= lmax, special

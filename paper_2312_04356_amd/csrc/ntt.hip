@@ -411,7 +411,9 @@ __device__ __forceinline__ void ip_load_x(const KeyJobs &kj, const IpRow &r, int
 // the converted limb ext_z[j][t] of tau_g(d_z), which arrives with only its column
 // pass applied: the block finishes that tile's transform in LDS and
 // multiplies it by the key words at once, so extended digits are never stored in
-// evaluation form.  Grid (jobs, N/4096, l+1+alpha).  SUM: u = (accumulate ? u : 0) +
+// evaluation form.  Grid (jobs, N/4096, l+1+alpha-skip): grid row 0 is limb 0, row r > 0
+// limb r + skip (skip = l - 1: only Q limbs 0 and l and the special primes, what a
+// rescale followed by a drop to level 0 reads).  SUM: u = (accumulate ? u : 0) +
 // the sum over all jobs (one block per tile); else job z = blockIdx.x has its own u_z
 // = u_base + z 2 ne N (plus its previous value when accumulate): jobs vary fastest, so
 // jobs sharing one key read each key tile close together in time.  After each job the
@@ -423,12 +425,12 @@ __device__ __forceinline__ void ip_load_x(const KeyJobs &kj, const IpRow &r, int
 template <int ND, bool SUM>
 __global__ __launch_bounds__(kNT, 2) void k_ntt_ip(KeyJobs kj, int n_jobs, uint64_t *u_base, int accumulate, int level,
                                                 int L, int alpha, int nq, const double *tw, const PrimeInfo *info,
-                                                int logN, uint64_t *pout, const double *itw)
+                                                int logN, uint64_t *pout, const double *itw, int skip)
 {
     __shared__ double s[kT + kT / 16];
     __shared__ double tws[kTwAll];
     const int N = 1 << logN, logN1 = logN - 12;
-    const int t = blockIdx.z, tile = blockIdx.y, tid = threadIdx.x;
+    const int t = blockIdx.z == 0 ? 0 : (int)blockIdx.z + skip, tile = blockIdx.y, tid = threadIdx.x;
     const int pidx = t <= level ? t : nq + (t - level - 1);
     const Mod m = info[pidx].m;
     const double *W = tw + (size_t)pidx * N;
@@ -672,16 +674,16 @@ template <bool CONJ>
 __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, const uint64_t *u_base, MdJobs mj, int acc,
                                                      int level, int ne, const double *pinv, const double *tw,
                                                      const PrimeInfo *info, int logN, const uint64_t *acc0,
-                                                     uint64_t *last_out, const double *itw, MdConj cj)
+                                                     uint64_t *last_out, const double *itw, MdConj cj, int skip)
 {
     __shared__ double s[kT + kT / 16];
-    const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1;
-    const int w = blockIdx.y, h = w / L1, i = w - h * L1, z = h >> 1, p = h & 1;
+    const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1, L1e = L1 - skip;
+    const int w = blockIdx.y, h = w / L1e, ie = w - h * L1e, i = ie == 0 ? 0 : ie + skip, z = h >> 1, p = h & 1;
     const int tile = blockIdx.x, tid = threadIdx.x;
     const Mod m = info[i].m;
     const double *W = tw + (size_t)i * N;
     const size_t t0 = (size_t)tile * kT;
-    const uint64_t *in = conv + (size_t)w * N + t0;
+    const uint64_t *in = conv + ((size_t)h * L1 + i) * N + t0;
     double v[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
@@ -902,10 +904,11 @@ hipError_t launch_bconv_col(const nj_ctx *c, const BconvShared &sh, const BconvP
 // as the transform followed by the combine.
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0,
-                              uint64_t *last_out, const MdConj *conj)
+                              uint64_t *last_out, const MdConj *conj, int skip)
 {
-    const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1;
-    if (N < kT || K < 1 || K > NJ_MAX_JOBS || ((last_out || conj) && K != 1) || (last_out && conj))
+    const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * (L1 - skip);
+    if (N < kT || K < 1 || K > NJ_MAX_JOBS || ((last_out || conj) && K != 1) || (last_out && conj) || skip < 0 ||
+        skip > std::max(0, level - 1) || (skip && (!cols_done || last_out || conj)))
         return hipErrorInvalidValue;
     MdConj cj{nullptr, nullptr, nullptr};
     if (conj) cj = *conj;
@@ -919,30 +922,31 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
             if (e != hipSuccess) return e;
         }
     }
-    const double bytes = 8.0 * N * (n * 3.0 + K * L1 + (acc ? n : 0));
+    const double bytes = 8.0 * N * (n * 3.0 + K * (L1 - skip) + (acc ? n : 0));
     if (conj)
         return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md<true>, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc,
-                      level, L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj);
+                      level, L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj, skip);
     return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md<false>, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
-                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj);
+                  L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj, skip);
 }
 
 // Key inner products of n_jobs jobs (digits of tau_g(d) column-passed only, own limbs
 // read from d through X -> X^g) fused with the digits' tile pass; sum = 1: one output,
 // summed over the jobs; accumulate: added to the output's previous value.
 hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u, int sum,
-                         int accumulate, hipStream_t s, uint64_t *pout)
+                         int accumulate, hipStream_t s, uint64_t *pout, int skip)
 {
     const int N = c->N, N1 = N / kT, nd = n_digits(c, level), ne = level + 1 + c->alpha;
-    if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS) return hipErrorInvalidValue;
-    const double bytes = 8.0 * N * ne * (3.0 * nd * n_jobs + 2.0 * (sum ? 1 : n_jobs) * (1 + accumulate));
-    const dim3 grid(sum ? 1 : n_jobs, N1, ne);
+    if (N1 < 2 || nd < 1 || nd > 4 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS || skip < 0 || skip > std::max(0, level - 1))
+        return hipErrorInvalidValue;
+    const double bytes = 8.0 * N * (ne - skip) * (3.0 * nd * n_jobs + 2.0 * (sum ? 1 : n_jobs) * (1 + accumulate));
+    const dim3 grid(sum ? 1 : n_jobs, N1, ne - skip);
 #define NJ_IP(ND)                                                                                                   \
     case ND:                                                                                                        \
         return sum ? launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, true>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
-                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw)           \
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw, skip)     \
                    : launch(c, PROF_KEYIP, bytes, k_ntt_ip<ND, false>, grid, dim3(kNT), s, kj, n_jobs, u, accumulate, \
-                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw);
+                            level, c->L, c->alpha, c->n_q, c->d_tw, c->d_info, c->log_n, pout, c->d_itw, skip);
     switch (nd) {
         NJ_IP(1) NJ_IP(2) NJ_IP(3) NJ_IP(4)
     }

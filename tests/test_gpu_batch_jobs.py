@@ -164,6 +164,27 @@ def test_plain_batched_graph_agree_full():
         assert_same(res[1], rep, "graph replay %d" % r)
 
 
+def test_lazy_plans_agree_full():
+    """lazy giant steps at N = 2^16: the batched schedule computes each conv's output
+    only at the limbs the rescale and the level drop read (Q limbs 0 and l, from
+    restricted ModUp digits, inner products, c0 sums and ModDown); every mode must give
+    the plain schedule's words, levels 2 (nothing left out) to 23"""
+    g = GpuWorkload("full", with_cts=True)
+    gctx, C, w0 = g.ctx, g.C, g.w["w0"]
+    K1 = RNG.uniform(-1, 1, (C, C, 1, 1))
+    p1 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(K1), level=g.ctx.L).set_lazy(True)
+    p3 = gctx.nj_conv_plan_create_taps(w0, C, C, PL.taps_same(g.K), level=g.ctx.L).set_lazy(True)
+    g.make_keys(sorted(set(p3.galois()) | set(p1.galois()) | set(g.cts_plan.galois())))
+    plans = [(p3, 1, 1), (p1, 1, 1), (p3, 1, 1), (p3, 1, 1), (p1, 1, 1), (p3, 1, 1)]
+    levels = [2, 9, 12, 23, 16, 8]
+    res, reps = run_all_modes(g, plans, levels)
+    assert_same(res[0], res[1], "batched vs plain")
+    assert_same(res[0], res[2], "concurrent vs plain")
+    assert_same(res[0], res[3], "batched across levels vs plain")
+    for r, rep in enumerate(reps):
+        assert_same(res[1], rep, "graph replay %d" % r)
+
+
 def test_conv_below_plan_level_decrypts_full():
     g = GpuWorkload("full", with_cts=False)
     gctx, C, w0 = g.ctx, g.C, g.w["w0"]

@@ -373,7 +373,10 @@ typedef struct {
 /* Runs the jobs on `stream` using the context scratch.
  *   mode 0, plain: one job after another, each step as the single-job calls run it.
  *   mode 1, batched: each conv on the fused single-ciphertext path, the rescale
- *     computing only the limb the level drop keeps, the jobs spread over the worker
+ *     computing only the limb the level drop keeps (and, for plans with lazy giant steps
+ *     at N >= 8192, the conv itself only the limbs 0 and l that rescale reads: the
+ *     giant steps' ModUp digits, inner products and ModDown are restricted to them),
+ *     the jobs spread over the worker
  *     streams as in mode 2 (convs at low levels leave much of the GPU idle); then every
  *     conv output (all at one level after ModRaise) goes through batched CoeffToSlot on
  *     `stream`, which reads each rotation key and plaintext diagonal once for up to 8

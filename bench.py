@@ -165,26 +165,16 @@ def job_plans(g, specs, n1_of=None):
 
 
 def tune_splits(g, plans, level=15, reps=3):
-    """exhaustive timing, per plan structure, of the baby-step count n1 (powers of two
-    within a factor 4 of sqrt(#diagonals)) and of the giant steps' ModDown (one per giant
-    step, or one for all: lazy), on random-diagonal plans with timing keys; returns
-    {key: (n1, lazy)}"""
+    """the library's autotuner (nj_tune_split, every candidate timed) per plan structure:
+    baby-step count n1, hoisting and the giant steps' ModDown form (one per giant step,
+    or one for all: lazy), on random-diagonal plans with timing keys; returns
+    {key: (n1, hoist, lazy)}"""
     gctx, out = g.ctx, {}
     gctx.nj_timing_keys(16)
     try:
         for key, plan in plans.items():
-            lvl, W, C, ell, bi, bo = plan.layout()
-            offs = plan.offsets(0)
-            r = math.sqrt(len(offs))
-            cands = [1 << k for k in range(12) if r / 4 <= (1 << k) <= 4 * r and (1 << k) <= len(offs)]
-            t = {}
-            for n1 in cands:
-                for lazy in (False, True) if bi == 1 and bo == 1 else (False,):  # block transforms: never lazy
-                    rp = gctx.nj_plan_create_random(level, ell, offs, n1, bi, bo, seed=n1)
-                    rp.set_lazy(lazy)
-                    t[(n1, lazy)] = gctx.nj_time_plan(rp, level, reps=reps)
-                    del rp
-            out[key] = min(t, key=t.get)
+            n1, hoist, lazy, _, _ = gctx.nj_tune_split(plan, level, model=None, reps=reps, lazy=True)
+            out[key] = (n1, hoist, lazy)
     finally:
         gctx.nj_timing_keys(0)
     return out
@@ -195,7 +185,8 @@ def jobs_bench(g, n_jobs, steps=2):
     on 16/64/256 channels per ciphertext) at its level -> level drop -> ModRaise ->
     CoeffToSlot -> split.  Plain: one job after another with default plans.  Batched:
     each conv on its fused path, then CoeffToSlot over all 64 outputs together, replayed
-    as one HIP graph, with n1 and lazy giant steps tuned by timing per shape; across
+    as one HIP graph, with n1, hoisting and lazy giant steps tuned per shape by the
+    library's autotuner; across
     levels: the same with each conv
     plan's jobs grouped across their levels.  Concurrent: the plain schedule spread over
     4 worker streams, as one HIP graph."""
@@ -207,8 +198,8 @@ def jobs_bench(g, n_jobs, steps=2):
     best = tune_splits(g, default)
     n1_of = {k: v[0] for k, v in best.items()}
     tuned = job_plans(g, [(o, c, 0) for (o, c) in best], n1_of)
-    for k, (_, lazy) in best.items():
-        tuned[k].set_lazy(lazy)
+    for k, (_, hoist, lazy) in best.items():
+        tuned[k].set_hoist(hoist).set_lazy(lazy)
     gs = set(g.cts_plan.galois())
     for p in list(default.values()) + list(tuned.values()):
         gs |= set(p.galois())
@@ -257,7 +248,7 @@ def jobs_bench(g, n_jobs, steps=2):
             "speedup_vs_plain": round(plain / replay, 3), "across_levels_graph_ms": round(across, 3),
             "concurrent_graph_ms": round(conc, 3),
             "concurrent_speedup_vs_plain": round(plain / conc, 3),
-            "tuned_n1_lazy": {"%s/C%d" % k: list(v) for k, v in sorted(best.items())}}
+            "tuned_n1_hoist_lazy": {"%s/C%d" % k: list(v) for k, v in sorted(best.items())}}
 
 
 PLAN_MODEL = os.path.join(ROOT, "paper_2312_04356_amd", "data", "plan_model_n65536.json")

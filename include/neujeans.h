@@ -557,21 +557,25 @@ nj_status nj_mlp_train(nj_mlp *mlp, const float *X, const float *y, int n, int e
 nj_status nj_mlp_predict(nj_mlp *mlp, const float *X, int n, float *out);
 
 /* Autotuner (plan selection, Sec. 2.6's BSGS split and hoisting): picks the baby-step
- * count n1 and the hoisting mode of transform t of a plan at `level` (1 <= level <= the
- * transform's).  Candidates: n1 = 0 (the default split) and the powers of two within a
- * factor 4 of sqrt(#diagonals), each hoisted or not (block transforms: hoisted only).
- * With model (may be null) and shortlist > 0, the model ranks the candidates by their
- * features (nj_plan_features of each split) and only its `shortlist` best are timed;
- * otherwise every candidate is.  The default split, hoisted, is always timed, so the
- * choice is never slower than the default as measured.  Each candidate is timed as
- * nj_time_plan times it (reps runs, median), on a plan of the same diagonal offsets with
- * random diagonals, so the rotation keys must be present or timing mode on
- * (nj_timing_keys).  Outputs: n1 (0 = default), hoist (1/0), its time in ms, and the
- * default's time (default_ms may be null).  The plan itself is not changed: rebuild it
- * with the chosen n1 (plan constructors take n1) and apply nj_plan_set_hoist.
- * Synchronous; allocates the candidate plans one at a time. */
+ * count n1, the hoisting mode and (when lazy is non-null) the giant steps' ModDown of
+ * transform t of a plan at `level` (1 <= level <= the transform's).  Candidates: n1 = 0
+ * (the default split) and the powers of two within a factor 4 of sqrt(#diagonals), each
+ * hoisted or not (block transforms: hoisted only).  With model (may be null) and
+ * shortlist > 0, the model ranks the candidates by their features (nj_plan_features of
+ * each split) and only its `shortlist` best are timed; otherwise every candidate is.
+ * The default split, hoisted, is always timed, so the choice is never slower than the
+ * default as measured.  Each candidate is timed as nj_time_plan times it (reps runs,
+ * median), on a plan of the same diagonal offsets with random diagonals, so the rotation
+ * keys must be present or timing mode on (nj_timing_keys); with lazy non-null every
+ * timed split of a single-block transform is timed both with the plan's own giant-step
+ * ModDown and with the other form (nj_plan_set_lazy: one ModDown for all giant steps,
+ * or one per step).  Outputs: n1 (0 = default), hoist (1/0), lazy (1/0; may be null:
+ * the plan's own form only), the choice's time in ms, and the default's time with the
+ * plan's own form (default_ms may be null).  The plan itself is not changed: rebuild it
+ * with the chosen n1 (plan constructors take n1) and apply nj_plan_set_hoist and
+ * nj_plan_set_lazy.  Synchronous; allocates the candidate plans one at a time. */
 nj_status nj_tune_split(nj_ctx *ctx, const nj_plan *plan, int t, int level, const nj_mlp *model, int shortlist,
-                        int reps, int *n1, int *hoist, float *ms, float *default_ms);
+                        int reps, int *n1, int *hoist, int *lazy, float *ms, float *default_ms);
 
 /* ------------------------------------------------------------ profiling */
 

@@ -124,7 +124,7 @@ _SIGS = {
     "nj_plan_create_random": (i32, [vp, i32, i32, vp, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]),
     "nj_time_plan": (i32, [vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
     "nj_plan_features": (i32, [vp, i32, i32, vp]),
-    "nj_tune_split": (i32, [vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+    "nj_tune_split": (i32, [vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp,
                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "nj_mlp_create": (i32, [u64, ctypes.POINTER(vp)]),
     "nj_mlp_destroy": (None, [vp]),
@@ -837,14 +837,16 @@ class Ctx:
                "nj_time_plan")
         return ms.value
 
-    def nj_tune_split(self, plan, level, t=0, model=None, shortlist=3, reps=3):
-        """(n1, hoist, ms, default ms) the library's autotuner picks for transform t"""
-        n1, ho = i32(), i32()
+    def nj_tune_split(self, plan, level, t=0, model=None, shortlist=3, reps=3, lazy=False):
+        """(n1, hoist, lazy, ms, default ms) the library's autotuner picks for transform t;
+        lazy=True also times the other giant-step ModDown form (else lazy is the plan's)"""
+        n1, ho, lz = i32(), i32(), i32(-1)
         ms, dms = ctypes.c_float(), ctypes.c_float()
         _check(_lib.nj_tune_split(self.ptr, plan.ptr, int(t), int(level), model.ptr if model is not None else None,
-                                  int(shortlist), int(reps), ctypes.byref(n1), ctypes.byref(ho), ctypes.byref(ms),
+                                  int(shortlist), int(reps), ctypes.byref(n1), ctypes.byref(ho),
+                                  ctypes.cast(ctypes.pointer(lz), vp) if lazy else None, ctypes.byref(ms),
                                   ctypes.byref(dms)), "nj_tune_split")
-        return n1.value, bool(ho.value), ms.value, dms.value
+        return n1.value, bool(ho.value), (bool(lz.value) if lazy else None), ms.value, dms.value
 
     def nj_cts_plan_create(self, groups):
         h = vp()

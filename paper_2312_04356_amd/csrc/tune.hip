@@ -193,7 +193,7 @@ nj_status nj_plan_features(const nj_plan *p, int t, int level, float *f)
 }
 
 nj_status nj_tune_split(nj_ctx *c, const nj_plan *p, int t, int level, const nj_mlp *model, int shortlist, int reps,
-                        int *n1_out, int *hoist_out, float *ms_out, float *default_ms)
+                        int *n1_out, int *hoist_out, int *lazy_out, float *ms_out, float *default_ms)
 {
     if (!c || !p || t < 0 || t >= (int)p->lts.size() || reps < 1 || shortlist < 0 || !n1_out || !hoist_out || !ms_out)
         return fail(NJ_EINVAL, "nj_tune_split: bad arguments");
@@ -235,20 +235,30 @@ nj_status nj_tune_split(nj_ctx *c, const nj_plan *p, int t, int level, const nj_
     for (size_t i = 0; i < cands.size(); i++)
         if (cands[i].n1 == 0 && cands[i].hoist && std::find(timed.begin(), timed.end(), (int)i) == timed.end())
             timed.push_back((int)i);
+    // each timed split with the plan's own giant-step ModDown and, when asked for
+    // (lazy_out), with the other (one ModDown per giant step, or one for all); block
+    // transforms have only per-step ModDowns
     std::vector<int32_t> offs(src.js.begin(), src.js.end());
     int best = -1;
-    for (int i : timed) {
-        nj_plan *q = nullptr;
-        nj_status st = nj_plan_create_random(c, level, src.u, offs.data(), (int)offs.size(), cands[i].n1, src.bi,
-                                             src.bo, 0x7u + (uint64_t)i, &q);
-        if (st) return st;
-        q->lts[0].stages = src.stages, q->lts[0].hoist = cands[i].hoist;
-        st = nj_time_plan(c, q, 0, level, reps, &cands[i].ms);
-        nj_plan_destroy(q);
-        if (st) return st;
-        if (best < 0 || cands[i].ms < cands[best].ms) best = i;
-    }
-    *n1_out = cands[best].n1, *hoist_out = cands[best].hoist ? 1 : 0, *ms_out = cands[best].ms;
+    bool best_lazy = src.lazy;
+    float best_ms = 0.f;
+    for (int i : timed)
+        for (int v = 0; v < (lazy_out && !blk ? 2 : 1); v++) {
+            const bool lz = v ? !src.lazy : src.lazy;
+            nj_plan *q = nullptr;
+            nj_status st = nj_plan_create_random(c, level, src.u, offs.data(), (int)offs.size(), cands[i].n1, src.bi,
+                                                 src.bo, 0x7u + (uint64_t)i, &q);
+            if (st) return st;
+            q->lts[0].stages = src.stages, q->lts[0].hoist = cands[i].hoist, q->lts[0].lazy = lz;
+            float ms = 0.f;
+            st = nj_time_plan(c, q, 0, level, reps, &ms);
+            nj_plan_destroy(q);
+            if (st) return st;
+            if (v == 0) cands[i].ms = ms;  // the plan's own setting (the default's time)
+            if (best < 0 || ms < best_ms) best = i, best_lazy = lz, best_ms = ms;
+        }
+    *n1_out = cands[best].n1, *hoist_out = cands[best].hoist ? 1 : 0, *ms_out = best_ms;
+    if (lazy_out) *lazy_out = best_lazy ? 1 : 0;
     if (default_ms)
         for (const Cand &k : cands)
             if (k.n1 == 0 && k.hoist) *default_ms = k.ms;

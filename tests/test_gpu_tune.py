@@ -118,12 +118,17 @@ def test_autotuner_behind_the_abi():
         ctx.nj_tune_split(conv, 1, model=None)
     ctx.nj_timing_keys(16)
     try:
-        for name, plan, level in (("conv", conv, 1), ("32 diagonals", cts, 23)):
-            n1, h, ms, dms = ctx.nj_tune_split(plan, level, model=None, reps=3)
-            n1m, hm, msm, dmsm = ctx.nj_tune_split(plan, level, model=model, shortlist=3, reps=3)
-            print("%s at level %d: exhaustive n1=%d hoist=%s %.3f ms, model n1=%d hoist=%s %.3f ms, default %.3f ms"
-                  % (name, level, n1, h, ms, n1m, hm, msm, dms))
-            assert 0 < ms <= dms and 0 < msm <= dmsm
+        for name, plan, level in (("conv", conv, 1), ("32 diagonals", cts, 23), ("conv at level 15", conv, 15)):
+            if level > 1 and name.startswith("conv"):
+                plan = ctx.nj_plan_create_random(level, 2048, list(range(-33, 34)), n1=0)
+            n1, h, lz, ms, dms = ctx.nj_tune_split(plan, level, model=None, reps=3)
+            n1m, hm, _, msm, dmsm = ctx.nj_tune_split(plan, level, model=model, shortlist=3, reps=3)
+            n1z, hz, lzz, msz, dmsz = ctx.nj_tune_split(plan, level, model=None, reps=3, lazy=True)
+            print("%s at level %d: exhaustive n1=%d hoist=%s %.3f ms, model n1=%d hoist=%s %.3f ms, default %.3f ms; "
+                  "with the ModDown form: n1=%d hoist=%s lazy=%s %.3f ms" % (name, level, n1, h, ms, n1m, hm, msm, dms,
+                                                                             n1z, hz, lzz, msz))
+            assert lz is None and lzz in (False, True)
+            assert 0 < ms <= dms and 0 < msm <= dmsm and 0 < msz <= dmsz
             assert n1 == 0 or (n1 & (n1 - 1)) == 0
     finally:
         ctx.nj_timing_keys(0)

@@ -334,7 +334,6 @@ std::vector<MixJob> unit_jobs(const nj_job *jobs, const std::vector<int> &u)
 }
 
 // worker streams (defined with the concurrent schedule below)
-nj_status workers_ready(nj_ctx *c);
 int n_workers(const nj_ctx *c, int n);
 template <class Run>
 nj_status on_workers(nj_ctx *c, const std::vector<double> &cost, size_t per, Arena A0, hipStream_t s, Run run);
@@ -514,7 +513,6 @@ nj_status run_plain(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n, Ar
 // The workers fork from the caller's stream and join back into it through events, so
 // the schedule also captures into one HIP graph.
 
-constexpr int kMaxWorkers = 4;  // hardware queues per process on the target (GPU_MAX_HW_QUEUES)
 
 // estimated relative cost of a job, to balance the workers: key switches x limbs of
 // its conv, plus the CoeffToSlot every output block runs at the top levels
@@ -527,19 +525,6 @@ double job_cost(const nj_plan *cts, const nj_job &j)
     return conv + lt.bo * ct;
 }
 
-nj_status workers_ready(nj_ctx *c)
-{
-    while ((int)c->workers.size() < kMaxWorkers) {
-        hipStream_t w;
-        hipEvent_t e;
-        NJ_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
-        c->workers.push_back(w);
-        NJ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        c->worker_done.push_back(e);
-    }
-    if (!c->fork_ev) NJ_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-    return NJ_OK;
-}
 
 size_t worker_words(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
 {
@@ -615,6 +600,21 @@ void set_outputs(nj_ctx *c, const nj_plan *cts, const nj_job *jobs, int n)
 }
 
 }  // namespace
+
+// the context's worker streams (default priority) and their fork/join events, made once
+nj_status nj::ex::workers_ready(nj_ctx *c)
+{
+    while ((int)c->workers.size() < kMaxWorkers) {
+        hipStream_t w;
+        hipEvent_t e;
+        NJ_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+        c->workers.push_back(w);
+        NJ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->worker_done.push_back(e);
+    }
+    if (!c->fork_ev) NJ_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    return NJ_OK;
+}
 
 extern "C" {
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <initializer_list>
 #include <vector>
 
 #include "exec.h"
@@ -30,9 +31,21 @@ struct Cx {
     double s = 0.0;
 };
 
+// Scratch of the parts of one ModEval that run on worker streams: the Chebyshev basis
+// products T3, then T5, T6, T7 (slots 0..3, kBranchSlots each), the quotient of the
+// series' top division (slot 4, kTreeSlots), and one key-switch arena per worker.
+constexpr int kBranchSlots = 8, kTreeSlots = 24, kBranchWorkers = 3;
+struct BranchMem {
+    Arena slots[5];
+    Arena ks[kBranchWorkers];
+};
+
 // Ciphertext buffers of one evaluation: fixed-size slots (K level-lmax ciphertexts
 // each) from an arena with a free list; the key-switch scratch is a separate arena.
 // Every operation applies to the K packed ciphertexts at once (K > 1 needs N >= 8192).
+// Independent products can run as branches: an Ev on a worker stream with its own slots
+// and scratch, forked after the values it reads are enqueued and joined before its
+// result is used, so every value is computed by the same kernels as in one stream.
 class Ev {
   public:
     Ev(nj_ctx *c, int lmax, Arena cts, Arena ks, hipStream_t s, int K = 1)
@@ -46,9 +59,29 @@ class Ev {
     int lmax, K;
     Arena cts, ks;
     hipStream_t s;
+    int wid = -1;  // worker stream of a branch
     nj_status err = NJ_OK;
     const uint64_t *relin = nullptr;
     std::vector<uint64_t *> free_;
+
+    Ev branch(int w, Arena slots, Arena kscratch) const
+    {
+        Ev b(c, lmax, slots, kscratch, c->workers[w], K);
+        b.wid = w;
+        for (int j = 0; j < 33; j++) b.T[j] = T[j];
+        return b;
+    }
+    void fork(std::initializer_list<Ev *> bs)
+    {
+        check(hipEventRecord(c->fork_ev, s));
+        for (Ev *b : bs) check(hipStreamWaitEvent(b->s, c->fork_ev, 0));
+    }
+    void join(Ev &b)
+    {
+        check(hipEventRecord(c->worker_done[b.wid], b.s));
+        check(hipStreamWaitEvent(s, c->worker_done[b.wid], 0));
+        check(b.err);
+    }
 
     static size_t slots_needed() { return 48; }
     size_t slot_words() const { return (size_t)K * 2 * N * (lmax + 1); }
@@ -179,21 +212,42 @@ class Ev {
     }
 
     Cx T[33];
-    void basis(const Cx &x)
+    // bm: T3 alongside T4, then T5, T6, T7 alongside T8, on worker streams
+    void basis(const Cx &x, const BranchMem *bm = nullptr)
     {
         T[1] = x;
         T[2] = sq_minus1(T[1]);
-        T[3] = prod_minus(T[1], T[2], T[1]);
-        T[4] = sq_minus1(T[2]);
-        T[5] = prod_minus(T[2], T[3], T[1]);
-        T[6] = sq_minus1(T[3]);
-        T[7] = prod_minus(T[3], T[4], T[1]);
-        T[8] = sq_minus1(T[4]);
+        if (!bm) {
+            T[3] = prod_minus(T[1], T[2], T[1]);
+            T[4] = sq_minus1(T[2]);
+            T[5] = prod_minus(T[2], T[3], T[1]);
+            T[6] = sq_minus1(T[3]);
+            T[7] = prod_minus(T[3], T[4], T[1]);
+            T[8] = sq_minus1(T[4]);
+        } else {
+            Ev b3 = branch(0, bm->slots[0], bm->ks[0]);
+            fork({&b3});
+            const Cx t3 = b3.prod_minus(T[1], T[2], T[1]);
+            T[4] = sq_minus1(T[2]);
+            join(b3);
+            T[3] = t3;
+            Ev b5 = branch(0, bm->slots[1], bm->ks[0]), b6 = branch(1, bm->slots[2], bm->ks[1]),
+               b7 = branch(2, bm->slots[3], bm->ks[2]);
+            fork({&b5, &b6, &b7});
+            const Cx t5 = b5.prod_minus(T[2], T[3], T[1]);
+            const Cx t6 = b6.sq_minus1(T[3]);
+            const Cx t7 = b7.prod_minus(T[3], T[4], T[1]);
+            T[8] = sq_minus1(T[4]);
+            join(b5), join(b6), join(b7);
+            T[5] = t5, T[6] = t6, T[7] = t7;
+        }
         T[16] = sq_minus1(T[8]);
         T[32] = sq_minus1(T[16]);
     }
 
-    Cx eval(const std::vector<double> &cf, int lam, double tau)
+    // bm (the top call): the quotient of the top division on a worker stream alongside
+    // the remainder
+    Cx eval(const std::vector<double> &cf, int lam, double tau, const BranchMem *bm = nullptr)
     {
         const int d = (int)cf.size() - 1;
         if (d < 8 && c->eval_order == 0) {
@@ -250,10 +304,19 @@ class Ev {
             r[G - j] -= cf[G + j];
         }
         const double tau_q = tau * (double)c->primes[lam + 1] / T[G].s;
-        Cx Q = eval(q, lam + 1, tau_q);
+        Cx Q, rr;
+        if (bm) {
+            Ev bq = branch(0, bm->slots[4], bm->ks[0]);
+            fork({&bq});
+            Q = bq.eval(q, lam + 1, tau_q);
+            rr = eval(r, lam, tau);
+            join(bq);
+        } else {
+            Q = eval(q, lam + 1, tau_q);
+        }
         Cx prod = hmult(Q, T[G]);
-        release(Q);
-        Cx rr = eval(r, lam, tau);
+        release(Q);  // (a branch's slot joins this free list: the branch is done)
+        if (!bm) rr = eval(r, lam, tau);
         Cx o = add(prod, rr, 0);
         o.s = tau;
         release(prod), release(rr);
@@ -261,10 +324,15 @@ class Ev {
     }
 };
 
+size_t eval_ks_words(const nj_ctx *c, int l0, int K)
+{
+    return std::max(ks_words(c, l0), multi_words(c, l0, K)) + (size_t)c->N * (l0 + 3) * K;
+}
+
 size_t eval_mod_words(const nj_ctx *c, int l0, int K = 1)
 {
-    return Ev::slots_needed() * K * 2 * (size_t)c->N * (l0 + 1) +
-           std::max(ks_words(c, l0), multi_words(c, l0, K)) + (size_t)c->N * (l0 + 3) * K;
+    const size_t slot = K * 2 * (size_t)c->N * (l0 + 1);
+    return (Ev::slots_needed() + 4 * kBranchSlots + kTreeSlots) * slot + (1 + kBranchWorkers) * eval_ks_words(c, l0, K);
 }
 
 // ModEval of K ciphertexts in[z] (level l0, scale s0) evaluated together (packed; K > 1
@@ -272,9 +340,22 @@ size_t eval_mod_words(const nj_ctx *c, int l0, int K = 1)
 nj_status eval_mod(nj_ctx *c, int K, const uint64_t *const *in, int l0, double s0, double Kr, const double *cf,
                    uint64_t *const *out, double *out_scale, Arena A, hipStream_t s)
 {
-    const size_t N = c->N, pool = Ev::slots_needed() * K * 2 * N * (l0 + 1);
+    const size_t N = c->N, slot = K * 2 * N * (l0 + 1), pool = Ev::slots_needed() * slot;
+    nj_status st = workers_ready(c);
+    if (st) return st;
     uint64_t *ctsbuf = A.take(pool);
     if (!ctsbuf) return fail(NJ_ENOMEM, "scratch");
+    BranchMem bm;  // the worker streams' slots and key-switch scratch
+    for (int i = 0; i < 5; i++) {
+        const size_t w = (i < 4 ? kBranchSlots : kTreeSlots) * slot;
+        bm.slots[i] = Arena{A.take(w), w};
+        if (!bm.slots[i].p) return fail(NJ_ENOMEM, "scratch");
+    }
+    for (int k = 0; k < kBranchWorkers; k++) {
+        const size_t w = eval_ks_words(c, l0, K);
+        bm.ks[k] = Arena{A.take(w), w};
+        if (!bm.ks[k].p) return fail(NJ_ENOMEM, "scratch");
+    }
     Ev ev(c, l0, Arena{ctsbuf, pool}, A, s, K);
     if (!ev.ok()) return ev.err;
     const double q0 = (double)c->primes[0];
@@ -286,9 +367,9 @@ nj_status eval_mod(nj_ctx *c, int K, const uint64_t *const *in, int l0, double s
         ev.check(launch_mul_int(c, in[z], N * (l0 + 1), t.d + z * ev.cstride(l0), l0 + 1, ev.residues(k, l0 + 1), s));
     ev.rescale_into(t, x, ev.ks);
     ev.release(t);
-    ev.basis(x);
+    ev.basis(x, &bm);
     const int lam = x.l - 7;
-    Cx g = ev.eval(std::vector<double>(cf, cf + kChebDegree + 1), lam, (double)c->primes[lam]);
+    Cx g = ev.eval(std::vector<double>(cf, cf + kChebDegree + 1), lam, (double)c->primes[lam], &bm);
     for (int i = 0; i < 3; i++) {
         Cx h = ev.sq_minus1(g);
         ev.release(g);

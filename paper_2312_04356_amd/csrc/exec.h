@@ -32,6 +32,9 @@ struct MultiBufs {
 };
 
 constexpr int kGiantChunk = 8;  // giant-step key switches per batch in a single-ciphertext transform
+constexpr int kMaxWorkers = 4;  // worker streams: hardware queues per process on the target (GPU_MAX_HW_QUEUES)
+// creates the context's kMaxWorkers worker streams and their events if not yet made
+nj_status workers_ready(nj_ctx *c);
 constexpr int kBatch = 8;       // ciphertexts per sub-batch of the batched calls
 
 Arena arena_for(nj_ctx *c, size_t words, bool &ok);

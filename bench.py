@@ -323,15 +323,15 @@ def learned_plan_bench(g, ct, default_ms, steps, reps=3):
              for n1 in (1, 2, 4, 8, 16) for h in (True, False)}
     gctx.nj_timing_keys(16)
     try:
-        # the model's best candidates and the default plan (n1 = 4, hoisted; depth 3 with the
-        # default splits) are timed; the fastest is used
+        # the model's best candidates and the benchmark's own plan (n1 = 4, hoisted; depth 3
+        # with the workload's splits) are timed; the fastest is used
         cr = rank_conv(gctx, model, convs, 1)
         pred_of = {k: p for p, k in cr}
         short = [k for _, k in cr[:SHORTLIST]] + ([(4, True)] if (4, True) not in [k for _, k in cr[:SHORTLIST]] else [])
         conv_t = [(gctx.nj_time_plan(convs[k], 1, reps=reps), k, pred_of[k]) for k in short]
         conv_ms, (cn1, ch), conv_pred = min(conv_t)
         ranked = rank_cts(gctx, model)
-        dflt_n1 = [int(math.ceil(math.sqrt(f[1]))) for f in gctx.nj_cts_plan_features(3)]
+        dflt_n1 = list(g.w.get("cts_n1") or [int(math.ceil(math.sqrt(f[1]))) for f in gctx.nj_cts_plan_features(3)])
         cands = [(d, n1s, hs, pred) for pred, d, n1s, hs in ranked[:SHORTLIST]]
         if not any(d == 3 and n1s == dflt_n1 and all(hs) for d, n1s, hs, _ in cands):
             cands.append((3, dflt_n1, [True] * 3, None))
@@ -668,7 +668,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "N=2^16 fused CinS conv 3x3 16->16 32x32 + CoeffToSlot (3 groups), 24+8 primes, dnum=3",
                    "log_n": gctx.log_n, "n_q": gctx.L + 1, "alpha": gctx.alpha,
-                   "cts_groups": g.w["cts_groups"], "lazy_giant_steps": not args.no_lazy,
+                   "cts_groups": g.w["cts_groups"], "cts_n1": g.w.get("cts_n1"), "lazy_giant_steps": not args.no_lazy,
                    "host_wall_s": round(wall, 3)},
         "keyswitch_per_s": {"plain": ks, "batched": ks_batch, "batch": nbk, "galois": gk},
         "batched": {"n_ct": args.batch, "ms_per_batch": round(batch_ms, 3),

@@ -20,7 +20,9 @@ def padded_width(w0, f):
 
 
 class GpuWorkload:
-    def __init__(self, name, with_cts=True, conv_n1=0, lazy=False):
+    def __init__(self, name, with_cts=True, conv_n1=0, lazy=False, cts_split=True):
+        """cts_split: the CoeffToSlot groups' baby-step counts from the workload's
+        "cts_n1" (else, or when False, the library's default split)"""
         import torch
         self.torch = torch
         w = dict(synth.WORKLOADS[name])
@@ -37,7 +39,11 @@ class GpuWorkload:
         self.img = synth.uniform_real((w["c_in"], w["w0"], w["w0"]), w["data_seed"], 0)
         self.K = synth.uniform_real((w["c_out"], w["c_in"], w["f"], w["f"]), w["data_seed"], 1)
         self.conv_plan = self.ctx.nj_conv_plan_create(w["w0"], w["f"], self.K, conv_n1)
-        self.cts_plan = self.ctx.nj_cts_plan_create(w["cts_groups"]) if with_cts else None
+        self.cts_plan = None
+        if with_cts:
+            n1s = w.get("cts_n1") if cts_split else None
+            self.cts_plan = (self.ctx.nj_cts_plan_create_split(w["cts_groups"], n1s) if n1s
+                             else self.ctx.nj_cts_plan_create(w["cts_groups"]))
         if lazy and self.cts_plan is not None:
             self.cts_plan.set_lazy(True)
         self.keys_made = set()

@@ -76,7 +76,7 @@ def run_job(o, plans, name, level, sub):
 def main():
     from tests.oracle_workload import OracleWorkload
     t0 = time.time()
-    o = OracleWorkload("full", with_cts=True)
+    o = OracleWorkload("full", with_cts=True, cts_split=False)  # CoeffToSlot with the default split
     plans = oracle_plans(o)
     gs = set(o.galois_elements())
     for bs, _ in plans.values():

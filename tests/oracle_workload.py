@@ -9,7 +9,9 @@ from oracle.pipeline import Ctx
 
 
 class OracleWorkload:
-    def __init__(self, name, with_cts=True, n1=None):
+    def __init__(self, name, with_cts=True, n1=None, cts_split=True):
+        """cts_split: the CoeffToSlot groups' baby-step counts from the workload's
+        "cts_n1" (else, or when False, the default split)"""
         w = dict(synth.WORKLOADS[name])
         self.w = w
         self.N = N = 1 << w["log_n"]
@@ -29,7 +31,8 @@ class OracleWorkload:
         self.cts = []
         if with_cts:
             L = self.ring.L
-            for g, (plan, diags) in enumerate(PL.cts_plan(N, w["cts_groups"])):
+            n1s = w.get("cts_n1") if cts_split else None
+            for g, (plan, diags) in enumerate(PL.cts_plan(N, w["cts_groups"], n1s)):
                 lvl = L - g
                 self.cts.append((plan, PL.encode_diagonals(diags, N, float(q[lvl]), self.ring, lvl)))
 

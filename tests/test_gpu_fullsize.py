@@ -136,8 +136,8 @@ def test_batched_mixed_levels_parity_full():
     doc = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_batch_jobs.json")))
     O.set_threads(0)
     say("batched jobs: setup")
-    o = OracleWorkload("full", with_cts=True)
-    g = GpuWorkload("full", with_cts=True, lazy=True)
+    o = OracleWorkload("full", with_cts=True, cts_split=False)  # the split the digests were made with
+    g = GpuWorkload("full", with_cts=True, lazy=True, cts_split=False)
     gctx = g.ctx
     for t, (_, pts) in enumerate(o.cts):
         load(gctx, g.cts_plan, t, pts)

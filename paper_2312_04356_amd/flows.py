@@ -18,11 +18,12 @@ Both start from the same encrypted activations and end in CinS ciphertexts of th
 output channels at 28 x 28; the slots before the last StoC1 are compared with the FP64
 stride-2 conv (masked, squared).  Weights U(-1, 1) / sqrt(9 * 64), inputs U(-1, 1).
 
-    python -m paper_2312_04356_amd.flows --out gpurun_out/flows.json
+    python -m paper_2312_04356_amd.flows --out results/flows.json
 """
 import argparse
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -312,8 +313,7 @@ def main():
         json.dump(res, fh, indent=1)
     if args.md:
         with open(args.md, "w") as fh:
-            fh.write(summary(res, "python -m paper_2312_04356_amd.flows --out gpurun_out/flows.json --md "
-                                  "gpurun_out/downsampling_flows_n65536.md"))
+            fh.write(summary(res, "python -m paper_2312_04356_amd.flows " + " ".join(sys.argv[1:])))
     log("decomposed / densify: %.2fx faster" % res["speedup"])
 
 

@@ -23,11 +23,12 @@ on the same phase images as the block's first conv.  Weights U(-1, 1) (synthetic
 0.2 (the role BN folding plays in a trained network); input U(-1, 1).  Phases are timed by HIP events around each
 library call (one call at a time), in Table 2's rows.
 
-    python -m paper_2312_04356_amd.network --out gpurun_out/resnet18.json [--md gpurun_out/resnet18.md]
+    python -m paper_2312_04356_amd.network --out results/resnet18.json [--md results/resnet18.md]
 """
 import argparse
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -428,8 +429,7 @@ def main():
         json.dump(res, fh, indent=1)
     if args.md:
         with open(args.md, "w") as fh:
-            fh.write(summary(res, "python -m paper_2312_04356_amd.network --out gpurun_out/resnet18.json --md "
-                                  "gpurun_out/resnet18_e2e_n65536.md"))
+            fh.write(summary(res, "python -m paper_2312_04356_amd.network " + " ".join(sys.argv[1:])))
 
 
 if __name__ == "__main__":

@@ -9,7 +9,7 @@ the model's plans with exhaustive timing and the default plans on
     Algorithm 1 leaves room for d <= 6), each group's BSGS split and hoisting.
 The trained model and the timing database are written for later plan selection:
 
-    python -m paper_2312_04356_amd.tune --out gpurun_out/tune.json \
+    python -m paper_2312_04356_amd.tune --out results/tune.json \
         --model paper_2312_04356_amd/data/plan_model_n65536.json [--samples 5000]
 
 Every timing runs in libneujeans (nj_time_plan); the model is trained and evaluated by

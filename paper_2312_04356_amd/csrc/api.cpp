@@ -179,6 +179,11 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
+    if (fuse_ip(c, l)) {  // special-prime rows straight into ModDown's inverse tile pass
+        NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s, l + 1));
+        NJ_HIP(launch_key_ip_ptile(c, l, kj, K, M.pc, s));
+        return ks_down(c, l, K, mj, sum, acc, M, s, true);
+    }
     NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
     return ks_down(c, l, K, mj, sum, acc, M, s);
 }

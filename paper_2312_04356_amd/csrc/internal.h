@@ -325,6 +325,12 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
 // (pout given: the special-prime rows skip u and leave through the first 12 stages of
 // ModDown's inverse transform, job z's halves at rows (2 z + p) alpha + a of pout;
 // skip > 0: Q limbs 1..skip are not computed, skip = l - 1 keeping Q limbs 0 and l)
+// special-prime rows of n_jobs key inner products whose digits are extended and in
+// evaluation form (KeyJobs as for launch_key_ip_multi): the products pass through the
+// first 12 stages of ModDown's inverse transform into pout, job z's halves at rows
+// (2 z + p) alpha + a (N >= 8192, 1..4 digits, alpha <= 8)
+hipError_t launch_key_ip_ptile(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout,
+                               hipStream_t s);
 // centred lift of n_polys limbs (prime src_pidx, coefficient form, src + z N) into
 // primes 0..n_out-1 with the column pass applied, out [n_polys][n_out][N] (N >= 8192)
 hipError_t launch_lift_col(const nj_ctx *c, const uint64_t *src, int src_pidx, int n_polys, int n_out, uint64_t *out,
@@ -365,8 +371,10 @@ hipError_t launch_keygen_combine(const nj_ctx *c, int digit, uint64_t *b, const 
 
 // ------------------------------------------------------------------- ksw.hip
 hipError_t launch_bconv_multi(const nj_ctx *c, const BconvShared &sh, const BconvPtrs &jp, int n_jobs, hipStream_t s);
+// key inner products of n_jobs jobs into u_base + z 2 ne N, output limbs 0..rows-1 (rows
+// < 0: all l + 1 + alpha; rows = l + 1: the Q limbs alone)
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
-                               hipStream_t s);
+                               hipStream_t s, int rows = -1);
 hipError_t launch_moddown_multi(const nj_ctx *c, int level, const MdJobs &mj, int n_jobs, int sum,
                                 const uint64_t *u_base, const uint64_t *conv_base, const uint64_t *acc, hipStream_t s);
 hipError_t launch_automorph_multi(const nj_ctx *c, const AutoJobs &aj, int n_jobs, int n_limbs, hipStream_t s);

@@ -323,11 +323,13 @@ hipError_t launch_key_ip_sum(const nj_ctx *c, int level, const KeyJobs &kj, int 
 }
 
 hipError_t launch_key_ip_multi(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *u_base,
-                               hipStream_t s)
+                               hipStream_t s, int rows)
 {
     const int nd = n_digits(c, level), ne = level + 1 + c->alpha;
-    dim3 grid((c->N + kBT - 1) / kBT, ne, n_jobs);
-    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * ne * (3.0 * nd + 2.0) * n_jobs, k_key_ip_multi<ND>, grid,
+    if (rows < 0) rows = ne;
+    if (rows < 1 || rows > ne) return hipErrorInvalidValue;
+    dim3 grid((c->N + kBT - 1) / kBT, rows, n_jobs);
+    NJ_ND_SWITCH(nd, launch(c, PROF_KEYIP, 8.0 * c->N * rows * (3.0 * nd + 2.0) * n_jobs, k_key_ip_multi<ND>, grid,
                             dim3(kBT), s, kj, u_base, nd, level, c->L, c->alpha, c->n_q, c->d_info, c->log_n));
 }
 

@@ -498,6 +498,50 @@ __global__ __launch_bounds__(kNT, 2) void k_ntt_ip(KeyJobs kj, int n_jobs, uint6
     }
 }
 
+// Special-prime rows of the key inner products of n_jobs jobs whose digits are already
+// extended and in evaluation form (job z: [ND][ne][N] at kj.ext[z], read through
+// X -> X^g, g = kj.g[z]; a special prime is in no digit, so no own limb): each block
+// sums one tile of one half's products over the digits and sends it through the first
+// 12 stages of ModDown's inverse transform into row (2 z + p) alpha + a of pout, as
+// launch_ntt_ip does with its special-prime rows.  The products never go to memory in
+// evaluation form.  Grid (2 jobs, N/4096, alpha): blockIdx.x = 2 z + p, so the two
+// halves of one tile, which read the same digit words, are dispatched together.
+template <int ND>
+__global__ __launch_bounds__(kNT, 4) void k_key_ip_ptile(KeyJobs kj, int level, int L, int alpha, int nq,
+                                                         const PrimeInfo *info, int logN, uint64_t *pout,
+                                                         const double *itw)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12;
+    const int z = blockIdx.x >> 1, p = blockIdx.x & 1, tile = blockIdx.y, a = blockIdx.z, tid = threadIdx.x;
+    const int t = level + 1 + a, pidx = nq + a;
+    const Mod m = info[pidx].m;
+    const IpRow r = ip_row(t, level, L, alpha);
+    const uint32_t g = kj.g[z], w0 = (uint32_t)tile * kT + tid;
+    const auto e = buf_rsrc(kj.ext[z], 8u * (uint32_t)(ND * r.ne) * (uint32_t)N);
+    const auto key = buf_rsrc(kj.key[z], 8u * (uint32_t)(2 * ND * r.nk) * (uint32_t)N);
+    uint32_t src[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) src[k] = 8u * (uint32_t)galois_src2((int)(w0 + 256u * k), g, logN);
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) acc[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < ND; j++) {
+        const uint32_t xo = 8u * (uint32_t)((j * r.ne + r.t) * N),
+                       vk = 8u * ((uint32_t)((j * 2 + p) * r.nk + r.kl) * (uint32_t)N + w0);
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            acc[k] += mul_lazy(u2d(buf_ld(e, src[k], xo)), u2d(buf_ld(key, vk, 2048u * k)), m);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) acc[k] = reduce(acc[k], m);
+    tile_inverse(acc, s, tid, tile, logN1, itw + (size_t)pidx * N, N, m);
+    uint64_t *out = pout + ((size_t)(2 * z + p) * alpha + a) * N + w0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) out[256 * k] = d2u(acc[k]);
+}
+
 // Inverse tile pass whose input limbs are read through X -> X^g (the automorphism of a
 // key switch folded into ModUp's inverse transform): limb lt[b] is of job off / L1,
 // read from src + soff N at the words the Galois element gt.g[job] moves to each
@@ -951,6 +995,28 @@ hipError_t launch_ntt_ip(const nj_ctx *c, int level, const KeyJobs &kj, int n_jo
         NJ_IP(1) NJ_IP(2) NJ_IP(3) NJ_IP(4)
     }
 #undef NJ_IP
+    return hipErrorInvalidValue;
+}
+
+// Special-prime rows of n_jobs key inner products from extended evaluation-form digits,
+// through the first 12 stages of ModDown's inverse transform into pout (N >= 8192,
+// 1..4 digits, alpha <= 8).
+hipError_t launch_key_ip_ptile(const nj_ctx *c, int level, const KeyJobs &kj, int n_jobs, uint64_t *pout,
+                               hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT, nd = n_digits(c, level);
+    if (N1 < 2 || nd < 1 || nd > 4 || c->alpha > 8 || n_jobs < 1 || n_jobs > NJ_MAX_JOBS || !pout)
+        return hipErrorInvalidValue;
+    const double bytes = 8.0 * N * c->alpha * (3.0 * nd + 2.0) * n_jobs;
+    const dim3 grid(2 * n_jobs, N1, c->alpha);
+#define NJ_PT(ND)                                                                                             \
+    case ND:                                                                                                  \
+        return launch(c, PROF_KEYIP, bytes, k_key_ip_ptile<ND>, grid, dim3(kNT), s, kj, level, c->L, c->alpha, \
+                      c->n_q, c->d_info, c->log_n, pout, c->d_itw);
+    switch (nd) {
+        NJ_PT(1) NJ_PT(2) NJ_PT(3) NJ_PT(4)
+    }
+#undef NJ_PT
     return hipErrorInvalidValue;
 }
 

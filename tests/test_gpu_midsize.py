@@ -2,8 +2,9 @@
 (N = 2^13, 2^14, 2^15: 2, 4 and 8 tiles of 4096 words per limb), word for word against
 the oracle through the C ABI (needs an MI355X).
 
-Each case runs the benchmark's step on a ring of 12 + 4 primes (three key-switching
-digits of four primes at the top level, the last one partial below it): the conv at
+Each case runs the benchmark's step on a ring of 12 + alpha primes (alpha = 4: three
+key-switching digits at the top level, the last one partial below it; alpha = 3: four
+digits; alpha = 8: two): the conv at
 level 1 (hoisted baby steps: key inner products on the Q limbs, special-prime rows
 through ModDown's first inverse stages) -> rescale -> ModRaise -> CoeffToSlot in three
 groups, with the giant steps lazy (one ModDown per group, inner products fused with
@@ -27,16 +28,17 @@ from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
 from tests.oracle_workload import OracleWorkload  # noqa: E402
 
 
-def mid_workload(log_n):
-    """a named workload (registered once) of the small workload's shape on a 2^log_n ring"""
-    name = "mid%d" % log_n
+def mid_workload(log_n, alpha):
+    """a named workload (registered once) of the small workload's shape on a 2^log_n ring
+    with 12 + alpha primes"""
+    name = "mid%d_a%d" % (log_n, alpha)
     if name not in synth.WORKLOADS:
         w = dict(synth.WORKLOADS["small"])
         C = (1 << log_n) // 1024
-        w.update({"description": "N = 2^%d, 12 + 4 primes, 3x3 conv %d->%d on 16x16, CoeffToSlot in 3 groups"
-                                 % (log_n, C, C),
-                  "log_n": log_n, "n_q": 12, "alpha": 4, "cts_groups": 3, "c_in": C, "c_out": C,
-                  "data_seed": 1100 + log_n, "key_seed": 2100 + log_n})
+        w.update({"description": "N = 2^%d, 12 + %d primes, 3x3 conv %d->%d on 16x16, CoeffToSlot in 3 groups"
+                                 % (log_n, alpha, C, C),
+                  "log_n": log_n, "n_q": 12, "alpha": alpha, "cts_groups": 3, "c_in": C, "c_out": C,
+                  "data_seed": 1100 + log_n, "key_seed": 2100 + log_n + 20 * alpha})
         synth.WORKLOADS[name] = w
     return name
 
@@ -54,15 +56,17 @@ def load(gctx, plan, t, pts):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("log_n,lazy", [(13, True), (14, False), (15, True), (15, False)])
-def test_step_parity_midsize(log_n, lazy):
+@pytest.mark.parametrize("log_n,lazy,alpha", [(13, True, 4), (14, False, 4), (15, True, 4), (15, False, 4),
+                                              (14, True, 3), (13, False, 3), (14, True, 8), (15, False, 8)])
+def test_step_parity_midsize(log_n, lazy, alpha):
     O.set_threads(0)
-    name = mid_workload(log_n)
-    print("[midsize] N=2^%d lazy=%s: setup" % (log_n, lazy), flush=True)
+    name = mid_workload(log_n, alpha)
+    print("[midsize] N=2^%d lazy=%s alpha=%d: setup" % (log_n, lazy, alpha), flush=True)
     o = OracleWorkload(name, with_cts=True)
     g = GpuWorkload(name, with_cts=True, lazy=lazy)
     gctx = g.ctx
     assert g.q == o.ring.q and g.p == o.ring.p
+    assert gctx.dnum == {3: 4, 4: 3, 8: 2}[alpha]
     assert sorted(g.conv_plan.offsets(0)) == sorted(o.conv_bsgs.js)
     load(gctx, g.conv_plan, 0, o.conv_pts)
     assert g.cts_plan.count() == len(o.cts) == 3
@@ -75,14 +79,14 @@ def test_step_parity_midsize(log_n, lazy):
     m = o.ring.to_rns(o.input_plaintext(), 1)
     x_o = o.encrypt_input(1)
     x_g = g.encrypt_input(1, m_dev=gctx.to_device(m))
-    print("[midsize] N=2^%d lazy=%s: library" % (log_n, lazy), flush=True)
+    print("[midsize] N=2^%d lazy=%s alpha=%d: library" % (log_n, lazy, alpha), flush=True)
     y = gctx.empty_ct(0)
     gctx.nj_conv2d_cins(g.conv_plan, x_g, y)
     lvl = gctx.L - 3
     re, im = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
     gctx.nj_coeff_to_slot(g.cts_plan, y, re, im)
     torch.cuda.synchronize()
-    print("[midsize] N=2^%d lazy=%s: oracle" % (log_n, lazy), flush=True)
+    print("[midsize] N=2^%d lazy=%s alpha=%d: oracle" % (log_n, lazy, alpha), flush=True)
     y_o = o.ctx.conv2d_cins(x_o, o.conv_bsgs, o.conv_pts)
     assert np.array_equal(host_coeff(gctx, y), y_o), "conv output differs"
     w_re, w_im = o.ctx.coeff_to_slot(y_o, [p for p, _ in o.cts], [pts for _, pts in o.cts], lazy=lazy)

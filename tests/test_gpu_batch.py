@@ -9,6 +9,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+from tests.midsize import mid_workload  # noqa: E402
 
 
 def encrypt_many(g, n, level):
@@ -25,10 +26,16 @@ def encrypt_many(g, n, level):
     return batch
 
 
-@pytest.mark.parametrize("name,n", [("small", 10), ("full", 3)])
-def test_batched_conv_and_coeff_to_slot_equal_separate_calls(name, n):
+@pytest.mark.parametrize("name,n,lazy", [("small", 10, False), ("full", 3, False), ((14, 4), 11, True),
+                                         ((15, 3), 9, False)],
+                         ids=["small-10", "full-3", "n14_a4-11-lazy", "n15_a3-9"])
+def test_batched_conv_and_coeff_to_slot_equal_separate_calls(name, n, lazy):
+    """(log_n, alpha) names a ring between the small ring and the benchmark's (12 + alpha
+    primes); 9 and 11 ciphertexts run as sub-batches of 8 and the rest"""
     from paper_2312_04356_amd import Ct
-    g = GpuWorkload(name, with_cts=True)
+    if isinstance(name, tuple):
+        name = mid_workload(*name)
+    g = GpuWorkload(name, with_cts=True, lazy=lazy)
     gctx = g.ctx
     g.make_keys()
     x = encrypt_many(g, n, 1)

@@ -16,7 +16,6 @@ import numpy as np
 import pytest
 
 import oracle as O
-import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -25,22 +24,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2312_04356_amd.workload import GpuWorkload  # noqa: E402
+from tests.midsize import mid_workload  # noqa: E402
 from tests.oracle_workload import OracleWorkload  # noqa: E402
-
-
-def mid_workload(log_n, alpha):
-    """a named workload (registered once) of the small workload's shape on a 2^log_n ring
-    with 12 + alpha primes"""
-    name = "mid%d_a%d" % (log_n, alpha)
-    if name not in synth.WORKLOADS:
-        w = dict(synth.WORKLOADS["small"])
-        C = (1 << log_n) // 1024
-        w.update({"description": "N = 2^%d, 12 + %d primes, 3x3 conv %d->%d on 16x16, CoeffToSlot in 3 groups"
-                                 % (log_n, alpha, C, C),
-                  "log_n": log_n, "n_q": 12, "alpha": alpha, "cts_groups": 3, "c_in": C, "c_out": C,
-                  "data_seed": 1100 + log_n, "key_seed": 2100 + log_n + 20 * alpha})
-        synth.WORKLOADS[name] = w
-    return name
 
 
 def host_coeff(gctx, ct, n_polys=2):

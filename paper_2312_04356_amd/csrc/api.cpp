@@ -174,23 +174,27 @@ nj_status modup_multi(nj_ctx *c, int l, int K, const uint64_t *d, MultiBufs &M, 
 // K key switches from already-extended digits: inner products, ModDown, combine.
 // sum = 0: job z writes mj.out[z]; sum = 1: mj.out[0] = acc + sum of all jobs.
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop);
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop, const KeyJobs *ipq);
 
 nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj, int sum, const uint64_t *acc,
                    MultiBufs &M, hipStream_t s)
 {
     if (fuse_ip(c, l)) {  // special-prime rows straight into ModDown's inverse tile pass
-        NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s, l + 1));
         NJ_HIP(launch_key_ip_ptile(c, l, kj, K, M.pc, s));
+        if (!sum && !acc)  // the Q limbs' products inside the ModDown combine
+            return ks_down(c, l, K, mj, 0, nullptr, M, s, true, nullptr, nullptr, false, &kj);
+        NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s, l + 1));
         return ks_down(c, l, K, mj, sum, acc, M, s, true);
     }
     NJ_HIP(launch_key_ip_multi(c, l, kj, K, M.u, s));
     return ks_down(c, l, K, mj, sum, acc, M, s);
 }
 
-// ModDown of K jobs' inner products (M.u) and the combine into their outputs.
+// ModDown of K jobs' inner products (M.u) and the combine into their outputs (ipq: the
+// Q limbs' inner products are computed inside the combine from these jobs' extended
+// evaluation-form digits instead of read from M.u; plain combine only).
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
-                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop)
+                  hipStream_t s, bool p_tiled, uint64_t *last_out, const MdConj *conj, bool drop, const KeyJobs *ipq)
 {
     const int N = c->N, ne = l + 1 + c->alpha, al = c->alpha;
     const bool fused = N >= 8192 && al <= 8;  // as in modup_multi
@@ -199,6 +203,8 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     if (drop && (sum || !fused || last_out || conj || l < 2))
         return fail(NJ_EUNSUPPORTED, "ModDown: limbs 0 and l only with the fused combine, no hand-off, level >= 2");
     if (last_out && !(one && fused)) return fail(NJ_EUNSUPPORTED, "ModDown: the rescale hand-off needs one job, N >= 8192");
+    if (ipq && (sum || acc || last_out || conj || drop || !fused || !fuse_ip(c, l)))
+        return fail(NJ_EUNSUPPORTED, "ModDown: inner products in the combine need the plain fused combine");
     if (conj && !one) return fail(NJ_EUNSUPPORTED, "ModDown: the fused split needs one job, N >= 4096");
     // one job with a previous value held elsewhere: the fused combine reads it there
     const uint64_t *acc0 = one && acc && acc != mj.out[0] ? acc : nullptr;
@@ -230,6 +236,10 @@ nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint
     BconvPtrs jp;
     for (int h = 0; h < 2 * K; h++) jp.in[h] = M.pc + (size_t)h * al * N, jp.out[h] = M.conv + (size_t)h * (l + 1) * N;
     NJ_HIP(fused ? launch_bconv_col(c, sh, jp, 2 * K, s) : launch_bconv_multi(c, sh, jp, 2 * K, s));
+    if (ipq) {
+        NJ_HIP(launch_key_ip_moddown(c, l, K, M.conv, *ipq, mj, s));
+        return NJ_OK;
+    }
     if (!sum && N >= 4096) {  // the combine runs inside the transform's tile pass
         NJ_HIP(launch_ntt_moddown(c, l, K, M.conv, M.u, mj, acc != nullptr, fused, s, acc0, last_out, conj,
                                   drop ? l - 1 : 0));

@@ -86,7 +86,7 @@ nj_status ks_multi(nj_ctx *c, int l, int K, const KeyJobs &kj, const MdJobs &mj,
 // the inner products' Q rows 0 and l and special-prime rows are all it reads)
 nj_status ks_down(nj_ctx *c, int l, int K, const MdJobs &mj, int sum, const uint64_t *acc, MultiBufs &M,
                   hipStream_t s, bool p_tiled = false, uint64_t *last_out = nullptr, const MdConj *conj = nullptr,
-                  bool drop = false);
+                  bool drop = false, const KeyJobs *ipq = nullptr);
 
 // inner_g += diag_dg (.) baby_b for each entry, any number of baby and giant steps
 struct MacEntry {

@@ -341,6 +341,11 @@ hipError_t launch_intt_cols_scaled(const nj_ctx *c, uint64_t *data, const LimbTa
 // job: the last limb also leaves through the first 12 stages of its inverse transform
 // into last_out [2][N], for launch_rescale_fused(last_tiled))
 // skip > 0 (with cols_done, no last_out or conj): only output limbs 0 and 1 + skip ..
+// the plain combine of launch_ntt_moddown (no accumulation, converted limbs column-passed)
+// with the jobs' Q-limb key inner products computed inside it from extended
+// evaluation-form digits (KeyJobs as for launch_key_ip_multi; N >= 8192, 1..4 digits)
+hipError_t launch_key_ip_moddown(const nj_ctx *c, int level, int K, const uint64_t *conv, const KeyJobs &kj,
+                                 const MdJobs &mj, hipStream_t s);
 hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv, const uint64_t *u_base,
                               const MdJobs &mj, int acc, int cols_done, hipStream_t s, const uint64_t *acc0 = nullptr,
                               uint64_t *last_out = nullptr, const MdConj *conj = nullptr, int skip = 0);

@@ -768,6 +768,75 @@ __global__ __launch_bounds__(kNT, 4) void k_ntt_tile_md(const uint64_t *conv, co
     }
 }
 
+// ModDown combine of K key switches from extended evaluation-form digits, with their
+// key inner products on the Q limbs computed in the same block (the plain combine of
+// k_ntt_tile_md, no accumulation): job z's half p at limb i is the sum over digits j of
+// x_j read through X -> X^g (the own limb of kj.d[z] for i's digit, else the extended
+// digit j at kj.ext[z]) times the key words, then (that - the converted special-prime
+// part, after its tile pass) P^-1 plus add.  The products never go to memory.  Grid
+// (N/4096, 2 K (l+1)).
+template <int ND>
+__global__ __launch_bounds__(kNT, ND == 1 ? 3 : ND == 4 ? 2 : 4) void k_key_ip_md(const uint64_t *conv, KeyJobs kj, MdJobs mj, int level, int L,
+                                                      int alpha, const double *pinv, const double *tw,
+                                                      const PrimeInfo *info, int logN)
+{
+    __shared__ double s[kT + kT / 16];
+    const int N = 1 << logN, logN1 = logN - 12, L1 = level + 1;
+    const int w = blockIdx.y, h = w / L1, i = w - h * L1, z = h >> 1, p = h & 1;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const Mod m = info[i].m;
+    const size_t t0 = (size_t)tile * kT;
+    const IpRow r = ip_row(i, level, L, alpha);
+    const uint32_t g = kj.g[z], w0 = (uint32_t)t0 + tid;
+    const auto e = buf_rsrc(kj.ext[z], 8u * (uint32_t)(ND * r.ne) * (uint32_t)N);
+    const auto dd = buf_rsrc(kj.d[z] + (size_t)i * N, 8u * (uint32_t)N);
+    const auto key = buf_rsrc(kj.key[z], 8u * (uint32_t)(2 * ND * r.nk) * (uint32_t)N);
+    double a[16];
+    {
+        uint32_t src[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            src[k] = 8u * (g <= 1u ? w0 + 256u * k : (uint32_t)galois_src2((int)(w0 + 256u * k), g, logN));
+#pragma unroll
+        for (int k = 0; k < 16; k++) a[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < ND; j++) {
+            const uint32_t vk = 8u * ((uint32_t)((j * 2 + p) * r.nk + r.kl) * (uint32_t)N + w0);
+            if (j == r.own) {
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    a[k] += mul_lazy(u2d(buf_ld(dd, src[k], 0)), u2d(buf_ld(key, vk, 2048u * k)), m);
+            } else {
+                const uint32_t xo = 8u * (uint32_t)((j * r.ne + r.t) * N);
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    a[k] += mul_lazy(u2d(buf_ld(e, src[k], xo)), u2d(buf_ld(key, vk, 2048u * k)), m);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; k++) a[k] = reduce(a[k], m);
+    }
+    const uint64_t *in = conv + ((size_t)h * L1 + i) * N + t0;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = u2d(in[tid + 256 * k]);
+    tile_forward_lean(v, s, tid, tile, logN1, tw + (size_t)i * N, N, m);
+    const uint64_t *add = p == 0 ? mj.add[z] : nullptr;
+    const uint32_t ga = mj.g_add[z];
+    uint64_t *out = mj.out[z] + ((size_t)p * L1 + i) * N + t0;
+    const double pv = pinv[i];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int x = tid + 256 * k;
+        double t = mul_canon(sub_mod(a[k], s[pad16(x)], m), pv, m);
+        if (add) {
+            const int kk = (int)t0 + x;
+            t = add_mod(t, u2d(add[(size_t)i * N + (ga <= 1u ? kk : galois_src2(kk, ga, logN))]), m);
+        }
+        out[x] = d2u(t);
+    }
+}
+
 // Rescale by q_l, fused into the lifted limbs' transform (N >= 8192).  k_lift_col: the
 // last limb of each polynomial (coefficient form, last [P][N]) lifted centred into
 // target limb i, then the forward column pass; grid (4096/256, n_out, P).
@@ -972,6 +1041,26 @@ hipError_t launch_ntt_moddown(const nj_ctx *c, int level, int K, uint64_t *conv,
                       level, L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj, skip);
     return launch(c, PROF_NTT_MD, bytes, k_ntt_tile_md<false>, dim3(N1, n), dim3(kNT), s, conv, u_base, mj, acc, level,
                   L1 + c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n, acc0, last_out, c->d_itw, cj, skip);
+}
+
+// The plain ModDown combine of K key switches (converted limbs column-passed) with their
+// Q-limb key inner products computed inside it from extended evaluation-form digits
+// (N >= 8192, 1..4 digits).
+hipError_t launch_key_ip_moddown(const nj_ctx *c, int level, int K, const uint64_t *conv, const KeyJobs &kj,
+                                 const MdJobs &mj, hipStream_t s)
+{
+    const int N = c->N, N1 = N / kT, L1 = level + 1, n = 2 * K * L1, nd = n_digits(c, level);
+    if (N1 < 2 || K < 1 || K > NJ_MAX_JOBS || nd < 1 || nd > 4) return hipErrorInvalidValue;
+    const double bytes = 8.0 * N * (n * (2.0 * nd + 2.0) + K * L1);
+#define NJ_IPMD(ND)                                                                                                \
+    case ND:                                                                                                       \
+        return launch(c, PROF_KEYIP, bytes, k_key_ip_md<ND>, dim3(N1, n), dim3(kNT), s, conv, kj, mj, level, c->L, \
+                      c->alpha, c->d_pinv, c->d_tw, c->d_info, c->log_n);
+    switch (nd) {
+        NJ_IPMD(1) NJ_IPMD(2) NJ_IPMD(3) NJ_IPMD(4)
+    }
+#undef NJ_IPMD
+    return hipErrorInvalidValue;
 }
 
 // Key inner products of n_jobs jobs (digits of tau_g(d) column-passed only, own limbs

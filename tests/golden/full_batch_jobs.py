@@ -3,7 +3,7 @@
 Each job (Algorithm 1 up to EvalMod, at the ciphertext's own level) is: the fused
 conv (Sec. 4) with a plan encoded for the top level and applied with the first l+1
 residues of its diagonals -> rescale -> exact drop to level 0 -> ModRaise ->
-CoeffToSlot in three groups with lazy giant steps -> real split (Algorithm 1, line 2).
+CoeffToSlot in three groups with lazy giant steps -> real split (Algorithm 1, up to ModEval).
 The oracle computes every job; this script stores the SHA-256 of each output
 ciphertext (coefficient form, uint64 little-endian, [2][l+1][N] C order) in
 `full_batch_jobs.json`, so the GPU test can compare the library's batched schedule

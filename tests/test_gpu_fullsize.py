@@ -4,7 +4,7 @@ C ABI, word for word against the oracle (needs an MI355X):
 * the benchmark step exactly as bench.py times it: fused conv at level 1 (hoisted baby
   steps, per-rotation giant steps) -> rescale -> ModRaise -> CoeffToSlot in three groups
   at levels 23/22/21 (lazy giant steps, partial last digits of 8/7/6 primes) -> the
-  conjugate split fused into the conjugation's ModDown (Algorithm 1, lines 1-2);
+  conjugate split fused into the conjugation's ModDown (Algorithm 1, conv through CoeffToSlot);
 * ModEval as one call on a level-20 ciphertext (Sec. 2.4; the library's evaluation in
   both Chebyshev orders);
 * a mixed-level job list run by the batched schedule (mode 1: two jobs of one conv plan

@@ -302,7 +302,50 @@ def slot_error(g, y, re, im, lvl):
     return err
 
 
-def learned_plan_bench(g, ct, default_ms, steps, reps=3):
+def encrypted_batch(g, n):
+    """n distinct secret-key encryptions of the workload's image at level 1, as one batch"""
+    import torch
+
+    import synth
+    from paper_2312_04356_amd import Ct
+    gctx = g.ctx
+    coeffs = gctx.nj_encode_cins(g.image_slices(), g.scale)
+    mdev = torch.empty((2, g.N), dtype=torch.int64, device=gctx.device)
+    gctx.nj_upload_plain(coeffs, 1, mdev)
+    xb = gctx.empty_batch(n, 1)
+    for z in range(n):
+        a, e = synth.enc_randomness(g.q[:2], g.N, g.w["data_seed"], 100 + z)
+        gctx.nj_encrypt_sk(mdev, 1, a, e, g.scale, Ct(xb.data[z], 1))
+    return xb
+
+
+def batched_ms(g, conv, cts, xb, n, lvl, steps):
+    """ms per batch of n ciphertexts through conv + CoeffToSlot (batched calls), and the
+    slot error of the first ciphertext's outputs"""
+    import torch
+
+    from paper_2312_04356_amd import Ct
+    gctx = g.ctx
+    yb = gctx.empty_batch(n, 0)
+    reb, imb = gctx.empty_batch(n, lvl), gctx.empty_batch(n, lvl)
+
+    def bstep():
+        gctx.nj_conv2d_cins_batch(conv, xb, n, yb)
+        gctx.nj_coeff_to_slot_batch(cts, yb, n, reb, imb)
+
+    bstep()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        bstep()
+    e1.record()
+    torch.cuda.synchronize()
+    err = slot_error(g, Ct(yb.data[0], 0), Ct(reb.data[0], lvl), Ct(imb.data[0], lvl), lvl)
+    return e0.elapsed_time(e1) / steps, err
+
+
+def learned_plan_bench(g, ct, default_ms, steps, reps=3, batch=0, batch_steps=2):
     """The step with the plan the learned latency model proposes (the model trained by
     paper_2312_04356_amd/tune.py from the library's own timings, run by nj_mlp_predict):
     the conv's BSGS split and hoisting, CoeffToSlot's depth (2..6, within Algorithm 1's
@@ -365,6 +408,14 @@ def learned_plan_bench(g, ct, default_ms, steps, reps=3):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     err = slot_error(g, y, re, im, lvl)
+    both = None
+    if batch > 0:
+        # batched and learned together: the model's plans on the batched calls
+        xb = encrypted_batch(g, batch)
+        bms, berr = batched_ms(g, conv, cts, xb, batch, lvl, batch_steps)
+        del xb
+        both = {"n_ct": batch, "ms_per_ct": round(bms / batch, 4), "speedup_vs_plain": round(default_ms / (bms / batch), 3),
+                "cts_slot_err_first_ct": berr}
     return {"conv": {"n1": cn1, "hoist": ch, "predicted_ms": round(conv_pred, 3), "timed_ms": round(conv_ms, 3)},
             "cts": {"groups": d, "n1": n1s, "hoist": hs, "predicted_ms": None if cts_pred is None else round(cts_pred, 3),
                     "timed_ms": round(cts_ms, 3)},
@@ -372,7 +423,8 @@ def learned_plan_bench(g, ct, default_ms, steps, reps=3):
             "cts_shortlist": [{"groups": dd, "n1": nn, "hoist": hh, "timed_ms": round(t, 3),
                                "predicted_ms": None if p is None else round(p, 3)} for t, dd, nn, hh, p in cts_t],
             "ms": round(ms, 4), "default_ms": round(default_ms, 4), "speedup_vs_default": round(default_ms / ms, 3),
-            "cts_slot_err": err, "output_level": lvl, "model": os.path.relpath(PLAN_MODEL, ROOT),
+            "cts_slot_err": err, "output_level": lvl, "batched_with_learned_plan": both,
+            "model": os.path.relpath(PLAN_MODEL, ROOT),
             "model_heldout_rel_err": doc.get("heldout_rel_err")}
 
 
@@ -568,31 +620,9 @@ def main():
     torch.cuda.empty_cache()
 
     # batched fused conv + CoeffToSlot: 64 ciphertexts (distinct encryptions of the image)
-    import synth
-    from paper_2312_04356_amd import Ct
-    coeffs = gctx.nj_encode_cins(g.image_slices(), g.scale)
-    mdev = torch.empty((2, g.N), dtype=torch.int64, device=gctx.device)
-    gctx.nj_upload_plain(coeffs, 1, mdev)
-    xb = gctx.empty_batch(args.batch, 1)
-    for z in range(args.batch):
-        a, e = synth.enc_randomness(g.q[:2], g.N, g.w["data_seed"], 100 + z)
-        gctx.nj_encrypt_sk(mdev, 1, a, e, g.scale, Ct(xb.data[z], 1))
-    yb = gctx.empty_batch(args.batch, 0)
-    reb, imb = gctx.empty_batch(args.batch, lvl), gctx.empty_batch(args.batch, lvl)
-
-    def bstep():
-        gctx.nj_conv2d_cins_batch(g.conv_plan, xb, args.batch, yb)
-        gctx.nj_coeff_to_slot_batch(g.cts_plan, yb, args.batch, reb, imb)
-
-    bstep()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.batch_steps):
-        bstep()
-    e1.record()
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1) / args.batch_steps
-    del xb, yb, reb, imb
+    xb = encrypted_batch(g, args.batch)
+    batch_ms, batch_err = batched_ms(g, g.conv_plan, g.cts_plan, xb, args.batch, lvl, args.batch_steps)
+    del xb
 
     def step():
         gctx.nj_conv2d_cins(g.conv_plan, ct, y)
@@ -611,7 +641,8 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
 
     default_err = slot_error(g, y, re, im, lvl)
-    learned = None if args.no_learned else learned_plan_bench(g, ct, ms, args.steps)
+    learned = None if args.no_learned else learned_plan_bench(g, ct, ms, args.steps, batch=args.batch,
+                                                                batch_steps=args.batch_steps)
     torch.cuda.empty_cache()
 
     # the same steps again with the library's live per-kernel event timing
@@ -674,6 +705,7 @@ def main():
         "batched": {"n_ct": args.batch, "ms_per_batch": round(batch_ms, 3),
                     "ms_per_ct": round(batch_ms / args.batch, 4),
                     "speedup_vs_plain": round(ms / (batch_ms / args.batch), 3),
+                    "cts_slot_err_first_ct": batch_err,
                     "hbm_frac_per_ct": round(pipeline_bytes(g) / (batch_ms / args.batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "jobs": jobs,
         "learned_plan": learned,

@@ -518,41 +518,61 @@ def cpu_model():
     return "unknown"
 
 
+def _oracle_step(name, threads_list):
+    """the oracle's whole step on workload `name` timed once per thread count, and one
+    top-level rotation timed per thread count -> ({threads: step s}, {threads: rotation s})"""
+    import oracle as O
+    from oracle.plans import galois_elt
+    from tests.oracle_workload import OracleWorkload
+    O.set_threads(0)
+    o = OracleWorkload(name, with_cts=True)
+    o.make_keys()
+    ct = o.encrypt_input(1)
+    step, rot = {}, {}
+    y = None
+    for n in threads_list:
+        O.set_threads(n)
+        t = time.perf_counter()
+        y = o.ctx.conv2d_cins(ct, o.conv_bsgs, o.conv_pts)
+        o.ctx.coeff_to_slot(y, [p for p, _ in o.cts], [pts for _, pts in o.cts], lazy=True)
+        step[n] = time.perf_counter() - t
+    x = o.ctx.ct_modraise(y)
+    r = o.cts[0][0].rotations()[0]
+    assert galois_elt(r, o.N) in o.ctx.keys
+    for n in sorted(set(threads_list) | {1}):
+        O.set_threads(n)
+        t = time.perf_counter()
+        o.ctx.rotate(o.ring.L, x, r)
+        rot[n] = time.perf_counter() - t
+    O.set_threads(0)
+    return step, rot
+
+
 def cpu_baseline(name):
     """The oracle on the host, the whole step once: the fused conv at level 1, rescale,
     ModRaise, CoeffToSlot in three groups with lazy giant steps and the real split, on
     one ciphertext with its limb loops on every host core (keys generated before the
     timed region, as they are resident on the GPU).  The single-thread figure scales
-    that time by the one-core / all-core ratio of one level-23 rotation."""
+    that time by the one-core / all-core ratio of one top-level rotation; the same
+    estimate is checked on the small workload (N = 2^12), whose whole step is also
+    timed on one core."""
     import oracle as O
-    from oracle.plans import galois_elt
-    from tests.oracle_workload import OracleWorkload
     t0 = time.time()
     O.set_threads(0)
     threads = O.get_threads()
-    o = OracleWorkload(name, with_cts=True)
-    o.make_keys()
-    ct = o.encrypt_input(1)
-    t = time.perf_counter()
-    y = o.ctx.conv2d_cins(ct, o.conv_bsgs, o.conv_pts)
-    o.ctx.coeff_to_slot(y, [p for p, _ in o.cts], [pts for _, pts in o.cts], lazy=True)
-    total = time.perf_counter() - t
-    # one rotation at the top level on one core and on all of them
-    x = o.ctx.ct_modraise(y)
-    r = o.cts[0][0].rotations()[0]
-    assert galois_elt(r, o.N) in o.ctx.keys
-    times = {}
-    for n in (1, threads):
-        O.set_threads(n)
-        t = time.perf_counter()
-        o.ctx.rotate(o.ring.L, x, r)
-        times[n] = time.perf_counter() - t
-    O.set_threads(0)
+    step, rot = _oracle_step(name, [threads])
+    total = step[threads]
+    s_small, r_small = _oracle_step("small", [threads, 1])
+    est_small = s_small[threads] * r_small[1] / r_small[threads]
     return {"value": round(total * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
             "sample": "the whole step once (conv at level 1, rescale, ModRaise, CoeffToSlot 3 groups with lazy "
                       "giant steps, real split) on one ciphertext, limb loops over %d OpenMP threads" % threads,
-            "single_thread_ms_est": round(total * times[1] / times[threads] * 1e3, 1),
-            "thread_speedup_one_rotation": round(times[1] / times[threads], 2),
+            "single_thread_ms_est": round(total * rot[1] / rot[threads] * 1e3, 1),
+            "thread_speedup_one_rotation": round(rot[1] / rot[threads], 2),
+            "estimate_check_n4096": {"single_thread_ms": round(s_small[1] * 1e3, 1),
+                                     "all_threads_ms": round(s_small[threads] * 1e3, 1),
+                                     "single_thread_ms_est": round(est_small * 1e3, 1),
+                                     "rel_err": round(est_small / s_small[1] - 1.0, 3)},
             "nproc": os.cpu_count(), "cpu_model": cpu_model(), "wall_s": round(time.time() - t0, 1)}
 
 

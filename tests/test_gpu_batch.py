@@ -54,6 +54,35 @@ def test_batched_conv_and_coeff_to_slot_equal_separate_calls(name, n, lazy):
         assert torch.equal(rz.data, re.data[z]) and torch.equal(iz.data, im.data[z]), "cts %d" % z
 
 
+def test_batched_with_the_cost_models_plan_equals_separate_calls():
+    """the trained cost model's first-choice CoeffToSlot plan at full size (N = 2^16; its
+    depth, splits and hoisting) with lazy giant steps on the batched calls, 3 ciphertexts,
+    equals single calls word for word (single calls of split plans are checked against the
+    oracle at this size in test_gpu_plans)"""
+    import json
+
+    from bench import PLAN_MODEL
+    from paper_2312_04356_amd import Ct, Mlp
+    from paper_2312_04356_amd.tune import rank_cts
+    g = GpuWorkload("full", with_cts=False)
+    gctx = g.ctx
+    _, d, n1s, hs = rank_cts(gctx, Mlp.from_dict(json.load(open(PLAN_MODEL))))[0]
+    cts = gctx.nj_cts_plan_create_split(d, n1s).set_lazy(True).set_hoist(hs)
+    print("plan: depth %d, n1 %s, hoist %s" % (d, n1s, hs), flush=True)
+    g.make_keys(sorted(set(g.conv_plan.galois()) | set(cts.galois())))
+    n, lvl = 3, gctx.L - d
+    x = encrypt_many(g, n, 1)
+    y = gctx.empty_batch(n, 0)
+    re, im = gctx.empty_batch(n, lvl), gctx.empty_batch(n, lvl)
+    gctx.nj_conv2d_cins_batch(g.conv_plan, x, n, y)
+    gctx.nj_coeff_to_slot_batch(cts, y, n, re, im)
+    torch.cuda.synchronize()
+    for z in range(n):
+        rz, iz = gctx.empty_ct(lvl), gctx.empty_ct(lvl)
+        gctx.nj_coeff_to_slot(cts, Ct(y.data[z], 0), rz, iz)
+        assert torch.equal(rz.data, re.data[z]) and torch.equal(iz.data, im.data[z]), "cts %d" % z
+
+
 def test_batched_galois_equals_separate_calls():
     from paper_2312_04356_amd import Ct
     g = GpuWorkload("small", with_cts=False)

@@ -7,7 +7,8 @@ For every kernel family the bench line reports (launches per step x steps), the
 last that-many dispatches in the trace are the bench's live-profiled steps (the
 last GPU work of a bench run); their rocprofv3 average duration is set beside the
 HIP-event average of a plain bench run (no profiler attached: under rocprofv3 the
-events also count the profiler's own per-dispatch work).  Whole-run totals follow.
+events also count the profiler's own per-dispatch work).  Whole-run totals follow,
+then the last profiled step launch by launch (grid, registers, LDS, duration).
 """
 import csv
 import json
@@ -80,6 +81,23 @@ def main(trace, bench_json, plain_json, command):
         print("| %s | %d | %.3f | %.2f |" % (k, len(v), sum(v) / 1e6, sum(v) / len(v) / 1e3))
     print()
     print("Total kernel time %.3f ms." % (tot / 1e6))
+    # the last profiled step, launch by launch (the trace's final dispatches)
+    per_step = int(round(sum(v["launches_per_step"] for v in bench["pipeline"]["kernels"].values())))
+    last = rows[-per_step:] if per_step else []
+    if last:
+        print()
+        print("## The last profiled step, launch by launch (%d launches, %.3f ms of kernel time)"
+              % (len(last), sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / 1e6))
+        print()
+        print("| # | kernel | blocks (x, y, z) | threads | VGPR | LDS B | us |")
+        print("|---|---|---|---|---|---|---|")
+        for i, r in enumerate(last):
+            wg = int(r["Workgroup_Size_X"])
+            blocks = (int(r["Grid_Size_X"]) // wg, int(r["Grid_Size_Y"]), int(r["Grid_Size_Z"]))
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("nj::", "").strip()
+            print("| %d | %s | %d, %d, %d | %d | %s | %s | %.1f |"
+                  % (i, name, blocks[0], blocks[1], blocks[2], wg, r["VGPR_Count"], r["LDS_Block_Size"],
+                     (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
 
 
 if __name__ == "__main__":
